@@ -1,0 +1,239 @@
+"""ctypes binding of the MR. POP C ABI.
+
+Functions take and return torch tensors on the context's device; host
+inputs (numpy arrays) are copied to the device first.  Work is queued on
+torch's current stream for that device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libmrpop.so"
+
+STATUS_NAMES = {
+    0: "OK", 1: "E_INVALID_ARG", 2: "E_NONFINITE", 3: "E_START_INVALID", 4: "E_GOAL_INVALID",
+    5: "E_NO_SOLUTION", 6: "E_CAPACITY", 7: "E_NOMEM", 8: "E_BUFFER", 9: "E_DEVICE",
+}
+
+
+class MrpopError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, _LIB_NAME)
+
+
+class _Robot(C.Structure):
+    _fields_ = [("n_joints", C.c_int32), ("dh", C.c_void_p), ("q_lo", C.c_void_p), ("q_hi", C.c_void_p),
+                ("base_tf", C.c_void_p), ("n_spheres", C.c_int32), ("sphere_link", C.c_void_p),
+                ("sphere_xyzr", C.c_void_p)]
+
+
+class _Env(C.Structure):
+    _fields_ = [("n_spheres", C.c_int32), ("spheres", C.c_void_p), ("n_boxes", C.c_int32), ("boxes", C.c_void_p)]
+
+
+class _ValidateStats(C.Structure):
+    _fields_ = [("edge_states", C.c_int64), ("states_checked", C.c_int64), ("edges_invalid", C.c_int64),
+                ("nonfinite_edges", C.c_int64), ("tiles", C.c_int64)]
+
+
+@dataclass
+class ValidateStats:
+    edge_states: int
+    states_checked: int
+    edges_invalid: int
+    nonfinite_edges: int
+    tiles: int
+
+
+_lib = None
+
+
+def load_library():
+    """Load libmrpop.so; raises ImportError when it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    # torch ships its own HIP runtime (same soname); load it first so that the
+    # process holds a single runtime and torch's allocations and streams are
+    # valid for the library.
+    _torch()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2609_30644_amd.build`")
+    lib = C.CDLL(path)
+    P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.mrpop_version.restype = C.c_char_p
+    lib.mrpop_last_error.restype = C.c_char_p
+    lib.mrpop_last_error.argtypes = [P]
+    lib.mrpop_ctx_create.argtypes = [C.c_int, C.POINTER(P)]
+    lib.mrpop_ctx_destroy.argtypes = [P]
+    lib.mrpop_scene_create.argtypes = [P, P, I32, P, C.POINTER(P)]
+    lib.mrpop_scene_destroy.argtypes = [P]
+    lib.mrpop_scene_dof.argtypes = [P]
+    lib.mrpop_scene_dof.restype = I32
+    lib.mrpop_scene_total_spheres.argtypes = [P]
+    lib.mrpop_scene_total_spheres.restype = I32
+    lib.mrpop_fk_spheres.argtypes = [P, P, P, I64, P, P]
+    lib.mrpop_validate_edges.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(device) -> int:
+    torch = _torch()
+    return int(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """Owns a library context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load_library()
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch")
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        h = C.c_void_p()
+        self._check(self._lib.mrpop_ctx_create(device, C.byref(h)), None)
+        self._h = h
+
+    def _check(self, st: int, h) -> None:
+        if st != 0:
+            msg = self._lib.mrpop_last_error(h).decode()
+            raise MrpopError(st, msg)
+
+    def check(self, st: int) -> None:
+        self._check(st, self._h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mrpop_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # tensors -----------------------------------------------------------
+    def to_device(self, a, dtype=None):
+        torch = _torch()
+        if isinstance(a, torch.Tensor):
+            t = a.to(self.device)
+        else:
+            t = torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
+        if dtype is not None:
+            t = t.to(dtype)
+        return t.contiguous()
+
+    def stream(self) -> int:
+        return _stream_ptr(self.device)
+
+
+class Scene:
+    """Arms and obstacles uploaded to the device (``mrpop_scene_create``).
+
+    ``scene`` is a ``workloads.Scene``-like object with ``models`` (each with
+    dh, q_lo, q_hi, sphere_link, sphere_xyzr), ``base_tf`` (R x 12),
+    ``env_spheres`` (N x 4) and ``env_boxes`` (N x 6)."""
+
+    def __init__(self, ctx: Context, scene):
+        self.ctx = ctx
+        self.src = scene
+        keep = []
+        robots = (_Robot * len(scene.models))()
+        for i, m in enumerate(scene.models):
+            arrs = [np.ascontiguousarray(m.dh, np.float32), np.ascontiguousarray(m.q_lo, np.float32),
+                    np.ascontiguousarray(m.q_hi, np.float32),
+                    np.ascontiguousarray(np.asarray(scene.base_tf, np.float32).reshape(-1, 12)[i]),
+                    np.ascontiguousarray(m.sphere_link, np.int32), np.ascontiguousarray(m.sphere_xyzr, np.float32)]
+            keep.extend(arrs)
+            robots[i] = _Robot(m.dh.shape[0], arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+                               arrs[3].ctypes.data, m.sphere_xyzr.shape[0], arrs[4].ctypes.data, arrs[5].ctypes.data)
+        es = np.ascontiguousarray(np.asarray(scene.env_spheres, np.float32).reshape(-1, 4))
+        eb = np.ascontiguousarray(np.asarray(scene.env_boxes, np.float32).reshape(-1, 6))
+        keep.extend([es, eb])
+        env = _Env(es.shape[0], es.ctypes.data if es.size else None, eb.shape[0], eb.ctypes.data if eb.size else None)
+        h = C.c_void_p()
+        ctx.check(ctx._lib.mrpop_scene_create(ctx.handle, robots, len(scene.models), C.byref(env), C.byref(h)))
+        self._h = h
+        self.dof = int(ctx._lib.mrpop_scene_dof(h))
+        self.total_spheres = int(ctx._lib.mrpop_scene_total_spheres(h))
+        self.n_robots = len(scene.models)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.ctx._lib.mrpop_scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def fk_spheres(self, q, out=None):
+        """World spheres (n_cfg, S_total, 4) float32 on the device."""
+        torch = _torch()
+        qd = self.ctx.to_device(q, torch.float32).reshape(-1, self.dof)
+        n = qd.shape[0]
+        if out is None:
+            out = torch.empty((n, self.total_spheres, 4), dtype=torch.float32, device=self.ctx.device)
+        self.ctx.check(self.ctx._lib.mrpop_fk_spheres(self.ctx.handle, self._h, qd.data_ptr(), n, out.data_ptr(),
+                                                      self.ctx.stream()))
+        return out
+
+    def validate_edges(self, qa, qb, resolution: float, n_states=None, out=None, stats: bool = False):
+        """Edge-valid bits (uint8, 1 = free) on the device; with stats=True
+        also returns a ValidateStats (the call then waits for the stream)."""
+        torch = _torch()
+        a = self.ctx.to_device(qa, torch.float32).reshape(-1, self.dof)
+        b = self.ctx.to_device(qb, torch.float32).reshape(-1, self.dof)
+        if a.shape != b.shape:
+            raise ValueError("qa and qb differ in shape")
+        E = a.shape[0]
+        ns = None if n_states is None else self.ctx.to_device(n_states, torch.int32).reshape(E)
+        if out is None:
+            out = torch.empty(E, dtype=torch.uint8, device=self.ctx.device)
+        st = _ValidateStats()
+        self.ctx.check(self.ctx._lib.mrpop_validate_edges(
+            self.ctx.handle, self._h, a.data_ptr(), b.data_ptr(), E, float(resolution),
+            None if ns is None else ns.data_ptr(), out.data_ptr(), C.byref(st) if stats else None,
+            self.ctx.stream()))
+        if stats:
+            return out, ValidateStats(st.edge_states, st.states_checked, st.edges_invalid, st.nonfinite_edges,
+                                      st.tiles)
+        return out
+
+    def states_free(self, q) -> np.ndarray:
+        """Host bool per composite state (True = collision-free)."""
+        qd = self.ctx.to_device(q, _torch().float32).reshape(-1, self.dof)
+        return self.validate_edges(qd, qd, 1.0).cpu().numpy().astype(bool)

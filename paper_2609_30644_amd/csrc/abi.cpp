@@ -1,0 +1,394 @@
+// C ABI entry points: contexts, scenes, argument checks and dispatch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "mrpop_internal.h"
+
+namespace {
+thread_local std::string g_create_error;
+}
+
+namespace mrpop {
+
+mrpop_status fail(mrpop_ctx *ctx, mrpop_status st, const std::string &msg) {
+  if (ctx) ctx->last_error = msg;
+  else g_create_error = msg;
+  return st;
+}
+
+mrpop_status hip_fail(mrpop_ctx *ctx, hipError_t e, const char *what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(ctx, e == hipErrorOutOfMemory ? MRPOP_E_NOMEM : MRPOP_E_DEVICE, msg);
+}
+
+mrpop_status scratch(mrpop_ctx *ctx, int slot, size_t bytes, void **out) {
+  DeviceBuffer &b = ctx->scratch[slot];
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      hipError_t e = hipFree(b.ptr);
+      b.ptr = nullptr;
+      b.bytes = 0;
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipFree(scratch)");
+    }
+    size_t want = std::max<size_t>(bytes + bytes / 4, 1 << 16);
+    hipError_t e = hipMalloc(&b.ptr, want);
+    if (e != hipSuccess) {
+      b.ptr = nullptr;
+      return hip_fail(ctx, e, "hipMalloc(scratch)");
+    }
+    b.bytes = want;
+  }
+  *out = b.ptr;
+  return MRPOP_OK;
+}
+
+}  // namespace mrpop
+
+using namespace mrpop;
+
+extern "C" {
+
+const char *mrpop_version(void) { return "mrpop-mi355x 0.1 (gfx950)"; }
+
+mrpop_status mrpop_ctx_create(int device, mrpop_ctx **out) {
+  if (!out) return fail(nullptr, MRPOP_E_INVALID_ARG, "ctx_create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(nullptr, MRPOP_E_INVALID_ARG, "ctx_create: no such device");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  mrpop_ctx *c = new mrpop_ctx();
+  c->device = device;
+  *out = c;
+  return MRPOP_OK;
+}
+
+void mrpop_ctx_destroy(mrpop_ctx *ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  for (auto &b : ctx->scratch)
+    if (b.ptr) hipFree(b.ptr);
+  if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
+  if (ctx->ev_b) hipEventDestroy(ctx->ev_b);
+  delete ctx;
+}
+
+const char *mrpop_last_error(const mrpop_ctx *ctx) {
+  return ctx ? ctx->last_error.c_str() : g_create_error.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// Scene packing
+// ---------------------------------------------------------------------------
+
+static bool finite_all(const float *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+static bool same_model(const mrpop_robot &a, const mrpop_robot &b) {
+  if (a.n_joints != b.n_joints || a.n_spheres != b.n_spheres) return false;
+  if (std::memcmp(a.dh, b.dh, sizeof(float) * 4 * a.n_joints)) return false;
+  if (std::memcmp(a.sphere_link, b.sphere_link, sizeof(int32_t) * a.n_spheres)) return false;
+  if (std::memcmp(a.sphere_xyzr, b.sphere_xyzr, sizeof(float) * 4 * a.n_spheres)) return false;
+  return true;
+}
+
+// Round a non-negative double up to the next float that is >= it.
+static float round_up_f(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = std::nextafter(f, INFINITY);
+  return f;
+}
+
+// Inflation of the per-link bounding sphere.  The coarse level is a filter
+// only: a fine sphere that touches an obstacle lies inside its link's coarse
+// sphere with this much room to spare, so single-precision rounding in the
+// coarse test can never hide a contact.
+static constexpr double kCoarseInflate = 1e-4;
+
+struct Blob {
+  std::vector<unsigned char> host;
+  size_t add(const void *p, size_t bytes) {
+    size_t off = (host.size() + 255) & ~size_t(255);
+    host.resize(off + bytes);
+    if (bytes) std::memcpy(host.data() + off, p, bytes);
+    return off;
+  }
+};
+
+mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32_t n_robots,
+                                const mrpop_env *env, mrpop_scene **out) {
+  if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "scene_create: ctx is NULL");
+  if (!out || !robots || !env) return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: NULL argument");
+  *out = nullptr;
+  if (n_robots < 1 || n_robots > MRPOP_MAX_ROBOTS)
+    return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: n_robots out of range");
+  for (int r = 0; r < n_robots; ++r) {
+    const mrpop_robot &rb = robots[r];
+    if (rb.n_joints < 1 || rb.n_joints > MRPOP_MAX_JOINTS)
+      return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: n_joints out of range");
+    if (rb.n_spheres < 1 || rb.n_spheres > MRPOP_MAX_SPHERES)
+      return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: n_spheres out of range");
+    if (!rb.dh || !rb.q_lo || !rb.q_hi || !rb.base_tf || !rb.sphere_link || !rb.sphere_xyzr)
+      return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: NULL robot array");
+    if (!finite_all(rb.dh, 4 * rb.n_joints) || !finite_all(rb.q_lo, rb.n_joints) ||
+        !finite_all(rb.q_hi, rb.n_joints) || !finite_all(rb.base_tf, 12) ||
+        !finite_all(rb.sphere_xyzr, 4 * rb.n_spheres))
+      return fail(ctx, MRPOP_E_NONFINITE, "scene_create: non-finite robot data");
+    for (int j = 0; j < rb.n_joints; ++j)
+      if (rb.q_lo[j] > rb.q_hi[j]) return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: q_lo > q_hi");
+    for (int i = 0; i < rb.n_spheres; ++i) {
+      if (rb.sphere_link[i] < 0 || rb.sphere_link[i] > rb.n_joints)
+        return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: sphere_link out of range");
+      if (rb.sphere_xyzr[4 * i + 3] < 0) return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: negative radius");
+    }
+  }
+  if (env->n_spheres < 0 || env->n_spheres > MRPOP_MAX_ENV || env->n_boxes < 0 || env->n_boxes > MRPOP_MAX_ENV)
+    return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: obstacle count out of range");
+  if ((env->n_spheres && !env->spheres) || (env->n_boxes && !env->boxes))
+    return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: NULL obstacle array");
+  if (!finite_all(env->spheres, 4 * (size_t)env->n_spheres) || !finite_all(env->boxes, 6 * (size_t)env->n_boxes))
+    return fail(ctx, MRPOP_E_NONFINITE, "scene_create: non-finite obstacle");
+  for (int k = 0; k < env->n_spheres; ++k)
+    if (env->spheres[4 * k + 3] < 0) return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: negative radius");
+  for (int k = 0; k < env->n_boxes; ++k)
+    for (int a = 0; a < 3; ++a)
+      if (env->boxes[6 * k + a] > env->boxes[6 * k + 3 + a])
+        return fail(ctx, MRPOP_E_INVALID_ARG, "scene_create: box lo > hi");
+
+  // Models: one shared model when every arm is identical.
+  bool homog = true;
+  for (int r = 1; r < n_robots; ++r) homog = homog && same_model(robots[0], robots[r]);
+  std::vector<int32_t> model_of(n_robots);
+  std::vector<const mrpop_robot *> models;
+  for (int r = 0; r < n_robots; ++r) {
+    if (homog && r > 0) { model_of[r] = 0; continue; }
+    model_of[r] = (int32_t)models.size();
+    models.push_back(&robots[r]);
+  }
+  const int M = (int)models.size();
+  int sph_stride = 0;
+  for (auto *m : models) sph_stride = std::max(sph_stride, m->n_spheres);
+
+  // Recentre the world on the middle of the bases' bounding box so that
+  // single-precision coordinates stay small.
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int r = 0; r < n_robots; ++r)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], (double)robots[r].base_tf[4 * a + 3]);
+      hi[a] = std::max(hi[a], (double)robots[r].base_tf[4 * a + 3]);
+    }
+  double org[3];
+  for (int a = 0; a < 3; ++a) org[a] = (double)(float)(0.5 * (lo[a] + hi[a]));
+
+  std::vector<int32_t> nj(M), link_start((size_t)M * (kMaxLinks + 1), 0), fine_src((size_t)M * sph_stride, 0);
+  std::vector<float4> dh((size_t)M * kMaxJoints, float4{0, 0, 1, 0}), fine((size_t)M * sph_stride, float4{0, 0, 0, 0}),
+      coarse((size_t)M * kMaxLinks, float4{0, 0, 0, -1});
+  std::vector<float> th((size_t)M * kMaxJoints, 0.f);
+  for (int m = 0; m < M; ++m) {
+    const mrpop_robot &rb = *models[m];
+    nj[m] = rb.n_joints;
+    for (int j = 0; j < rb.n_joints; ++j) {
+      double alpha = rb.dh[4 * j + 2];
+      dh[(size_t)m * kMaxJoints + j] = float4{rb.dh[4 * j], rb.dh[4 * j + 1], (float)std::cos(alpha), (float)std::sin(alpha)};
+      th[(size_t)m * kMaxJoints + j] = rb.dh[4 * j + 3];
+    }
+    // group spheres by link (stable)
+    std::vector<int> order(rb.n_spheres);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rb.sphere_link[a] < rb.sphere_link[b]; });
+    int32_t *ls = &link_start[(size_t)m * (kMaxLinks + 1)];
+    for (int i = 0; i < rb.n_spheres; ++i) {
+      int src = order[i];
+      fine[(size_t)m * sph_stride + i] = float4{rb.sphere_xyzr[4 * src], rb.sphere_xyzr[4 * src + 1],
+                                                rb.sphere_xyzr[4 * src + 2], rb.sphere_xyzr[4 * src + 3]};
+      fine_src[(size_t)m * sph_stride + i] = src;
+      ls[rb.sphere_link[src] + 1]++;
+    }
+    for (int l = 0; l < kMaxLinks; ++l) ls[l + 1] += ls[l];
+    // coarse sphere per link: middle of the bounding box of the link's sphere
+    // centres, radius reaching past every fine sphere, plus the inflation
+    for (int l = 0; l <= rb.n_joints; ++l) {
+      if (ls[l + 1] == ls[l]) continue;
+      double bl[3] = {INFINITY, INFINITY, INFINITY}, bh[3] = {-INFINITY, -INFINITY, -INFINITY};
+      for (int i = ls[l]; i < ls[l + 1]; ++i) {
+        const float4 f = fine[(size_t)m * sph_stride + i];
+        const double p[3] = {f.x, f.y, f.z};
+        for (int a = 0; a < 3; ++a) { bl[a] = std::min(bl[a], p[a]); bh[a] = std::max(bh[a], p[a]); }
+      }
+      float c[3];
+      for (int a = 0; a < 3; ++a) c[a] = (float)(0.5 * (bl[a] + bh[a]));
+      double rad = 0;
+      for (int i = ls[l]; i < ls[l + 1]; ++i) {
+        const float4 f = fine[(size_t)m * sph_stride + i];
+        double dx = (double)f.x - c[0], dy = (double)f.y - c[1], dz = (double)f.z - c[2];
+        rad = std::max(rad, std::sqrt(dx * dx + dy * dy + dz * dz) + (double)f.w);
+      }
+      coarse[(size_t)m * kMaxLinks + l] = float4{c[0], c[1], c[2], round_up_f(rad + kCoarseInflate)};
+    }
+  }
+  std::vector<int32_t> q_off(n_robots), s_out(n_robots);
+  std::vector<float> base((size_t)n_robots * 12);
+  int dof = 0, S = 0;
+  for (int r = 0; r < n_robots; ++r) {
+    q_off[r] = dof;
+    s_out[r] = S;
+    dof += robots[r].n_joints;
+    S += robots[r].n_spheres;
+    for (int i = 0; i < 12; ++i) base[(size_t)r * 12 + i] = robots[r].base_tf[i];
+    for (int a = 0; a < 3; ++a) base[(size_t)r * 12 + 4 * a + 3] = (float)((double)robots[r].base_tf[4 * a + 3] - org[a]);
+  }
+  std::vector<float4> env_s(std::max(1, env->n_spheres)), env_b(2 * (size_t)std::max(1, env->n_boxes));
+  for (int k = 0; k < env->n_spheres; ++k)
+    env_s[k] = float4{(float)((double)env->spheres[4 * k] - org[0]), (float)((double)env->spheres[4 * k + 1] - org[1]),
+                      (float)((double)env->spheres[4 * k + 2] - org[2]), env->spheres[4 * k + 3]};
+  for (int k = 0; k < env->n_boxes; ++k) {
+    const float *b = env->boxes + 6 * k;
+    env_b[2 * k] = float4{(float)((double)b[0] - org[0]), (float)((double)b[1] - org[1]), (float)((double)b[2] - org[2]), 0.f};
+    env_b[2 * k + 1] = float4{(float)((double)b[3] - org[0]), (float)((double)b[4] - org[1]), (float)((double)b[5] - org[2]), 0.f};
+  }
+
+  Blob blob;
+  size_t o_model = blob.add(model_of.data(), sizeof(int32_t) * n_robots);
+  size_t o_qoff = blob.add(q_off.data(), sizeof(int32_t) * n_robots);
+  size_t o_sout = blob.add(s_out.data(), sizeof(int32_t) * n_robots);
+  size_t o_base = blob.add(base.data(), sizeof(float) * base.size());
+  size_t o_nj = blob.add(nj.data(), sizeof(int32_t) * M);
+  size_t o_dh = blob.add(dh.data(), sizeof(float4) * dh.size());
+  size_t o_th = blob.add(th.data(), sizeof(float) * th.size());
+  size_t o_ls = blob.add(link_start.data(), sizeof(int32_t) * link_start.size());
+  size_t o_fine = blob.add(fine.data(), sizeof(float4) * fine.size());
+  size_t o_fsrc = blob.add(fine_src.data(), sizeof(int32_t) * fine_src.size());
+  size_t o_coarse = blob.add(coarse.data(), sizeof(float4) * coarse.size());
+  size_t o_es = blob.add(env_s.data(), sizeof(float4) * env_s.size());
+  size_t o_eb = blob.add(env_b.data(), sizeof(float4) * env_b.size());
+
+  mrpop_scene *sc = new mrpop_scene();
+  sc->ctx = ctx;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMalloc(&sc->blob, blob.host.size());
+  if (e != hipSuccess) {
+    delete sc;
+    return hip_fail(ctx, e, "hipMalloc(scene)");
+  }
+  sc->blob_bytes = blob.host.size();
+  e = hipMemcpy(sc->blob, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(sc->blob);
+    delete sc;
+    return hip_fail(ctx, e, "hipMemcpy(scene)");
+  }
+  auto at = [&](size_t off) { return (void *)((unsigned char *)sc->blob + off); };
+  SceneDev &d = sc->dev;
+  d.n_robots = n_robots;
+  d.dof = dof;
+  d.homogeneous = homog ? 1 : 0;
+  d.total_spheres = S;
+  d.model = (const int32_t *)at(o_model);
+  d.q_off = (const int32_t *)at(o_qoff);
+  d.s_out = (const int32_t *)at(o_sout);
+  d.base = (const float *)at(o_base);
+  d.n_models = M;
+  d.sph_stride = sph_stride;
+  d.nj = (const int32_t *)at(o_nj);
+  d.dh = (const float4 *)at(o_dh);
+  d.theta_off = (const float *)at(o_th);
+  d.link_start = (const int32_t *)at(o_ls);
+  d.fine = (const float4 *)at(o_fine);
+  d.fine_src = (const int32_t *)at(o_fsrc);
+  d.coarse = (const float4 *)at(o_coarse);
+  d.n_env_spheres = env->n_spheres;
+  d.n_env_boxes = env->n_boxes;
+  d.env_s = (const float4 *)at(o_es);
+  d.env_b = (const float4 *)at(o_eb);
+  d.origin = float3{(float)org[0], (float)org[1], (float)org[2]};
+  sc->n_robots = n_robots;
+  sc->dof = dof;
+  sc->total_spheres = S;
+  sc->q_lo.resize(dof);
+  sc->q_hi.resize(dof);
+  sc->nj.resize(n_robots);
+  for (int r = 0; r < n_robots; ++r) {
+    sc->nj[r] = robots[r].n_joints;
+    for (int j = 0; j < robots[r].n_joints; ++j) {
+      sc->q_lo[q_off[r] + j] = robots[r].q_lo[j];
+      sc->q_hi[q_off[r] + j] = robots[r].q_hi[j];
+    }
+  }
+  *out = sc;
+  return MRPOP_OK;
+}
+
+void mrpop_scene_destroy(mrpop_scene *scene) {
+  if (!scene) return;
+  if (scene->blob) {
+    hipSetDevice(scene->ctx->device);
+    hipFree(scene->blob);
+  }
+  delete scene;
+}
+
+int32_t mrpop_scene_dof(const mrpop_scene *scene) { return scene ? scene->dof : 0; }
+int32_t mrpop_scene_total_spheres(const mrpop_scene *scene) { return scene ? scene->total_spheres : 0; }
+
+// ---------------------------------------------------------------------------
+// FK and validation
+// ---------------------------------------------------------------------------
+
+mrpop_status mrpop_fk_spheres(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q, int64_t n_cfg,
+                              float *out_xyzr, void *stream) {
+  if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "fk_spheres: ctx is NULL");
+  if (!scene || scene->ctx != ctx) return fail(ctx, MRPOP_E_INVALID_ARG, "fk_spheres: scene not from this ctx");
+  if (n_cfg < 0) return fail(ctx, MRPOP_E_INVALID_ARG, "fk_spheres: n_cfg < 0");
+  if (n_cfg == 0) return MRPOP_OK;
+  if (!q || !out_xyzr) return fail(ctx, MRPOP_E_INVALID_ARG, "fk_spheres: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = launch_fk_spheres(scene->dev, q, n_cfg, out_xyzr, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "fk_spheres launch");
+  return MRPOP_OK;
+}
+
+mrpop_status mrpop_validate_edges(mrpop_ctx *ctx, const mrpop_scene *scene, const float *qa, const float *qb,
+                                  int64_t n_edges, float resolution, const int32_t *n_states_opt,
+                                  uint8_t *out_valid, mrpop_validate_stats *stats_opt, void *stream) {
+  if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "validate_edges: ctx is NULL");
+  if (!scene || scene->ctx != ctx) return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: scene not from this ctx");
+  if (n_edges < 0) return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: n_edges < 0");
+  if (!n_states_opt && !(resolution > 0.f && std::isfinite(resolution)))
+    return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: resolution must be finite and > 0");
+  if (stats_opt) std::memset(stats_opt, 0, sizeof(*stats_opt));
+  if (n_edges == 0) return MRPOP_OK;
+  if (!qa || !qb || !out_valid) return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: NULL buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  void *ws_base = nullptr;
+  mrpop_status st = scratch(ctx, 0, validate_scratch_bytes(n_edges), &ws_base);
+  if (st != MRPOP_OK) return st;
+  ValidateScratch ws = validate_scratch_layout(ws_base, n_edges);
+  hipStream_t s = (hipStream_t)stream;
+  e = launch_validate(scene->dev, qa, qb, n_edges, resolution, n_states_opt, out_valid, ws, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "validate_edges launch");
+  if (stats_opt) {
+    uint64_t c[8];
+    e = hipMemcpyAsync(c, ws.counters, sizeof(c), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "validate_edges stats");
+    stats_opt->edge_states = (int64_t)c[1];
+    stats_opt->states_checked = (int64_t)c[2];
+    stats_opt->tiles = (int64_t)c[3];
+    stats_opt->nonfinite_edges = (int64_t)c[4];
+    stats_opt->edges_invalid = (int64_t)c[5];
+    if (c[6]) return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: an edge has too many states");
+  }
+  return MRPOP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Device helpers shared by the HIP kernels: rigid frames, the modified
+// Denavit-Hartenberg joint step, and small wave utilities.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mrpop_internal.h"
+
+namespace mrpop {
+
+// Rigid transform [R | t] as three rows.
+struct Frame {
+  float r00, r01, r02, t0;
+  float r10, r11, r12, t1;
+  float r20, r21, r22, t2;
+};
+
+__device__ __forceinline__ Frame load_frame(const float *__restrict__ p) {
+  Frame f;
+  f.r00 = p[0]; f.r01 = p[1]; f.r02 = p[2]; f.t0 = p[3];
+  f.r10 = p[4]; f.r11 = p[5]; f.r12 = p[6]; f.t1 = p[7];
+  f.r20 = p[8]; f.r21 = p[9]; f.r22 = p[10]; f.t2 = p[11];
+  return f;
+}
+
+// One row of T_{j-1} times the joint transform
+//   A = RotX(alpha) TransX(a) RotZ(theta) TransZ(d)
+//     = [[c, -s, 0, a], [ca s, ca c, -sa, -sa d], [sa s, sa c, ca, ca d]],
+// written with u = R1 ca + R2 sa (the rotated second column).
+__device__ __forceinline__ void row_step(float &R0, float &R1, float &R2, float &t, float a, float d, float ca,
+                                         float sa, float c, float s) {
+  const float u = fmaf(R1, ca, R2 * sa);
+  const float n2 = fmaf(R2, ca, -(R1 * sa));
+  const float n0 = fmaf(R0, c, u * s);
+  const float n1 = fmaf(u, c, -(R0 * s));
+  t = fmaf(n2, d, fmaf(R0, a, t));
+  R0 = n0;
+  R1 = n1;
+  R2 = n2;
+}
+
+// T_j = T_{j-1} RotX(alpha_{j-1}) TransX(a_{j-1}) RotZ(theta_j) TransZ(d_j)
+// (Craig's modified convention).  dh = (a, d, cos alpha, sin alpha).
+__device__ __forceinline__ void joint_step(Frame &T, float4 dh, float theta) {
+  float s, c;
+  sincosf(theta, &s, &c);
+  row_step(T.r00, T.r01, T.r02, T.t0, dh.x, dh.y, dh.z, dh.w, c, s);
+  row_step(T.r10, T.r11, T.r12, T.t1, dh.x, dh.y, dh.z, dh.w, c, s);
+  row_step(T.r20, T.r21, T.r22, T.t2, dh.x, dh.y, dh.z, dh.w, c, s);
+}
+
+__device__ __forceinline__ float3 apply(const Frame &T, float x, float y, float z) {
+  return make_float3(fmaf(T.r00, x, fmaf(T.r01, y, fmaf(T.r02, z, T.t0))),
+                     fmaf(T.r10, x, fmaf(T.r11, y, fmaf(T.r12, z, T.t1))),
+                     fmaf(T.r20, x, fmaf(T.r21, y, fmaf(T.r22, z, T.t2))));
+}
+
+// Squared distance from p to an axis-aligned box: sum of squared per-axis
+// excesses max(lo - p, p - hi, 0).
+__device__ __forceinline__ float box_dist2(float3 p, float4 lo, float4 hi) {
+  const float ex = fmaxf(fmaxf(lo.x - p.x, p.x - hi.x), 0.f);
+  const float ey = fmaxf(fmaxf(lo.y - p.y, p.y - hi.y), 0.f);
+  const float ez = fmaxf(fmaxf(lo.z - p.z, p.z - hi.z), 0.f);
+  return fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+}
+
+__device__ __forceinline__ float dist2(float3 a, float4 b) {
+  const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+  return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+__device__ __forceinline__ float dist2(float3 a, float3 b) {
+  const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+  return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace mrpop

@@ -1,0 +1,103 @@
+// Internal declarations of the MR. POP HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mrpop.h"
+
+namespace mrpop {
+
+constexpr int kMaxJoints = MRPOP_MAX_JOINTS;
+constexpr int kMaxLinks = MRPOP_MAX_JOINTS + 1;
+constexpr int kWave = 64;
+
+// Device-side view of a scene, passed to kernels by value.
+//
+// Arms share one kinematic model when the scene is homogeneous (the common
+// case: a team of identical arms); the kernels then read every model field
+// with wave-uniform addresses (scalar loads).  Otherwise each arm carries its
+// own model and the same fields are read per lane.
+struct SceneDev {
+  int32_t n_robots;
+  int32_t dof;
+  int32_t homogeneous;     // 1 if every arm uses model 0
+  int32_t total_spheres;
+  // per arm
+  const int32_t *model;    // [R] model index
+  const int32_t *q_off;    // [R] offset of the arm's joints in q
+  const int32_t *s_out;    // [R] offset of the arm's spheres in FK output order
+  const float *base;       // [R][12] world-from-base (recentred world frame)
+  // per model (stride kMaxLinks / kMaxJoints / max spheres)
+  int32_t n_models;
+  int32_t sph_stride;      // spheres per model slot (max over models)
+  const int32_t *nj;       // [M]
+  const float4 *dh;        // [M][kMaxJoints]: a, d, cos(alpha), sin(alpha)
+  const float *theta_off;  // [M][kMaxJoints]
+  const int32_t *link_start;  // [M][kMaxLinks + 1] fine spheres grouped by link
+  const float4 *fine;      // [M][sph_stride] link-local x, y, z, r (grouped by link)
+  const int32_t *fine_src; // [M][sph_stride] index of the sphere in the input order
+  const float4 *coarse;    // [M][kMaxLinks] link-local centre, radius (r < 0: empty link)
+  // environment
+  int32_t n_env_spheres;
+  int32_t n_env_boxes;
+  const float4 *env_s;     // [Ns] x, y, z, r (recentred)
+  const float4 *env_b;     // [Nb][2] (lo x, lo y, lo z, 0), (hi x, hi y, hi z, 0) (recentred)
+  float3 origin;           // world = recentred + origin
+};
+
+struct DeviceBuffer {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace mrpop
+
+struct mrpop_ctx {
+  int device = 0;
+  std::string last_error;
+  // Scratch reused across calls (grown on demand).
+  mrpop::DeviceBuffer scratch[8];
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+};
+
+struct mrpop_scene {
+  mrpop_ctx *ctx = nullptr;
+  mrpop::SceneDev dev{};
+  void *blob = nullptr;            // one device allocation holding every array
+  size_t blob_bytes = 0;
+  // host copies used by the planner driver
+  std::vector<float> q_lo, q_hi;   // [D]
+  std::vector<int32_t> nj;         // per arm
+  int32_t n_robots = 0, dof = 0, total_spheres = 0;
+};
+
+namespace mrpop {
+
+// Record an error message on the context and return the status.
+mrpop_status fail(mrpop_ctx *ctx, mrpop_status st, const std::string &msg);
+// Map a HIP error to E_DEVICE (or E_NOMEM) with the call site in the message.
+mrpop_status hip_fail(mrpop_ctx *ctx, hipError_t e, const char *what);
+// Ensure scratch slot `slot` holds at least `bytes`.
+mrpop_status scratch(mrpop_ctx *ctx, int slot, size_t bytes, void **out);
+
+// Kernel launchers (host functions defined next to their kernels).
+hipError_t launch_fk_spheres(const SceneDev &sc, const float *q, int64_t n_cfg, float *out, hipStream_t s);
+
+struct ValidateScratch {
+  int32_t *n_states;     // [E]
+  int64_t *offsets;      // [E + 1]
+  uint32_t *flags;       // [E] bit 0: collides, bit 1: non-finite
+  uint64_t *counters;    // [8]: 0 tile queue, 1 total states, 2 states checked, 3 tiles, 4 nonfinite
+  int64_t *block_sums;   // scan partials
+};
+size_t validate_scratch_bytes(int64_t n_edges);
+ValidateScratch validate_scratch_layout(void *base, int64_t n_edges);
+hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb, int64_t n_edges, float res,
+                           const int32_t *n_states_opt, uint8_t *out_valid, const ValidateScratch &ws,
+                           hipStream_t s);
+
+}  // namespace mrpop

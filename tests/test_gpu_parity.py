@@ -1,0 +1,173 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle:
+forward kinematics to 4e-6 m, edge bits exact outside the 1e-5 m band."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_common import BAND, assert_bits_match, problem
+
+pytestmark = pytest.mark.gpu
+
+FK_TOL = 4e-6  # metres; half the boundary band minus rounding of the tests
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2609_30644_amd as M
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+def _scene(ctx, sc):
+    import paper_2609_30644_amd as M
+    return M.Scene(ctx, sc)
+
+
+def _fk_err(ctx, sc, q):
+    got = _scene(ctx, sc).fk_spheres(q).cpu().numpy().astype(np.float64)
+    want = oracle.fk_spheres(sc, q)
+    assert got.shape == want.shape
+    np.testing.assert_array_equal(got[..., 3], want[..., 3].astype(np.float32))
+    return np.abs(got[..., :3] - want[..., :3]).max()
+
+
+@pytest.mark.parametrize("kind", ["c1", "c2", "c3"])
+def test_fk_parity(ctx, kind):
+    print(f"[fk_parity] {kind}", flush=True)
+    sc = problem(kind).scene
+    q = W.random_configs(sc, 512, np.random.default_rng(11))
+    assert _fk_err(ctx, sc, q) <= FK_TOL
+
+
+def test_fk_planar_closed_form(ctx):
+    sc = W.Scene([W.planar_two_link(0.6, 0.4)], W.base_transform(0.2, -0.1, 0.3)[None],
+                 np.zeros((0, 4), np.float32), np.zeros((0, 6), np.float32))
+    q = np.random.default_rng(0).uniform(-3, 3, (257, 2)).astype(np.float32)
+    out = _scene(ctx, sc).fk_spheres(q).cpu().numpy().astype(np.float64)
+    q64 = q.astype(np.float64)
+    f = lambda v: float(np.float32(v))
+    a = q64[:, 0] + 0.3
+    x = f(0.6) * np.cos(a) + f(0.4) * np.cos(a + q64[:, 1])
+    y = f(0.6) * np.sin(a) + f(0.4) * np.sin(a + q64[:, 1])
+    np.testing.assert_allclose(out[:, 1, 0], f(0.2) + x, atol=FK_TOL)
+    np.testing.assert_allclose(out[:, 1, 1], f(-0.1) + y, atol=FK_TOL)
+
+
+def test_fk_empty_and_order(ctx):
+    sc = problem("c1").scene
+    s = _scene(ctx, sc)
+    assert s.fk_spheres(np.zeros((0, sc.dof), np.float32)).shape == (0, sc.n_robots * 20, 4)
+    # spheres come back in input order: radii match the model per robot
+    out = s.fk_spheres(np.zeros((1, sc.dof), np.float32)).cpu().numpy()
+    np.testing.assert_array_equal(out[0, :20, 3], sc.models[0].sphere_xyzr[:, 3])
+
+
+def _parity(ctx, sc, qa, qb, res, what, n_states=None):
+    print(f"[validate_parity] {what}: {qa.shape[0]} edges", flush=True)
+    valid, st = _scene(ctx, sc).validate_edges(qa, qb, res, n_states=n_states, stats=True)
+    valid = valid.cpu().numpy()
+    n, m = oracle.classify_edges(sc, qa, qb, res, nstates=n_states)
+    info = assert_bits_match(valid, m, what)
+    assert st.edge_states == int(n.sum())
+    assert st.edges_invalid == int((valid == 0).sum())
+    print(f"  {info} states={st.edge_states} checked={st.states_checked}", flush=True)
+    return valid, m, st
+
+
+@pytest.mark.parametrize("kind,res", [("c1", 0.05), ("c2", 0.05), ("c3", 0.02)])
+def test_validate_random_edges(ctx, kind, res):
+    sc = problem(kind).scene
+    E = 1024 if kind != "c3" else 256
+    qa, qb = W.edge_batch(sc, E, res, 100, 8, 64)
+    _parity(ctx, sc, qa, qb, res, f"{kind}/random")
+
+
+@pytest.mark.parametrize("kind,res", [("c1", 0.05), ("c2", 0.05), ("c3", 0.02)])
+def test_validate_near_free_edges(ctx, kind, res):
+    """Edges anchored at oracle-free states: a real mix of free and colliding
+    edges, so both bit values are exercised."""
+    p = problem(kind)
+    sc = p.scene
+    rng = np.random.default_rng(5)
+    anchors = W.random_configs(sc, 4000 if kind != "c3" else 1500, rng)
+    anchors = anchors[oracle.states_free(sc, anchors)]
+    anchors = np.concatenate([anchors, p.q_start[None], p.q_goal[None]])
+    E = 1024 if kind != "c3" else 256
+    qa, qb = W.edge_batch_near(sc, anchors, E, res, 101, 2, 40, spread=0.02)
+    valid, m, _ = _parity(ctx, sc, qa, qb, res, f"{kind}/near")
+    assert 0 < valid.sum() < E, "batch should mix free and colliding edges"
+
+
+def test_validate_c2_full_batch(ctx):
+    """4096 edges at the workload's full batch size, every edge checked."""
+    p = problem("c2")
+    sc = p.scene
+    rng = np.random.default_rng(6)
+    anchors = W.random_configs(sc, 6000, rng)
+    anchors = anchors[oracle.states_free(sc, anchors)]
+    qa, qb = W.edge_batch_near(sc, anchors, 4096, 0.05, 102, 8, 64, spread=0.02)
+    _parity(ctx, sc, qa, qb, 0.05, "c2/full")
+
+
+def test_validate_degenerate_edges(ctx):
+    p = problem("c2")
+    sc = p.scene
+    q = np.stack([p.q_start, p.q_goal])
+    # null edges (n = 1), an explicit state count, and a NaN endpoint
+    valid, st = _scene(ctx, sc).validate_edges(q, q, 0.05, stats=True)
+    assert valid.cpu().numpy().tolist() == [1, 1] and st.edge_states == 2
+    qa = np.stack([p.q_start, p.q_start, p.q_start])
+    qb = np.stack([p.q_goal, p.q_goal, p.q_goal])
+    qb[2, 3] = np.nan
+    ns = np.array([1, 7, 5], np.int32)
+    valid, st = _scene(ctx, sc).validate_edges(qa, qb, 0.05, n_states=ns, stats=True)
+    v = valid.cpu().numpy()
+    assert v[2] == 0 and st.nonfinite_edges == 1
+    n, m = oracle.classify_edges(sc, qa[:2], qb[:2], 0.05, nstates=ns[:2])
+    assert_bits_match(v[:2], m, "explicit n")
+    assert st.edge_states == 1 + 7
+
+
+def test_validate_empty_batch(ctx):
+    sc = problem("c1").scene
+    z = np.zeros((0, sc.dof), np.float32)
+    valid, st = _scene(ctx, sc).validate_edges(z, z, 0.05, stats=True)
+    assert valid.numel() == 0 and st.edge_states == 0
+
+
+def test_validate_long_edges_span_many_tiles(ctx):
+    p = problem("c1")
+    sc = p.scene
+    rng = np.random.default_rng(7)
+    anchors = W.random_configs(sc, 3000, rng)
+    anchors = anchors[oracle.states_free(sc, anchors)]
+    qa, qb = W.edge_batch_near(sc, anchors, 64, 0.002, 103, 300, 700, spread=0.0)
+    _parity(ctx, sc, qa, qb, 0.002, "c1/long")
+
+
+def test_validate_single_arm_and_mixed_models(ctx):
+    rng = np.random.default_rng(8)
+    one = W.Scene([W.panda_like(59)], W.base_transform(0, 0, 0)[None],
+                  np.array([[0.4, 0.2, 0.5, 0.1], [-0.3, -0.4, 0.8, 0.12]], np.float32),
+                  np.array([[0.3, -0.5, 0.0, 0.6, -0.2, 0.4]], np.float32))
+    qa, qb = W.edge_batch(one, 512, 0.05, 104, 2, 30)
+    _parity(ctx, one, qa, qb, 0.05, "single arm")
+    mixed = W.Scene([W.panda_like(20), W.panda_like(59), W.planar_two_link()],
+                    np.stack([W.base_transform(-0.5, 0, 0), W.base_transform(0.5, 0, math.pi),
+                              W.base_transform(0.0, 0.6, -math.pi / 2, 0.4)]),
+                    np.array([[0.0, 0.0, 0.6, 0.1]], np.float32), np.array([[0.1, 0.3, 0.0, 0.3, 0.5, 0.2]], np.float32))
+    qa, qb = W.edge_batch(mixed, 512, 0.05, 105, 2, 30)
+    _parity(ctx, mixed, qa, qb, 0.05, "mixed models")
+
+
+def test_validate_deterministic(ctx):
+    sc = problem("c2").scene
+    qa, qb = W.edge_batch(sc, 2048, 0.05, 106, 8, 64)
+    s = _scene(ctx, sc)
+    a = s.validate_edges(qa, qb, 0.05).cpu().numpy()
+    b = s.validate_edges(qa, qb, 0.05).cpu().numpy()
+    assert (a == b).all()

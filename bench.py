@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Benchmark of the MR. POP hot path on one MI355X.
+
+Workload (4 arms x 7-DoF, 59 spheres per arm, 32 spheres + 32 boxes,
+0.05 rad resolution): every step validates two batches of 4096 composite
+edges with ``mrpop_validate_edges`` -- one whose edges are all certainly free
+(every state must be fully checked) and one drawn the same way without
+selection (mostly colliding, early exit applies) -- and, once the planner is
+built, runs a plan.  Inputs sit in device memory before the timed region.
+
+Printed: one JSON line with edge-states per second, the roofline of the
+edge-validation tile kernel (executed algorithmic flops / its HIP-event
+time, against the FP32 vector peak) and the oracle's CPU rate on a sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FIXTURE = os.path.join(ROOT, "tests", "golden", "c2_bench.json")
+METRIC = "composite edge-states validated/sec + p50 time-to-solution; batched vs plain"
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 flop/clk)
+
+# Flops per operation (FMA = 2): a modified-DH joint step updates three rows
+# of a 3x4 frame at 16 flops each; a point transform is 9 FMAs; a
+# sphere-sphere test is 3 sub + 1 mul + 2 FMA + (r1 + r2)^2 (add, mul); a
+# sphere-box test is 2 sub + 2 max per axis and a 3-term sum of squares.
+F_JOINT, F_XFORM, F_SS, F_SB = 48, 18, 10, 17
+
+
+def load_workload():
+    import workloads as W
+    d = json.load(open(FIXTURE))
+    sc = W.scene_c2(d["scene_seed"]).with_env(np.array(d["env_spheres"], np.float32),
+                                              np.array(d["env_boxes"], np.float32))
+    anchors = W.random_configs(sc, d["anchor_draws"], np.random.default_rng([d["anchor_seed"]]))
+    anchors = anchors[np.array(d["anchor_free_idx"])]
+    qa, qb = W.edge_batch_near(sc, anchors, d["pool"], d["resolution"], d["pool_seed"], d["n_min"], d["n_max"],
+                               spread=d["spread"])
+    free = np.array(d["free_edge_idx"])
+    batches = {"free": (qa[free], qb[free]), "mixed": (qa[:4096], qb[:4096])}
+    return sc, batches, d
+
+
+def algorithmic_flops(work: dict, scene) -> float:
+    """Flops of the operations the kernel executed, by the model above."""
+    nj = scene.models[0].n_joints
+    # chains: nj joint steps; links: coarse centre transforms; env tests:
+    # coarse link-obstacle sphere tests (obstacle spheres and box bounding
+    # spheres); exact link-box tests where those passed; then the fine tests
+    return (work["chains"] * nj * F_JOINT + work["links"] * F_XFORM + work["env_tests"] * F_SS
+            + work["box_exact"] * F_SB + work["rr_coarse"] * F_SS + work["fine_sphere"] * F_SS
+            + work["fine_box"] * F_SB + work["fine_rr"] * F_SS)
+
+
+def cpu_baseline(scene, batches, res, target_s: float) -> dict:
+    """The oracle's coarse-to-fine checker (early exit) on a bounded sample of
+    the same two batches, on the host cores."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    sc = oracle.OracleScene(scene)
+
+    def run(k, passes=1):
+        t0 = time.perf_counter()
+        states = 0
+        for _ in range(passes):
+            for name in ("free", "mixed"):
+                qa, qb = batches[name]
+                _, n, _ = oracle.validate_fast(sc, qa[:k], qb[:k], res, threads=threads)
+                states += int(n.sum())
+        return states, time.perf_counter() - t0
+
+    k, passes = 64, 1
+    states, dt = run(k)
+    while dt < target_s / 2:
+        if k < 4096:
+            k = min(4096, int(k * max(2.0, target_s / max(dt, 1e-3) / 2)))
+        else:
+            passes = max(passes + 1, int(passes * target_s / max(dt, 1e-3)))
+        states, dt = run(k, passes)
+    return {"value": states / dt, "unit": "edge-states/s", "cores": threads, "kind": "oracle",
+            "sample": f"{passes} pass(es) over the first {k} edges of each batch ({states} edge-states), "
+                      f"FP64 coarse-to-fine checker with early exit, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2609_30644_amd as M
+
+    scene, batches, fx = load_workload()
+    res = float(fx["resolution"])
+    print(f"[bench] workload loaded: free {batches['free'][0].shape}, mixed {batches['mixed'][0].shape}",
+          file=sys.stderr, flush=True)
+    ctx = M.Context(0)
+    s = M.Scene(ctx, scene)
+    dev = {k: (ctx.to_device(a), ctx.to_device(b)) for k, (a, b) in batches.items()}
+    outs = {k: torch.empty(a.shape[0], dtype=torch.uint8, device=ctx.device) for k, (a, _) in dev.items()}
+    nominal = {}
+    for k, (a, b) in dev.items():
+        _, st = s.validate_edges(a, b, res, out=outs[k], stats=True)
+        nominal[k] = st.edge_states
+    states_per_step = sum(nominal.values())
+
+    def step():
+        for k, (a, b) in dev.items():
+            s.validate_edges(a, b, res, out=outs[k])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    flops = algorithmic_flops(prof.work, scene)
+    achieved = flops / (prof.kernel_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "kernel": "validate_tiles_kernel", "launches": prof.launches,
+                "avg_launch_us": prof.kernel_ms * 1e3 / max(1, prof.launches),
+                "flops_per_launch": flops / max(1, prof.launches),
+                "grid": [prof.grid_blocks, prof.block_threads], "work": prof.work}
+    value = states_per_step * args.steps / elapsed
+    line = {
+        "metric": METRIC, "value": value, "unit": "edge-states/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "4 arms x 7-DoF (59 spheres/arm), 32 spheres + 32 boxes, res 0.05 rad; "
+                               "per step 4096 certainly-free + 4096 unselected composite edges",
+                   "edge_states_per_step": states_per_step, "edges_per_step": 8192,
+                   "free_batch_states": nominal["free"], "mixed_batch_states": nominal["mixed"]},
+        "roofline": roofline,
+        "states_checked_frac": prof.states_checked / max(1, prof.edge_states),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(scene, batches, res, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

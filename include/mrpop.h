@@ -36,7 +36,7 @@ extern "C" {
 
 #define MRPOP_MAX_JOINTS 7         /* joints per arm (links 0..7)            */
 #define MRPOP_MAX_SPHERES 256      /* collision spheres per arm              */
-#define MRPOP_MAX_ROBOTS 32        /* arms per scene                          */
+#define MRPOP_MAX_ROBOTS 16        /* arms per scene                          */
 #define MRPOP_MAX_ENV 65536        /* environment spheres and boxes, each    */
 #define MRPOP_MAX_STATES_PER_EDGE (1 << 24)
 
@@ -133,6 +133,11 @@ typedef struct {
   int64_t edges_invalid;  /* edges with out_valid == 0                       */
   int64_t nonfinite_edges;/* edges rejected for NaN/inf endpoints            */
   int64_t tiles;          /* work tiles processed                            */
+  /* Work executed: kinematic chains (arm x state), coarse link centres
+   * placed, coarse link-obstacle sphere tests (environment spheres and box
+   * bounding spheres), exact link-box tests, coarse link-link tests, fine
+   * sphere-sphere, sphere-box and arm-arm sphere tests. */
+  int64_t work[8];
 } mrpop_validate_stats;
 
 /* Decide for each composite edge (qa[e], qb[e]) whether the straight motion
@@ -161,6 +166,30 @@ typedef struct {
 mrpop_status mrpop_validate_edges(mrpop_ctx *ctx, const mrpop_scene *scene, const float *qa, const float *qb,
                                   int64_t n_edges, float resolution, const int32_t *n_states_opt,
                                   uint8_t *out_valid, mrpop_validate_stats *stats_opt, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel profiling                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Totals over the launches of the edge-validation tile kernel made on `ctx`
+ * since profiling was (re-)enabled: launch count, summed kernel time taken
+ * from HIP events recorded on the launch stream right before and after each
+ * tile-kernel launch, and the states the kernel evaluated and was given. */
+typedef struct {
+  int64_t launches;
+  double kernel_ms;
+  int64_t states_checked;
+  int64_t edge_states;
+  int64_t work[8];        /* as mrpop_validate_stats.work, summed */
+  int32_t grid_blocks;    /* workgroups of the last tile-kernel launch      */
+  int32_t block_threads;  /* threads per workgroup                          */
+} mrpop_kernel_profile;
+
+/* enable != 0 starts recording (and clears the totals); 0 stops. */
+mrpop_status mrpop_profile_enable(mrpop_ctx *ctx, int enable);
+/* Waits for the recorded events and fills `out`.  E_INVALID_ARG if out is
+ * NULL. */
+mrpop_status mrpop_profile_read(mrpop_ctx *ctx, mrpop_kernel_profile *out);
 
 #ifdef __cplusplus
 }

@@ -10,9 +10,11 @@ from ._binding import (  # noqa: F401
     Context,
     Scene,
     ValidateStats,
+    KernelProfile,
+    WORK_NAMES,
     lib_path,
     load_library,
     STATUS_NAMES,
 )
 
-__all__ = ["MrpopError", "Context", "Scene", "ValidateStats", "lib_path", "load_library", "STATUS_NAMES"]
+__all__ = ["MrpopError", "Context", "Scene", "ValidateStats", "KernelProfile", "WORK_NAMES", "lib_path", "load_library", "STATUS_NAMES"]

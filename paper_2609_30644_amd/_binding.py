@@ -45,7 +45,16 @@ class _Env(C.Structure):
 
 class _ValidateStats(C.Structure):
     _fields_ = [("edge_states", C.c_int64), ("states_checked", C.c_int64), ("edges_invalid", C.c_int64),
-                ("nonfinite_edges", C.c_int64), ("tiles", C.c_int64)]
+                ("nonfinite_edges", C.c_int64), ("tiles", C.c_int64), ("work", C.c_int64 * 8)]
+
+
+class _KernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("kernel_ms", C.c_double), ("states_checked", C.c_int64),
+                ("edge_states", C.c_int64), ("work", C.c_int64 * 8), ("grid_blocks", C.c_int32),
+                ("block_threads", C.c_int32)]
+
+
+WORK_NAMES = ("chains", "links", "env_tests", "box_exact", "rr_coarse", "fine_sphere", "fine_box", "fine_rr")
 
 
 @dataclass
@@ -55,6 +64,18 @@ class ValidateStats:
     edges_invalid: int
     nonfinite_edges: int
     tiles: int
+    work: dict
+
+
+@dataclass
+class KernelProfile:
+    launches: int
+    kernel_ms: float
+    states_checked: int
+    edge_states: int
+    work: dict
+    grid_blocks: int = 0
+    block_threads: int = 0
 
 
 _lib = None
@@ -87,6 +108,8 @@ def load_library():
     lib.mrpop_scene_total_spheres.restype = I32
     lib.mrpop_fk_spheres.argtypes = [P, P, P, I64, P, P]
     lib.mrpop_validate_edges.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
+    lib.mrpop_profile_enable.argtypes = [P, C.c_int]
+    lib.mrpop_profile_read.argtypes = [P, P]
     _lib = lib
     return lib
 
@@ -151,6 +174,15 @@ class Context:
 
     def stream(self) -> int:
         return _stream_ptr(self.device)
+
+    def profile_enable(self, on: bool = True) -> None:
+        self.check(self._lib.mrpop_profile_enable(self._h, int(on)))
+
+    def profile_read(self) -> "KernelProfile":
+        p = _KernelProfile()
+        self.check(self._lib.mrpop_profile_read(self._h, C.byref(p)))
+        return KernelProfile(p.launches, p.kernel_ms, p.states_checked, p.edge_states,
+                             dict(zip(WORK_NAMES, list(p.work))), p.grid_blocks, p.block_threads)
 
 
 class Scene:
@@ -230,7 +262,7 @@ class Scene:
             self.ctx.stream()))
         if stats:
             return out, ValidateStats(st.edge_states, st.states_checked, st.edges_invalid, st.nonfinite_edges,
-                                      st.tiles)
+                                      st.tiles, dict(zip(WORK_NAMES, list(st.work))))
         return out
 
     def states_free(self, q) -> np.ndarray:

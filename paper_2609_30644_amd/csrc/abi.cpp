@@ -46,6 +46,20 @@ mrpop_status scratch(mrpop_ctx *ctx, int slot, size_t bytes, void **out) {
   return MRPOP_OK;
 }
 
+const std::pair<hipEvent_t, hipEvent_t> *profile_slot(mrpop_ctx *ctx) {
+  if (!ctx->profiling) return nullptr;
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
+    if (hipEventCreate(&p.first) != hipSuccess) return nullptr;
+    if (hipEventCreate(&p.second) != hipSuccess) {
+      hipEventDestroy(p.first);
+      return nullptr;
+    }
+    ctx->ev_pool.push_back(p);
+  }
+  return &ctx->ev_pool[ctx->ev_used++];
+}
+
 }  // namespace mrpop
 
 using namespace mrpop;
@@ -74,9 +88,74 @@ void mrpop_ctx_destroy(mrpop_ctx *ctx) {
   hipSetDevice(ctx->device);
   for (auto &b : ctx->scratch)
     if (b.ptr) hipFree(b.ptr);
-  if (ctx->ev_a) hipEventDestroy(ctx->ev_a);
-  if (ctx->ev_b) hipEventDestroy(ctx->ev_b);
+  for (auto &p : ctx->ev_pool) {
+    hipEventDestroy(p.first);
+    hipEventDestroy(p.second);
+  }
+  if (ctx->prof_totals) hipFree(ctx->prof_totals);
   delete ctx;
+}
+
+mrpop_status mrpop_profile_enable(mrpop_ctx *ctx, int enable) {
+  if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "profile_enable: ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  ctx->profiling = enable != 0;
+  ctx->ev_used = 0;
+  ctx->prof_ms = 0.0;
+  ctx->prof_launches = 0;
+  if (enable) {
+    if (!ctx->prof_totals) {
+      e = hipMalloc((void **)&ctx->prof_totals, 10 * sizeof(uint64_t));
+      if (e != hipSuccess) {
+        ctx->prof_totals = nullptr;
+        ctx->profiling = false;
+        return hip_fail(ctx, e, "hipMalloc(profile)");
+      }
+    }
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemset(ctx->prof_totals, 0, 10 * sizeof(uint64_t));
+    if (e != hipSuccess) return hip_fail(ctx, e, "profile_enable");
+  }
+  return MRPOP_OK;
+}
+
+// Sum the elapsed time of the recorded event pairs and recycle them.
+static mrpop_status drain_events(mrpop_ctx *ctx) {
+  for (size_t i = 0; i < ctx->ev_used; ++i) {
+    hipError_t e = hipEventSynchronize(ctx->ev_pool[i].second);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->ev_pool[i].first, ctx->ev_pool[i].second);
+    if (e != hipSuccess) return hip_fail(ctx, e, "profile events");
+    ctx->prof_ms += ms;
+    ctx->prof_launches++;
+  }
+  ctx->ev_used = 0;
+  return MRPOP_OK;
+}
+
+mrpop_status mrpop_profile_read(mrpop_ctx *ctx, mrpop_kernel_profile *out) {
+  if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "profile_read: ctx is NULL");
+  if (!out) return fail(ctx, MRPOP_E_INVALID_ARG, "profile_read: out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  mrpop_status st = drain_events(ctx);
+  if (st != MRPOP_OK) return st;
+  out->launches = ctx->prof_launches;
+  out->kernel_ms = ctx->prof_ms;
+  out->grid_blocks = ctx->last_grid;
+  out->block_threads = ctx->last_block;
+  if (ctx->prof_totals) {
+    uint64_t t[10];
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(t, ctx->prof_totals, sizeof(t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "profile_read");
+    out->states_checked = (int64_t)t[0];
+    out->edge_states = (int64_t)t[1];
+    for (int i = 0; i < 8; ++i) out->work[i] = (int64_t)t[2 + i];
+  }
+  return MRPOP_OK;
 }
 
 const char *mrpop_last_error(const mrpop_ctx *ctx) {
@@ -256,6 +335,106 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
     env_b[2 * k + 1] = float4{(float)((double)b[3] - org[0]), (float)((double)b[4] - org[1]), (float)((double)b[5] - org[2]), 0.f};
   }
 
+  // Expanded-form coarse filter tables (see SceneDev).  delta covers the
+  // rounding error of the single-precision expanded test: near a contact every
+  // point involved lies within M of the origin, the table entry is rounded
+  // once (|B| <= 2 M^2), the three FMAs round partial sums of size <= 4 M^2
+  // and -|c|^2 takes three roundings of size <= M^2, so the computed value of
+  // d^2 - R^2 is off by at most eps = 20 u M^2 (u = 2^-24).  Testing against
+  // R' = sqrt(R^2 + eps) keeps every true contact, and R' - R is at most
+  // min(sqrt(eps), eps / (2 R)).
+  double reach = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const mrpop_robot &rb = *models[m];
+    double chain = 0.0, far = 0.0;
+    for (int j = 0; j < rb.n_joints; ++j) chain += std::hypot((double)rb.dh[4 * j], (double)rb.dh[4 * j + 1]);
+    for (int i = 0; i < rb.n_spheres; ++i)
+      far = std::max(far, std::hypot(std::hypot((double)rb.sphere_xyzr[4 * i], (double)rb.sphere_xyzr[4 * i + 1]),
+                                     (double)rb.sphere_xyzr[4 * i + 2]) + (double)rb.sphere_xyzr[4 * i + 3]);
+    reach = std::max(reach, chain + far);
+  }
+  double base_far = 0.0, obs_r = 0.0, rc_min = INFINITY;
+  for (int r = 0; r < n_robots; ++r)
+    base_far = std::max(base_far, std::hypot(std::hypot((double)base[(size_t)r * 12 + 3], (double)base[(size_t)r * 12 + 7]),
+                                             (double)base[(size_t)r * 12 + 11]));
+  std::vector<double> box_rad(std::max(1, env->n_boxes));
+  for (int k = 0; k < env->n_spheres; ++k) obs_r = std::max(obs_r, (double)env->spheres[4 * k + 3]);
+  for (int k = 0; k < env->n_boxes; ++k) {
+    const float *b = env->boxes + 6 * k;
+    box_rad[k] = 0.5 * std::sqrt((double)(b[3] - b[0]) * (b[3] - b[0]) + (double)(b[4] - b[1]) * (b[4] - b[1]) +
+                                 (double)(b[5] - b[2]) * (b[5] - b[2]));
+    obs_r = std::max(obs_r, box_rad[k]);
+  }
+  double rc_max = 0.0;
+  for (const float4 &cv : coarse)
+    if (cv.w >= 0) { rc_min = std::min(rc_min, (double)cv.w); rc_max = std::max(rc_max, (double)cv.w); }
+  const double Mx = base_far + reach + rc_max + obs_r;
+  const double eps = 20.0 * std::ldexp(1.0, -24) * Mx * Mx;
+  const double delta = std::max(1e-4, std::min(std::sqrt(eps), eps / (2.0 * std::max(rc_min, 1e-30))));
+  static_assert(kRowFloats >= 3 + kMaxLinks, "row too short");
+  std::vector<float> sph_rows((size_t)M * std::max(1, env->n_spheres) * kRowFloats, 0.f);
+  std::vector<float> box_rows((size_t)M * std::max(1, env->n_boxes) * kRowFloats, 0.f);
+  for (int m = 0; m < M; ++m) {
+    for (int k = 0; k < env->n_spheres; ++k) {
+      const float4 o = env_s[k];
+      float *row = &sph_rows[((size_t)m * env->n_spheres + k) * kRowFloats];
+      row[0] = -2.f * o.x; row[1] = -2.f * o.y; row[2] = -2.f * o.z;
+      const double o2 = (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z;
+      for (int l = 0; l < kMaxLinks; ++l) {
+        const float4 cv = coarse[(size_t)m * kMaxLinks + l];
+        if (cv.w < 0 || l > models[m]->n_joints) { row[3 + l] = 3.0e38f; continue; }
+        const double R = (double)cv.w + (double)o.w + delta;
+        row[3 + l] = (float)(o2 - R * R);
+      }
+    }
+    for (int k = 0; k < env->n_boxes; ++k) {
+      const float4 lo = env_b[2 * k], hi = env_b[2 * k + 1];
+      const float mx = 0.5f * (lo.x + hi.x), my = 0.5f * (lo.y + hi.y), mz = 0.5f * (lo.z + hi.z);
+      // radius from the rounded centre to the farthest corner
+      double far = 0.0;
+      for (int cx = 0; cx < 2; ++cx)
+        for (int cy = 0; cy < 2; ++cy)
+          for (int cz = 0; cz < 2; ++cz) {
+            const double dx = (double)(cx ? hi.x : lo.x) - mx, dy = (double)(cy ? hi.y : lo.y) - my,
+                         dz = (double)(cz ? hi.z : lo.z) - mz;
+            far = std::max(far, std::sqrt(dx * dx + dy * dy + dz * dz));
+          }
+      float *row = &box_rows[((size_t)m * env->n_boxes + k) * kRowFloats];
+      row[0] = -2.f * mx; row[1] = -2.f * my; row[2] = -2.f * mz;
+      const double m2 = (double)mx * mx + (double)my * my + (double)mz * mz;
+      for (int l = 0; l < kMaxLinks; ++l) {
+        const float4 cv = coarse[(size_t)m * kMaxLinks + l];
+        if (cv.w < 0 || l > models[m]->n_joints) { row[3 + l] = 3.0e38f; continue; }
+        const double R = (double)cv.w + far + delta;
+        row[3 + l] = (float)(m2 - R * R);
+      }
+    }
+  }
+
+  // Arm pairs that can touch: base distance at most the sum of reach bounds.
+  std::vector<double> reach_of(M, 0.0);
+  for (int m = 0; m < M; ++m) {
+    const mrpop_robot &rb = *models[m];
+    double chain = 0.0, far = 0.0;
+    for (int j = 0; j < rb.n_joints; ++j) chain += std::hypot((double)rb.dh[4 * j], (double)rb.dh[4 * j + 1]);
+    for (int i = 0; i < rb.n_spheres; ++i)
+      far = std::max(far, std::hypot(std::hypot((double)rb.sphere_xyzr[4 * i], (double)rb.sphere_xyzr[4 * i + 1]),
+                                     (double)rb.sphere_xyzr[4 * i + 2]) + (double)rb.sphere_xyzr[4 * i + 3]);
+    reach_of[m] = chain + far + 1e-3;
+  }
+  std::vector<int32_t> pairs;
+  for (int i = 0; i < n_robots; ++i)
+    for (int j = i + 1; j < n_robots; ++j) {
+      const double dx = (double)robots[i].base_tf[3] - robots[j].base_tf[3];
+      const double dy = (double)robots[i].base_tf[7] - robots[j].base_tf[7];
+      const double dz = (double)robots[i].base_tf[11] - robots[j].base_tf[11];
+      if (std::sqrt(dx * dx + dy * dy + dz * dz) <= reach_of[model_of[i]] + reach_of[model_of[j]]) {
+        pairs.push_back(i);
+        pairs.push_back(j);
+      }
+    }
+  if (pairs.empty()) pairs.push_back(0), pairs.push_back(0);  // placeholder, n_pairs = 0
+
   Blob blob;
   size_t o_model = blob.add(model_of.data(), sizeof(int32_t) * n_robots);
   size_t o_qoff = blob.add(q_off.data(), sizeof(int32_t) * n_robots);
@@ -270,6 +449,9 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   size_t o_coarse = blob.add(coarse.data(), sizeof(float4) * coarse.size());
   size_t o_es = blob.add(env_s.data(), sizeof(float4) * env_s.size());
   size_t o_eb = blob.add(env_b.data(), sizeof(float4) * env_b.size());
+  size_t o_st = blob.add(sph_rows.data(), sizeof(float) * sph_rows.size());
+  size_t o_bt = blob.add(box_rows.data(), sizeof(float) * box_rows.size());
+  size_t o_pairs = blob.add(pairs.data(), sizeof(int32_t) * pairs.size());
 
   mrpop_scene *sc = new mrpop_scene();
   sc->ctx = ctx;
@@ -310,6 +492,10 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   d.env_s = (const float4 *)at(o_es);
   d.env_b = (const float4 *)at(o_eb);
   d.origin = float3{(float)org[0], (float)org[1], (float)org[2]};
+  d.sph_rows = (const float *)at(o_st);
+  d.box_rows = (const float *)at(o_bt);
+  d.n_pairs = (pairs.size() == 2 && pairs[0] == pairs[1]) ? 0 : (int32_t)(pairs.size() / 2);
+  d.pairs = (const int32_t *)at(o_pairs);
   sc->n_robots = n_robots;
   sc->dof = dof;
   sc->total_spheres = S;
@@ -374,10 +560,11 @@ mrpop_status mrpop_validate_edges(mrpop_ctx *ctx, const mrpop_scene *scene, cons
   if (st != MRPOP_OK) return st;
   ValidateScratch ws = validate_scratch_layout(ws_base, n_edges);
   hipStream_t s = (hipStream_t)stream;
-  e = launch_validate(scene->dev, qa, qb, n_edges, resolution, n_states_opt, out_valid, ws, s);
+  e = launch_validate(scene->dev, qa, qb, n_edges, resolution, n_states_opt, out_valid, ws, s, profile_slot(ctx),
+                      ctx->profiling ? ctx->prof_totals : nullptr, &ctx->last_grid, &ctx->last_block);
   if (e != hipSuccess) return hip_fail(ctx, e, "validate_edges launch");
   if (stats_opt) {
-    uint64_t c[8];
+    uint64_t c[16];
     e = hipMemcpyAsync(c, ws.counters, sizeof(c), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(ctx, e, "validate_edges stats");
@@ -386,6 +573,7 @@ mrpop_status mrpop_validate_edges(mrpop_ctx *ctx, const mrpop_scene *scene, cons
     stats_opt->tiles = (int64_t)c[3];
     stats_opt->nonfinite_edges = (int64_t)c[4];
     stats_opt->edges_invalid = (int64_t)c[5];
+    for (int i = 0; i < 8; ++i) stats_opt->work[i] = (int64_t)c[8 + i];
     if (c[6]) return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: an edge has too many states");
   }
   return MRPOP_OK;

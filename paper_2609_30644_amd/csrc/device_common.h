@@ -76,6 +76,24 @@ __device__ __forceinline__ float dist2(float3 a, float3 b) {
   return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
+// Read-only scene data viewed through the constant address space: loads with
+// wave-uniform addresses then compile to scalar loads (SGPRs, scalar cache)
+// instead of vector memory loads, which matters for the obstacle loops.
+template <class T>
+using cptr = const T __attribute__((address_space(4))) *;
+
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const T *p) {
+  return (cptr<T>)p;
+}
+
+// float4 element i of a constant-space array (the vector type's copy
+// constructor does not bind to constant-space references).
+__device__ __forceinline__ float4 ld4(cptr<float4> p, int64_t i) {
+  const cptr<float> f = (cptr<float>)p + 4 * i;
+  return make_float4(f[0], f[1], f[2], f[3]);
+}
+
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {

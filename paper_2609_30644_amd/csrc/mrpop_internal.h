@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "mrpop.h"
@@ -47,7 +48,25 @@ struct SceneDev {
   const float4 *env_s;     // [Ns] x, y, z, r (recentred)
   const float4 *env_b;     // [Nb][2] (lo x, lo y, lo z, 0), (hi x, hi y, hi z, 0) (recentred)
   float3 origin;           // world = recentred + origin
+  // Coarse filter rows in expanded form.  For link l of model m and
+  // obstacle k, the coarse sphere (centre c, radius rc) can touch the
+  // obstacle's bounding sphere (centre o, radius s) only if
+  //   |c|^2 - 2 c.o + |o|^2 - (rc + s + delta)^2 < 0.
+  // Row k of model m holds (-2 o_x, -2 o_y, -2 o_z, w_0 .. w_7, pad) with
+  // w_l = |o|^2 - (rc_l + s + delta)^2, so that each link test is three FMAs
+  // and a compare of |c|^2 + c.(-2 o) against -w_l.  delta bounds the
+  // single-precision error of the expanded form over the scene's extent, so
+  // the filter never drops a contact; links a model lacks get w = +3e38.
+  const float *sph_rows;   // [M][Ns][kRowFloats]: env spheres
+  const float *box_rows;   // [M][Nb][kRowFloats]: bounding spheres of env boxes
+  // Arm pairs (i < j) whose bases are close enough for contact; other pairs
+  // can never touch (every sphere stays within its arm's reach bound).
+  int32_t n_pairs;
+  const int32_t *pairs;    // [n_pairs][2]
 };
+
+constexpr int kRowFloats = 16;
+constexpr int kMaxWavesPerBlock = 8;
 
 struct DeviceBuffer {
   void *ptr = nullptr;
@@ -61,7 +80,15 @@ struct mrpop_ctx {
   std::string last_error;
   // Scratch reused across calls (grown on demand).
   mrpop::DeviceBuffer scratch[8];
-  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  // Profiling of the validation tile kernel: event pairs recorded on the
+  // launch stream, and device totals (states checked, edge states).
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+  uint64_t *prof_totals = nullptr;  // device [10]
+  int32_t last_grid = 0, last_block = 0;  // last tile-kernel launch
 };
 
 struct mrpop_scene {
@@ -91,13 +118,27 @@ struct ValidateScratch {
   int32_t *n_states;     // [E]
   int64_t *offsets;      // [E + 1]
   uint32_t *flags;       // [E] bit 0: collides, bit 1: non-finite
-  uint64_t *counters;    // [8]: 0 tile queue, 1 total states, 2 states checked, 3 tiles, 4 nonfinite
+  uint64_t *counters;    // [16]: 0 tile queue, 1 total states, 2 states checked, 3 tiles, 4 nonfinite,
+                         //       5 invalid, 6 too long, 8..15 work counts (chains, links, env tests,
+                         //       exact box, rr coarse, fine sphere, fine box, fine rr)
   int64_t *block_sums;   // scan partials
+  uint64_t *partials;    // [kMaxGrid][kPartialSlots] per-workgroup work counts of the tile kernel
+  int32_t *tile_first;   // [kTileFirstCap] edge holding each tile's first list position
 };
+constexpr int kPartialSlots = 10;  // states checked, 8 work counts, tiles
+constexpr int kMaxGrid = 8192;
+constexpr int64_t kTileFirstCap = 1 << 20;
 size_t validate_scratch_bytes(int64_t n_edges);
 ValidateScratch validate_scratch_layout(void *base, int64_t n_edges);
+// ev_pair (optional): events recorded right before and after the tile
+// kernel; totals (optional): device [10] accumulators (states checked, edge
+// states, then the eight work counts) added by the final kernel.
 hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb, int64_t n_edges, float res,
                            const int32_t *n_states_opt, uint8_t *out_valid, const ValidateScratch &ws,
-                           hipStream_t s);
+                           hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> *ev_pair = nullptr,
+                           uint64_t *totals = nullptr, int32_t *grid_out = nullptr,
+                           int32_t *block_out = nullptr);
+// Take an event pair for one profiled launch (nullptr when not profiling).
+const std::pair<hipEvent_t, hipEvent_t> *profile_slot(mrpop_ctx *ctx);
 
 }  // namespace mrpop

@@ -168,6 +168,95 @@ mrpop_status mrpop_validate_edges(mrpop_ctx *ctx, const mrpop_scene *scene, cons
                                   uint8_t *out_valid, mrpop_validate_stats *stats_opt, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Search primitives                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Cost-bounded nearest vertex, NEAREST(V, q, c) of Alg. 2: for each query i,
+ * among vertices v with costs[v] + |queries[i] - vertices[v]| < budgets[i],
+ * the one of least Euclidean distance; equal distances go to the lower cost,
+ * then to the lower index.  out_idx[i] = -1 when no vertex qualifies.
+ *   vertices  device [n_vertices][dim] (row-major)
+ *   costs     device [n_vertices] or NULL (all zero)
+ *   queries   device [n_queries][dim]
+ *   budgets   device [n_queries] or NULL (+infinity)
+ *   out_idx   device [n_queries]
+ * Errors: E_INVALID_ARG (negative counts, dim < 1 or above 112, NULL
+ * buffers with non-zero counts). */
+mrpop_status mrpop_nearest(mrpop_ctx *ctx, const float *vertices, const float *costs, int64_t n_vertices,
+                           int32_t dim, const float *queries, const float *budgets, int64_t n_queries,
+                           int32_t *out_idx, void *stream);
+
+/* Candidate samples of one search round (INFORMED_SAMPLE and the cost
+ * coordinate of Alg. 2).  Candidate i uses the random streams keyed by
+ * (seed, purpose, round, first + i).  With c_best = +infinity, q is uniform in
+ * the scene's joint limits and c = +infinity.  Otherwise q is uniform in the
+ * prolate hyperspheroid with foci q_start, q_goal and transverse diameter
+ * c_best (clamped onto the joint limits) and c ~ U[|q - root|, c_best].
+ *   q_start, q_goal, root  device [D];  out_q device [n][D];
+ *   out_c device [n] or NULL.
+ * Errors: E_INVALID_ARG (n < 0, NULL buffers, c_best NaN or below
+ * |q_goal - q_start| is allowed and collapses onto the segment). */
+mrpop_status mrpop_sample(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
+                          const float *root, float c_best, uint64_t seed, uint64_t round, int64_t first, int64_t n,
+                          float *out_q, float *out_c, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Planning (Alg. 1)                                                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  uint64_t seed;
+  float delta;               /* roadmap connection radius (rad, per-arm joint space) */
+  int32_t n_roadmap;         /* free samples added per arm per roadmap growth round */
+  int32_t candidates;        /* P: candidate iterations per search round (1..4096) */
+  float resolution;          /* edge discretisation (rad), > 0 */
+  int32_t max_rounds;        /* search rounds over the whole call, > 0 */
+  int32_t max_iterations;    /* outer iterations: roadmap growth then one search */
+  int32_t max_growth_rounds; /* roadmap growth rounds per iteration */
+  double time_budget_s;      /* wall-clock budget in seconds; 0 = none */
+  int32_t max_tree_nodes;    /* vertices per search tree */
+  int32_t max_roadmap_nodes; /* vertices per arm roadmap */
+  int32_t stop_at_first;     /* 1: return after the first solution */
+  float warm_cost;           /* incumbent cost to beat (+infinity: none) */
+} mrpop_plan_params;
+
+typedef struct {
+  double time_to_first_s;    /* wall time to the first solution, -1 if none */
+  double total_time_s;
+  int32_t rounds, iterations, solutions, first_round;
+  int64_t edge_states;       /* composite edge states validated by the search */
+  int64_t roadmap_edge_states;
+  int32_t roadmap_vertices;  /* summed over arms */
+  int32_t roadmap_connected; /* every arm's start and goal joined (last iteration) */
+  int32_t capacity_hit;      /* a tree or roadmap reached its capacity */
+  int32_t n_costs;           /* entries of costs[] */
+  float costs[64];           /* incumbent cost after each improvement */
+} mrpop_plan_stats;
+
+/* Defaults: seed 0, delta 3.0, n_roadmap 32, candidates 128, resolution
+ * 0.05, max_rounds 1000, max_iterations 8, max_growth_rounds 16, no time
+ * budget, 65536 tree and 8192 roadmap vertices, stop_at_first 0, no warm
+ * cost. */
+void mrpop_plan_params_default(mrpop_plan_params *p);
+
+/* MR. POP (Alg. 1): grow per-arm roadmaps (ROADMAP), search their tensor
+ * product with bidirectional dRRT for a first path, then repeat roadmap
+ * growth and cost-bounded search (AO-X) for strictly cheaper paths until a
+ * budget runs out.  Blocking; runs on the null stream of ctx's device.
+ *   q_start, q_goal  host [D], composite configurations.
+ *   path_out         host [path_cap][D]: the best path, start to goal.
+ *   path_len         host: its number of waypoints (also on E_BUFFER).
+ *   cost_out         host: its cost, the sum of Euclidean waypoint steps.
+ *   stats_opt        host or NULL.
+ * Status: OK with a path; E_START_INVALID / E_GOAL_INVALID when an endpoint
+ * collides; E_NONFINITE; E_NO_SOLUTION when the budget ends without a path;
+ * E_CAPACITY when a tree filled up before any path; E_BUFFER when path_cap is
+ * too small; E_INVALID_ARG for out-of-range parameters. */
+mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
+                        const mrpop_plan_params *params, float *path_out, int32_t path_cap, int32_t *path_len,
+                        float *cost_out, mrpop_plan_stats *stats_opt);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel profiling                                                          */
 /* ------------------------------------------------------------------------ */
 

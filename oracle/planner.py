@@ -1,0 +1,321 @@
+"""Plain CPU planner: MR. POP as bulk-synchronous rounds (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Follows Alg. 1 (the
+outer anytime loop) and Alg. 2 (ROADMAP, AO-X with the dRRT oracle, NEAREST)
+step by step, in double precision, with Python loops over candidates.  It
+uses the oracle's C primitives for the collision check, NEAREST, the random
+stream and the informed sample.
+
+Readings where the paper is silent (each is also a GPU-side rule):
+  * Rounds: every round draws P candidates against the round-start trees;
+    the valid ones are inserted in candidate order; a round that connects
+    keeps the cheapest connection (ties: lowest candidate index).
+  * Random numbers: counter-based SplitMix64 streams keyed by
+    (seed, purpose, round, candidate) -- purpose 1: configuration sample,
+    2: unit-ball sample, 3: cost sample, 4: roadmap samples.
+  * ROADMAP adds the start and goal as vertices 0 and 1 and connects only new
+    samples to their neighbours (as Alg. 2 reads), so start and goal are
+    never adjacent to each other.
+  * ROADMAP: each call resets the connected flags; every unconnected arm gets
+    n samples (uniform in its limits, kept when free of the environment,
+    first n free in draw order), then every pair (new vertex i, any vertex
+    j < i) closer than delta becomes an edge when its single-arm motion is
+    free; BFS from the start vertex (0) to the goal vertex (1).  Roadmaps
+    persist across calls.
+  * dRRT oracle: per arm, the roadmap neighbour of the near vertex best
+    aligned with the sample direction (largest cosine, ties to the lowest
+    neighbour id); the arm stays if no cosine is positive.  A candidate
+    where every arm stays is dropped; under a finite budget a candidate whose
+    cost-to-come would reach c_rand is dropped (admissibility).
+  * Informed samples outside the joint limits are clamped onto them (the
+    clamped point stays inside the prolate hyperspheroid because both foci
+    are inside the box).
+  * The cost lower bound g(q) of a sample is its distance to the root of the
+    tree being extended (the start, or the goal after a swap).
+  * Connection: NEAREST in the other tree with budget c_best - g_new (the
+    initial solve uses an infinite budget); accepted only if the new path is
+    strictly cheaper than the incumbent.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import (OracleScene, classify_edges, edge_nstates, ellipsoid_map, key, nearest, u01, unit_ball,
+               validate_fast)
+
+PURPOSE_Q, PURPOSE_BALL, PURPOSE_C, PURPOSE_ROADMAP = 1, 2, 3, 4
+ROADMAP_BATCH = 4  # candidates drawn per needed sample in one roadmap draw
+
+
+@dataclass
+class PlanParams:
+    seed: int = 0
+    delta: float = 1.0
+    n_roadmap: int = 32
+    candidates: int = 64
+    resolution: float = 0.05
+    max_rounds: int = 200
+    max_iterations: int = 4
+    max_growth_rounds: int = 16
+    max_tree_nodes: int = 100000
+    stop_at_first: bool = False
+
+
+@dataclass
+class PlanResult:
+    status: str
+    path: Optional[np.ndarray]
+    cost: float
+    rounds: int
+    iterations: int
+    first_round: int = -1
+    costs: List[float] = field(default_factory=list)
+    edge_states: int = 0
+    roadmaps: list = field(default_factory=list)
+    last_search_solved: bool = False
+
+
+class _Roadmap:
+    def __init__(self, q_start: np.ndarray, q_goal: np.ndarray):
+        self.V: List[np.ndarray] = [q_start.astype(np.float32), q_goal.astype(np.float32)]
+        self.adj: List[set] = [set(), set()]
+
+    def add_vertex(self, q):
+        self.V.append(np.asarray(q, np.float32))
+        self.adj.append(set())
+        return len(self.V) - 1
+
+    def add_edge(self, i, j):
+        self.adj[i].add(j)
+        self.adj[j].add(i)
+
+    def connected(self) -> bool:
+        seen, frontier = {0}, [0]
+        while frontier:
+            nxt = []
+            for v in frontier:
+                for u in self.adj[v]:
+                    if u not in seen:
+                        seen.add(u)
+                        nxt.append(u)
+            frontier = nxt
+        return 1 in seen
+
+
+def _arm_scene(scene, r):
+    from workloads import Scene
+    return Scene([scene.models[r]], scene.base_tf[r:r + 1], scene.env_spheres, scene.env_boxes)
+
+
+def roadmap_step(scene, roadmaps, arm_scenes, params: PlanParams, iteration: int, q_off):
+    """ROADMAP (Alg. 2): grow every arm's roadmap until start and goal are
+    connected (at most max_growth_rounds rounds).  Returns True if all are
+    connected."""
+    connected = [False] * scene.n_robots
+    for g in range(params.max_growth_rounds):
+        for r, rm in enumerate(roadmaps):
+            if connected[r]:
+                continue
+            m = scene.models[r]
+            lo, hi = m.q_lo.astype(np.float64), m.q_hi.astype(np.float64)
+            k = key(params.seed, PURPOSE_ROADMAP, iteration * 1024 + g, r)
+            accepted, j = [], 0
+            while len(accepted) < params.n_roadmap:
+                batch = ROADMAP_BATCH * params.n_roadmap
+                u = u01(k, (j + batch) * 8)
+                cand = np.array([lo + u[(j + b) * 8:(j + b) * 8 + m.n_joints] * (hi - lo) for b in range(batch)],
+                                np.float32)
+                _, mm = classify_edges(arm_scenes[r], cand, cand, 1.0)
+                for b in range(batch):
+                    if mm[b] >= 0 and len(accepted) < params.n_roadmap:
+                        accepted.append(cand[b])
+                j += batch
+            n0 = len(rm.V)
+            for q in accepted:
+                rm.add_vertex(q)
+            pairs = []
+            for i in range(n0, len(rm.V)):
+                for jj in range(i):
+                    if np.linalg.norm(rm.V[i].astype(np.float64) - rm.V[jj].astype(np.float64)) <= params.delta:
+                        pairs.append((jj, i))
+            if pairs:
+                qa = np.array([rm.V[a] for a, _ in pairs], np.float32)
+                qb = np.array([rm.V[b] for _, b in pairs], np.float32)
+                valid, _, _ = validate_fast(arm_scenes[r], qa, qb, params.resolution)
+                for (a, b), v in zip(pairs, valid):
+                    if v:
+                        rm.add_edge(a, b)
+            connected[r] = rm.connected()
+        if all(connected):
+            return True
+    return all(connected)
+
+
+@dataclass
+class _Tree:
+    q: List[np.ndarray]
+    g: List[float]
+    parent: List[int]
+    vid: List[tuple]
+
+    def __len__(self):
+        return len(self.q)
+
+
+def _new_tree(q, vid):
+    return _Tree([np.asarray(q, np.float32)], [0.0], [-1], [vid])
+
+
+def _path_to_root(t: _Tree, i: int):
+    out = []
+    while i >= 0:
+        out.append(t.q[i])
+        i = t.parent[i]
+    return out[::-1]
+
+
+def _cost(path) -> float:
+    p = np.asarray(path, np.float64)
+    return float(np.linalg.norm(np.diff(p, axis=0), axis=1).sum()) if len(p) > 1 else 0.0
+
+
+def drrt_oracle(roadmaps, vid_near, q_near_arms, q_rand_arms):
+    """Per arm: best-aligned roadmap neighbour of the near vertex (or stay)."""
+    out = []
+    for r, rm in enumerate(roadmaps):
+        v = vid_near[r]
+        d = q_rand_arms[r].astype(np.float64) - rm.V[v].astype(np.float64)
+        nd = np.linalg.norm(d)
+        best, best_cos = v, 0.0
+        if nd > 0:
+            for u in sorted(rm.adj[v]):
+                e = rm.V[u].astype(np.float64) - rm.V[v].astype(np.float64)
+                ne = np.linalg.norm(e)
+                if ne == 0:
+                    continue
+                cos = float(np.dot(e, d) / (ne * nd))
+                if cos > best_cos:
+                    best, best_cos = u, cos
+        out.append(best)
+    return out
+
+
+def plan(scene, q_start, q_goal, params: PlanParams) -> PlanResult:
+    """Alg. 1 with the subroutines of Alg. 2, in rounds of P candidates."""
+    osc = OracleScene(scene)
+    R, D = scene.n_robots, scene.dof
+    q_off = np.concatenate([[0], np.cumsum([m.n_joints for m in scene.models])]).astype(int)
+    q_start = np.asarray(q_start, np.float32)
+    q_goal = np.asarray(q_goal, np.float32)
+    _, m_ends = classify_edges(osc, np.stack([q_start, q_goal]), np.stack([q_start, q_goal]), 1.0)
+    if m_ends[0] < 0:
+        return PlanResult("E_START_INVALID", None, math.inf, 0, 0)
+    if m_ends[1] < 0:
+        return PlanResult("E_GOAL_INVALID", None, math.inf, 0, 0)
+    lo, hi = scene.q_lo.astype(np.float64), scene.q_hi.astype(np.float64)
+    arm_scenes = [OracleScene(_arm_scene(scene, r)) for r in range(R)]
+    roadmaps = [_Roadmap(q_start[q_off[r]:q_off[r + 1]], q_goal[q_off[r]:q_off[r + 1]]) for r in range(R)]
+    c_best, best_path, costs = math.inf, None, []
+    rnd, it, first_round, edge_states = 0, 0, -1, 0
+    solved = False
+
+    def arms(q):
+        return [q[q_off[r]:q_off[r + 1]] for r in range(R)]
+
+    def composite(vid):
+        return np.concatenate([roadmaps[r].V[vid[r]] for r in range(R)]).astype(np.float32)
+
+    while it < params.max_iterations and rnd < params.max_rounds:
+        roadmap_step(scene, roadmaps, arm_scenes, params, it, q_off)
+        ta, tb = _new_tree(q_start, tuple([0] * R)), _new_tree(q_goal, tuple([1] * R))
+        a_is_start = True
+        solved = False
+        while not solved and rnd < params.max_rounds:
+            if len(ta) > len(tb):
+                ta, tb = tb, ta
+                a_is_start = not a_is_start
+            root_a = ta.q[0].astype(np.float64)
+            na, nb = len(ta), len(tb)
+            Va, ga = np.array(ta.q[:na], np.float32), np.array(ta.g[:na], np.float32)
+            Vb, gb = np.array(tb.q[:nb], np.float32), np.array(tb.g[:nb], np.float32)
+            cands = []
+            for i in range(params.candidates):
+                if math.isinf(c_best):
+                    u = u01(key(params.seed, PURPOSE_Q, rnd, i), D)
+                    q_rand = lo + u * (hi - lo)
+                    c_rand = math.inf
+                else:
+                    x = unit_ball(key(params.seed, PURPOSE_BALL, rnd, i), D)
+                    q_rand = np.clip(ellipsoid_map(q_start, q_goal, c_best, x), lo, hi)
+                    lb = float(np.linalg.norm(q_rand - root_a))
+                    uc = u01(key(params.seed, PURPOSE_C, rnd, i), 1)[0]
+                    c_rand = lb + uc * (c_best - lb) if lb < c_best else c_best
+                k_near = nearest(Va, ga, q_rand.astype(np.float32), c_rand)
+                if k_near < 0:
+                    continue
+                vid_new = tuple(drrt_oracle(roadmaps, ta.vid[k_near], arms(ta.q[k_near]), arms(q_rand)))
+                if vid_new == ta.vid[k_near]:
+                    continue
+                q_new = composite(vid_new)
+                g_new = float(ta.g[k_near]) + float(np.linalg.norm(q_new.astype(np.float64) -
+                                                                   ta.q[k_near].astype(np.float64)))
+                if not math.isinf(c_best) and g_new >= c_rand:
+                    continue
+                cands.append((i, k_near, vid_new, q_new, g_new))
+            if cands:
+                qa = np.array([ta.q[c[1]] for c in cands], np.float32)
+                qb = np.array([c[3] for c in cands], np.float32)
+                valid, n, _ = validate_fast(osc, qa, qb, params.resolution)
+                edge_states += int(n.sum())
+            else:
+                valid = []
+            inserted = []
+            for c, v in zip(cands, valid):
+                if v and len(ta) < params.max_tree_nodes:
+                    ta.q.append(c[3])
+                    ta.g.append(np.float32(c[4]))
+                    ta.parent.append(c[1])
+                    ta.vid.append(c[2])
+                    inserted.append((c[0], len(ta) - 1))
+            conns = []
+            for ci, idx in inserted:
+                budget = c_best - float(ta.g[idx]) if not math.isinf(c_best) else math.inf
+                kc = nearest(Vb, gb, ta.q[idx], budget)
+                if kc >= 0:
+                    conns.append((ci, idx, kc))
+            if conns:
+                qa = np.array([ta.q[c[1]] for c in conns], np.float32)
+                qb = np.array([tb.q[c[2]] for c in conns], np.float32)
+                valid, n, _ = validate_fast(osc, qa, qb, params.resolution)
+                edge_states += int(n.sum())
+                best = None
+                for (ci, idx, kc), v in zip(conns, valid):
+                    if not v:
+                        continue
+                    tot = float(ta.g[idx]) + float(np.linalg.norm(ta.q[idx].astype(np.float64) -
+                                                                  tb.q[kc].astype(np.float64))) + float(tb.g[kc])
+                    if best is None or tot < best[0]:
+                        best = (tot, ci, idx, kc)
+                if best is not None:
+                    path = _path_to_root(ta, best[2]) + _path_to_root(tb, best[3])[::-1]
+                    if not a_is_start:
+                        path = path[::-1]
+                    cost = _cost(path)
+                    if cost < c_best:
+                        c_best, best_path = cost, np.array(path, np.float32)
+                        costs.append(cost)
+                        if first_round < 0:
+                            first_round = rnd
+                        solved = True
+            rnd += 1
+        it += 1
+        if solved and params.stop_at_first:
+            break
+        if not solved:
+            break
+    status = "OK" if best_path is not None else "E_NO_SOLUTION"
+    return PlanResult(status, best_path, c_best, rnd, it, first_round, costs, edge_states, roadmaps, solved)

@@ -12,9 +12,11 @@ from ._binding import (  # noqa: F401
     ValidateStats,
     KernelProfile,
     WORK_NAMES,
+    PlanParams,
+    PlanResult,
     lib_path,
     load_library,
     STATUS_NAMES,
 )
 
-__all__ = ["MrpopError", "Context", "Scene", "ValidateStats", "KernelProfile", "WORK_NAMES", "lib_path", "load_library", "STATUS_NAMES"]
+__all__ = ["MrpopError", "Context", "Scene", "ValidateStats", "KernelProfile", "WORK_NAMES", "PlanParams", "PlanResult", "lib_path", "load_library", "STATUS_NAMES"]

@@ -54,6 +54,29 @@ class _KernelProfile(C.Structure):
                 ("block_threads", C.c_int32)]
 
 
+class PlanParams(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("delta", C.c_float), ("n_roadmap", C.c_int32), ("candidates", C.c_int32),
+                ("resolution", C.c_float), ("max_rounds", C.c_int32), ("max_iterations", C.c_int32),
+                ("max_growth_rounds", C.c_int32), ("time_budget_s", C.c_double), ("max_tree_nodes", C.c_int32),
+                ("max_roadmap_nodes", C.c_int32), ("stop_at_first", C.c_int32), ("warm_cost", C.c_float)]
+
+
+class _PlanStats(C.Structure):
+    _fields_ = [("time_to_first_s", C.c_double), ("total_time_s", C.c_double), ("rounds", C.c_int32),
+                ("iterations", C.c_int32), ("solutions", C.c_int32), ("first_round", C.c_int32),
+                ("edge_states", C.c_int64), ("roadmap_edge_states", C.c_int64), ("roadmap_vertices", C.c_int32),
+                ("roadmap_connected", C.c_int32), ("capacity_hit", C.c_int32), ("n_costs", C.c_int32),
+                ("costs", C.c_float * 64)]
+
+
+@dataclass
+class PlanResult:
+    status: str
+    path: Optional[np.ndarray]
+    cost: float
+    stats: dict
+
+
 WORK_NAMES = ("chains", "links", "env_tests", "box_exact", "rr_coarse", "fine_sphere", "fine_box", "fine_rr")
 
 
@@ -108,6 +131,11 @@ def load_library():
     lib.mrpop_scene_total_spheres.restype = I32
     lib.mrpop_fk_spheres.argtypes = [P, P, P, I64, P, P]
     lib.mrpop_validate_edges.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
+    lib.mrpop_nearest.argtypes = [P, P, P, I64, I32, P, P, I64, P, P]
+    lib.mrpop_sample.argtypes = [P, P, P, P, P, C.c_float, C.c_uint64, C.c_uint64, I64, I64, P, P, P]
+    lib.mrpop_plan_params_default.argtypes = [P]
+    lib.mrpop_plan_params_default.restype = None
+    lib.mrpop_plan.argtypes = [P, P, P, P, P, P, I32, P, P, P]
     lib.mrpop_profile_enable.argtypes = [P, C.c_int]
     lib.mrpop_profile_read.argtypes = [P, P]
     _lib = lib
@@ -174,6 +202,22 @@ class Context:
 
     def stream(self) -> int:
         return _stream_ptr(self.device)
+
+    def nearest(self, vertices, costs, queries, budgets=None, out=None):
+        """Cost-bounded nearest vertex per query (int32, -1 when none)."""
+        torch = _torch()
+        Q = self.to_device(queries, torch.float32)
+        dim = Q.shape[-1]
+        Q = Q.reshape(-1, dim)
+        V = self.to_device(vertices, torch.float32).reshape(-1, dim)
+        g = None if costs is None else self.to_device(costs, torch.float32).reshape(V.shape[0])
+        b = None if budgets is None else self.to_device(budgets, torch.float32).reshape(Q.shape[0])
+        if out is None:
+            out = torch.empty(Q.shape[0], dtype=torch.int32, device=self.device)
+        self.check(self._lib.mrpop_nearest(self._h, V.data_ptr(), None if g is None else g.data_ptr(), V.shape[0],
+                                           V.shape[1], Q.data_ptr(), None if b is None else b.data_ptr(), Q.shape[0],
+                                           out.data_ptr(), self.stream()))
+        return out
 
     def profile_enable(self, on: bool = True) -> None:
         self.check(self._lib.mrpop_profile_enable(self._h, int(on)))
@@ -264,6 +308,45 @@ class Scene:
             return out, ValidateStats(st.edge_states, st.states_checked, st.edges_invalid, st.nonfinite_edges,
                                       st.tiles, dict(zip(WORK_NAMES, list(st.work))))
         return out
+
+    def sample(self, q_start, q_goal, root, c_best: float, seed: int, round_: int, n: int, first: int = 0):
+        """Candidate samples (q [n, D], c [n]) of one round on the device."""
+        torch = _torch()
+        qs = self.ctx.to_device(q_start, torch.float32).reshape(self.dof)
+        qg = self.ctx.to_device(q_goal, torch.float32).reshape(self.dof)
+        rt = self.ctx.to_device(root, torch.float32).reshape(self.dof)
+        out_q = torch.empty((n, self.dof), dtype=torch.float32, device=self.ctx.device)
+        out_c = torch.empty(n, dtype=torch.float32, device=self.ctx.device)
+        self.ctx.check(self.ctx._lib.mrpop_sample(self.ctx.handle, self._h, qs.data_ptr(), qg.data_ptr(), rt.data_ptr(),
+                                                  float(c_best), seed & 0xFFFFFFFFFFFFFFFF, round_, first, n,
+                                                  out_q.data_ptr(), out_c.data_ptr(), self.ctx.stream()))
+        return out_q, out_c
+
+    def plan(self, q_start, q_goal, path_cap: int = 4096, raise_on_error: bool = True, **params) -> "PlanResult":
+        """mrpop_plan on host start/goal; keyword arguments override the
+        defaults of mrpop_plan_params."""
+        lib = self.ctx._lib
+        pp = PlanParams()
+        lib.mrpop_plan_params_default(C.byref(pp))
+        for k, v in params.items():
+            if not hasattr(pp, k):
+                raise KeyError(k)
+            setattr(pp, k, v)
+        qs = np.ascontiguousarray(q_start, np.float32).reshape(self.dof)
+        qg = np.ascontiguousarray(q_goal, np.float32).reshape(self.dof)
+        path = np.zeros((max(1, path_cap), self.dof), np.float32)
+        plen = C.c_int32(0)
+        cost = C.c_float(0)
+        st = _PlanStats()
+        rc = lib.mrpop_plan(self.ctx.handle, self._h, qs.ctypes.data, qg.ctypes.data, C.byref(pp), path.ctypes.data,
+                            path_cap, C.byref(plen), C.byref(cost), C.byref(st))
+        stats = {k: getattr(st, k) for k, _ in _PlanStats._fields_ if k != "costs"}
+        stats["costs"] = list(st.costs[:st.n_costs])
+        stats["path_len"] = plen.value
+        name = STATUS_NAMES.get(rc, str(rc))
+        if rc != 0 and raise_on_error:
+            raise MrpopError(rc, lib.mrpop_last_error(self.ctx.handle).decode())
+        return PlanResult(name, path[:plen.value].copy() if rc == 0 else None, float(cost.value), stats)
 
     def states_free(self, q) -> np.ndarray:
         """Host bool per composite state (True = collision-free)."""

@@ -452,6 +452,14 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   size_t o_st = blob.add(sph_rows.data(), sizeof(float) * sph_rows.size());
   size_t o_bt = blob.add(box_rows.data(), sizeof(float) * box_rows.size());
   size_t o_pairs = blob.add(pairs.data(), sizeof(int32_t) * pairs.size());
+  std::vector<float> qlo_all, qhi_all;
+  for (int r = 0; r < n_robots; ++r)
+    for (int j = 0; j < robots[r].n_joints; ++j) {
+      qlo_all.push_back(robots[r].q_lo[j]);
+      qhi_all.push_back(robots[r].q_hi[j]);
+    }
+  size_t o_qlo = blob.add(qlo_all.data(), sizeof(float) * qlo_all.size());
+  size_t o_qhi = blob.add(qhi_all.data(), sizeof(float) * qhi_all.size());
 
   mrpop_scene *sc = new mrpop_scene();
   sc->ctx = ctx;
@@ -496,6 +504,22 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   d.box_rows = (const float *)at(o_bt);
   d.n_pairs = (pairs.size() == 2 && pairs[0] == pairs[1]) ? 0 : (int32_t)(pairs.size() / 2);
   d.pairs = (const int32_t *)at(o_pairs);
+  d.q_lo = (const float *)at(o_qlo);
+  d.q_hi = (const float *)at(o_qhi);
+  sc->h_robots.resize(n_robots);
+  for (int r = 0; r < n_robots; ++r) {
+    const mrpop_robot &rb = robots[r];
+    HostRobot &h = sc->h_robots[r];
+    h.n_joints = rb.n_joints;
+    h.dh.assign(rb.dh, rb.dh + 4 * rb.n_joints);
+    h.q_lo.assign(rb.q_lo, rb.q_lo + rb.n_joints);
+    h.q_hi.assign(rb.q_hi, rb.q_hi + rb.n_joints);
+    h.base.assign(rb.base_tf, rb.base_tf + 12);
+    h.xyzr.assign(rb.sphere_xyzr, rb.sphere_xyzr + 4 * rb.n_spheres);
+    h.link.assign(rb.sphere_link, rb.sphere_link + rb.n_spheres);
+  }
+  if (env->n_spheres) sc->h_env_s.assign(env->spheres, env->spheres + 4 * (size_t)env->n_spheres);
+  if (env->n_boxes) sc->h_env_b.assign(env->boxes, env->boxes + 6 * (size_t)env->n_boxes);
   sc->n_robots = n_robots;
   sc->dof = dof;
   sc->total_spheres = S;

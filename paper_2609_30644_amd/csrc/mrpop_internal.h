@@ -59,6 +59,7 @@ struct SceneDev {
   // the filter never drops a contact; links a model lacks get w = +3e38.
   const float *sph_rows;   // [M][Ns][kRowFloats]: env spheres
   const float *box_rows;   // [M][Nb][kRowFloats]: bounding spheres of env boxes
+  const float *q_lo, *q_hi;  // [D] composite joint limits
   // Arm pairs (i < j) whose bases are close enough for contact; other pairs
   // can never touch (every sphere stays within its arm's reach bound).
   int32_t n_pairs;
@@ -91,8 +92,19 @@ struct mrpop_ctx {
   int32_t last_grid = 0, last_block = 0;  // last tile-kernel launch
 };
 
+namespace mrpop {
+// Host copy of one arm as given to mrpop_scene_create.
+struct HostRobot {
+  int32_t n_joints = 0;
+  std::vector<float> dh, q_lo, q_hi, base, xyzr;
+  std::vector<int32_t> link;
+};
+}  // namespace mrpop
+
 struct mrpop_scene {
   mrpop_ctx *ctx = nullptr;
+  std::vector<mrpop::HostRobot> h_robots;
+  std::vector<float> h_env_s, h_env_b;
   mrpop::SceneDev dev{};
   void *blob = nullptr;            // one device allocation holding every array
   size_t blob_bytes = 0;

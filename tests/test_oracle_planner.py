@@ -1,0 +1,126 @@
+"""Pins of the oracle planner (Alg. 1 / Alg. 2 in rounds): invariants of
+every returned path, the dRRT oracle on hand-built roadmaps, roadmap
+invariants checked by independent means, and a closed-form convergence case."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import planner as PL
+
+PARAMS = dict(seed=1, candidates=64, max_rounds=120, max_iterations=4, n_roadmap=32, delta=3.0)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return W.make_problem(W.scene_c1(0), 0, oracle.states_free)
+
+
+def test_plan_path_invariants(c1):
+    r = PL.plan(c1.scene, c1.q_start, c1.q_goal, PL.PlanParams(**PARAMS))
+    assert r.status == "OK"
+    path = r.path
+    assert np.array_equal(path[0], c1.q_start) and np.array_equal(path[-1], c1.q_goal)
+    _, m = oracle.classify_edges(c1.scene, path[:-1], path[1:], 0.05)
+    assert np.all(m >= 0)
+    cost = float(np.linalg.norm(np.diff(path.astype(np.float64), axis=0), axis=1).sum())
+    assert cost == pytest.approx(r.cost, rel=1e-12)
+    assert cost >= float(np.linalg.norm(c1.q_goal.astype(np.float64) - c1.q_start))
+    assert all(b < a for a, b in zip(r.costs, r.costs[1:]))
+    assert r.first_round >= 0 and r.edge_states > 0
+
+
+def test_plan_deterministic(c1):
+    a = PL.plan(c1.scene, c1.q_start, c1.q_goal, PL.PlanParams(**PARAMS))
+    b = PL.plan(c1.scene, c1.q_start, c1.q_goal, PL.PlanParams(**PARAMS))
+    assert np.array_equal(a.path, b.path) and a.costs == b.costs
+
+
+def test_plan_start_in_collision(c1):
+    sph = np.concatenate([c1.scene.env_spheres, [[-0.5, 0.0, 0.2, 0.2]]]).astype(np.float32)
+    r = PL.plan(c1.scene.with_env(sph, c1.scene.env_boxes), c1.q_start, c1.q_goal, PL.PlanParams(**PARAMS))
+    assert r.status == "E_START_INVALID"
+
+
+def test_empty_scene_single_arm_reaches_roadmap_optimum():
+    """One arm, no obstacles: every edge is free, so after the last search
+    has run out of rounds without improving, the incumbent is the cheapest
+    path available, start -> v -> goal over a roadmap neighbour v of the start
+    or of the goal (any longer chain is no shorter by the triangle
+    inequality)."""
+    m = W.panda_like(20)
+    sc = W.Scene([m], W.base_transform(0, 0, 0)[None], np.zeros((0, 4), np.float32), np.zeros((0, 6), np.float32))
+    rng = np.random.default_rng(3)
+    qs = W.random_configs(sc, 1, rng)[0]
+    step = rng.uniform(-1, 1, sc.dof).astype(np.float32)
+    step *= 1.0 / np.abs(step).max()
+    qg = np.clip(qs + step, sc.q_lo, sc.q_hi).astype(np.float32)
+    r = PL.plan(sc, qs, qg, PL.PlanParams(seed=2, candidates=64, max_rounds=300, max_iterations=3, n_roadmap=16,
+                                           delta=3.0))
+    assert r.status == "OK" and not r.last_search_solved
+    rm = r.roadmaps[0]
+    s64, g64 = qs.astype(np.float64), qg.astype(np.float64)
+    best = min(np.linalg.norm(rm.V[v].astype(np.float64) - s64) + np.linalg.norm(rm.V[v].astype(np.float64) - g64)
+               for v in set(rm.adj[0]) | set(rm.adj[1]))
+    assert r.cost == pytest.approx(best, rel=1e-6)
+    assert r.cost > float(np.linalg.norm(g64 - s64))
+
+
+def _line_roadmap(points):
+    rm = PL._Roadmap(np.asarray(points[0], np.float32), np.asarray(points[1], np.float32))
+    for q in points[2:]:
+        rm.add_vertex(q)
+    return rm
+
+
+def test_drrt_oracle_best_aligned_and_stay():
+    # one planar-ish arm (2 joints): neighbours of vertex 0 in three directions
+    rm = _line_roadmap([[0, 0], [1, 0], [0, 1], [-1, 0], [0.7, 0.7]])
+    for u in (1, 2, 3, 4):
+        rm.add_edge(0, u)
+    # sample toward +x: vertex 1 (cos 1)
+    assert PL.drrt_oracle([rm], (0,), None, [np.array([3.0, 0.2])]) == [1]
+    # sample along the diagonal: vertex 4
+    assert PL.drrt_oracle([rm], (0,), None, [np.array([1.0, 1.0])]) == [4]
+    # no neighbour with a positive cosine: stay
+    rm2 = _line_roadmap([[0, 0], [1, 0]])
+    rm2.add_edge(0, 1)
+    assert PL.drrt_oracle([rm2], (0,), None, [np.array([-1.0, 0.0])]) == [0]
+    # sample at the vertex itself: stay
+    assert PL.drrt_oracle([rm2], (0,), None, [np.array([0.0, 0.0])]) == [0]
+    # equal cosines: the lower neighbour id
+    rm3 = _line_roadmap([[0, 0], [2, 0], [1, 0]])
+    rm3.add_edge(0, 1)
+    rm3.add_edge(0, 2)
+    assert PL.drrt_oracle([rm3], (0,), None, [np.array([5.0, 0.0])]) == [1]
+
+
+def test_roadmap_invariants(c1):
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    sc = c1.scene
+    q_off = [0, 7, 14]
+    arms = [oracle.OracleScene(PL._arm_scene(sc, r)) for r in range(2)]
+    rms = [PL._Roadmap(c1.q_start[q_off[r]:q_off[r + 1]], c1.q_goal[q_off[r]:q_off[r + 1]]) for r in range(2)]
+    params = PL.PlanParams(n_roadmap=16, delta=3.0, max_growth_rounds=4)
+    PL.roadmap_step(sc, rms, arms, params, 0, q_off)
+    sizes = [len(rm.V) for rm in rms]
+    PL.roadmap_step(sc, rms, arms, params, 1, q_off)
+    for r, rm in enumerate(rms):
+        assert len(rm.V) > sizes[r]  # roadmaps persist and grow across calls
+        V = np.array(rm.V)
+        assert np.all(oracle.state_margins(arms[r], V) >= 0)  # every vertex free of the environment
+        edges = [(a, b) for a in range(len(V)) for b in rm.adj[a] if a < b]
+        qa = np.array([V[a] for a, _ in edges], np.float32)
+        qb = np.array([V[b] for _, b in edges], np.float32)
+        assert np.all(np.linalg.norm(qa.astype(np.float64) - qb, axis=1) <= params.delta + 1e-6)
+        _, m = oracle.classify_edges(arms[r], qa, qb, params.resolution)
+        assert np.all(m >= 0)
+        # BFS connectivity agrees with connected components of the same graph
+        ii = np.array([a for a, _ in edges] + [b for _, b in edges])
+        jj = np.array([b for _, b in edges] + [a for a, _ in edges])
+        g = coo_matrix((np.ones(len(ii)), (ii, jj)), shape=(len(V), len(V)))
+        _, lab = connected_components(g, directed=False)
+        assert rm.connected() == (lab[0] == lab[1])

@@ -5,12 +5,16 @@ Workload (4 arms x 7-DoF, 59 spheres per arm, 32 spheres + 32 boxes,
 0.05 rad resolution): every step validates two batches of 4096 composite
 edges with ``mrpop_validate_edges`` -- one whose edges are all certainly free
 (every state must be fully checked) and one drawn the same way without
-selection (mostly colliding, early exit applies) -- and, once the planner is
-built, runs a plan.  Inputs sit in device memory before the timed region.
+selection (mostly colliding, early exit applies) -- and runs one full plan
+(``mrpop_plan``: roadmaps, initial dRRT solve, AO-X improvement) between the
+workload's start and goal with the step's seed.  Inputs sit in device memory
+before the timed region.
 
-Printed: one JSON line with edge-states per second, the roofline of the
-edge-validation tile kernel (executed algorithmic flops / its HIP-event
-time, against the FP32 vector peak) and the oracle's CPU rate on a sample.
+Printed: one JSON line with composite edge-states validated per second over
+the step (both batches and the plan's search), the plans' p50 time to first
+solution, the roofline of the edge-validation tile kernel (executed
+algorithmic flops / its HIP-event time, against the FP32 vector peak) and
+the oracle's CPU rate on a sample.
 """
 from __future__ import annotations
 
@@ -34,6 +38,11 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 flop/clk
 # sphere-sphere test is 3 sub + 1 mul + 2 FMA + (r1 + r2)^2 (add, mul); a
 # sphere-box test is 2 sub + 2 max per axis and a 3-term sum of squares.
 F_JOINT, F_XFORM, F_SS, F_SB = 48, 18, 10, 17
+
+# Planner settings of the benchmark step (delta: per-arm roadmap radius in
+# rad; P = candidates per round; the plan stops after max_iterations outer
+# iterations or max_rounds rounds).
+PLAN = dict(candidates=128, n_roadmap=32, delta=3.0, max_rounds=150, max_iterations=4)
 
 
 def load_workload():
@@ -98,6 +107,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plan", action="store_true", help="validation batches only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -121,17 +131,24 @@ def main():
         nominal[k] = st.edge_states
     states_per_step = sum(nominal.values())
 
-    def step():
+    q_start = np.array(fx["q_start"], np.float32)
+    q_goal = np.array(fx["q_goal"], np.float32)
+    plans = []
+
+    def step(seed):
         for k, (a, b) in dev.items():
             s.validate_edges(a, b, res, out=outs[k])
+        if not args.no_plan:
+            plans.append(s.plan(q_start, q_goal, raise_on_error=False, resolution=res, **dict(PLAN, seed=seed)))
 
-    for _ in range(args.warmup):
-        step()
+    for w in range(args.warmup):
+        step(10_000 + w)
     torch.cuda.synchronize()
+    plans.clear()
     ctx.profile_enable(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for k in range(args.steps):
+        step(k)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = ctx.profile_read()
@@ -146,7 +163,9 @@ def main():
                 "avg_launch_us": prof.kernel_ms * 1e3 / max(1, prof.launches),
                 "flops_per_launch": flops / max(1, prof.launches),
                 "grid": [prof.grid_blocks, prof.block_threads], "work": prof.work}
-    value = states_per_step * args.steps / elapsed
+    plan_states = sum(p.stats["edge_states"] for p in plans)
+    value = (states_per_step * args.steps + plan_states) / elapsed
+    tts = [p.stats["time_to_first_s"] for p in plans if p.stats["time_to_first_s"] >= 0]
     line = {
         "metric": METRIC, "value": value, "unit": "edge-states/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
@@ -158,6 +177,15 @@ def main():
         "roofline": roofline,
         "states_checked_frac": prof.states_checked / max(1, prof.edge_states),
     }
+    if plans:
+        line["plan"] = {"tts_p50_ms": float(np.median(tts)) * 1e3 if tts else None,
+                        "tts_p90_ms": float(np.percentile(tts, 90)) * 1e3 if tts else None,
+                        "solve_rate": len(tts) / len(plans),
+                        "median_cost": float(np.median([p.cost for p in plans if p.status == "OK"] or [np.nan])),
+                        "mean_plan_ms": float(np.mean([p.stats["total_time_s"] for p in plans])) * 1e3,
+                        "edge_states_per_plan": plan_states / len(plans),
+                        "params": PLAN}
+        line["config"]["plan"] = "one mrpop_plan per step, seed = step index"
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(scene, batches, res, args.cpu_seconds)

@@ -111,6 +111,18 @@ void mrpop_scene_destroy(mrpop_scene *scene);
 int32_t mrpop_scene_dof(const mrpop_scene *scene);
 int32_t mrpop_scene_total_spheres(const mrpop_scene *scene);
 
+/* Where the edge-validation kernel reads the scene's coarse filter rows
+ * (performance only; every mode gives the same bits):
+ *   MRPOP_TILE_AUTO   -- LDS when the scene's copy fits the LDS budget,
+ *                        otherwise scalar loads (the default);
+ *   MRPOP_TILE_LDS    -- a copy in LDS per workgroup (falls back to scalar
+ *                        loads when it does not fit);
+ *   MRPOP_TILE_SCALAR -- scalar loads from device memory.
+ * Errors: E_INVALID_ARG (NULL scene or unknown mode). */
+enum { MRPOP_TILE_AUTO = 0, MRPOP_TILE_LDS = 1, MRPOP_TILE_SCALAR = 2 };
+mrpop_status mrpop_scene_set_tile_mode(mrpop_scene *scene, int32_t mode);
+int32_t mrpop_scene_tile_mode(const mrpop_scene *scene);
+
 /* ------------------------------------------------------------------------ */
 /* Forward kinematics to world spheres                                       */
 /* ------------------------------------------------------------------------ */

@@ -129,6 +129,10 @@ def load_library():
     lib.mrpop_scene_dof.restype = I32
     lib.mrpop_scene_total_spheres.argtypes = [P]
     lib.mrpop_scene_total_spheres.restype = I32
+    lib.mrpop_scene_set_tile_mode.argtypes = [P, I32]
+    lib.mrpop_scene_set_tile_mode.restype = I32
+    lib.mrpop_scene_tile_mode.argtypes = [P]
+    lib.mrpop_scene_tile_mode.restype = I32
     lib.mrpop_fk_spheres.argtypes = [P, P, P, I64, P, P]
     lib.mrpop_validate_edges.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
     lib.mrpop_nearest.argtypes = [P, P, P, I64, I32, P, P, I64, P, P]
@@ -177,6 +181,18 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    TILE_MODES = {"auto": 0, "lds": 1, "scalar": 2}
+
+    def set_tile_mode(self, mode: str):
+        """Where the validation kernel reads the coarse rows: "auto", "lds"
+        or "scalar" (performance only)."""
+        self.ctx.check(self.ctx._lib.mrpop_scene_set_tile_mode(self._h, self.TILE_MODES[mode]))
+
+    @property
+    def tile_mode(self) -> str:
+        v = int(self.ctx._lib.mrpop_scene_tile_mode(self._h))
+        return {b: a for a, b in self.TILE_MODES.items()}[v]
 
     def close(self):
         if getattr(self, "_h", None):
@@ -263,6 +279,18 @@ class Scene:
     @property
     def handle(self):
         return self._h
+
+    TILE_MODES = {"auto": 0, "lds": 1, "scalar": 2}
+
+    def set_tile_mode(self, mode: str):
+        """Where the validation kernel reads the coarse rows: "auto", "lds"
+        or "scalar" (performance only)."""
+        self.ctx.check(self.ctx._lib.mrpop_scene_set_tile_mode(self._h, self.TILE_MODES[mode]))
+
+    @property
+    def tile_mode(self) -> str:
+        v = int(self.ctx._lib.mrpop_scene_tile_mode(self._h))
+        return {b: a for a, b in self.TILE_MODES.items()}[v]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -371,45 +371,39 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   const double Mx = base_far + reach + rc_max + obs_r;
   const double eps = 20.0 * std::ldexp(1.0, -24) * Mx * Mx;
   const double delta = std::max(1e-4, std::min(std::sqrt(eps), eps / (2.0 * std::max(rc_min, 1e-30))));
-  static_assert(kRowFloats >= 3 + kMaxLinks, "row too short");
-  std::vector<float> sph_rows((size_t)M * std::max(1, env->n_spheres) * kRowFloats, 0.f);
-  std::vector<float> box_rows((size_t)M * std::max(1, env->n_boxes) * kRowFloats, 0.f);
-  for (int m = 0; m < M; ++m) {
-    for (int k = 0; k < env->n_spheres; ++k) {
-      const float4 o = env_s[k];
-      float *row = &sph_rows[((size_t)m * env->n_spheres + k) * kRowFloats];
-      row[0] = -2.f * o.x; row[1] = -2.f * o.y; row[2] = -2.f * o.z;
-      const double o2 = (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z;
-      for (int l = 0; l < kMaxLinks; ++l) {
-        const float4 cv = coarse[(size_t)m * kMaxLinks + l];
-        if (cv.w < 0 || l > models[m]->n_joints) { row[3 + l] = 3.0e38f; continue; }
-        const double R = (double)cv.w + (double)o.w + delta;
-        row[3 + l] = (float)(o2 - R * R);
-      }
-    }
-    for (int k = 0; k < env->n_boxes; ++k) {
-      const float4 lo = env_b[2 * k], hi = env_b[2 * k + 1];
-      const float mx = 0.5f * (lo.x + hi.x), my = 0.5f * (lo.y + hi.y), mz = 0.5f * (lo.z + hi.z);
-      // radius from the rounded centre to the farthest corner
-      double far = 0.0;
-      for (int cx = 0; cx < 2; ++cx)
-        for (int cy = 0; cy < 2; ++cy)
-          for (int cz = 0; cz < 2; ++cz) {
-            const double dx = (double)(cx ? hi.x : lo.x) - mx, dy = (double)(cy ? hi.y : lo.y) - my,
-                         dz = (double)(cz ? hi.z : lo.z) - mz;
-            far = std::max(far, std::sqrt(dx * dx + dy * dy + dz * dz));
-          }
-      float *row = &box_rows[((size_t)m * env->n_boxes + k) * kRowFloats];
-      row[0] = -2.f * mx; row[1] = -2.f * my; row[2] = -2.f * mz;
-      const double m2 = (double)mx * mx + (double)my * my + (double)mz * mz;
-      for (int l = 0; l < kMaxLinks; ++l) {
-        const float4 cv = coarse[(size_t)m * kMaxLinks + l];
-        if (cv.w < 0 || l > models[m]->n_joints) { row[3 + l] = 3.0e38f; continue; }
-        const double R = (double)cv.w + far + delta;
-        row[3 + l] = (float)(m2 - R * R);
-      }
-    }
+  const int NS = env->n_spheres, NB = env->n_boxes, NO = NS + NB, NO4 = std::max(4, (NO + 3) & ~3);
+  std::vector<float4> rows((size_t)M * kMaxLinks * NO4, float4{0.f, 0.f, 0.f, 3.0e38f});
+  // bounding sphere of every obstacle: centre (single precision) and radius
+  std::vector<float4> bound(std::max(1, NO));
+  for (int k = 0; k < NS; ++k) bound[k] = env_s[k];
+  std::vector<double> bound_r(std::max(1, NO));
+  for (int k = 0; k < NS; ++k) bound_r[k] = (double)env_s[k].w;
+  for (int k = 0; k < NB; ++k) {
+    const float4 lo = env_b[2 * k], hi = env_b[2 * k + 1];
+    const float mx = 0.5f * (lo.x + hi.x), my = 0.5f * (lo.y + hi.y), mz = 0.5f * (lo.z + hi.z);
+    // radius from the rounded centre to the farthest corner
+    double far = 0.0;
+    for (int cx = 0; cx < 2; ++cx)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cz = 0; cz < 2; ++cz) {
+          const double dx = (double)(cx ? hi.x : lo.x) - mx, dy = (double)(cy ? hi.y : lo.y) - my,
+                       dz = (double)(cz ? hi.z : lo.z) - mz;
+          far = std::max(far, std::sqrt(dx * dx + dy * dy + dz * dz));
+        }
+    bound[NS + k] = float4{mx, my, mz, 0.f};
+    bound_r[NS + k] = far;
   }
+  for (int m = 0; m < M; ++m)
+    for (int l = 0; l < kMaxLinks; ++l) {
+      const float4 cv = coarse[(size_t)m * kMaxLinks + l];
+      if (cv.w < 0 || l > models[m]->n_joints) continue;
+      for (int k = 0; k < NO; ++k) {
+        const float4 o = bound[k];
+        const double o2 = (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z;
+        const double R = (double)cv.w + bound_r[k] + delta;
+        rows[((size_t)m * kMaxLinks + l) * NO4 + k] = float4{-2.f * o.x, -2.f * o.y, -2.f * o.z, (float)(o2 - R * R)};
+      }
+    }
 
   // Arm pairs that can touch: base distance at most the sum of reach bounds.
   std::vector<double> reach_of(M, 0.0);
@@ -449,8 +443,7 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   size_t o_coarse = blob.add(coarse.data(), sizeof(float4) * coarse.size());
   size_t o_es = blob.add(env_s.data(), sizeof(float4) * env_s.size());
   size_t o_eb = blob.add(env_b.data(), sizeof(float4) * env_b.size());
-  size_t o_st = blob.add(sph_rows.data(), sizeof(float) * sph_rows.size());
-  size_t o_bt = blob.add(box_rows.data(), sizeof(float) * box_rows.size());
+  size_t o_rows = blob.add(rows.data(), sizeof(float4) * rows.size());
   size_t o_pairs = blob.add(pairs.data(), sizeof(int32_t) * pairs.size());
   std::vector<float> qlo_all, qhi_all;
   for (int r = 0; r < n_robots; ++r)
@@ -500,8 +493,8 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   d.env_s = (const float4 *)at(o_es);
   d.env_b = (const float4 *)at(o_eb);
   d.origin = float3{(float)org[0], (float)org[1], (float)org[2]};
-  d.sph_rows = (const float *)at(o_st);
-  d.box_rows = (const float *)at(o_bt);
+  d.rows = (const float4 *)at(o_rows);
+  d.n_rows4 = NO4;
   d.n_pairs = (pairs.size() == 2 && pairs[0] == pairs[1]) ? 0 : (int32_t)(pairs.size() / 2);
   d.pairs = (const int32_t *)at(o_pairs);
   d.q_lo = (const float *)at(o_qlo);
@@ -548,6 +541,16 @@ void mrpop_scene_destroy(mrpop_scene *scene) {
 
 int32_t mrpop_scene_dof(const mrpop_scene *scene) { return scene ? scene->dof : 0; }
 int32_t mrpop_scene_total_spheres(const mrpop_scene *scene) { return scene ? scene->total_spheres : 0; }
+
+mrpop_status mrpop_scene_set_tile_mode(mrpop_scene *scene, int32_t mode) {
+  if (!scene) return MRPOP_E_INVALID_ARG;
+  if (mode != MRPOP_TILE_AUTO && mode != MRPOP_TILE_LDS && mode != MRPOP_TILE_SCALAR)
+    return fail(scene->ctx, MRPOP_E_INVALID_ARG, "scene_set_tile_mode: unknown mode");
+  scene->dev.tile_mode = mode;
+  return MRPOP_OK;
+}
+
+int32_t mrpop_scene_tile_mode(const mrpop_scene *scene) { return scene ? scene->dev.tile_mode : -1; }
 
 // ---------------------------------------------------------------------------
 // FK and validation

@@ -49,24 +49,27 @@ struct SceneDev {
   const float4 *env_b;     // [Nb][2] (lo x, lo y, lo z, 0), (hi x, hi y, hi z, 0) (recentred)
   float3 origin;           // world = recentred + origin
   // Coarse filter rows in expanded form.  For link l of model m and
-  // obstacle k, the coarse sphere (centre c, radius rc) can touch the
-  // obstacle's bounding sphere (centre o, radius s) only if
+  // obstacle k (environment spheres first, then the bounding spheres of the
+  // boxes), the coarse sphere (centre c, radius rc) can touch the obstacle's
+  // bounding sphere (centre o, radius s) only if
   //   |c|^2 - 2 c.o + |o|^2 - (rc + s + delta)^2 < 0.
-  // Row k of model m holds (-2 o_x, -2 o_y, -2 o_z, w_0 .. w_7, pad) with
-  // w_l = |o|^2 - (rc_l + s + delta)^2, so that each link test is three FMAs
-  // and a compare of |c|^2 + c.(-2 o) against -w_l.  delta bounds the
-  // single-precision error of the expanded form over the scene's extent, so
-  // the filter never drops a contact; links a model lacks get w = +3e38.
-  const float *sph_rows;   // [M][Ns][kRowFloats]: env spheres
-  const float *box_rows;   // [M][Nb][kRowFloats]: bounding spheres of env boxes
+  // rows[m][l][k] = (-2 o_x, -2 o_y, -2 o_z, w) with w = |o|^2 - (rc + s +
+  // delta)^2, so that each test is three FMAs from |c|^2 and a compare
+  // against -w.  delta bounds the single-precision error of the expanded form
+  // over the scene's extent, so the filter never drops a contact; links a
+  // model lacks get w = +3e38.
+  // Rows of each link are padded with never-passing entries (w = +3e38) to
+  // n_rows4, a multiple of four, so that the kernel reads them in groups.
+  int32_t n_rows4;
+  const float4 *rows;      // [M][kMaxLinks][n_rows4]
   const float *q_lo, *q_hi;  // [D] composite joint limits
   // Arm pairs (i < j) whose bases are close enough for contact; other pairs
   // can never touch (every sphere stays within its arm's reach bound).
+  int32_t tile_mode;       // MRPOP_TILE_*: where the tile kernel reads the rows
   int32_t n_pairs;
   const int32_t *pairs;    // [n_pairs][2]
 };
 
-constexpr int kRowFloats = 16;
 constexpr int kMaxWavesPerBlock = 8;
 
 struct DeviceBuffer {

@@ -189,80 +189,108 @@ hipError_t launch_nearest(const NearestArgs &a, hipStream_t s) {
 // a4: dRRT extension oracle (ORACLE_AOX)
 // ---------------------------------------------------------------------------
 
-// One thread per candidate.  Per arm, the roadmap neighbour of the near
-// vertex best aligned with the sample direction (largest cosine; adjacency
-// rows are sorted, so ties keep the lowest neighbour id); the arm stays if no
-// cosine is positive.  The candidate survives if some arm moves and, under a
-// finite budget, g_near + |q_new - q_near| < c_rand.  Writes the edge to
-// validate (q_near -> q_new); dropped candidates get a null edge at q_near.
-__global__ __launch_bounds__(256) void extend_kernel(ExtendArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+// One wavefront per candidate.  For every arm,
+// the lanes scan the roadmap neighbours of the arm's vertex in q_near and the
+// wave keeps the neighbour best aligned with the sample direction: largest
+// cosine, ties to the lowest neighbour id, so the result does not depend on
+// the order of an adjacency row.  The arm stays if no cosine is positive.
+// The candidate survives if some arm moves and, under a finite budget,
+// g_near + |q_new - q_near| < c_rand.  Writes the edge to validate
+// (q_near -> q_new); dropped candidates get a null edge at q_near.
+constexpr int kExtendWaves = 4;
+
+__global__ __launch_bounds__(kExtendWaves * kWave) void extend_kernel(ExtendArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int i = blockIdx.x * kExtendWaves + (int)(threadIdx.x / kWave);
+  if (i >= a.n) return;  // whole waves leave together
   const int D = a.dim, R = a.n_robots;
   const int near = a.near_idx[i];
   float *ea = a.edge_a + (int64_t)i * D, *eb = a.edge_b + (int64_t)i * D, *qn = a.q_new + (int64_t)i * D;
   const float *qr = a.q_rand + (int64_t)i * D;
   if (near < 0) {
-    a.alive[i] = 0;
-    for (int j = 0; j < D; ++j) ea[j] = eb[j] = qn[j] = a.tree_q[j * a.tree_cap];
+    if (lane == 0) a.alive[i] = 0;
+    for (int j = lane; j < D; j += kWave) ea[j] = eb[j] = qn[j] = a.tree_q[(int64_t)j * a.tree_cap];
     return;
   }
   bool moved = false;
-  float dist2 = 0.f;
+  float dist2 = 0.f;  // identical in every lane
+  int my_best = 0;    // lane r keeps arm r's choice
   for (int r = 0; r < R; ++r) {
     const int nj = a.nj[r], q0 = a.q_off[r];
     const int v = a.tree_vid[(int64_t)r * a.tree_cap + near];
     const float *V = a.rm_V + ((int64_t)r * a.rm_cap) * kRmStride;
     const int32_t *rp = a.rm_rowptr + (int64_t)r * (a.rm_cap + 1);
     const int32_t *col = a.rm_col + (int64_t)r * a.rm_col_cap;
+    float dir[MRPOP_MAX_JOINTS];
     float dn2 = 0.f;
     for (int j = 0; j < nj; ++j) {
-      const float d = qr[q0 + j] - V[(int64_t)v * kRmStride + j];
-      dn2 = fmaf(d, d, dn2);
+      dir[j] = qr[q0 + j] - V[(int64_t)v * kRmStride + j];
+      dn2 = fmaf(dir[j], dir[j], dn2);
     }
     int best = v;
     float best_cos = 0.f;
     if (dn2 > 0.f) {
       const float dn = sqrtf(dn2);
-      for (int e = rp[v]; e < rp[v + 1]; ++e) {
+      const int e0 = rp[v], e1 = min(rp[v + 1], a.rm_col_cap);
+      for (int e = e0 + lane; e < e1; e += kWave) {
         const int u = col[e];
         float dot = 0.f, en2 = 0.f;
         for (int j = 0; j < nj; ++j) {
           const float ej = V[(int64_t)u * kRmStride + j] - V[(int64_t)v * kRmStride + j];
-          dot = fmaf(ej, qr[q0 + j] - V[(int64_t)v * kRmStride + j], dot);
+          dot = fmaf(ej, dir[j], dot);
           en2 = fmaf(ej, ej, en2);
         }
         if (en2 <= 0.f) continue;
         const float cs = dot / (sqrtf(en2) * dn);
-        if (cs > best_cos) {
+        if (cs > best_cos || (cs == best_cos && best != v && u < best)) {
           best_cos = cs;
           best = u;
         }
       }
+      for (int d = kWave / 2; d > 0; d >>= 1) {
+        const float oc = __shfl_xor(best_cos, d, kWave);
+        const int ob = __shfl_xor(best, d, kWave);
+        const bool o_moves = ob != v, moves = best != v;
+        if (o_moves && (!moves || oc > best_cos || (oc == best_cos && ob < best))) {
+          best_cos = oc;
+          best = ob;
+        }
+      }
     }
     moved = moved || best != v;
-    a.vid_new[(int64_t)r * a.n + i] = best;
+    if (lane == r) my_best = best;
     for (int j = 0; j < nj; ++j) {
       const float x = V[(int64_t)best * kRmStride + j];
       const float y = a.tree_q[(int64_t)(q0 + j) * a.tree_cap + near];
-      qn[q0 + j] = x;
-      ea[q0 + j] = y;
-      eb[q0 + j] = x;
       dist2 = fmaf(x - y, x - y, dist2);
     }
   }
   const float g = a.tree_g[near] + sqrtf(dist2);
-  a.g_new[i] = g;
   bool ok = moved;
   if (a.c_rand && a.c_rand[i] < INFINITY && !(g < a.c_rand[i])) ok = false;
-  a.alive[i] = ok ? 1 : 0;
-  if (!ok)
-    for (int j = 0; j < D; ++j) eb[j] = ea[j];
+  if (lane == 0) {
+    a.g_new[i] = g;
+    a.alive[i] = ok ? 1 : 0;
+  }
+  // outputs, one joint per lane (at most 7 joints per arm)
+  for (int r = 0; r < R; ++r) {
+    const int best = __shfl(my_best, r, kWave);
+    const int nj = a.nj[r], q0 = a.q_off[r];
+    if (lane == 0) a.vid_new[(int64_t)r * a.n + i] = best;
+    if (lane < nj) {
+      const float x = a.rm_V[((int64_t)r * a.rm_cap + best) * kRmStride + lane];
+      const float y = a.tree_q[(int64_t)(q0 + lane) * a.tree_cap + near];
+      qn[q0 + lane] = x;
+      ea[q0 + lane] = y;
+      eb[q0 + lane] = ok ? x : y;
+    }
+  }
 }
 
 hipError_t launch_extend(const ExtendArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(extend_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(extend_kernel, dim3((unsigned)((a.n + kExtendWaves - 1) / kExtendWaves)),
+                     dim3(kExtendWaves * kWave), 0, s, a);
   return hipGetLastError();
 }
 
@@ -552,60 +580,64 @@ hipError_t launch_rm_add_edges(const int32_t *pair_ids, const uint8_t *valid, co
   return hipGetLastError();
 }
 
-// Single workgroup: rebuild the arm's adjacency (CSR, rows sorted by
-// neighbour id) from its edge list, then breadth-first search from vertex 0;
-// writes whether vertex 1 is reached.
+// Single workgroup: rebuild the arm's adjacency (CSR) from its edge list,
+// then breadth-first search from vertex 0; writes whether vertex 1 is
+// reached.  The order inside an adjacency row is whatever the atomics give:
+// the extension oracle's choice does not depend on it.
 __global__ __launch_bounds__(1024) void rm_csr_bfs_kernel(const int32_t *edges, const int32_t *n_edges_p,
                                                           int cap_edges, int n_v, int32_t *rowptr, int32_t *col,
                                                           int col_cap, int32_t *deg, int32_t *level,
                                                           int32_t *connected) {
+  __shared__ int32_t wsum[1024 / kWave];
+  __shared__ int32_t carry;
+  __shared__ int changed, stop;
   const int ne = *n_edges_p < cap_edges ? *n_edges_p : cap_edges;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
   for (int v = threadIdx.x; v < n_v; v += blockDim.x) deg[v] = 0;
+  if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
     atomicAdd(&deg[edges[2 * e]], 1);
     atomicAdd(&deg[edges[2 * e + 1]], 1);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int v = 0; v < n_v; ++v) {
-      rowptr[v] = run;
-      run += deg[v];
-      deg[v] = 0;
+  // exclusive scan of the degrees into rowptr; deg becomes each row's cursor
+  for (int v0 = 0; v0 < n_v; v0 += blockDim.x) {
+    const int v = v0 + threadIdx.x;
+    const int x = v < n_v ? deg[v] : 0;
+    int incl = x;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int y = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += y;
     }
-    rowptr[n_v] = run;
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int off = carry, chunk = 0;
+    for (int k = 0; k < nw; ++k) {
+      off += k < w ? wsum[k] : 0;
+      chunk += wsum[k];
+    }
+    if (v < n_v) rowptr[v] = deg[v] = off + incl - x;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += chunk;
+    __syncthreads();
   }
-  __syncthreads();
+  if (threadIdx.x == 0) rowptr[n_v] = carry;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
     const int a = edges[2 * e], b = edges[2 * e + 1];
-    const int pa = rowptr[a] + atomicAdd(&deg[a], 1);
-    const int pb = rowptr[b] + atomicAdd(&deg[b], 1);
+    const int pa = atomicAdd(&deg[a], 1), pb = atomicAdd(&deg[b], 1);
     if (pa < col_cap) col[pa] = b;
     if (pb < col_cap) col[pb] = a;
   }
+  for (int v = threadIdx.x; v < n_v; v += blockDim.x) level[v] = v == 0 ? 0 : -1;
   __syncthreads();
-  for (int v = threadIdx.x; v < n_v; v += blockDim.x) {  // insertion sort of each row
-    const int b0 = rowptr[v], b1 = rowptr[v + 1] < col_cap ? rowptr[v + 1] : col_cap;
-    for (int x = b0 + 1; x < b1; ++x) {
-      const int key = col[x];
-      int y = x - 1;
-      while (y >= b0 && col[y] > key) {
-        col[y + 1] = col[y];
-        --y;
-      }
-      col[y + 1] = key;
-    }
-    level[v] = v == 0 ? 0 : -1;
-  }
-  __syncthreads();
-  __shared__ int changed;
   for (int depth = 0;; ++depth) {
     if (threadIdx.x == 0) changed = 0;
     __syncthreads();
     for (int v = threadIdx.x; v < n_v; v += blockDim.x) {
       if (level[v] != depth) continue;
-      for (int e = rowptr[v]; e < rowptr[v + 1] && e < col_cap; ++e) {
+      const int e1 = rowptr[v + 1] < col_cap ? rowptr[v + 1] : col_cap;
+      for (int e = rowptr[v]; e < e1; ++e) {
         const int u = col[e];
         if (level[u] < 0) {
           level[u] = depth + 1;
@@ -614,8 +646,9 @@ __global__ __launch_bounds__(1024) void rm_csr_bfs_kernel(const int32_t *edges, 
       }
     }
     __syncthreads();
-    if (!changed) break;
+    if (threadIdx.x == 0) stop = !changed || (n_v > 1 && level[1] >= 0);
     __syncthreads();
+    if (stop) break;
   }
   if (threadIdx.x == 0) *connected = (n_v > 1 && level[1] >= 0) ? 1 : 0;
 }

@@ -3,25 +3,30 @@
 // An edge (q_a, q_b) is checked at n discretised states (paper, Sec.
 // "Multi-Thread Reassignment for Collision Checking").  The states of all
 // edges form one global list (exclusive prefix sum of the per-edge counts);
-// persistent workgroups pull tiles of 64 consecutive list positions from an
-// atomic queue.
+// persistent workgroups take tiles of 64 consecutive list positions in a
+// static grid-stride order.
 //
-// Mapping: one lane per state.  A workgroup has W = min(R, 8) waves; wave w
-// runs arms w, w + W, ... over the tile's 64 states, so every wave works on
-// one arm at a time and all of that arm's model data is wave-uniform (scalar
-// loads), while consecutive states of an edge sit in neighbouring lanes and
-// take the same branches.  Per arm:
-//   1. compose all link frames (modified DH) in registers and publish the
-//      links' coarse centres in LDS;
-//   2. obstacle by obstacle, one 64-byte scalar row holds everything needed
-//      to test the obstacle (sphere, or a box's bounding sphere) against all
-//      eight coarse link spheres in expanded form (three FMAs and a compare
-//      each); one wave-wide vote per obstacle skips it when no lane flags it;
-//   3. only for flagged (link, obstacle) pairs: the exact link-box distance,
-//      then the link's fine spheres.
+// Mapping: one lane per state.  A workgroup has W = min(R S, 8) waves, where
+// S = 2 splits every arm's links over two waves when 2 R <= 8 (S = 1
+// otherwise); wave w runs the (arm, link part) jobs w, w + W, ... over the
+// tile's 64 states, so every wave works on one arm at a time and all of that
+// arm's model data is wave-uniform (scalar loads), while consecutive states
+// of an edge sit in neighbouring lanes and take the same branches.  Per arm, link by link:
+//   1. compose the link frame (modified DH) in registers, publish the link's
+//      coarse centre in LDS (for the arm-pair stage) and the frame in the
+//      wave's LDS slot;
+//   2. test the coarse sphere against every obstacle (environment spheres
+//      and the bounding spheres of boxes) in expanded form: three FMAs from
+//      |c|^2 and a compare against a per-(link, obstacle) row, four obstacles
+//      per step, with the wave's compare masks kept in scalar registers;
+//   3. append the flagged (lane, obstacle) pairs to a per-wave LDS queue and
+//      test them one pair per lane (exact link-box distance for boxes, then
+//      the link's fine spheres), so that the rare flagged pairs do not make
+//      the whole wave wait on a few lanes.
 // After a barrier, the arm pairs that can reach each other are split over the
-// waves: coarse link-link tests from the LDS centres, and for flagged link
-// pairs the two frames are rebuilt and the fine spheres tested.
+// waves as (pair, link of the first arm) items: coarse link-link tests from
+// the LDS centres, and for flagged link pairs the two frames are rebuilt and
+// the fine spheres tested.
 // A collision marks the edge in a flag word and marks all of the edge's lanes
 // of the tile in an LDS mask, which the other waves read as they go; states of
 // an edge already marked by an earlier tile are skipped.
@@ -265,36 +270,38 @@ __device__ __forceinline__ uint64_t dead_mask(const unsigned long long *d) {
   return __hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-constexpr int kRowUsed = 3 + kMaxLinks;  // -2 o (3 floats), w_l for every link
+// Per-wave LDS of the environment stage: the current link's frame at every
+// lane's state (12 floats x 64, one row per element) and the queue of flagged
+// (lane, obstacle) pairs awaiting the fine test.
+constexpr int kGroup = 4;                           // obstacles per coarse step
+constexpr int kQueueFlushAt = kWave;                 // flush once more items than this are queued
+constexpr int kQueueCap = kQueueFlushAt + kGroup * kWave;
+constexpr int kWaveLdsFloats = 12 * kWave + kQueueCap;
 
-struct Row {
-  float v[kRowUsed];
-};
-
-// Scene data the tile kernel reads inside its loops: obstacle rows, box
-// corners, fine spheres, link ranges and coarse radii.  STAGED: copies in
-// LDS, made once per persistent workgroup (the scalar cache starts cold at
-// every launch, and a miss costs far more than the tests one row feeds).
-// Otherwise: the scene arrays themselves, read with scalar loads.
+// Scene data the tile kernel reads inside its loops: coarse rows, obstacle
+// spheres and boxes, fine spheres, link ranges and coarse radii.  STAGED:
+// copies in LDS, made once per persistent workgroup (the scalar cache starts
+// cold at every launch, and a miss costs far more than the tests one row
+// feeds).  Otherwise: the scene arrays themselves.
 template <bool STAGED>
 struct Src;
 
 template <>
 struct Src<true> {
-  const float *srows, *brows;  // [M][N][kRowFloats]
-  const float4 *boxes;         // [Nb][2]
-  const float4 *fine;          // [M][sph_stride]
-  const int32_t *lstart;       // [M][kMaxLinks + 1]
-  const float *crad;           // [M][kMaxLinks]
-  int ns, nb, stride;
-  __device__ Row srow(int m, int k) const { return row(srows + ((int64_t)m * ns + k) * kRowFloats); }
-  __device__ Row brow(int m, int k) const { return row(brows + ((int64_t)m * nb + k) * kRowFloats); }
-  __device__ static Row row(const float *p) {
-    Row r;
+  const float4 *rows;    // [M][kMaxLinks][n4]
+  const float4 *env_s;   // [Ns]
+  const float4 *boxes;   // [Nb][2]
+  const float4 *fine;    // [M][sph_stride]
+  const int32_t *lstart; // [M][kMaxLinks + 1]
+  const float *crad;     // [M][kMaxLinks]
+  int ns, nb, n4, stride;
+  // rows k0 .. k0 + kGroup - 1 of link l (LDS reads at one base address)
+  __device__ void group(int m, int l, int k0, float4 (&r)[kGroup]) const {
+    const float4 *p = rows + ((int64_t)m * kMaxLinks + l) * n4 + k0;
 #pragma unroll
-    for (int i = 0; i < kRowUsed; ++i) r.v[i] = p[i];
-    return r;
+    for (int i = 0; i < kGroup; ++i) r[i] = p[i];
   }
+  __device__ float4 sphere(int k) const { return env_s[k]; }
   __device__ float4 box(int i) const { return boxes[i]; }
   __device__ float4 sph(int m, int i) const { return fine[m * stride + i]; }
   __device__ int ls(int m, int l) const { return lstart[m * (kMaxLinks + 1) + l]; }
@@ -303,28 +310,27 @@ struct Src<true> {
 
 template <>
 struct Src<false> {
-  cptr<float> srows, brows;
-  cptr<float4> boxes, fine, coarse;
+  cptr<float4> rows, fine, coarse;
+  const float4 *env_s, *boxes;  // read at lane-varying indices
   cptr<int32_t> lstart;
-  int ns, nb, stride;
-  __device__ Row srow(int m, int k) const { return row(srows + ((int64_t)m * ns + k) * kRowFloats); }
-  __device__ Row brow(int m, int k) const { return row(brows + ((int64_t)m * nb + k) * kRowFloats); }
-  __device__ static Row row(cptr<float> p) {
-    Row r;
+  int ns, nb, n4, stride;
+  // rows k0 .. k0 + kGroup - 1 of link l: one 64-byte scalar load
+  __device__ void group(int m, int l, int k0, float4 (&r)[kGroup]) const {
+    const cptr<float> p = (cptr<float>)(rows + ((int64_t)m * kMaxLinks + l) * n4 + k0);
 #pragma unroll
-    for (int i = 0; i < kRowUsed; ++i) r.v[i] = p[i];
-    return r;
+    for (int i = 0; i < kGroup; ++i) r[i] = make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
   }
-  __device__ float4 box(int i) const { return ld4(boxes, i); }
+  __device__ float4 sphere(int k) const { return env_s[k]; }
+  __device__ float4 box(int i) const { return boxes[i]; }
   __device__ float4 sph(int m, int i) const { return ld4(fine, (int64_t)m * stride + i); }
   __device__ int ls(int m, int l) const { return lstart[m * (kMaxLinks + 1) + l]; }
   __device__ float rad(int m, int l) const { return ld4(coarse, m * kMaxLinks + l).w; }
 };
 
-// LDS floats needed to stage a scene (0 when it does not fit the budget).
+// LDS floats needed to stage a scene.
 __host__ __device__ inline size_t staged_floats(const SceneDev &sc) {
-  const size_t M = sc.n_models;
-  return M * (size_t)(sc.n_env_spheres + sc.n_env_boxes) * kRowFloats + (size_t)sc.n_env_boxes * 8 +
+  const size_t M = sc.n_models, N = (size_t)sc.n_rows4;
+  return M * kMaxLinks * N * 4 + (size_t)sc.n_env_spheres * 4 + (size_t)sc.n_env_boxes * 8 +
          M * (size_t)sc.sph_stride * 4 + M * (kMaxLinks + 1) + M * kMaxLinks;
 }
 
@@ -338,27 +344,28 @@ __device__ Src<true> make_src<true>(const SceneDev &sc, float *stage) {
   Src<true> s;
   s.ns = sc.n_env_spheres;
   s.nb = sc.n_env_boxes;
+  s.n4 = sc.n_rows4;
   s.stride = sc.sph_stride;
-  float *p = stage;
-  s.srows = p;
-  const int n_s = M * s.ns * kRowFloats;
-  for (int i = threadIdx.x; i < n_s; i += blockDim.x) p[i] = sc.sph_rows[i];
-  p += n_s;
-  s.brows = p;
-  const int n_b = M * s.nb * kRowFloats;
-  for (int i = threadIdx.x; i < n_b; i += blockDim.x) p[i] = sc.box_rows[i];
-  p += n_b;
-  s.boxes = (const float4 *)p;
-  for (int i = threadIdx.x; i < 2 * s.nb; i += blockDim.x) ((float4 *)p)[i] = sc.env_b[i];
-  p += 8 * s.nb;
-  s.fine = (const float4 *)p;
-  for (int i = threadIdx.x; i < M * s.stride; i += blockDim.x) ((float4 *)p)[i] = sc.fine[i];
-  p += 4 * M * s.stride;
-  s.lstart = (const int32_t *)p;
-  for (int i = threadIdx.x; i < M * (kMaxLinks + 1); i += blockDim.x) ((int32_t *)p)[i] = sc.link_start[i];
-  p += M * (kMaxLinks + 1);
-  s.crad = p;
-  for (int i = threadIdx.x; i < M * kMaxLinks; i += blockDim.x) p[i] = sc.coarse[i].w;
+  float4 *p = (float4 *)stage;
+  s.rows = p;
+  const int n_r = M * kMaxLinks * s.n4;
+  for (int i = threadIdx.x; i < n_r; i += blockDim.x) p[i] = sc.rows[i];
+  p += n_r;
+  s.env_s = p;
+  for (int i = threadIdx.x; i < s.ns; i += blockDim.x) p[i] = sc.env_s[i];
+  p += s.ns;
+  s.boxes = p;
+  for (int i = threadIdx.x; i < 2 * s.nb; i += blockDim.x) p[i] = sc.env_b[i];
+  p += 2 * s.nb;
+  s.fine = p;
+  for (int i = threadIdx.x; i < M * s.stride; i += blockDim.x) p[i] = sc.fine[i];
+  p += M * s.stride;
+  int32_t *ip = (int32_t *)p;
+  s.lstart = ip;
+  for (int i = threadIdx.x; i < M * (kMaxLinks + 1); i += blockDim.x) ip[i] = sc.link_start[i];
+  float *fp = (float *)(ip + M * (kMaxLinks + 1));
+  s.crad = fp;
+  for (int i = threadIdx.x; i < M * kMaxLinks; i += blockDim.x) fp[i] = sc.coarse[i].w;
   __syncthreads();
   return s;
 }
@@ -366,169 +373,226 @@ __device__ Src<true> make_src<true>(const SceneDev &sc, float *stage) {
 template <>
 __device__ Src<false> make_src<false>(const SceneDev &sc, float *) {
   Src<false> s;
-  s.srows = as_const(sc.sph_rows);
-  s.brows = as_const(sc.box_rows);
-  s.boxes = as_const(sc.env_b);
+  s.rows = as_const(sc.rows);
+  s.env_s = sc.env_s;
+  s.boxes = sc.env_b;
   s.fine = as_const(sc.fine);
   s.coarse = as_const(sc.coarse);
   s.lstart = as_const(sc.link_start);
   s.ns = sc.n_env_spheres;
   s.nb = sc.n_env_boxes;
+  s.n4 = sc.n_rows4;
   s.stride = sc.sph_stride;
   return s;
 }
 
-__device__ __forceinline__ float link_test(const float3 &c, float c2, const Row &row, int l) {
-  return fmaf(c.z, row.v[2], fmaf(c.y, row.v[1], fmaf(c.x, row.v[0], c2))) + row.v[3 + l];
+// Orders this wave's LDS accesses made by different lanes (LDS operations of
+// one wave are performed in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Environment test of arm model m at every lane's state.  F: link frames,
-// c/c2: coarse centres and their squared norms for links 0..kMaxLinks-1 (links
-// the model lacks have row entries that never pass).  Returns true for lanes
-// whose state collides.
+// Fine test of the queued (lane, obstacle) pairs of link l, one pair per
+// lane: the frame of the pair's state comes from LDS; an environment sphere
+// is tested against every fine sphere of the link, a box first against the
+// link's coarse sphere (exact distance), then against the fine spheres.  A
+// collision sets the state's bit in *hitw.
 template <bool STAGED>
-__device__ bool arm_env(const SceneDev &sc, const Src<STAGED> &src, int m, const Frame (&F)[kMaxLinks],
-                        const float3 (&c)[kMaxLinks], const float (&c2)[kMaxLinks], int n_links, bool live,
-                        WorkCount &wc) {
-  const cptr<float4> env_s = as_const(sc.env_s);
-  bool hit = false;
-  int ls[kMaxLinks + 1];
-#pragma unroll
-  for (int l = 0; l <= kMaxLinks; ++l) ls[l] = src.ls(m, l);
-  // environment spheres; rows are fetched one obstacle ahead
-  Row nxt;
-  if (src.ns > 0) nxt = src.srow(m, 0);
-  for (int k = 0; k < src.ns; ++k) {
-    const Row row = nxt;
-    if (k + 1 < src.ns) nxt = src.srow(m, k + 1);
-    uint64_t any = 0;
-#pragma unroll
-    for (int l = 0; l < kMaxLinks; ++l) any |= __ballot(link_test(c[l], c2[l], row, l) < 0.f);
-    if (live) wc.env_tests += n_links;
-    if ((any & __ballot(live)) == 0ull) continue;
-    const float4 o = ld4(env_s, k);
-#pragma unroll
-    for (int l = 0; l < kMaxLinks; ++l) {
-      if (live && link_test(c[l], c2[l], row, l) < 0.f) {
-        for (int i = ls[l]; i < ls[l + 1]; ++i) {
-          const float4 p = src.sph(m, i);
-          const float3 w = apply(F[l], p.x, p.y, p.z);
-          const float rr = p.w + o.w;
-          ++wc.fine_s;
-          if (dist2(w, o) < rr * rr) {
-            hit = true;
-            live = false;
+__device__ void flush_queue(const Src<STAGED> &src, int m, int l, float4 cs, const float *fr,
+                            const uint32_t *queue, int qn, unsigned long long *hitw, int lane, WorkCount &wc) {
+  wave_lds_sync();
+  const int x0 = src.ls(m, l), x1 = src.ls(m, l + 1);
+  for (int i0 = 0; i0 < qn; i0 += kWave) {
+    const int i = i0 + lane;
+    if (i >= qn) continue;
+    const uint32_t item = queue[i];
+    const int s = (int)(item & (kWave - 1));
+    const int k = (int)(item >> 6);
+    Frame G;
+    G.r00 = fr[0 * kWave + s]; G.r01 = fr[1 * kWave + s]; G.r02 = fr[2 * kWave + s]; G.t0 = fr[3 * kWave + s];
+    G.r10 = fr[4 * kWave + s]; G.r11 = fr[5 * kWave + s]; G.r12 = fr[6 * kWave + s]; G.t1 = fr[7 * kWave + s];
+    G.r20 = fr[8 * kWave + s]; G.r21 = fr[9 * kWave + s]; G.r22 = fr[10 * kWave + s]; G.t2 = fr[11 * kWave + s];
+    bool h = false;
+    if (k < src.ns) {
+      const float4 o = src.sphere(k);
+      for (int x = x0; x < x1; ++x) {
+        const float4 p = src.sph(m, x);
+        const float3 w = apply(G, p.x, p.y, p.z);
+        const float rr = p.w + o.w;
+        ++wc.fine_s;
+        if (dist2(w, o) < rr * rr) {
+          h = true;
+          break;
+        }
+      }
+    } else {
+      const int kb = k - src.ns;
+      const float4 lo = src.box(2 * kb), hi = src.box(2 * kb + 1);
+      const float3 c = apply(G, cs.x, cs.y, cs.z);
+      ++wc.box_exact;
+      if (box_dist2(c, lo, hi) < cs.w * cs.w) {
+        for (int x = x0; x < x1; ++x) {
+          const float4 p = src.sph(m, x);
+          const float3 w = apply(G, p.x, p.y, p.z);
+          ++wc.fine_b;
+          if (box_dist2(w, lo, hi) < p.w * p.w) {
+            h = true;
             break;
           }
         }
       }
     }
+    if (h) atomicOr(hitw, 1ull << s);
   }
-  // boxes: bounding-sphere filter, exact distance, then fine spheres
-  if (src.nb > 0) nxt = src.brow(m, 0);
-  for (int k = 0; k < src.nb; ++k) {
-    const Row row = nxt;
-    if (k + 1 < src.nb) nxt = src.brow(m, k + 1);
-    uint64_t any = 0;
+  wave_lds_sync();
+}
+
+// Environment stage of arm r (model m) at every lane's state for the links l
+// with l % S == part, link by link: compose the link frame, publish the coarse centre in LDS (for the arm-pair
+// stage), test the coarse sphere against every obstacle in expanded form
+// (three FMAs and a compare), queue the flagged (lane, obstacle) pairs and
+// run their fine tests one pair per lane.  Returns true for lanes whose state
+// collides; such a lane also marks its edge's lanes in *dead.
+template <bool STAGED>
+__device__ bool arm_env(const SceneDev &sc, const Src<STAGED> &src, int r, int m, int part, int S,
+                        const float (&qv)[kMaxJoints], bool live, uint64_t emask, float *cen, float *fr,
+                        uint32_t *queue, unsigned long long *hitw, unsigned long long *dead, int lane, WorkCount &wc) {
+  const int nj = as_const(sc.nj)[m];
+  const int N = src.ns + src.nb;
+  bool hit = false;
+  if (lane == 0) *hitw = 0ull;
+  if (live && part == 0) ++wc.chains;
+  Frame F = base_frame(sc, r);
+  for (int l = 0; l <= nj; ++l) {
+    if (l > 0)
+      joint_step(F, ld4(as_const(sc.dh), m * kMaxJoints + l - 1),
+                 qv[l - 1] + as_const(sc.theta_off)[m * kMaxJoints + l - 1]);
+    if (l % S != part) continue;  // another wave tests this link
+    live = live && !((dead_mask(dead) >> lane) & 1ull);
+    if (__ballot(live) == 0ull) break;  // nothing left to test in this wave
+    const float4 cs = ld4(as_const(sc.coarse), m * kMaxLinks + l);
+    const float3 c = apply(F, cs.x, cs.y, cs.z);
+    {
+      float *slot = cen + ((r * kMaxLinks + l) * 3) * kWave + lane;
+      slot[0] = c.x;
+      slot[kWave] = c.y;
+      slot[2 * kWave] = c.z;
+    }
+    if (cs.w < 0.f) continue;  // a link without spheres
+    const float c2 = fmaf(c.z, c.z, fmaf(c.y, c.y, c.x * c.x));
+    if (live) {
+      ++wc.links;
+      wc.env_tests += N;
+    }
+    fr[0 * kWave + lane] = F.r00; fr[1 * kWave + lane] = F.r01; fr[2 * kWave + lane] = F.r02;
+    fr[3 * kWave + lane] = F.t0;  fr[4 * kWave + lane] = F.r10; fr[5 * kWave + lane] = F.r11;
+    fr[6 * kWave + lane] = F.r12; fr[7 * kWave + lane] = F.t1;  fr[8 * kWave + lane] = F.r20;
+    fr[9 * kWave + lane] = F.r21; fr[10 * kWave + lane] = F.r22; fr[11 * kWave + lane] = F.t2;
+    if (N == 0) continue;
+    const float4 csr = make_float4(cs.x, cs.y, cs.z, src.rad(m, l));
+    const uint64_t livem = __builtin_amdgcn_ballot_w64(live);
+    int qn = 0;  // wave-uniform queue length
+    for (int k0 = 0; k0 < src.n4; k0 += kGroup) {
+      float4 rw[kGroup];
+      src.group(m, l, k0, rw);
+      bool h[kGroup];
+      uint64_t b[kGroup], any = 0;
 #pragma unroll
-    for (int l = 0; l < kMaxLinks; ++l) any |= __ballot(link_test(c[l], c2[l], row, l) < 0.f);
-    if (live) wc.env_tests += n_links;
-    if ((any & __ballot(live)) == 0ull) continue;
-    const float4 lo = src.box(2 * k), hi = src.box(2 * k + 1);
-#pragma unroll
-    for (int l = 0; l < kMaxLinks; ++l) {
-      if (live && link_test(c[l], c2[l], row, l) < 0.f) {
-        ++wc.box_exact;
-        const float cr = src.rad(m, l);
-        if (box_dist2(c[l], lo, hi) < cr * cr) {
-          for (int i = ls[l]; i < ls[l + 1]; ++i) {
-            const float4 p = src.sph(m, i);
-            const float3 w = apply(F[l], p.x, p.y, p.z);
-            ++wc.fine_b;
-            if (box_dist2(w, lo, hi) < p.w * p.w) {
-              hit = true;
-              live = false;
-              break;
-            }
-          }
-        }
+      for (int i = 0; i < kGroup; ++i) {
+        const float t = fmaf(c.z, rw[i].z, fmaf(c.y, rw[i].y, fmaf(c.x, rw[i].x, c2)));
+        h[i] = t < -rw[i].w;
+        b[i] = __builtin_amdgcn_ballot_w64(h[i]);
+        any |= b[i];
       }
+      if ((any & livem) == 0ull) continue;
+#pragma unroll
+      for (int i = 0; i < kGroup; ++i) {
+        const uint64_t bi = b[i] & livem;
+        if (bi == 0ull) continue;
+        if (h[i] && live)
+          queue[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(bi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bi, 0u))] =
+              (uint32_t)lane | ((uint32_t)(k0 + i) << 6);
+        qn += __popcll(bi);
+      }
+      if (qn > kQueueFlushAt) {
+        flush_queue<STAGED>(src, m, l, csr, fr, queue, qn, hitw, lane, wc);
+        qn = 0;
+      }
+    }
+    if (qn > 0) flush_queue<STAGED>(src, m, l, csr, fr, queue, qn, hitw, lane, wc);
+    if (!hit && ((*hitw >> lane) & 1ull)) {
+      hit = true;
+      live = false;
+      atomicOr(dead, (unsigned long long)emask);
     }
   }
   return hit;
 }
 
-// Arm pair (i, j) at the lane's state: coarse link-link tests on the
-// published centres; flagged link pairs rebuild both frames and test the
-// fine spheres.
+// Link a of arm i against every link of arm j at the lane's state: coarse
+// link-link tests on the published centres; for flagged link pairs both
+// frames are rebuilt from the joint values and the fine spheres tested.
 template <bool STAGED>
-__device__ bool pair_test(const SceneDev &sc, const Src<STAGED> &src, const float *cen, int lane, int i, int j,
-                          const LaneState &ls, WorkCount &wc) {
+__device__ bool pair_link_test(const SceneDev &sc, const Src<STAGED> &src, const float *cen, int lane, int i, int j,
+                               int a, const LaneState &ls, WorkCount &wc) {
   const int mi = as_const(sc.model)[i], mj = as_const(sc.model)[j];
-  const int nji = as_const(sc.nj)[mi], njj = as_const(sc.nj)[mj];
-  float3 cb[kMaxLinks];
-  float rb[kMaxLinks], ra[kMaxLinks];
-#pragma unroll
-  for (int b = 0; b < kMaxLinks; ++b) {
-    const float *p = cen + ((j * kMaxLinks + b) * 3) * kWave + lane;
-    cb[b] = make_float3(p[0], p[kWave], p[2 * kWave]);
-    rb[b] = b <= njj ? src.rad(mj, b) : -1.f;
-    ra[b] = b <= nji ? src.rad(mi, b) : -1.f;
+  const int njj = as_const(sc.nj)[mj];
+  const float ra = src.rad(mi, a);
+  if (ra < 0.f) return false;
+  const float *pa = cen + ((i * kMaxLinks + a) * 3) * kWave + lane;
+  const float3 ca = make_float3(pa[0], pa[kWave], pa[2 * kWave]);
+  uint32_t flagged = 0;  // links b of arm j whose coarse sphere meets link a's
+  for (int b = 0; b <= njj; ++b) {
+    const float rb = src.rad(mj, b);
+    if (rb < 0.f) continue;
+    const float *pb = cen + ((j * kMaxLinks + b) * 3) * kWave + lane;
+    const float3 cb = make_float3(pb[0], pb[kWave], pb[2 * kWave]);
+    const float rs = ra + rb;
+    ++wc.rr_coarse;
+    if (dist2(ca, cb) < rs * rs) flagged |= 1u << b;
   }
-  for (int a = 0; a <= nji; ++a) {
-    if (ra[a] < 0.f) continue;
-    const float *p = cen + ((i * kMaxLinks + a) * 3) * kWave + lane;
-    const float3 ca = make_float3(p[0], p[kWave], p[2 * kWave]);
-    uint64_t any = 0;
-#pragma unroll
-    for (int b = 0; b < kMaxLinks; ++b) {
-      if (rb[b] < 0.f) continue;
-      const float rs = ra[a] + rb[b];
-      ++wc.rr_coarse;
-      any |= __ballot(dist2(ca, cb[b]) < rs * rs);
-    }
-    if (any == 0ull) continue;
-    bool have_a = false;
-    Frame Fa;
-    for (int b = 0; b <= njj; ++b) {
-      const float rbb = src.rad(mj, b);
-      if (rbb < 0.f) continue;
-      const float *q = cen + ((j * kMaxLinks + b) * 3) * kWave + lane;
-      const float3 cq = make_float3(q[0], q[kWave], q[2 * kWave]);
-      const float rs = ra[a] + rbb;
-      if (!(dist2(ca, cq) < rs * rs)) continue;
-      if (!have_a) {
-        Fa = frame_at(sc, i, mi, ls, a);
-        have_a = true;
-      }
-      const Frame Fb = frame_at(sc, j, mj, ls, b);
-      for (int x = src.ls(mi, a); x < src.ls(mi, a + 1); ++x) {
-        const float4 pa = src.sph(mi, x);
-        const float3 wa = apply(Fa, pa.x, pa.y, pa.z);
-        for (int y = src.ls(mj, b); y < src.ls(mj, b + 1); ++y) {
-          const float4 pb = src.sph(mj, y);
-          const float3 wb = apply(Fb, pb.x, pb.y, pb.z);
-          const float r2 = pa.w + pb.w;
-          ++wc.fine_rr;
-          if (dist2(wa, wb) < r2 * r2) return true;
-        }
+  if (flagged == 0u) return false;
+  const Frame Fa = frame_at(sc, i, mi, ls, a);
+  for (int b = 0; b <= njj; ++b) {
+    if (!((flagged >> b) & 1u)) continue;
+    const Frame Fb = frame_at(sc, j, mj, ls, b);
+    for (int x = src.ls(mi, a); x < src.ls(mi, a + 1); ++x) {
+      const float4 sa = src.sph(mi, x);
+      const float3 wa = apply(Fa, sa.x, sa.y, sa.z);
+      for (int y = src.ls(mj, b); y < src.ls(mj, b + 1); ++y) {
+        const float4 sb = src.sph(mj, y);
+        const float3 wb = apply(Fb, sb.x, sb.y, sb.z);
+        const float r2 = sa.w + sb.w;
+        ++wc.fine_rr;
+        if (dist2(wa, wb) < r2 * r2) return true;
       }
     }
   }
   return false;
 }
 
+// Links of an arm are split over S waves when the workgroup has room for
+// every (arm, part) job: shorter per-wave chains for small arm counts.
+__host__ __device__ inline int link_split(int n_robots) { return 2 * n_robots <= kMaxWavesPerBlock ? 2 : 1; }
+
 template <bool STAGED>
-__global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void validate_tiles_kernel(
+__global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 2) void validate_tiles_kernel(
     SceneDev sc, const float *__restrict__ qa, const float *__restrict__ qb, int64_t n_edges,
     const int64_t *__restrict__ off, const int32_t *__restrict__ tile_first, uint32_t *__restrict__ flags,
     uint64_t *__restrict__ counters, uint64_t *__restrict__ partials) {
-  extern __shared__ float cen[];  // [R][kMaxLinks][3][64] published coarse centres, then staged scene data
-  __shared__ unsigned long long s_cur, s_dead;
+  // dynamic LDS: [R][kMaxLinks][3][64] published coarse centres, then per
+  // wave kWaveLdsFloats (link frames, fine-test queue), then the staged scene
+  extern __shared__ float cen[];
+  // s_dead[t & 1]: lanes of tile t whose edge is known to collide (two
+  // copies, so that the next tile's copy is cleared while this one is in use)
+  __shared__ unsigned long long s_dead[2], s_hit[kMaxWavesPerBlock];
   const int lane = threadIdx.x & (kWave - 1);
   // wave index, marked wave-uniform so that per-arm data is read with scalar loads
   const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave), W = blockDim.x / kWave;
   const int R = sc.n_robots;
+  const int S = link_split(R);
   const int64_t total = (int64_t)counters[1];
   const int64_t n_tiles = (total + kWave - 1) / kWave;
   if ((int64_t)blockIdx.x >= n_tiles) {
@@ -537,20 +601,35 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void validate_tiles_kern
   }
   uint32_t checked = 0, tiles = 0;
   WorkCount wc;
-  // The first tile of every workgroup is its block index; later ones come
-  // from the shared queue, claimed one tile ahead so that the claim's latency
-  // overlaps the current tile (device-wide atomics are slow on this chip,
-  // whose eight XCDs do not share an L2).
-  unsigned long long pending = 0;
-  if (threadIdx.x == 0) {
-    s_dead = 0ull;
-    pending = (unsigned long long)gridDim.x + atomicAdd((unsigned long long *)&counters[0], 1ull);
-  }
-  const Src<STAGED> src = make_src<STAGED>(sc, cen + (size_t)R * kMaxLinks * 3 * kWave);
+  if (threadIdx.x < 2) s_dead[threadIdx.x] = 0ull;
+  float *const wave_fr = cen + (size_t)R * kMaxLinks * 3 * kWave + (size_t)w * kWaveLdsFloats;
+  uint32_t *const wave_q = (uint32_t *)(wave_fr + 12 * kWave);
+  const Src<STAGED> src = make_src<STAGED>(sc, cen + (size_t)R * kMaxLinks * 3 * kWave + (size_t)W * kWaveLdsFloats);
+  // Static order: workgroup b takes tiles b, b + G, b + 2G, ... (G = grid).
+  // A shared work queue would need a device-wide atomic per tile, whose round
+  // trip across the chip's eight XCDs costs more than a tile's setup.  The
+  // edge lookup of the next tile (first edge, then the lanes' offsets) is
+  // loaded one and two tiles ahead, so no tile waits for it.
+  const int64_t G = gridDim.x;
+  auto first_edge = [&](int64_t t) -> int64_t {
+    return t < kTileFirstCap ? (int64_t)as_const(tile_first)[t] : find_edge(off, n_edges, t * kWave);
+  };
+  auto lane_off = [&](int64_t e_first) -> int64_t {
+    const int64_t ei = e_first + lane < n_edges ? e_first + lane : n_edges;
+    return off[ei];
+  };
   int64_t tile = blockIdx.x;
-  for (;;) {
-    __syncthreads();
-    if (tile >= n_tiles) break;
+  int64_t e0_cur = first_edge(tile);
+  int64_t off_cur = lane_off(e0_cur);
+  int64_t e0_nxt = tile + G < n_tiles ? first_edge(tile + G) : 0;
+  for (int it = 0; tile < n_tiles; ++it, tile += G) {
+    unsigned long long *const dead = &s_dead[it & 1];
+    const int64_t e0 = e0_cur, my_off = off_cur;
+    if (tile + G < n_tiles) {
+      e0_cur = e0_nxt;
+      off_cur = lane_off(e0_nxt);
+      if (tile + 2 * G < n_tiles) e0_nxt = first_edge(tile + 2 * G);
+    }
     if (w == 0) ++tiles;
     const int64_t s0 = tile * kWave;
     const int64_t s = s0 + lane;
@@ -558,9 +637,6 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void validate_tiles_kern
     // edge of each lane: the tile starts in edge e0 and spans at most 64
     // consecutive edges; lane i holds off[e0 + i] and a binary search over
     // lanes finds the last edge starting at or before the lane's position
-    const int64_t e0 = tile < kTileFirstCap ? (int64_t)as_const(tile_first)[tile] : find_edge(off, n_edges, s0);
-    const int64_t ei = e0 + lane < n_edges ? e0 + lane : n_edges;
-    const int64_t my_off = off[ei];
     int pos = 0;
 #pragma unroll
     for (int step = kWave / 2; step > 0; step >>= 1) {
@@ -584,16 +660,17 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void validate_tiles_kern
       const int lo = (int)((e_start > s0 ? e_start : s0) - s0);
       const int hi = (int)((e_end < s0 + kWave ? e_end : s0 + kWave) - s0);
       emask = (hi - lo >= 64 ? ~0ull : ((1ull << (hi - lo)) - 1ull)) << lo;
-      if (load_relaxed(flags + e) != 0u) act = false;
     }
-    if (act && w == 0) ++checked;
     bool hit = false;
-    // environment, one arm per wave at a time
-    for (int r = w; r < R; r += W) {
+    // environment: jobs (arm r, link part) over the waves
+    for (int jb = w; jb < R * S; jb += W) {
+      const int r = jb / S, part = jb - r * S;
       const int m = as_const(sc.model)[r];
       const int nj = as_const(sc.nj)[m];
       const int q0 = as_const(sc.q_off)[r];
-      // all joint values of the arm first, so that their loads overlap
+      // all joint values of the arm first, so that their loads overlap (with
+      // the edge's flag on the wave's first arm: states of an edge that an
+      // earlier tile found colliding are skipped)
       float qv[kMaxJoints];
       {
         float qa_v[kMaxJoints], qb_v[kMaxJoints];
@@ -603,65 +680,31 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void validate_tiles_kern
           qa_v[j] = st.qa[idx];
           qb_v[j] = st.qb[idx];
         }
+        if (jb == w && act && load_relaxed(flags + e) != 0u) act = false;
 #pragma unroll
         for (int j = 0; j < kMaxJoints; ++j) qv[j] = st.last ? qb_v[j] : fmaf(st.t, qb_v[j] - qa_v[j], qa_v[j]);
       }
-      Frame F[kMaxLinks];
-      float3 c[kMaxLinks];
-      float c2[kMaxLinks];
-      F[0] = base_frame(sc, r);
-#pragma unroll
-      for (int l = 1; l < kMaxLinks; ++l) {
-        F[l] = F[l - 1];
-        if (l <= nj)
-          joint_step(F[l], ld4(as_const(sc.dh), m * kMaxJoints + l - 1),
-                     qv[l - 1] + as_const(sc.theta_off)[m * kMaxJoints + l - 1]);
-      }
-      int n_links = 0;
-#pragma unroll
-      for (int l = 0; l < kMaxLinks; ++l) {
-        const float4 cs = ld4(as_const(sc.coarse), m * kMaxLinks + l);
-        c[l] = apply(F[l], cs.x, cs.y, cs.z);
-        c2[l] = fmaf(c[l].z, c[l].z, fmaf(c[l].y, c[l].y, c[l].x * c[l].x));
-        n_links += (l <= nj && cs.w >= 0.f) ? 1 : 0;
-        if (l <= nj) {
-          float *slot = cen + ((r * kMaxLinks + l) * 3) * kWave + lane;
-          slot[0] = c[l].x;
-          slot[kWave] = c[l].y;
-          slot[2 * kWave] = c[l].z;
-        }
-      }
-      const bool live = act && !hit && !((dead_mask(&s_dead) >> lane) & 1ull);
-      if (live) {
-        ++wc.chains;
-        wc.links += n_links;
-      }
-      if (arm_env<STAGED>(sc, src, m, F, c, c2, n_links, live, wc)) {
+      const bool live = act && !hit;
+      if (arm_env<STAGED>(sc, src, r, m, part, S, qv, live, emask, cen, wave_fr, wave_q, &s_hit[w], dead, lane, wc))
         hit = true;
-        atomicOr(&s_dead, (unsigned long long)emask);
-      }
     }
+    if (act && w == 0) ++checked;
     __syncthreads();
-    // arm pairs that can reach each other
-    for (int p = w; p < sc.n_pairs; p += W) {
+    if (threadIdx.x == 0) s_dead[(it + 1) & 1] = 0ull;  // last used by the previous tile
+    // arm pairs that can reach each other, one (pair, link of the first arm)
+    // item per wave at a time
+    for (int q = w; q < sc.n_pairs * kMaxLinks; q += W) {
+      const int p = q / kMaxLinks, a = q - p * kMaxLinks;
       const int pi = as_const(sc.pairs)[2 * p], pj = as_const(sc.pairs)[2 * p + 1];
-      const bool live = act && !hit && !((dead_mask(&s_dead) >> lane) & 1ull);
-      if (live && pair_test<STAGED>(sc, src, cen, lane, pi, pj, st, wc)) {
+      if (a > as_const(sc.nj)[as_const(sc.model)[pi]]) continue;
+      const bool live = act && !hit && !((dead_mask(dead) >> lane) & 1ull);
+      if (live && pair_link_test<STAGED>(sc, src, cen, lane, pi, pj, a, st, wc)) {
         hit = true;
-        atomicOr(&s_dead, (unsigned long long)emask);
+        atomicOr(dead, (unsigned long long)emask);
       }
     }
     if (hit) flags[e] = kFlagHit;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      // hand over the claimed tile and claim the next one; its result is not
-      // needed before the next hand-over
-      s_cur = pending;
-      pending = (unsigned long long)gridDim.x + atomicAdd((unsigned long long *)&counters[0], 1ull);
-      s_dead = 0ull;
-    }
-    __syncthreads();
-    tile = (int64_t)uniform_u64(s_cur);
+    __syncthreads();  // centres and dead masks are reused by the next tile
   }
   // workgroup totals of the work counters, one slot row per workgroup
   // (summed by the final kernel; no device-wide atomics)
@@ -721,15 +764,22 @@ __global__ __launch_bounds__(256) void finalize_kernel(const uint32_t *__restric
   }
 }
 
-static int block_waves(int n_robots) { return n_robots < kMaxWavesPerBlock ? n_robots : kMaxWavesPerBlock; }
+static int block_waves(int n_robots) {
+  const int jobs = n_robots * link_split(n_robots);
+  return jobs < kMaxWavesPerBlock ? jobs : kMaxWavesPerBlock;
+}
 
-static size_t centre_lds_bytes(int n_robots) { return (size_t)n_robots * kMaxLinks * 3 * kWave * sizeof(float); }
+// Centres published for the arm-pair stage plus every wave's frame and queue.
+static size_t centre_lds_bytes(int n_robots) {
+  return ((size_t)n_robots * kMaxLinks * 3 * kWave + (size_t)block_waves(n_robots) * kWaveLdsFloats) * sizeof(float);
+}
 
 // Dynamic LDS budget of the tile kernel: staging is used when the scene's
 // copy fits next to the published centres.
 constexpr size_t kLdsBudget = 150 * 1024;
 
 static bool use_staged(const SceneDev &sc) {
+  if (sc.tile_mode == MRPOP_TILE_SCALAR) return false;
   return centre_lds_bytes(sc.n_robots) + staged_floats(sc) * sizeof(float) <= kLdsBudget;
 }
 

@@ -171,3 +171,50 @@ def test_validate_deterministic(ctx):
     a = s.validate_edges(qa, qb, 0.05).cpu().numpy()
     b = s.validate_edges(qa, qb, 0.05).cpu().numpy()
     assert (a == b).all()
+
+
+def test_validate_scene_too_large_for_lds_staging(ctx):
+    """Thousands of small obstacles: the scene's filter rows exceed the LDS
+    budget, so the tile kernel reads them from global memory instead."""
+    rng = np.random.default_rng(9)
+    base = problem("c1").scene
+    ns, nb = 700, 700  # 8 links x 1400 rows x 16 B: beyond the staging budget
+    cs = rng.uniform([-1.5, -1.5, 0.0], [1.5, 1.5, 1.6], (ns, 3))
+    sph = np.concatenate([cs, rng.uniform(0.005, 0.02, (ns, 1))], 1).astype(np.float32)
+    lo = rng.uniform([-1.5, -1.5, 0.0], [1.5, 1.5, 1.6], (nb, 3))
+    box = np.concatenate([lo, lo + rng.uniform(0.005, 0.03, (nb, 3))], 1).astype(np.float32)
+    sc = base.with_env(sph, box)
+    anchors = W.random_configs(sc, 4000, rng)
+    anchors = anchors[oracle.states_free(sc, anchors)]
+    assert len(anchors) > 64
+    qa, qb = W.edge_batch_near(sc, anchors, 384, 0.05, 107, 2, 8, spread=0.0)
+    _parity(ctx, sc, qa, qb, 0.05, "large env (global rows)")
+
+
+def test_validate_no_obstacles_arm_pairs_only(ctx):
+    sc = problem("c2").scene
+    empty = sc.with_env(np.zeros((0, 4), np.float32), np.zeros((0, 6), np.float32))
+    qa, qb = W.edge_batch(empty, 1024, 0.05, 108, 8, 64)
+    valid, m, _ = _parity(ctx, empty, qa, qb, 0.05, "no obstacles")
+    assert (m < -BAND).any() and (m > BAND).any()  # both outcomes present
+
+
+@pytest.mark.parametrize("mode", ["lds", "scalar"])
+def test_validate_tile_modes(ctx, mode):
+    """Both places the tile kernel can read its coarse rows from give the
+    oracle's bits (and the same bits as each other)."""
+    p = problem("c2")
+    sc = p.scene
+    rng = np.random.default_rng(10)
+    anchors = W.random_configs(sc, 3000, rng)
+    anchors = anchors[oracle.states_free(sc, anchors)]
+    qa, qb = W.edge_batch_near(sc, anchors, 1024, 0.05, 109, 2, 48)
+    s = _scene(ctx, sc)
+    s.set_tile_mode(mode)
+    assert s.tile_mode == mode
+    print(f"[validate_parity] tile mode {mode}", flush=True)
+    got = s.validate_edges(qa, qb, 0.05).cpu().numpy()
+    _, m = oracle.classify_edges(sc, qa, qb, 0.05)
+    print(f"  {assert_bits_match(got, m, f'tile mode {mode}')}", flush=True)
+    s.set_tile_mode("auto")
+    assert np.array_equal(got, s.validate_edges(qa, qb, 0.05).cpu().numpy())

@@ -113,7 +113,8 @@ int32_t mrpop_scene_total_spheres(const mrpop_scene *scene);
 
 /* Where the edge-validation kernel reads the scene's coarse filter rows
  * (performance only; every mode gives the same bits):
- *   MRPOP_TILE_AUTO   -- LDS when the scene's copy fits the LDS budget,
+ *   MRPOP_TILE_AUTO   -- LDS when the scene's copy fits the LDS budget
+ *                        without lowering the workgroups a CU holds,
  *                        otherwise scalar loads (the default);
  *   MRPOP_TILE_LDS    -- a copy in LDS per workgroup (falls back to scalar
  *                        loads when it does not fit);

@@ -405,29 +405,46 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
       }
     }
 
-  // Arm pairs that can touch: base distance at most the sum of reach bounds.
-  std::vector<double> reach_of(M, 0.0);
+  // Arm pairs and, per pair, the link pairs that can touch: link l's coarse
+  // sphere stays within reach(l) = sum_{j <= l} |(a_{j-1}, d_j)| + |c_l| + r_l
+  // of its arm's base origin in every configuration, so links a, b of arms i,
+  // j never meet when the bases are farther apart than reach_i(a) +
+  // reach_j(b).  Bit a * 8 + b of a pair's mask marks a possible link pair.
+  std::vector<double> link_reach((size_t)M * kMaxLinks, -1.0);
   for (int m = 0; m < M; ++m) {
     const mrpop_robot &rb = *models[m];
-    double chain = 0.0, far = 0.0;
-    for (int j = 0; j < rb.n_joints; ++j) chain += std::hypot((double)rb.dh[4 * j], (double)rb.dh[4 * j + 1]);
-    for (int i = 0; i < rb.n_spheres; ++i)
-      far = std::max(far, std::hypot(std::hypot((double)rb.sphere_xyzr[4 * i], (double)rb.sphere_xyzr[4 * i + 1]),
-                                     (double)rb.sphere_xyzr[4 * i + 2]) + (double)rb.sphere_xyzr[4 * i + 3]);
-    reach_of[m] = chain + far + 1e-3;
+    double chain = 0.0;
+    for (int l = 0; l <= rb.n_joints && l < kMaxLinks; ++l) {
+      if (l > 0) chain += std::hypot((double)rb.dh[4 * (l - 1)], (double)rb.dh[4 * (l - 1) + 1]);
+      const float4 cv = coarse[(size_t)m * kMaxLinks + l];
+      if (cv.w < 0) continue;
+      link_reach[(size_t)m * kMaxLinks + l] =
+          chain + std::sqrt((double)cv.x * cv.x + (double)cv.y * cv.y + (double)cv.z * cv.z) + (double)cv.w + 1e-3;
+    }
   }
   std::vector<int32_t> pairs;
+  std::vector<uint64_t> pair_links;
   for (int i = 0; i < n_robots; ++i)
     for (int j = i + 1; j < n_robots; ++j) {
       const double dx = (double)robots[i].base_tf[3] - robots[j].base_tf[3];
       const double dy = (double)robots[i].base_tf[7] - robots[j].base_tf[7];
       const double dz = (double)robots[i].base_tf[11] - robots[j].base_tf[11];
-      if (std::sqrt(dx * dx + dy * dy + dz * dz) <= reach_of[model_of[i]] + reach_of[model_of[j]]) {
+      const double dist = std::sqrt(dx * dx + dy * dy + dz * dz);
+      uint64_t mask = 0;
+      for (int a = 0; a < kMaxLinks; ++a)
+        for (int b = 0; b < kMaxLinks; ++b) {
+          const double ra = link_reach[(size_t)model_of[i] * kMaxLinks + a],
+                       rb = link_reach[(size_t)model_of[j] * kMaxLinks + b];
+          if (ra >= 0 && rb >= 0 && dist <= ra + rb) mask |= 1ull << (a * kMaxLinks + b);
+        }
+      if (mask) {
         pairs.push_back(i);
         pairs.push_back(j);
+        pair_links.push_back(mask);
       }
     }
-  if (pairs.empty()) pairs.push_back(0), pairs.push_back(0);  // placeholder, n_pairs = 0
+  const int n_pairs = (int)pair_links.size();
+  if (pairs.empty()) pairs.push_back(0), pairs.push_back(0), pair_links.push_back(0);  // placeholder
 
   Blob blob;
   size_t o_model = blob.add(model_of.data(), sizeof(int32_t) * n_robots);
@@ -445,6 +462,7 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   size_t o_eb = blob.add(env_b.data(), sizeof(float4) * env_b.size());
   size_t o_rows = blob.add(rows.data(), sizeof(float4) * rows.size());
   size_t o_pairs = blob.add(pairs.data(), sizeof(int32_t) * pairs.size());
+  size_t o_plinks = blob.add(pair_links.data(), sizeof(uint64_t) * pair_links.size());
   std::vector<float> qlo_all, qhi_all;
   for (int r = 0; r < n_robots; ++r)
     for (int j = 0; j < robots[r].n_joints; ++j) {
@@ -495,7 +513,8 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   d.origin = float3{(float)org[0], (float)org[1], (float)org[2]};
   d.rows = (const float4 *)at(o_rows);
   d.n_rows4 = NO4;
-  d.n_pairs = (pairs.size() == 2 && pairs[0] == pairs[1]) ? 0 : (int32_t)(pairs.size() / 2);
+  d.n_pairs = n_pairs;
+  d.pair_links = (const uint64_t *)at(o_plinks);
   d.pairs = (const int32_t *)at(o_pairs);
   d.q_lo = (const float *)at(o_qlo);
   d.q_hi = (const float *)at(o_qhi);

@@ -43,12 +43,17 @@ __device__ __forceinline__ void row_step(float &R0, float &R1, float &R2, float 
 
 // T_j = T_{j-1} RotX(alpha_{j-1}) TransX(a_{j-1}) RotZ(theta_j) TransZ(d_j)
 // (Craig's modified convention).  dh = (a, d, cos alpha, sin alpha).
-__device__ __forceinline__ void joint_step(Frame &T, float4 dh, float theta) {
-  float s, c;
-  sincosf(theta, &s, &c);
+// The same step from sin(theta_j), cos(theta_j).
+__device__ __forceinline__ void joint_step_sc(Frame &T, float4 dh, float s, float c) {
   row_step(T.r00, T.r01, T.r02, T.t0, dh.x, dh.y, dh.z, dh.w, c, s);
   row_step(T.r10, T.r11, T.r12, T.t1, dh.x, dh.y, dh.z, dh.w, c, s);
   row_step(T.r20, T.r21, T.r22, T.t2, dh.x, dh.y, dh.z, dh.w, c, s);
+}
+
+__device__ __forceinline__ void joint_step(Frame &T, float4 dh, float theta) {
+  float s, c;
+  sincosf(theta, &s, &c);
+  joint_step_sc(T, dh, s, c);
 }
 
 __device__ __forceinline__ float3 apply(const Frame &T, float x, float y, float z) {

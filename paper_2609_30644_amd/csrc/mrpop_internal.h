@@ -68,9 +68,10 @@ struct SceneDev {
   int32_t tile_mode;       // MRPOP_TILE_*: where the tile kernel reads the rows
   int32_t n_pairs;
   const int32_t *pairs;    // [n_pairs][2]
+  const uint64_t *pair_links;  // [n_pairs] bit a * 8 + b: links a, b can touch
 };
 
-constexpr int kMaxWavesPerBlock = 8;
+constexpr int kMaxWavesPerBlock = 16;
 
 struct DeviceBuffer {
   void *ptr = nullptr;

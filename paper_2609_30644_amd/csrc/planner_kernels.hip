@@ -55,60 +55,83 @@ __device__ inline float normal_at(uint64_t key, int j) {
 // a2: candidate sampling
 // ---------------------------------------------------------------------------
 
-// One thread per candidate.  c_best = +inf: q_rand uniform in the joint box
-// and c_rand = +inf.  Otherwise q_rand is the informed sample (prolate
+// One wavefront per candidate, one lane per dimension (D <= 2 x 64 handled
+// in two strided passes).  c_best = +inf: q_rand uniform in the joint box and
+// c_rand = +inf.  Otherwise q_rand is the informed sample (prolate
 // hyperspheroid with foci q_s, q_g and transverse diameter c_best; a uniform
 // point of the unit D-ball from D normals scaled by u^(1/D), stretched along
 // the focal axis, reflected onto it, centred, clamped to the limits) and
 // c_rand ~ U[|q_rand - root|, c_best].
-__global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+constexpr int kSampleWaves = 4;
+constexpr int kSamplePer = kMaxDof / kWave + 1;  // dimensions per lane
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+__global__ __launch_bounds__(kSampleWaves * kWave) void sample_kernel(SampleArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int i = blockIdx.x * kSampleWaves + (int)(threadIdx.x / kWave);
+  if (i >= a.n) return;  // whole waves leave together
   const int D = a.dim;
   float *q = a.out_q + (int64_t)i * D;
   if (!(a.c_best < INFINITY)) {
     const uint64_t k = stream_key(a.seed, kPurposeQ, a.round, a.first + i);
-    for (int j = 0; j < D; ++j) q[j] = fmaf(uniform01(k, j), a.hi[j] - a.lo[j], a.lo[j]);
-    if (a.out_c) a.out_c[i] = INFINITY;
+    for (int j = lane; j < D; j += kWave) q[j] = fmaf(uniform01(k, j), a.hi[j] - a.lo[j], a.lo[j]);
+    if (a.out_c && lane == 0) a.out_c[i] = INFINITY;
     return;
   }
   const uint64_t k = stream_key(a.seed, kPurposeBall, a.round, a.first + i);
   float cmin2 = 0.f;
-  for (int j = 0; j < D; ++j) {
+  for (int j = lane; j < D; j += kWave) {
     const float d = a.qg[j] - a.qs[j];
     cmin2 = fmaf(d, d, cmin2);
   }
+  cmin2 = wave_sum(cmin2);
   const float cmin = sqrtf(cmin2);
   const float r1 = 0.5f * a.c_best;
   const float rr = a.c_best * a.c_best - cmin2;
   const float r2 = rr > 0.f ? 0.5f * sqrtf(rr) : 0.f;
-  // pass 1: |z|^2, and v . (L z) with v = e_1 - (q_g - q_s) / c_min
+  // |z|^2, and v . (L z) with v = e_1 - (q_g - q_s) / c_min
+  float z[kSamplePer], v[kSamplePer];
   float n2 = 0.f, vy = 0.f, vv = 0.f;
-  for (int j = 0; j < D; ++j) {
-    const float z = normal_at(k, j);
-    n2 = fmaf(z, z, n2);
-    const float a1 = cmin > 0.f ? (a.qg[j] - a.qs[j]) / cmin : (j == 0 ? 1.f : 0.f);
-    const float v = (j == 0 ? 1.f : 0.f) - a1;
-    vv = fmaf(v, v, vv);
-    vy = fmaf(v, z * (j == 0 ? r1 : r2), vy);
+#pragma unroll
+  for (int t = 0; t < kSamplePer; ++t) {
+    const int j = lane + t * kWave;
+    z[t] = 0.f;
+    v[t] = 0.f;
+    if (j < D) {
+      z[t] = normal_at(k, j);
+      n2 = fmaf(z[t], z[t], n2);
+      const float a1 = cmin > 0.f ? (a.qg[j] - a.qs[j]) / cmin : (j == 0 ? 1.f : 0.f);
+      v[t] = (j == 0 ? 1.f : 0.f) - a1;
+      vv = fmaf(v[t], v[t], vv);
+      vy = fmaf(v[t], z[t] * (j == 0 ? r1 : r2), vy);
+    }
   }
+  n2 = wave_sum(n2);
+  vv = wave_sum(vv);
+  vy = wave_sum(vy);
   const int pairs = (D + 1) / 2;
   const float scale = powf(uniform01(k, 2 * pairs), 1.0f / (float)D) / sqrtf(n2);
   const float refl = vv > 1e-30f ? 2.f * scale * vy / vv : 0.f;
-  // pass 2: q = centre + H (scale L z), clamped
+  // q = centre + H (scale L z), clamped
   float lb2 = 0.f;
-  for (int j = 0; j < D; ++j) {
-    const float z = normal_at(k, j);
-    const float a1 = cmin > 0.f ? (a.qg[j] - a.qs[j]) / cmin : (j == 0 ? 1.f : 0.f);
-    const float v = (j == 0 ? 1.f : 0.f) - a1;
-    const float y = scale * z * (j == 0 ? r1 : r2);
-    float x = 0.5f * (a.qs[j] + a.qg[j]) + (vv > 1e-30f ? y - v * refl : y);
-    x = fminf(fmaxf(x, a.lo[j]), a.hi[j]);
-    q[j] = x;
-    const float d = x - a.root[j * a.root_stride];
-    lb2 = fmaf(d, d, lb2);
+#pragma unroll
+  for (int t = 0; t < kSamplePer; ++t) {
+    const int j = lane + t * kWave;
+    if (j < D) {
+      const float y = scale * z[t] * (j == 0 ? r1 : r2);
+      float x = 0.5f * (a.qs[j] + a.qg[j]) + (vv > 1e-30f ? y - v[t] * refl : y);
+      x = fminf(fmaxf(x, a.lo[j]), a.hi[j]);
+      q[j] = x;
+      const float d = x - a.root[j * a.root_stride];
+      lb2 = fmaf(d, d, lb2);
+    }
   }
-  if (a.out_c) {
+  lb2 = wave_sum(lb2);
+  if (a.out_c && lane == 0) {
     const float lb = sqrtf(lb2);
     const float u = uniform01(stream_key(a.seed, kPurposeC, a.round, a.first + i), 0);
     a.out_c[i] = lb < a.c_best ? fmaf(u, a.c_best - lb, lb) : a.c_best;
@@ -117,7 +140,9 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
 
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  if (a.dim > kMaxDof) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)((a.n + kSampleWaves - 1) / kSampleWaves)),
+                     dim3(kSampleWaves * kWave), 0, s, a);
   return hipGetLastError();
 }
 

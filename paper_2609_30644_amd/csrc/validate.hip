@@ -42,6 +42,9 @@ constexpr int kScanChunk = kScanThreads * kScanItems;
 
 enum : uint32_t { kFlagHit = 1u, kFlagNonFinite = 2u, kFlagTooLong = 4u };
 
+// Batches of at most this many edges count as small for the tile shape.
+constexpr int64_t kSmallBatchEdges = 1024;
+
 static int64_t scan_blocks(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
 
 size_t validate_scratch_bytes(int64_t n_edges) {
@@ -83,12 +86,9 @@ ValidateScratch validate_scratch_layout(void *base, int64_t n_edges) {
 // 1. per-edge state counts
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void count_states_kernel(const float *__restrict__ qa, const float *__restrict__ qb,
-                                                           int64_t n_edges, int dof, float res,
-                                                           const int32_t *__restrict__ n_opt,
-                                                           int32_t *__restrict__ n_out, uint32_t *__restrict__ flags) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_edges) return;
+// State count of edge e and its flag word (non-finite input, too long).
+__device__ __forceinline__ int32_t edge_states(const float *__restrict__ qa, const float *__restrict__ qb, int64_t e,
+                                               int dof, float res, const int32_t *__restrict__ n_opt, uint32_t *flag) {
   const float *a = qa + e * dof, *b = qb + e * dof;
   bool finite = true;
   float linf = 0.f;
@@ -112,7 +112,18 @@ __global__ __launch_bounds__(256) void count_states_kernel(const float *__restri
     if (!(ratio <= (float)(MRPOP_MAX_STATES_PER_EDGE - 1))) f = kFlagTooLong;
     else n = 1 + (int32_t)ceilf(ratio);
   }
-  n_out[e] = n;
+  *flag = f;
+  return n;
+}
+
+__global__ __launch_bounds__(256) void count_states_kernel(const float *__restrict__ qa, const float *__restrict__ qb,
+                                                           int64_t n_edges, int dof, float res,
+                                                           const int32_t *__restrict__ n_opt,
+                                                           int32_t *__restrict__ n_out, uint32_t *__restrict__ flags) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_edges) return;
+  uint32_t f;
+  n_out[e] = edge_states(qa, qb, e, dof, res, n_opt, &f);
   flags[e] = f;
 }
 
@@ -209,6 +220,36 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const int32_t 
     run += v[i];
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) offsets[n_edges] = block_sums[gridDim.x];
+}
+
+// Batches of at most kScanThreads edges: counts, flags, exclusive offsets,
+// the tile table and the totals in one workgroup, one edge per thread (one
+// launch instead of four).
+__global__ __launch_bounds__(kScanThreads) void count_scan_small_kernel(
+    const float *__restrict__ qa, const float *__restrict__ qb, int64_t n_edges, int dof, float res,
+    const int32_t *__restrict__ n_opt, int32_t *__restrict__ n_out, uint32_t *__restrict__ flags,
+    int64_t *__restrict__ offsets, int32_t *__restrict__ tile_first, uint64_t *__restrict__ counters) {
+  const int64_t e = threadIdx.x;
+  int64_t v = 0;
+  if (e < n_edges) {
+    uint32_t f;
+    v = edge_states(qa, qb, e, dof, res, n_opt, &f);
+    n_out[e] = (int32_t)v;
+    flags[e] = f;
+  }
+  int64_t total;
+  const int64_t run = block_exclusive_scan(v, &total);
+  if (e < n_edges) {
+    offsets[e] = run;
+    for (int64_t tl = (run + kWave - 1) / kWave; tl * kWave < run + v && tl < kTileFirstCap; ++tl)
+      tile_first[tl] = (int32_t)e;
+  }
+  if (threadIdx.x == 0) {
+    offsets[n_edges] = total;
+    counters[0] = 0;
+    counters[1] = (uint64_t)total;
+    for (int c = 2; c < 16; ++c) counters[c] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -457,8 +498,9 @@ __device__ void flush_queue(const Src<STAGED> &src, int m, int l, float4 cs, con
 // collides; such a lane also marks its edge's lanes in *dead.
 template <bool STAGED>
 __device__ bool arm_env(const SceneDev &sc, const Src<STAGED> &src, int r, int m, int part, int S,
-                        const float (&qv)[kMaxJoints], bool live, uint64_t emask, float *cen, float *fr,
-                        uint32_t *queue, unsigned long long *hitw, unsigned long long *dead, int lane, WorkCount &wc) {
+                        const float (&qv)[kMaxJoints], bool live, uint64_t emask, float *cen, float *sc_lds,
+                        float *fr, uint32_t *queue, unsigned long long *hitw, unsigned long long *dead, int lane,
+                        WorkCount &wc) {
   const int nj = as_const(sc.nj)[m];
   const int N = src.ns + src.nb;
   bool hit = false;
@@ -466,9 +508,16 @@ __device__ bool arm_env(const SceneDev &sc, const Src<STAGED> &src, int r, int m
   if (live && part == 0) ++wc.chains;
   Frame F = base_frame(sc, r);
   for (int l = 0; l <= nj; ++l) {
-    if (l > 0)
-      joint_step(F, ld4(as_const(sc.dh), m * kMaxJoints + l - 1),
-                 qv[l - 1] + as_const(sc.theta_off)[m * kMaxJoints + l - 1]);
+    if (l > 0) {
+      float sn, cs;
+      sincosf(qv[l - 1] + as_const(sc.theta_off)[m * kMaxJoints + l - 1], &sn, &cs);
+      joint_step_sc(F, ld4(as_const(sc.dh), m * kMaxJoints + l - 1), sn, cs);
+      if (sc_lds) {  // cached for the arm-pair stage (every wave of the arm writes the same values)
+        float *q = sc_lds + ((r * kMaxJoints + l - 1) * 2) * kWave + lane;
+        q[0] = sn;
+        q[kWave] = cs;
+      }
+    }
     if (l % S != part) continue;  // another wave tests this link
     live = live && !((dead_mask(dead) >> lane) & 1ull);
     if (__ballot(live) == 0ull) break;  // nothing left to test in this wave
@@ -531,57 +580,176 @@ __device__ bool arm_env(const SceneDev &sc, const Src<STAGED> &src, int r, int m
   return hit;
 }
 
-// Link a of arm i against every link of arm j at the lane's state: coarse
-// link-link tests on the published centres; for flagged link pairs both
-// frames are rebuilt from the joint values and the fine spheres tested.
-template <bool STAGED>
-__device__ bool pair_link_test(const SceneDev &sc, const Src<STAGED> &src, const float *cen, int lane, int i, int j,
-                               int a, const LaneState &ls, WorkCount &wc) {
-  const int mi = as_const(sc.model)[i], mj = as_const(sc.model)[j];
-  const int njj = as_const(sc.nj)[mj];
-  const float ra = src.rad(mi, a);
-  if (ra < 0.f) return false;
-  const float *pa = cen + ((i * kMaxLinks + a) * 3) * kWave + lane;
-  const float3 ca = make_float3(pa[0], pa[kWave], pa[2 * kWave]);
-  uint32_t flagged = 0;  // links b of arm j whose coarse sphere meets link a's
-  for (int b = 0; b <= njj; ++b) {
-    const float rb = src.rad(mj, b);
-    if (rb < 0.f) continue;
-    const float *pb = cen + ((j * kMaxLinks + b) * 3) * kWave + lane;
-    const float3 cb = make_float3(pb[0], pb[kWave], pb[2 * kWave]);
-    const float rs = ra + rb;
-    ++wc.rr_coarse;
-    if (dist2(ca, cb) < rs * rs) flagged |= 1u << b;
+// Frame of link `link` of arm r (model m) at the state of lane s, composed
+// from the sines and cosines the environment stage cached in LDS (the same
+// operations as the environment stage's chain, so the same frame).  Arm,
+// model and link may differ between lanes.
+__device__ Frame frame_cached(const SceneDev &sc, int r, int m, int link, int s, const float *sc_lds) {
+  const float *p = sc.base + 12 * r;
+  Frame F;
+  F.r00 = p[0]; F.r01 = p[1]; F.r02 = p[2]; F.t0 = p[3];
+  F.r10 = p[4]; F.r11 = p[5]; F.r12 = p[6]; F.t1 = p[7];
+  F.r20 = p[8]; F.r21 = p[9]; F.r22 = p[10]; F.t2 = p[11];
+  for (int j = 1; j <= link; ++j) {
+    const float *q = sc_lds + ((r * kMaxJoints + j - 1) * 2) * kWave + s;
+    joint_step_sc(F, sc.dh[m * kMaxJoints + j - 1], q[0], q[kWave]);
   }
-  if (flagged == 0u) return false;
-  const Frame Fa = frame_at(sc, i, mi, ls, a);
-  for (int b = 0; b <= njj; ++b) {
-    if (!((flagged >> b) & 1u)) continue;
-    const Frame Fb = frame_at(sc, j, mj, ls, b);
-    for (int x = src.ls(mi, a); x < src.ls(mi, a + 1); ++x) {
-      const float4 sa = src.sph(mi, x);
-      const float3 wa = apply(Fa, sa.x, sa.y, sa.z);
-      for (int y = src.ls(mj, b); y < src.ls(mj, b + 1); ++y) {
-        const float4 sb = src.sph(mj, y);
-        const float3 wb = apply(Fb, sb.x, sb.y, sb.z);
-        const float r2 = sa.w + sb.w;
+  return F;
+}
+
+// Fine test of queued arm-pair items (lane s, pair p, link a of the pair's
+// first arm, link b of its second), one item per lane: both frames come from
+// the cached sines and cosines; spheres of link b that miss link a's coarse
+// sphere cannot touch any sphere of link a and are dropped first (the coarse
+// sphere contains every fine sphere of its link), then the remaining sphere
+// pairs are tested.  A collision sets the state's bit in *hitw.
+// Without the cache (scenes with many arms, where it does not fit in LDS):
+// the same frame rebuilt from the joint values of the state that lane s
+// holds (ls: that lane's state, fetched by the caller).
+__device__ Frame frame_rebuilt(const SceneDev &sc, int r, int m, int link, const LaneState &ls) {
+  const float *p = sc.base + 12 * r;
+  Frame F;
+  F.r00 = p[0]; F.r01 = p[1]; F.r02 = p[2]; F.t0 = p[3];
+  F.r10 = p[4]; F.r11 = p[5]; F.r12 = p[6]; F.t1 = p[7];
+  F.r20 = p[8]; F.r21 = p[9]; F.r22 = p[10]; F.t2 = p[11];
+  const int q0 = sc.q_off[r];
+  for (int j = 1; j <= link; ++j) {
+    float sn, cs;
+    sincosf(joint_value(ls, q0 + j - 1) + sc.theta_off[m * kMaxJoints + j - 1], &sn, &cs);
+    joint_step_sc(F, sc.dh[m * kMaxJoints + j - 1], sn, cs);
+  }
+  return F;
+}
+
+// LaneState of lane s (every lane of the wave must take part).
+__device__ __forceinline__ LaneState lane_state_of(const LaneState &st, int s) {
+  LaneState o;
+  const uint64_t a = (uint64_t)st.qa, b = (uint64_t)st.qb;
+  o.qa = (const float *)(((uint64_t)(uint32_t)__shfl((int)(a >> 32), s, kWave) << 32) |
+                         (uint32_t)__shfl((int)(uint32_t)a, s, kWave));
+  o.qb = (const float *)(((uint64_t)(uint32_t)__shfl((int)(b >> 32), s, kWave) << 32) |
+                         (uint32_t)__shfl((int)(uint32_t)b, s, kWave));
+  o.t = __shfl(st.t, s, kWave);
+  o.last = __shfl((int)st.last, s, kWave) != 0;
+  return o;
+}
+
+template <bool STAGED>
+__device__ void flush_pairs(const SceneDev &sc, const Src<STAGED> &src, const float *cen, const float *sc_lds,
+                            const LaneState &st, const uint32_t *queue, int qn, unsigned long long *hitw, int lane,
+                            WorkCount &wc) {
+  wave_lds_sync();
+  for (int i0 = 0; i0 < qn; i0 += kWave) {
+    const int i = i0 + lane;
+    const uint32_t item = i < qn ? queue[i] : 0u;
+    const int s = (int)(item & (kWave - 1)), a = (int)((item >> 6) & 7u), b = (int)((item >> 9) & 7u);
+    const int p = (int)(item >> 12);
+    const LaneState ls = sc_lds ? st : lane_state_of(st, s);  // all lanes active here
+    if (i >= qn) continue;
+    const int ai = sc.pairs[2 * p], aj = sc.pairs[2 * p + 1];
+    const int mi = sc.model[ai], mj = sc.model[aj];
+    const float *pa = cen + ((ai * kMaxLinks + a) * 3) * kWave + s;
+    const float *pb = cen + ((aj * kMaxLinks + b) * 3) * kWave + s;
+    const float4 ca = make_float4(pa[0], pa[kWave], pa[2 * kWave], src.rad(mi, a));
+    const float4 cb = make_float4(pb[0], pb[kWave], pb[2 * kWave], src.rad(mj, b));
+    const Frame Fa = sc_lds ? frame_cached(sc, ai, mi, a, s, sc_lds) : frame_rebuilt(sc, ai, mi, a, ls);
+    const Frame Fb = sc_lds ? frame_cached(sc, aj, mj, b, s, sc_lds) : frame_rebuilt(sc, aj, mj, b, ls);
+    const int x0 = src.ls(mi, a), x1 = src.ls(mi, a + 1), y0 = src.ls(mj, b), y1 = src.ls(mj, b + 1);
+    // spheres of link b within reach of link a's coarse sphere (links with
+    // more than 64 spheres keep the rest unfiltered)
+    const int ny = y1 - y0 < 64 ? y1 - y0 : 64;
+    uint64_t ym = 0;
+    for (int y = y0; y < y0 + ny; ++y) {
+      const float4 q = src.sph(mj, y);
+      const float3 wy = apply(Fb, q.x, q.y, q.z);
+      const float rr = q.w + ca.w;
+      ++wc.fine_rr;
+      if (dist2(wy, ca) < rr * rr) ym |= 1ull << (y - y0);
+    }
+    const bool rest = y1 - y0 > 64;
+    bool h = false;
+    for (int x = x0; x < x1 && (ym != 0ull || rest) && !h; ++x) {
+      const float4 q = src.sph(mi, x);
+      const float3 wx = apply(Fa, q.x, q.y, q.z);
+      const float rx = q.w + cb.w;
+      ++wc.fine_rr;
+      if (!(dist2(wx, cb) < rx * rx)) continue;
+      for (int y = y0; y < y1; ++y) {
+        if (y - y0 < 64 && !((ym >> (y - y0)) & 1ull)) continue;
+        const float4 t = src.sph(mj, y);
+        const float3 wy = apply(Fb, t.x, t.y, t.z);
+        const float rr = q.w + t.w;
         ++wc.fine_rr;
-        if (dist2(wa, wb) < r2 * r2) return true;
+        if (dist2(wx, wy) < rr * rr) {
+          h = true;
+          break;
+        }
+      }
+    }
+    if (h) atomicOr(hitw, 1ull << s);
+  }
+  wave_lds_sync();
+}
+
+// Arm-pair stage of one wave: items (pair p, link a of the pair's first arm)
+// p * kMaxLinks + a = w, w + W, ...; coarse link-link tests on the published
+// centres for the link pairs the pair's static mask allows, flagged (lane,
+// pair, a, b) items queued and tested by flush_pairs.  Returns true for lanes
+// whose state collides.
+template <bool STAGED>
+__device__ bool arm_pairs(const SceneDev &sc, const Src<STAGED> &src, const float *cen, const float *sc_lds, int w,
+                          int W, bool live, const LaneState &st, uint64_t emask, uint32_t *queue,
+                          unsigned long long *hitw, unsigned long long *dead, int lane, WorkCount &wc) {
+  if (lane == 0) *hitw = 0ull;
+  int qn = 0;
+  for (int q = w; q < sc.n_pairs * kMaxLinks; q += W) {
+    const int p = q / kMaxLinks, a = q - p * kMaxLinks;
+    const uint32_t row = (uint32_t)(as_const(sc.pair_links)[p] >> (a * kMaxLinks)) & 0xffu;
+    if (row == 0u) continue;
+    live = live && !((dead_mask(dead) >> lane) & 1ull);
+    const uint64_t livem = __builtin_amdgcn_ballot_w64(live);
+    if (livem == 0ull) break;
+    const int pi = as_const(sc.pairs)[2 * p], pj = as_const(sc.pairs)[2 * p + 1];
+    const int mi = as_const(sc.model)[pi], mj = as_const(sc.model)[pj];
+    const float ra = src.rad(mi, a);
+    const float *pa = cen + ((pi * kMaxLinks + a) * 3) * kWave + lane;
+    const float3 ca = make_float3(pa[0], pa[kWave], pa[2 * kWave]);
+    for (int b = 0; b < kMaxLinks; ++b) {
+      if (!((row >> b) & 1u)) continue;
+      const float *pb = cen + ((pj * kMaxLinks + b) * 3) * kWave + lane;
+      const float3 cb = make_float3(pb[0], pb[kWave], pb[2 * kWave]);
+      const float rs = ra + src.rad(mj, b);
+      if (live) ++wc.rr_coarse;
+      const bool h = dist2(ca, cb) < rs * rs;
+      const uint64_t bm = __builtin_amdgcn_ballot_w64(h) & livem;
+      if (bm == 0ull) continue;
+      if (h && live)
+        queue[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u))] =
+            (uint32_t)lane | ((uint32_t)a << 6) | ((uint32_t)b << 9) | ((uint32_t)p << 12);
+      qn += __popcll(bm);
+      if (qn > kQueueFlushAt) {
+        flush_pairs<STAGED>(sc, src, cen, sc_lds, st, queue, qn, hitw, lane, wc);
+        qn = 0;
       }
     }
   }
-  return false;
+  if (qn > 0) flush_pairs<STAGED>(sc, src, cen, sc_lds, st, queue, qn, hitw, lane, wc);
+  const bool hit = live && ((*hitw >> lane) & 1ull);
+  if (hit) atomicOr(dead, (unsigned long long)emask);
+  return hit;
 }
 
-// Links of an arm are split over S waves when the workgroup has room for
-// every (arm, part) job: shorter per-wave chains for small arm counts.
-__host__ __device__ inline int link_split(int n_robots) { return 2 * n_robots <= kMaxWavesPerBlock ? 2 : 1; }
+// LDS floats before the per-wave areas: published coarse centres
+// [R][kMaxLinks][3][64] and cached joint sines/cosines [R][kMaxJoints][2][64].
+__host__ __device__ inline size_t tile_shared_floats(int n_robots, int cache_sc) {
+  return (size_t)n_robots * (kMaxLinks * 3 + (cache_sc ? kMaxJoints * 2 : 0)) * kWave;
+}
 
 template <bool STAGED>
-__global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 2) void validate_tiles_kernel(
+__global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_kernel(
     SceneDev sc, const float *__restrict__ qa, const float *__restrict__ qb, int64_t n_edges,
     const int64_t *__restrict__ off, const int32_t *__restrict__ tile_first, uint32_t *__restrict__ flags,
-    uint64_t *__restrict__ counters, uint64_t *__restrict__ partials) {
+    uint64_t *__restrict__ counters, uint64_t *__restrict__ partials, int S, int cache_sc) {
   // dynamic LDS: [R][kMaxLinks][3][64] published coarse centres, then per
   // wave kWaveLdsFloats (link frames, fine-test queue), then the staged scene
   extern __shared__ float cen[];
@@ -592,7 +760,6 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 2) void validate_tiles_k
   // wave index, marked wave-uniform so that per-arm data is read with scalar loads
   const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave), W = blockDim.x / kWave;
   const int R = sc.n_robots;
-  const int S = link_split(R);
   const int64_t total = (int64_t)counters[1];
   const int64_t n_tiles = (total + kWave - 1) / kWave;
   if ((int64_t)blockIdx.x >= n_tiles) {
@@ -602,9 +769,10 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 2) void validate_tiles_k
   uint32_t checked = 0, tiles = 0;
   WorkCount wc;
   if (threadIdx.x < 2) s_dead[threadIdx.x] = 0ull;
-  float *const wave_fr = cen + (size_t)R * kMaxLinks * 3 * kWave + (size_t)w * kWaveLdsFloats;
+  float *const sc_lds = cache_sc ? cen + (size_t)R * kMaxLinks * 3 * kWave : nullptr;
+  float *const wave_fr = cen + tile_shared_floats(R, cache_sc) + (size_t)w * kWaveLdsFloats;
   uint32_t *const wave_q = (uint32_t *)(wave_fr + 12 * kWave);
-  const Src<STAGED> src = make_src<STAGED>(sc, cen + (size_t)R * kMaxLinks * 3 * kWave + (size_t)W * kWaveLdsFloats);
+  const Src<STAGED> src = make_src<STAGED>(sc, cen + tile_shared_floats(R, cache_sc) + (size_t)W * kWaveLdsFloats);
   // Static order: workgroup b takes tiles b, b + G, b + 2G, ... (G = grid).
   // A shared work queue would need a device-wide atomic per tile, whose round
   // trip across the chip's eight XCDs costs more than a tile's setup.  The
@@ -685,24 +853,16 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 2) void validate_tiles_k
         for (int j = 0; j < kMaxJoints; ++j) qv[j] = st.last ? qb_v[j] : fmaf(st.t, qb_v[j] - qa_v[j], qa_v[j]);
       }
       const bool live = act && !hit;
-      if (arm_env<STAGED>(sc, src, r, m, part, S, qv, live, emask, cen, wave_fr, wave_q, &s_hit[w], dead, lane, wc))
+      if (arm_env<STAGED>(sc, src, r, m, part, S, qv, live, emask, cen, sc_lds, wave_fr, wave_q, &s_hit[w], dead,
+                          lane, wc))
         hit = true;
     }
     if (act && w == 0) ++checked;
     __syncthreads();
     if (threadIdx.x == 0) s_dead[(it + 1) & 1] = 0ull;  // last used by the previous tile
-    // arm pairs that can reach each other, one (pair, link of the first arm)
-    // item per wave at a time
-    for (int q = w; q < sc.n_pairs * kMaxLinks; q += W) {
-      const int p = q / kMaxLinks, a = q - p * kMaxLinks;
-      const int pi = as_const(sc.pairs)[2 * p], pj = as_const(sc.pairs)[2 * p + 1];
-      if (a > as_const(sc.nj)[as_const(sc.model)[pi]]) continue;
-      const bool live = act && !hit && !((dead_mask(dead) >> lane) & 1ull);
-      if (live && pair_link_test<STAGED>(sc, src, cen, lane, pi, pj, a, st, wc)) {
-        hit = true;
-        atomicOr(dead, (unsigned long long)emask);
-      }
-    }
+    // arm pairs that can reach each other
+    if (arm_pairs<STAGED>(sc, src, cen, sc_lds, w, W, act && !hit, st, emask, wave_q, &s_hit[w], dead, lane, wc))
+      hit = true;
     if (hit) flags[e] = kFlagHit;
     __syncthreads();  // centres and dead masks are reused by the next tile
   }
@@ -735,11 +895,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(const uint32_t *__restric
     __shared__ unsigned long long col[kPartialSlots];
     if (threadIdx.x < kPartialSlots) col[threadIdx.x] = 0ull;
     __syncthreads();
+    uint64_t acc[kPartialSlots] = {};
+    for (int b = threadIdx.x; b < n_partials; b += blockDim.x) {
+#pragma unroll
+      for (int i = 0; i < kPartialSlots; ++i) acc[i] += partials[(int64_t)b * kPartialSlots + i];
+    }
+#pragma unroll
     for (int i = 0; i < kPartialSlots; ++i) {
-      uint64_t acc = 0;
-      for (int b = threadIdx.x; b < n_partials; b += blockDim.x) acc += partials[(int64_t)b * kPartialSlots + i];
-      for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
-      if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&col[i], (unsigned long long)acc);
+      for (int d = kWave / 2; d > 0; d >>= 1) acc[i] += __shfl_xor(acc[i], d, kWave);
+      if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&col[i], (unsigned long long)acc[i]);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -764,44 +928,67 @@ __global__ __launch_bounds__(256) void finalize_kernel(const uint32_t *__restric
   }
 }
 
-static int block_waves(int n_robots) {
-  const int jobs = n_robots * link_split(n_robots);
-  return jobs < kMaxWavesPerBlock ? jobs : kMaxWavesPerBlock;
-}
+// Tile shape: S link parts per arm (waves per arm), W waves per workgroup,
+// and whether the joint sines/cosines are cached in LDS for the arm-pair
+// stage.  Small batches (few tiles, the planner's case) get the most waves
+// per tile, so that a tile's latency shrinks; large batches keep two
+// workgroups per CU.
+struct TileShape {
+  int S, W, cache_sc;
+};
 
-// Centres published for the arm-pair stage plus every wave's frame and queue.
-static size_t centre_lds_bytes(int n_robots) {
-  return ((size_t)n_robots * kMaxLinks * 3 * kWave + (size_t)block_waves(n_robots) * kWaveLdsFloats) * sizeof(float);
+// Centres (and cached sines/cosines) of the tile plus every wave's frame and queue.
+static size_t centre_lds_bytes(int n_robots, int W, int cache_sc) {
+  return (tile_shared_floats(n_robots, cache_sc) + (size_t)W * kWaveLdsFloats) * sizeof(float);
 }
 
 // Dynamic LDS budget of the tile kernel: staging is used when the scene's
 // copy fits next to the published centres.
 constexpr size_t kLdsBudget = 150 * 1024;
 
-static bool use_staged(const SceneDev &sc) {
-  if (sc.tile_mode == MRPOP_TILE_SCALAR) return false;
-  return centre_lds_bytes(sc.n_robots) + staged_floats(sc) * sizeof(float) <= kLdsBudget;
+static TileShape tile_shape(int n_robots, int64_t n_edges) {
+  const int cap = n_edges <= kSmallBatchEdges ? kMaxWavesPerBlock : kMaxWavesPerBlock / 2;
+  int S = 1;
+  while (S < 4 && n_robots * S * 2 <= cap) S *= 2;
+  int W = std::min(n_robots * S, cap);
+  while (W > 1 && centre_lds_bytes(n_robots, W, 0) > kLdsBudget) W /= 2;
+  const int cache = centre_lds_bytes(n_robots, W, 1) <= kLdsBudget ? 1 : 0;
+  return {S, W, cache};
 }
 
-// Resident workgroups for a persistent launch (cached per arm count, staging
+// LDS of one CU.
+constexpr size_t kLdsPerCu = 160 * 1024;
+
+// Staging in LDS: always under MRPOP_TILE_LDS when it fits; under
+// MRPOP_TILE_AUTO only when it fits and does not lower the number of
+// workgroups a CU holds (the scalar cache then serves the rows).
+static bool use_staged(const SceneDev &sc, const TileShape &ts) {
+  if (sc.tile_mode == MRPOP_TILE_SCALAR) return false;
+  const size_t base = centre_lds_bytes(sc.n_robots, ts.W, ts.cache_sc);
+  const size_t staged = base + staged_floats(sc) * sizeof(float);
+  if (staged > kLdsBudget) return false;
+  if (sc.tile_mode == MRPOP_TILE_LDS) return true;
+  return kLdsPerCu / staged >= kLdsPerCu / base;
+}
+
+// Resident workgroups for a persistent launch (cached per block size, staging
 // and LDS size).
 template <bool STAGED>
-static int persistent_grid(int n_robots, size_t lds) {
+static int persistent_grid(int W, size_t lds) {
   struct Key {
-    int r;
+    int w;
     size_t lds;
     int grid;
   };
   static std::vector<Key> cache;
   for (const Key &k : cache)
-    if (k.r == n_robots && k.lds == lds) return k.grid;
+    if (k.w == W && k.lds == lds) return k.grid;
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_tiles_kernel<STAGED>,
-                                                     kWave * block_waves(n_robots), lds);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_tiles_kernel<STAGED>, kWave * W, lds);
   const int grid = std::min(kMaxGrid, std::max(1, cus) * std::max(1, per));
-  cache.push_back({n_robots, lds, grid});
+  cache.push_back({W, lds, grid});
   return grid;
 }
 
@@ -812,25 +999,32 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
   const int64_t nb = scan_blocks(n_edges);
   const int64_t g256 = (n_edges + 255) / 256;
   if (g256 > 0x7fffffff || nb > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(count_states_kernel, dim3((unsigned)g256), dim3(256), 0, s, qa, qb, n_edges, sc.dof, res,
-                     n_states_opt, ws.n_states, ws.flags);
-  hipLaunchKernelGGL(scan_partials_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_edges,
-                     ws.block_sums);
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, ws.block_sums, nb, ws.counters);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_edges,
-                     ws.block_sums, ws.offsets, ws.tile_first);
-  const bool staged = use_staged(sc);
-  const size_t lds = centre_lds_bytes(sc.n_robots) + (staged ? staged_floats(sc) * sizeof(float) : 0);
-  const int grid = staged ? persistent_grid<true>(sc.n_robots, lds) : persistent_grid<false>(sc.n_robots, lds);
+  if (n_edges <= kScanThreads) {
+    hipLaunchKernelGGL(count_scan_small_kernel, dim3(1), dim3(kScanThreads), 0, s, qa, qb, n_edges, sc.dof, res,
+                       n_states_opt, ws.n_states, ws.flags, ws.offsets, ws.tile_first, ws.counters);
+  } else {
+    hipLaunchKernelGGL(count_states_kernel, dim3((unsigned)g256), dim3(256), 0, s, qa, qb, n_edges, sc.dof, res,
+                       n_states_opt, ws.n_states, ws.flags);
+    hipLaunchKernelGGL(scan_partials_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_edges,
+                       ws.block_sums);
+    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, ws.block_sums, nb, ws.counters);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_edges,
+                       ws.block_sums, ws.offsets, ws.tile_first);
+  }
+  const TileShape ts = tile_shape(sc.n_robots, n_edges);
+  const bool staged = use_staged(sc, ts);
+  const size_t lds =
+      centre_lds_bytes(sc.n_robots, ts.W, ts.cache_sc) + (staged ? staged_floats(sc) * sizeof(float) : 0);
+  const int grid = staged ? persistent_grid<true>(ts.W, lds) : persistent_grid<false>(ts.W, lds);
   if (grid_out) *grid_out = grid;
-  if (block_out) *block_out = kWave * block_waves(sc.n_robots);
+  if (block_out) *block_out = kWave * ts.W;
   if (ev_pair) (void)hipEventRecord(ev_pair->first, s);
   if (staged)
-    hipLaunchKernelGGL(validate_tiles_kernel<true>, dim3(grid), dim3(kWave * block_waves(sc.n_robots)), lds, s, sc,
-                       qa, qb, n_edges, ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials);
+    hipLaunchKernelGGL(validate_tiles_kernel<true>, dim3(grid), dim3(kWave * ts.W), lds, s, sc, qa, qb, n_edges,
+                       ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials, ts.S, ts.cache_sc);
   else
-    hipLaunchKernelGGL(validate_tiles_kernel<false>, dim3(grid), dim3(kWave * block_waves(sc.n_robots)), lds, s, sc,
-                       qa, qb, n_edges, ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials);
+    hipLaunchKernelGGL(validate_tiles_kernel<false>, dim3(grid), dim3(kWave * ts.W), lds, s, sc, qa, qb, n_edges,
+                       ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials, ts.S, ts.cache_sc);
   if (ev_pair) (void)hipEventRecord(ev_pair->second, s);
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)g256), dim3(256), 0, s, ws.flags, n_edges, out_valid,
                      ws.counters, ws.partials, grid, totals);

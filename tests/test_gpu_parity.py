@@ -218,3 +218,43 @@ def test_validate_tile_modes(ctx, mode):
     print(f"  {assert_bits_match(got, m, f'tile mode {mode}')}", flush=True)
     s.set_tile_mode("auto")
     assert np.array_equal(got, s.validate_edges(qa, qb, 0.05).cpu().numpy())
+
+
+def test_validate_more_edges_than_one_scan_block(ctx):
+    """More than 4096 edges take the multi-block count and scan path."""
+    sc = problem("c1").scene
+    qa, qb = W.edge_batch(sc, 6000, 0.05, 110, 1, 40)
+    _parity(ctx, sc, qa, qb, 0.05, "c1/6000 edges")
+
+
+def test_validate_sixteen_arms(ctx):
+    """Sixteen arms: the joint sine/cosine cache no longer fits next to the
+    published centres, so the arm-pair stage rebuilds frames from the joint
+    values."""
+    m = W.panda_like(20)
+    R = 16
+    sc = W.Scene([m] * R, W.ring_bases(R, W.ring_radius_for_spacing(R, 1.0)),
+                 np.array([[0.0, 0.0, 0.5, 0.2]], np.float32), np.zeros((0, 6), np.float32))
+    qa, qb = W.edge_batch(sc, 256, 0.05, 111, 2, 24)
+    _, m_, _ = _parity(ctx, sc, qa, qb, 0.05, "16 arms")
+    assert (m_ < -BAND).any() and (m_ > BAND).any()
+
+
+def _long_link_arm(n_tool: int) -> "W.RobotModel":
+    """Planar 2R arm whose second link carries n_tool small spheres."""
+    dh = np.array([[0.0, 0.0, 0.0, 0.0], [0.5, 0.0, 0.0, 0.0]], np.float32)
+    xs = np.linspace(0.02, 0.45, n_tool)
+    xyzr = [[0.25, 0.0, 0.0, 0.05]] + [[x, 0.0, 0.0, 0.012] for x in xs]
+    return W.RobotModel("planar_long_link", dh, np.array([-math.pi] * 2, np.float32), np.array([math.pi] * 2, np.float32),
+                        np.array([1] + [2] * n_tool, np.int32), np.array(xyzr, np.float32))
+
+
+@pytest.mark.parametrize("n_tool", [40, 100])
+def test_validate_arm_pairs_with_many_spheres_per_link(ctx, n_tool):
+    """Arm-pair fine tests where a link has fewer or more than 64 spheres."""
+    m = _long_link_arm(n_tool)
+    sc = W.Scene([m, m], np.stack([W.base_transform(-0.35, 0, 0), W.base_transform(0.35, 0, math.pi)]),
+                 np.zeros((0, 4), np.float32), np.zeros((0, 6), np.float32))
+    qa, qb = W.edge_batch(sc, 512, 0.05, 112, 2, 30)
+    _, m_, _ = _parity(ctx, sc, qa, qb, 0.05, f"pairs, {n_tool} spheres on a link")
+    assert (m_ < -BAND).any() and (m_ > BAND).any()

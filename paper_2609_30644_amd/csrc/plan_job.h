@@ -1,0 +1,93 @@
+// One planning instance (Alg. 1 with the subroutines of Alg. 2) whose device
+// work goes through an Exec, so that the same code runs a plain plan or one
+// instance of a batch.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "planner.h"
+
+namespace mrpop {
+
+class PlanJob {
+ public:
+  PlanJob() = default;
+  PlanJob(const PlanJob &) = delete;
+  PlanJob &operator=(const PlanJob &) = delete;
+  ~PlanJob();
+
+  // Host-side preparation: argument checks, device and pinned allocations,
+  // the one-arm sub-scenes of the roadmaps.  Queues no device work.
+  mrpop_status prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
+                       const mrpop_plan_params &params);
+  // Runs the planner; every device operation goes through ex.
+  mrpop_status run(Exec &ex);
+
+  // Results (after run): the best path (start -> goal, row-major [len][D]),
+  // its cost recomputed in double precision, statistics, and the message of
+  // a failed status.
+  const std::vector<float> &path() const { return best_path_; }
+  float cost() const { return c_best_; }
+  const mrpop_plan_stats &stats() const { return st_; }
+  const std::string &error() const { return err_; }
+  int dof() const { return D_; }
+  // Device bytes held by the instance (arena and sub-scenes).
+  size_t device_bytes() const { return device_bytes_; }
+
+ private:
+  mrpop_status fail_(mrpop_status s, const std::string &m) {
+    err_ = m;
+    return s;
+  }
+  mrpop_status hip_fail_(hipError_t e, const char *what) {
+    err_ = std::string(what) + ": " + hipGetErrorString(e);
+    return MRPOP_E_DEVICE;
+  }
+  mrpop_status validate_(Exec &ex, const mrpop_scene *sc, const float *a, const float *b, int64_t n, float res,
+                         uint8_t *out, uint64_t *counters);
+  mrpop_status copy_(Exec &ex, void *dst, const void *src, size_t bytes);
+  mrpop_status roadmap_(Exec &ex, int it);
+  double elapsed_() const;
+  bool out_of_time_() const;
+
+  mrpop_ctx *ctx_ = nullptr;
+  const mrpop_scene *scene_ = nullptr;
+  mrpop_plan_params P_{};
+  int R_ = 0, D_ = 0, PC_ = 0;
+  int rm_cap_ = 0, edge_cap_ = 0, col_cap_ = 0, cand_batch_ = 0, pair_cap_ = 0, tcap_ = 0, path_max_ = 0;
+  double t_start_ = 0.0;
+  std::string err_;
+  mrpop_plan_stats st_{};
+  float c_best_ = INFINITY;
+  std::vector<float> best_path_;
+  std::vector<int32_t> h_qoff_, h_nj_, rm_n_;
+  std::vector<mrpop_scene *> arms_;
+  size_t device_bytes_ = 0;
+
+  // device arena
+  void *arena_ = nullptr;
+  float *qs_, *qg_, *rm_V_, *cand_, *pair_qa_, *pair_qb_, *tq_[2], *tg_[2], *q_rand_, *c_rand_, *q_new_, *g_new_,
+      *ea_, *eb_, *budget_, *ca_, *cb_, *path_d_;
+  int32_t *rm_rowptr_, *rm_col_, *rm_edges_, *rm_nv_, *rm_ne_, *pair_ids_, *pair_count_, *taken_, *connected_, *deg_,
+      *level_, *tvid_[2], *tpar_[2], *tn_[2], *near_idx_, *vid_new_, *ins_idx_, *conn_idx_, *path_len_d_, *d_nj_,
+      *d_qoff_;
+  uint8_t *cand_valid_, *pair_valid_, *alive_, *valid_, *cvalid_;
+  uint64_t *cnt_;  // [3][16]: counters of the extension, connection and roadmap validations
+  RoundStatus *status_;
+
+  // pinned host memory (device-visible): uploads, and what comes back
+  struct Pinned {
+    RoundStatus status;
+    int32_t ints[4];
+    uint64_t cnt[2];
+    uint8_t valid2[8];
+  };
+  Pinned *pin_ = nullptr;
+  float *upload_ = nullptr;  // qs, qg, roadmap seeds [R][2][kRmStride]
+  int32_t *upload_i_ = nullptr;  // nj, q_off
+  float *pin_path_ = nullptr;
+  size_t pin_path_cap_ = 0;
+};
+
+}  // namespace mrpop

@@ -8,6 +8,10 @@
 // One small status record per round comes back to the host (pinned memory),
 // which decides whether the search ended, swaps the trees when the extended
 // one has grown larger, and extracts a path on success.
+//
+// The driver is a PlanJob: its device work goes through an Exec, which runs
+// it at once on a stream for mrpop_plan, or merges it with other instances'
+// work for mrpop_plan_batch.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -15,54 +19,11 @@
 #include <memory>
 #include <vector>
 
-#include "planner.h"
+#include "plan_job.h"
 
 using namespace mrpop;
 
 namespace {
-
-struct Arena {
-  std::vector<std::pair<void **, size_t>> items;
-  template <class T>
-  void add(T **p, size_t n) {
-    items.push_back({(void **)p, std::max<size_t>(n, 1) * sizeof(T)});
-  }
-  void *base = nullptr;
-  hipError_t alloc() {
-    size_t total = 0;
-    for (auto &it : items) total += (it.second + 255) & ~size_t(255);
-    hipError_t e = hipMalloc(&base, total);
-    if (e != hipSuccess) {
-      base = nullptr;
-      return e;
-    }
-    size_t off = 0;
-    for (auto &it : items) {
-      *it.first = (unsigned char *)base + off;
-      off += (it.second + 255) & ~size_t(255);
-    }
-    return hipSuccess;
-  }
-  ~Arena() {
-    if (base) (void)hipFree(base);
-  }
-};
-
-struct PinnedStatus {
-  RoundStatus *h = nullptr;
-  int32_t *ints = nullptr;
-  ~PinnedStatus() {
-    if (h) (void)hipHostFree(h);
-    if (ints) (void)hipHostFree(ints);
-  }
-};
-
-struct SceneHolder {
-  mrpop_scene *s = nullptr;
-  ~SceneHolder() {
-    if (s) mrpop_scene_destroy(s);
-  }
-};
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -78,11 +39,447 @@ mrpop_status arm_scene(mrpop_ctx *ctx, const mrpop_scene *sc, int r, mrpop_scene
   return mrpop_scene_create(ctx, &rb, 1, &env, out);
 }
 
+// Sub-allocations of one device allocation (256-byte aligned).
+struct ArenaPlan {
+  std::vector<std::pair<void **, size_t>> items;
+  template <class T>
+  void add(T **p, size_t n) {
+    items.push_back({(void **)p, std::max<size_t>(n, 1) * sizeof(T)});
+  }
+  size_t total() const {
+    size_t t = 0;
+    for (auto &it : items) t += (it.second + 255) & ~size_t(255);
+    return t;
+  }
+  void assign(void *base) {
+    size_t off = 0;
+    for (auto &it : items) {
+      *it.first = (unsigned char *)base + off;
+      off += (it.second + 255) & ~size_t(255);
+    }
+  }
+};
+
 }  // namespace
 
-#define HIP_TRY(expr, what)                      \
-  do {                                           \
-    hipError_t e_ = (expr);                      \
+namespace mrpop {
+
+// Device work launched at once on one stream.
+class PlainExec : public Exec {
+ public:
+  PlainExec(mrpop_ctx *ctx, hipStream_t s) : ctx_(ctx), s_(s) {}
+  hipError_t submit(const Cmd &c) override {
+    if (c.op == Op::Validate) {
+      const ValidateReq &v = c.val;
+      if (v.n <= 0) return hipSuccess;
+      void *base = nullptr;
+      if (scratch(ctx_, 1, validate_scratch_bytes(v.n), &base) != MRPOP_OK) return hipErrorOutOfMemory;
+      ValidateScratch ws = validate_scratch_layout(base, v.n);
+      ws.counters = v.counters;
+      return launch_validate(*v.scene, v.qa, v.qb, v.n, v.res, nullptr, v.out, ws, s_, profile_slot(ctx_),
+                             ctx_->profiling ? ctx_->prof_totals : nullptr, &ctx_->last_grid, &ctx_->last_block);
+    }
+    if (c.op == Op::Copy) return hipMemcpyAsync(c.copy.dst, c.copy.src, c.copy.bytes, hipMemcpyDefault, s_);
+    return launch_op(c.op, c.args(), s_);
+  }
+  hipError_t sync() override { return hipStreamSynchronize(s_); }
+
+ private:
+  mrpop_ctx *ctx_;
+  hipStream_t s_;
+};
+
+PlanJob::~PlanJob() {
+  for (mrpop_scene *a : arms_)
+    if (a) mrpop_scene_destroy(a);
+  if (arena_) (void)hipFree(arena_);
+  if (pin_) (void)hipHostFree(pin_);
+  if (upload_) (void)hipHostFree(upload_);
+  if (upload_i_) (void)hipHostFree(upload_i_);
+  if (pin_path_) (void)hipHostFree(pin_path_);
+}
+
+double PlanJob::elapsed_() const { return now_s() - t_start_; }
+bool PlanJob::out_of_time_() const { return P_.time_budget_s > 0 && elapsed_() >= P_.time_budget_s; }
+
+mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
+                              const mrpop_plan_params &P) {
+  ctx_ = ctx;
+  scene_ = scene;
+  P_ = P;
+  if (P.candidates < 1 || P.candidates > 4096 || !(P.resolution > 0.f) || !std::isfinite(P.resolution) ||
+      P.max_rounds < 1 || P.max_iterations < 1 || P.max_growth_rounds < 1 || P.n_roadmap < 1 ||
+      P.max_tree_nodes < 2 || P.max_roadmap_nodes < 4 || !(P.delta > 0.f) || P.time_budget_s < 0 ||
+      std::isnan(P.warm_cost))
+    return fail_(MRPOP_E_INVALID_ARG, "plan: parameter out of range");
+  R_ = scene->n_robots;
+  D_ = scene->dof;
+  PC_ = P.candidates;
+  for (int j = 0; j < D_; ++j)
+    if (!std::isfinite(q_start[j]) || !std::isfinite(q_goal[j]))
+      return fail_(MRPOP_E_NONFINITE, "plan: non-finite start or goal");
+  std::memset(&st_, 0, sizeof(st_));
+  st_.time_to_first_s = -1.0;
+  st_.first_round = -1;
+  c_best_ = P.warm_cost;
+
+  rm_cap_ = P.max_roadmap_nodes;
+  edge_cap_ = rm_cap_ * 32;
+  col_cap_ = 2 * edge_cap_;
+  cand_batch_ = 4 * P.n_roadmap;
+  pair_cap_ = P.n_roadmap * rm_cap_;
+  tcap_ = P.max_tree_nodes;
+  path_max_ = 16384;
+  int max_nj = 0;
+  for (int r = 0; r < R_; ++r) max_nj = std::max(max_nj, scene->nj[r]);
+  const int R = R_, D = D_, PC = PC_;
+
+  ArenaPlan ar;
+  ar.add(&qs_, D);
+  ar.add(&qg_, D);
+  ar.add(&rm_V_, (size_t)R * rm_cap_ * kRmStride);
+  ar.add(&rm_rowptr_, (size_t)R * (rm_cap_ + 1));
+  ar.add(&rm_col_, (size_t)R * col_cap_);
+  ar.add(&rm_edges_, (size_t)R * edge_cap_ * 2);
+  ar.add(&rm_nv_, R);
+  ar.add(&rm_ne_, R);
+  ar.add(&cand_, (size_t)cand_batch_ * kRmStride);
+  ar.add(&cand_valid_, cand_batch_);
+  ar.add(&pair_ids_, (size_t)pair_cap_ * 2);
+  ar.add(&pair_qa_, (size_t)pair_cap_ * max_nj);
+  ar.add(&pair_qb_, (size_t)pair_cap_ * max_nj);
+  ar.add(&pair_valid_, pair_cap_);
+  ar.add(&pair_count_, 1);
+  ar.add(&taken_, 1);
+  ar.add(&connected_, 1);
+  ar.add(&deg_, rm_cap_);
+  ar.add(&level_, rm_cap_);
+  for (int t = 0; t < 2; ++t) {
+    ar.add(&tq_[t], (size_t)D * tcap_);
+    ar.add(&tg_[t], tcap_);
+    ar.add(&tvid_[t], (size_t)R * tcap_);
+    ar.add(&tpar_[t], tcap_);
+    ar.add(&tn_[t], 1);
+  }
+  ar.add(&q_rand_, (size_t)PC * D);
+  ar.add(&c_rand_, PC);
+  ar.add(&near_idx_, PC);
+  ar.add(&q_new_, (size_t)PC * D);
+  ar.add(&g_new_, PC);
+  ar.add(&vid_new_, (size_t)R * PC);
+  ar.add(&alive_, PC);
+  ar.add(&ea_, (size_t)PC * D);
+  ar.add(&eb_, (size_t)PC * D);
+  ar.add(&valid_, PC);
+  ar.add(&ins_idx_, PC);
+  ar.add(&budget_, PC);
+  ar.add(&conn_idx_, PC);
+  ar.add(&ca_, (size_t)PC * D);
+  ar.add(&cb_, (size_t)PC * D);
+  ar.add(&cvalid_, PC);
+  ar.add(&cnt_, 3 * 16);
+  ar.add(&status_, 1);
+  ar.add(&path_d_, (size_t)path_max_ * D);
+  ar.add(&path_len_d_, 1);
+  ar.add(&d_nj_, R);
+  ar.add(&d_qoff_, R);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMalloc(&arena_, ar.total());
+  if (e != hipSuccess) {
+    arena_ = nullptr;
+    return e == hipErrorOutOfMemory ? fail_(MRPOP_E_NOMEM, "plan: device memory") : hip_fail_(e, "hipMalloc(plan)");
+  }
+  ar.assign(arena_);
+  device_bytes_ = ar.total();
+  if ((e = hipHostMalloc((void **)&pin_, sizeof(Pinned))) != hipSuccess) return hip_fail_(e, "hipHostMalloc");
+  const size_t up_floats = 2 * (size_t)D + (size_t)R * 2 * kRmStride;
+  if ((e = hipHostMalloc((void **)&upload_, sizeof(float) * up_floats)) != hipSuccess)
+    return hip_fail_(e, "hipHostMalloc");
+  if ((e = hipHostMalloc((void **)&upload_i_, sizeof(int32_t) * (4 * (size_t)R + 2))) != hipSuccess)
+    return hip_fail_(e, "hipHostMalloc");
+
+  h_qoff_.assign(R, 0);
+  h_nj_.assign(R, 0);
+  for (int r = 0, o = 0; r < R; ++r) {
+    h_qoff_[r] = o;
+    h_nj_[r] = scene->nj[r];
+    o += scene->nj[r];
+  }
+  // uploads: start, goal, roadmap seeds (vertex 0 = the arm's start, 1 = its goal)
+  std::memcpy(upload_, q_start, sizeof(float) * D);
+  std::memcpy(upload_ + D, q_goal, sizeof(float) * D);
+  float *init = upload_ + 2 * D;
+  std::fill(init, init + (size_t)R * 2 * kRmStride, 0.f);
+  for (int r = 0; r < R; ++r)
+    for (int j = 0; j < h_nj_[r]; ++j) {
+      init[((size_t)r * 2 + 0) * kRmStride + j] = q_start[h_qoff_[r] + j];
+      init[((size_t)r * 2 + 1) * kRmStride + j] = q_goal[h_qoff_[r] + j];
+    }
+  for (int r = 0; r < R; ++r) {
+    upload_i_[r] = h_nj_[r];
+    upload_i_[R + r] = h_qoff_[r];
+    upload_i_[2 * R + r] = 2;  // roadmap vertex counts
+    upload_i_[3 * R + r] = 0;  // roadmap edge counts
+  }
+  arms_.assign(R, nullptr);
+  for (int r = 0; r < R; ++r) {
+    mrpop_status a = arm_scene(ctx, scene, r, &arms_[r]);
+    if (a != MRPOP_OK) return fail_(a, "plan: arm scene: " + ctx->last_error);
+    device_bytes_ += arms_[r]->blob_bytes;
+  }
+  rm_n_.assign(R, 2);
+  return MRPOP_OK;
+}
+
+mrpop_status PlanJob::copy_(Exec &ex, void *dst, const void *src, size_t bytes) {
+  Cmd c;
+  c.op = Op::Copy;
+  c.copy = CopyArgs{dst, src, (int64_t)bytes};
+  const hipError_t e = ex.submit(c);
+  return e == hipSuccess ? MRPOP_OK : hip_fail_(e, "copy");
+}
+
+mrpop_status PlanJob::validate_(Exec &ex, const mrpop_scene *sc, const float *a, const float *b, int64_t n,
+                                float res, uint8_t *out, uint64_t *counters) {
+  if (n <= 0) {
+    Cmd z;
+    z.op = Op::Fill;
+    z.fill = FillArgs{(uint32_t *)counters, 0u, 32};
+    const hipError_t e = ex.submit(z);
+    return e == hipSuccess ? MRPOP_OK : hip_fail_(e, "fill");
+  }
+  Cmd c;
+  c.op = Op::Validate;
+  c.val = ValidateReq{&sc->dev, a, b, n, res, out, counters};
+  const hipError_t e = ex.submit(c);
+  return e == hipSuccess ? MRPOP_OK : hip_fail_(e, "validate launch");
+}
+
+#define SUBMIT(OPV, FIELD, ...)                         \
+  do {                                                  \
+    Cmd c_;                                             \
+    c_.op = OPV;                                        \
+    c_.FIELD = __VA_ARGS__;                             \
+    const hipError_t e_ = ex.submit(c_);                \
+    if (e_ != hipSuccess) return hip_fail_(e_, #FIELD); \
+  } while (0)
+
+#define SYNC()                                          \
+  do {                                                  \
+    const hipError_t e_ = ex.sync();                    \
+    if (e_ != hipSuccess) return hip_fail_(e_, "sync"); \
+  } while (0)
+
+#define TRY(expr)                   \
+  do {                              \
+    const mrpop_status s_ = (expr); \
+    if (s_ != MRPOP_OK) return s_;  \
+  } while (0)
+
+// ROADMAP (Alg. 2) for outer iteration `it`.
+mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
+  const int R = R_;
+  std::vector<char> conn(R, 0);
+  for (int g = 0; g < P_.max_growth_rounds; ++g) {
+    bool all = true;
+    for (int r = 0; r < R; ++r) {
+      if (conn[r]) continue;
+      const int nj = h_nj_[r];
+      float *V = rm_V_ + (size_t)r * rm_cap_ * kRmStride;
+      const int n0 = rm_n_[r];
+      int need = std::min(P_.n_roadmap, rm_cap_ - n0);
+      if (need <= 0) st_.capacity_hit = 1;
+      for (int64_t j0 = 0; need > 0; j0 += cand_batch_) {
+        SUBMIT(Op::RmSample, rm_sample,
+               RmSampleArgs{cand_, cand_batch_, nj, scene_->dev.q_lo + h_qoff_[r], scene_->dev.q_hi + h_qoff_[r],
+                            roadmap_key(P_.seed, (uint64_t)it * 1024 + g, (uint64_t)r), j0});
+        TRY(validate_(ex, arms_[r], cand_, cand_, cand_batch_, 1.0f, cand_valid_, cnt_ + 32));
+        SUBMIT(Op::RmAccept, rm_accept,
+               RmAcceptArgs{cand_, cand_valid_, cand_batch_, nj, need, V, rm_nv_ + r, rm_cap_, taken_});
+        TRY(copy_(ex, &pin_->ints[0], taken_, sizeof(int32_t)));
+        SYNC();
+        need -= pin_->ints[0];
+        if (j0 > (int64_t)cand_batch_ * 64) break;  // the arm's free space is (nearly) empty
+      }
+      TRY(copy_(ex, &pin_->ints[0], rm_nv_ + r, sizeof(int32_t)));
+      SYNC();
+      rm_n_[r] = pin_->ints[0];
+      // candidate edges between the new vertices and all earlier ones
+      SUBMIT(Op::Fill, fill, FillArgs{(uint32_t *)pair_count_, 0u, 1});
+      SUBMIT(Op::RmPairs, rm_pairs,
+             RmPairsArgs{V, n0, rm_n_[r], nj, P_.delta, pair_count_, pair_cap_, pair_ids_, pair_qa_, pair_qb_});
+      TRY(copy_(ex, &pin_->ints[0], pair_count_, sizeof(int32_t)));
+      SYNC();
+      const int np = std::min(pin_->ints[0], pair_cap_);
+      if (pin_->ints[0] > pair_cap_) st_.capacity_hit = 1;
+      TRY(validate_(ex, arms_[r], pair_qa_, pair_qb_, np, P_.resolution, pair_valid_, cnt_ + 32));
+      if (np > 0)
+        SUBMIT(Op::RmAddEdges, rm_add_edges,
+               RmAddEdgesArgs{pair_ids_, pair_valid_, pair_count_, np, rm_edges_ + (size_t)r * edge_cap_ * 2,
+                              rm_ne_ + r, edge_cap_});
+      SUBMIT(Op::RmBfs, rm_bfs,
+             RmBfsArgs{rm_edges_ + (size_t)r * edge_cap_ * 2, rm_ne_ + r, edge_cap_, rm_n_[r],
+                       rm_rowptr_ + (size_t)r * (rm_cap_ + 1), rm_col_ + (size_t)r * col_cap_, col_cap_, deg_, level_,
+                       connected_});
+      TRY(copy_(ex, &pin_->ints[0], connected_, sizeof(int32_t)));
+      TRY(copy_(ex, &pin_->cnt[0], cnt_ + 32, 2 * sizeof(uint64_t)));
+      SYNC();
+      if (np > 0) st_.roadmap_edge_states += (int64_t)pin_->cnt[1];
+      conn[r] = (char)pin_->ints[0];
+      all = all && conn[r];
+    }
+    if (all) break;
+    if (out_of_time_()) break;
+  }
+  st_.roadmap_connected = 1;
+  for (int r = 0; r < R; ++r) st_.roadmap_connected = st_.roadmap_connected && conn[r];
+  return MRPOP_OK;
+}
+
+mrpop_status PlanJob::run(Exec &ex) {
+  const int R = R_, D = D_, PC = PC_;
+  t_start_ = now_s();
+  // uploads
+  TRY(copy_(ex, qs_, upload_, sizeof(float) * D));
+  TRY(copy_(ex, qg_, upload_ + D, sizeof(float) * D));
+  TRY(copy_(ex, d_nj_, upload_i_, sizeof(int32_t) * R));
+  TRY(copy_(ex, d_qoff_, upload_i_ + R, sizeof(int32_t) * R));
+  TRY(copy_(ex, rm_nv_, upload_i_ + 2 * R, sizeof(int32_t) * R));
+  TRY(copy_(ex, rm_ne_, upload_i_ + 3 * R, sizeof(int32_t) * R));
+  for (int r = 0; r < R; ++r)
+    TRY(copy_(ex, rm_V_ + (size_t)r * rm_cap_ * kRmStride, upload_ + 2 * D + (size_t)r * 2 * kRmStride,
+              sizeof(float) * 2 * kRmStride));
+  SUBMIT(Op::Fill, fill, FillArgs{(uint32_t *)rm_rowptr_, 0u, (int64_t)R * (rm_cap_ + 1)});
+
+  // endpoints
+  TRY(copy_(ex, ea_, upload_, sizeof(float) * D));
+  TRY(copy_(ex, ea_ + D, upload_ + D, sizeof(float) * D));
+  TRY(validate_(ex, scene_, ea_, ea_, 2, 1.0f, valid_, cnt_));
+  TRY(copy_(ex, pin_->valid2, valid_, 2));
+  SYNC();
+  if (!pin_->valid2[0]) return fail_(MRPOP_E_START_INVALID, "plan: start state collides");
+  if (!pin_->valid2[1]) return fail_(MRPOP_E_GOAL_INVALID, "plan: goal state collides");
+
+  int rnd = 0, it = 0;
+  bool overflow_no_path = false;
+  std::vector<float> hpath;
+  while (it < P_.max_iterations && rnd < P_.max_rounds && !out_of_time_()) {
+    TRY(roadmap_(ex, it));
+    // fresh trees: 0 rooted at the start, 1 at the goal
+    SUBMIT(Op::TreeRoot, tree_root, TreeRootArgs{tq_[0], tg_[0], tvid_[0], tpar_[0], tn_[0], tcap_, qs_, D, R, 0});
+    SUBMIT(Op::TreeRoot, tree_root, TreeRootArgs{tq_[1], tg_[1], tvid_[1], tpar_[1], tn_[1], tcap_, qg_, D, R, 1});
+    int n_t[2] = {1, 1};
+    int a = 0;  // index of the tree being extended
+    bool solved = false;
+    while (!solved && rnd < P_.max_rounds && !out_of_time_()) {
+      if (n_t[a] > n_t[1 - a]) a = 1 - a;
+      const int b = 1 - a;
+      const float cb = c_best_;
+      SUBMIT(Op::Sample, sample,
+             SampleArgs{PC, D, cb, P_.seed, (uint64_t)rnd, 0, scene_->dev.q_lo, scene_->dev.q_hi, qs_, qg_, tq_[a],
+                        tcap_, q_rand_, c_rand_});
+      SUBMIT(Op::Nearest, nearest,
+             NearestArgs{tq_[a], tg_[a], n_t[a], D, 1, tcap_, q_rand_, D, cb < INFINITY ? c_rand_ : nullptr, PC,
+                         near_idx_});
+      SUBMIT(Op::Extend, extend,
+             ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a], tvid_[a], tg_[a],
+                        tcap_, rm_V_, rm_rowptr_, rm_col_, rm_cap_, col_cap_, d_nj_, d_qoff_, q_new_, vid_new_, g_new_,
+                        alive_, ea_, eb_});
+      TRY(validate_(ex, scene_, ea_, eb_, PC, P_.resolution, valid_, cnt_));
+      SUBMIT(Op::Insert, insert,
+             InsertArgs{PC, D, R, alive_, valid_, q_new_, g_new_, vid_new_, near_idx_, tq_[a], tg_[a], tvid_[a],
+                        tpar_[a], tn_[a], tcap_, cb, ins_idx_, budget_, status_});
+      SUBMIT(Op::Nearest, nearest,
+             NearestArgs{tq_[b], tg_[b], n_t[b], D, 1, tcap_, q_new_, D, budget_, PC, conn_idx_});
+      SUBMIT(Op::Conn, conn, ConnArgs{PC, D, conn_idx_, q_new_, tq_[b], tcap_, ca_, cb_});
+      TRY(validate_(ex, scene_, ca_, cb_, PC, P_.resolution, cvalid_, cnt_ + 16));
+      SUBMIT(Op::Select, select,
+             SelectArgs{PC, D, ins_idx_, conn_idx_, cvalid_, q_new_, g_new_, tq_[b], tg_[b], tcap_, cnt_, cnt_ + 16,
+                        status_});
+      TRY(copy_(ex, &pin_->status, status_, sizeof(RoundStatus)));
+      SYNC();
+      const RoundStatus rsx = pin_->status;
+      st_.edge_states += rsx.states_ext + rsx.states_conn;
+      n_t[a] += rsx.inserted;
+      if (rsx.overflow) st_.capacity_hit = 1;
+      ++rnd;
+      if (rsx.found) {
+        SUBMIT(Op::Path, path,
+               PathArgs{rsx.a_idx, rsx.b_idx, D, tcap_, path_max_, tpar_[a], tpar_[b], tq_[a], tq_[b], path_d_,
+                        path_len_d_});
+        TRY(copy_(ex, &pin_->ints[0], path_len_d_, sizeof(int32_t)));
+        SYNC();
+        const int len = pin_->ints[0];
+        if (len > path_max_ || len < 2) {
+          st_.capacity_hit = 1;
+        } else {
+          const size_t need = (size_t)len * D;
+          if (need > pin_path_cap_) {
+            if (pin_path_) (void)hipHostFree(pin_path_);
+            pin_path_ = nullptr;
+            pin_path_cap_ = 0;
+            const hipError_t e = hipHostMalloc((void **)&pin_path_, sizeof(float) * need);
+            if (e != hipSuccess) return hip_fail_(e, "hipHostMalloc(path)");
+            pin_path_cap_ = need;
+          }
+          TRY(copy_(ex, pin_path_, path_d_, sizeof(float) * need));
+          SYNC();
+          hpath.assign(pin_path_, pin_path_ + need);
+          if (a == 1) {  // tree 1 is rooted at the goal: orient start -> goal
+            for (int x = 0, y = len - 1; x < y; ++x, --y)
+              std::swap_ranges(hpath.begin() + (size_t)x * D, hpath.begin() + (size_t)(x + 1) * D,
+                               hpath.begin() + (size_t)y * D);
+          }
+          double cost = 0.0;
+          for (int k = 0; k + 1 < len; ++k) {
+            double d2 = 0.0;
+            for (int j = 0; j < D; ++j) {
+              const double t = (double)hpath[(size_t)(k + 1) * D + j] - (double)hpath[(size_t)k * D + j];
+              d2 += t * t;
+            }
+            cost += std::sqrt(d2);
+          }
+          if ((float)cost < c_best_) {  // strictly cheaper incumbents only
+            c_best_ = (float)cost;
+            best_path_ = hpath;
+            if (st_.n_costs < 64) st_.costs[st_.n_costs++] = c_best_;
+            ++st_.solutions;
+            if (st_.first_round < 0) {
+              st_.first_round = rnd - 1;
+              st_.time_to_first_s = elapsed_();
+            }
+            solved = true;
+          }
+        }
+      }
+      if (rsx.overflow && !solved) {
+        overflow_no_path = best_path_.empty();
+        break;
+      }
+    }
+    ++it;
+    if (!solved) break;
+    if (P_.stop_at_first && !best_path_.empty()) break;
+  }
+  st_.rounds = rnd;
+  st_.iterations = it;
+  for (int r = 0; r < R; ++r) st_.roadmap_vertices += rm_n_[r];
+  st_.total_time_s = elapsed_();
+  if (best_path_.empty())
+    return overflow_no_path ? fail_(MRPOP_E_CAPACITY, "plan: search tree full before any solution")
+                            : fail_(MRPOP_E_NO_SOLUTION, "plan: budget exhausted without a solution");
+  return MRPOP_OK;
+}
+
+#undef SUBMIT
+#undef SYNC
+#undef TRY
+
+}  // namespace mrpop
+
+#define HIP_TRY(expr, what)                               \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
     if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
   } while (0)
 
@@ -110,7 +507,8 @@ mrpop_status mrpop_nearest(mrpop_ctx *ctx, const float *vertices, const float *c
                            const float *queries, const float *budgets, int64_t n_queries, int32_t *out_idx,
                            void *stream) {
   if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "nearest: ctx is NULL");
-  if (n_vertices < 0 || n_queries < 0 || dim < 1 || dim > kMaxDof || n_vertices > 0x7fffffff)
+  if (n_vertices < 0 || n_queries < 0 || dim < 1 || dim > kMaxDof || n_vertices > 0x7fffffff ||
+      n_queries > 0x7fffffff)
     return fail(ctx, MRPOP_E_INVALID_ARG, "nearest: sizes out of range");
   if (n_queries == 0) return MRPOP_OK;
   if (!queries || !out_idx || (n_vertices > 0 && !vertices))
@@ -144,328 +542,22 @@ mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q
   if (!scene || scene->ctx != ctx) return fail(ctx, MRPOP_E_INVALID_ARG, "plan: scene not from this ctx");
   if (!q_start || !q_goal || !params || !path_len || !cost_out || (path_cap > 0 && !path_out))
     return fail(ctx, MRPOP_E_INVALID_ARG, "plan: NULL argument");
-  const mrpop_plan_params &P = *params;
-  if (P.candidates < 1 || P.candidates > 4096 || !(P.resolution > 0.f) || !std::isfinite(P.resolution) ||
-      P.max_rounds < 1 || P.max_iterations < 1 || P.max_growth_rounds < 1 || P.n_roadmap < 1 ||
-      P.max_tree_nodes < 2 || P.max_roadmap_nodes < 4 || !(P.delta > 0.f) || P.time_budget_s < 0 ||
-      std::isnan(P.warm_cost))
-    return fail(ctx, MRPOP_E_INVALID_ARG, "plan: parameter out of range");
-  const int R = scene->n_robots, D = scene->dof, PC = P.candidates;
-  for (int j = 0; j < D; ++j)
-    if (!std::isfinite(q_start[j]) || !std::isfinite(q_goal[j]))
-      return fail(ctx, MRPOP_E_NONFINITE, "plan: non-finite start or goal");
   *path_len = 0;
   *cost_out = INFINITY;
-  mrpop_plan_stats st;
-  std::memset(&st, 0, sizeof(st));
-  st.time_to_first_s = -1.0;
-  st.first_round = -1;
-  const double t_start = now_s();
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-  hipStream_t s = nullptr;
-
-  // ---- device buffers ----------------------------------------------------
-  const int rm_cap = P.max_roadmap_nodes, edge_cap = rm_cap * 32, col_cap = 2 * edge_cap;
-  const int cand_batch = 4 * P.n_roadmap;
-  const int pair_cap = P.n_roadmap * rm_cap;
-  const int tcap = P.max_tree_nodes;
-  const int path_max = 16384;
-  int max_nj = 0;
-  for (int r = 0; r < R; ++r) max_nj = std::max(max_nj, scene->nj[r]);
-  Arena ar;
-  float *qs, *qg, *rm_V, *cand, *pair_qa, *pair_qb, *tq[2], *tg[2], *q_rand, *c_rand, *q_new, *g_new, *ea, *eb,
-      *budget, *ca, *cb, *path;
-  int32_t *rm_rowptr, *rm_col, *rm_edges, *rm_nv, *rm_ne, *pair_ids, *pair_count, *taken, *connected, *deg, *level,
-      *tvid[2], *tpar[2], *tn[2], *near_idx, *vid_new, *ins_idx, *conn_idx, *path_len_d, *d_nj, *d_qoff;
-  uint8_t *cand_valid, *pair_valid, *alive, *valid, *cvalid;
-  RoundStatus *status;
-  ar.add(&qs, D);
-  ar.add(&qg, D);
-  ar.add(&rm_V, (size_t)R * rm_cap * kRmStride);
-  ar.add(&rm_rowptr, (size_t)R * (rm_cap + 1));
-  ar.add(&rm_col, (size_t)R * col_cap);
-  ar.add(&rm_edges, (size_t)R * edge_cap * 2);
-  ar.add(&rm_nv, R);
-  ar.add(&rm_ne, R);
-  ar.add(&cand, (size_t)cand_batch * kRmStride);
-  ar.add(&cand_valid, cand_batch);
-  ar.add(&pair_ids, (size_t)pair_cap * 2);
-  ar.add(&pair_qa, (size_t)pair_cap * max_nj);
-  ar.add(&pair_qb, (size_t)pair_cap * max_nj);
-  ar.add(&pair_valid, pair_cap);
-  ar.add(&pair_count, 1);
-  ar.add(&taken, 1);
-  ar.add(&connected, 1);
-  ar.add(&deg, rm_cap);
-  ar.add(&level, rm_cap);
-  for (int t = 0; t < 2; ++t) {
-    ar.add(&tq[t], (size_t)D * tcap);
-    ar.add(&tg[t], tcap);
-    ar.add(&tvid[t], (size_t)R * tcap);
-    ar.add(&tpar[t], tcap);
-    ar.add(&tn[t], 1);
+  PlanJob job;
+  mrpop_status st = job.prepare(ctx, scene, q_start, q_goal, *params);
+  if (st == MRPOP_OK) {
+    PlainExec ex(ctx, nullptr);
+    st = job.run(ex);
   }
-  ar.add(&q_rand, (size_t)PC * D);
-  ar.add(&c_rand, PC);
-  ar.add(&near_idx, PC);
-  ar.add(&q_new, (size_t)PC * D);
-  ar.add(&g_new, PC);
-  ar.add(&vid_new, (size_t)R * PC);
-  ar.add(&alive, PC);
-  ar.add(&ea, (size_t)PC * D);
-  ar.add(&eb, (size_t)PC * D);
-  ar.add(&valid, PC);
-  ar.add(&ins_idx, PC);
-  ar.add(&budget, PC);
-  ar.add(&conn_idx, PC);
-  ar.add(&ca, (size_t)PC * D);
-  ar.add(&cb, (size_t)PC * D);
-  ar.add(&cvalid, PC);
-  ar.add(&status, 1);
-  ar.add(&path, (size_t)path_max * D);
-  ar.add(&path_len_d, 1);
-  ar.add(&d_nj, R);
-  ar.add(&d_qoff, R);
-  HIP_TRY(ar.alloc(), "hipMalloc(plan)");
-  PinnedStatus pin;
-  HIP_TRY(hipHostMalloc((void **)&pin.h, sizeof(RoundStatus)), "hipHostMalloc");
-  HIP_TRY(hipHostMalloc((void **)&pin.ints, 4 * sizeof(int32_t)), "hipHostMalloc");
-
-  std::vector<int32_t> h_qoff(R), h_nj(R);
-  for (int r = 0, o = 0; r < R; ++r) {
-    h_qoff[r] = o;
-    h_nj[r] = scene->nj[r];
-    o += scene->nj[r];
-  }
-  HIP_TRY(hipMemcpy(qs, q_start, sizeof(float) * D, hipMemcpyHostToDevice), "copy");
-  HIP_TRY(hipMemcpy(qg, q_goal, sizeof(float) * D, hipMemcpyHostToDevice), "copy");
-  HIP_TRY(hipMemcpy(d_nj, h_nj.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice), "copy");
-  HIP_TRY(hipMemcpy(d_qoff, h_qoff.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice), "copy");
-
-  // ---- validation helper (separate scratch per use) -----------------------
-  auto validate = [&](const mrpop_scene *sc, const float *a, const float *b, int64_t n, float res, uint8_t *out,
-                      int slot, uint64_t **counters) -> mrpop_status {
-    void *base = nullptr;
-    mrpop_status st2 = scratch(ctx, slot, validate_scratch_bytes(std::max<int64_t>(n, 1)), &base);
-    if (st2 != MRPOP_OK) return st2;
-    ValidateScratch ws = validate_scratch_layout(base, std::max<int64_t>(n, 1));
-    if (counters) *counters = ws.counters;
-    if (n == 0) return MRPOP_OK;
-    hipError_t e = launch_validate(sc->dev, a, b, n, res, nullptr, out, ws, s, profile_slot(ctx),
-                                   ctx->profiling ? ctx->prof_totals : nullptr, &ctx->last_grid, &ctx->last_block);
-    return e == hipSuccess ? MRPOP_OK : hip_fail(ctx, e, "validate launch");
-  };
-
-  // ---- endpoints -----------------------------------------------------------
-  {
-    HIP_TRY(hipMemcpy(ea, q_start, sizeof(float) * D, hipMemcpyHostToDevice), "copy");
-    HIP_TRY(hipMemcpy(ea + D, q_goal, sizeof(float) * D, hipMemcpyHostToDevice), "copy");
-    mrpop_status v = validate(scene, ea, ea, 2, 1.0f, valid, 1, nullptr);
-    if (v != MRPOP_OK) return v;
-    uint8_t ok[2];
-    HIP_TRY(hipMemcpy(ok, valid, 2, hipMemcpyDeviceToHost), "copy");
-    if (!ok[0]) return fail(ctx, MRPOP_E_START_INVALID, "plan: start state collides");
-    if (!ok[1]) return fail(ctx, MRPOP_E_GOAL_INVALID, "plan: goal state collides");
-  }
-
-  // ---- roadmaps: vertex 0 = the arm's start, vertex 1 = its goal -----------
-  std::vector<SceneHolder> arms(R);
-  for (int r = 0; r < R; ++r) {
-    mrpop_status a = arm_scene(ctx, scene, r, &arms[r].s);
-    if (a != MRPOP_OK) return a;
-  }
-  std::vector<int32_t> rm_n(R, 2);
-  {
-    std::vector<float> init((size_t)R * 2 * kRmStride, 0.f);
-    for (int r = 0; r < R; ++r)
-      for (int j = 0; j < h_nj[r]; ++j) {
-        init[((size_t)r * 2 + 0) * kRmStride + j] = q_start[h_qoff[r] + j];
-        init[((size_t)r * 2 + 1) * kRmStride + j] = q_goal[h_qoff[r] + j];
-      }
-    for (int r = 0; r < R; ++r)
-      HIP_TRY(hipMemcpy(rm_V + (size_t)r * rm_cap * kRmStride, &init[(size_t)r * 2 * kRmStride],
-                        sizeof(float) * 2 * kRmStride, hipMemcpyHostToDevice),
-              "copy");
-    std::vector<int32_t> two(R, 2), zero(R, 0);
-    HIP_TRY(hipMemcpy(rm_nv, two.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice), "copy");
-    HIP_TRY(hipMemcpy(rm_ne, zero.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice), "copy");
-    HIP_TRY(hipMemset(rm_rowptr, 0, sizeof(int32_t) * (size_t)R * (rm_cap + 1)), "memset");
-  }
-
-  auto elapsed = [&]() { return now_s() - t_start; };
-  auto out_of_time = [&]() { return P.time_budget_s > 0 && elapsed() >= P.time_budget_s; };
-
-  // ROADMAP (Alg. 2) for outer iteration `it`
-  auto roadmap = [&](int it) -> mrpop_status {
-    std::vector<char> conn(R, 0);
-    for (int g = 0; g < P.max_growth_rounds; ++g) {
-      bool all = true;
-      for (int r = 0; r < R; ++r) {
-        if (conn[r]) continue;
-        const int nj = h_nj[r];
-        float *V = rm_V + (size_t)r * rm_cap * kRmStride;
-        const int n0 = rm_n[r];
-        int need = std::min(P.n_roadmap, rm_cap - n0);
-        if (need <= 0) st.capacity_hit = 1;
-        for (int64_t j0 = 0; need > 0; j0 += cand_batch) {
-          HIP_TRY(launch_rm_sample(cand, cand_batch, nj, scene->dev.q_lo + h_qoff[r], scene->dev.q_hi + h_qoff[r],
-                                   P.seed, (uint64_t)it * 1024 + g, (uint64_t)r, j0, s),
-                  "rm_sample");
-          mrpop_status v = validate(arms[r].s, cand, cand, cand_batch, 1.0f, cand_valid, 3, nullptr);
-          if (v != MRPOP_OK) return v;
-          HIP_TRY(launch_rm_accept(cand, cand_valid, cand_batch, nj, need, V, rm_nv + r, rm_cap, taken, s),
-                  "rm_accept");
-          HIP_TRY(hipMemcpyAsync(pin.ints, taken, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy");
-          HIP_TRY(hipStreamSynchronize(s), "sync");
-          need -= pin.ints[0];
-          if (j0 > (int64_t)cand_batch * 64) break;  // the arm's free space is (nearly) empty
-        }
-        HIP_TRY(hipMemcpyAsync(pin.ints, rm_nv + r, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy");
-        HIP_TRY(hipStreamSynchronize(s), "sync");
-        rm_n[r] = pin.ints[0];
-        // candidate edges between the new vertices and all earlier ones
-        HIP_TRY(hipMemsetAsync(pair_count, 0, sizeof(int32_t), s), "memset");
-        HIP_TRY(launch_rm_pairs(V, n0, rm_n[r], nj, P.delta, pair_count, pair_cap, pair_ids, pair_qa, pair_qb, s),
-                "rm_pairs");
-        HIP_TRY(hipMemcpyAsync(pin.ints, pair_count, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy");
-        HIP_TRY(hipStreamSynchronize(s), "sync");
-        const int np = std::min(pin.ints[0], pair_cap);
-        if (pin.ints[0] > pair_cap) st.capacity_hit = 1;
-        uint64_t *cnt = nullptr;
-        mrpop_status v = validate(arms[r].s, pair_qa, pair_qb, np, P.resolution, pair_valid, 4, &cnt);
-        if (v != MRPOP_OK) return v;
-        if (np > 0) {
-          HIP_TRY(launch_rm_add_edges(pair_ids, pair_valid, pair_count, np, rm_edges + (size_t)r * edge_cap * 2,
-                                      rm_ne + r, edge_cap, s),
-                  "rm_add_edges");
-          uint64_t c2[2];
-          HIP_TRY(hipMemcpyAsync(c2, cnt, sizeof(c2), hipMemcpyDeviceToHost, s), "copy");
-          HIP_TRY(hipStreamSynchronize(s), "sync");
-          st.roadmap_edge_states += (int64_t)c2[1];
-        }
-        HIP_TRY(launch_rm_csr_bfs(rm_edges + (size_t)r * edge_cap * 2, rm_ne + r, edge_cap, rm_n[r],
-                                  rm_rowptr + (size_t)r * (rm_cap + 1), rm_col + (size_t)r * col_cap, col_cap, deg,
-                                  level, connected, s),
-                "rm_csr_bfs");
-        HIP_TRY(hipMemcpyAsync(pin.ints, connected, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy");
-        HIP_TRY(hipStreamSynchronize(s), "sync");
-        conn[r] = (char)pin.ints[0];
-        all = all && conn[r];
-      }
-      if (all) break;
-      if (out_of_time()) break;
-    }
-    st.roadmap_connected = 1;
-    for (int r = 0; r < R; ++r) st.roadmap_connected = st.roadmap_connected && conn[r];
-    return MRPOP_OK;
-  };
-
-  float c_best = P.warm_cost;
-  std::vector<float> best_path;
-  int rnd = 0, it = 0;
-  bool overflow_no_path = false;
-  std::vector<float> hpath;
-  while (it < P.max_iterations && rnd < P.max_rounds && !out_of_time()) {
-    mrpop_status rs = roadmap(it);
-    if (rs != MRPOP_OK) return rs;
-    // fresh trees: 0 rooted at the start, 1 at the goal
-    HIP_TRY(launch_tree_root(tq[0], tvid[0], tg[0], tpar[0], tn[0], tcap, qs, D, R, 0, s), "tree_root");
-    HIP_TRY(launch_tree_root(tq[1], tvid[1], tg[1], tpar[1], tn[1], tcap, qg, D, R, 1, s), "tree_root");
-    int n_t[2] = {1, 1};
-    int a = 0;  // index of the tree being extended
-    bool solved = false;
-    while (!solved && rnd < P.max_rounds && !out_of_time()) {
-      if (n_t[a] > n_t[1 - a]) a = 1 - a;
-      const int b = 1 - a;
-      SampleArgs sa{PC, D, c_best, P.seed, (uint64_t)rnd, 0, scene->dev.q_lo, scene->dev.q_hi, qs, qg, tq[a], tcap,
-                    q_rand, c_rand};
-      HIP_TRY(launch_sample(sa, s), "sample");
-      NearestArgs na{tq[a], tg[a], n_t[a], D, 1, tcap, q_rand, D, c_best < INFINITY ? c_rand : nullptr, PC, near_idx};
-      HIP_TRY(launch_nearest(na, s), "nearest");
-      ExtendArgs xa{PC, D, R, near_idx, q_rand, c_best < INFINITY ? c_rand : nullptr, tq[a], tvid[a], tg[a], tcap,
-                    rm_V, rm_rowptr, rm_col, rm_cap, col_cap, d_nj, d_qoff, q_new, vid_new, g_new, alive, ea, eb};
-      HIP_TRY(launch_extend(xa, s), "extend");
-      uint64_t *cnt_ext = nullptr, *cnt_conn = nullptr;
-      mrpop_status v = validate(scene, ea, eb, PC, P.resolution, valid, 1, &cnt_ext);
-      if (v != MRPOP_OK) return v;
-      InsertArgs ia{PC, D, R, alive, valid, q_new, g_new, vid_new, near_idx, tq[a], tg[a], tvid[a], tpar[a], tn[a],
-                    tcap, c_best, ins_idx, budget, status};
-      HIP_TRY(launch_insert(ia, s), "insert");
-      NearestArgs nb{tq[b], tg[b], n_t[b], D, 1, tcap, q_new, D, budget, PC, conn_idx};
-      HIP_TRY(launch_nearest(nb, s), "nearest");
-      ConnArgs cna{PC, D, conn_idx, q_new, tq[b], tcap, ca, cb};
-      HIP_TRY(launch_conn_edges(cna, s), "conn_edges");
-      v = validate(scene, ca, cb, PC, P.resolution, cvalid, 2, &cnt_conn);
-      if (v != MRPOP_OK) return v;
-      SelectArgs sl{PC, D, ins_idx, conn_idx, cvalid, q_new, g_new, tq[b], tg[b], tcap, cnt_ext, cnt_conn, status};
-      HIP_TRY(launch_select(sl, s), "select");
-      HIP_TRY(hipMemcpyAsync(pin.h, status, sizeof(RoundStatus), hipMemcpyDeviceToHost, s), "copy");
-      HIP_TRY(hipStreamSynchronize(s), "sync");
-      const RoundStatus rsx = *pin.h;
-      st.edge_states += rsx.states_ext + rsx.states_conn;
-      n_t[a] += rsx.inserted;
-      if (rsx.overflow) st.capacity_hit = 1;
-      ++rnd;
-      if (rsx.found) {
-        PathArgs pa{rsx.a_idx, rsx.b_idx, D, tcap, path_max, tpar[a], tpar[b], tq[a], tq[b], path, path_len_d};
-        HIP_TRY(launch_path(pa, s), "path");
-        HIP_TRY(hipMemcpyAsync(pin.ints, path_len_d, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy");
-        HIP_TRY(hipStreamSynchronize(s), "sync");
-        const int len = pin.ints[0];
-        if (len > path_max || len < 2) {
-          st.capacity_hit = 1;
-        } else {
-          hpath.resize((size_t)len * D);
-          HIP_TRY(hipMemcpy(hpath.data(), path, sizeof(float) * len * D, hipMemcpyDeviceToHost), "copy");
-          if (a == 1) {  // tree 1 is rooted at the goal: orient start -> goal
-            for (int x = 0, y = len - 1; x < y; ++x, --y)
-              std::swap_ranges(hpath.begin() + (size_t)x * D, hpath.begin() + (size_t)(x + 1) * D,
-                               hpath.begin() + (size_t)y * D);
-          }
-          double cost = 0.0;
-          for (int k = 0; k + 1 < len; ++k) {
-            double d2 = 0.0;
-            for (int j = 0; j < D; ++j) {
-              const double t = (double)hpath[(size_t)(k + 1) * D + j] - (double)hpath[(size_t)k * D + j];
-              d2 += t * t;
-            }
-            cost += std::sqrt(d2);
-          }
-          if ((float)cost < c_best) {  // strictly cheaper incumbents only
-            c_best = (float)cost;
-            best_path = hpath;
-            if (st.n_costs < 64) st.costs[st.n_costs++] = c_best;
-            ++st.solutions;
-            if (st.first_round < 0) {
-              st.first_round = rnd - 1;
-              st.time_to_first_s = elapsed();
-            }
-            solved = true;
-          }
-        }
-      }
-      if (rsx.overflow && !solved) {
-        overflow_no_path = best_path.empty();
-        break;
-      }
-    }
-    ++it;
-    if (!solved) break;
-    if (P.stop_at_first && !best_path.empty()) break;
-  }
-  st.rounds = rnd;
-  st.iterations = it;
-  for (int r = 0; r < R; ++r) st.roadmap_vertices += rm_n[r];
-  st.total_time_s = elapsed();
-  if (stats_opt) *stats_opt = st;
-  if (best_path.empty())
-    return overflow_no_path ? fail(ctx, MRPOP_E_CAPACITY, "plan: search tree full before any solution")
-                            : fail(ctx, MRPOP_E_NO_SOLUTION, "plan: budget exhausted without a solution");
-  const int len = (int)(best_path.size() / D);
+  if (stats_opt) *stats_opt = job.stats();
+  if (st != MRPOP_OK) return fail(ctx, st, job.error());
+  const int len = (int)(job.path().size() / job.dof());
   *path_len = len;
-  *cost_out = c_best;
+  *cost_out = job.cost();
   if (len > path_cap) return fail(ctx, MRPOP_E_BUFFER, "plan: path buffer too small");
-  std::memcpy(path_out, best_path.data(), sizeof(float) * best_path.size());
+  std::memcpy(path_out, job.path().data(), sizeof(float) * job.path().size());
   return MRPOP_OK;
 }
 

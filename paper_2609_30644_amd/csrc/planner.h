@@ -105,6 +105,72 @@ struct PathArgs {
   int32_t *out_len;
 };
 
+struct TreeRootArgs {
+  float *tree_q, *tree_g;
+  int32_t *tree_vid, *tree_parent, *tree_n;
+  int tree_cap;
+  const float *q;
+  int dim, n_robots, vid;
+};
+
+struct RmSampleArgs {
+  float *out;
+  int n, nj;
+  const float *lo, *hi;
+  uint64_t key;
+  int64_t j0;
+};
+
+struct RmAcceptArgs {
+  const float *cand;
+  const uint8_t *valid;
+  int n, nj, need;
+  float *V;
+  int32_t *n_v;
+  int cap;
+  int32_t *taken;
+};
+
+struct RmPairsArgs {
+  const float *V;
+  int i0, i1, nj;
+  float delta;
+  int32_t *count;
+  int cap;
+  int32_t *pair_ids;
+  float *qa, *qb;
+};
+
+struct RmAddEdgesArgs {
+  const int32_t *pair_ids;
+  const uint8_t *valid;
+  const int32_t *n_pairs;
+  int max_pairs;
+  int32_t *edges, *n_edges;
+  int cap_edges;
+};
+
+struct RmBfsArgs {
+  const int32_t *edges, *n_edges;
+  int cap_edges, n_v;
+  int32_t *rowptr, *col;
+  int col_cap;
+  int32_t *deg, *level, *connected;
+};
+
+// 32-bit fill and byte copy (device or mapped pinned host memory).
+struct FillArgs {
+  uint32_t *dst;
+  uint32_t value;
+  int64_t n;  // words
+};
+
+struct CopyArgs {
+  void *dst;
+  const void *src;
+  int64_t bytes;
+};
+
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
 hipError_t launch_nearest(const NearestArgs &a, hipStream_t s);
 hipError_t launch_extend(const ExtendArgs &a, hipStream_t s);
@@ -112,18 +178,78 @@ hipError_t launch_insert(const InsertArgs &a, hipStream_t s);
 hipError_t launch_conn_edges(const ConnArgs &a, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_path(const PathArgs &a, hipStream_t s);
-hipError_t launch_tree_root(float *tree_q, int32_t *tree_vid, float *tree_g, int32_t *tree_parent, int32_t *tree_n,
-                            int tree_cap, const float *q, int dim, int n_robots, int vid, hipStream_t s);
-hipError_t launch_rm_sample(float *out, int n, int nj, const float *lo, const float *hi, uint64_t seed,
-                            uint64_t stream_a, uint64_t stream_b, int64_t j0, hipStream_t s);
-hipError_t launch_rm_accept(const float *cand, const uint8_t *valid, int n, int nj, int need, float *V, int32_t *n_v,
-                            int cap, int32_t *taken, hipStream_t s);
-hipError_t launch_rm_pairs(const float *V, int i0, int i1, int nj, float delta, int32_t *count, int cap,
-                           int32_t *pair_ids, float *qa, float *qb, hipStream_t s);
-hipError_t launch_rm_add_edges(const int32_t *pair_ids, const uint8_t *valid, const int32_t *n_pairs, int max_pairs,
-                               int32_t *edges, int32_t *n_edges, int cap_edges, hipStream_t s);
-hipError_t launch_rm_csr_bfs(const int32_t *edges, const int32_t *n_edges, int cap_edges, int n_v, int32_t *rowptr,
-                             int32_t *col, int col_cap, int32_t *deg, int32_t *level, int32_t *connected,
-                             hipStream_t s);
+hipError_t launch_tree_root(const TreeRootArgs &a, hipStream_t s);
+hipError_t launch_rm_sample(const RmSampleArgs &a, hipStream_t s);
+hipError_t launch_rm_accept(const RmAcceptArgs &a, hipStream_t s);
+hipError_t launch_rm_pairs(const RmPairsArgs &a, hipStream_t s);
+hipError_t launch_rm_add_edges(const RmAddEdgesArgs &a, hipStream_t s);
+hipError_t launch_rm_csr_bfs(const RmBfsArgs &a, hipStream_t s);
+hipError_t launch_fill(const FillArgs &a, hipStream_t s);
+hipError_t launch_copy(const CopyArgs &a, hipStream_t s);
+
+// Key of an arm's roadmap sample stream.
+uint64_t roadmap_key(uint64_t seed, uint64_t stream_a, uint64_t stream_b);
+
+// The same kernels over many independent argument records at once (record
+// blockIdx.y of the device array `args`; grid_x = the most blocks any record
+// needs, records that need fewer leave early).
+enum class Op : uint8_t {
+  Sample, Nearest, Extend, Insert, Conn, Select, Path, TreeRoot,
+  RmSample, RmAccept, RmPairs, RmAddEdges, RmBfs, Fill, Copy, Validate
+};
+constexpr int kNumOps = 16;
+
+// Blocks one record needs (0: nothing to do).
+int op_blocks(Op op, const void *args);
+size_t op_args_bytes(Op op);
+hipError_t launch_op(Op op, const void *args, hipStream_t s);
+hipError_t launch_op_batch(Op op, const void *d_args, int count, int grid_x, hipStream_t s);
+
+// A validation request of the planner: edges (qa[i], qb[i]) of one scene;
+// bits to out[i]; the call's counters (the validation counter layout, [1] =
+// edge states) to the caller's device array counters[16].
+struct ValidateReq {
+  const SceneDev *scene;  // host copy of the scene's device descriptor
+  const float *qa, *qb;
+  int64_t n;
+  float res;
+  uint8_t *out;
+  uint64_t *counters;
+};
+
+// One unit of device work of a planning instance.
+struct Cmd {
+  Op op;
+  union {
+    SampleArgs sample;
+    NearestArgs nearest;
+    ExtendArgs extend;
+    InsertArgs insert;
+    ConnArgs conn;
+    SelectArgs select;
+    PathArgs path;
+    TreeRootArgs tree_root;
+    RmSampleArgs rm_sample;
+    RmAcceptArgs rm_accept;
+    RmPairsArgs rm_pairs;
+    RmAddEdgesArgs rm_add_edges;
+    RmBfsArgs rm_bfs;
+    FillArgs fill;
+    CopyArgs copy;
+    ValidateReq val;
+  };
+  const void *args() const { return &sample; }
+};
+
+// Where a planning instance's device work goes: launched at once on a
+// stream (a plain plan), or queued and merged with other instances' work (a
+// batch).  Work is executed in submission order; sync() returns once all of
+// it has completed (host buffers written by copies are then valid).
+class Exec {
+ public:
+  virtual ~Exec() = default;
+  virtual hipError_t submit(const Cmd &c) = 0;
+  virtual hipError_t sync() = 0;
+};
 
 }  // namespace mrpop

@@ -70,9 +70,9 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-__global__ __launch_bounds__(kSampleWaves * kWave) void sample_kernel(SampleArgs a) {
+__device__ __forceinline__ void sample_body(const SampleArgs &a, int bx) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int i = blockIdx.x * kSampleWaves + (int)(threadIdx.x / kWave);
+  const int i = bx * kSampleWaves + (int)(threadIdx.x / kWave);
   if (i >= a.n) return;  // whole waves leave together
   const int D = a.dim;
   float *q = a.out_q + (int64_t)i * D;
@@ -138,14 +138,6 @@ __global__ __launch_bounds__(kSampleWaves * kWave) void sample_kernel(SampleArgs
   }
 }
 
-hipError_t launch_sample(const SampleArgs &a, hipStream_t s) {
-  if (a.n <= 0) return hipSuccess;
-  if (a.dim > kMaxDof) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)((a.n + kSampleWaves - 1) / kSampleWaves)),
-                     dim3(kSampleWaves * kWave), 0, s, a);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // a3: cost-bounded nearest neighbour (NEAREST of Alg. 2)
 // ---------------------------------------------------------------------------
@@ -166,10 +158,12 @@ __device__ __forceinline__ bool better(const Best &a, const Best &b) {
 // One workgroup per query: threads stride over vertices; admissible when
 // g_v + |q - q_v| < c; the least distance wins, ties to the lower cost, then
 // the lower index.
-__global__ __launch_bounds__(256) void nearest_kernel(NearestArgs a) {
+__device__ __forceinline__ void nearest_body(const NearestArgs &a, int bx) {
+  if (bx >= a.n_queries) return;
+
   __shared__ float sq[kMaxDof];
   __shared__ Best sb[256 / kWave];
-  const int64_t qi = blockIdx.x;
+  const int64_t qi = bx;
   const int D = a.dim;
   for (int j = threadIdx.x; j < D; j += blockDim.x) sq[j] = a.queries[qi * a.q_stride + j];
   __syncthreads();
@@ -203,13 +197,6 @@ __global__ __launch_bounds__(256) void nearest_kernel(NearestArgs a) {
   }
 }
 
-hipError_t launch_nearest(const NearestArgs &a, hipStream_t s) {
-  if (a.n_queries <= 0) return hipSuccess;
-  if (a.dim > kMaxDof || a.n_queries > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(nearest_kernel, dim3((unsigned)a.n_queries), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // a4: dRRT extension oracle (ORACLE_AOX)
 // ---------------------------------------------------------------------------
@@ -224,9 +211,9 @@ hipError_t launch_nearest(const NearestArgs &a, hipStream_t s) {
 // (q_near -> q_new); dropped candidates get a null edge at q_near.
 constexpr int kExtendWaves = 4;
 
-__global__ __launch_bounds__(kExtendWaves * kWave) void extend_kernel(ExtendArgs a) {
+__device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int i = blockIdx.x * kExtendWaves + (int)(threadIdx.x / kWave);
+  const int i = bx * kExtendWaves + (int)(threadIdx.x / kWave);
   if (i >= a.n) return;  // whole waves leave together
   const int D = a.dim, R = a.n_robots;
   const int near = a.near_idx[i];
@@ -312,13 +299,6 @@ __global__ __launch_bounds__(kExtendWaves * kWave) void extend_kernel(ExtendArgs
   }
 }
 
-hipError_t launch_extend(const ExtendArgs &a, hipStream_t s) {
-  if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(extend_kernel, dim3((unsigned)((a.n + kExtendWaves - 1) / kExtendWaves)),
-                     dim3(kExtendWaves * kWave), 0, s, a);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // a10: insertion in candidate order; a11: connection edges; a12: selection
 // ---------------------------------------------------------------------------
@@ -328,7 +308,9 @@ hipError_t launch_extend(const ExtendArgs &a, hipStream_t s) {
 // capacity; writes each candidate's tree index (-1 if not inserted) and the
 // connection budget c_best - g_new (-1 if not inserted, so no vertex is
 // admissible).
-__global__ __launch_bounds__(1024) void insert_kernel(InsertArgs a) {
+__device__ __forceinline__ void insert_body(const InsertArgs &a, int bx) {
+  if (bx != 0) return;
+
   __shared__ int32_t wsum[1024 / kWave];
   __shared__ int32_t base;
   if (threadIdx.x == 0) base = 0;
@@ -373,15 +355,10 @@ __global__ __launch_bounds__(1024) void insert_kernel(InsertArgs a) {
   }
 }
 
-hipError_t launch_insert(const InsertArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(insert_kernel, dim3(1), dim3(1024), 0, s, a);
-  return hipGetLastError();
-}
-
 // Connection edges (q_new -> q_conn); candidates without a connection get a
 // null edge.
-__global__ __launch_bounds__(256) void conn_edges_kernel(ConnArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void conn_body(const ConnArgs &a, int bx) {
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int c = a.conn_idx[i];
   float *ea = a.edge_a + (int64_t)i * a.dim, *eb = a.edge_b + (int64_t)i * a.dim;
@@ -392,16 +369,12 @@ __global__ __launch_bounds__(256) void conn_edges_kernel(ConnArgs a) {
   }
 }
 
-hipError_t launch_conn_edges(const ConnArgs &a, hipStream_t s) {
-  if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(conn_edges_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
 // Single workgroup: among inserted candidates whose connection edge is free,
 // the least total cost g_new + |q_new - q_conn| + g_conn (ties: lowest
 // candidate index).
-__global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
+__device__ __forceinline__ void select_body(const SelectArgs &a, int bx) {
+  if (bx != 0) return;
+
   __shared__ float sc[256];
   __shared__ int si[256];
   float best = INFINITY;
@@ -439,14 +412,9 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
   }
 }
 
-hipError_t launch_select(const SelectArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
 // Path: root of tree A -> a_idx, then b_idx -> root of tree B (one thread).
-__global__ void path_kernel(PathArgs a) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void path_body(const PathArgs &a, int bx) {
+  if (threadIdx.x != 0 || bx != 0) return;
   int len_a = 0;
   for (int v = a.a_idx; v >= 0 && len_a <= a.cap; v = a.parent_a[v]) ++len_a;
   int len_b = 0;
@@ -462,14 +430,14 @@ __global__ void path_kernel(PathArgs a) {
     for (int j = 0; j < a.dim; ++j) a.out[(int64_t)k * a.dim + j] = a.q_b[(int64_t)j * a.tree_cap + v];
 }
 
-hipError_t launch_path(const PathArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(path_kernel, dim3(1), dim3(64), 0, s, a);
-  return hipGetLastError();
-}
-
 // Seed a tree with its root (q, vertex ids of every arm's start or goal).
-__global__ void tree_root_kernel(float *tree_q, int32_t *tree_vid, float *tree_g, int32_t *tree_parent, int32_t *tree_n,
-                                 int tree_cap, const float *q, int dim, int n_robots, int vid) {
+__device__ __forceinline__ void tree_root_body(const TreeRootArgs &A, int bx) {
+  float *tree_q = A.tree_q, *tree_g = A.tree_g;
+  int32_t *tree_vid = A.tree_vid, *tree_parent = A.tree_parent, *tree_n = A.tree_n;
+  const int tree_cap = A.tree_cap, dim = A.dim, n_robots = A.n_robots, vid = A.vid;
+  const float *q = A.q;
+  if (bx != 0) return;
+
   for (int j = threadIdx.x; j < dim; j += blockDim.x) tree_q[(int64_t)j * tree_cap] = q[j];
   for (int r = threadIdx.x; r < n_robots; r += blockDim.x) tree_vid[(int64_t)r * tree_cap] = vid;
   if (threadIdx.x == 0) {
@@ -479,39 +447,35 @@ __global__ void tree_root_kernel(float *tree_q, int32_t *tree_vid, float *tree_g
   }
 }
 
-hipError_t launch_tree_root(float *tree_q, int32_t *tree_vid, float *tree_g, int32_t *tree_parent, int32_t *tree_n,
-                            int tree_cap, const float *q, int dim, int n_robots, int vid, hipStream_t s) {
-  hipLaunchKernelGGL(tree_root_kernel, dim3(1), dim3(128), 0, s, tree_q, tree_vid, tree_g, tree_parent, tree_n,
-                     tree_cap, q, dim, n_robots, vid);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // a13: roadmap growth (per arm)
 // ---------------------------------------------------------------------------
 
 // Candidate samples j0 .. j0 + n - 1 of an arm's roadmap stream: uniform in
 // the arm's joint limits (uniforms 8 j + d of the stream).
-__global__ __launch_bounds__(256) void rm_sample_kernel(float *out, int n, int nj, const float *lo, const float *hi,
-                                                        uint64_t key, int64_t j0) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rm_sample_body(const RmSampleArgs &A, int bx) {
+  float *out = A.out;
+  const int n = A.n, nj = A.nj;
+  const float *lo = A.lo, *hi = A.hi;
+  const uint64_t key = A.key;
+  const int64_t j0 = A.j0;
+
+  const int b = bx * blockDim.x + threadIdx.x;
   if (b >= n) return;
   for (int d = 0; d < nj; ++d)
     out[(int64_t)b * nj + d] = fmaf(uniform01(key, (uint64_t)(j0 + b) * 8 + d), hi[d] - lo[d], lo[d]);
 }
 
-hipError_t launch_rm_sample(float *out, int n, int nj, const float *lo, const float *hi, uint64_t seed,
-                            uint64_t stream_a, uint64_t stream_b, int64_t j0, hipStream_t s) {
-  const uint64_t key = stream_key(seed, kPurposeRoadmap, stream_a, stream_b);
-  hipLaunchKernelGGL(rm_sample_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, nj, lo, hi, key,
-                     j0);
-  return hipGetLastError();
-}
-
 // Single workgroup: append the first `need` free candidates (in draw order)
 // to the roadmap; writes how many were taken.
-__global__ __launch_bounds__(1024) void rm_accept_kernel(const float *cand, const uint8_t *valid, int n, int nj,
-                                                         int need, float *V, int32_t *n_v, int cap, int32_t *taken) {
+__device__ __forceinline__ void rm_accept_body(const RmAcceptArgs &A, int bx) {
+  const float *cand = A.cand;
+  const uint8_t *valid = A.valid;
+  const int n = A.n, nj = A.nj, need = A.need, cap = A.cap;
+  float *V = A.V;
+  int32_t *n_v = A.n_v, *taken = A.taken;
+  if (bx != 0) return;
+
   __shared__ int32_t wsum[1024 / kWave];
   __shared__ int32_t base;
   if (threadIdx.x == 0) base = 0;
@@ -544,19 +508,18 @@ __global__ __launch_bounds__(1024) void rm_accept_kernel(const float *cand, cons
   }
 }
 
-hipError_t launch_rm_accept(const float *cand, const uint8_t *valid, int n, int nj, int need, float *V, int32_t *n_v,
-                            int cap, int32_t *taken, hipStream_t s) {
-  hipLaunchKernelGGL(rm_accept_kernel, dim3(1), dim3(1024), 0, s, cand, valid, n, nj, need, V, n_v, cap, taken);
-  return hipGetLastError();
-}
-
 // Pairs (j, i), i in [i0, i1), j < i, with |V_i - V_j| <= delta: written as
 // edge endpoints (qa = V_j, qb = V_i) and ids, compacted with an atomic
-// counter (order is irrelevant: adjacency rows are sorted afterwards).
-__global__ __launch_bounds__(256) void rm_pairs_kernel(const float *V, int i0, int i1, int nj, float delta,
-                                                       int32_t *count, int cap, int32_t *pair_ids, float *qa,
-                                                       float *qb) {
-  const int i = i0 + blockIdx.x;
+// counter (their order does not reach any result: adjacency is rebuilt as a
+// set and the extension oracle breaks ties by vertex id).
+__device__ __forceinline__ void rm_pairs_body(const RmPairsArgs &A, int bx) {
+  const float *V = A.V;
+  const int i0 = A.i0, i1 = A.i1, nj = A.nj, cap = A.cap;
+  const float delta = A.delta;
+  int32_t *count = A.count, *pair_ids = A.pair_ids;
+  float *qa = A.qa, *qb = A.qb;
+
+  const int i = i0 + bx;
   if (i >= i1) return;
   for (int j = threadIdx.x; j < i; j += blockDim.x) {
     float d2 = 0.f;
@@ -576,19 +539,14 @@ __global__ __launch_bounds__(256) void rm_pairs_kernel(const float *V, int i0, i
   }
 }
 
-hipError_t launch_rm_pairs(const float *V, int i0, int i1, int nj, float delta, int32_t *count, int cap,
-                           int32_t *pair_ids, float *qa, float *qb, hipStream_t s) {
-  if (i1 <= i0) return hipSuccess;
-  hipLaunchKernelGGL(rm_pairs_kernel, dim3((unsigned)(i1 - i0)), dim3(256), 0, s, V, i0, i1, nj, delta, count, cap,
-                     pair_ids, qa, qb);
-  return hipGetLastError();
-}
-
 // Append the valid pairs to the arm's edge list.
-__global__ __launch_bounds__(256) void rm_add_edges_kernel(const int32_t *pair_ids, const uint8_t *valid,
-                                                           const int32_t *n_pairs, int cap_pairs, int32_t *edges,
-                                                           int32_t *n_edges, int cap_edges) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rm_add_edges_body(const RmAddEdgesArgs &A, int bx) {
+  const int32_t *pair_ids = A.pair_ids, *n_pairs = A.n_pairs;
+  const uint8_t *valid = A.valid;
+  const int cap_pairs = A.max_pairs, cap_edges = A.cap_edges;
+  int32_t *edges = A.edges, *n_edges = A.n_edges;
+
+  const int k = bx * blockDim.x + threadIdx.x;
   const int np = *n_pairs < cap_pairs ? *n_pairs : cap_pairs;
   if (k >= np || !valid[k]) return;
   const int e = atomicAdd(n_edges, 1);
@@ -597,22 +555,16 @@ __global__ __launch_bounds__(256) void rm_add_edges_kernel(const int32_t *pair_i
   edges[2 * e + 1] = pair_ids[2 * k + 1];
 }
 
-hipError_t launch_rm_add_edges(const int32_t *pair_ids, const uint8_t *valid, const int32_t *n_pairs, int max_pairs,
-                               int32_t *edges, int32_t *n_edges, int cap_edges, hipStream_t s) {
-  if (max_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(rm_add_edges_kernel, dim3((unsigned)((max_pairs + 255) / 256)), dim3(256), 0, s, pair_ids, valid,
-                     n_pairs, max_pairs, edges, n_edges, cap_edges);
-  return hipGetLastError();
-}
-
 // Single workgroup: rebuild the arm's adjacency (CSR) from its edge list,
 // then breadth-first search from vertex 0; writes whether vertex 1 is
 // reached.  The order inside an adjacency row is whatever the atomics give:
 // the extension oracle's choice does not depend on it.
-__global__ __launch_bounds__(1024) void rm_csr_bfs_kernel(const int32_t *edges, const int32_t *n_edges_p,
-                                                          int cap_edges, int n_v, int32_t *rowptr, int32_t *col,
-                                                          int col_cap, int32_t *deg, int32_t *level,
-                                                          int32_t *connected) {
+__device__ __forceinline__ void rm_csr_bfs_body(const RmBfsArgs &A, int bx) {
+  const int32_t *edges = A.edges, *n_edges_p = A.n_edges;
+  const int cap_edges = A.cap_edges, n_v = A.n_v, col_cap = A.col_cap;
+  int32_t *rowptr = A.rowptr, *col = A.col, *deg = A.deg, *level = A.level, *connected = A.connected;
+  if (bx != 0) return;
+
   __shared__ int32_t wsum[1024 / kWave];
   __shared__ int32_t carry;
   __shared__ int changed, stop;
@@ -678,12 +630,177 @@ __global__ __launch_bounds__(1024) void rm_csr_bfs_kernel(const int32_t *edges, 
   if (threadIdx.x == 0) *connected = (n_v > 1 && level[1] >= 0) ? 1 : 0;
 }
 
-hipError_t launch_rm_csr_bfs(const int32_t *edges, const int32_t *n_edges, int cap_edges, int n_v, int32_t *rowptr,
-                             int32_t *col, int col_cap, int32_t *deg, int32_t *level, int32_t *connected,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(rm_csr_bfs_kernel, dim3(1), dim3(1024), 0, s, edges, n_edges, cap_edges, n_v, rowptr, col,
-                     col_cap, deg, level, connected);
+// ---------------------------------------------------------------------------
+// fill and copy (device or mapped pinned host memory)
+// ---------------------------------------------------------------------------
+
+constexpr int kCopyBlocksMax = 1024;
+
+__device__ __forceinline__ void fill_body(const FillArgs &a, int bx) {
+  for (int64_t i = (int64_t)bx * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) a.dst[i] = a.value;
+}
+
+__device__ __forceinline__ void copy_body(const CopyArgs &a, int bx) {
+  unsigned char *d = (unsigned char *)a.dst;
+  const unsigned char *src = (const unsigned char *)a.src;
+  for (int64_t i = (int64_t)bx * 256 + threadIdx.x; i < a.bytes; i += (int64_t)gridDim.x * 256) d[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// entry points: one record, or many records (blockIdx.y) per launch
+// ---------------------------------------------------------------------------
+
+#define MRPOP_OP_KERNELS(name, Args, threads)                                              \
+  __global__ __launch_bounds__(threads) void name##_kernel(Args a) { name##_body(a, blockIdx.x); } \
+  __global__ __launch_bounds__(threads) void name##_batch_kernel(const Args *records) {     \
+    const Args a = records[blockIdx.y];                                                    \
+    name##_body(a, blockIdx.x);                                                            \
+  }
+
+MRPOP_OP_KERNELS(sample, SampleArgs, kSampleWaves * kWave)
+MRPOP_OP_KERNELS(nearest, NearestArgs, 256)
+MRPOP_OP_KERNELS(extend, ExtendArgs, kExtendWaves * kWave)
+MRPOP_OP_KERNELS(insert, InsertArgs, 1024)
+MRPOP_OP_KERNELS(conn, ConnArgs, 256)
+MRPOP_OP_KERNELS(select, SelectArgs, 256)
+MRPOP_OP_KERNELS(path, PathArgs, 64)
+MRPOP_OP_KERNELS(tree_root, TreeRootArgs, 128)
+MRPOP_OP_KERNELS(rm_sample, RmSampleArgs, 256)
+MRPOP_OP_KERNELS(rm_accept, RmAcceptArgs, 1024)
+MRPOP_OP_KERNELS(rm_pairs, RmPairsArgs, 256)
+MRPOP_OP_KERNELS(rm_add_edges, RmAddEdgesArgs, 256)
+MRPOP_OP_KERNELS(rm_csr_bfs, RmBfsArgs, 1024)
+MRPOP_OP_KERNELS(fill, FillArgs, 256)
+MRPOP_OP_KERNELS(copy, CopyArgs, 256)
+
+static int clamp_blocks(int64_t b) { return (int)std::min<int64_t>(std::max<int64_t>(b, 0), 0x7fffffff); }
+
+int op_blocks(Op op, const void *p) {
+  switch (op) {
+    case Op::Sample: {
+      const SampleArgs &a = *(const SampleArgs *)p;
+      return clamp_blocks((a.n + kSampleWaves - 1) / kSampleWaves);
+    }
+    case Op::Nearest: return clamp_blocks(((const NearestArgs *)p)->n_queries);
+    case Op::Extend: {
+      const ExtendArgs &a = *(const ExtendArgs *)p;
+      return clamp_blocks((a.n + kExtendWaves - 1) / kExtendWaves);
+    }
+    case Op::Insert: return 1;
+    case Op::Conn: return clamp_blocks((((const ConnArgs *)p)->n + 255) / 256);
+    case Op::Select: return 1;
+    case Op::Path: return 1;
+    case Op::TreeRoot: return 1;
+    case Op::RmSample: return clamp_blocks((((const RmSampleArgs *)p)->n + 255) / 256);
+    case Op::RmAccept: return 1;
+    case Op::RmPairs: {
+      const RmPairsArgs &a = *(const RmPairsArgs *)p;
+      return clamp_blocks(a.i1 - a.i0);
+    }
+    case Op::RmAddEdges: return clamp_blocks((((const RmAddEdgesArgs *)p)->max_pairs + 255) / 256);
+    case Op::RmBfs: return 1;
+    case Op::Fill: return (int)std::min<int64_t>((((const FillArgs *)p)->n + 255) / 256, kCopyBlocksMax);
+    case Op::Copy: return (int)std::min<int64_t>((((const CopyArgs *)p)->bytes + 255) / 256, kCopyBlocksMax);
+    case Op::Validate: return 0;
+  }
+  return 0;
+}
+
+size_t op_args_bytes(Op op) {
+  switch (op) {
+    case Op::Sample: return sizeof(SampleArgs);
+    case Op::Nearest: return sizeof(NearestArgs);
+    case Op::Extend: return sizeof(ExtendArgs);
+    case Op::Insert: return sizeof(InsertArgs);
+    case Op::Conn: return sizeof(ConnArgs);
+    case Op::Select: return sizeof(SelectArgs);
+    case Op::Path: return sizeof(PathArgs);
+    case Op::TreeRoot: return sizeof(TreeRootArgs);
+    case Op::RmSample: return sizeof(RmSampleArgs);
+    case Op::RmAccept: return sizeof(RmAcceptArgs);
+    case Op::RmPairs: return sizeof(RmPairsArgs);
+    case Op::RmAddEdges: return sizeof(RmAddEdgesArgs);
+    case Op::RmBfs: return sizeof(RmBfsArgs);
+    case Op::Fill: return sizeof(FillArgs);
+    case Op::Copy: return sizeof(CopyArgs);
+    case Op::Validate: return 0;
+  }
+  return 0;
+}
+
+// Argument checks shared by both entry points.
+static hipError_t op_check(Op op, const void *p) {
+  if (op == Op::Sample && ((const SampleArgs *)p)->dim > kMaxDof) return hipErrorInvalidValue;
+  if (op == Op::Nearest && ((const NearestArgs *)p)->dim > kMaxDof) return hipErrorInvalidValue;
+  return hipSuccess;
+}
+
+#define MRPOP_OP_CASE(OP, name, Args, threads)                                                     \
+  case Op::OP:                                                                                     \
+    if (batch)                                                                                     \
+      hipLaunchKernelGGL(name##_batch_kernel, dim3((unsigned)grid_x, (unsigned)count), dim3(threads), 0, s, \
+                         (const Args *)p);                                                         \
+    else                                                                                           \
+      hipLaunchKernelGGL(name##_kernel, dim3((unsigned)grid_x), dim3(threads), 0, s, *(const Args *)p); \
+    break;
+
+static hipError_t launch_any(Op op, const void *p, bool batch, int count, int grid_x, hipStream_t s) {
+  switch (op) {
+    MRPOP_OP_CASE(Sample, sample, SampleArgs, kSampleWaves * kWave)
+    MRPOP_OP_CASE(Nearest, nearest, NearestArgs, 256)
+    MRPOP_OP_CASE(Extend, extend, ExtendArgs, kExtendWaves * kWave)
+    MRPOP_OP_CASE(Insert, insert, InsertArgs, 1024)
+    MRPOP_OP_CASE(Conn, conn, ConnArgs, 256)
+    MRPOP_OP_CASE(Select, select, SelectArgs, 256)
+    MRPOP_OP_CASE(Path, path, PathArgs, 64)
+    MRPOP_OP_CASE(TreeRoot, tree_root, TreeRootArgs, 128)
+    MRPOP_OP_CASE(RmSample, rm_sample, RmSampleArgs, 256)
+    MRPOP_OP_CASE(RmAccept, rm_accept, RmAcceptArgs, 1024)
+    MRPOP_OP_CASE(RmPairs, rm_pairs, RmPairsArgs, 256)
+    MRPOP_OP_CASE(RmAddEdges, rm_add_edges, RmAddEdgesArgs, 256)
+    MRPOP_OP_CASE(RmBfs, rm_csr_bfs, RmBfsArgs, 1024)
+    MRPOP_OP_CASE(Fill, fill, FillArgs, 256)
+    MRPOP_OP_CASE(Copy, copy, CopyArgs, 256)
+    case Op::Validate: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_op(Op op, const void *args, hipStream_t s) {
+  const hipError_t c = op_check(op, args);
+  if (c != hipSuccess) return c;
+  const int g = op_blocks(op, args);
+  if (g <= 0) return hipSuccess;
+  return launch_any(op, args, false, 1, g, s);
+}
+
+hipError_t launch_op_batch(Op op, const void *d_args, int count, int grid_x, hipStream_t s) {
+  if (count <= 0 || grid_x <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  return launch_any(op, d_args, true, count, grid_x, s);
+}
+
+hipError_t launch_sample(const SampleArgs &a, hipStream_t s) { return launch_op(Op::Sample, &a, s); }
+hipError_t launch_nearest(const NearestArgs &a, hipStream_t s) {
+  if (a.n_queries > 0x7fffffff) return hipErrorInvalidValue;
+  return launch_op(Op::Nearest, &a, s);
+}
+hipError_t launch_extend(const ExtendArgs &a, hipStream_t s) { return launch_op(Op::Extend, &a, s); }
+hipError_t launch_insert(const InsertArgs &a, hipStream_t s) { return launch_op(Op::Insert, &a, s); }
+hipError_t launch_conn_edges(const ConnArgs &a, hipStream_t s) { return launch_op(Op::Conn, &a, s); }
+hipError_t launch_select(const SelectArgs &a, hipStream_t s) { return launch_op(Op::Select, &a, s); }
+hipError_t launch_path(const PathArgs &a, hipStream_t s) { return launch_op(Op::Path, &a, s); }
+hipError_t launch_tree_root(const TreeRootArgs &a, hipStream_t s) { return launch_op(Op::TreeRoot, &a, s); }
+hipError_t launch_rm_sample(const RmSampleArgs &a, hipStream_t s) { return launch_op(Op::RmSample, &a, s); }
+hipError_t launch_rm_accept(const RmAcceptArgs &a, hipStream_t s) { return launch_op(Op::RmAccept, &a, s); }
+hipError_t launch_rm_pairs(const RmPairsArgs &a, hipStream_t s) { return launch_op(Op::RmPairs, &a, s); }
+hipError_t launch_rm_add_edges(const RmAddEdgesArgs &a, hipStream_t s) { return launch_op(Op::RmAddEdges, &a, s); }
+hipError_t launch_rm_csr_bfs(const RmBfsArgs &a, hipStream_t s) { return launch_op(Op::RmBfs, &a, s); }
+hipError_t launch_fill(const FillArgs &a, hipStream_t s) { return launch_op(Op::Fill, &a, s); }
+hipError_t launch_copy(const CopyArgs &a, hipStream_t s) { return launch_op(Op::Copy, &a, s); }
+
+uint64_t roadmap_key(uint64_t seed, uint64_t stream_a, uint64_t stream_b) {
+  return stream_key(seed, kPurposeRoadmap, stream_a, stream_b);
 }
 
 }  // namespace mrpop

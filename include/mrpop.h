@@ -270,6 +270,43 @@ mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q
                         float *cost_out, mrpop_plan_stats *stats_opt);
 
 /* ------------------------------------------------------------------------ */
+/* Batched planning: many independent instances at once                     */
+/* ------------------------------------------------------------------------ */
+
+/* One planning instance of a batch.  Inputs as for mrpop_plan (host start,
+ * goal and path buffer; the scene must come from the same context); the
+ * outputs (status, path_len, cost, stats) are written by mrpop_plan_batch. */
+typedef struct {
+  const mrpop_scene *scene;
+  const float *q_start, *q_goal;   /* host [D] */
+  mrpop_plan_params params;
+  float *path_out;                 /* host [path_cap][D] */
+  int32_t path_cap;
+  mrpop_status status;             /* out: as mrpop_plan would return */
+  int32_t path_len;                /* out */
+  float cost;                      /* out */
+  mrpop_plan_stats stats;          /* out */
+} mrpop_plan_request;
+
+typedef struct {
+  double wall_s;                   /* whole call */
+  int32_t instances, solved;
+  int64_t flushes;                 /* merged submissions of device work */
+  int64_t launches;                /* kernel launches they made */
+} mrpop_batch_stats;
+
+/* Plans every request concurrently (the batching of the paper's many parallel
+ * planning iterations, extended across independent problems): each instance
+ * runs exactly the computation of mrpop_plan with the same parameters, so
+ * with round/iteration budgets its path and cost equal the plain call's;
+ * the device work of all instances is merged into shared launches, with the
+ * edge validations of many scenes in one launch.  Wall-clock budgets
+ * (time_budget_s) count from the start of the batch.  Returns E_INVALID_ARG
+ * for a NULL context or request array; per-request failures are reported in
+ * reqs[i].status.  Blocking; uses one host thread per request. */
+mrpop_status mrpop_plan_batch(mrpop_ctx *ctx, mrpop_plan_request *reqs, int32_t n, mrpop_batch_stats *stats_opt);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel profiling                                                          */
 /* ------------------------------------------------------------------------ */
 

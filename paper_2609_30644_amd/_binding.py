@@ -69,6 +69,17 @@ class _PlanStats(C.Structure):
                 ("costs", C.c_float * 64)]
 
 
+class _PlanRequest(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("q_start", C.c_void_p), ("q_goal", C.c_void_p), ("params", PlanParams),
+                ("path_out", C.c_void_p), ("path_cap", C.c_int32), ("status", C.c_int32), ("path_len", C.c_int32),
+                ("cost", C.c_float), ("stats", _PlanStats)]
+
+
+class _BatchStats(C.Structure):
+    _fields_ = [("wall_s", C.c_double), ("instances", C.c_int32), ("solved", C.c_int32), ("flushes", C.c_int64),
+                ("launches", C.c_int64)]
+
+
 @dataclass
 class PlanResult:
     status: str
@@ -140,6 +151,7 @@ def load_library():
     lib.mrpop_plan_params_default.argtypes = [P]
     lib.mrpop_plan_params_default.restype = None
     lib.mrpop_plan.argtypes = [P, P, P, P, P, P, I32, P, P, P]
+    lib.mrpop_plan_batch.argtypes = [P, P, I32, P]
     lib.mrpop_profile_enable.argtypes = [P, C.c_int]
     lib.mrpop_profile_read.argtypes = [P, P]
     _lib = lib
@@ -182,18 +194,6 @@ class Context:
     def handle(self):
         return self._h
 
-    TILE_MODES = {"auto": 0, "lds": 1, "scalar": 2}
-
-    def set_tile_mode(self, mode: str):
-        """Where the validation kernel reads the coarse rows: "auto", "lds"
-        or "scalar" (performance only)."""
-        self.ctx.check(self.ctx._lib.mrpop_scene_set_tile_mode(self._h, self.TILE_MODES[mode]))
-
-    @property
-    def tile_mode(self) -> str:
-        v = int(self.ctx._lib.mrpop_scene_tile_mode(self._h))
-        return {b: a for a, b in self.TILE_MODES.items()}[v]
-
     def close(self):
         if getattr(self, "_h", None):
             self._lib.mrpop_ctx_destroy(self._h)
@@ -218,6 +218,44 @@ class Context:
 
     def stream(self) -> int:
         return _stream_ptr(self.device)
+
+    def plan_batch(self, problems, path_cap: int = 4096, **common):
+        """mrpop_plan_batch over problems = [(scene, q_start, q_goal, params
+        dict), ...]; `common` holds parameters shared by all.  Returns
+        ([PlanResult], batch stats dict)."""
+        lib = self._lib
+        n = len(problems)
+        reqs = (_PlanRequest * max(1, n))()
+        keep = []
+        for i, (scene, qs, qg, prm) in enumerate(problems):
+            pp = PlanParams()
+            lib.mrpop_plan_params_default(C.byref(pp))
+            for k, v in {**common, **(prm or {})}.items():
+                if not hasattr(pp, k):
+                    raise KeyError(k)
+                setattr(pp, k, v)
+            qs = np.ascontiguousarray(qs, np.float32).reshape(scene.dof)
+            qg = np.ascontiguousarray(qg, np.float32).reshape(scene.dof)
+            path = np.zeros((max(1, path_cap), scene.dof), np.float32)
+            keep.append((qs, qg, path))
+            reqs[i].scene = scene.handle
+            reqs[i].q_start = qs.ctypes.data
+            reqs[i].q_goal = qg.ctypes.data
+            reqs[i].params = pp
+            reqs[i].path_out = path.ctypes.data
+            reqs[i].path_cap = path_cap
+        bs = _BatchStats()
+        self.check(lib.mrpop_plan_batch(self.handle, reqs, n, C.byref(bs)))
+        out = []
+        for i in range(n):
+            r = reqs[i]
+            stats = {k: getattr(r.stats, k) for k, _ in _PlanStats._fields_ if k != "costs"}
+            stats["costs"] = list(r.stats.costs[:r.stats.n_costs])
+            stats["path_len"] = r.path_len
+            path = keep[i][2]
+            out.append(PlanResult(STATUS_NAMES.get(r.status, str(r.status)),
+                                  path[:r.path_len].copy() if r.status == 0 else None, float(r.cost), stats))
+        return out, {k: getattr(bs, k) for k, _ in _BatchStats._fields_}
 
     def nearest(self, vertices, costs, queries, budgets=None, out=None):
         """Cost-bounded nearest vertex per query (int32, -1 when none)."""

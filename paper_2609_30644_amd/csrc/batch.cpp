@@ -1,0 +1,343 @@
+// Many independent planning instances at once (mrpop_plan_batch).
+//
+// Every instance is a PlanJob running on a host thread of its own; its device
+// work goes to a shared queue instead of a stream.  Whenever every unfinished
+// instance is waiting for its queued work, the work of all instances is
+// merged and launched on one stream: layer by layer (the next command of
+// every instance), commands of one kind in one launch over all instances'
+// argument records, and the validations of a layer in one many-scene launch.
+// An instance's commands keep their order, and each instance computes
+// exactly what it computes alone: the batch changes when work runs, never
+// what it computes.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "batch.h"
+
+namespace mrpop {
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Grow-only buffers.
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n) return hipSuccess;
+    const size_t want = std::max(bytes, n * 2);
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) n = want;
+    return e;
+  }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+struct HostBuf {
+  unsigned char *p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n) return hipSuccess;
+    const size_t want = std::max(bytes, n * 2);
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    hipError_t e = hipHostMalloc((void **)&p, want);
+    if (e == hipSuccess) n = want;
+    return e;
+  }
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+}  // namespace
+
+struct BatchEngine::Impl {
+  mrpop_ctx *ctx;
+  hipStream_t s;
+  std::mutex mu;
+  std::condition_variable cv_main, cv_jobs;
+  struct Slot {
+    std::vector<Cmd> pending;
+    bool waiting = false, done = false, active = false;
+  };
+  std::vector<Slot> slots;
+  int n_active = 0, n_waiting = 0;
+  uint64_t generation = 0;
+  hipError_t last_err = hipSuccess;
+  // merge buffers
+  HostBuf h_args;
+  DevBuf d_args, seg_scratch;
+  int64_t flushes = 0, launches = 0;
+  // batch limits
+  static constexpr int kMaxPerLaunch = 65535;
+
+  explicit Impl(mrpop_ctx *c, hipStream_t st) : ctx(c), s(st) {}
+
+  hipError_t flush();
+};
+
+// Device work of one slot, queued for the next merged launch.
+class BatchExec : public Exec {
+ public:
+  BatchExec(BatchEngine::Impl *e, int k) : e_(e), k_(k) {}
+  hipError_t submit(const Cmd &c) override {
+    e_->slots[k_].pending.push_back(c);
+    return hipSuccess;
+  }
+  hipError_t sync() override {
+    std::unique_lock<std::mutex> lk(e_->mu);
+    BatchEngine::Impl::Slot &sl = e_->slots[k_];
+    sl.waiting = true;
+    ++e_->n_waiting;
+    const uint64_t gen = e_->generation;
+    e_->cv_main.notify_one();
+    e_->cv_jobs.wait(lk, [&] { return e_->generation != gen; });
+    return e_->last_err;
+  }
+
+ private:
+  BatchEngine::Impl *e_;
+  int k_;
+};
+
+hipError_t BatchEngine::Impl::flush() {
+  const int K = (int)slots.size();
+  std::vector<size_t> head(K, 0);
+  // plan every layer: (op, records), packing argument records into h_args
+  struct Launch {
+    Op op;
+    size_t off;   // byte offset of the records in the argument buffer
+    int count;    // records
+    int grid_x;   // blocks (Validate: flat edges)
+    int r_max;
+  };
+  std::vector<Launch> plan;
+  std::vector<unsigned char> packed;
+  auto put = [&](const void *p, size_t n) -> size_t {
+    const size_t off = (packed.size() + 255) & ~size_t(255);
+    packed.resize(off + n);
+    std::memcpy(packed.data() + off, p, n);
+    return off;
+  };
+  for (;;) {
+    // next command of every slot, grouped by kind (kinds in enum order)
+    bool any = false;
+    std::vector<std::vector<int>> by_op(kNumOps);
+    for (int k = 0; k < K; ++k)
+      if (head[k] < slots[k].pending.size()) {
+        by_op[(int)slots[k].pending[head[k]].op].push_back(k);
+        any = true;
+      }
+    if (!any) break;
+    for (int o = 0; o < kNumOps; ++o) {
+      const std::vector<int> &ks = by_op[o];
+      for (size_t c0 = 0; c0 < ks.size(); c0 += kMaxPerLaunch) {
+        const size_t c1 = std::min(ks.size(), c0 + (size_t)kMaxPerLaunch);
+        const Op op = (Op)o;
+        if (op == Op::Validate) {
+          std::vector<ValSeg> segs;
+          int64_t flat = 0;
+          int r_max = 1;
+          for (size_t i = c0; i < c1; ++i) {
+            const ValidateReq &v = slots[ks[i]].pending[head[ks[i]]].val;
+            r_max = std::max(r_max, (int)v.scene->n_robots);
+          }
+          for (size_t i = c0; i < c1; ++i) flat += slots[ks[i]].pending[head[ks[i]]].val.n;
+          int W = 0, cache = 0;
+          seg_shape(r_max, flat, &W, &cache);
+          flat = 0;
+          for (size_t i = c0; i < c1; ++i) {
+            const ValidateReq &v = slots[ks[i]].pending[head[ks[i]]].val;
+            ValSeg g;
+            std::memset(&g, 0, sizeof(g));
+            g.sc = *v.scene;
+            g.qa = v.qa;
+            g.qb = v.qb;
+            g.edge0 = flat;
+            g.n_edges = v.n;
+            g.tile0 = 0;
+            g.res = v.res;
+            g.S = seg_link_split(v.scene->n_robots, W);
+            g.out = v.out;
+            g.counters = v.counters;
+            flat += v.n;
+            segs.push_back(g);
+          }
+          const size_t off = put(segs.data(), sizeof(ValSeg) * segs.size());
+          plan.push_back({op, off, (int)segs.size(), (int)std::min<int64_t>(flat, 0x7fffffff), r_max});
+          if (flat > 0x7fffffff) return hipErrorInvalidValue;
+        } else {
+          const size_t rec = op_args_bytes(op);
+          const size_t off = (packed.size() + 255) & ~size_t(255);
+          packed.resize(off + rec * (c1 - c0));
+          int gx = 0;
+          for (size_t i = c0; i < c1; ++i) {
+            const Cmd &c = slots[ks[i]].pending[head[ks[i]]];
+            std::memcpy(packed.data() + off + rec * (i - c0), c.args(), rec);
+            gx = std::max(gx, op_blocks(op, c.args()));
+          }
+          if (gx > 0) plan.push_back({op, off, (int)(c1 - c0), gx, 0});
+        }
+      }
+      for (int k : ks) ++head[k];
+    }
+  }
+  if (plan.empty()) return hipSuccess;
+  hipError_t e;
+  if ((e = h_args.ensure(packed.size())) != hipSuccess) return e;
+  if ((e = d_args.ensure(packed.size())) != hipSuccess) return e;
+  std::memcpy(h_args.p, packed.data(), packed.size());
+  int64_t flat_max = 0;
+  for (const Launch &L : plan)
+    if (L.op == Op::Validate) flat_max = std::max<int64_t>(flat_max, L.grid_x);
+  if (flat_max > 0 && (e = seg_scratch.ensure(seg_scratch_bytes(flat_max))) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(d_args.p, h_args.p, packed.size(), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+  for (const Launch &L : plan) {
+    unsigned char *rec = (unsigned char *)d_args.p + L.off;
+    if (L.op == Op::Validate) {
+      const SegScratch ws = seg_scratch_layout(seg_scratch.p, L.grid_x);
+      e = launch_validate_segments((ValSeg *)rec, L.count, L.r_max, L.grid_x, ws, s, profile_slot(ctx),
+                                   ctx->profiling ? ctx->prof_totals : nullptr, &ctx->last_grid, &ctx->last_block);
+    } else {
+      e = launch_op_batch(L.op, rec, L.count, L.grid_x, s);
+    }
+    if (e != hipSuccess) return e;
+    ++launches;
+  }
+  ++flushes;
+  return hipStreamSynchronize(s);
+}
+
+BatchEngine::BatchEngine(mrpop_ctx *ctx, hipStream_t s) : impl_(new Impl(ctx, s)) {}
+BatchEngine::~BatchEngine() { delete impl_; }
+
+int64_t BatchEngine::flushes() const { return impl_->flushes; }
+int64_t BatchEngine::launches() const { return impl_->launches; }
+
+void BatchEngine::run(std::vector<PlanJob *> &jobs, std::vector<mrpop_status> &status) {
+  Impl &I = *impl_;
+  const int K = (int)jobs.size();
+  I.slots.assign(K, Impl::Slot());
+  status.assign(K, MRPOP_OK);
+  I.n_active = 0;
+  I.n_waiting = 0;
+  I.last_err = hipSuccess;
+  std::vector<std::thread> threads;
+  threads.reserve(K);
+  {
+    std::lock_guard<std::mutex> lk(I.mu);
+    for (int k = 0; k < K; ++k)
+      if (jobs[k]) {
+        I.slots[k].active = true;
+        ++I.n_active;
+      }
+  }
+  for (int k = 0; k < K; ++k) {
+    if (!jobs[k]) continue;
+    threads.emplace_back([&, k] {
+      const int dev = I.ctx->device;
+      (void)hipSetDevice(dev);
+      BatchExec ex(&I, k);
+      const mrpop_status st = jobs[k]->run(ex);
+      std::lock_guard<std::mutex> lk(I.mu);
+      status[k] = st;
+      I.slots[k].done = true;
+      I.slots[k].pending.clear();
+      --I.n_active;
+      I.cv_main.notify_one();
+    });
+  }
+  std::unique_lock<std::mutex> lk(I.mu);
+  for (;;) {
+    I.cv_main.wait(lk, [&] { return I.n_active == 0 || I.n_waiting == I.n_active; });
+    if (I.n_active == 0) break;
+    // every unfinished instance waits for its work: merge and launch it
+    const hipError_t e = I.flush();
+    if (e != hipSuccess) I.last_err = e;
+    for (auto &sl : I.slots) {
+      sl.pending.clear();
+      sl.waiting = false;
+    }
+    I.n_waiting = 0;
+    ++I.generation;
+    I.cv_jobs.notify_all();
+  }
+  lk.unlock();
+  for (auto &t : threads) t.join();
+}
+
+}  // namespace mrpop
+
+using namespace mrpop;
+
+extern "C" {
+
+mrpop_status mrpop_plan_batch(mrpop_ctx *ctx, mrpop_plan_request *reqs, int32_t n, mrpop_batch_stats *stats_opt) {
+  if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "plan_batch: ctx is NULL");
+  if (n < 0 || (n > 0 && !reqs)) return fail(ctx, MRPOP_E_INVALID_ARG, "plan_batch: bad request array");
+  const double t0 = now_s();
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, MRPOP_E_DEVICE, "plan_batch: hipSetDevice");
+  std::vector<std::unique_ptr<PlanJob>> jobs(n);
+  std::vector<PlanJob *> run_jobs(n, nullptr);
+  for (int i = 0; i < n; ++i) {
+    mrpop_plan_request &q = reqs[i];
+    q.status = MRPOP_OK;
+    q.path_len = 0;
+    q.cost = INFINITY;
+    std::memset(&q.stats, 0, sizeof(q.stats));
+    if (!q.scene || q.scene->ctx != ctx || !q.q_start || !q.q_goal || (q.path_cap > 0 && !q.path_out)) {
+      q.status = MRPOP_E_INVALID_ARG;
+      continue;
+    }
+    jobs[i].reset(new PlanJob());
+    q.status = jobs[i]->prepare(ctx, q.scene, q.q_start, q.q_goal, q.params);
+    if (q.status == MRPOP_OK) run_jobs[i] = jobs[i].get();
+  }
+  std::vector<mrpop_status> st;
+  BatchEngine eng(ctx, nullptr);
+  eng.run(run_jobs, st);
+  int solved = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!run_jobs[i]) continue;
+    mrpop_plan_request &q = reqs[i];
+    PlanJob &j = *jobs[i];
+    q.stats = j.stats();
+    q.status = st[i];
+    if (st[i] != MRPOP_OK) continue;
+    const int len = (int)(j.path().size() / j.dof());
+    q.path_len = len;
+    q.cost = j.cost();
+    ++solved;
+    if (len > q.path_cap) {
+      q.status = MRPOP_E_BUFFER;
+      continue;
+    }
+    std::memcpy(q.path_out, j.path().data(), sizeof(float) * j.path().size());
+  }
+  if (stats_opt) {
+    stats_opt->wall_s = now_s() - t0;
+    stats_opt->instances = n;
+    stats_opt->solved = solved;
+    stats_opt->flushes = eng.flushes();
+    stats_opt->launches = eng.launches();
+  }
+  return MRPOP_OK;
+}
+
+}  // extern "C"

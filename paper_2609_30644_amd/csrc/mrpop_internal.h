@@ -157,4 +157,40 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
 // Take an event pair for one profiled launch (nullptr when not profiling).
 const std::pair<hipEvent_t, hipEvent_t> *profile_slot(mrpop_ctx *ctx);
 
+// One validation request of a many-scene launch: edges [edge0, edge0 +
+// n_edges) of the flat list are (qa[i], qb[i]) of scene sc; bits go to
+// out[i], the request's counters (layout of ValidateScratch::counters) to
+// counters[16].  tile0 (first tile) is filled on the device.
+struct ValSeg {
+  SceneDev sc;
+  const float *qa, *qb;
+  int64_t edge0, n_edges, tile0;
+  float res;
+  int32_t S;  // link parts per arm (tile shape of this scene)
+  uint8_t *out;
+  uint64_t *counters;
+};
+
+struct SegScratch {
+  int32_t *n_states, *edge_seg;  // [F]
+  uint32_t *flags;               // [F]
+  int64_t *offsets;              // [F + 1]
+  int64_t *block_sums;
+  uint64_t *batch;               // [16]: 1 total tiles, 2 tile table overflow
+  uint64_t *partials;            // [kMaxGrid][kPartialSlots]
+  int32_t *tile_first, *tile_seg;  // [kTileFirstCap]
+};
+size_t seg_scratch_bytes(int64_t n_flat);
+SegScratch seg_scratch_layout(void *base, int64_t n_flat);
+// Link parts per arm for a scene of n_robots arms in a launch of W waves.
+int seg_link_split(int n_robots, int W);
+// Waves per workgroup and whether joint sines/cosines are cached, for a
+// launch whose largest scene has r_max arms.
+void seg_shape(int r_max, int64_t n_flat, int *W, int *cache_sc);
+// d_segs: device copy of the requests (tile0 is written there).
+hipError_t launch_validate_segments(ValSeg *d_segs, int n_segs, int r_max, int64_t n_flat, const SegScratch &ws,
+                                    hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> *ev_pair = nullptr,
+                                    uint64_t *totals = nullptr, int32_t *grid_out = nullptr,
+                                    int32_t *block_out = nullptr);
+
 }  // namespace mrpop

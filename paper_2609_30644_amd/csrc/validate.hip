@@ -214,8 +214,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const int32_t 
     if (base + i < n_edges) {
       offsets[base + i] = run;
       // tiles whose first position falls inside this edge: [run, run + v)
-      for (int64_t tl = (run + kWave - 1) / kWave; tl * kWave < run + v[i] && tl < kTileFirstCap; ++tl)
-        tile_first[tl] = (int32_t)(base + i);
+      if (tile_first)
+        for (int64_t tl = (run + kWave - 1) / kWave; tl * kWave < run + v[i] && tl < kTileFirstCap; ++tl)
+          tile_first[tl] = (int32_t)(base + i);
     }
     run += v[i];
   }
@@ -745,6 +746,124 @@ __host__ __device__ inline size_t tile_shared_floats(int n_robots, int cache_sc)
   return (size_t)n_robots * (kMaxLinks * 3 + (cache_sc ? kMaxJoints * 2 : 0)) * kWave;
 }
 
+// Lanes of one tile: lane i holds list position s0 + i (positions relative
+// to `base`, the list offset of the first edge considered, e_base its index);
+// my_off is off[e0 + lane] - base (clamped to the last edge).  Returns the
+// lane's state, whether it is active, its edge and the lanes of the tile on
+// the same edge.
+struct TileLanes {
+  LaneState st;
+  bool act;
+  int64_t e;
+  uint64_t emask;
+};
+
+__device__ __forceinline__ TileLanes map_lanes(int64_t s0, int64_t total, int64_t e0, int64_t my_off,
+                                               const int64_t *__restrict__ off, int64_t base, int64_t e_base,
+                                               const float *qa, const float *qb, int dof, int lane) {
+  TileLanes t;
+  const int64_t s = s0 + lane;
+  t.act = s < total;
+  // the tile starts in edge e0 and spans at most 64 consecutive edges; a
+  // binary search over lanes finds the last edge starting at or before the
+  // lane's position
+  int pos = 0;
+#pragma unroll
+  for (int step = kWave / 2; step > 0; step >>= 1) {
+    const int cand = pos + step;
+    const int64_t o = __shfl(my_off, cand, kWave);
+    if (o <= s) pos = cand;
+  }
+  t.e = e0 + pos;
+  const int64_t e_start = __shfl(my_off, pos, kWave);
+  int64_t e_end = __shfl(my_off, pos < kWave - 1 ? pos + 1 : pos, kWave);
+  if (t.act && pos == kWave - 1) e_end = off[t.e + 1] - base;  // active lanes are on a real edge
+  t.st = LaneState{qa, qb, 0.f, false};
+  t.emask = 0;
+  if (t.act) {
+    const int64_t n = e_end - e_start;
+    const int64_t k = s - e_start;
+    t.st.qa = qa + (t.e - e_base) * dof;
+    t.st.qb = qb + (t.e - e_base) * dof;
+    t.st.last = n > 1 && k == n - 1;
+    t.st.t = n > 1 ? (float)k / (float)(n - 1) : 0.f;
+    const int lo = (int)((e_start > s0 ? e_start : s0) - s0);
+    const int hi = (int)((e_end < s0 + kWave ? e_end : s0 + kWave) - s0);
+    t.emask = (hi - lo >= 64 ? ~0ull : ((1ull << (hi - lo)) - 1ull)) << lo;
+  }
+  return t;
+}
+
+// One tile on the whole workgroup: the environment jobs (arm, link part)
+// over the waves, a barrier, the arm-pair stage, the edge flag; ends with a
+// barrier (the tile's LDS is reused by the next one).
+template <bool STAGED>
+__device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int w, int W, int lane, int it,
+                          const TileLanes &tl, uint32_t *flags, float *cen, float *sc_lds, float *wave_fr,
+                          uint32_t *wave_q, unsigned long long *s_dead, unsigned long long *s_hit, WorkCount &wc,
+                          uint32_t &checked) {
+  unsigned long long *const dead = &s_dead[it & 1];
+  const LaneState &st = tl.st;
+  bool act = tl.act;
+  const int R = sc.n_robots;
+  bool hit = false;
+  for (int jb = w; jb < R * S; jb += W) {
+    const int r = jb / S, part = jb - r * S;
+    const int m = as_const(sc.model)[r];
+    const int nj = as_const(sc.nj)[m];
+    const int q0 = as_const(sc.q_off)[r];
+    // all joint values of the arm first, so that their loads overlap (with
+    // the edge's flag on the wave's first arm: states of an edge that an
+    // earlier tile found colliding are skipped)
+    float qv[kMaxJoints];
+    {
+      float qa_v[kMaxJoints], qb_v[kMaxJoints];
+#pragma unroll
+      for (int j = 0; j < kMaxJoints; ++j) {
+        const int idx = j < nj ? q0 + j : q0;
+        qa_v[j] = st.qa[idx];
+        qb_v[j] = st.qb[idx];
+      }
+      if (jb == w && act && load_relaxed(flags + tl.e) != 0u) act = false;
+#pragma unroll
+      for (int j = 0; j < kMaxJoints; ++j) qv[j] = st.last ? qb_v[j] : fmaf(st.t, qb_v[j] - qa_v[j], qa_v[j]);
+    }
+    const bool live = act && !hit;
+    if (arm_env<STAGED>(sc, src, r, m, part, S, qv, live, tl.emask, cen, sc_lds, wave_fr, wave_q, &s_hit[w], dead,
+                        lane, wc))
+      hit = true;
+  }
+  if (act && w == 0) ++checked;
+  __syncthreads();
+  if (threadIdx.x == 0) s_dead[(it + 1) & 1] = 0ull;  // last used by the previous tile
+  // arm pairs that can reach each other
+  if (arm_pairs<STAGED>(sc, src, cen, sc_lds, w, W, act && !hit, st, tl.emask, wave_q, &s_hit[w], dead, lane, wc))
+    hit = true;
+  if (hit) flags[tl.e] = kFlagHit;
+  __syncthreads();
+}
+
+// Workgroup totals of the work counters, one slot row per workgroup (summed
+// by the final kernel; no device-wide atomics).
+__device__ void write_partials(uint64_t *partials, uint32_t checked, uint32_t tiles, const WorkCount &wc, int w,
+                               int lane) {
+  __shared__ unsigned long long s_part[kPartialSlots];
+  if (threadIdx.x < kPartialSlots) s_part[threadIdx.x] = 0ull;
+  __syncthreads();
+  uint64_t v[kPartialSlots - 1] = {checked,      wc.chains, wc.links,  wc.env_tests, wc.box_exact,
+                                   wc.rr_coarse, wc.fine_s, wc.fine_b, wc.fine_rr};
+#pragma unroll
+  for (int i = 0; i < kPartialSlots - 1; ++i)
+    for (int d = kWave / 2; d > 0; d >>= 1) v[i] += __shfl_xor(v[i], d, kWave);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < kPartialSlots - 1; ++i) atomicAdd(&s_part[i], (unsigned long long)v[i]);
+    if (w == 0) atomicAdd(&s_part[kPartialSlots - 1], (unsigned long long)tiles);
+  }
+  __syncthreads();
+  if (threadIdx.x < kPartialSlots) partials[(int64_t)blockIdx.x * kPartialSlots + threadIdx.x] = s_part[threadIdx.x];
+}
+
 template <bool STAGED>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_kernel(
     SceneDev sc, const float *__restrict__ qa, const float *__restrict__ qb, int64_t n_edges,
@@ -791,7 +910,6 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
   int64_t off_cur = lane_off(e0_cur);
   int64_t e0_nxt = tile + G < n_tiles ? first_edge(tile + G) : 0;
   for (int it = 0; tile < n_tiles; ++it, tile += G) {
-    unsigned long long *const dead = &s_dead[it & 1];
     const int64_t e0 = e0_cur, my_off = off_cur;
     if (tile + G < n_tiles) {
       e0_cur = e0_nxt;
@@ -799,90 +917,174 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
       if (tile + 2 * G < n_tiles) e0_nxt = first_edge(tile + 2 * G);
     }
     if (w == 0) ++tiles;
-    const int64_t s0 = tile * kWave;
-    const int64_t s = s0 + lane;
-    bool act = s < total;
-    // edge of each lane: the tile starts in edge e0 and spans at most 64
-    // consecutive edges; lane i holds off[e0 + i] and a binary search over
-    // lanes finds the last edge starting at or before the lane's position
-    int pos = 0;
-#pragma unroll
-    for (int step = kWave / 2; step > 0; step >>= 1) {
-      const int cand = pos + step;
-      const int64_t o = __shfl(my_off, cand, kWave);
-      if (o <= s) pos = cand;
+    const TileLanes tl = map_lanes(tile * kWave, total, e0, my_off, off, 0, 0, qa, qb, sc.dof, lane);
+    tile_work<STAGED>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, wc,
+                      checked);
+  }
+  write_partials(partials, checked, tiles, wc, w, lane);
+}
+
+// ---------------------------------------------------------------------------
+// 4. many scenes in one launch (independent planning instances)
+// ---------------------------------------------------------------------------
+//
+// The edges of all segments form one flat list; every segment's states are
+// laid out from a tile boundary, so that a tile belongs to one segment (one
+// scene, wave-uniform model data).  The tile table records each tile's
+// segment and first edge.
+
+// Segment of flat edge f (segments sorted by edge0).
+__device__ __forceinline__ int seg_of_edge(const ValSeg *__restrict__ segs, int n_segs, int64_t f) {
+  int lo = 0, hi = n_segs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].edge0 <= f) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void seg_count_kernel(const ValSeg *__restrict__ segs, int n_segs, int64_t n_flat,
+                                                        int32_t *__restrict__ n_out, uint32_t *__restrict__ flags,
+                                                        int32_t *__restrict__ edge_seg) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n_flat) return;
+  const int k = seg_of_edge(segs, n_segs, f);
+  const ValSeg &g = segs[k];
+  uint32_t fl;
+  n_out[f] = edge_states(g.qa, g.qb, f - g.edge0, g.sc.dof, g.res, nullptr, &fl);
+  flags[f] = fl;
+  edge_seg[f] = k;
+}
+
+// Single workgroup: states and tiles of every segment, the first tile of
+// each, the segments' counters (reset; [1] = edge states) and the total tile
+// count (batch[1]; batch[2] = 1 when the tile table would overflow).
+__global__ __launch_bounds__(kScanThreads) void seg_tiles_kernel(ValSeg *__restrict__ segs, int n_segs,
+                                                                 const int64_t *__restrict__ off,
+                                                                 uint64_t *__restrict__ batch) {
+  int64_t carry = 0;
+  for (int k0 = 0; k0 < n_segs; k0 += kScanThreads) {
+    const int k = k0 + threadIdx.x;
+    int64_t tiles = 0, states = 0;
+    if (k < n_segs) {
+      states = off[segs[k].edge0 + segs[k].n_edges] - off[segs[k].edge0];
+      tiles = (states + kWave - 1) / kWave;
     }
-    const int64_t e = e0 + pos;
-    const int64_t e_start = __shfl(my_off, pos, kWave);
-    int64_t e_end = __shfl(my_off, pos < kWave - 1 ? pos + 1 : pos, kWave);
-    if (act && pos == kWave - 1) e_end = off[e + 1];  // active lanes have e < n_edges
-    LaneState st{qa, qb, 0.f, false};
-    uint64_t emask = 0;  // lanes of this tile on the same edge
-    if (act) {
-      const int64_t n = e_end - e_start;
-      const int64_t k = s - e_start;
-      st.qa = qa + e * sc.dof;
-      st.qb = qb + e * sc.dof;
-      st.last = n > 1 && k == n - 1;
-      st.t = n > 1 ? (float)k / (float)(n - 1) : 0.f;
-      const int lo = (int)((e_start > s0 ? e_start : s0) - s0);
-      const int hi = (int)((e_end < s0 + kWave ? e_end : s0 + kWave) - s0);
-      emask = (hi - lo >= 64 ? ~0ull : ((1ull << (hi - lo)) - 1ull)) << lo;
+    int64_t total;
+    const int64_t ex = block_exclusive_scan(tiles, &total);
+    if (k < n_segs) {
+      segs[k].tile0 = carry + ex;
+      uint64_t *c = segs[k].counters;
+      for (int i = 0; i < 16; ++i) c[i] = 0;
+      c[1] = (uint64_t)states;
     }
-    bool hit = false;
-    // environment: jobs (arm r, link part) over the waves
-    for (int jb = w; jb < R * S; jb += W) {
-      const int r = jb / S, part = jb - r * S;
-      const int m = as_const(sc.model)[r];
-      const int nj = as_const(sc.nj)[m];
-      const int q0 = as_const(sc.q_off)[r];
-      // all joint values of the arm first, so that their loads overlap (with
-      // the edge's flag on the wave's first arm: states of an edge that an
-      // earlier tile found colliding are skipped)
-      float qv[kMaxJoints];
-      {
-        float qa_v[kMaxJoints], qb_v[kMaxJoints];
-#pragma unroll
-        for (int j = 0; j < kMaxJoints; ++j) {
-          const int idx = j < nj ? q0 + j : q0;
-          qa_v[j] = st.qa[idx];
-          qb_v[j] = st.qb[idx];
-        }
-        if (jb == w && act && load_relaxed(flags + e) != 0u) act = false;
-#pragma unroll
-        for (int j = 0; j < kMaxJoints; ++j) qv[j] = st.last ? qb_v[j] : fmaf(st.t, qb_v[j] - qa_v[j], qa_v[j]);
-      }
-      const bool live = act && !hit;
-      if (arm_env<STAGED>(sc, src, r, m, part, S, qv, live, emask, cen, sc_lds, wave_fr, wave_q, &s_hit[w], dead,
-                          lane, wc))
-        hit = true;
-    }
-    if (act && w == 0) ++checked;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    batch[0] = 0;
+    batch[1] = (uint64_t)carry;
+    batch[2] = carry > kTileFirstCap ? 1 : 0;
+    for (int c = 3; c < 16; ++c) batch[c] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void seg_table_kernel(const ValSeg *__restrict__ segs, int64_t n_flat,
+                                                        const int32_t *__restrict__ n_states,
+                                                        const int32_t *__restrict__ edge_seg,
+                                                        const int64_t *__restrict__ off,
+                                                        int32_t *__restrict__ tile_first, int32_t *__restrict__ tile_seg) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n_flat) return;
+  const int k = edge_seg[f];
+  const ValSeg &g = segs[k];
+  const int64_t run = off[f] - off[g.edge0];
+  const int64_t v = n_states[f];
+  for (int64_t tl = (run + kWave - 1) / kWave; tl * kWave < run + v; ++tl) {
+    const int64_t t = g.tile0 + tl;
+    if (t >= kTileFirstCap) break;
+    tile_first[t] = (int32_t)f;
+    tile_seg[t] = k;
+  }
+}
+
+__global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_segments_kernel(
+    const ValSeg *__restrict__ segs, const int64_t *__restrict__ off, const int32_t *__restrict__ tile_first,
+    const int32_t *__restrict__ tile_seg, uint32_t *__restrict__ flags, const uint64_t *__restrict__ batch,
+    uint64_t *__restrict__ partials, int r_max, int cache_sc) {
+  extern __shared__ float cen[];
+  __shared__ unsigned long long s_dead[2], s_hit[kMaxWavesPerBlock];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave), W = blockDim.x / kWave;
+  int64_t n_tiles = (int64_t)batch[1];
+  if (batch[2]) n_tiles = 0;  // table overflow: reported by the host, nothing checked
+  uint32_t checked = 0, tiles = 0;
+  WorkCount wc;
+  if ((int64_t)blockIdx.x >= n_tiles) {
+    if (threadIdx.x < kPartialSlots) partials[(int64_t)blockIdx.x * kPartialSlots + threadIdx.x] = 0ull;
+    return;
+  }
+  if (threadIdx.x < 2) s_dead[threadIdx.x] = 0ull;
+  __syncthreads();
+  float *const sc_lds = cache_sc ? cen + (size_t)r_max * kMaxLinks * 3 * kWave : nullptr;
+  float *const wave_fr = cen + tile_shared_floats(r_max, cache_sc) + (size_t)w * kWaveLdsFloats;
+  uint32_t *const wave_q = (uint32_t *)(wave_fr + 12 * kWave);
+  const int64_t G = gridDim.x;
+  int it = 0;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += G, ++it) {
+    const int k = (int)__builtin_amdgcn_readfirstlane(tile_seg[tile]);
+    const ValSeg &g = segs[k];
+    const SceneDev &sc = g.sc;
+    const Src<false> src = make_src<false>(sc, nullptr);
+    const int64_t base = off[g.edge0], e_last = g.edge0 + g.n_edges;
+    const int64_t e0 = tile_first[tile];
+    const int64_t ei = e0 + lane < e_last ? e0 + lane : e_last;
+    const int64_t my_off = off[ei] - base;
+    const int64_t total = off[e_last] - base;
+    if (w == 0) ++tiles;
+    const TileLanes tl = map_lanes((tile - g.tile0) * kWave, total, e0, my_off, off, base, g.edge0, g.qa, g.qb,
+                                   sc.dof, lane);
+    tile_work<false>(sc, src, g.S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, wc,
+                     checked);
+  }
+  write_partials(partials, checked, tiles, wc, w, lane);
+}
+
+// Bits of every segment's edges, their invalid counts, and (block 0) the
+// work totals.
+__global__ __launch_bounds__(256) void seg_finalize_kernel(const ValSeg *__restrict__ segs, int64_t n_flat,
+                                                           const uint32_t *__restrict__ flags,
+                                                           const int32_t *__restrict__ edge_seg,
+                                                           const uint64_t *__restrict__ partials, int n_partials,
+                                                           uint64_t *__restrict__ totals) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && totals) {
+    __shared__ unsigned long long col[kPartialSlots];
+    if (threadIdx.x < kPartialSlots) col[threadIdx.x] = 0ull;
     __syncthreads();
-    if (threadIdx.x == 0) s_dead[(it + 1) & 1] = 0ull;  // last used by the previous tile
-    // arm pairs that can reach each other
-    if (arm_pairs<STAGED>(sc, src, cen, sc_lds, w, W, act && !hit, st, emask, wave_q, &s_hit[w], dead, lane, wc))
-      hit = true;
-    if (hit) flags[e] = kFlagHit;
-    __syncthreads();  // centres and dead masks are reused by the next tile
-  }
-  // workgroup totals of the work counters, one slot row per workgroup
-  // (summed by the final kernel; no device-wide atomics)
-  __shared__ unsigned long long s_part[kPartialSlots];
-  if (threadIdx.x < kPartialSlots) s_part[threadIdx.x] = 0ull;
-  __syncthreads();
-  uint64_t v[kPartialSlots - 1] = {checked,      wc.chains, wc.links,  wc.env_tests, wc.box_exact,
-                                   wc.rr_coarse, wc.fine_s, wc.fine_b, wc.fine_rr};
+    uint64_t acc[kPartialSlots] = {};
+    for (int b = threadIdx.x; b < n_partials; b += blockDim.x) {
 #pragma unroll
-  for (int i = 0; i < kPartialSlots - 1; ++i)
-    for (int d = kWave / 2; d > 0; d >>= 1) v[i] += __shfl_xor(v[i], d, kWave);
-  if (lane == 0) {
+      for (int i = 0; i < kPartialSlots; ++i) acc[i] += partials[(int64_t)b * kPartialSlots + i];
+    }
 #pragma unroll
-    for (int i = 0; i < kPartialSlots - 1; ++i) atomicAdd(&s_part[i], (unsigned long long)v[i]);
-    if (w == 0) atomicAdd(&s_part[kPartialSlots - 1], (unsigned long long)tiles);
+    for (int i = 0; i < kPartialSlots; ++i) {
+      for (int d = kWave / 2; d > 0; d >>= 1) acc[i] += __shfl_xor(acc[i], d, kWave);
+      if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&col[i], (unsigned long long)acc[i]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      totals[0] += col[0];
+      for (int i = 1; i < kPartialSlots - 1; ++i) totals[1 + i] += col[i];
+    }
   }
-  __syncthreads();
-  if (threadIdx.x < kPartialSlots) partials[(int64_t)blockIdx.x * kPartialSlots + threadIdx.x] = s_part[threadIdx.x];
+  if (f >= n_flat) return;
+  const int k = edge_seg[f];
+  const ValSeg &g = segs[k];
+  const uint32_t fl = flags[f];
+  g.out[f - g.edge0] = fl == 0u ? 1 : 0;
+  if (fl != 0u) atomicAdd((unsigned long long *)&g.counters[5], 1ull);
+  if (f == g.edge0 && totals) atomicAdd((unsigned long long *)&totals[1], (unsigned long long)g.counters[1]);
 }
 
 __global__ __launch_bounds__(256) void finalize_kernel(const uint32_t *__restrict__ flags, int64_t n_edges,
@@ -1028,6 +1230,107 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
   if (ev_pair) (void)hipEventRecord(ev_pair->second, s);
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)g256), dim3(256), 0, s, ws.flags, n_edges, out_valid,
                      ws.counters, ws.partials, grid, totals);
+  return hipGetLastError();
+}
+
+size_t seg_scratch_bytes(int64_t n_flat) {
+  size_t b = 0;
+  auto add = [&](size_t n) {
+    b = (b + 255) & ~size_t(255);
+    b += n;
+  };
+  add(sizeof(int32_t) * n_flat);
+  add(sizeof(int32_t) * n_flat);
+  add(sizeof(uint32_t) * n_flat);
+  add(sizeof(int64_t) * (n_flat + 1));
+  add(sizeof(int64_t) * (scan_blocks(n_flat) + 1));
+  add(sizeof(uint64_t) * 16);
+  add(sizeof(uint64_t) * kPartialSlots * kMaxGrid);
+  add(sizeof(int32_t) * kTileFirstCap);
+  add(sizeof(int32_t) * kTileFirstCap);
+  return b + 256;
+}
+
+SegScratch seg_scratch_layout(void *base, int64_t n_flat) {
+  size_t b = 0;
+  auto take = [&](size_t n) {
+    b = (b + 255) & ~size_t(255);
+    void *p = (unsigned char *)base + b;
+    b += n;
+    return p;
+  };
+  SegScratch w;
+  w.n_states = (int32_t *)take(sizeof(int32_t) * n_flat);
+  w.edge_seg = (int32_t *)take(sizeof(int32_t) * n_flat);
+  w.flags = (uint32_t *)take(sizeof(uint32_t) * n_flat);
+  w.offsets = (int64_t *)take(sizeof(int64_t) * (n_flat + 1));
+  w.block_sums = (int64_t *)take(sizeof(int64_t) * (scan_blocks(n_flat) + 1));
+  w.batch = (uint64_t *)take(sizeof(uint64_t) * 16);
+  w.partials = (uint64_t *)take(sizeof(uint64_t) * kPartialSlots * kMaxGrid);
+  w.tile_first = (int32_t *)take(sizeof(int32_t) * kTileFirstCap);
+  w.tile_seg = (int32_t *)take(sizeof(int32_t) * kTileFirstCap);
+  return w;
+}
+
+int seg_link_split(int n_robots, int W) {
+  int S = 1;
+  while (S < 4 && n_robots * S * 2 <= W) S *= 2;
+  return S;
+}
+
+void seg_shape(int r_max, int64_t n_flat, int *W, int *cache_sc) {
+  const TileShape ts = tile_shape(r_max, n_flat);
+  *W = ts.W;
+  *cache_sc = ts.cache_sc;
+}
+
+static int segments_grid(int W, size_t lds) {
+  struct Key {
+    int w;
+    size_t lds;
+    int grid;
+  };
+  static std::vector<Key> cache;
+  for (const Key &k : cache)
+    if (k.w == W && k.lds == lds) return k.grid;
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_segments_kernel, kWave * W, lds);
+  const int grid = std::min(kMaxGrid, std::max(1, cus) * std::max(1, per));
+  cache.push_back({W, lds, grid});
+  return grid;
+}
+
+hipError_t launch_validate_segments(ValSeg *d_segs, int n_segs, int r_max, int64_t n_flat, const SegScratch &ws,
+                                    hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> *ev_pair,
+                                    uint64_t *totals, int32_t *grid_out, int32_t *block_out) {
+  if (n_segs <= 0 || n_flat <= 0) return hipSuccess;
+  const int64_t nb = scan_blocks(n_flat);
+  const int64_t g256 = (n_flat + 255) / 256;
+  if (g256 > 0x7fffffff || nb > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(seg_count_kernel, dim3((unsigned)g256), dim3(256), 0, s, d_segs, n_segs, n_flat, ws.n_states,
+                     ws.flags, ws.edge_seg);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_flat,
+                     ws.block_sums);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, ws.block_sums, nb, ws.batch);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_flat,
+                     ws.block_sums, ws.offsets, (int32_t *)nullptr);
+  hipLaunchKernelGGL(seg_tiles_kernel, dim3(1), dim3(kScanThreads), 0, s, d_segs, n_segs, ws.offsets, ws.batch);
+  hipLaunchKernelGGL(seg_table_kernel, dim3((unsigned)g256), dim3(256), 0, s, d_segs, n_flat, ws.n_states,
+                     ws.edge_seg, ws.offsets, ws.tile_first, ws.tile_seg);
+  int W = 0, cache = 0;
+  seg_shape(r_max, n_flat, &W, &cache);
+  const size_t lds = centre_lds_bytes(r_max, W, cache);
+  const int grid = segments_grid(W, lds);
+  if (grid_out) *grid_out = grid;
+  if (block_out) *block_out = kWave * W;
+  if (ev_pair) (void)hipEventRecord(ev_pair->first, s);
+  hipLaunchKernelGGL(validate_segments_kernel, dim3(grid), dim3(kWave * W), lds, s, d_segs, ws.offsets,
+                     ws.tile_first, ws.tile_seg, ws.flags, ws.batch, ws.partials, r_max, cache);
+  if (ev_pair) (void)hipEventRecord(ev_pair->second, s);
+  hipLaunchKernelGGL(seg_finalize_kernel, dim3((unsigned)g256), dim3(256), 0, s, d_segs, n_flat, ws.flags,
+                     ws.edge_seg, ws.partials, grid, totals);
   return hipGetLastError();
 }
 

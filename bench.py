@@ -100,6 +100,56 @@ def cpu_baseline(scene, batches, res, target_s: float) -> dict:
                       f"FP64 coarse-to-fine checker with early exit, {dt:.1f} s"}
 
 
+BATCH_FIXTURE = os.path.join(ROOT, "tests", "golden", "c4_batch.json")
+# Planner settings of the batched comparison (round budgets, so that the
+# batch and the plain runs compute the same paths).
+BATCH_PLAN = dict(candidates=64, n_roadmap=16, delta=3.0, max_rounds=200, max_iterations=3, max_tree_nodes=8192,
+                  max_roadmap_nodes=2048)
+
+
+def batched_vs_plain(ctx, n_inst: int) -> dict:
+    """The batched workload (independent instances with 2-8 arms, 16-256
+    obstacles, uneven edge resolutions) planned once as one mrpop_plan_batch
+    call and once as sequential mrpop_plan calls; both timed on the wall
+    clock, results compared instance by instance."""
+    import paper_2609_30644_amd as M
+    import workloads as W
+    d = json.load(open(BATCH_FIXTURE))
+    inst = d["instances"][:n_inst]
+    jobs = []
+    for i, x in enumerate(inst):
+        R = x["n_robots"]
+        sc = W.Scene([W.panda_like(59)] * R, np.array(x["bases"], np.float32).reshape(R, 12),
+                     np.array(x["env_spheres"], np.float32).reshape(-1, 4),
+                     np.array(x["env_boxes"], np.float32).reshape(-1, 6))
+        jobs.append((M.Scene(ctx, sc), np.array(x["q_start"], np.float32), np.array(x["q_goal"], np.float32),
+                     dict(BATCH_PLAN, seed=i, resolution=x["resolution"])))
+    ctx.plan_batch(jobs[:4])  # warm-up (kernel loading, buffers)
+    t = time.perf_counter()
+    got, bst = ctx.plan_batch(jobs)
+    t_batch = time.perf_counter() - t
+    plain = []
+    t = time.perf_counter()
+    for s, qs, qg, prm in jobs:
+        plain.append(s.plan(qs, qg, raise_on_error=False, **prm))
+    t_plain = time.perf_counter() - t
+    same = all(g.status == p.status and g.cost == p.cost and
+               (g.path is None and p.path is None or (g.path is not None and p.path is not None and
+                                                      np.array_equal(g.path, p.path)))
+               for g, p in zip(got, plain))
+    states = sum(g.stats["edge_states"] + g.stats["roadmap_edge_states"] for g in got)
+    tts_b = [g.stats["time_to_first_s"] for g in got if g.stats["time_to_first_s"] >= 0]
+    tts_p = [p.stats["time_to_first_s"] for p in plain if p.stats["time_to_first_s"] >= 0]
+    return {"instances": len(jobs), "arms": sorted(set(x["n_robots"] for x in inst)),
+            "batched_wall_s": t_batch, "plain_wall_s": t_plain, "speedup": t_plain / t_batch,
+            "identical_to_plain": bool(same), "solved": sum(g.status == "OK" for g in got),
+            "edge_states": int(states), "batched_edge_states_per_s": states / t_batch,
+            "plain_edge_states_per_s": states / t_plain,
+            "tts_p50_ms_batched": float(np.median(tts_b)) * 1e3 if tts_b else None,
+            "tts_p50_ms_plain_alone": float(np.median(tts_p)) * 1e3 if tts_p else None,
+            "merged_launches": bst["launches"], "flushes": bst["flushes"], "params": BATCH_PLAN}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +158,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plan", action="store_true", help="validation batches only")
+    ap.add_argument("--batch-instances", type=int, default=64,
+                    help="instances of the batched-vs-plain comparison (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -186,6 +238,9 @@ def main():
                         "edge_states_per_plan": plan_states / len(plans),
                         "params": PLAN}
         line["config"]["plan"] = "one mrpop_plan per step, seed = step index"
+    if args.batch_instances > 0:
+        print("[bench] batched vs plain", file=sys.stderr, flush=True)
+        line["batched"] = batched_vs_plain(ctx, args.batch_instances)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(scene, batches, res, args.cpu_seconds)

@@ -50,7 +50,8 @@ typedef enum {
   MRPOP_E_CAPACITY = 6,      /* a tree or roadmap reached its capacity          */
   MRPOP_E_NOMEM = 7,         /* a device allocation failed                      */
   MRPOP_E_BUFFER = 8,        /* an output buffer is too small                   */
-  MRPOP_E_DEVICE = 9         /* a HIP runtime call failed                       */
+  MRPOP_E_DEVICE = 9,        /* a HIP runtime call failed                       */
+  MRPOP_PENDING = 10         /* a served request is queued or running           */
 } mrpop_status;
 
 typedef struct mrpop_ctx mrpop_ctx;
@@ -305,6 +306,64 @@ typedef struct {
  * for a NULL context or request array; per-request failures are reported in
  * reqs[i].status.  Blocking; uses one host thread per request. */
 mrpop_status mrpop_plan_batch(mrpop_ctx *ctx, mrpop_plan_request *reqs, int32_t n, mrpop_batch_stats *stats_opt);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of planning requests                         */
+/* ------------------------------------------------------------------------ */
+
+/* A server plans requests as they arrive.  A request waits in a queue until a
+ * slot is free and its device memory (PlanJob arena and one-arm sub-scenes,
+ * estimated before allocation) fits the budget next to the running ones; it
+ * then runs alongside them, its device work merged with theirs at every
+ * synchronisation point (as in mrpop_plan_batch), and its trees and roadmaps
+ * stay on the device until it ends.  Each request computes exactly what
+ * mrpop_plan computes for it alone (with round budgets; a time budget counts
+ * from the request's admission). */
+typedef struct mrpop_server mrpop_server;
+
+typedef struct {
+  int32_t max_slots;           /* requests running at once (1 .. 4096)        */
+  int64_t mem_budget_bytes;    /* device memory for running requests (0: none) */
+} mrpop_server_config;
+
+typedef struct {
+  mrpop_status status;         /* MRPOP_PENDING until the request ends        */
+  int32_t path_len;
+  float cost;
+  mrpop_plan_stats stats;
+  double t_submit, t_admit, t_done;  /* server clock (mrpop_server_clock), s  */
+  int64_t device_bytes;        /* memory reserved for the request             */
+} mrpop_server_result;
+
+typedef struct {
+  int64_t submitted, admitted, completed, rejected;
+  int32_t queue_len, running, max_queue_len, max_running;
+  int64_t reserved_bytes, peak_reserved_bytes;
+  int64_t flushes, launches;
+} mrpop_server_stats;
+
+/* Starts the server's scheduling thread.  E_INVALID_ARG for a bad config. */
+mrpop_status mrpop_server_create(mrpop_ctx *ctx, const mrpop_server_config *cfg, mrpop_server **out);
+/* Finishes running requests, drops queued ones (they stay PENDING) and stops. */
+void mrpop_server_destroy(mrpop_server *srv);
+/* Queues a request.  Start, goal and params are copied; the scene must stay
+ * alive until the request ends.  *ticket identifies it.  A request whose
+ * memory exceeds the whole budget ends at once with E_NOMEM. */
+mrpop_status mrpop_server_submit(mrpop_server *srv, const mrpop_scene *scene, const float *q_start,
+                                 const float *q_goal, const mrpop_plan_params *params, int64_t *ticket);
+/* Result of a request (status MRPOP_PENDING while it has not ended).  Returns
+ * E_INVALID_ARG for an unknown ticket, MRPOP_OK otherwise. */
+mrpop_status mrpop_server_poll(mrpop_server *srv, int64_t ticket, mrpop_server_result *out);
+/* As poll, after waiting up to timeout_s seconds for the request to end. */
+mrpop_status mrpop_server_wait(mrpop_server *srv, int64_t ticket, double timeout_s, mrpop_server_result *out);
+/* Copies an ended request's path (start -> goal, [path_len][D]); E_BUFFER if
+ * cap is too small, E_INVALID_ARG if the ticket is unknown or has no path. */
+mrpop_status mrpop_server_path(mrpop_server *srv, int64_t ticket, float *path_out, int32_t cap);
+/* Forgets an ended request's result. */
+mrpop_status mrpop_server_release(mrpop_server *srv, int64_t ticket);
+mrpop_status mrpop_server_get_stats(mrpop_server *srv, mrpop_server_stats *out);
+/* Seconds on the server's clock (the clock of the result timestamps). */
+double mrpop_server_clock(const mrpop_server *srv);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel profiling                                                          */

@@ -18,7 +18,7 @@ _LIB_NAME = "libmrpop.so"
 
 STATUS_NAMES = {
     0: "OK", 1: "E_INVALID_ARG", 2: "E_NONFINITE", 3: "E_START_INVALID", 4: "E_GOAL_INVALID",
-    5: "E_NO_SOLUTION", 6: "E_CAPACITY", 7: "E_NOMEM", 8: "E_BUFFER", 9: "E_DEVICE",
+    5: "E_NO_SOLUTION", 6: "E_CAPACITY", 7: "E_NOMEM", 8: "E_BUFFER", 9: "E_DEVICE", 10: "PENDING",
 }
 
 
@@ -73,6 +73,23 @@ class _PlanRequest(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("q_start", C.c_void_p), ("q_goal", C.c_void_p), ("params", PlanParams),
                 ("path_out", C.c_void_p), ("path_cap", C.c_int32), ("status", C.c_int32), ("path_len", C.c_int32),
                 ("cost", C.c_float), ("stats", _PlanStats)]
+
+
+class _ServerConfig(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("mem_budget_bytes", C.c_int64)]
+
+
+class _ServerResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("path_len", C.c_int32), ("cost", C.c_float), ("stats", _PlanStats),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("rejected", C.c_int64), ("queue_len", C.c_int32), ("running", C.c_int32),
+                ("max_queue_len", C.c_int32), ("max_running", C.c_int32), ("reserved_bytes", C.c_int64),
+                ("peak_reserved_bytes", C.c_int64), ("flushes", C.c_int64), ("launches", C.c_int64)]
 
 
 class _BatchStats(C.Structure):
@@ -152,6 +169,17 @@ def load_library():
     lib.mrpop_plan_params_default.restype = None
     lib.mrpop_plan.argtypes = [P, P, P, P, P, P, I32, P, P, P]
     lib.mrpop_plan_batch.argtypes = [P, P, I32, P]
+    lib.mrpop_server_create.argtypes = [P, P, P]
+    lib.mrpop_server_destroy.argtypes = [P]
+    lib.mrpop_server_destroy.restype = None
+    lib.mrpop_server_submit.argtypes = [P, P, P, P, P, P]
+    lib.mrpop_server_poll.argtypes = [P, I64, P]
+    lib.mrpop_server_wait.argtypes = [P, I64, C.c_double, P]
+    lib.mrpop_server_path.argtypes = [P, I64, P, I32]
+    lib.mrpop_server_release.argtypes = [P, I64]
+    lib.mrpop_server_get_stats.argtypes = [P, P]
+    lib.mrpop_server_clock.argtypes = [P]
+    lib.mrpop_server_clock.restype = C.c_double
     lib.mrpop_profile_enable.argtypes = [P, C.c_int]
     lib.mrpop_profile_read.argtypes = [P, P]
     _lib = lib
@@ -418,3 +446,79 @@ class Scene:
         """Host bool per composite state (True = collision-free)."""
         qd = self.ctx.to_device(q, _torch().float32).reshape(-1, self.dof)
         return self.validate_edges(qd, qd, 1.0).cpu().numpy().astype(bool)
+
+
+class Server:
+    """Continuous-batching planning server (mrpop_server_*): requests are
+    queued, admitted by slots and device memory, and run with their device
+    work merged; results are kept per ticket."""
+
+    def __init__(self, ctx: "Context", max_slots: int = 64, mem_budget_bytes: int = 0):
+        self.ctx = ctx
+        cfg = _ServerConfig(max_slots, mem_budget_bytes)
+        h = C.c_void_p()
+        ctx.check(ctx._lib.mrpop_server_create(ctx.handle, C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._dof = {}
+
+    def submit(self, scene: "Scene", q_start, q_goal, **params) -> int:
+        lib = self.ctx._lib
+        pp = PlanParams()
+        lib.mrpop_plan_params_default(C.byref(pp))
+        for k, v in params.items():
+            if not hasattr(pp, k):
+                raise KeyError(k)
+            setattr(pp, k, v)
+        qs = np.ascontiguousarray(q_start, np.float32).reshape(scene.dof)
+        qg = np.ascontiguousarray(q_goal, np.float32).reshape(scene.dof)
+        t = C.c_int64(0)
+        self.ctx.check(lib.mrpop_server_submit(self._h, scene.handle, qs.ctypes.data, qg.ctypes.data,
+                                               C.byref(pp), C.byref(t)))
+        self._dof[t.value] = scene.dof
+        return t.value
+
+    def _result(self, ticket: int, r: "_ServerResult") -> dict:
+        out = {k: getattr(r, k) for k, _ in _ServerResult._fields_ if k != "stats"}
+        out["status"] = STATUS_NAMES.get(r.status, str(r.status))
+        st = {k: getattr(r.stats, k) for k, _ in _PlanStats._fields_ if k != "costs"}
+        st["costs"] = list(r.stats.costs[:r.stats.n_costs])
+        out["stats"] = st
+        out["path"] = None
+        if r.status == 0:
+            path = np.zeros((max(1, r.path_len), self._dof[ticket]), np.float32)
+            self.ctx.check(self.ctx._lib.mrpop_server_path(self._h, ticket, path.ctypes.data, r.path_len))
+            out["path"] = path[:r.path_len]
+        return out
+
+    def poll(self, ticket: int) -> dict:
+        r = _ServerResult()
+        self.ctx.check(self.ctx._lib.mrpop_server_poll(self._h, ticket, C.byref(r)))
+        return self._result(ticket, r)
+
+    def wait(self, ticket: int, timeout_s: float = 60.0) -> dict:
+        r = _ServerResult()
+        self.ctx.check(self.ctx._lib.mrpop_server_wait(self._h, ticket, timeout_s, C.byref(r)))
+        return self._result(ticket, r)
+
+    def release(self, ticket: int) -> None:
+        self.ctx.check(self.ctx._lib.mrpop_server_release(self._h, ticket))
+        self._dof.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        self.ctx.check(self.ctx._lib.mrpop_server_get_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def clock(self) -> float:
+        return float(self.ctx._lib.mrpop_server_clock(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.ctx._lib.mrpop_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

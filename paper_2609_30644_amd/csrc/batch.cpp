@@ -67,58 +67,57 @@ struct HostBuf {
 
 }  // namespace
 
-struct BatchEngine::Impl {
+struct JobEngine::Impl {
   mrpop_ctx *ctx;
   hipStream_t s;
   std::mutex mu;
   std::condition_variable cv_main, cv_jobs;
   struct Slot {
     std::vector<Cmd> pending;
-    bool waiting = false, done = false, active = false;
+    bool used = false, running = false, waiting = false, finished = false;
+    std::thread th;
   };
-  std::vector<Slot> slots;
-  int n_active = 0, n_waiting = 0;
+  std::vector<Slot> slots;  // fixed capacity
+  int n_running = 0, n_waiting = 0, n_finished = 0;  // finished: ended, not yet reaped
   uint64_t generation = 0;
   hipError_t last_err = hipSuccess;
   // merge buffers
   HostBuf h_args;
   DevBuf d_args, seg_scratch;
   int64_t flushes = 0, launches = 0;
-  // batch limits
   static constexpr int kMaxPerLaunch = 65535;
 
-  explicit Impl(mrpop_ctx *c, hipStream_t st) : ctx(c), s(st) {}
-
+  Impl(mrpop_ctx *c, hipStream_t st, int cap) : ctx(c), s(st), slots(cap) {}
   hipError_t flush();
 };
 
 // Device work of one slot, queued for the next merged launch.
-class BatchExec : public Exec {
+class QueuedExec : public Exec {
  public:
-  BatchExec(BatchEngine::Impl *e, int k) : e_(e), k_(k) {}
+  QueuedExec(JobEngine::Impl *e, int k) : e_(e), k_(k) {}
   hipError_t submit(const Cmd &c) override {
     e_->slots[k_].pending.push_back(c);
     return hipSuccess;
   }
   hipError_t sync() override {
     std::unique_lock<std::mutex> lk(e_->mu);
-    BatchEngine::Impl::Slot &sl = e_->slots[k_];
-    sl.waiting = true;
+    e_->slots[k_].waiting = true;
     ++e_->n_waiting;
     const uint64_t gen = e_->generation;
-    e_->cv_main.notify_one();
+    e_->cv_main.notify_all();
     e_->cv_jobs.wait(lk, [&] { return e_->generation != gen; });
     return e_->last_err;
   }
 
  private:
-  BatchEngine::Impl *e_;
+  JobEngine::Impl *e_;
   int k_;
 };
 
-hipError_t BatchEngine::Impl::flush() {
+hipError_t JobEngine::Impl::flush() {
   const int K = (int)slots.size();
   std::vector<size_t> head(K, 0);
+  last_err = hipSuccess;
   // plan every layer: (op, records), packing argument records into h_args
   struct Launch {
     Op op;
@@ -224,63 +223,104 @@ hipError_t BatchEngine::Impl::flush() {
   return hipStreamSynchronize(s);
 }
 
-BatchEngine::BatchEngine(mrpop_ctx *ctx, hipStream_t s) : impl_(new Impl(ctx, s)) {}
-BatchEngine::~BatchEngine() { delete impl_; }
+JobEngine::JobEngine(mrpop_ctx *ctx, hipStream_t s, int capacity) : impl_(new Impl(ctx, s, std::max(1, capacity))) {}
 
-int64_t BatchEngine::flushes() const { return impl_->flushes; }
-int64_t BatchEngine::launches() const { return impl_->launches; }
+JobEngine::~JobEngine() {
+  for (auto &sl : impl_->slots)
+    if (sl.th.joinable()) sl.th.join();
+  delete impl_;
+}
 
-void BatchEngine::run(std::vector<PlanJob *> &jobs, std::vector<mrpop_status> &status) {
+int JobEngine::start(PlanJob *job, std::function<void(int, mrpop_status)> on_done) {
   Impl &I = *impl_;
-  const int K = (int)jobs.size();
-  I.slots.assign(K, Impl::Slot());
-  status.assign(K, MRPOP_OK);
-  I.n_active = 0;
+  std::lock_guard<std::mutex> lk(I.mu);
+  int k = -1;
+  for (int i = 0; i < (int)I.slots.size(); ++i)
+    if (!I.slots[i].used) {
+      k = i;
+      break;
+    }
+  if (k < 0) return -1;
+  Impl::Slot &sl = I.slots[k];
+  sl.used = true;
+  sl.running = true;
+  sl.finished = false;
+  sl.waiting = false;
+  sl.pending.clear();
+  ++I.n_running;
+  const int dev = I.ctx->device;
+  sl.th = std::thread([&I, k, job, on_done, dev] {
+    (void)hipSetDevice(dev);
+    QueuedExec ex(&I, k);
+    const mrpop_status st = job->run(ex);
+    std::lock_guard<std::mutex> g(I.mu);
+    Impl::Slot &me = I.slots[k];
+    me.pending.clear();
+    me.running = false;
+    me.finished = true;
+    --I.n_running;
+    ++I.n_finished;
+    if (on_done) on_done(k, st);
+    I.cv_main.notify_all();
+  });
+  return k;
+}
+
+bool JobEngine::step(const std::function<bool()> &wake) {
+  Impl &I = *impl_;
+  std::unique_lock<std::mutex> lk(I.mu);
+  I.cv_main.wait(lk, [&] {
+    return I.n_waiting == I.n_running && (I.n_running > 0 || I.n_finished > 0 || wake());
+  });
+  if (I.n_finished > 0 || I.n_running == 0) return false;  // jobs to reap first (or nothing to run)
+  // every running job waits for its device work: merge and launch it (the
+  // jobs stay blocked, so their queues can be read without the lock)
+  lk.unlock();
+  const hipError_t e = I.flush();
+  lk.lock();
+  I.last_err = e;
+  for (auto &sl : I.slots) {
+    sl.pending.clear();
+    sl.waiting = false;
+  }
   I.n_waiting = 0;
-  I.last_err = hipSuccess;
-  std::vector<std::thread> threads;
-  threads.reserve(K);
+  ++I.generation;
+  I.cv_jobs.notify_all();
+  return true;
+}
+
+void JobEngine::notify() {
+  std::lock_guard<std::mutex> lk(impl_->mu);
+  impl_->cv_main.notify_all();
+}
+
+std::vector<int> JobEngine::reap() {
+  Impl &I = *impl_;
+  std::vector<int> done;
+  std::vector<std::thread> ths;
   {
     std::lock_guard<std::mutex> lk(I.mu);
-    for (int k = 0; k < K; ++k)
-      if (jobs[k]) {
-        I.slots[k].active = true;
-        ++I.n_active;
+    for (int k = 0; k < (int)I.slots.size(); ++k)
+      if (I.slots[k].used && I.slots[k].finished) {
+        ths.push_back(std::move(I.slots[k].th));
+        I.slots[k].used = false;
+        I.slots[k].finished = false;
+        --I.n_finished;
+        done.push_back(k);
       }
   }
-  for (int k = 0; k < K; ++k) {
-    if (!jobs[k]) continue;
-    threads.emplace_back([&, k] {
-      const int dev = I.ctx->device;
-      (void)hipSetDevice(dev);
-      BatchExec ex(&I, k);
-      const mrpop_status st = jobs[k]->run(ex);
-      std::lock_guard<std::mutex> lk(I.mu);
-      status[k] = st;
-      I.slots[k].done = true;
-      I.slots[k].pending.clear();
-      --I.n_active;
-      I.cv_main.notify_one();
-    });
-  }
-  std::unique_lock<std::mutex> lk(I.mu);
-  for (;;) {
-    I.cv_main.wait(lk, [&] { return I.n_active == 0 || I.n_waiting == I.n_active; });
-    if (I.n_active == 0) break;
-    // every unfinished instance waits for its work: merge and launch it
-    const hipError_t e = I.flush();
-    if (e != hipSuccess) I.last_err = e;
-    for (auto &sl : I.slots) {
-      sl.pending.clear();
-      sl.waiting = false;
-    }
-    I.n_waiting = 0;
-    ++I.generation;
-    I.cv_jobs.notify_all();
-  }
-  lk.unlock();
-  for (auto &t : threads) t.join();
+  for (auto &t : ths) t.join();
+  return done;
 }
+
+int JobEngine::running() const {
+  std::lock_guard<std::mutex> lk(impl_->mu);
+  return impl_->n_running;
+}
+int JobEngine::capacity() const { return (int)impl_->slots.size(); }
+int64_t JobEngine::flushes() const { return impl_->flushes; }
+int64_t JobEngine::launches() const { return impl_->launches; }
+std::mutex &JobEngine::mutex() { return impl_->mu; }
 
 }  // namespace mrpop
 
@@ -309,9 +349,15 @@ mrpop_status mrpop_plan_batch(mrpop_ctx *ctx, mrpop_plan_request *reqs, int32_t 
     q.status = jobs[i]->prepare(ctx, q.scene, q.q_start, q.q_goal, q.params);
     if (q.status == MRPOP_OK) run_jobs[i] = jobs[i].get();
   }
-  std::vector<mrpop_status> st;
-  BatchEngine eng(ctx, nullptr);
-  eng.run(run_jobs, st);
+  std::vector<mrpop_status> st(n, MRPOP_OK);
+  JobEngine eng(ctx, nullptr, std::max(1, n));
+  for (int i = 0; i < n; ++i)
+    if (run_jobs[i]) eng.start(run_jobs[i], [&st, i](int, mrpop_status s) { st[i] = s; });
+  for (;;) {
+    eng.reap();
+    if (eng.running() == 0) break;
+    eng.step([] { return false; });
+  }
   int solved = 0;
   for (int i = 0; i < n; ++i) {
     if (!run_jobs[i]) continue;

@@ -34,6 +34,9 @@ class PlanJob {
   int dof() const { return D_; }
   // Device bytes held by the instance (arena and sub-scenes).
   size_t device_bytes() const { return device_bytes_; }
+  // Device bytes an instance of `scene` with `params` would hold (an upper
+  // bound: the sub-scenes are counted at the size of the whole scene).
+  static size_t device_bytes_for(const mrpop_scene *scene, const mrpop_plan_params &params);
 
  private:
   mrpop_status fail_(mrpop_status s, const std::string &m) {
@@ -48,13 +51,15 @@ class PlanJob {
                          uint8_t *out, uint64_t *counters);
   mrpop_status copy_(Exec &ex, void *dst, const void *src, size_t bytes);
   mrpop_status roadmap_(Exec &ex, int it);
+  void set_sizes_(const mrpop_scene *scene, const mrpop_plan_params &P);
+  size_t plan_arena_(void *base);  // assigns the arena's arrays (base may be null); returns its size
   double elapsed_() const;
   bool out_of_time_() const;
 
   mrpop_ctx *ctx_ = nullptr;
   const mrpop_scene *scene_ = nullptr;
   mrpop_plan_params P_{};
-  int R_ = 0, D_ = 0, PC_ = 0;
+  int R_ = 0, D_ = 0, PC_ = 0, max_nj_ = 0;
   int rm_cap_ = 0, edge_cap_ = 0, col_cap_ = 0, cand_batch_ = 0, pair_cap_ = 0, tcap_ = 0, path_max_ = 0;
   double t_start_ = 0.0;
   std::string err_;

@@ -102,27 +102,10 @@ PlanJob::~PlanJob() {
 double PlanJob::elapsed_() const { return now_s() - t_start_; }
 bool PlanJob::out_of_time_() const { return P_.time_budget_s > 0 && elapsed_() >= P_.time_budget_s; }
 
-mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
-                              const mrpop_plan_params &P) {
-  ctx_ = ctx;
-  scene_ = scene;
-  P_ = P;
-  if (P.candidates < 1 || P.candidates > 4096 || !(P.resolution > 0.f) || !std::isfinite(P.resolution) ||
-      P.max_rounds < 1 || P.max_iterations < 1 || P.max_growth_rounds < 1 || P.n_roadmap < 1 ||
-      P.max_tree_nodes < 2 || P.max_roadmap_nodes < 4 || !(P.delta > 0.f) || P.time_budget_s < 0 ||
-      std::isnan(P.warm_cost))
-    return fail_(MRPOP_E_INVALID_ARG, "plan: parameter out of range");
+void PlanJob::set_sizes_(const mrpop_scene *scene, const mrpop_plan_params &P) {
   R_ = scene->n_robots;
   D_ = scene->dof;
   PC_ = P.candidates;
-  for (int j = 0; j < D_; ++j)
-    if (!std::isfinite(q_start[j]) || !std::isfinite(q_goal[j]))
-      return fail_(MRPOP_E_NONFINITE, "plan: non-finite start or goal");
-  std::memset(&st_, 0, sizeof(st_));
-  st_.time_to_first_s = -1.0;
-  st_.first_round = -1;
-  c_best_ = P.warm_cost;
-
   rm_cap_ = P.max_roadmap_nodes;
   edge_cap_ = rm_cap_ * 32;
   col_cap_ = 2 * edge_cap_;
@@ -130,10 +113,12 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   pair_cap_ = P.n_roadmap * rm_cap_;
   tcap_ = P.max_tree_nodes;
   path_max_ = 16384;
-  int max_nj = 0;
-  for (int r = 0; r < R_; ++r) max_nj = std::max(max_nj, scene->nj[r]);
-  const int R = R_, D = D_, PC = PC_;
+  max_nj_ = 0;
+  for (int r = 0; r < R_; ++r) max_nj_ = std::max(max_nj_, scene->nj[r]);
+}
 
+size_t PlanJob::plan_arena_(void *base) {
+  const int R = R_, D = D_, PC = PC_, max_nj = max_nj_;
   ArenaPlan ar;
   ar.add(&qs_, D);
   ar.add(&qg_, D);
@@ -183,14 +168,48 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   ar.add(&path_len_d_, 1);
   ar.add(&d_nj_, R);
   ar.add(&d_qoff_, R);
+  if (base) ar.assign(base);
+  return ar.total();
+}
+
+size_t PlanJob::device_bytes_for(const mrpop_scene *scene, const mrpop_plan_params &params) {
+  PlanJob j;
+  j.set_sizes_(scene, params);
+  return j.plan_arena_(nullptr) + (size_t)scene->n_robots * scene->blob_bytes;
+}
+
+mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
+                              const mrpop_plan_params &P) {
+  ctx_ = ctx;
+  scene_ = scene;
+  P_ = P;
+  if (P.candidates < 1 || P.candidates > 4096 || !(P.resolution > 0.f) || !std::isfinite(P.resolution) ||
+      P.max_rounds < 1 || P.max_iterations < 1 || P.max_growth_rounds < 1 || P.n_roadmap < 1 ||
+      P.max_tree_nodes < 2 || P.max_roadmap_nodes < 4 || !(P.delta > 0.f) || P.time_budget_s < 0 ||
+      std::isnan(P.warm_cost))
+    return fail_(MRPOP_E_INVALID_ARG, "plan: parameter out of range");
+  R_ = scene->n_robots;
+  D_ = scene->dof;
+  PC_ = P.candidates;
+  for (int j = 0; j < D_; ++j)
+    if (!std::isfinite(q_start[j]) || !std::isfinite(q_goal[j]))
+      return fail_(MRPOP_E_NONFINITE, "plan: non-finite start or goal");
+  std::memset(&st_, 0, sizeof(st_));
+  st_.time_to_first_s = -1.0;
+  st_.first_round = -1;
+  c_best_ = P.warm_cost;
+
+  set_sizes_(scene, P);
+  const int R = R_, D = D_;
+  const size_t arena_bytes = plan_arena_(nullptr);
   hipError_t e = hipSetDevice(ctx->device);
-  if (e == hipSuccess) e = hipMalloc(&arena_, ar.total());
+  if (e == hipSuccess) e = hipMalloc(&arena_, arena_bytes);
   if (e != hipSuccess) {
     arena_ = nullptr;
     return e == hipErrorOutOfMemory ? fail_(MRPOP_E_NOMEM, "plan: device memory") : hip_fail_(e, "hipMalloc(plan)");
   }
-  ar.assign(arena_);
-  device_bytes_ = ar.total();
+  plan_arena_(arena_);
+  device_bytes_ = arena_bytes;
   if ((e = hipHostMalloc((void **)&pin_, sizeof(Pinned))) != hipSuccess) return hip_fail_(e, "hipHostMalloc");
   const size_t up_floats = 2 * (size_t)D + (size_t)R * 2 * kRmStride;
   if ((e = hipHostMalloc((void **)&upload_, sizeof(float) * up_floats)) != hipSuccess)

@@ -150,6 +150,59 @@ def batched_vs_plain(ctx, n_inst: int) -> dict:
             "merged_launches": bst["launches"], "flushes": bst["flushes"], "params": BATCH_PLAN}
 
 
+SERVE_FIXTURE = os.path.join(ROOT, "tests", "golden", "c5_served.json")
+# Per-query settings of the served workload: first solution within a round
+# budget and a 2 s deadline (counted from admission).
+SERVE_PLAN = dict(candidates=64, n_roadmap=16, delta=3.0, resolution=0.05, max_rounds=100, max_iterations=1,
+                  stop_at_first=1, max_tree_nodes=8192, max_roadmap_nodes=2048, time_budget_s=2.0)
+
+
+def served(ctx, rate_hz: float, duration_s: float, slots: int, mem_gb: float) -> dict:
+    """Poisson arrivals of queries (2-16 arms, 32-512 obstacles) submitted to
+    a continuous-batching server on the wall clock; latency is arrival ->
+    result on the server's clock."""
+    import paper_2609_30644_amd as M
+    import workloads as W
+    d = json.load(open(SERVE_FIXTURE))
+    probs = []
+    for x in d["instances"]:
+        R = x["n_robots"]
+        sc = W.Scene([W.panda_like(59)] * R, np.array(x["bases"], np.float32).reshape(R, 12),
+                     np.array(x["env_spheres"], np.float32).reshape(-1, 4),
+                     np.array(x["env_boxes"], np.float32).reshape(-1, 6))
+        probs.append((M.Scene(ctx, sc), np.array(x["q_start"], np.float32), np.array(x["q_goal"], np.float32)))
+    arrivals = W.poisson_arrivals(rate_hz, duration_s, 0)
+    srv = M.Server(ctx, max_slots=slots, mem_budget_bytes=int(mem_gb * (1 << 30)))
+    # warm-up request (kernel loading), not counted
+    s0, a0, b0 = probs[0]
+    srv.wait(srv.submit(s0, a0, b0, **dict(SERVE_PLAN, seed=10 ** 6)), 60.0)
+    t0 = srv.clock()
+    tickets = []
+    for i, a in enumerate(arrivals):
+        while srv.clock() - t0 < a:
+            time.sleep(0.0002)
+        s, qs, qg = probs[i % len(probs)]
+        tickets.append(srv.submit(s, qs, qg, **dict(SERVE_PLAN, seed=i)))
+    res = [srv.wait(t, 600.0) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    done = [r for r in res if r["status"] != "PENDING"]
+    lat = np.array([r["t_done"] - (t0 + a) for r, a in zip(res, arrivals) if r["status"] != "PENDING"])
+    queue = np.array([r["t_admit"] - (t0 + a) for r, a in zip(res, arrivals) if r["status"] != "PENDING"])
+    span = max(r["t_done"] for r in done) - t0 if done else float("nan")
+    states = sum(r["stats"]["edge_states"] + r["stats"]["roadmap_edge_states"] for r in done)
+    return {"rate_hz": rate_hz, "duration_s": duration_s, "queries": len(tickets), "completed": len(done),
+            "solved": sum(r["status"] == "OK" for r in done),
+            "statuses": {k: sum(r["status"] == k for r in done) for k in sorted(set(r["status"] for r in done))},
+            "latency_p50_ms": float(np.percentile(lat, 50)) * 1e3, "latency_p99_ms": float(np.percentile(lat, 99)) * 1e3,
+            "queue_wait_p50_ms": float(np.percentile(queue, 50)) * 1e3,
+            "queries_per_s": len(done) / span, "edge_states_per_s": states / span,
+            "slots": slots, "mem_budget_gb": mem_gb, "max_running": st["max_running"],
+            "max_queue_len": st["max_queue_len"], "peak_reserved_gb": st["peak_reserved_bytes"] / (1 << 30),
+            "rejected": st["rejected"], "merged_launches": st["launches"], "flushes": st["flushes"],
+            "params": SERVE_PLAN}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +213,10 @@ def main():
     ap.add_argument("--no-plan", action="store_true", help="validation batches only")
     ap.add_argument("--batch-instances", type=int, default=64,
                     help="instances of the batched-vs-plain comparison (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the served run (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of the served run")
+    ap.add_argument("--serve-slots", type=int, default=128)
+    ap.add_argument("--serve-mem-gb", type=float, default=96.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -241,6 +298,9 @@ def main():
     if args.batch_instances > 0:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         line["batched"] = batched_vs_plain(ctx, args.batch_instances)
+    if args.serve_seconds > 0:
+        print("[bench] served", file=sys.stderr, flush=True)
+        line["served"] = served(ctx, args.serve_rate, args.serve_seconds, args.serve_slots, args.serve_mem_gb)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(scene, batches, res, args.cpu_seconds)

@@ -318,6 +318,12 @@ int JobEngine::running() const {
   return impl_->n_running;
 }
 int JobEngine::capacity() const { return (int)impl_->slots.size(); }
+int JobEngine::free_slots() const {
+  std::lock_guard<std::mutex> lk(impl_->mu);
+  int n = 0;
+  for (const auto &sl : impl_->slots) n += sl.used ? 0 : 1;
+  return n;
+}
 int64_t JobEngine::flushes() const { return impl_->flushes; }
 int64_t JobEngine::launches() const { return impl_->launches; }
 std::mutex &JobEngine::mutex() { return impl_->mu; }

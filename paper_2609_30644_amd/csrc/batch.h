@@ -37,6 +37,7 @@ class JobEngine {
   std::vector<int> reap();
   int running() const;
   int capacity() const;
+  int free_slots() const;  // slots neither running nor holding an unreaped job
   int64_t flushes() const;   // merged submissions so far
   int64_t launches() const;  // kernel launches they made
   // The engine's lock, for state shared with on_done callbacks.

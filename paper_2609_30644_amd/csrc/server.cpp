@@ -137,7 +137,7 @@ void mrpop_server::run() {
           cv_done.notify_all();
           continue;
         }
-        if (eng->running() >= eng->capacity()) break;
+        if (eng->free_slots() == 0) break;
         if (budget && reserved + need > budget) break;
         rq = std::move(queue.front());
         queue.pop_front();
@@ -166,13 +166,12 @@ void mrpop_server::run() {
         self->slots[slot].status = s;
         self->slots[slot].t_done = self->clock();
       });
-      if (k < 0) {  // cannot happen: a slot was free
-        Result res;
-        std::memset(&res.r, 0, sizeof(res.r));
-        res.r.status = MRPOP_E_CAPACITY;
-        res.r.cost = INFINITY;
-        finish(rq.ticket, res);
-        continue;
+      if (k < 0) {  // no free slot after all (only this thread takes slots): queue it again
+        std::lock_guard<std::mutex> lk(qmu);
+        --st.admitted;
+        queue.push_front(std::move(rq));
+        ++queued;
+        break;
       }
       Slot &sl = slots[k];
       sl.job = std::move(job);

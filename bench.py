@@ -42,7 +42,7 @@ F_JOINT, F_XFORM, F_SS, F_SB = 48, 18, 10, 17
 # Planner settings of the benchmark step (delta: per-arm roadmap radius in
 # rad; P = candidates per round; the plan stops after max_iterations outer
 # iterations or max_rounds rounds).
-PLAN = dict(candidates=128, n_roadmap=32, delta=3.0, max_rounds=150, max_iterations=4)
+PLAN = dict(candidates=512, n_roadmap=32, delta=3.0, max_rounds=150, max_iterations=4)
 
 
 def load_workload():

@@ -135,12 +135,27 @@ hipError_t JobEngine::Impl::flush() {
     return off;
   };
   for (;;) {
-    // next command of every slot, grouped by kind (kinds in enum order)
+    // next command of every slot, grouped by kind (kinds in enum order); a
+    // slot whose next command is a validation contributes its whole run of
+    // consecutive validations (independent by contract)
     bool any = false;
     std::vector<std::vector<int>> by_op(kNumOps);
+    std::vector<int> vals;  // (slot, command index) pairs of this layer's validations
     for (int k = 0; k < K; ++k)
       if (head[k] < slots[k].pending.size()) {
-        by_op[(int)slots[k].pending[head[k]].op].push_back(k);
+        const Op op = slots[k].pending[head[k]].op;
+        if (op == Op::Validate) {
+          size_t h = head[k];
+          while (h < slots[k].pending.size() && slots[k].pending[h].op == Op::Validate) {
+            vals.push_back(k);
+            vals.push_back((int)h);
+            ++h;
+          }
+          head[k] = h - 1;  // advanced past the run below
+          by_op[(int)op].push_back(k);
+        } else {
+          by_op[(int)op].push_back(k);
+        }
         any = true;
       }
     if (!any) break;
@@ -150,19 +165,26 @@ hipError_t JobEngine::Impl::flush() {
         const size_t c1 = std::min(ks.size(), c0 + (size_t)kMaxPerLaunch);
         const Op op = (Op)o;
         if (op == Op::Validate) {
+          if (c0 > 0) break;  // all of the layer's validations go into one launch below
+          std::vector<const ValidateReq *> reqs;
+          for (size_t i = 0; i < vals.size(); i += 2) {
+            const ValidateReq &v = slots[vals[i]].pending[vals[i + 1]].val;
+            if (v.n > 0) reqs.push_back(&v);
+          }
           std::vector<ValSeg> segs;
           int64_t flat = 0;
           int r_max = 1;
-          for (size_t i = c0; i < c1; ++i) {
-            const ValidateReq &v = slots[ks[i]].pending[head[ks[i]]].val;
-            r_max = std::max(r_max, (int)v.scene->n_robots);
+          for (const ValidateReq *v : reqs) {
+            r_max = std::max(r_max, (int)v->scene->n_robots);
+            flat += v->n;
           }
-          for (size_t i = c0; i < c1; ++i) flat += slots[ks[i]].pending[head[ks[i]]].val.n;
+          if (reqs.empty()) continue;
+          if ((int64_t)reqs.size() > kMaxPerLaunch) return hipErrorInvalidValue;
           int W = 0, cache = 0;
           seg_shape(r_max, flat, &W, &cache);
           flat = 0;
-          for (size_t i = c0; i < c1; ++i) {
-            const ValidateReq &v = slots[ks[i]].pending[head[ks[i]]].val;
+          for (const ValidateReq *vp : reqs) {
+            const ValidateReq &v = *vp;
             ValSeg g;
             std::memset(&g, 0, sizeof(g));
             g.sc = *v.scene;

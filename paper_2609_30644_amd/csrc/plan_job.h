@@ -74,21 +74,25 @@ class PlanJob {
   void *arena_ = nullptr;
   float *qs_, *qg_, *rm_V_, *cand_, *pair_qa_, *pair_qb_, *tq_[2], *tg_[2], *q_rand_, *c_rand_, *q_new_, *g_new_,
       *ea_, *eb_, *budget_, *ca_, *cb_, *path_d_;
-  int32_t *rm_rowptr_, *rm_col_, *rm_edges_, *rm_nv_, *rm_ne_, *pair_ids_, *pair_count_, *taken_, *connected_, *deg_,
-      *level_, *tvid_[2], *tpar_[2], *tn_[2], *near_idx_, *vid_new_, *ins_idx_, *conn_idx_, *path_len_d_, *d_nj_,
-      *d_qoff_;
+  // per arm r: cand_ [r][cand_batch][kRmStride], cand_valid_ [r][cand_batch],
+  // rm_i_ [r][kRmInts] (taken, pair count, pair count when writing,
+  // connected), uf_ [r][rm_cap] union-find parents, cnt_ [2 + r][16]
+  int32_t *rm_rowptr_, *rm_col_, *rm_edges_, *rm_nv_, *rm_ne_, *pair_ids_, *rm_i_, *uf_, *deg_, *tvid_[2],
+      *tpar_[2], *tn_[2], *near_idx_, *vid_new_, *ins_idx_, *conn_idx_, *path_len_d_, *d_nj_, *d_qoff_;
   uint8_t *cand_valid_, *pair_valid_, *alive_, *valid_, *cvalid_;
-  uint64_t *cnt_;  // [3][16]: counters of the extension, connection and roadmap validations
+  uint64_t *cnt_;  // [2 + R][16]: counters of the extension, connection and per-arm roadmap validations
   RoundStatus *status_;
+  static constexpr int kRmInts = 4;
 
   // pinned host memory (device-visible): uploads, and what comes back
   struct Pinned {
     RoundStatus status;
     int32_t ints[4];
-    uint64_t cnt[2];
     uint8_t valid2[8];
   };
   Pinned *pin_ = nullptr;
+  int32_t *pin_rm_ = nullptr;   // [R][kRmInts + 1] (the + 1: vertex count)
+  uint64_t *pin_cnt_ = nullptr; // [R][2]
   float *upload_ = nullptr;  // qs, qg, roadmap seeds [R][2][kRmStride]
   int32_t *upload_i_ = nullptr;  // nj, q_off
   float *pin_path_ = nullptr;

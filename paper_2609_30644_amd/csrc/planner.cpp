@@ -64,29 +64,115 @@ struct ArenaPlan {
 
 namespace mrpop {
 
-// Device work launched at once on one stream.
+// Device work launched at once on one stream.  Consecutive validations are
+// held back and launched together (one many-scene launch) when the next
+// other command arrives or at sync(): they are independent by contract.
 class PlainExec : public Exec {
  public:
   PlainExec(mrpop_ctx *ctx, hipStream_t s) : ctx_(ctx), s_(s) {}
+  ~PlainExec() override {
+    for (void *p : staging_) (void)hipHostFree(p);
+    if (d_segs_) (void)hipFree(d_segs_);
+    if (seg_ws_) (void)hipFree(seg_ws_);
+  }
   hipError_t submit(const Cmd &c) override {
     if (c.op == Op::Validate) {
-      const ValidateReq &v = c.val;
-      if (v.n <= 0) return hipSuccess;
-      void *base = nullptr;
-      if (scratch(ctx_, 1, validate_scratch_bytes(v.n), &base) != MRPOP_OK) return hipErrorOutOfMemory;
-      ValidateScratch ws = validate_scratch_layout(base, v.n);
-      ws.counters = v.counters;
-      return launch_validate(*v.scene, v.qa, v.qb, v.n, v.res, nullptr, v.out, ws, s_, profile_slot(ctx_),
-                             ctx_->profiling ? ctx_->prof_totals : nullptr, &ctx_->last_grid, &ctx_->last_block);
+      if (c.val.n > 0) val_.push_back(c.val);
+      return hipSuccess;
     }
+    hipError_t e = flush_validations();
+    if (e != hipSuccess) return e;
     if (c.op == Op::Copy) return hipMemcpyAsync(c.copy.dst, c.copy.src, c.copy.bytes, hipMemcpyDefault, s_);
     return launch_op(c.op, c.args(), s_);
   }
-  hipError_t sync() override { return hipStreamSynchronize(s_); }
+  hipError_t sync() override {
+    hipError_t e = flush_validations();
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s_);
+    used_ = 0;  // every staged upload has completed
+    return e;
+  }
 
  private:
+  hipError_t flush_validations() {
+    if (val_.empty()) return hipSuccess;
+    std::vector<ValidateReq> v;
+    v.swap(val_);
+    if (v.size() == 1) {
+      void *base = nullptr;
+      if (scratch(ctx_, 1, validate_scratch_bytes(v[0].n), &base) != MRPOP_OK) return hipErrorOutOfMemory;
+      ValidateScratch ws = validate_scratch_layout(base, v[0].n);
+      ws.counters = v[0].counters;
+      return launch_validate(*v[0].scene, v[0].qa, v[0].qb, v[0].n, v[0].res, nullptr, v[0].out, ws, s_,
+                             profile_slot(ctx_), ctx_->profiling ? ctx_->prof_totals : nullptr, &ctx_->last_grid,
+                             &ctx_->last_block);
+    }
+    int r_max = 1;
+    int64_t flat = 0;
+    for (const ValidateReq &q : v) {
+      r_max = std::max(r_max, (int)q.scene->n_robots);
+      flat += q.n;
+    }
+    int W = 0, cache = 0;
+    seg_shape(r_max, flat, &W, &cache);
+    const size_t bytes = sizeof(ValSeg) * v.size();
+    hipError_t e;
+    if (used_ == staging_.size() || stage_bytes_ < bytes) {
+      if (stage_bytes_ < bytes) {  // all staging buffers grow together (only between syncs if in use)
+        if (used_ > 0 && (e = hipStreamSynchronize(s_)) != hipSuccess) return e;
+        for (void *p : staging_) (void)hipHostFree(p);
+        staging_.clear();
+        used_ = 0;
+        stage_bytes_ = std::max(bytes, 2 * stage_bytes_);
+      }
+      void *p = nullptr;
+      if ((e = hipHostMalloc(&p, stage_bytes_)) != hipSuccess) return e;
+      staging_.push_back(p);
+    }
+    ValSeg *h = (ValSeg *)staging_[used_++];
+    int64_t e0 = 0;
+    for (size_t i = 0; i < v.size(); ++i) {
+      ValSeg &g = h[i];
+      std::memset(&g, 0, sizeof(g));
+      g.sc = *v[i].scene;
+      g.qa = v[i].qa;
+      g.qb = v[i].qb;
+      g.edge0 = e0;
+      g.n_edges = v[i].n;
+      g.res = v[i].res;
+      g.S = seg_link_split(v[i].scene->n_robots, W);
+      g.out = v[i].out;
+      g.counters = v[i].counters;
+      e0 += v[i].n;
+    }
+    if (d_segs_bytes_ < bytes) {
+      if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
+      if (d_segs_) (void)hipFree(d_segs_);
+      d_segs_ = nullptr;
+      d_segs_bytes_ = std::max(bytes, 2 * d_segs_bytes_);
+      if ((e = hipMalloc(&d_segs_, d_segs_bytes_)) != hipSuccess) return e;
+    }
+    const size_t ws_bytes = seg_scratch_bytes(flat);
+    if (seg_ws_bytes_ < ws_bytes) {
+      if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
+      if (seg_ws_) (void)hipFree(seg_ws_);
+      seg_ws_ = nullptr;
+      seg_ws_bytes_ = std::max(ws_bytes, 2 * seg_ws_bytes_);
+      if ((e = hipMalloc(&seg_ws_, seg_ws_bytes_)) != hipSuccess) return e;
+    }
+    if ((e = hipMemcpyAsync(d_segs_, h, bytes, hipMemcpyHostToDevice, s_)) != hipSuccess) return e;
+    return launch_validate_segments((ValSeg *)d_segs_, (int)v.size(), r_max, flat, seg_scratch_layout(seg_ws_, flat),
+                                    s_, profile_slot(ctx_), ctx_->profiling ? ctx_->prof_totals : nullptr,
+                                    &ctx_->last_grid, &ctx_->last_block);
+  }
+
   mrpop_ctx *ctx_;
   hipStream_t s_;
+  std::vector<ValidateReq> val_;
+  std::vector<void *> staging_;  // pinned uploads of segment tables, free again after sync()
+  size_t used_ = 0, stage_bytes_ = 0;
+  void *d_segs_ = nullptr, *seg_ws_ = nullptr;
+  size_t d_segs_bytes_ = 0, seg_ws_bytes_ = 0;
 };
 
 PlanJob::~PlanJob() {
@@ -97,6 +183,8 @@ PlanJob::~PlanJob() {
   if (upload_) (void)hipHostFree(upload_);
   if (upload_i_) (void)hipHostFree(upload_i_);
   if (pin_path_) (void)hipHostFree(pin_path_);
+  if (pin_rm_) (void)hipHostFree(pin_rm_);
+  if (pin_cnt_) (void)hipHostFree(pin_cnt_);
 }
 
 double PlanJob::elapsed_() const { return now_s() - t_start_; }
@@ -128,17 +216,15 @@ size_t PlanJob::plan_arena_(void *base) {
   ar.add(&rm_edges_, (size_t)R * edge_cap_ * 2);
   ar.add(&rm_nv_, R);
   ar.add(&rm_ne_, R);
-  ar.add(&cand_, (size_t)cand_batch_ * kRmStride);
-  ar.add(&cand_valid_, cand_batch_);
+  ar.add(&cand_, (size_t)R * cand_batch_ * kRmStride);
+  ar.add(&cand_valid_, (size_t)R * cand_batch_);
   ar.add(&pair_ids_, (size_t)pair_cap_ * 2);
   ar.add(&pair_qa_, (size_t)pair_cap_ * max_nj);
   ar.add(&pair_qb_, (size_t)pair_cap_ * max_nj);
   ar.add(&pair_valid_, pair_cap_);
-  ar.add(&pair_count_, 1);
-  ar.add(&taken_, 1);
-  ar.add(&connected_, 1);
-  ar.add(&deg_, rm_cap_);
-  ar.add(&level_, rm_cap_);
+  ar.add(&rm_i_, (size_t)R * kRmInts);
+  ar.add(&uf_, (size_t)R * rm_cap_);
+  ar.add(&deg_, (size_t)R * rm_cap_);
   for (int t = 0; t < 2; ++t) {
     ar.add(&tq_[t], (size_t)D * tcap_);
     ar.add(&tg_[t], tcap_);
@@ -162,7 +248,7 @@ size_t PlanJob::plan_arena_(void *base) {
   ar.add(&ca_, (size_t)PC * D);
   ar.add(&cb_, (size_t)PC * D);
   ar.add(&cvalid_, PC);
-  ar.add(&cnt_, 3 * 16);
+  ar.add(&cnt_, (size_t)(2 + R) * 16);
   ar.add(&status_, 1);
   ar.add(&path_d_, (size_t)path_max_ * D);
   ar.add(&path_len_d_, 1);
@@ -185,8 +271,8 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   P_ = P;
   if (P.candidates < 1 || P.candidates > 4096 || !(P.resolution > 0.f) || !std::isfinite(P.resolution) ||
       P.max_rounds < 1 || P.max_iterations < 1 || P.max_growth_rounds < 1 || P.n_roadmap < 1 ||
-      P.max_tree_nodes < 2 || P.max_roadmap_nodes < 4 || !(P.delta > 0.f) || P.time_budget_s < 0 ||
-      std::isnan(P.warm_cost))
+      P.max_tree_nodes < 2 || P.max_roadmap_nodes < 4 || P.max_roadmap_nodes > kUfMaxVertices ||
+      !(P.delta > 0.f) || P.time_budget_s < 0 || std::isnan(P.warm_cost))
     return fail_(MRPOP_E_INVALID_ARG, "plan: parameter out of range");
   R_ = scene->n_robots;
   D_ = scene->dof;
@@ -211,10 +297,14 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   plan_arena_(arena_);
   device_bytes_ = arena_bytes;
   if ((e = hipHostMalloc((void **)&pin_, sizeof(Pinned))) != hipSuccess) return hip_fail_(e, "hipHostMalloc");
+  if ((e = hipHostMalloc((void **)&pin_rm_, sizeof(int32_t) * (size_t)R * (kRmInts + 1))) != hipSuccess)
+    return hip_fail_(e, "hipHostMalloc");
+  if ((e = hipHostMalloc((void **)&pin_cnt_, sizeof(uint64_t) * (size_t)R * 2)) != hipSuccess)
+    return hip_fail_(e, "hipHostMalloc");
   const size_t up_floats = 2 * (size_t)D + (size_t)R * 2 * kRmStride;
   if ((e = hipHostMalloc((void **)&upload_, sizeof(float) * up_floats)) != hipSuccess)
     return hip_fail_(e, "hipHostMalloc");
-  if ((e = hipHostMalloc((void **)&upload_i_, sizeof(int32_t) * (4 * (size_t)R + 2))) != hipSuccess)
+  if ((e = hipHostMalloc((void **)&upload_i_, sizeof(int32_t) * (4 * (size_t)R + 4))) != hipSuccess)
     return hip_fail_(e, "hipHostMalloc");
 
   h_qoff_.assign(R, 0);
@@ -240,6 +330,8 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
     upload_i_[2 * R + r] = 2;  // roadmap vertex counts
     upload_i_[3 * R + r] = 0;  // roadmap edge counts
   }
+  upload_i_[4 * R] = 0;  // union-find parents of vertices 0 and 1
+  upload_i_[4 * R + 1] = 1;
   arms_.assign(R, nullptr);
   for (int r = 0; r < R; ++r) {
     mrpop_status a = arm_scene(ctx, scene, r, &arms_[r]);
@@ -295,61 +387,114 @@ mrpop_status PlanJob::validate_(Exec &ex, const mrpop_scene *sc, const float *a,
     if (s_ != MRPOP_OK) return s_;  \
   } while (0)
 
-// ROADMAP (Alg. 2) for outer iteration `it`.
+// ROADMAP (Alg. 2) for outer iteration `it`.  Every arm still unconnected
+// grows in the same steps (its launches side by side, one host round trip per
+// step): free samples, counts of candidate pairs (new vertex, any vertex
+// within delta), then the pairs themselves, their single-arm validation and
+// the union of the components they join; connectivity of start and goal is
+// read from the union-find.  The adjacency used by the extension oracle is
+// rebuilt once at the end.
 mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
   const int R = R_;
-  std::vector<char> conn(R, 0);
+  std::vector<char> conn(R, 0), grew(R, 0);
+  std::vector<int> need(R, 0), n0(R, 0), np(R, 0), off(R, 0);
+  auto ri = [&](int r, int i) { return rm_i_ + (size_t)r * kRmInts + i; };
+  auto cand = [&](int r) { return cand_ + (size_t)r * cand_batch_ * kRmStride; };
+  auto candv = [&](int r) { return cand_valid_ + (size_t)r * cand_batch_; };
+  auto V = [&](int r) { return rm_V_ + (size_t)r * rm_cap_ * kRmStride; };
   for (int g = 0; g < P_.max_growth_rounds; ++g) {
-    bool all = true;
-    for (int r = 0; r < R; ++r) {
-      if (conn[r]) continue;
-      const int nj = h_nj_[r];
-      float *V = rm_V_ + (size_t)r * rm_cap_ * kRmStride;
-      const int n0 = rm_n_[r];
-      int need = std::min(P_.n_roadmap, rm_cap_ - n0);
-      if (need <= 0) st_.capacity_hit = 1;
-      for (int64_t j0 = 0; need > 0; j0 += cand_batch_) {
-        SUBMIT(Op::RmSample, rm_sample,
-               RmSampleArgs{cand_, cand_batch_, nj, scene_->dev.q_lo + h_qoff_[r], scene_->dev.q_hi + h_qoff_[r],
-                            roadmap_key(P_.seed, (uint64_t)it * 1024 + g, (uint64_t)r), j0});
-        TRY(validate_(ex, arms_[r], cand_, cand_, cand_batch_, 1.0f, cand_valid_, cnt_ + 32));
-        SUBMIT(Op::RmAccept, rm_accept,
-               RmAcceptArgs{cand_, cand_valid_, cand_batch_, nj, need, V, rm_nv_ + r, rm_cap_, taken_});
-        TRY(copy_(ex, &pin_->ints[0], taken_, sizeof(int32_t)));
-        SYNC();
-        need -= pin_->ints[0];
-        if (j0 > (int64_t)cand_batch_ * 64) break;  // the arm's free space is (nearly) empty
-      }
-      TRY(copy_(ex, &pin_->ints[0], rm_nv_ + r, sizeof(int32_t)));
-      SYNC();
-      rm_n_[r] = pin_->ints[0];
-      // candidate edges between the new vertices and all earlier ones
-      SUBMIT(Op::Fill, fill, FillArgs{(uint32_t *)pair_count_, 0u, 1});
-      SUBMIT(Op::RmPairs, rm_pairs,
-             RmPairsArgs{V, n0, rm_n_[r], nj, P_.delta, pair_count_, pair_cap_, pair_ids_, pair_qa_, pair_qb_});
-      TRY(copy_(ex, &pin_->ints[0], pair_count_, sizeof(int32_t)));
-      SYNC();
-      const int np = std::min(pin_->ints[0], pair_cap_);
-      if (pin_->ints[0] > pair_cap_) st_.capacity_hit = 1;
-      TRY(validate_(ex, arms_[r], pair_qa_, pair_qb_, np, P_.resolution, pair_valid_, cnt_ + 32));
-      if (np > 0)
-        SUBMIT(Op::RmAddEdges, rm_add_edges,
-               RmAddEdgesArgs{pair_ids_, pair_valid_, pair_count_, np, rm_edges_ + (size_t)r * edge_cap_ * 2,
-                              rm_ne_ + r, edge_cap_});
-      SUBMIT(Op::RmBfs, rm_bfs,
-             RmBfsArgs{rm_edges_ + (size_t)r * edge_cap_ * 2, rm_ne_ + r, edge_cap_, rm_n_[r],
-                       rm_rowptr_ + (size_t)r * (rm_cap_ + 1), rm_col_ + (size_t)r * col_cap_, col_cap_, deg_, level_,
-                       connected_});
-      TRY(copy_(ex, &pin_->ints[0], connected_, sizeof(int32_t)));
-      TRY(copy_(ex, &pin_->cnt[0], cnt_ + 32, 2 * sizeof(uint64_t)));
-      SYNC();
-      if (np > 0) st_.roadmap_edge_states += (int64_t)pin_->cnt[1];
-      conn[r] = (char)pin_->ints[0];
-      all = all && conn[r];
+    std::vector<int> todo;
+    for (int r = 0; r < R; ++r)
+      if (!conn[r]) todo.push_back(r);
+    if (todo.empty()) break;
+    // 1. n free samples per arm, drawn in batches (first free ones in draw order)
+    for (int r : todo) {
+      n0[r] = rm_n_[r];
+      need[r] = std::min(P_.n_roadmap, rm_cap_ - n0[r]);
+      if (need[r] <= 0) st_.capacity_hit = 1;
     }
+    for (int64_t j0 = 0;; j0 += cand_batch_) {
+      std::vector<int> act;
+      for (int r : todo)
+        if (need[r] > 0) act.push_back(r);
+      if (act.empty()) break;
+      for (int r : act)
+        SUBMIT(Op::RmSample, rm_sample,
+               RmSampleArgs{cand(r), cand_batch_, h_nj_[r], scene_->dev.q_lo + h_qoff_[r],
+                            scene_->dev.q_hi + h_qoff_[r], roadmap_key(P_.seed, (uint64_t)it * 1024 + g, (uint64_t)r),
+                            j0});
+      for (int r : act)  // consecutive validations: one launch over the arms
+        TRY(validate_(ex, arms_[r], cand(r), cand(r), cand_batch_, 1.0f, candv(r), cnt_ + (size_t)(2 + r) * 16));
+      for (int r : act) {
+        SUBMIT(Op::RmAccept, rm_accept,
+               RmAcceptArgs{cand(r), candv(r), cand_batch_, h_nj_[r], need[r], V(r), rm_nv_ + r, rm_cap_, ri(r, 0),
+                            uf_ + (size_t)r * rm_cap_});
+        TRY(copy_(ex, pin_rm_ + (size_t)r * (kRmInts + 1), ri(r, 0), sizeof(int32_t)));
+        TRY(copy_(ex, pin_rm_ + (size_t)r * (kRmInts + 1) + kRmInts, rm_nv_ + r, sizeof(int32_t)));
+      }
+      SYNC();
+      for (int r : act) {
+        need[r] -= pin_rm_[(size_t)r * (kRmInts + 1)];
+        rm_n_[r] = pin_rm_[(size_t)r * (kRmInts + 1) + kRmInts];
+      }
+      if (j0 > (int64_t)cand_batch_ * 64) break;  // (nearly) no free space left
+    }
+    // 2. candidate pairs per arm: count, then share the pair buffer in arm order
+    for (int r : todo) {
+      SUBMIT(Op::Fill, fill, FillArgs{(uint32_t *)ri(r, 1), 0u, 2});
+      SUBMIT(Op::RmPairs, rm_pairs,
+             RmPairsArgs{V(r), n0[r], rm_n_[r], h_nj_[r], P_.delta, ri(r, 1), 0, nullptr, nullptr, nullptr});
+      TRY(copy_(ex, pin_rm_ + (size_t)r * (kRmInts + 1) + 1, ri(r, 1), sizeof(int32_t)));
+    }
+    SYNC();
+    int base = 0;
+    for (int r : todo) {
+      const int want = pin_rm_[(size_t)r * (kRmInts + 1) + 1];
+      np[r] = std::min(want, pair_cap_ - base);
+      if (want > np[r]) st_.capacity_hit = 1;
+      off[r] = base;
+      base += np[r];
+    }
+    // 3. the pairs, their validation, new edges, union of components
+    for (int r : todo)
+      if (np[r] > 0)
+        SUBMIT(Op::RmPairs, rm_pairs,
+               RmPairsArgs{V(r), n0[r], rm_n_[r], h_nj_[r], P_.delta, ri(r, 2), np[r], pair_ids_ + 2 * (size_t)off[r],
+                           pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r]});
+    for (int r : todo)
+      if (np[r] > 0)
+        TRY(validate_(ex, arms_[r], pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r],
+                      np[r], P_.resolution, pair_valid_ + off[r], cnt_ + (size_t)(2 + r) * 16));
+    for (int r : todo) {
+      if (np[r] > 0) {
+        SUBMIT(Op::RmAddEdges, rm_add_edges,
+               RmAddEdgesArgs{pair_ids_ + 2 * (size_t)off[r], pair_valid_ + off[r], ri(r, 2), np[r],
+                              rm_edges_ + (size_t)r * edge_cap_ * 2, rm_ne_ + r, edge_cap_});
+        grew[r] = 1;
+      }
+      SUBMIT(Op::RmUnion, rm_union,
+             RmUnionArgs{pair_ids_ + 2 * (size_t)off[r], pair_valid_ + off[r], ri(r, 2), np[r], rm_n_[r],
+                         uf_ + (size_t)r * rm_cap_, ri(r, 3)});
+      TRY(copy_(ex, pin_rm_ + (size_t)r * (kRmInts + 1) + 3, ri(r, 3), sizeof(int32_t)));
+      if (np[r] > 0) TRY(copy_(ex, pin_cnt_ + (size_t)r * 2, cnt_ + (size_t)(2 + r) * 16, 2 * sizeof(uint64_t)));
+    }
+    SYNC();
+    bool all = true;
+    for (int r : todo) {
+      if (np[r] > 0) st_.roadmap_edge_states += (int64_t)pin_cnt_[(size_t)r * 2 + 1];
+      conn[r] = (char)pin_rm_[(size_t)r * (kRmInts + 1) + 3];
+    }
+    for (int r = 0; r < R; ++r) all = all && conn[r];
     if (all) break;
     if (out_of_time_()) break;
   }
+  // adjacency (CSR) of the arms that gained edges
+  for (int r = 0; r < R; ++r)
+    if (grew[r])
+      SUBMIT(Op::RmBfs, rm_bfs,
+             RmBfsArgs{rm_edges_ + (size_t)r * edge_cap_ * 2, rm_ne_ + r, edge_cap_, rm_n_[r],
+                       rm_rowptr_ + (size_t)r * (rm_cap_ + 1), rm_col_ + (size_t)r * col_cap_, col_cap_,
+                       deg_ + (size_t)r * rm_cap_, nullptr, nullptr});
   st_.roadmap_connected = 1;
   for (int r = 0; r < R; ++r) st_.roadmap_connected = st_.roadmap_connected && conn[r];
   return MRPOP_OK;
@@ -368,6 +513,7 @@ mrpop_status PlanJob::run(Exec &ex) {
   for (int r = 0; r < R; ++r)
     TRY(copy_(ex, rm_V_ + (size_t)r * rm_cap_ * kRmStride, upload_ + 2 * D + (size_t)r * 2 * kRmStride,
               sizeof(float) * 2 * kRmStride));
+  for (int r = 0; r < R; ++r) TRY(copy_(ex, uf_ + (size_t)r * rm_cap_, upload_i_ + 4 * R, 2 * sizeof(int32_t)));
   SUBMIT(Op::Fill, fill, FillArgs{(uint32_t *)rm_rowptr_, 0u, (int64_t)R * (rm_cap_ + 1)});
 
   // endpoints

@@ -129,6 +129,7 @@ struct RmAcceptArgs {
   int32_t *n_v;
   int cap;
   int32_t *taken;
+  int32_t *parent;  // union-find parent of every roadmap vertex
 };
 
 struct RmPairsArgs {
@@ -150,12 +151,20 @@ struct RmAddEdgesArgs {
   int cap_edges;
 };
 
+struct RmUnionArgs {
+  const int32_t *pair_ids;
+  const uint8_t *valid;
+  const int32_t *n_pairs;
+  int max_pairs, n_v;
+  int32_t *parent, *connected;
+};
+
 struct RmBfsArgs {
   const int32_t *edges, *n_edges;
   int cap_edges, n_v;
   int32_t *rowptr, *col;
   int col_cap;
-  int32_t *deg, *level, *connected;
+  int32_t *deg, *level, *connected;  // level null: adjacency only
 };
 
 // 32-bit fill and byte copy (device or mapped pinned host memory).
@@ -184,6 +193,7 @@ hipError_t launch_rm_accept(const RmAcceptArgs &a, hipStream_t s);
 hipError_t launch_rm_pairs(const RmPairsArgs &a, hipStream_t s);
 hipError_t launch_rm_add_edges(const RmAddEdgesArgs &a, hipStream_t s);
 hipError_t launch_rm_csr_bfs(const RmBfsArgs &a, hipStream_t s);
+hipError_t launch_rm_union(const RmUnionArgs &a, hipStream_t s);
 hipError_t launch_fill(const FillArgs &a, hipStream_t s);
 hipError_t launch_copy(const CopyArgs &a, hipStream_t s);
 
@@ -195,9 +205,10 @@ uint64_t roadmap_key(uint64_t seed, uint64_t stream_a, uint64_t stream_b);
 // needs, records that need fewer leave early).
 enum class Op : uint8_t {
   Sample, Nearest, Extend, Insert, Conn, Select, Path, TreeRoot,
-  RmSample, RmAccept, RmPairs, RmAddEdges, RmBfs, Fill, Copy, Validate
+  RmSample, RmAccept, RmPairs, RmAddEdges, RmBfs, RmUnion, Fill, Copy, Validate
 };
-constexpr int kNumOps = 16;
+constexpr int kNumOps = 17;
+constexpr int kUfMaxVertices = 32768;  // roadmap vertices per arm (union-find in LDS)
 
 // Blocks one record needs (0: nothing to do).
 int op_blocks(Op op, const void *args);
@@ -234,6 +245,7 @@ struct Cmd {
     RmPairsArgs rm_pairs;
     RmAddEdgesArgs rm_add_edges;
     RmBfsArgs rm_bfs;
+    RmUnionArgs rm_union;
     FillArgs fill;
     CopyArgs copy;
     ValidateReq val;

@@ -473,7 +473,7 @@ __device__ __forceinline__ void rm_accept_body(const RmAcceptArgs &A, int bx) {
   const uint8_t *valid = A.valid;
   const int n = A.n, nj = A.nj, need = A.need, cap = A.cap;
   float *V = A.V;
-  int32_t *n_v = A.n_v, *taken = A.taken;
+  int32_t *n_v = A.n_v, *taken = A.taken, *parent = A.parent;
   if (bx != 0) return;
 
   __shared__ int32_t wsum[1024 / kWave];
@@ -494,8 +494,10 @@ __device__ __forceinline__ void rm_accept_body(const RmAcceptArgs &A, int bx) {
       chunk += wsum[k];
     }
     const int pos = base + off + before;
-    if (ok && pos < need && *n_v + pos < cap)
+    if (ok && pos < need && *n_v + pos < cap) {
       for (int d = 0; d < nj; ++d) V[(int64_t)(*n_v + pos) * kRmStride + d] = cand[(int64_t)i * nj + d];
+      parent[*n_v + pos] = *n_v + pos;  // a new vertex is its own component
+    }
     __syncthreads();
     if (threadIdx.x == 0) base += chunk;
     __syncthreads();
@@ -508,9 +510,9 @@ __device__ __forceinline__ void rm_accept_body(const RmAcceptArgs &A, int bx) {
   }
 }
 
-// Pairs (j, i), i in [i0, i1), j < i, with |V_i - V_j| <= delta: written as
-// edge endpoints (qa = V_j, qb = V_i) and ids, compacted with an atomic
-// counter (their order does not reach any result: adjacency is rebuilt as a
+// Pairs (j, i), i in [i0, i1), j < i, with |V_i - V_j| <= delta: counted
+// (pair_ids null), or written as edge endpoints (qa = V_j, qb = V_i) and ids,
+// compacted with an atomic counter (their order does not reach any result: adjacency is rebuilt as a
 // set and the extension oracle breaks ties by vertex id).
 __device__ __forceinline__ void rm_pairs_body(const RmPairsArgs &A, int bx) {
   const float *V = A.V;
@@ -529,7 +531,7 @@ __device__ __forceinline__ void rm_pairs_body(const RmPairsArgs &A, int bx) {
     }
     if (!(sqrtf(d2) <= delta)) continue;
     const int k = atomicAdd(count, 1);
-    if (k >= cap) continue;
+    if (!pair_ids || k >= cap) continue;  // counting only, or beyond the allotted room
     pair_ids[2 * k] = j;
     pair_ids[2 * k + 1] = i;
     for (int d = 0; d < nj; ++d) {
@@ -553,6 +555,47 @@ __device__ __forceinline__ void rm_add_edges_body(const RmAddEdgesArgs &A, int b
   if (e >= cap_edges) return;
   edges[2 * e] = pair_ids[2 * k];
   edges[2 * e + 1] = pair_ids[2 * k + 1];
+}
+
+// Single workgroup: union-find over the arm's roadmap (parent pointers, a
+// vertex's parent never has a larger index, so a component's root is its
+// smallest vertex and vertex 0 is always a root).  Merges the components of
+// the valid new edges, then writes whether vertex 1 shares vertex 0's
+// component.  The pointers are worked on in LDS (at most kUfMax vertices).
+constexpr int kUfMax = 32768;
+
+__device__ __forceinline__ int uf_find(int32_t *par, int x) {
+  for (;;) {
+    const int p = par[x];
+    if (p == x) return x;
+    const int gp = par[p];
+    if (gp != p) par[x] = gp;  // path halving (still an ancestor)
+    x = gp;
+  }
+}
+
+__device__ __forceinline__ void rm_union_body(const RmUnionArgs &A, int bx) {
+  if (bx != 0) return;
+  __shared__ int32_t par[kUfMax];
+  const int nv = A.n_v < kUfMax ? A.n_v : kUfMax;
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) par[v] = A.parent[v];
+  __syncthreads();
+  const int np = *A.n_pairs < A.max_pairs ? *A.n_pairs : A.max_pairs;
+  for (int k = threadIdx.x; k < np; k += blockDim.x) {
+    if (!A.valid[k]) continue;
+    int a = A.pair_ids[2 * k], b = A.pair_ids[2 * k + 1];
+    if (a >= nv || b >= nv) continue;
+    for (;;) {  // hook the larger root under the smaller one
+      a = uf_find(par, a);
+      b = uf_find(par, b);
+      if (a == b) break;
+      const int hi = a > b ? a : b, lo = a > b ? b : a;
+      if (atomicCAS(&par[hi], hi, lo) == hi) break;
+    }
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) A.parent[v] = uf_find(par, v);
+  if (threadIdx.x == 0) *A.connected = (nv > 1 && uf_find(par, 1) == uf_find(par, 0)) ? 1 : 0;
 }
 
 // Single workgroup: rebuild the arm's adjacency (CSR) from its edge list,
@@ -606,6 +649,7 @@ __device__ __forceinline__ void rm_csr_bfs_body(const RmBfsArgs &A, int bx) {
     if (pa < col_cap) col[pa] = b;
     if (pb < col_cap) col[pb] = a;
   }
+  if (!level) return;  // adjacency only
   for (int v = threadIdx.x; v < n_v; v += blockDim.x) level[v] = v == 0 ? 0 : -1;
   __syncthreads();
   for (int depth = 0;; ++depth) {
@@ -670,6 +714,7 @@ MRPOP_OP_KERNELS(rm_accept, RmAcceptArgs, 1024)
 MRPOP_OP_KERNELS(rm_pairs, RmPairsArgs, 256)
 MRPOP_OP_KERNELS(rm_add_edges, RmAddEdgesArgs, 256)
 MRPOP_OP_KERNELS(rm_csr_bfs, RmBfsArgs, 1024)
+MRPOP_OP_KERNELS(rm_union, RmUnionArgs, 1024)
 MRPOP_OP_KERNELS(fill, FillArgs, 256)
 MRPOP_OP_KERNELS(copy, CopyArgs, 256)
 
@@ -699,6 +744,7 @@ int op_blocks(Op op, const void *p) {
     }
     case Op::RmAddEdges: return clamp_blocks((((const RmAddEdgesArgs *)p)->max_pairs + 255) / 256);
     case Op::RmBfs: return 1;
+    case Op::RmUnion: return 1;
     case Op::Fill: return (int)std::min<int64_t>((((const FillArgs *)p)->n + 255) / 256, kCopyBlocksMax);
     case Op::Copy: return (int)std::min<int64_t>((((const CopyArgs *)p)->bytes + 255) / 256, kCopyBlocksMax);
     case Op::Validate: return 0;
@@ -721,6 +767,7 @@ size_t op_args_bytes(Op op) {
     case Op::RmPairs: return sizeof(RmPairsArgs);
     case Op::RmAddEdges: return sizeof(RmAddEdgesArgs);
     case Op::RmBfs: return sizeof(RmBfsArgs);
+    case Op::RmUnion: return sizeof(RmUnionArgs);
     case Op::Fill: return sizeof(FillArgs);
     case Op::Copy: return sizeof(CopyArgs);
     case Op::Validate: return 0;
@@ -759,6 +806,7 @@ static hipError_t launch_any(Op op, const void *p, bool batch, int count, int gr
     MRPOP_OP_CASE(RmPairs, rm_pairs, RmPairsArgs, 256)
     MRPOP_OP_CASE(RmAddEdges, rm_add_edges, RmAddEdgesArgs, 256)
     MRPOP_OP_CASE(RmBfs, rm_csr_bfs, RmBfsArgs, 1024)
+    MRPOP_OP_CASE(RmUnion, rm_union, RmUnionArgs, 1024)
     MRPOP_OP_CASE(Fill, fill, FillArgs, 256)
     MRPOP_OP_CASE(Copy, copy, CopyArgs, 256)
     case Op::Validate: return hipErrorInvalidValue;
@@ -796,6 +844,7 @@ hipError_t launch_rm_accept(const RmAcceptArgs &a, hipStream_t s) { return launc
 hipError_t launch_rm_pairs(const RmPairsArgs &a, hipStream_t s) { return launch_op(Op::RmPairs, &a, s); }
 hipError_t launch_rm_add_edges(const RmAddEdgesArgs &a, hipStream_t s) { return launch_op(Op::RmAddEdges, &a, s); }
 hipError_t launch_rm_csr_bfs(const RmBfsArgs &a, hipStream_t s) { return launch_op(Op::RmBfs, &a, s); }
+hipError_t launch_rm_union(const RmUnionArgs &a, hipStream_t s) { return launch_op(Op::RmUnion, &a, s); }
 hipError_t launch_fill(const FillArgs &a, hipStream_t s) { return launch_op(Op::Fill, &a, s); }
 hipError_t launch_copy(const CopyArgs &a, hipStream_t s) { return launch_op(Op::Copy, &a, s); }
 

@@ -44,6 +44,57 @@ F_JOINT, F_XFORM, F_SS, F_SB = 48, 18, 10, 17
 # iterations or max_rounds rounds).
 PLAN = dict(candidates=512, n_roadmap=32, delta=3.0, max_rounds=150, max_iterations=4)
 
+# HBM traffic of the tile kernels, from hardware counters (FETCH_SIZE and
+# WRITE_SIZE per dispatch, scaled by what they read for a plain copy of known
+# size).  The summary records a digest of the kernel sources it was taken on;
+# when the sources differ, the figure no longer applies and is reported as null.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "validate_tiles_traffic_c2.md")
+KERNEL_SOURCES = ("validate.hip", "device_common.h", "mrpop_internal.h")
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2609_30644_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_counters():
+    """(fields, note) from the committed counter summary: bytes per tile-kernel
+    launch and the FP32 flops the hardware issued per launch; fields is None
+    when the summary is missing or was taken on other kernel sources."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None, "no counter summary"
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip("` ")] = v.strip("` ")
+    if fields.get("kernel_digest") != kernel_digest():
+        return None, "counters were taken on other kernel sources"
+    try:
+        out = {k: float(fields[k]) for k in ("traffic_bytes_per_launch", "valu_fp32_flops_per_launch")}
+    except (KeyError, ValueError):
+        return None, "counter summary lacks its fields"
+    return out, "FETCH_SIZE + WRITE_SIZE per launch, copy-calibrated"
+
+
+def copy_probe(mib: int):
+    """A plain device copy of `mib` MiB, three times: the calibration run of
+    the traffic counters (each copy reads and writes `mib` MiB)."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "copies": 3}), flush=True)
+
 
 def load_workload():
     import workloads as W
@@ -217,10 +268,15 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of the served run")
     ap.add_argument("--serve-slots", type=int, default=128)
     ap.add_argument("--serve-mem-gb", type=float, default=96.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB on the device three times (traffic-counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "one GPU only: the hot path is measured on a single GPU; run with --gpus 1"}))
         sys.exit(2)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
 
@@ -266,9 +322,13 @@ def main():
 
     flops = algorithmic_flops(prof.work, scene)
     achieved = flops / (prof.kernel_ms * 1e-3) / 1e12
+    counted, traffic_note = recorded_counters()
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                "kernel": "validate_tiles_kernel", "launches": prof.launches,
+                "frac": achieved / PEAK_FP32_TFLOPS,
+                "traffic": counted["traffic_bytes_per_launch"] if counted else None, "traffic_unit": "bytes/launch",
+                "traffic_note": traffic_note,
+                "valu_fp32_flops_per_launch": counted["valu_fp32_flops_per_launch"] if counted else None,
+                "kernel": "validate_tiles_kernel + validate_segments_kernel", "launches": prof.launches,
                 "avg_launch_us": prof.kernel_ms * 1e3 / max(1, prof.launches),
                 "flops_per_launch": flops / max(1, prof.launches),
                 "grid": [prof.grid_blocks, prof.block_threads], "work": prof.work}

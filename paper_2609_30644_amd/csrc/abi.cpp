@@ -50,14 +50,45 @@ const std::pair<hipEvent_t, hipEvent_t> *profile_slot(mrpop_ctx *ctx) {
   if (!ctx->profiling) return nullptr;
   if (ctx->ev_used == ctx->ev_pool.size()) {
     std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
-    if (hipEventCreate(&p.first) != hipSuccess) return nullptr;
-    if (hipEventCreate(&p.second) != hipSuccess) {
+    // device-scope release: timing events need no system-scope cache
+    // write-back at the kernel's end, which would lengthen what they time
+    if (hipEventCreateWithFlags(&p.first, hipEventReleaseToDevice) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&p.second, hipEventReleaseToDevice) != hipSuccess) {
       hipEventDestroy(p.first);
       return nullptr;
     }
     ctx->ev_pool.push_back(p);
   }
   return &ctx->ev_pool[ctx->ev_used++];
+}
+
+hipError_t small_launch_state(mrpop_ctx *ctx, uint32_t **arrived, uint32_t **flags, uint32_t *token) {
+  // one allocation: the arrival counter, then kFusedMaxEdges flag words that
+  // only these launches write (zero, or an earlier launch's token)
+  if (!ctx->small_arrived) {
+    const size_t bytes = 256 + sizeof(uint32_t) * kFusedMaxEdges;
+    hipError_t e = hipMalloc((void **)&ctx->small_arrived, bytes);
+    if (e != hipSuccess) {
+      ctx->small_arrived = nullptr;
+      return e;
+    }
+    e = hipMemset(ctx->small_arrived, 0, bytes);
+    if (e != hipSuccess) return e;
+  }
+  *flags = ctx->small_arrived + 64;
+  // tokens 0x80000001, 0x80000002, ...: the top bit keeps them apart from
+  // the general path's flag values; when the sequence wraps, the words are
+  // cleared so that no word keeps a token about to be reused
+  ctx->small_tokens = (ctx->small_tokens + 1u) & 0x7fffffffu;
+  if (ctx->small_tokens == 0u) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemset(*flags, 0, sizeof(uint32_t) * kFusedMaxEdges);
+    if (e != hipSuccess) return e;
+    ctx->small_tokens = 1u;
+  }
+  *arrived = ctx->small_arrived;
+  *token = 0x80000000u | ctx->small_tokens;
+  return hipSuccess;
 }
 
 }  // namespace mrpop
@@ -93,6 +124,7 @@ void mrpop_ctx_destroy(mrpop_ctx *ctx) {
     hipEventDestroy(p.second);
   }
   if (ctx->prof_totals) hipFree(ctx->prof_totals);
+  if (ctx->small_arrived) hipFree(ctx->small_arrived);
   delete ctx;
 }
 

@@ -111,4 +111,21 @@ __device__ __forceinline__ uint32_t load_relaxed(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Number of states at which an edge is checked (paper, Sec. "Multi-Thread
+// Reassignment for Collision Checking": edges are discretised into states),
+// from the largest joint difference linf over its endpoints, so that no joint
+// moves more than res between states: 1 + ceil(linf / res) in single
+// precision with a correctly rounded division, 1 for a null edge.  Negative codes: an
+// endpoint is not finite, or the edge would need more than
+// MRPOP_MAX_STATES_PER_EDGE states.  Every count of the library is made here.
+constexpr int32_t kCodeNonFinite = -1, kCodeTooLong = -2;
+
+__device__ __forceinline__ int32_t state_count_code(float linf, bool finite, float res) {
+  if (!finite) return kCodeNonFinite;
+  if (linf == 0.f) return 1;
+  const float ratio = linf / res;
+  if (!(ratio <= (float)(MRPOP_MAX_STATES_PER_EDGE - 1))) return kCodeTooLong;
+  return 1 + (int32_t)ceilf(ratio);
+}
+
 }  // namespace mrpop

@@ -94,6 +94,11 @@ struct mrpop_ctx {
   int64_t prof_launches = 0;
   uint64_t *prof_totals = nullptr;  // device [10]
   int32_t last_grid = 0, last_block = 0;  // last tile-kernel launch
+  // One-launch small validations: the device arrival counter (zero between
+  // launches) followed by their flag words, and the source of each launch's
+  // hit token.
+  uint32_t *small_arrived = nullptr;
+  uint32_t small_tokens = 0;
 };
 
 namespace mrpop {
@@ -142,6 +147,8 @@ struct ValidateScratch {
   int32_t *tile_first;   // [kTileFirstCap] edge holding each tile's first list position
 };
 constexpr int kPartialSlots = 10;  // states checked, 8 work counts, tiles
+// Largest batch validated in one launch from the producer's state counts.
+constexpr int64_t kFusedMaxEdges = 1024;
 constexpr int kMaxGrid = 8192;
 constexpr int64_t kTileFirstCap = 1 << 20;
 size_t validate_scratch_bytes(int64_t n_edges);
@@ -154,8 +161,23 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
                            hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> *ev_pair = nullptr,
                            uint64_t *totals = nullptr, int32_t *grid_out = nullptr,
                            int32_t *block_out = nullptr);
+// The same for 1..kFusedMaxEdges edges in one launch, from state-count codes
+// the edges' producer wrote (codes, device [n_edges]; the counts of
+// state_count_code): arrived is a device counter that is zero between
+// launches, ws.flags flag words that hold no value equal to token (zero or
+// earlier tokens), token a value with the top bit set.  Results and
+// counters as launch_validate.
+hipError_t launch_validate_small(const SceneDev &sc, const float *qa, const float *qb, int64_t n_edges,
+                                 const int32_t *codes, uint8_t *out_valid, const ValidateScratch &ws,
+                                 uint32_t *arrived, uint32_t token, hipStream_t s,
+                                 const std::pair<hipEvent_t, hipEvent_t> *ev_pair = nullptr,
+                                 uint64_t *totals = nullptr, int32_t *grid_out = nullptr,
+                                 int32_t *block_out = nullptr);
 // Take an event pair for one profiled launch (nullptr when not profiling).
 const std::pair<hipEvent_t, hipEvent_t> *profile_slot(mrpop_ctx *ctx);
+// Arrival counter, flag words ([kFusedMaxEdges], written only by these
+// launches) and a fresh hit token for one launch_validate_small.
+hipError_t small_launch_state(mrpop_ctx *ctx, uint32_t **arrived, uint32_t **flags, uint32_t *token);
 
 // One validation request of a many-scene launch: edges [edge0, edge0 +
 // n_edges) of the flat list are (qa[i], qb[i]) of scene sc; bits go to

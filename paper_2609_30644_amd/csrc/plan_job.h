@@ -47,8 +47,9 @@ class PlanJob {
     err_ = std::string(what) + ": " + hipGetErrorString(e);
     return MRPOP_E_DEVICE;
   }
+  // n_codes (device, optional): state-count codes the edges' producer wrote
   mrpop_status validate_(Exec &ex, const mrpop_scene *sc, const float *a, const float *b, int64_t n, float res,
-                         uint8_t *out, uint64_t *counters);
+                         uint8_t *out, uint64_t *counters, const int32_t *n_codes = nullptr);
   mrpop_status copy_(Exec &ex, void *dst, const void *src, size_t bytes);
   mrpop_status roadmap_(Exec &ex, int it);
   void set_sizes_(const mrpop_scene *scene, const mrpop_plan_params &P);
@@ -79,6 +80,7 @@ class PlanJob {
   // connected), uf_ [r][rm_cap] union-find parents, cnt_ [2 + r][16]
   int32_t *rm_rowptr_, *rm_col_, *rm_edges_, *rm_nv_, *rm_ne_, *pair_ids_, *rm_i_, *uf_, *deg_, *tvid_[2],
       *tpar_[2], *tn_[2], *near_idx_, *vid_new_, *ins_idx_, *conn_idx_, *path_len_d_, *d_nj_, *d_qoff_;
+  int32_t *codes_ext_, *codes_conn_;  // [PC] state-count codes of the extension and connection edges
   uint8_t *cand_valid_, *pair_valid_, *alive_, *valid_, *cvalid_;
   uint64_t *cnt_;  // [2 + R][16]: counters of the extension, connection and per-arm roadmap validations
   RoundStatus *status_;

@@ -99,13 +99,22 @@ class PlainExec : public Exec {
     std::vector<ValidateReq> v;
     v.swap(val_);
     if (v.size() == 1) {
+      const ValidateReq &q = v[0];
       void *base = nullptr;
-      if (scratch(ctx_, 1, validate_scratch_bytes(v[0].n), &base) != MRPOP_OK) return hipErrorOutOfMemory;
-      ValidateScratch ws = validate_scratch_layout(base, v[0].n);
-      ws.counters = v[0].counters;
-      return launch_validate(*v[0].scene, v[0].qa, v[0].qb, v[0].n, v[0].res, nullptr, v[0].out, ws, s_,
-                             profile_slot(ctx_), ctx_->profiling ? ctx_->prof_totals : nullptr, &ctx_->last_grid,
-                             &ctx_->last_block);
+      if (scratch(ctx_, 1, validate_scratch_bytes(q.n), &base) != MRPOP_OK) return hipErrorOutOfMemory;
+      ValidateScratch ws = validate_scratch_layout(base, q.n);
+      ws.counters = q.counters;
+      if (q.n_codes && q.n <= kFusedMaxEdges) {  // counts made by the producer: one launch
+        uint32_t *arrived = nullptr, *flags = nullptr, token = 0;
+        const hipError_t e = small_launch_state(ctx_, &arrived, &flags, &token);
+        if (e != hipSuccess) return e;
+        ws.flags = flags;
+        return launch_validate_small(*q.scene, q.qa, q.qb, q.n, q.n_codes, q.out, ws, arrived, token, s_,
+                                     profile_slot(ctx_), ctx_->profiling ? ctx_->prof_totals : nullptr,
+                                     &ctx_->last_grid, &ctx_->last_block);
+      }
+      return launch_validate(*q.scene, q.qa, q.qb, q.n, q.res, nullptr, q.out, ws, s_, profile_slot(ctx_),
+                             ctx_->profiling ? ctx_->prof_totals : nullptr, &ctx_->last_grid, &ctx_->last_block);
     }
     int r_max = 1;
     int64_t flat = 0;
@@ -248,6 +257,8 @@ size_t PlanJob::plan_arena_(void *base) {
   ar.add(&ca_, (size_t)PC * D);
   ar.add(&cb_, (size_t)PC * D);
   ar.add(&cvalid_, PC);
+  ar.add(&codes_ext_, PC);
+  ar.add(&codes_conn_, PC);
   ar.add(&cnt_, (size_t)(2 + R) * 16);
   ar.add(&status_, 1);
   ar.add(&path_d_, (size_t)path_max_ * D);
@@ -351,7 +362,7 @@ mrpop_status PlanJob::copy_(Exec &ex, void *dst, const void *src, size_t bytes) 
 }
 
 mrpop_status PlanJob::validate_(Exec &ex, const mrpop_scene *sc, const float *a, const float *b, int64_t n,
-                                float res, uint8_t *out, uint64_t *counters) {
+                                float res, uint8_t *out, uint64_t *counters, const int32_t *n_codes) {
   if (n <= 0) {
     Cmd z;
     z.op = Op::Fill;
@@ -361,7 +372,7 @@ mrpop_status PlanJob::validate_(Exec &ex, const mrpop_scene *sc, const float *a,
   }
   Cmd c;
   c.op = Op::Validate;
-  c.val = ValidateReq{&sc->dev, a, b, n, res, out, counters};
+  c.val = ValidateReq{&sc->dev, a, b, n, res, out, counters, n_codes};
   const hipError_t e = ex.submit(c);
   return e == hipSuccess ? MRPOP_OK : hip_fail_(e, "validate launch");
 }
@@ -549,15 +560,15 @@ mrpop_status PlanJob::run(Exec &ex) {
       SUBMIT(Op::Extend, extend,
              ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a], tvid_[a], tg_[a],
                         tcap_, rm_V_, rm_rowptr_, rm_col_, rm_cap_, col_cap_, d_nj_, d_qoff_, q_new_, vid_new_, g_new_,
-                        alive_, ea_, eb_});
-      TRY(validate_(ex, scene_, ea_, eb_, PC, P_.resolution, valid_, cnt_));
+                        alive_, ea_, eb_, P_.resolution, codes_ext_});
+      TRY(validate_(ex, scene_, ea_, eb_, PC, P_.resolution, valid_, cnt_, codes_ext_));
       SUBMIT(Op::Insert, insert,
              InsertArgs{PC, D, R, alive_, valid_, q_new_, g_new_, vid_new_, near_idx_, tq_[a], tg_[a], tvid_[a],
                         tpar_[a], tn_[a], tcap_, cb, ins_idx_, budget_, status_});
       SUBMIT(Op::Nearest, nearest,
              NearestArgs{tq_[b], tg_[b], n_t[b], D, 1, tcap_, q_new_, D, budget_, PC, conn_idx_});
-      SUBMIT(Op::Conn, conn, ConnArgs{PC, D, conn_idx_, q_new_, tq_[b], tcap_, ca_, cb_});
-      TRY(validate_(ex, scene_, ca_, cb_, PC, P_.resolution, cvalid_, cnt_ + 16));
+      SUBMIT(Op::Conn, conn, ConnArgs{PC, D, conn_idx_, q_new_, tq_[b], tcap_, ca_, cb_, P_.resolution, codes_conn_});
+      TRY(validate_(ex, scene_, ca_, cb_, PC, P_.resolution, cvalid_, cnt_ + 16, codes_conn_));
       SUBMIT(Op::Select, select,
              SelectArgs{PC, D, ins_idx_, conn_idx_, cvalid_, q_new_, g_new_, tq_[b], tg_[b], tcap_, cnt_, cnt_ + 16,
                         status_});

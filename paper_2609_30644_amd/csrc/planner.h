@@ -56,6 +56,8 @@ struct ExtendArgs {
   float *g_new;               // [n]
   uint8_t *alive;             // [n]
   float *edge_a, *edge_b;     // [n][dim]
+  float res;                  // resolution of the edge's validation
+  int32_t *n_codes;           // [n] or null: state-count code of each edge
 };
 
 struct RoundStatus {
@@ -85,6 +87,8 @@ struct ConnArgs {
   const float *q_new, *other_q;
   int tree_cap;
   float *edge_a, *edge_b;
+  float res;          // resolution of the edge's validation
+  int32_t *n_codes;   // [n] or null: state-count code of each edge
 };
 
 struct SelectArgs {
@@ -226,6 +230,7 @@ struct ValidateReq {
   float res;
   uint8_t *out;
   uint64_t *counters;
+  const int32_t *n_codes;  // device [n] or null: state-count codes written by the edges' producer
 };
 
 // One unit of device work of a planning instance.

@@ -201,14 +201,15 @@ __device__ __forceinline__ void nearest_body(const NearestArgs &a, int bx) {
 // a4: dRRT extension oracle (ORACLE_AOX)
 // ---------------------------------------------------------------------------
 
-// One wavefront per candidate.  For every arm,
-// the lanes scan the roadmap neighbours of the arm's vertex in q_near and the
-// wave keeps the neighbour best aligned with the sample direction: largest
+// One wavefront per candidate.  The arms are searched at the same time, each
+// by a group of lanes (64 / R rounded down to a power of two, at least 4):
+// the group scans the roadmap neighbours of the arm's vertex in q_near and
+// keeps the neighbour best aligned with the sample direction: largest
 // cosine, ties to the lowest neighbour id, so the result does not depend on
-// the order of an adjacency row.  The arm stays if no cosine is positive.
-// The candidate survives if some arm moves and, under a finite budget,
-// g_near + |q_new - q_near| < c_rand.  Writes the edge to validate
-// (q_near -> q_new); dropped candidates get a null edge at q_near.
+// the order of an adjacency row or on how lanes share it.  The arm stays if
+// no cosine is positive.  The candidate survives if some arm moves and,
+// under a finite budget, g_near + |q_new - q_near| < c_rand.  Writes the edge
+// to validate (q_near -> q_new); dropped candidates get a null edge at q_near.
 constexpr int kExtendWaves = 4;
 
 __device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
@@ -222,14 +223,18 @@ __device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
   if (near < 0) {
     if (lane == 0) a.alive[i] = 0;
     for (int j = lane; j < D; j += kWave) ea[j] = eb[j] = qn[j] = a.tree_q[(int64_t)j * a.tree_cap];
+    if (lane == 0 && a.n_codes) a.n_codes[i] = 1;  // a null edge at a tree vertex (finite)
     return;
   }
-  bool moved = false;
-  float dist2 = 0.f;  // identical in every lane
-  int my_best = 0;    // lane r keeps arm r's choice
-  for (int r = 0; r < R; ++r) {
+  int gs = kWave;  // lanes per arm (MRPOP_MAX_ROBOTS <= 16 arms: at least 4)
+  while (gs > 4 && gs * R > kWave) gs >>= 1;
+  const int g = lane / gs, sub = lane & (gs - 1);
+  // lane r * gs ends with arm r's choice
+  int best = -1, v = -1;
+  if (g < R) {
+    const int r = g;
     const int nj = a.nj[r], q0 = a.q_off[r];
-    const int v = a.tree_vid[(int64_t)r * a.tree_cap + near];
+    v = a.tree_vid[(int64_t)r * a.tree_cap + near];
     const float *V = a.rm_V + ((int64_t)r * a.rm_cap) * kRmStride;
     const int32_t *rp = a.rm_rowptr + (int64_t)r * (a.rm_cap + 1);
     const int32_t *col = a.rm_col + (int64_t)r * a.rm_col_cap;
@@ -239,12 +244,12 @@ __device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
       dir[j] = qr[q0 + j] - V[(int64_t)v * kRmStride + j];
       dn2 = fmaf(dir[j], dir[j], dn2);
     }
-    int best = v;
+    best = v;
     float best_cos = 0.f;
     if (dn2 > 0.f) {
       const float dn = sqrtf(dn2);
       const int e0 = rp[v], e1 = min(rp[v + 1], a.rm_col_cap);
-      for (int e = e0 + lane; e < e1; e += kWave) {
+      for (int e = e0 + sub; e < e1; e += gs) {
         const int u = col[e];
         float dot = 0.f, en2 = 0.f;
         for (int j = 0; j < nj; ++j) {
@@ -259,43 +264,61 @@ __device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
           best = u;
         }
       }
-      for (int d = kWave / 2; d > 0; d >>= 1) {
-        const float oc = __shfl_xor(best_cos, d, kWave);
-        const int ob = __shfl_xor(best, d, kWave);
-        const bool o_moves = ob != v, moves = best != v;
-        if (o_moves && (!moves || oc > best_cos || (oc == best_cos && ob < best))) {
-          best_cos = oc;
-          best = ob;
-        }
+    }
+    // reduction within the group (partners lane ^ d stay in the group)
+    for (int d = gs / 2; d > 0; d >>= 1) {
+      const float oc = __shfl_xor(best_cos, d, kWave);
+      const int ob = __shfl_xor(best, d, kWave);
+      const bool o_moves = ob != v, moves = best != v;
+      if (o_moves && (!moves || oc > best_cos || (oc == best_cos && ob < best))) {
+        best_cos = oc;
+        best = ob;
       }
     }
-    moved = moved || best != v;
-    if (lane == r) my_best = best;
+  }
+  // (a group is active or idle as a whole, so the shuffles above read active lanes only)
+  const bool moved = __ballot(g < R && sub == 0 && best != v) != 0ull;
+  // |q_new - q_near|^2 summed arm by arm, joint by joint (identical in every lane)
+  float dist2 = 0.f;
+  for (int r = 0; r < R; ++r) {
+    const int br = __shfl(best, r * gs, kWave);
+    const int nj = a.nj[r], q0 = a.q_off[r];
     for (int j = 0; j < nj; ++j) {
-      const float x = V[(int64_t)best * kRmStride + j];
+      const float x = a.rm_V[((int64_t)r * a.rm_cap + br) * kRmStride + j];
       const float y = a.tree_q[(int64_t)(q0 + j) * a.tree_cap + near];
       dist2 = fmaf(x - y, x - y, dist2);
     }
   }
-  const float g = a.tree_g[near] + sqrtf(dist2);
+  const float gn = a.tree_g[near] + sqrtf(dist2);
   bool ok = moved;
-  if (a.c_rand && a.c_rand[i] < INFINITY && !(g < a.c_rand[i])) ok = false;
+  if (a.c_rand && a.c_rand[i] < INFINITY && !(gn < a.c_rand[i])) ok = false;
   if (lane == 0) {
-    a.g_new[i] = g;
+    a.g_new[i] = gn;
     a.alive[i] = ok ? 1 : 0;
   }
-  // outputs, one joint per lane (at most 7 joints per arm)
+  // outputs, one joint per lane (at most 7 joints per arm), and the edge's
+  // largest joint difference for its state count
+  float linf = 0.f;
+  bool finite = true;
   for (int r = 0; r < R; ++r) {
-    const int best = __shfl(my_best, r, kWave);
+    const int br = __shfl(best, r * gs, kWave);
     const int nj = a.nj[r], q0 = a.q_off[r];
-    if (lane == 0) a.vid_new[(int64_t)r * a.n + i] = best;
+    if (lane == 0) a.vid_new[(int64_t)r * a.n + i] = br;
     if (lane < nj) {
-      const float x = a.rm_V[((int64_t)r * a.rm_cap + best) * kRmStride + lane];
+      const float x = a.rm_V[((int64_t)r * a.rm_cap + br) * kRmStride + lane];
       const float y = a.tree_q[(int64_t)(q0 + lane) * a.tree_cap + near];
+      const float b = ok ? x : y;
       qn[q0 + lane] = x;
       ea[q0 + lane] = y;
-      eb[q0 + lane] = ok ? x : y;
+      eb[q0 + lane] = b;
+      finite = finite && isfinite(y) && isfinite(b);
+      linf = fmaxf(linf, fabsf(b - y));
     }
+  }
+  if (a.n_codes) {
+    for (int d = kWave / 2; d > 0; d >>= 1) linf = fmaxf(linf, __shfl_xor(linf, d, kWave));
+    const bool all_finite = __ballot(!finite) == 0ull;
+    if (lane == 0) a.n_codes[i] = state_count_code(linf, all_finite, a.res);
   }
 }
 
@@ -362,11 +385,17 @@ __device__ __forceinline__ void conn_body(const ConnArgs &a, int bx) {
   if (i >= a.n) return;
   const int c = a.conn_idx[i];
   float *ea = a.edge_a + (int64_t)i * a.dim, *eb = a.edge_b + (int64_t)i * a.dim;
+  float linf = 0.f;
+  bool finite = true;
   for (int j = 0; j < a.dim; ++j) {
     const float x = a.q_new[(int64_t)i * a.dim + j];
+    const float y = c >= 0 ? a.other_q[(int64_t)j * a.tree_cap + c] : x;
     ea[j] = x;
-    eb[j] = c >= 0 ? a.other_q[(int64_t)j * a.tree_cap + c] : x;
+    eb[j] = y;
+    finite = finite && isfinite(x) && isfinite(y);
+    linf = fmaxf(linf, fabsf(y - x));
   }
+  if (a.n_codes) a.n_codes[i] = state_count_code(linf, finite, a.res);
 }
 
 // Single workgroup: among inserted candidates whose connection edge is free,
@@ -375,8 +404,8 @@ __device__ __forceinline__ void conn_body(const ConnArgs &a, int bx) {
 __device__ __forceinline__ void select_body(const SelectArgs &a, int bx) {
   if (bx != 0) return;
 
-  __shared__ float sc[256];
-  __shared__ int si[256];
+  __shared__ float sc[256 / kWave];
+  __shared__ int si[256 / kWave];
   float best = INFINITY;
   int bi = -1;
   for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
@@ -393,11 +422,22 @@ __device__ __forceinline__ void select_body(const SelectArgs &a, int bx) {
       bi = i;
     }
   }
-  sc[threadIdx.x] = best;
-  si[threadIdx.x] = bi;
+  // least (cost, index) over the wave, then over the waves
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    const float oc = __shfl_xor(best, d, kWave);
+    const int oi = __shfl_xor(bi, d, kWave);
+    if (oi >= 0 && (bi < 0 || oc < best || (oc == best && oi < bi))) {
+      best = oc;
+      bi = oi;
+    }
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    sc[threadIdx.x / kWave] = best;
+    si[threadIdx.x / kWave] = bi;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int t = 1; t < (int)blockDim.x; ++t)
+    for (int t = 1; t < (int)(blockDim.x / kWave); ++t)
       if (si[t] >= 0 && (si[0] < 0 || sc[t] < sc[0] || (sc[t] == sc[0] && si[t] < si[0]))) {
         sc[0] = sc[t];
         si[0] = si[t];

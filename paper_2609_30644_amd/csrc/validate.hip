@@ -30,6 +30,7 @@
 // A collision marks the edge in a flag word and marks all of the edge's lanes
 // of the tile in an LDS mask, which the other waves read as they go; states of
 // an edge already marked by an earlier tile are skipped.
+#include <hip/hip_ext.h>
 #include <algorithm>
 
 #include "device_common.h"
@@ -105,12 +106,10 @@ __device__ __forceinline__ int32_t edge_states(const float *__restrict__ qa, con
     const int32_t v = n_opt[e];
     if (v < 1 || v > MRPOP_MAX_STATES_PER_EDGE) f = kFlagTooLong;
     else n = v;
-  } else if (linf == 0.f) {
-    n = 1;
   } else {
-    const float ratio = linf / res;  // correctly rounded single-precision division
-    if (!(ratio <= (float)(MRPOP_MAX_STATES_PER_EDGE - 1))) f = kFlagTooLong;
-    else n = 1 + (int32_t)ceilf(ratio);
+    const int32_t c = state_count_code(linf, true, res);
+    if (c == kCodeTooLong) f = kFlagTooLong;
+    else n = c;
   }
   *flag = f;
   return n;
@@ -795,13 +794,15 @@ __device__ __forceinline__ TileLanes map_lanes(int64_t s0, int64_t total, int64_
 }
 
 // One tile on the whole workgroup: the environment jobs (arm, link part)
-// over the waves, a barrier, the arm-pair stage, the edge flag; ends with a
-// barrier (the tile's LDS is reused by the next one).
+// over the waves, a barrier, the arm-pair stage, the edge flag (a colliding
+// edge's flag word is set to hit_token; states of an edge whose word already
+// holds it are skipped); ends with a barrier (the tile's LDS is reused by the
+// next one).
 template <bool STAGED>
 __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int w, int W, int lane, int it,
                           const TileLanes &tl, uint32_t *flags, float *cen, float *sc_lds, float *wave_fr,
                           uint32_t *wave_q, unsigned long long *s_dead, unsigned long long *s_hit, WorkCount &wc,
-                          uint32_t &checked) {
+                          uint32_t &checked, uint32_t hit_token) {
   unsigned long long *const dead = &s_dead[it & 1];
   const LaneState &st = tl.st;
   bool act = tl.act;
@@ -824,7 +825,7 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
         qa_v[j] = st.qa[idx];
         qb_v[j] = st.qb[idx];
       }
-      if (jb == w && act && load_relaxed(flags + tl.e) != 0u) act = false;
+      if (jb == w && act && load_relaxed(flags + tl.e) == hit_token) act = false;
 #pragma unroll
       for (int j = 0; j < kMaxJoints; ++j) qv[j] = st.last ? qb_v[j] : fmaf(st.t, qb_v[j] - qa_v[j], qa_v[j]);
     }
@@ -839,7 +840,7 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
   // arm pairs that can reach each other
   if (arm_pairs<STAGED>(sc, src, cen, sc_lds, w, W, act && !hit, st, tl.emask, wave_q, &s_hit[w], dead, lane, wc))
     hit = true;
-  if (hit) flags[tl.e] = kFlagHit;
+  if (hit) flags[tl.e] = hit_token;
   __syncthreads();
 }
 
@@ -919,9 +920,131 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
     if (w == 0) ++tiles;
     const TileLanes tl = map_lanes(tile * kWave, total, e0, my_off, off, 0, 0, qa, qb, sc.dof, lane);
     tile_work<STAGED>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, wc,
-                      checked);
+                      checked, kFlagHit);
   }
   write_partials(partials, checked, tiles, wc, w, lane);
+}
+
+// ---------------------------------------------------------------------------
+// 3b. small batches in one launch
+// ---------------------------------------------------------------------------
+//
+// For at most kFusedMaxEdges edges whose state counts the producer of the
+// edges has made (codes of state_count_code): every workgroup scans the
+// counts into LDS itself, so no count and scan launches come first, and takes
+// its tiles as the tile kernel does.  Colliding edges are marked with this
+// launch's token, so flag words never need clearing between launches.  The
+// last workgroup to finish (a device-wide arrival counter) writes the bits
+// and the counters and resets the counter: one launch where the general path
+// makes three.  Workgroups never wait for each other.
+template <bool STAGED>
+__global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_kernel(
+    SceneDev sc, const float *__restrict__ qa, const float *__restrict__ qb, int n_edges,
+    const int32_t *__restrict__ codes, uint32_t *__restrict__ flags, uint32_t token, uint8_t *__restrict__ out,
+    uint64_t *__restrict__ counters, uint64_t *__restrict__ partials, uint32_t *__restrict__ arrived,
+    uint64_t *__restrict__ totals, int S, int cache_sc) {
+  extern __shared__ float cen[];
+  __shared__ unsigned long long s_dead[2], s_hit[kMaxWavesPerBlock];
+  __shared__ int64_t s_off[kFusedMaxEdges + 1];
+  __shared__ unsigned long long s_sum[kPartialSlots + 3];
+  __shared__ int s_last;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave), W = blockDim.x / kWave;
+  const int R = sc.n_robots;
+  // exclusive offsets of the counts in LDS (thread t sums edges [t k, t k + k))
+  const int per = (n_edges + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int i0 = (int)threadIdx.x * per, i1 = min(i0 + per, n_edges);
+  int64_t mine = 0;
+  for (int i = i0; i < i1; ++i) mine += max(codes[i], 0);
+  int64_t total_v;
+  int64_t run = block_exclusive_scan(mine, &total_v);
+  for (int i = i0; i < i1; ++i) {
+    s_off[i] = run;
+    run += max(codes[i], 0);
+  }
+  const int64_t total = (int64_t)uniform_u64((uint64_t)total_v);  // the same in every lane
+  if (threadIdx.x == 0) s_off[n_edges] = total;
+  if (threadIdx.x < 2) s_dead[threadIdx.x] = 0ull;
+  __syncthreads();
+  const int64_t n_tiles = (total + kWave - 1) / kWave;
+  if ((int64_t)blockIdx.x < n_tiles) {
+    uint32_t checked = 0, tiles = 0;
+    WorkCount wc;
+    float *const sc_lds = cache_sc ? cen + (size_t)R * kMaxLinks * 3 * kWave : nullptr;
+    float *const wave_fr = cen + tile_shared_floats(R, cache_sc) + (size_t)w * kWaveLdsFloats;
+    uint32_t *const wave_q = (uint32_t *)(wave_fr + 12 * kWave);
+    const Src<STAGED> src =
+        make_src<STAGED>(sc, cen + tile_shared_floats(R, cache_sc) + (size_t)W * kWaveLdsFloats);
+    int it = 0;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, ++it) {
+      const int64_t e0 = find_edge(s_off, n_edges, tile * kWave);
+      const int64_t my_off = s_off[e0 + lane < n_edges ? e0 + lane : n_edges];
+      if (w == 0) ++tiles;
+      const TileLanes tl = map_lanes(tile * kWave, total, e0, my_off, s_off, 0, 0, qa, qb, sc.dof, lane);
+      tile_work<STAGED>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, wc,
+                        checked, token);
+    }
+    write_partials(partials, checked, tiles, wc, w, lane);
+  } else if (threadIdx.x < kPartialSlots) {
+    partials[(int64_t)blockIdx.x * kPartialSlots + threadIdx.x] = 0ull;
+  }
+  // Arrival.  Every wave waits until its own stores (flag words, partials)
+  // are performed, the barrier orders them before thread 0's increment, and
+  // that increment is an agent-scope release (an L2 write-back for the whole
+  // workgroup's stores: one per workgroup instead of one per wave); the last
+  // workgroup's waves acquire before reading what the others wrote.
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = __hip_atomic_fetch_add(arrived, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1u;
+  __syncthreads();
+  if (!s_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  // the last workgroup: column sums of the partials, then the bits
+  if (threadIdx.x < kPartialSlots + 3) s_sum[threadIdx.x] = 0ull;
+  __syncthreads();
+  // one (workgroup, slot) entry per thread and step, added in LDS
+  for (int64_t k = threadIdx.x; k < (int64_t)gridDim.x * kPartialSlots; k += blockDim.x) {
+    const uint64_t v = partials[k];
+    if (v) atomicAdd(&s_sum[k % kPartialSlots], (unsigned long long)v);
+  }
+  uint64_t inval = 0, nonfin = 0, toolong = 0;
+  for (int e = threadIdx.x; e < n_edges; e += blockDim.x) {
+    const int32_t c = codes[e];
+    const bool ok = c > 0 && flags[e] != token;
+    out[e] = ok ? 1 : 0;
+    inval += ok ? 0 : 1;
+    nonfin += c == kCodeNonFinite ? 1 : 0;
+    toolong += c == kCodeTooLong ? 1 : 0;
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    inval += __shfl_xor(inval, d, kWave);
+    nonfin += __shfl_xor(nonfin, d, kWave);
+    toolong += __shfl_xor(toolong, d, kWave);
+  }
+  if (lane == 0) {
+    atomicAdd(&s_sum[kPartialSlots], (unsigned long long)inval);
+    atomicAdd(&s_sum[kPartialSlots + 1], (unsigned long long)nonfin);
+    atomicAdd(&s_sum[kPartialSlots + 2], (unsigned long long)toolong);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    counters[0] = 0;
+    counters[1] = (uint64_t)total;
+    counters[2] = s_sum[0];
+    counters[3] = s_sum[kPartialSlots - 1];
+    counters[4] = s_sum[kPartialSlots + 1];
+    counters[5] = s_sum[kPartialSlots];
+    counters[6] = s_sum[kPartialSlots + 2];
+    counters[7] = 0;
+    for (int i = 1; i < kPartialSlots - 1; ++i) counters[7 + i] = s_sum[i];
+    if (totals) {
+      totals[0] += s_sum[0];
+      totals[1] += (uint64_t)total;
+      for (int i = 1; i < kPartialSlots - 1; ++i) totals[1 + i] += s_sum[i];
+    }
+    *arrived = 0u;  // ready for the next launch
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1045,7 +1168,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_segment
     const TileLanes tl = map_lanes((tile - g.tile0) * kWave, total, e0, my_off, off, base, g.edge0, g.qa, g.qb,
                                    sc.dof, lane);
     tile_work<false>(sc, src, g.S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, wc,
-                     checked);
+                     checked, kFlagHit);
   }
   write_partials(partials, checked, tiles, wc, w, lane);
 }
@@ -1220,16 +1343,63 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
   const int grid = staged ? persistent_grid<true>(ts.W, lds) : persistent_grid<false>(ts.W, lds);
   if (grid_out) *grid_out = grid;
   if (block_out) *block_out = kWave * ts.W;
-  if (ev_pair) (void)hipEventRecord(ev_pair->first, s);
+  // with events: recorded by the dispatch itself, at the kernel's start and end
+  hipEvent_t e0 = ev_pair ? ev_pair->first : nullptr, e1 = ev_pair ? ev_pair->second : nullptr;
   if (staged)
-    hipLaunchKernelGGL(validate_tiles_kernel<true>, dim3(grid), dim3(kWave * ts.W), lds, s, sc, qa, qb, n_edges,
-                       ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials, ts.S, ts.cache_sc);
+    hipExtLaunchKernelGGL(validate_tiles_kernel<true>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
+                          sc, qa, qb, n_edges, ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials, ts.S,
+                          ts.cache_sc);
   else
-    hipLaunchKernelGGL(validate_tiles_kernel<false>, dim3(grid), dim3(kWave * ts.W), lds, s, sc, qa, qb, n_edges,
-                       ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials, ts.S, ts.cache_sc);
-  if (ev_pair) (void)hipEventRecord(ev_pair->second, s);
+    hipExtLaunchKernelGGL(validate_tiles_kernel<false>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
+                          sc, qa, qb, n_edges, ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials, ts.S,
+                          ts.cache_sc);
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)g256), dim3(256), 0, s, ws.flags, n_edges, out_valid,
                      ws.counters, ws.partials, grid, totals);
+  return hipGetLastError();
+}
+
+template <bool STAGED>
+static int small_grid(int W, size_t lds) {
+  struct Key {
+    int w;
+    size_t lds;
+    int grid;
+  };
+  static std::vector<Key> cache;
+  for (const Key &k : cache)
+    if (k.w == W && k.lds == lds) return k.grid;
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_small_kernel<STAGED>, kWave * W, lds);
+  const int grid = std::min(kMaxGrid, std::max(1, cus) * std::max(1, per));
+  cache.push_back({W, lds, grid});
+  return grid;
+}
+
+hipError_t launch_validate_small(const SceneDev &sc, const float *qa, const float *qb, int64_t n_edges,
+                                 const int32_t *codes, uint8_t *out_valid, const ValidateScratch &ws,
+                                 uint32_t *arrived, uint32_t token, hipStream_t s,
+                                 const std::pair<hipEvent_t, hipEvent_t> *ev_pair, uint64_t *totals,
+                                 int32_t *grid_out, int32_t *block_out) {
+  if (n_edges <= 0 || n_edges > kFusedMaxEdges || !codes || !arrived || (token & 0x80000000u) == 0u)
+    return hipErrorInvalidValue;
+  const TileShape ts = tile_shape(sc.n_robots, n_edges);
+  const bool staged = use_staged(sc, ts);
+  const size_t lds =
+      centre_lds_bytes(sc.n_robots, ts.W, ts.cache_sc) + (staged ? staged_floats(sc) * sizeof(float) : 0);
+  const int grid = staged ? small_grid<true>(ts.W, lds) : small_grid<false>(ts.W, lds);
+  if (grid_out) *grid_out = grid;
+  if (block_out) *block_out = kWave * ts.W;
+  hipEvent_t e0 = ev_pair ? ev_pair->first : nullptr, e1 = ev_pair ? ev_pair->second : nullptr;
+  if (staged)
+    hipExtLaunchKernelGGL(validate_small_kernel<true>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
+                          sc, qa, qb, (int)n_edges, codes, ws.flags, token, out_valid, ws.counters, ws.partials,
+                          arrived, totals, ts.S, ts.cache_sc);
+  else
+    hipExtLaunchKernelGGL(validate_small_kernel<false>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
+                          sc, qa, qb, (int)n_edges, codes, ws.flags, token, out_valid, ws.counters, ws.partials,
+                          arrived, totals, ts.S, ts.cache_sc);
   return hipGetLastError();
 }
 
@@ -1325,10 +1495,9 @@ hipError_t launch_validate_segments(ValSeg *d_segs, int n_segs, int r_max, int64
   const int grid = segments_grid(W, lds);
   if (grid_out) *grid_out = grid;
   if (block_out) *block_out = kWave * W;
-  if (ev_pair) (void)hipEventRecord(ev_pair->first, s);
-  hipLaunchKernelGGL(validate_segments_kernel, dim3(grid), dim3(kWave * W), lds, s, d_segs, ws.offsets,
-                     ws.tile_first, ws.tile_seg, ws.flags, ws.batch, ws.partials, r_max, cache);
-  if (ev_pair) (void)hipEventRecord(ev_pair->second, s);
+  hipEvent_t e0 = ev_pair ? ev_pair->first : nullptr, e1 = ev_pair ? ev_pair->second : nullptr;
+  hipExtLaunchKernelGGL(validate_segments_kernel, dim3(grid), dim3(kWave * W), (uint32_t)lds, s, e0, e1, 0, d_segs,
+                        ws.offsets, ws.tile_first, ws.tile_seg, ws.flags, ws.batch, ws.partials, r_max, cache);
   hipLaunchKernelGGL(seg_finalize_kernel, dim3((unsigned)g256), dim3(256), 0, s, d_segs, n_flat, ws.flags,
                      ws.edge_seg, ws.partials, grid, totals);
   return hipGetLastError();

@@ -68,6 +68,8 @@ namespace mrpop {
 // held back and launched together (one many-scene launch) when the next
 // other command arrives or at sync(): they are independent by contract.
 class PlainExec : public Exec {
+  static constexpr int64_t kKernelCopyMax = 4096;
+
  public:
   PlainExec(mrpop_ctx *ctx, hipStream_t s) : ctx_(ctx), s_(s) {}
   ~PlainExec() override {
@@ -82,7 +84,10 @@ class PlainExec : public Exec {
     }
     hipError_t e = flush_validations();
     if (e != hipSuccess) return e;
-    if (c.op == Op::Copy) return hipMemcpyAsync(c.copy.dst, c.copy.src, c.copy.bytes, hipMemcpyDefault, s_);
+    // small copies (round status, counts) by the library's copy kernel, which
+    // starts as soon as the previous kernel ends; large ones by the runtime
+    if (c.op == Op::Copy && c.copy.bytes > kKernelCopyMax)
+      return hipMemcpyAsync(c.copy.dst, c.copy.src, c.copy.bytes, hipMemcpyDefault, s_);
     return launch_op(c.op, c.args(), s_);
   }
   hipError_t sync() override {
@@ -564,7 +569,7 @@ mrpop_status PlanJob::run(Exec &ex) {
       TRY(validate_(ex, scene_, ea_, eb_, PC, P_.resolution, valid_, cnt_, codes_ext_));
       SUBMIT(Op::Insert, insert,
              InsertArgs{PC, D, R, alive_, valid_, q_new_, g_new_, vid_new_, near_idx_, tq_[a], tg_[a], tvid_[a],
-                        tpar_[a], tn_[a], tcap_, cb, ins_idx_, budget_, status_});
+                        tpar_[a], tn_[a], tcap_, cb, ins_idx_, budget_, status_, n_t[a]});
       SUBMIT(Op::Nearest, nearest,
              NearestArgs{tq_[b], tg_[b], n_t[b], D, 1, tcap_, q_new_, D, budget_, PC, conn_idx_});
       SUBMIT(Op::Conn, conn, ConnArgs{PC, D, conn_idx_, q_new_, tq_[b], tcap_, ca_, cb_, P_.resolution, codes_conn_});

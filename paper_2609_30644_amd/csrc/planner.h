@@ -79,6 +79,7 @@ struct InsertArgs {
   int32_t *ins_idx;
   float *budget;
   RoundStatus *status;
+  int n_before;  // vertices in the tree before this insertion (the host's count)
 };
 
 struct ConnArgs {

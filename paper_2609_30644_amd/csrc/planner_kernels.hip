@@ -165,9 +165,13 @@ __device__ __forceinline__ void nearest_body(const NearestArgs &a, int bx) {
   __shared__ Best sb[256 / kWave];
   const int64_t qi = bx;
   const int D = a.dim;
+  const float c = a.budgets ? a.budgets[qi] : INFINITY;
+  if (!(c > 0.f)) {  // g_v + |q - q_v| >= 0: no vertex is admissible
+    if (threadIdx.x == 0) a.out_idx[qi] = -1;
+    return;
+  }
   for (int j = threadIdx.x; j < D; j += blockDim.x) sq[j] = a.queries[qi * a.q_stride + j];
   __syncthreads();
-  const float c = a.budgets ? a.budgets[qi] : INFINITY;
   Best best{INFINITY, INFINITY, -1};
   for (int64_t v = threadIdx.x; v < a.n; v += blockDim.x) {
     float d2 = 0.f;
@@ -326,68 +330,96 @@ __device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
 // a10: insertion in candidate order; a11: connection edges; a12: selection
 // ---------------------------------------------------------------------------
 
-// Single workgroup: exclusive scan over surviving candidates (alive and
-// edge-valid) in index order; appends them to the tree (SoA) up to its
-// capacity; writes each candidate's tree index (-1 if not inserted) and the
-// connection budget c_best - g_new (-1 if not inserted, so no vertex is
-// admissible).
-__device__ __forceinline__ void insert_body(const InsertArgs &a, int bx) {
-  if (bx != 0) return;
+// Insertion of the surviving candidates (alive and edge-valid) in index
+// order, kInsertPer candidates per workgroup: each workgroup counts the
+// survivors before its range and in total, places its own survivors at
+// n_before + (survivors before them) up to the tree's capacity, copies them
+// into the tree (SoA) and writes each candidate's tree index (-1 if not
+// inserted) and connection budget c_best - g_new (-1 if not inserted, so no
+// vertex is admissible).  Workgroup 0 records the count and the new size.
+constexpr int kInsertPer = kWave;
 
-  __shared__ int32_t wsum[1024 / kWave];
-  __shared__ int32_t base;
-  if (threadIdx.x == 0) base = 0;
+__device__ __forceinline__ void insert_body(const InsertArgs &a, int bx) {
+  const int i0 = bx * kInsertPer;
+  if (bx > 0 && i0 >= a.n) return;
+  __shared__ int32_t s_pos[kInsertPer];
+  __shared__ int32_t s_red[2][256 / kWave];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  // survivors before i0 and in total
+  int before = 0, all = 0;
+  for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
+    const int ok = (a.alive[i] && a.valid[i]) ? 1 : 0;
+    all += ok;
+    before += i < i0 ? ok : 0;
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    all += __shfl_xor(all, d, kWave);
+    before += __shfl_xor(before, d, kWave);
+  }
+  if (lane == 0) {
+    s_red[0][w] = before;
+    s_red[1][w] = all;
+  }
   __syncthreads();
-  for (int i0 = 0; i0 < a.n; i0 += blockDim.x) {
-    const int i = i0 + threadIdx.x;
-    const int ok = (i < a.n && a.alive[i] && a.valid[i]) ? 1 : 0;
-    // block exclusive scan of ok
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  before = 0;
+  all = 0;
+  for (int k = 0; k < nw; ++k) {
+    before += s_red[0][k];
+    all += s_red[1][k];
+  }
+  // this workgroup's candidates, one per lane of wave 0
+  if (w == 0) {
+    const int i = i0 + lane;
+    const bool ok = i < a.n && a.alive[i] && a.valid[i];
     const uint64_t bal = __ballot(ok);
-    const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[w] = __popcll(bal);
-    __syncthreads();
-    int off = 0;
-    for (int k = 0; k < w; ++k) off += wsum[k];
-    int chunk = 0;
-    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) chunk += wsum[k];
-    const int pos = base + off + before;
+    const int pos = before + __popcll(bal & ((1ull << lane) - 1ull));
+    const int32_t t = (ok && a.n_before + pos < a.tree_cap) ? a.n_before + pos : -1;
+    s_pos[lane] = t;
     if (i < a.n) {
-      int32_t t = -1;
-      if (ok && *a.tree_n + pos < a.tree_cap) {
-        t = *a.tree_n + pos;
-        for (int j = 0; j < a.dim; ++j) a.tree_q[(int64_t)j * a.tree_cap + t] = a.q_new[(int64_t)i * a.dim + j];
-        for (int r = 0; r < a.n_robots; ++r)
-          a.tree_vid[(int64_t)r * a.tree_cap + t] = a.vid_new[(int64_t)r * a.n + i];
-        a.tree_g[t] = a.g_new[i];
-        a.tree_parent[t] = a.near_idx[i];
-      }
       a.ins_idx[i] = t;
       a.budget[i] = t < 0 ? -1.f : (a.c_best < INFINITY ? a.c_best - a.g_new[i] : INFINITY);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) base += chunk;
-    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const int room = a.tree_cap - *a.tree_n;
-    const int ins = base < room ? base : room;
+  __syncthreads();
+  for (int k = threadIdx.x; k < kInsertPer * a.dim; k += blockDim.x) {
+    const int li = k / a.dim, j = k - li * a.dim;
+    const int32_t t = s_pos[li];
+    if (t >= 0) a.tree_q[(int64_t)j * a.tree_cap + t] = a.q_new[(int64_t)(i0 + li) * a.dim + j];
+  }
+  for (int k = threadIdx.x; k < kInsertPer * a.n_robots; k += blockDim.x) {
+    const int li = k / a.n_robots, r = k - li * a.n_robots;
+    const int32_t t = s_pos[li];
+    if (t >= 0) a.tree_vid[(int64_t)r * a.tree_cap + t] = a.vid_new[(int64_t)r * a.n + i0 + li];
+  }
+  if (threadIdx.x < kInsertPer) {
+    const int32_t t = s_pos[threadIdx.x];
+    if (t >= 0) {
+      a.tree_g[t] = a.g_new[i0 + threadIdx.x];
+      a.tree_parent[t] = a.near_idx[i0 + threadIdx.x];
+    }
+  }
+  if (bx == 0 && threadIdx.x == 0) {
+    const int room = a.tree_cap - a.n_before;
+    const int ins = all < room ? all : room;
     a.status->inserted = ins;
-    a.status->overflow = base > room ? 1 : 0;
-    *a.tree_n += ins;
+    a.status->overflow = all > room ? 1 : 0;
+    *a.tree_n = a.n_before + ins;
   }
 }
 
-// Connection edges (q_new -> q_conn); candidates without a connection get a
-// null edge.
+// Connection edges (q_new -> q_conn), one wavefront per candidate and one
+// joint per lane; candidates without a connection get a null edge.
+constexpr int kConnWaves = 4;
+
 __device__ __forceinline__ void conn_body(const ConnArgs &a, int bx) {
-  const int i = bx * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int i = bx * kConnWaves + (int)(threadIdx.x / kWave);
+  if (i >= a.n) return;  // whole waves leave together
   const int c = a.conn_idx[i];
   float *ea = a.edge_a + (int64_t)i * a.dim, *eb = a.edge_b + (int64_t)i * a.dim;
   float linf = 0.f;
   bool finite = true;
-  for (int j = 0; j < a.dim; ++j) {
+  for (int j = lane; j < a.dim; j += kWave) {
     const float x = a.q_new[(int64_t)i * a.dim + j];
     const float y = c >= 0 ? a.other_q[(int64_t)j * a.tree_cap + c] : x;
     ea[j] = x;
@@ -395,7 +427,11 @@ __device__ __forceinline__ void conn_body(const ConnArgs &a, int bx) {
     finite = finite && isfinite(x) && isfinite(y);
     linf = fmaxf(linf, fabsf(y - x));
   }
-  if (a.n_codes) a.n_codes[i] = state_count_code(linf, finite, a.res);
+  if (a.n_codes) {
+    for (int d = kWave / 2; d > 0; d >>= 1) linf = fmaxf(linf, __shfl_xor(linf, d, kWave));
+    const bool all_finite = __ballot(!finite) == 0ull;
+    if (lane == 0) a.n_codes[i] = state_count_code(linf, all_finite, a.res);
+  }
 }
 
 // Single workgroup: among inserted candidates whose connection edge is free,
@@ -735,6 +771,7 @@ __device__ __forceinline__ void copy_body(const CopyArgs &a, int bx) {
 // ---------------------------------------------------------------------------
 
 #define MRPOP_OP_KERNELS(name, Args, threads)                                              \
+  constexpr int name##_threads = threads;                                                  \
   __global__ __launch_bounds__(threads) void name##_kernel(Args a) { name##_body(a, blockIdx.x); } \
   __global__ __launch_bounds__(threads) void name##_batch_kernel(const Args *records) {     \
     const Args a = records[blockIdx.y];                                                    \
@@ -744,8 +781,8 @@ __device__ __forceinline__ void copy_body(const CopyArgs &a, int bx) {
 MRPOP_OP_KERNELS(sample, SampleArgs, kSampleWaves * kWave)
 MRPOP_OP_KERNELS(nearest, NearestArgs, 256)
 MRPOP_OP_KERNELS(extend, ExtendArgs, kExtendWaves * kWave)
-MRPOP_OP_KERNELS(insert, InsertArgs, 1024)
-MRPOP_OP_KERNELS(conn, ConnArgs, 256)
+MRPOP_OP_KERNELS(insert, InsertArgs, 256)
+MRPOP_OP_KERNELS(conn, ConnArgs, kConnWaves * kWave)
 MRPOP_OP_KERNELS(select, SelectArgs, 256)
 MRPOP_OP_KERNELS(path, PathArgs, 64)
 MRPOP_OP_KERNELS(tree_root, TreeRootArgs, 128)
@@ -771,8 +808,8 @@ int op_blocks(Op op, const void *p) {
       const ExtendArgs &a = *(const ExtendArgs *)p;
       return clamp_blocks((a.n + kExtendWaves - 1) / kExtendWaves);
     }
-    case Op::Insert: return 1;
-    case Op::Conn: return clamp_blocks((((const ConnArgs *)p)->n + 255) / 256);
+    case Op::Insert: return clamp_blocks(std::max(1, (((const InsertArgs *)p)->n + kInsertPer - 1) / kInsertPer));
+    case Op::Conn: return clamp_blocks((((const ConnArgs *)p)->n + kConnWaves - 1) / kConnWaves);
     case Op::Select: return 1;
     case Op::Path: return 1;
     case Op::TreeRoot: return 1;
@@ -822,33 +859,34 @@ static hipError_t op_check(Op op, const void *p) {
   return hipSuccess;
 }
 
-#define MRPOP_OP_CASE(OP, name, Args, threads)                                                     \
+// block size: the one each kernel was compiled for (MRPOP_OP_KERNELS)
+#define MRPOP_OP_CASE(OP, name, Args)                                                               \
   case Op::OP:                                                                                     \
     if (batch)                                                                                     \
-      hipLaunchKernelGGL(name##_batch_kernel, dim3((unsigned)grid_x, (unsigned)count), dim3(threads), 0, s, \
-                         (const Args *)p);                                                         \
+      hipLaunchKernelGGL(name##_batch_kernel, dim3((unsigned)grid_x, (unsigned)count), dim3(name##_threads), 0, \
+                         s, (const Args *)p);                                                      \
     else                                                                                           \
-      hipLaunchKernelGGL(name##_kernel, dim3((unsigned)grid_x), dim3(threads), 0, s, *(const Args *)p); \
+      hipLaunchKernelGGL(name##_kernel, dim3((unsigned)grid_x), dim3(name##_threads), 0, s, *(const Args *)p); \
     break;
 
 static hipError_t launch_any(Op op, const void *p, bool batch, int count, int grid_x, hipStream_t s) {
   switch (op) {
-    MRPOP_OP_CASE(Sample, sample, SampleArgs, kSampleWaves * kWave)
-    MRPOP_OP_CASE(Nearest, nearest, NearestArgs, 256)
-    MRPOP_OP_CASE(Extend, extend, ExtendArgs, kExtendWaves * kWave)
-    MRPOP_OP_CASE(Insert, insert, InsertArgs, 1024)
-    MRPOP_OP_CASE(Conn, conn, ConnArgs, 256)
-    MRPOP_OP_CASE(Select, select, SelectArgs, 256)
-    MRPOP_OP_CASE(Path, path, PathArgs, 64)
-    MRPOP_OP_CASE(TreeRoot, tree_root, TreeRootArgs, 128)
-    MRPOP_OP_CASE(RmSample, rm_sample, RmSampleArgs, 256)
-    MRPOP_OP_CASE(RmAccept, rm_accept, RmAcceptArgs, 1024)
-    MRPOP_OP_CASE(RmPairs, rm_pairs, RmPairsArgs, 256)
-    MRPOP_OP_CASE(RmAddEdges, rm_add_edges, RmAddEdgesArgs, 256)
-    MRPOP_OP_CASE(RmBfs, rm_csr_bfs, RmBfsArgs, 1024)
-    MRPOP_OP_CASE(RmUnion, rm_union, RmUnionArgs, 1024)
-    MRPOP_OP_CASE(Fill, fill, FillArgs, 256)
-    MRPOP_OP_CASE(Copy, copy, CopyArgs, 256)
+    MRPOP_OP_CASE(Sample, sample, SampleArgs)
+    MRPOP_OP_CASE(Nearest, nearest, NearestArgs)
+    MRPOP_OP_CASE(Extend, extend, ExtendArgs)
+    MRPOP_OP_CASE(Insert, insert, InsertArgs)
+    MRPOP_OP_CASE(Conn, conn, ConnArgs)
+    MRPOP_OP_CASE(Select, select, SelectArgs)
+    MRPOP_OP_CASE(Path, path, PathArgs)
+    MRPOP_OP_CASE(TreeRoot, tree_root, TreeRootArgs)
+    MRPOP_OP_CASE(RmSample, rm_sample, RmSampleArgs)
+    MRPOP_OP_CASE(RmAccept, rm_accept, RmAcceptArgs)
+    MRPOP_OP_CASE(RmPairs, rm_pairs, RmPairsArgs)
+    MRPOP_OP_CASE(RmAddEdges, rm_add_edges, RmAddEdgesArgs)
+    MRPOP_OP_CASE(RmBfs, rm_csr_bfs, RmBfsArgs)
+    MRPOP_OP_CASE(RmUnion, rm_union, RmUnionArgs)
+    MRPOP_OP_CASE(Fill, fill, FillArgs)
+    MRPOP_OP_CASE(Copy, copy, CopyArgs)
     case Op::Validate: return hipErrorInvalidValue;
   }
   return hipGetLastError();

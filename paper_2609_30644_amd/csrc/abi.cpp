@@ -486,7 +486,17 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   size_t o_nj = blob.add(nj.data(), sizeof(int32_t) * M);
   size_t o_dh = blob.add(dh.data(), sizeof(float4) * dh.size());
   size_t o_th = blob.add(th.data(), sizeof(float) * th.size());
+  // order in which the tile kernel's waves claim the links of an arm: the
+  // links with the most spheres (the longest fine tests) first
+  std::vector<int32_t> link_order((size_t)M * kMaxLinks);
+  for (int m = 0; m < M; ++m) {
+    const int32_t *ls = &link_start[(size_t)m * (kMaxLinks + 1)];
+    int32_t *ord = &link_order[(size_t)m * kMaxLinks];
+    std::iota(ord, ord + kMaxLinks, 0);
+    std::stable_sort(ord, ord + kMaxLinks, [&](int a, int b) { return ls[a + 1] - ls[a] > ls[b + 1] - ls[b]; });
+  }
   size_t o_ls = blob.add(link_start.data(), sizeof(int32_t) * link_start.size());
+  size_t o_lord = blob.add(link_order.data(), sizeof(int32_t) * link_order.size());
   size_t o_fine = blob.add(fine.data(), sizeof(float4) * fine.size());
   size_t o_fsrc = blob.add(fine_src.data(), sizeof(int32_t) * fine_src.size());
   size_t o_coarse = blob.add(coarse.data(), sizeof(float4) * coarse.size());
@@ -535,6 +545,7 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   d.dh = (const float4 *)at(o_dh);
   d.theta_off = (const float *)at(o_th);
   d.link_start = (const int32_t *)at(o_ls);
+  d.link_order = (const int32_t *)at(o_lord);
   d.fine = (const float4 *)at(o_fine);
   d.fine_src = (const int32_t *)at(o_fsrc);
   d.coarse = (const float4 *)at(o_coarse);

@@ -39,6 +39,7 @@ struct SceneDev {
   const float4 *dh;        // [M][kMaxJoints]: a, d, cos(alpha), sin(alpha)
   const float *theta_off;  // [M][kMaxJoints]
   const int32_t *link_start;  // [M][kMaxLinks + 1] fine spheres grouped by link
+  const int32_t *link_order;  // [M][kMaxLinks] links by decreasing sphere count (ties: lower link first)
   const float4 *fine;      // [M][sph_stride] link-local x, y, z, r (grouped by link)
   const int32_t *fine_src; // [M][sph_stride] index of the sphere in the input order
   const float4 *coarse;    // [M][kMaxLinks] link-local centre, radius (r < 0: empty link)

@@ -32,6 +32,7 @@
 // an edge already marked by an earlier tile are skipped.
 #include <hip/hip_ext.h>
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -490,93 +491,116 @@ __device__ void flush_queue(const Src<STAGED> &src, int m, int l, float4 cs, con
   wave_lds_sync();
 }
 
-// Environment stage of arm r (model m) at every lane's state for the links l
-// with l % S == part, link by link: compose the link frame, publish the coarse centre in LDS (for the arm-pair
-// stage), test the coarse sphere against every obstacle in expanded form
-// (three FMAs and a compare), queue the flagged (lane, obstacle) pairs and
-// run their fine tests one pair per lane.  Returns true for lanes whose state
-// collides; such a lane also marks its edge's lanes in *dead.
+// Environment tests of link l of arm r (model m) at every lane's state, given
+// the link's frame F and its coarse centre c (both at the lane's own state):
+// the frame goes to the wave's LDS slot, the coarse sphere is tested against
+// every obstacle in expanded form (three FMAs and a compare), flagged (lane,
+// obstacle) pairs are queued and get their fine tests one pair per lane.
+// Returns the lanes whose state collides; their edges are marked in *dead.
 template <bool STAGED>
-__device__ bool arm_env(const SceneDev &sc, const Src<STAGED> &src, int r, int m, int part, int S,
-                        const float (&qv)[kMaxJoints], bool live, uint64_t emask, float *cen, float *sc_lds,
-                        float *fr, uint32_t *queue, unsigned long long *hitw, unsigned long long *dead, int lane,
-                        WorkCount &wc) {
-  const int nj = as_const(sc.nj)[m];
+__device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int l, const Frame &F, float3 c,
+                         bool live, uint64_t emask, float *fr, uint32_t *queue, unsigned long long *hitw,
+                         unsigned long long *dead, int lane, WorkCount &wc) {
   const int N = src.ns + src.nb;
-  bool hit = false;
+  const float4 cs = ld4(as_const(sc.coarse), m * kMaxLinks + l);
+  if (cs.w < 0.f) return false;  // a link without spheres
+  if (live) {
+    ++wc.links;
+    wc.env_tests += N;
+  }
+  if (N == 0) return false;
+  const float c2 = fmaf(c.z, c.z, fmaf(c.y, c.y, c.x * c.x));
   if (lane == 0) *hitw = 0ull;
-  if (live && part == 0) ++wc.chains;
+  fr[0 * kWave + lane] = F.r00; fr[1 * kWave + lane] = F.r01; fr[2 * kWave + lane] = F.r02;
+  fr[3 * kWave + lane] = F.t0;  fr[4 * kWave + lane] = F.r10; fr[5 * kWave + lane] = F.r11;
+  fr[6 * kWave + lane] = F.r12; fr[7 * kWave + lane] = F.t1;  fr[8 * kWave + lane] = F.r20;
+  fr[9 * kWave + lane] = F.r21; fr[10 * kWave + lane] = F.r22; fr[11 * kWave + lane] = F.t2;
+  const float4 csr = make_float4(cs.x, cs.y, cs.z, src.rad(m, l));
+  const uint64_t livem = __builtin_amdgcn_ballot_w64(live);
+  int qn = 0;  // wave-uniform queue length
+  for (int k0 = 0; k0 < src.n4; k0 += kGroup) {
+    float4 rw[kGroup];
+    src.group(m, l, k0, rw);
+    bool h[kGroup];
+    uint64_t b[kGroup], any = 0;
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) {
+      const float t = fmaf(c.z, rw[i].z, fmaf(c.y, rw[i].y, fmaf(c.x, rw[i].x, c2)));
+      h[i] = t < -rw[i].w;
+      b[i] = __builtin_amdgcn_ballot_w64(h[i]);
+      any |= b[i];
+    }
+    if ((any & livem) == 0ull) continue;
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) {
+      const uint64_t bi = b[i] & livem;
+      if (bi == 0ull) continue;
+      if (h[i] && live)
+        queue[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(bi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bi, 0u))] =
+            (uint32_t)lane | ((uint32_t)(k0 + i) << 6);
+      qn += __popcll(bi);
+    }
+    if (qn > kQueueFlushAt) {
+      flush_queue<STAGED>(src, m, l, csr, fr, queue, qn, hitw, lane, wc);
+      qn = 0;
+    }
+  }
+  if (qn > 0) flush_queue<STAGED>(src, m, l, csr, fr, queue, qn, hitw, lane, wc);
+  const bool hit = live && ((*hitw >> lane) & 1ull);
+  if (hit) atomicOr(dead, (unsigned long long)emask);
+  return hit;
+}
+
+// Kinematic chain of arm r (model m) at every lane's state: every link's
+// frame in turn (modified DH), its coarse centre published in LDS for the
+// later stages, and with sc_lds the joints' sines and cosines cached there.
+// visit(l, F, c) runs at each link.
+template <class Visit>
+__device__ void arm_chain(const SceneDev &sc, int r, int m, const float (&qv)[kMaxJoints], float *cen, float *sc_lds,
+                          int lane, Visit &&visit) {
+  const int nj = as_const(sc.nj)[m];
   Frame F = base_frame(sc, r);
   for (int l = 0; l <= nj; ++l) {
     if (l > 0) {
       float sn, cs;
       sincosf(qv[l - 1] + as_const(sc.theta_off)[m * kMaxJoints + l - 1], &sn, &cs);
       joint_step_sc(F, ld4(as_const(sc.dh), m * kMaxJoints + l - 1), sn, cs);
-      if (sc_lds) {  // cached for the arm-pair stage (every wave of the arm writes the same values)
+      if (sc_lds) {
         float *q = sc_lds + ((r * kMaxJoints + l - 1) * 2) * kWave + lane;
         q[0] = sn;
         q[kWave] = cs;
       }
     }
-    if (l % S != part) continue;  // another wave tests this link
+    const float4 co = ld4(as_const(sc.coarse), m * kMaxLinks + l);
+    const float3 c = apply(F, co.x, co.y, co.z);
+    float *slot = cen + ((r * kMaxLinks + l) * 3) * kWave + lane;
+    slot[0] = c.x;
+    slot[kWave] = c.y;
+    slot[2 * kWave] = c.z;
+    if (!visit(l, F, c)) break;
+  }
+}
+
+// Environment stage of arm r (model m) for the links l with l % S == part
+// (static split: every wave of the arm runs the whole chain and tests its own
+// links).  Returns true for lanes whose state collides.
+template <bool STAGED>
+__device__ bool arm_env(const SceneDev &sc, const Src<STAGED> &src, int r, int m, int part, int S,
+                        const float (&qv)[kMaxJoints], bool live, uint64_t emask, float *cen, float *sc_lds,
+                        float *fr, uint32_t *queue, unsigned long long *hitw, unsigned long long *dead, int lane,
+                        WorkCount &wc) {
+  bool hit = false;
+  if (live && part == 0) ++wc.chains;
+  arm_chain(sc, r, m, qv, cen, sc_lds, lane, [&](int l, const Frame &F, float3 c) {
+    if (l % S != part) return true;  // another wave tests this link
     live = live && !((dead_mask(dead) >> lane) & 1ull);
-    if (__ballot(live) == 0ull) break;  // nothing left to test in this wave
-    const float4 cs = ld4(as_const(sc.coarse), m * kMaxLinks + l);
-    const float3 c = apply(F, cs.x, cs.y, cs.z);
-    {
-      float *slot = cen + ((r * kMaxLinks + l) * 3) * kWave + lane;
-      slot[0] = c.x;
-      slot[kWave] = c.y;
-      slot[2 * kWave] = c.z;
-    }
-    if (cs.w < 0.f) continue;  // a link without spheres
-    const float c2 = fmaf(c.z, c.z, fmaf(c.y, c.y, c.x * c.x));
-    if (live) {
-      ++wc.links;
-      wc.env_tests += N;
-    }
-    fr[0 * kWave + lane] = F.r00; fr[1 * kWave + lane] = F.r01; fr[2 * kWave + lane] = F.r02;
-    fr[3 * kWave + lane] = F.t0;  fr[4 * kWave + lane] = F.r10; fr[5 * kWave + lane] = F.r11;
-    fr[6 * kWave + lane] = F.r12; fr[7 * kWave + lane] = F.t1;  fr[8 * kWave + lane] = F.r20;
-    fr[9 * kWave + lane] = F.r21; fr[10 * kWave + lane] = F.r22; fr[11 * kWave + lane] = F.t2;
-    if (N == 0) continue;
-    const float4 csr = make_float4(cs.x, cs.y, cs.z, src.rad(m, l));
-    const uint64_t livem = __builtin_amdgcn_ballot_w64(live);
-    int qn = 0;  // wave-uniform queue length
-    for (int k0 = 0; k0 < src.n4; k0 += kGroup) {
-      float4 rw[kGroup];
-      src.group(m, l, k0, rw);
-      bool h[kGroup];
-      uint64_t b[kGroup], any = 0;
-#pragma unroll
-      for (int i = 0; i < kGroup; ++i) {
-        const float t = fmaf(c.z, rw[i].z, fmaf(c.y, rw[i].y, fmaf(c.x, rw[i].x, c2)));
-        h[i] = t < -rw[i].w;
-        b[i] = __builtin_amdgcn_ballot_w64(h[i]);
-        any |= b[i];
-      }
-      if ((any & livem) == 0ull) continue;
-#pragma unroll
-      for (int i = 0; i < kGroup; ++i) {
-        const uint64_t bi = b[i] & livem;
-        if (bi == 0ull) continue;
-        if (h[i] && live)
-          queue[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(bi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bi, 0u))] =
-              (uint32_t)lane | ((uint32_t)(k0 + i) << 6);
-        qn += __popcll(bi);
-      }
-      if (qn > kQueueFlushAt) {
-        flush_queue<STAGED>(src, m, l, csr, fr, queue, qn, hitw, lane, wc);
-        qn = 0;
-      }
-    }
-    if (qn > 0) flush_queue<STAGED>(src, m, l, csr, fr, queue, qn, hitw, lane, wc);
-    if (!hit && ((*hitw >> lane) & 1ull)) {
+    if (__ballot(live) == 0ull) return false;  // nothing left to test in this wave
+    if (link_env<STAGED>(sc, src, m, l, F, c, live, emask, fr, queue, hitw, dead, lane, wc)) {
       hit = true;
       live = false;
-      atomicOr(dead, (unsigned long long)emask);
     }
-  }
+    return true;
+  });
   return hit;
 }
 
@@ -634,7 +658,7 @@ __device__ __forceinline__ LaneState lane_state_of(const LaneState &st, int s) {
   return o;
 }
 
-template <bool STAGED>
+template <bool STAGED, bool CACHE>
 __device__ void flush_pairs(const SceneDev &sc, const Src<STAGED> &src, const float *cen, const float *sc_lds,
                             const LaneState &st, const uint32_t *queue, int qn, unsigned long long *hitw, int lane,
                             WorkCount &wc) {
@@ -644,7 +668,7 @@ __device__ void flush_pairs(const SceneDev &sc, const Src<STAGED> &src, const fl
     const uint32_t item = i < qn ? queue[i] : 0u;
     const int s = (int)(item & (kWave - 1)), a = (int)((item >> 6) & 7u), b = (int)((item >> 9) & 7u);
     const int p = (int)(item >> 12);
-    const LaneState ls = sc_lds ? st : lane_state_of(st, s);  // all lanes active here
+    const LaneState ls = CACHE ? st : lane_state_of(st, s);  // all lanes active here
     if (i >= qn) continue;
     const int ai = sc.pairs[2 * p], aj = sc.pairs[2 * p + 1];
     const int mi = sc.model[ai], mj = sc.model[aj];
@@ -652,8 +676,8 @@ __device__ void flush_pairs(const SceneDev &sc, const Src<STAGED> &src, const fl
     const float *pb = cen + ((aj * kMaxLinks + b) * 3) * kWave + s;
     const float4 ca = make_float4(pa[0], pa[kWave], pa[2 * kWave], src.rad(mi, a));
     const float4 cb = make_float4(pb[0], pb[kWave], pb[2 * kWave], src.rad(mj, b));
-    const Frame Fa = sc_lds ? frame_cached(sc, ai, mi, a, s, sc_lds) : frame_rebuilt(sc, ai, mi, a, ls);
-    const Frame Fb = sc_lds ? frame_cached(sc, aj, mj, b, s, sc_lds) : frame_rebuilt(sc, aj, mj, b, ls);
+    const Frame Fa = CACHE ? frame_cached(sc, ai, mi, a, s, sc_lds) : frame_rebuilt(sc, ai, mi, a, ls);
+    const Frame Fb = CACHE ? frame_cached(sc, aj, mj, b, s, sc_lds) : frame_rebuilt(sc, aj, mj, b, ls);
     const int x0 = src.ls(mi, a), x1 = src.ls(mi, a + 1), y0 = src.ls(mj, b), y1 = src.ls(mj, b + 1);
     // spheres of link b within reach of link a's coarse sphere (links with
     // more than 64 spheres keep the rest unfiltered)
@@ -696,7 +720,7 @@ __device__ void flush_pairs(const SceneDev &sc, const Src<STAGED> &src, const fl
 // centres for the link pairs the pair's static mask allows, flagged (lane,
 // pair, a, b) items queued and tested by flush_pairs.  Returns true for lanes
 // whose state collides.
-template <bool STAGED>
+template <bool STAGED, bool CACHE>
 __device__ bool arm_pairs(const SceneDev &sc, const Src<STAGED> &src, const float *cen, const float *sc_lds, int w,
                           int W, bool live, const LaneState &st, uint64_t emask, uint32_t *queue,
                           unsigned long long *hitw, unsigned long long *dead, int lane, WorkCount &wc) {
@@ -728,12 +752,12 @@ __device__ bool arm_pairs(const SceneDev &sc, const Src<STAGED> &src, const floa
             (uint32_t)lane | ((uint32_t)a << 6) | ((uint32_t)b << 9) | ((uint32_t)p << 12);
       qn += __popcll(bm);
       if (qn > kQueueFlushAt) {
-        flush_pairs<STAGED>(sc, src, cen, sc_lds, st, queue, qn, hitw, lane, wc);
+        flush_pairs<STAGED, CACHE>(sc, src, cen, sc_lds, st, queue, qn, hitw, lane, wc);
         qn = 0;
       }
     }
   }
-  if (qn > 0) flush_pairs<STAGED>(sc, src, cen, sc_lds, st, queue, qn, hitw, lane, wc);
+  if (qn > 0) flush_pairs<STAGED, CACHE>(sc, src, cen, sc_lds, st, queue, qn, hitw, lane, wc);
   const bool hit = live && ((*hitw >> lane) & 1ull);
   if (hit) atomicOr(dead, (unsigned long long)emask);
   return hit;
@@ -793,52 +817,97 @@ __device__ __forceinline__ TileLanes map_lanes(int64_t s0, int64_t total, int64_
   return t;
 }
 
-// One tile on the whole workgroup: the environment jobs (arm, link part)
-// over the waves, a barrier, the arm-pair stage, the edge flag (a colliding
-// edge's flag word is set to hit_token; states of an edge whose word already
-// holds it are skipped); ends with a barrier (the tile's LDS is reused by the
-// next one).
-template <bool STAGED>
+// Joint values of arm r at the lane's state (all loads first, so that they
+// overlap).
+__device__ __forceinline__ void arm_joints(const SceneDev &sc, const LaneState &st, int r, int nj,
+                                           float (&qv)[kMaxJoints]) {
+  const int q0 = as_const(sc.q_off)[r];
+  float qa_v[kMaxJoints], qb_v[kMaxJoints];
+#pragma unroll
+  for (int j = 0; j < kMaxJoints; ++j) {
+    const int idx = j < nj ? q0 + j : q0;
+    qa_v[j] = st.qa[idx];
+    qb_v[j] = st.qb[idx];
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxJoints; ++j) qv[j] = st.last ? qb_v[j] : fmaf(st.t, qb_v[j] - qa_v[j], qa_v[j]);
+}
+
+// One tile on the whole workgroup, then the edge flag (a colliding edge's
+// flag word is set to hit_token; states of an edge whose word already holds
+// it are skipped); ends with a barrier (the tile's LDS is reused by the next
+// one).
+//
+// With the joints' sines and cosines cached in LDS (sc_lds), the
+// environment stage is balanced at run time: waves first build the arms'
+// kinematic chains (one wave per arm; centres and sines and cosines into
+// LDS), then, after a barrier, claim (arm, link) jobs from an LDS counter in
+// the order of decreasing link size, each rebuilding its link's frame from
+// the cached values (the same operations as the chain, so the same frame).
+// Without the cache, every wave runs whole chains for its (arm, link part)
+// jobs.  Both end with a barrier before the arm-pair stage.
+template <bool STAGED, bool CACHE>
 __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int w, int W, int lane, int it,
                           const TileLanes &tl, uint32_t *flags, float *cen, float *sc_lds, float *wave_fr,
-                          uint32_t *wave_q, unsigned long long *s_dead, unsigned long long *s_hit, WorkCount &wc,
-                          uint32_t &checked, uint32_t hit_token) {
+                          uint32_t *wave_q, unsigned long long *s_dead, unsigned long long *s_hit, int *s_next,
+                          WorkCount &wc, uint32_t &checked, uint32_t hit_token) {
   unsigned long long *const dead = &s_dead[it & 1];
   const LaneState &st = tl.st;
   bool act = tl.act;
   const int R = sc.n_robots;
   bool hit = false;
+  if constexpr (CACHE) {
+    // states of an edge that an earlier tile found colliding are skipped
+    if (act && load_relaxed(flags + tl.e) == hit_token) act = false;
+    if (threadIdx.x == 0) *s_next = 0;
+    for (int r = w; r < R; r += W) {
+      const int m = as_const(sc.model)[r];
+      const int nj = as_const(sc.nj)[m];
+      float qv[kMaxJoints];
+      arm_joints(sc, st, r, nj, qv);
+      if (act) ++wc.chains;
+      arm_chain(sc, r, m, qv, cen, sc_lds, lane, [](int, const Frame &, float3) { return true; });
+    }
+    __syncthreads();
+    const int n_jobs = R * kMaxLinks;
+    for (;;) {
+      int job = 0;
+      if (lane == 0) job = atomicAdd(s_next, 1);
+      job = __builtin_amdgcn_readfirstlane(__shfl(job, 0, kWave));
+      if (job >= n_jobs) break;
+      const int k = job / R, r = job - k * R;  // rank k of every arm, then rank k + 1
+      const int m = as_const(sc.model)[r];
+      const int l = as_const(sc.link_order)[m * kMaxLinks + k];
+      if (l > as_const(sc.nj)[m]) continue;
+      const bool live = act && !hit && !((dead_mask(dead) >> lane) & 1ull);
+      if (__ballot(live) == 0ull) continue;
+      const Frame F = frame_cached(sc, r, m, l, lane, sc_lds);
+      const float *p = cen + ((r * kMaxLinks + l) * 3) * kWave + lane;
+      const float3 c = make_float3(p[0], p[kWave], p[2 * kWave]);
+      if (link_env<STAGED>(sc, src, m, l, F, c, live, tl.emask, wave_fr, wave_q, &s_hit[w], dead, lane, wc))
+        hit = true;
+    }
+  } else {
   for (int jb = w; jb < R * S; jb += W) {
     const int r = jb / S, part = jb - r * S;
     const int m = as_const(sc.model)[r];
     const int nj = as_const(sc.nj)[m];
-    const int q0 = as_const(sc.q_off)[r];
-    // all joint values of the arm first, so that their loads overlap (with
-    // the edge's flag on the wave's first arm: states of an edge that an
-    // earlier tile found colliding are skipped)
     float qv[kMaxJoints];
-    {
-      float qa_v[kMaxJoints], qb_v[kMaxJoints];
-#pragma unroll
-      for (int j = 0; j < kMaxJoints; ++j) {
-        const int idx = j < nj ? q0 + j : q0;
-        qa_v[j] = st.qa[idx];
-        qb_v[j] = st.qb[idx];
-      }
-      if (jb == w && act && load_relaxed(flags + tl.e) == hit_token) act = false;
-#pragma unroll
-      for (int j = 0; j < kMaxJoints; ++j) qv[j] = st.last ? qb_v[j] : fmaf(st.t, qb_v[j] - qa_v[j], qa_v[j]);
-    }
+    arm_joints(sc, st, r, nj, qv);
+    // with the edge's flag on the wave's first arm: states of an edge that an
+    // earlier tile found colliding are skipped
+    if (jb == w && act && load_relaxed(flags + tl.e) == hit_token) act = false;
     const bool live = act && !hit;
     if (arm_env<STAGED>(sc, src, r, m, part, S, qv, live, tl.emask, cen, sc_lds, wave_fr, wave_q, &s_hit[w], dead,
                         lane, wc))
       hit = true;
   }
+  }
   if (act && w == 0) ++checked;
   __syncthreads();
   if (threadIdx.x == 0) s_dead[(it + 1) & 1] = 0ull;  // last used by the previous tile
   // arm pairs that can reach each other
-  if (arm_pairs<STAGED>(sc, src, cen, sc_lds, w, W, act && !hit, st, tl.emask, wave_q, &s_hit[w], dead, lane, wc))
+  if (arm_pairs<STAGED, CACHE>(sc, src, cen, sc_lds, w, W, act && !hit, st, tl.emask, wave_q, &s_hit[w], dead, lane, wc))
     hit = true;
   if (hit) flags[tl.e] = hit_token;
   __syncthreads();
@@ -865,17 +934,18 @@ __device__ void write_partials(uint64_t *partials, uint32_t checked, uint32_t ti
   if (threadIdx.x < kPartialSlots) partials[(int64_t)blockIdx.x * kPartialSlots + threadIdx.x] = s_part[threadIdx.x];
 }
 
-template <bool STAGED>
+template <bool STAGED, bool CACHE>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_kernel(
     SceneDev sc, const float *__restrict__ qa, const float *__restrict__ qb, int64_t n_edges,
     const int64_t *__restrict__ off, const int32_t *__restrict__ tile_first, uint32_t *__restrict__ flags,
-    uint64_t *__restrict__ counters, uint64_t *__restrict__ partials, int S, int cache_sc) {
+    uint64_t *__restrict__ counters, uint64_t *__restrict__ partials, int S) {
   // dynamic LDS: [R][kMaxLinks][3][64] published coarse centres, then per
   // wave kWaveLdsFloats (link frames, fine-test queue), then the staged scene
   extern __shared__ float cen[];
   // s_dead[t & 1]: lanes of tile t whose edge is known to collide (two
   // copies, so that the next tile's copy is cleared while this one is in use)
   __shared__ unsigned long long s_dead[2], s_hit[kMaxWavesPerBlock];
+  __shared__ int s_next;  // next (arm, link) job of the tile
   const int lane = threadIdx.x & (kWave - 1);
   // wave index, marked wave-uniform so that per-arm data is read with scalar loads
   const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave), W = blockDim.x / kWave;
@@ -889,10 +959,10 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
   uint32_t checked = 0, tiles = 0;
   WorkCount wc;
   if (threadIdx.x < 2) s_dead[threadIdx.x] = 0ull;
-  float *const sc_lds = cache_sc ? cen + (size_t)R * kMaxLinks * 3 * kWave : nullptr;
-  float *const wave_fr = cen + tile_shared_floats(R, cache_sc) + (size_t)w * kWaveLdsFloats;
+  float *const sc_lds = CACHE ? cen + (size_t)R * kMaxLinks * 3 * kWave : nullptr;
+  float *const wave_fr = cen + tile_shared_floats(R, CACHE) + (size_t)w * kWaveLdsFloats;
   uint32_t *const wave_q = (uint32_t *)(wave_fr + 12 * kWave);
-  const Src<STAGED> src = make_src<STAGED>(sc, cen + tile_shared_floats(R, cache_sc) + (size_t)W * kWaveLdsFloats);
+  const Src<STAGED> src = make_src<STAGED>(sc, cen + tile_shared_floats(R, CACHE) + (size_t)W * kWaveLdsFloats);
   // Static order: workgroup b takes tiles b, b + G, b + 2G, ... (G = grid).
   // A shared work queue would need a device-wide atomic per tile, whose round
   // trip across the chip's eight XCDs costs more than a tile's setup.  The
@@ -919,7 +989,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
     }
     if (w == 0) ++tiles;
     const TileLanes tl = map_lanes(tile * kWave, total, e0, my_off, off, 0, 0, qa, qb, sc.dof, lane);
-    tile_work<STAGED>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, wc,
+    tile_work<STAGED, CACHE>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, &s_next, wc,
                       checked, kFlagHit);
   }
   write_partials(partials, checked, tiles, wc, w, lane);
@@ -937,14 +1007,15 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
 // last workgroup to finish (a device-wide arrival counter) writes the bits
 // and the counters and resets the counter: one launch where the general path
 // makes three.  Workgroups never wait for each other.
-template <bool STAGED>
+template <bool STAGED, bool CACHE>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_kernel(
     SceneDev sc, const float *__restrict__ qa, const float *__restrict__ qb, int n_edges,
     const int32_t *__restrict__ codes, uint32_t *__restrict__ flags, uint32_t token, uint8_t *__restrict__ out,
     uint64_t *__restrict__ counters, uint64_t *__restrict__ partials, uint32_t *__restrict__ arrived,
-    uint64_t *__restrict__ totals, int S, int cache_sc) {
+    uint64_t *__restrict__ totals, int S) {
   extern __shared__ float cen[];
   __shared__ unsigned long long s_dead[2], s_hit[kMaxWavesPerBlock];
+  __shared__ int s_next;  // next (arm, link) job of the tile
   __shared__ int64_t s_off[kFusedMaxEdges + 1];
   __shared__ unsigned long long s_sum[kPartialSlots + 3];
   __shared__ int s_last;
@@ -970,18 +1041,18 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
   if ((int64_t)blockIdx.x < n_tiles) {
     uint32_t checked = 0, tiles = 0;
     WorkCount wc;
-    float *const sc_lds = cache_sc ? cen + (size_t)R * kMaxLinks * 3 * kWave : nullptr;
-    float *const wave_fr = cen + tile_shared_floats(R, cache_sc) + (size_t)w * kWaveLdsFloats;
+    float *const sc_lds = CACHE ? cen + (size_t)R * kMaxLinks * 3 * kWave : nullptr;
+    float *const wave_fr = cen + tile_shared_floats(R, CACHE) + (size_t)w * kWaveLdsFloats;
     uint32_t *const wave_q = (uint32_t *)(wave_fr + 12 * kWave);
     const Src<STAGED> src =
-        make_src<STAGED>(sc, cen + tile_shared_floats(R, cache_sc) + (size_t)W * kWaveLdsFloats);
+        make_src<STAGED>(sc, cen + tile_shared_floats(R, CACHE) + (size_t)W * kWaveLdsFloats);
     int it = 0;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, ++it) {
       const int64_t e0 = find_edge(s_off, n_edges, tile * kWave);
       const int64_t my_off = s_off[e0 + lane < n_edges ? e0 + lane : n_edges];
       if (w == 0) ++tiles;
       const TileLanes tl = map_lanes(tile * kWave, total, e0, my_off, s_off, 0, 0, qa, qb, sc.dof, lane);
-      tile_work<STAGED>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, wc,
+      tile_work<STAGED, CACHE>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, &s_next, wc,
                         checked, token);
     }
     write_partials(partials, checked, tiles, wc, w, lane);
@@ -1131,12 +1202,14 @@ __global__ __launch_bounds__(256) void seg_table_kernel(const ValSeg *__restrict
   }
 }
 
+template <bool CACHE>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_segments_kernel(
     const ValSeg *__restrict__ segs, const int64_t *__restrict__ off, const int32_t *__restrict__ tile_first,
     const int32_t *__restrict__ tile_seg, uint32_t *__restrict__ flags, const uint64_t *__restrict__ batch,
-    uint64_t *__restrict__ partials, int r_max, int cache_sc) {
+    uint64_t *__restrict__ partials, int r_max) {
   extern __shared__ float cen[];
   __shared__ unsigned long long s_dead[2], s_hit[kMaxWavesPerBlock];
+  __shared__ int s_next;  // next (arm, link) job of the tile
   const int lane = threadIdx.x & (kWave - 1);
   const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave), W = blockDim.x / kWave;
   int64_t n_tiles = (int64_t)batch[1];
@@ -1149,8 +1222,8 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_segment
   }
   if (threadIdx.x < 2) s_dead[threadIdx.x] = 0ull;
   __syncthreads();
-  float *const sc_lds = cache_sc ? cen + (size_t)r_max * kMaxLinks * 3 * kWave : nullptr;
-  float *const wave_fr = cen + tile_shared_floats(r_max, cache_sc) + (size_t)w * kWaveLdsFloats;
+  float *const sc_lds = CACHE ? cen + (size_t)r_max * kMaxLinks * 3 * kWave : nullptr;
+  float *const wave_fr = cen + tile_shared_floats(r_max, CACHE) + (size_t)w * kWaveLdsFloats;
   uint32_t *const wave_q = (uint32_t *)(wave_fr + 12 * kWave);
   const int64_t G = gridDim.x;
   int it = 0;
@@ -1167,7 +1240,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_segment
     if (w == 0) ++tiles;
     const TileLanes tl = map_lanes((tile - g.tile0) * kWave, total, e0, my_off, off, base, g.edge0, g.qa, g.qb,
                                    sc.dof, lane);
-    tile_work<false>(sc, src, g.S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, wc,
+    tile_work<false, CACHE>(sc, src, g.S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, &s_next, wc,
                      checked, kFlagHit);
   }
   write_partials(partials, checked, tiles, wc, w, lane);
@@ -1296,9 +1369,24 @@ static bool use_staged(const SceneDev &sc, const TileShape &ts) {
   return kLdsPerCu / staged >= kLdsPerCu / base;
 }
 
+// Calls go(staged, cache) with both as compile-time constants
+// (std::integral_constant), one kernel instance per combination.
+template <class Go>
+static void dispatch_tile(bool staged, bool cache, Go &&go) {
+  using T = std::true_type;
+  using F = std::false_type;
+  if (staged) {
+    if (cache) go(T{}, T{});
+    else go(T{}, F{});
+  } else {
+    if (cache) go(F{}, T{});
+    else go(F{}, F{});
+  }
+}
+
 // Resident workgroups for a persistent launch (cached per block size, staging
 // and LDS size).
-template <bool STAGED>
+template <bool STAGED, bool CACHE>
 static int persistent_grid(int W, size_t lds) {
   struct Key {
     int w;
@@ -1311,7 +1399,7 @@ static int persistent_grid(int W, size_t lds) {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_tiles_kernel<STAGED>, kWave * W, lds);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_tiles_kernel<STAGED, CACHE>, kWave * W, lds);
   const int grid = std::min(kMaxGrid, std::max(1, cus) * std::max(1, per));
   cache.push_back({W, lds, grid});
   return grid;
@@ -1340,25 +1428,24 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
   const bool staged = use_staged(sc, ts);
   const size_t lds =
       centre_lds_bytes(sc.n_robots, ts.W, ts.cache_sc) + (staged ? staged_floats(sc) * sizeof(float) : 0);
-  const int grid = staged ? persistent_grid<true>(ts.W, lds) : persistent_grid<false>(ts.W, lds);
-  if (grid_out) *grid_out = grid;
-  if (block_out) *block_out = kWave * ts.W;
   // with events: recorded by the dispatch itself, at the kernel's start and end
   hipEvent_t e0 = ev_pair ? ev_pair->first : nullptr, e1 = ev_pair ? ev_pair->second : nullptr;
-  if (staged)
-    hipExtLaunchKernelGGL(validate_tiles_kernel<true>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
-                          sc, qa, qb, n_edges, ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials, ts.S,
-                          ts.cache_sc);
-  else
-    hipExtLaunchKernelGGL(validate_tiles_kernel<false>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
-                          sc, qa, qb, n_edges, ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials, ts.S,
-                          ts.cache_sc);
+  int grid = 0;
+  auto go = [&](auto staged_c, auto cache_c) {
+    constexpr bool ST = decltype(staged_c)::value, CA = decltype(cache_c)::value;
+    grid = persistent_grid<ST, CA>(ts.W, lds);
+    hipExtLaunchKernelGGL(validate_tiles_kernel<ST, CA>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
+                          sc, qa, qb, n_edges, ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials, ts.S);
+  };
+  dispatch_tile(staged, ts.cache_sc != 0, go);
+  if (grid_out) *grid_out = grid;
+  if (block_out) *block_out = kWave * ts.W;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)g256), dim3(256), 0, s, ws.flags, n_edges, out_valid,
                      ws.counters, ws.partials, grid, totals);
   return hipGetLastError();
 }
 
-template <bool STAGED>
+template <bool STAGED, bool CACHE>
 static int small_grid(int W, size_t lds) {
   struct Key {
     int w;
@@ -1371,7 +1458,7 @@ static int small_grid(int W, size_t lds) {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_small_kernel<STAGED>, kWave * W, lds);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_small_kernel<STAGED, CACHE>, kWave * W, lds);
   const int grid = std::min(kMaxGrid, std::max(1, cus) * std::max(1, per));
   cache.push_back({W, lds, grid});
   return grid;
@@ -1388,18 +1475,18 @@ hipError_t launch_validate_small(const SceneDev &sc, const float *qa, const floa
   const bool staged = use_staged(sc, ts);
   const size_t lds =
       centre_lds_bytes(sc.n_robots, ts.W, ts.cache_sc) + (staged ? staged_floats(sc) * sizeof(float) : 0);
-  const int grid = staged ? small_grid<true>(ts.W, lds) : small_grid<false>(ts.W, lds);
+  hipEvent_t e0 = ev_pair ? ev_pair->first : nullptr, e1 = ev_pair ? ev_pair->second : nullptr;
+  int grid = 0;
+  auto go = [&](auto staged_c, auto cache_c) {
+    constexpr bool ST = decltype(staged_c)::value, CA = decltype(cache_c)::value;
+    grid = small_grid<ST, CA>(ts.W, lds);
+    hipExtLaunchKernelGGL(validate_small_kernel<ST, CA>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
+                          sc, qa, qb, (int)n_edges, codes, ws.flags, token, out_valid, ws.counters, ws.partials,
+                          arrived, totals, ts.S);
+  };
+  dispatch_tile(staged, ts.cache_sc != 0, go);
   if (grid_out) *grid_out = grid;
   if (block_out) *block_out = kWave * ts.W;
-  hipEvent_t e0 = ev_pair ? ev_pair->first : nullptr, e1 = ev_pair ? ev_pair->second : nullptr;
-  if (staged)
-    hipExtLaunchKernelGGL(validate_small_kernel<true>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
-                          sc, qa, qb, (int)n_edges, codes, ws.flags, token, out_valid, ws.counters, ws.partials,
-                          arrived, totals, ts.S, ts.cache_sc);
-  else
-    hipExtLaunchKernelGGL(validate_small_kernel<false>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
-                          sc, qa, qb, (int)n_edges, codes, ws.flags, token, out_valid, ws.counters, ws.partials,
-                          arrived, totals, ts.S, ts.cache_sc);
   return hipGetLastError();
 }
 
@@ -1454,6 +1541,7 @@ void seg_shape(int r_max, int64_t n_flat, int *W, int *cache_sc) {
   *cache_sc = ts.cache_sc;
 }
 
+template <bool CACHE>
 static int segments_grid(int W, size_t lds) {
   struct Key {
     int w;
@@ -1466,7 +1554,7 @@ static int segments_grid(int W, size_t lds) {
   int dev = 0, cus = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_segments_kernel, kWave * W, lds);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_segments_kernel<CACHE>, kWave * W, lds);
   const int grid = std::min(kMaxGrid, std::max(1, cus) * std::max(1, per));
   cache.push_back({W, lds, grid});
   return grid;
@@ -1492,12 +1580,17 @@ hipError_t launch_validate_segments(ValSeg *d_segs, int n_segs, int r_max, int64
   int W = 0, cache = 0;
   seg_shape(r_max, n_flat, &W, &cache);
   const size_t lds = centre_lds_bytes(r_max, W, cache);
-  const int grid = segments_grid(W, lds);
+  hipEvent_t e0 = ev_pair ? ev_pair->first : nullptr, e1 = ev_pair ? ev_pair->second : nullptr;
+  int grid = 0;
+  auto go = [&](auto, auto cache_c) {
+    constexpr bool CA = decltype(cache_c)::value;
+    grid = segments_grid<CA>(W, lds);
+    hipExtLaunchKernelGGL(validate_segments_kernel<CA>, dim3(grid), dim3(kWave * W), (uint32_t)lds, s, e0, e1, 0,
+                          d_segs, ws.offsets, ws.tile_first, ws.tile_seg, ws.flags, ws.batch, ws.partials, r_max);
+  };
+  dispatch_tile(false, cache != 0, go);
   if (grid_out) *grid_out = grid;
   if (block_out) *block_out = kWave * W;
-  hipEvent_t e0 = ev_pair ? ev_pair->first : nullptr, e1 = ev_pair ? ev_pair->second : nullptr;
-  hipExtLaunchKernelGGL(validate_segments_kernel, dim3(grid), dim3(kWave * W), (uint32_t)lds, s, e0, e1, 0, d_segs,
-                        ws.offsets, ws.tile_first, ws.tile_seg, ws.flags, ws.batch, ws.partials, r_max, cache);
   hipLaunchKernelGGL(seg_finalize_kernel, dim3((unsigned)g256), dim3(256), 0, s, d_segs, n_flat, ws.flags,
                      ws.edge_seg, ws.partials, grid, totals);
   return hipGetLastError();

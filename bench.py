@@ -328,7 +328,7 @@ def main():
                 "traffic": counted["traffic_bytes_per_launch"] if counted else None, "traffic_unit": "bytes/launch",
                 "traffic_note": traffic_note,
                 "valu_fp32_flops_per_launch": counted["valu_fp32_flops_per_launch"] if counted else None,
-                "kernel": "validate_tiles_kernel + validate_segments_kernel", "launches": prof.launches,
+                "kernel": "validate_tiles_kernel + validate_small_kernel + validate_segments_kernel", "launches": prof.launches,
                 "avg_launch_us": prof.kernel_ms * 1e3 / max(1, prof.launches),
                 "flops_per_launch": flops / max(1, prof.launches),
                 "grid": [prof.grid_blocks, prof.block_threads], "work": prof.work}

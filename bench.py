@@ -53,11 +53,17 @@ KERNEL_SOURCES = ("validate.hip", "device_common.h", "mrpop_internal.h")
 
 
 def kernel_digest() -> str:
+    """Digest of the kernel sources' code (comments and whitespace removed,
+    so that only a change of code voids the recorded counters)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2609_30644_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2609_30644_amd", "csrc", name), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -6,27 +6,28 @@
 // persistent workgroups take tiles of 64 consecutive list positions in a
 // static grid-stride order.
 //
-// Mapping: one lane per state.  A workgroup has W = min(R S, 8) waves, where
-// S = 2 splits every arm's links over two waves when 2 R <= 8 (S = 1
-// otherwise); wave w runs the (arm, link part) jobs w, w + W, ... over the
-// tile's 64 states, so every wave works on one arm at a time and all of that
-// arm's model data is wave-uniform (scalar loads), while consecutive states
-// of an edge sit in neighbouring lanes and take the same branches.  Per arm, link by link:
-//   1. compose the link frame (modified DH) in registers, publish the link's
-//      coarse centre in LDS (for the arm-pair stage) and the frame in the
-//      wave's LDS slot;
-//   2. test the coarse sphere against every obstacle (environment spheres
-//      and the bounding spheres of boxes) in expanded form: three FMAs from
-//      |c|^2 and a compare against a per-(link, obstacle) row, four obstacles
-//      per step, with the wave's compare masks kept in scalar registers;
-//   3. append the flagged (lane, obstacle) pairs to a per-wave LDS queue and
-//      test them one pair per lane (exact link-box distance for boxes, then
-//      the link's fine spheres), so that the rare flagged pairs do not make
-//      the whole wave wait on a few lanes.
-// After a barrier, the arm pairs that can reach each other are split over the
-// waves as (pair, link of the first arm) items: coarse link-link tests from
-// the LDS centres, and for flagged link pairs the two frames are rebuilt and
-// the fine spheres tested.
+// Mapping: one lane per state; a workgroup of W waves (up to 16) works on
+// one tile at a time, and every arm's data is wave-uniform (scalar loads or
+// LDS broadcasts) while consecutive states of an edge sit in neighbouring
+// lanes and take the same branches.
+//   1. Chains: the arms' link frames (modified DH) are composed in registers;
+//      every link's coarse centre and (when they fit) the joints' sines and
+//      cosines are published in LDS.
+//   2. Environment jobs (arm, link), claimed from an LDS counter, largest
+//      links first (or, without the cached sines and cosines, a static split
+//      of every arm's links over S waves): the coarse sphere against every
+//      obstacle (environment spheres and the bounding spheres of boxes) in
+//      expanded form -- three FMAs from |c|^2 and a compare against a
+//      per-(link, obstacle) row, four obstacles per step, compare masks in
+//      scalar registers; flagged (lane, obstacle) pairs go to a per-wave LDS
+//      queue and are tested one pair per lane (exact link-box distance for
+//      boxes, then the link's fine spheres), so that the rare flagged pairs
+//      do not make the whole wave wait on a few lanes.
+//   3. After a barrier, the arm pairs that can reach each other are split
+//      over the waves as (pair, link of the first arm) items: coarse
+//      link-link tests from the LDS centres for the link pairs the pair's
+//      static mask allows, and for flagged link pairs the two frames are
+//      rebuilt and the fine spheres tested.
 // A collision marks the edge in a flag word and marks all of the edge's lanes
 // of the tile in an LDS mask, which the other waves read as they go; states of
 // an edge already marked by an earlier tile are skipped.

@@ -214,6 +214,30 @@ SERVE_PLAN = dict(candidates=64, n_roadmap=16, delta=3.0, resolution=0.05, max_r
                   stop_at_first=1, max_tree_nodes=8192, max_roadmap_nodes=2048, time_budget_s=2.0)
 
 
+def history_leg(s, q_start, q_goal, res: float, n: int) -> dict:
+    """Incumbent-history export: the same n plans (seeds 0..n-1) with and
+    without mrpop_plan_with_history; entries found and written, and the time
+    of both."""
+    t_with, t_without, entries, written, same = 0.0, 0.0, [], [], True
+    for seed in range(n):
+        kw = dict(PLAN, seed=seed, resolution=res)
+        t0 = time.perf_counter()
+        a = s.plan(q_start, q_goal, raise_on_error=False, **kw)
+        t1 = time.perf_counter()
+        b, hist, found = s.plan_with_history(q_start, q_goal, max_entries=16, max_waypoints=4096,
+                                             raise_on_error=False, **kw)
+        t2 = time.perf_counter()
+        t_without += t1 - t0
+        t_with += t2 - t1
+        entries.append(found)
+        written.append(len(hist))
+        same = same and a.status == b.status and a.cost == b.cost and (not hist or hist[0].cost == b.cost)
+    return {"plans": n, "incumbents_mean": float(np.mean(entries)), "incumbents_max": int(np.max(entries)),
+            "written_mean": float(np.mean(written)), "ms_per_plan_with": t_with * 1e3 / n,
+            "ms_per_plan_without": t_without * 1e3 / n, "same_plans": bool(same),
+            "buffers": {"max_entries": 16, "max_waypoints": 4096}}
+
+
 def served(ctx, rate_hz: float, duration_s: float, slots: int, mem_gb: float) -> dict:
     """Poisson arrivals of queries (2-16 arms, 32-512 obstacles) submitted to
     a continuous-batching server on the wall clock; latency is arrival ->
@@ -270,6 +294,8 @@ def main():
     ap.add_argument("--no-plan", action="store_true", help="validation batches only")
     ap.add_argument("--batch-instances", type=int, default=64,
                     help="instances of the batched-vs-plain comparison (0: skip)")
+    ap.add_argument("--history-plans", type=int, default=10,
+                    help="plans timed with and without the incumbent-history export (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the served run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of the served run")
     ap.add_argument("--serve-slots", type=int, default=128)
@@ -361,6 +387,9 @@ def main():
                         "edge_states_per_plan": plan_states / len(plans),
                         "params": PLAN}
         line["config"]["plan"] = "one mrpop_plan per step, seed = step index"
+    if plans and args.history_plans > 0:
+        print("[bench] incumbent history", file=sys.stderr, flush=True)
+        line["history"] = history_leg(s, q_start, q_goal, res, args.history_plans)
     if args.batch_instances > 0:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         line["batched"] = batched_vs_plain(ctx, args.batch_instances)

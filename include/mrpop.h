@@ -247,6 +247,35 @@ typedef struct {
   float costs[64];           /* incumbent cost after each improvement */
 } mrpop_plan_stats;
 
+/* Incumbent history (paper, Sec. "Seeding for Multi-Robot Jerk-Free
+ * Motion": the paths found while the cost bound shrinks serve as seeds for a
+ * local trajectory optimiser, cheaper paths first when there are more paths
+ * than seeds).  Every host array is the caller's; mrpop_plan_with_history
+ * writes the incumbents ranked by cost, cheapest first, as many as fit in
+ * both entry_cap and waypoint_cap (the cheapest ones: a ranked prefix).
+ *   waypoints    host [waypoint_cap][D]: the entries' paths back to back,
+ *                each start to goal.
+ *   offsets      host [entry_cap + 1]: entry k occupies rows
+ *                offsets[k] .. offsets[k + 1] - 1.
+ *   costs        host [entry_cap]: each entry's cost (sum of Euclidean
+ *                waypoint steps, recomputed in double precision).
+ *   found_s      host [entry_cap] or NULL: seconds from the call's start to
+ *                the entry's discovery.
+ *   found_round  host [entry_cap] or NULL: search round of the discovery.
+ *   n_entries    out: incumbents found in the call (may exceed n_written).
+ *   n_written    out: entries written. */
+typedef struct {
+  float *waypoints;
+  int64_t waypoint_cap;
+  int32_t *offsets;
+  float *costs;
+  double *found_s;
+  int32_t *found_round;
+  int32_t entry_cap;
+  int32_t n_entries;
+  int32_t n_written;
+} mrpop_plan_history;
+
 /* Defaults: seed 0, delta 3.0, n_roadmap 32, candidates 128, resolution
  * 0.05, max_rounds 1000, max_iterations 8, max_growth_rounds 16, no time
  * budget, 65536 tree and 8192 roadmap vertices, stop_at_first 0, no warm
@@ -269,6 +298,16 @@ void mrpop_plan_params_default(mrpop_plan_params *p);
 mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
                         const mrpop_plan_params *params, float *path_out, int32_t path_cap, int32_t *path_len,
                         float *cost_out, mrpop_plan_stats *stats_opt);
+
+/* mrpop_plan that also returns the incumbent history (above).  hist must not
+ * be NULL; its arrays may be NULL only when entry_cap (offsets, costs) or
+ * waypoint_cap (waypoints) is 0.  The plan's own status and outputs are those
+ * of mrpop_plan; the history is written whenever the plan ran (also with
+ * E_NO_SOLUTION, then empty). */
+mrpop_status mrpop_plan_with_history(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start,
+                                     const float *q_goal, const mrpop_plan_params *params, float *path_out,
+                                     int32_t path_cap, int32_t *path_len, float *cost_out,
+                                     mrpop_plan_stats *stats_opt, mrpop_plan_history *hist);
 
 /* ------------------------------------------------------------------------ */
 /* Batched planning: many independent instances at once                     */

@@ -77,6 +77,8 @@ class PlanResult:
     edge_states: int = 0
     roadmaps: list = field(default_factory=list)
     last_search_solved: bool = False
+    # every incumbent in discovery order: (cost, path start to goal, round)
+    history: list = field(default_factory=list)
 
 
 class _Roadmap:
@@ -219,7 +221,7 @@ def plan(scene, q_start, q_goal, params: PlanParams) -> PlanResult:
     lo, hi = scene.q_lo.astype(np.float64), scene.q_hi.astype(np.float64)
     arm_scenes = [OracleScene(_arm_scene(scene, r)) for r in range(R)]
     roadmaps = [_Roadmap(q_start[q_off[r]:q_off[r + 1]], q_goal[q_off[r]:q_off[r + 1]]) for r in range(R)]
-    c_best, best_path, costs = math.inf, None, []
+    c_best, best_path, costs, history = math.inf, None, [], []
     rnd, it, first_round, edge_states = 0, 0, -1, 0
     solved = False
 
@@ -308,6 +310,7 @@ def plan(scene, q_start, q_goal, params: PlanParams) -> PlanResult:
                     if cost < c_best:
                         c_best, best_path = cost, np.array(path, np.float32)
                         costs.append(cost)
+                        history.append((cost, best_path, rnd))
                         if first_round < 0:
                             first_round = rnd
                         solved = True
@@ -318,4 +321,11 @@ def plan(scene, q_start, q_goal, params: PlanParams) -> PlanResult:
         if not solved:
             break
     status = "OK" if best_path is not None else "E_NO_SOLUTION"
-    return PlanResult(status, best_path, c_best, rnd, it, first_round, costs, edge_states, roadmaps, solved)
+    return PlanResult(status, best_path, c_best, rnd, it, first_round, costs, edge_states, roadmaps, solved, history)
+
+
+def ranked_history(result: PlanResult, max_entries: int = 64):
+    """The incumbents as optimiser seeds (Sec. "Seeding for Multi-Robot
+    Jerk-Free Motion"): cheapest first, at most max_entries of them -- when
+    there are more paths than seeds, the cheaper ones are kept."""
+    return sorted(result.history, key=lambda e: e[0])[:max_entries]

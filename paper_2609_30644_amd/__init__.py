@@ -14,10 +14,11 @@ from ._binding import (  # noqa: F401
     WORK_NAMES,
     PlanParams,
     PlanResult,
+    Incumbent,
     Server,
     lib_path,
     load_library,
     STATUS_NAMES,
 )
 
-__all__ = ["MrpopError", "Context", "Scene", "ValidateStats", "KernelProfile", "WORK_NAMES", "PlanParams", "PlanResult", "Server", "lib_path", "load_library", "STATUS_NAMES"]
+__all__ = ["MrpopError", "Context", "Scene", "ValidateStats", "KernelProfile", "WORK_NAMES", "PlanParams", "PlanResult", "Incumbent", "Server", "lib_path", "load_library", "STATUS_NAMES"]

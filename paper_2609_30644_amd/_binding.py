@@ -75,6 +75,12 @@ class _PlanRequest(C.Structure):
                 ("cost", C.c_float), ("stats", _PlanStats)]
 
 
+class _PlanHistory(C.Structure):
+    _fields_ = [("waypoints", C.c_void_p), ("waypoint_cap", C.c_int64), ("offsets", C.c_void_p),
+                ("costs", C.c_void_p), ("found_s", C.c_void_p), ("found_round", C.c_void_p),
+                ("entry_cap", C.c_int32), ("n_entries", C.c_int32), ("n_written", C.c_int32)]
+
+
 class _ServerConfig(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("mem_budget_bytes", C.c_int64)]
 
@@ -103,6 +109,15 @@ class PlanResult:
     path: Optional[np.ndarray]
     cost: float
     stats: dict
+
+
+@dataclass
+class Incumbent:
+    """One entry of a plan's incumbent history (mrpop_plan_with_history)."""
+    path: np.ndarray   # [len][D], start to goal
+    cost: float
+    found_s: float     # seconds from the call's start
+    found_round: int
 
 
 WORK_NAMES = ("chains", "links", "env_tests", "box_exact", "rr_coarse", "fine_sphere", "fine_box", "fine_rr")
@@ -168,6 +183,7 @@ def load_library():
     lib.mrpop_plan_params_default.argtypes = [P]
     lib.mrpop_plan_params_default.restype = None
     lib.mrpop_plan.argtypes = [P, P, P, P, P, P, I32, P, P, P]
+    lib.mrpop_plan_with_history.argtypes = [P, P, P, P, P, P, I32, P, P, P, P]
     lib.mrpop_plan_batch.argtypes = [P, P, I32, P]
     lib.mrpop_server_create.argtypes = [P, P, P]
     lib.mrpop_server_destroy.argtypes = [P]
@@ -441,6 +457,45 @@ class Scene:
         if rc != 0 and raise_on_error:
             raise MrpopError(rc, lib.mrpop_last_error(self.ctx.handle).decode())
         return PlanResult(name, path[:plen.value].copy() if rc == 0 else None, float(cost.value), stats)
+
+    def plan_with_history(self, q_start, q_goal, max_entries: int = 64, max_waypoints: int = 65536,
+                          path_cap: int = 4096, raise_on_error: bool = True, **params):
+        """mrpop_plan_with_history: the plan's result and its incumbents,
+        cheapest first (at most max_entries entries and max_waypoints rows),
+        plus the number of incumbents found."""
+        lib = self.ctx._lib
+        pp = PlanParams()
+        lib.mrpop_plan_params_default(C.byref(pp))
+        for k, v in params.items():
+            if not hasattr(pp, k):
+                raise KeyError(k)
+            setattr(pp, k, v)
+        qs = np.ascontiguousarray(q_start, np.float32).reshape(self.dof)
+        qg = np.ascontiguousarray(q_goal, np.float32).reshape(self.dof)
+        path = np.zeros((max(1, path_cap), self.dof), np.float32)
+        plen = C.c_int32(0)
+        cost = C.c_float(0)
+        st = _PlanStats()
+        wp = np.zeros((max(1, max_waypoints), self.dof), np.float32)
+        off = np.zeros(max_entries + 1, np.int32)
+        costs = np.zeros(max(1, max_entries), np.float32)
+        found_s = np.zeros(max(1, max_entries), np.float64)
+        found_r = np.zeros(max(1, max_entries), np.int32)
+        h = _PlanHistory(wp.ctypes.data, max_waypoints, off.ctypes.data, costs.ctypes.data, found_s.ctypes.data,
+                         found_r.ctypes.data, max_entries, 0, 0)
+        rc = lib.mrpop_plan_with_history(self.ctx.handle, self._h, qs.ctypes.data, qg.ctypes.data, C.byref(pp),
+                                         path.ctypes.data, path_cap, C.byref(plen), C.byref(cost), C.byref(st),
+                                         C.byref(h))
+        stats = {k: getattr(st, k) for k, _ in _PlanStats._fields_ if k != "costs"}
+        stats["costs"] = list(st.costs[:st.n_costs])
+        stats["path_len"] = plen.value
+        name = STATUS_NAMES.get(rc, str(rc))
+        if rc != 0 and raise_on_error:
+            raise MrpopError(rc, lib.mrpop_last_error(self.ctx.handle).decode())
+        hist = [Incumbent(wp[off[k]:off[k + 1]].copy(), float(costs[k]), float(found_s[k]), int(found_r[k]))
+                for k in range(h.n_written)]
+        return PlanResult(name, path[:plen.value].copy() if rc == 0 else None, float(cost.value), stats), hist, \
+            h.n_entries
 
     def states_free(self, q) -> np.ndarray:
         """Host bool per composite state (True = collision-free)."""

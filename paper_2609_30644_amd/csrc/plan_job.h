@@ -31,6 +31,14 @@ class PlanJob {
   float cost() const { return c_best_; }
   const mrpop_plan_stats &stats() const { return st_; }
   const std::string &error() const { return err_; }
+  // Every incumbent of the call in discovery order (strictly decreasing cost).
+  struct Incumbent {
+    std::vector<float> path;  // [len][D], start to goal
+    float cost;
+    double found_s;
+    int32_t round;
+  };
+  const std::vector<Incumbent> &history() const { return history_; }
   int dof() const { return D_; }
   // Device bytes held by the instance (arena and sub-scenes).
   size_t device_bytes() const { return device_bytes_; }
@@ -67,6 +75,7 @@ class PlanJob {
   mrpop_plan_stats st_{};
   float c_best_ = INFINITY;
   std::vector<float> best_path_;
+  std::vector<Incumbent> history_;
   std::vector<int32_t> h_qoff_, h_nj_, rm_n_;
   std::vector<mrpop_scene *> arms_;
   size_t device_bytes_ = 0;

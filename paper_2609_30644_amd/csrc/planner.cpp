@@ -623,6 +623,7 @@ mrpop_status PlanJob::run(Exec &ex) {
           if ((float)cost < c_best_) {  // strictly cheaper incumbents only
             c_best_ = (float)cost;
             best_path_ = hpath;
+            history_.push_back(Incumbent{hpath, c_best_, elapsed_(), rnd - 1});
             if (st_.n_costs < 64) st_.costs[st_.n_costs++] = c_best_;
             ++st_.solutions;
             if (st_.first_round < 0) {
@@ -716,13 +717,44 @@ mrpop_status mrpop_sample(mrpop_ctx *ctx, const mrpop_scene *scene, const float 
   return MRPOP_OK;
 }
 
-mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
-                        const mrpop_plan_params *params, float *path_out, int32_t path_cap, int32_t *path_len,
-                        float *cost_out, mrpop_plan_stats *stats_opt) {
+}  // extern "C"
+
+// Writes job's incumbents into hist, cheapest first, as many as fit.
+static void write_history(const PlanJob &job, mrpop_plan_history *hist) {
+  const auto &h = job.history();
+  hist->n_entries = (int32_t)h.size();
+  hist->n_written = 0;
+  const int D = job.dof();
+  int64_t row = 0;
+  if (hist->entry_cap > 0) hist->offsets[0] = 0;
+  // discovery order has strictly decreasing costs: the ranking is its reverse
+  for (int k = (int)h.size() - 1; k >= 0; --k) {
+    const int n = hist->n_written;
+    const int64_t len = (int64_t)(h[k].path.size() / D);
+    if (n >= hist->entry_cap || row + len > hist->waypoint_cap) break;
+    std::memcpy(hist->waypoints + row * D, h[k].path.data(), sizeof(float) * h[k].path.size());
+    row += len;
+    hist->offsets[n + 1] = (int32_t)row;
+    hist->costs[n] = h[k].cost;
+    if (hist->found_s) hist->found_s[n] = h[k].found_s;
+    if (hist->found_round) hist->found_round[n] = h[k].round;
+    hist->n_written = n + 1;
+  }
+}
+
+static mrpop_status plan_impl(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
+                              const mrpop_plan_params *params, float *path_out, int32_t path_cap, int32_t *path_len,
+                              float *cost_out, mrpop_plan_stats *stats_opt, mrpop_plan_history *hist) {
   if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "plan: ctx is NULL");
   if (!scene || scene->ctx != ctx) return fail(ctx, MRPOP_E_INVALID_ARG, "plan: scene not from this ctx");
   if (!q_start || !q_goal || !params || !path_len || !cost_out || (path_cap > 0 && !path_out))
     return fail(ctx, MRPOP_E_INVALID_ARG, "plan: NULL argument");
+  if (hist) {
+    hist->n_entries = hist->n_written = 0;
+    if (hist->entry_cap < 0 || hist->waypoint_cap < 0 ||
+        (hist->entry_cap > 0 && (!hist->offsets || !hist->costs)) || (hist->waypoint_cap > 0 && !hist->waypoints))
+      return fail(ctx, MRPOP_E_INVALID_ARG, "plan: bad history buffers");
+  }
   *path_len = 0;
   *cost_out = INFINITY;
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
@@ -731,6 +763,7 @@ mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q
   if (st == MRPOP_OK) {
     PlainExec ex(ctx, nullptr);
     st = job.run(ex);
+    if (hist) write_history(job, hist);
   }
   if (stats_opt) *stats_opt = job.stats();
   if (st != MRPOP_OK) return fail(ctx, st, job.error());
@@ -740,6 +773,22 @@ mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q
   if (len > path_cap) return fail(ctx, MRPOP_E_BUFFER, "plan: path buffer too small");
   std::memcpy(path_out, job.path().data(), sizeof(float) * job.path().size());
   return MRPOP_OK;
+}
+
+extern "C" {
+
+mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
+                        const mrpop_plan_params *params, float *path_out, int32_t path_cap, int32_t *path_len,
+                        float *cost_out, mrpop_plan_stats *stats_opt) {
+  return plan_impl(ctx, scene, q_start, q_goal, params, path_out, path_cap, path_len, cost_out, stats_opt, nullptr);
+}
+
+mrpop_status mrpop_plan_with_history(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start,
+                                     const float *q_goal, const mrpop_plan_params *params, float *path_out,
+                                     int32_t path_cap, int32_t *path_len, float *cost_out,
+                                     mrpop_plan_stats *stats_opt, mrpop_plan_history *hist) {
+  if (!hist) return fail(ctx, MRPOP_E_INVALID_ARG, "plan_with_history: hist is NULL");
+  return plan_impl(ctx, scene, q_start, q_goal, params, path_out, path_cap, path_len, cost_out, stats_opt, hist);
 }
 
 }  // extern "C"

@@ -113,6 +113,13 @@ def test_sample_matches_oracle(ctx, informed):
 PARAMS = dict(seed=1, candidates=64, max_rounds=150, max_iterations=4, n_roadmap=32, delta=3.0)
 
 
+class PlanResultLike:
+    """A path with its cost in the shape _check_path reads."""
+
+    def __init__(self, path, cost, stats):
+        self.path, self.cost, self.stats = path, cost, stats
+
+
 def _check_path(sc, res, q_start, q_goal, params):
     path = res.path
     assert path is not None and len(path) >= 2
@@ -213,3 +220,32 @@ def test_plan_trajectory_vs_oracle_reported(ctx):
         np.abs(o.path - g.path).max() < 1e-4
     print(f"  gpu costs {[round(c, 4) for c in g.stats['costs']]} first round {g.stats['first_round']}")
     print(f"  cpu costs {[round(c, 4) for c in o.costs]} first round {o.first_round}; same final path: {same}")
+
+
+def test_plan_history_ranked_and_valid(ctx):
+    """mrpop_plan_with_history: every incumbent of the call, cheapest first;
+    the plan itself is the one mrpop_plan returns; each entry re-validated by
+    the oracle with its FP64 cost; smaller buffers keep the cheapest ones."""
+    print("[plan history] c2", flush=True)
+    p = problem("c2")
+    s = _scene(ctx, p.scene)
+    ref = s.plan(p.q_start, p.q_goal, **PARAMS)
+    res, hist, n = s.plan_with_history(p.q_start, p.q_goal, **PARAMS)
+    print(f"  {n} incumbents, costs {[h.cost for h in hist]}", flush=True)
+    assert res.status == "OK" and np.array_equal(res.path, ref.path) and res.cost == ref.cost
+    assert n == res.stats["solutions"] == len(hist) >= 1
+    assert np.array_equal(hist[0].path, res.path) and hist[0].cost == res.cost
+    costs = [h.cost for h in hist]
+    assert all(a < b for a, b in zip(costs, costs[1:]))
+    assert costs == [float(c) for c in reversed(res.stats["costs"][:n])]
+    assert all(a.found_round >= b.found_round and a.found_s >= b.found_s for a, b in zip(hist, hist[1:]))
+    for h in hist:
+        _check_path(p.scene, PlanResultLike(h.path, h.cost, {"costs": [h.cost]}), p.q_start, p.q_goal, PARAMS)
+    one = s.plan_with_history(p.q_start, p.q_goal, max_entries=1, **PARAMS)
+    assert one[2] == n and len(one[1]) == 1 and np.array_equal(one[1][0].path, hist[0].path)
+    if n >= 2:
+        rows = len(hist[0].path) + len(hist[1].path) - 1  # room for the cheapest only
+        cut = s.plan_with_history(p.q_start, p.q_goal, max_waypoints=rows, **PARAMS)
+        assert cut[2] == n and len(cut[1]) == 1 and cut[1][0].cost == hist[0].cost
+    none = s.plan_with_history(p.q_start, p.q_goal, max_entries=0, max_waypoints=0, **PARAMS)
+    assert none[2] == n and none[1] == [] and np.array_equal(none[0].path, res.path)

@@ -124,3 +124,28 @@ def test_roadmap_invariants(c1):
         g = coo_matrix((np.ones(len(ii)), (ii, jj)), shape=(len(V), len(V)))
         _, lab = connected_components(g, directed=False)
         assert rm.connected() == (lab[0] == lab[1])
+
+
+def test_incumbent_history_ranked_seeds(c1):
+    """Seeding (Sec. "Seeding for Multi-Robot Jerk-Free Motion"): every
+    improved path is kept with its cost; ranked cheapest first, a prefix of
+    that ranking when fewer seeds are wanted.  Each entry is checked by means
+    independent of the planner: endpoints, the checker, the FP64 cost of its
+    waypoints."""
+    r = PL.plan(c1.scene, c1.q_start, c1.q_goal, PL.PlanParams(**PARAMS))
+    assert r.status == "OK" and len(r.history) == len(r.costs) >= 2
+    costs = [c for c, _, _ in r.history]
+    assert costs == r.costs and all(b < a for a, b in zip(costs, costs[1:]))
+    assert np.array_equal(r.history[-1][1], r.path)
+    rounds = [k for _, _, k in r.history]
+    assert rounds == sorted(rounds)
+    for cost, path, _ in r.history:
+        assert np.array_equal(path[0], c1.q_start) and np.array_equal(path[-1], c1.q_goal)
+        _, m = oracle.classify_edges(c1.scene, path[:-1], path[1:], 0.05)
+        assert np.all(m >= 0)
+        assert float(np.linalg.norm(np.diff(path.astype(np.float64), axis=0), axis=1).sum()) == \
+            pytest.approx(cost, rel=1e-12)
+    ranked = PL.ranked_history(r)
+    assert [e[0] for e in ranked] == sorted(costs)
+    two = PL.ranked_history(r, 2)
+    assert [e[0] for e in two] == sorted(costs)[:2] and np.array_equal(two[0][1], r.path)

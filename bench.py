@@ -238,6 +238,40 @@ def history_leg(s, q_start, q_goal, res: float, n: int) -> dict:
             "buffers": {"max_entries": 16, "max_waypoints": 4096}}
 
 
+SINGLE_FIXTURE = os.path.join(ROOT, "tests", "golden", "single_arm.json")
+# Direct mode (one arm, no roadmaps): extension length `step` (rad).
+DIRECT_PLAN = dict(candidates=128, max_rounds=150, max_iterations=4, direct=1, step=1.0)
+
+
+def direct_leg(ctx, res: float) -> dict:
+    """Direct mode on the single-arm problems (one plan each, seed = index):
+    solve rate, time to first solution, final cost, edge-states/s."""
+    import workloads as W
+    import paper_2609_30644_amd as M
+    d = json.load(open(SINGLE_FIXTURE))
+    tts, costs, straight, states, wall, ok = [], [], [], 0, 0.0, 0
+    for i, pr in enumerate(d["problems"]):
+        sc = W.scene_single(pr["scene_seed"]).with_env(np.array(pr["env_spheres"], np.float32).reshape(-1, 4),
+                                                        np.array(pr["env_boxes"], np.float32).reshape(-1, 6))
+        s = M.Scene(ctx, sc)
+        qs, qg = np.array(pr["q_start"], np.float32), np.array(pr["q_goal"], np.float32)
+        s.plan(qs, qg, raise_on_error=False, resolution=res, **dict(DIRECT_PLAN, seed=10_000 + i))  # warm
+        t0 = time.perf_counter()
+        r = s.plan(qs, qg, raise_on_error=False, resolution=res, **dict(DIRECT_PLAN, seed=i))
+        wall += time.perf_counter() - t0
+        states += r.stats["edge_states"]
+        if r.status == "OK":
+            ok += 1
+            tts.append(r.stats["time_to_first_s"])
+            costs.append(r.cost)
+            straight.append(float(np.linalg.norm(qg.astype(np.float64) - qs)))
+    return {"problems": len(d["problems"]), "solved": ok,
+            "tts_p50_ms": float(np.median(tts)) * 1e3 if tts else None,
+            "mean_plan_ms": wall * 1e3 / len(d["problems"]),
+            "cost_over_straight_line_median": float(np.median(np.array(costs) / np.array(straight))) if costs else None,
+            "edge_states_per_s": states / wall if wall > 0 else None, "params": DIRECT_PLAN}
+
+
 def served(ctx, rate_hz: float, duration_s: float, slots: int, mem_gb: float) -> dict:
     """Poisson arrivals of queries (2-16 arms, 32-512 obstacles) submitted to
     a continuous-batching server on the wall clock; latency is arrival ->
@@ -294,6 +328,8 @@ def main():
     ap.add_argument("--no-plan", action="store_true", help="validation batches only")
     ap.add_argument("--batch-instances", type=int, default=64,
                     help="instances of the batched-vs-plain comparison (0: skip)")
+    ap.add_argument("--no-direct", dest="direct", action="store_false",
+                    help="skip the direct-mode (single-arm, no roadmap) leg")
     ap.add_argument("--history-plans", type=int, default=10,
                     help="plans timed with and without the incumbent-history export (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the served run (0: skip)")
@@ -387,6 +423,9 @@ def main():
                         "edge_states_per_plan": plan_states / len(plans),
                         "params": PLAN}
         line["config"]["plan"] = "one mrpop_plan per step, seed = step index"
+    if args.direct:
+        print("[bench] direct mode", file=sys.stderr, flush=True)
+        line["direct"] = direct_leg(ctx, res)
     if plans and args.history_plans > 0:
         print("[bench] incumbent history", file=sys.stderr, flush=True)
         line["history"] = history_leg(s, q_start, q_goal, res, args.history_plans)

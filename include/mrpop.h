@@ -232,6 +232,13 @@ typedef struct {
   int32_t max_roadmap_nodes; /* vertices per arm roadmap */
   int32_t stop_at_first;     /* 1: return after the first solution */
   float warm_cost;           /* incumbent cost to beat (+infinity: none) */
+  /* Direct mode (paper, Sec. "Single-Robot Simulation Benchmarks &
+   * Ablations": without roadmaps the search runs in the configuration space
+   * itself, a bidirectional RRT-Connect-style search followed by AO-X):
+   * 1 skips ROADMAP, and an extension moves from q_near toward q_rand by at
+   * most `step` (Euclidean, rad) instead of along roadmap edges. */
+  int32_t direct;
+  float step;                /* direct mode: extension length, > 0 */
 } mrpop_plan_params;
 
 typedef struct {
@@ -279,7 +286,7 @@ typedef struct {
 /* Defaults: seed 0, delta 3.0, n_roadmap 32, candidates 128, resolution
  * 0.05, max_rounds 1000, max_iterations 8, max_growth_rounds 16, no time
  * budget, 65536 tree and 8192 roadmap vertices, stop_at_first 0, no warm
- * cost. */
+ * cost, direct 0, step 1.0. */
 void mrpop_plan_params_default(mrpop_plan_params *p);
 
 /* MR. POP (Alg. 1): grow per-arm roadmaps (ROADMAP), search their tensor

@@ -35,6 +35,12 @@ Readings where the paper is silent (each is also a GPU-side rule):
   * Connection: NEAREST in the other tree with budget c_best - g_new (the
     initial solve uses an infinite budget); accepted only if the new path is
     strictly cheaper than the incumbent.
+  * Direct mode (single-robot planning without the roadmap layer): no
+    ROADMAP; an extension steers from q_near toward q_rand, all the way when
+    q_rand is within `step` (Euclidean), else by exactly `step` along the
+    segment (RRT-Connect's extend, the connection being its greedy connect);
+    a sample equal to q_near is dropped; the AO-X admissibility rule is
+    unchanged.  Every outer iteration is one search with fresh trees.
 """
 from __future__ import annotations
 
@@ -63,6 +69,10 @@ class PlanParams:
     max_growth_rounds: int = 16
     max_tree_nodes: int = 100000
     stop_at_first: bool = False
+    # direct mode: no roadmaps; extensions steer toward the sample by at most
+    # `step` (Sec. "Single-Robot Simulation Benchmarks & Ablations")
+    direct: bool = False
+    step: float = 1.0
 
 
 @dataclass
@@ -206,6 +216,19 @@ def drrt_oracle(roadmaps, vid_near, q_near_arms, q_rand_arms):
     return out
 
 
+def steer(q_near: np.ndarray, q_rand: np.ndarray, step: float) -> np.ndarray:
+    """Direct-mode extension (no roadmap layer): q_rand itself when it lies
+    within `step` of q_near (Euclidean), else the point at distance `step`
+    from q_near on the segment toward q_rand.  FP64."""
+    q_near = np.asarray(q_near, np.float64)
+    q_rand = np.asarray(q_rand, np.float64)
+    d = q_rand - q_near
+    dist = float(np.linalg.norm(d))
+    if dist <= step:
+        return q_rand.copy()
+    return q_near + (step / dist) * d
+
+
 def plan(scene, q_start, q_goal, params: PlanParams) -> PlanResult:
     """Alg. 1 with the subroutines of Alg. 2, in rounds of P candidates."""
     osc = OracleScene(scene)
@@ -232,7 +255,8 @@ def plan(scene, q_start, q_goal, params: PlanParams) -> PlanResult:
         return np.concatenate([roadmaps[r].V[vid[r]] for r in range(R)]).astype(np.float32)
 
     while it < params.max_iterations and rnd < params.max_rounds:
-        roadmap_step(scene, roadmaps, arm_scenes, params, it, q_off)
+        if not params.direct:
+            roadmap_step(scene, roadmaps, arm_scenes, params, it, q_off)
         ta, tb = _new_tree(q_start, tuple([0] * R)), _new_tree(q_goal, tuple([1] * R))
         a_is_start = True
         solved = False
@@ -259,10 +283,17 @@ def plan(scene, q_start, q_goal, params: PlanParams) -> PlanResult:
                 k_near = nearest(Va, ga, q_rand.astype(np.float32), c_rand)
                 if k_near < 0:
                     continue
-                vid_new = tuple(drrt_oracle(roadmaps, ta.vid[k_near], arms(ta.q[k_near]), arms(q_rand)))
-                if vid_new == ta.vid[k_near]:
-                    continue
-                q_new = composite(vid_new)
+                if params.direct:
+                    q_near = ta.q[k_near].astype(np.float64)
+                    if not np.any(q_rand != q_near):  # nothing to extend toward
+                        continue
+                    q_new = steer(q_near, q_rand, params.step).astype(np.float32)
+                    vid_new = ta.vid[k_near]
+                else:
+                    vid_new = tuple(drrt_oracle(roadmaps, ta.vid[k_near], arms(ta.q[k_near]), arms(q_rand)))
+                    if vid_new == ta.vid[k_near]:
+                        continue
+                    q_new = composite(vid_new)
                 g_new = float(ta.g[k_near]) + float(np.linalg.norm(q_new.astype(np.float64) -
                                                                    ta.q[k_near].astype(np.float64)))
                 if not math.isinf(c_best) and g_new >= c_rand:

@@ -58,7 +58,8 @@ class PlanParams(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("delta", C.c_float), ("n_roadmap", C.c_int32), ("candidates", C.c_int32),
                 ("resolution", C.c_float), ("max_rounds", C.c_int32), ("max_iterations", C.c_int32),
                 ("max_growth_rounds", C.c_int32), ("time_budget_s", C.c_double), ("max_tree_nodes", C.c_int32),
-                ("max_roadmap_nodes", C.c_int32), ("stop_at_first", C.c_int32), ("warm_cost", C.c_float)]
+                ("max_roadmap_nodes", C.c_int32), ("stop_at_first", C.c_int32), ("warm_cost", C.c_float),
+                ("direct", C.c_int32), ("step", C.c_float)]
 
 
 class _PlanStats(C.Structure):

@@ -208,7 +208,7 @@ void PlanJob::set_sizes_(const mrpop_scene *scene, const mrpop_plan_params &P) {
   R_ = scene->n_robots;
   D_ = scene->dof;
   PC_ = P.candidates;
-  rm_cap_ = P.max_roadmap_nodes;
+  rm_cap_ = P.direct ? 4 : P.max_roadmap_nodes;  // direct mode keeps no roadmaps
   edge_cap_ = rm_cap_ * 32;
   col_cap_ = 2 * edge_cap_;
   cand_batch_ = 4 * P.n_roadmap;
@@ -277,7 +277,7 @@ size_t PlanJob::plan_arena_(void *base) {
 size_t PlanJob::device_bytes_for(const mrpop_scene *scene, const mrpop_plan_params &params) {
   PlanJob j;
   j.set_sizes_(scene, params);
-  return j.plan_arena_(nullptr) + (size_t)scene->n_robots * scene->blob_bytes;
+  return j.plan_arena_(nullptr) + (params.direct ? 0 : (size_t)scene->n_robots * scene->blob_bytes);
 }
 
 mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
@@ -288,7 +288,8 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   if (P.candidates < 1 || P.candidates > 4096 || !(P.resolution > 0.f) || !std::isfinite(P.resolution) ||
       P.max_rounds < 1 || P.max_iterations < 1 || P.max_growth_rounds < 1 || P.n_roadmap < 1 ||
       P.max_tree_nodes < 2 || P.max_roadmap_nodes < 4 || P.max_roadmap_nodes > kUfMaxVertices ||
-      !(P.delta > 0.f) || P.time_budget_s < 0 || std::isnan(P.warm_cost))
+      !(P.delta > 0.f) || P.time_budget_s < 0 || std::isnan(P.warm_cost) || (P.direct != 0 && P.direct != 1) ||
+      (P.direct && !(P.step > 0.f && std::isfinite(P.step))))
     return fail_(MRPOP_E_INVALID_ARG, "plan: parameter out of range");
   R_ = scene->n_robots;
   D_ = scene->dof;
@@ -349,7 +350,7 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   upload_i_[4 * R] = 0;  // union-find parents of vertices 0 and 1
   upload_i_[4 * R + 1] = 1;
   arms_.assign(R, nullptr);
-  for (int r = 0; r < R; ++r) {
+  for (int r = 0; r < R && !P.direct; ++r) {  // one-arm scenes of the roadmaps
     mrpop_status a = arm_scene(ctx, scene, r, &arms_[r]);
     if (a != MRPOP_OK) return fail_(a, "plan: arm scene: " + ctx->last_error);
     device_bytes_ += arms_[r]->blob_bytes;
@@ -545,7 +546,7 @@ mrpop_status PlanJob::run(Exec &ex) {
   bool overflow_no_path = false;
   std::vector<float> hpath;
   while (it < P_.max_iterations && rnd < P_.max_rounds && !out_of_time_()) {
-    TRY(roadmap_(ex, it));
+    if (!P_.direct) TRY(roadmap_(ex, it));
     // fresh trees: 0 rooted at the start, 1 at the goal
     SUBMIT(Op::TreeRoot, tree_root, TreeRootArgs{tq_[0], tg_[0], tvid_[0], tpar_[0], tn_[0], tcap_, qs_, D, R, 0});
     SUBMIT(Op::TreeRoot, tree_root, TreeRootArgs{tq_[1], tg_[1], tvid_[1], tpar_[1], tn_[1], tcap_, qg_, D, R, 1});
@@ -562,10 +563,15 @@ mrpop_status PlanJob::run(Exec &ex) {
       SUBMIT(Op::Nearest, nearest,
              NearestArgs{tq_[a], tg_[a], n_t[a], D, 1, tcap_, q_rand_, D, cb < INFINITY ? c_rand_ : nullptr, PC,
                          near_idx_});
-      SUBMIT(Op::Extend, extend,
-             ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a], tvid_[a], tg_[a],
-                        tcap_, rm_V_, rm_rowptr_, rm_col_, rm_cap_, col_cap_, d_nj_, d_qoff_, q_new_, vid_new_, g_new_,
-                        alive_, ea_, eb_, P_.resolution, codes_ext_});
+      if (P_.direct)
+        SUBMIT(Op::Steer, steer,
+               SteerArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a], tg_[a], tcap_,
+                         P_.step, q_new_, vid_new_, g_new_, alive_, ea_, eb_, P_.resolution, codes_ext_});
+      else
+        SUBMIT(Op::Extend, extend,
+               ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a], tvid_[a], tg_[a],
+                          tcap_, rm_V_, rm_rowptr_, rm_col_, rm_cap_, col_cap_, d_nj_, d_qoff_, q_new_, vid_new_,
+                          g_new_, alive_, ea_, eb_, P_.resolution, codes_ext_});
       TRY(validate_(ex, scene_, ea_, eb_, PC, P_.resolution, valid_, cnt_, codes_ext_));
       SUBMIT(Op::Insert, insert,
              InsertArgs{PC, D, R, alive_, valid_, q_new_, g_new_, vid_new_, near_idx_, tq_[a], tg_[a], tvid_[a],
@@ -645,7 +651,7 @@ mrpop_status PlanJob::run(Exec &ex) {
   }
   st_.rounds = rnd;
   st_.iterations = it;
-  for (int r = 0; r < R; ++r) st_.roadmap_vertices += rm_n_[r];
+  for (int r = 0; r < R && !P_.direct; ++r) st_.roadmap_vertices += rm_n_[r];
   st_.total_time_s = elapsed_();
   if (best_path_.empty())
     return overflow_no_path ? fail_(MRPOP_E_CAPACITY, "plan: search tree full before any solution")
@@ -678,6 +684,8 @@ void mrpop_plan_params_default(mrpop_plan_params *p) {
   p->max_rounds = 1000;
   p->max_iterations = 8;
   p->max_growth_rounds = 16;
+  p->direct = 0;
+  p->step = 1.0f;
   p->time_budget_s = 0.0;
   p->max_tree_nodes = 65536;
   p->max_roadmap_nodes = 8192;

@@ -82,6 +82,25 @@ struct InsertArgs {
   int n_before;  // vertices in the tree before this insertion (the host's count)
 };
 
+// Direct-mode extension: from q_near toward q_rand by at most `step`.
+struct SteerArgs {
+  int n, dim, n_robots;
+  const int32_t *near_idx;    // [n]
+  const float *q_rand;        // [n][dim]
+  const float *c_rand;        // [n] or null
+  const float *tree_q;        // SoA [dim][tree_cap]
+  const float *tree_g;
+  int tree_cap;
+  float step;
+  float *q_new;               // [n][dim]
+  int32_t *vid_new;           // [R][n] (zeros: no roadmap)
+  float *g_new;               // [n]
+  uint8_t *alive;             // [n]
+  float *edge_a, *edge_b;     // [n][dim]
+  float res;                  // resolution of the edge's validation
+  int32_t *n_codes;           // [n] or null: state-count code of each edge
+};
+
 struct ConnArgs {
   int n, dim;
   const int32_t *conn_idx;
@@ -209,10 +228,10 @@ uint64_t roadmap_key(uint64_t seed, uint64_t stream_a, uint64_t stream_b);
 // blockIdx.y of the device array `args`; grid_x = the most blocks any record
 // needs, records that need fewer leave early).
 enum class Op : uint8_t {
-  Sample, Nearest, Extend, Insert, Conn, Select, Path, TreeRoot,
+  Sample, Nearest, Extend, Steer, Insert, Conn, Select, Path, TreeRoot,
   RmSample, RmAccept, RmPairs, RmAddEdges, RmBfs, RmUnion, Fill, Copy, Validate
 };
-constexpr int kNumOps = 17;
+constexpr int kNumOps = 18;
 constexpr int kUfMaxVertices = 32768;  // roadmap vertices per arm (union-find in LDS)
 
 // Blocks one record needs (0: nothing to do).
@@ -241,6 +260,7 @@ struct Cmd {
     SampleArgs sample;
     NearestArgs nearest;
     ExtendArgs extend;
+    SteerArgs steer;
     InsertArgs insert;
     ConnArgs conn;
     SelectArgs select;

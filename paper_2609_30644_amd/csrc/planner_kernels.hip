@@ -326,6 +326,67 @@ __device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
   }
 }
 
+// Direct mode (no roadmaps): the extension moves from q_near toward q_rand,
+// the whole way if it is at most `step` away, else by `step` along the
+// segment; a candidate that does not move is dropped, and under a finite
+// budget so is one with g_near + |q_new - q_near| >= c_rand (the AO-X rule).
+// One wavefront per candidate, one joint per lane; writes the edge to
+// validate (q_near -> q_new, or a null edge at q_near when dropped) and its
+// state count.
+constexpr int kSteerWaves = 4;
+
+__device__ __forceinline__ void steer_body(const SteerArgs &a, int bx) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int i = bx * kSteerWaves + (int)(threadIdx.x / kWave);
+  if (i >= a.n) return;  // whole waves leave together
+  const int D = a.dim;
+  const int near = a.near_idx[i];
+  float *ea = a.edge_a + (int64_t)i * D, *eb = a.edge_b + (int64_t)i * D, *qn = a.q_new + (int64_t)i * D;
+  const float *qr = a.q_rand + (int64_t)i * D;
+  for (int r = lane; r < a.n_robots; r += kWave) a.vid_new[(int64_t)r * a.n + i] = 0;
+  const int src = near < 0 ? 0 : near;  // dropped candidates: a null edge at the root
+  // |q_rand - q_near|^2
+  float d2 = 0.f;
+  for (int j = lane; j < D; j += kWave) {
+    const float t = qr[j] - a.tree_q[(int64_t)j * a.tree_cap + src];
+    d2 = fmaf(t, t, d2);
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) d2 += __shfl_xor(d2, d, kWave);
+  const float dist = sqrtf(d2);
+  const bool whole = dist <= a.step;
+  const float s = whole ? 1.f : a.step / dist;
+  float m2 = 0.f, linf = 0.f;
+  bool finite = true;
+  for (int j = lane; j < D; j += kWave) {
+    const float y = a.tree_q[(int64_t)j * a.tree_cap + src];
+    const float x = whole ? qr[j] : fmaf(s, qr[j] - y, y);
+    qn[j] = x;
+    const float t = x - y;
+    m2 = fmaf(t, t, m2);
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) m2 += __shfl_xor(m2, d, kWave);
+  const float gn = a.tree_g[src] + sqrtf(m2);
+  bool ok = near >= 0 && dist > 0.f;
+  if (ok && a.c_rand && a.c_rand[i] < INFINITY && !(gn < a.c_rand[i])) ok = false;
+  for (int j = lane; j < D; j += kWave) {
+    const float y = a.tree_q[(int64_t)j * a.tree_cap + src];
+    const float b = ok ? qn[j] : y;
+    ea[j] = y;
+    eb[j] = b;
+    finite = finite && isfinite(y) && isfinite(b);
+    linf = fmaxf(linf, fabsf(b - y));
+  }
+  if (lane == 0) {
+    a.g_new[i] = gn;
+    a.alive[i] = ok ? 1 : 0;
+  }
+  if (a.n_codes) {
+    for (int d = kWave / 2; d > 0; d >>= 1) linf = fmaxf(linf, __shfl_xor(linf, d, kWave));
+    const bool all_finite = __ballot(!finite) == 0ull;
+    if (lane == 0) a.n_codes[i] = state_count_code(linf, all_finite, a.res);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // a10: insertion in candidate order; a11: connection edges; a12: selection
 // ---------------------------------------------------------------------------
@@ -781,6 +842,7 @@ __device__ __forceinline__ void copy_body(const CopyArgs &a, int bx) {
 MRPOP_OP_KERNELS(sample, SampleArgs, kSampleWaves * kWave)
 MRPOP_OP_KERNELS(nearest, NearestArgs, 256)
 MRPOP_OP_KERNELS(extend, ExtendArgs, kExtendWaves * kWave)
+MRPOP_OP_KERNELS(steer, SteerArgs, kSteerWaves * kWave)
 MRPOP_OP_KERNELS(insert, InsertArgs, 256)
 MRPOP_OP_KERNELS(conn, ConnArgs, kConnWaves * kWave)
 MRPOP_OP_KERNELS(select, SelectArgs, 256)
@@ -808,6 +870,7 @@ int op_blocks(Op op, const void *p) {
       const ExtendArgs &a = *(const ExtendArgs *)p;
       return clamp_blocks((a.n + kExtendWaves - 1) / kExtendWaves);
     }
+    case Op::Steer: return clamp_blocks((((const SteerArgs *)p)->n + kSteerWaves - 1) / kSteerWaves);
     case Op::Insert: return clamp_blocks(std::max(1, (((const InsertArgs *)p)->n + kInsertPer - 1) / kInsertPer));
     case Op::Conn: return clamp_blocks((((const ConnArgs *)p)->n + kConnWaves - 1) / kConnWaves);
     case Op::Select: return 1;
@@ -834,6 +897,7 @@ size_t op_args_bytes(Op op) {
     case Op::Sample: return sizeof(SampleArgs);
     case Op::Nearest: return sizeof(NearestArgs);
     case Op::Extend: return sizeof(ExtendArgs);
+    case Op::Steer: return sizeof(SteerArgs);
     case Op::Insert: return sizeof(InsertArgs);
     case Op::Conn: return sizeof(ConnArgs);
     case Op::Select: return sizeof(SelectArgs);
@@ -874,6 +938,7 @@ static hipError_t launch_any(Op op, const void *p, bool batch, int count, int gr
     MRPOP_OP_CASE(Sample, sample, SampleArgs)
     MRPOP_OP_CASE(Nearest, nearest, NearestArgs)
     MRPOP_OP_CASE(Extend, extend, ExtendArgs)
+    MRPOP_OP_CASE(Steer, steer, SteerArgs)
     MRPOP_OP_CASE(Insert, insert, InsertArgs)
     MRPOP_OP_CASE(Conn, conn, ConnArgs)
     MRPOP_OP_CASE(Select, select, SelectArgs)

@@ -249,3 +249,57 @@ def test_plan_history_ranked_and_valid(ctx):
         assert cut[2] == n and len(cut[1]) == 1 and cut[1][0].cost == hist[0].cost
     none = s.plan_with_history(p.q_start, p.q_goal, max_entries=0, max_waypoints=0, **PARAMS)
     assert none[2] == n and none[1] == [] and np.array_equal(none[0].path, res.path)
+
+
+DIRECT = dict(seed=3, candidates=64, max_rounds=150, max_iterations=4, n_roadmap=32, delta=3.0, direct=1, step=1.0)
+
+
+def test_plan_direct_single_arm(ctx):
+    """Direct mode through the C ABI: no roadmap; the path passes the oracle's
+    re-validation with its FP64 cost; every edge but the connection is a tree
+    edge no longer than `step`; deterministic."""
+    print("[plan direct] single arm", flush=True)
+    p = W.make_problem(W.scene_single(0), 0, oracle.states_free)
+    s = _scene(ctx, p.scene)
+    res = s.plan(p.q_start, p.q_goal, **DIRECT)
+    assert res.status == "OK" and res.stats["roadmap_vertices"] == 0 and res.stats["roadmap_edge_states"] == 0
+    _check_path(p.scene, res, p.q_start, p.q_goal, DIRECT)
+    steps = np.linalg.norm(np.diff(res.path.astype(np.float64), axis=0), axis=1)
+    assert int((steps > DIRECT["step"] * (1 + 1e-5)).sum()) <= 1
+    again = s.plan(p.q_start, p.q_goal, **DIRECT)
+    assert np.array_equal(again.path, res.path) and again.cost == res.cost
+
+
+def test_plan_direct_first_solution_matches_oracle(ctx):
+    """One arm, no obstacles: the first solution is start -> steer(start,
+    q_rand_i) -> goal for the cheapest candidate of round 0 on both sides
+    (the same random streams); the GPU's equals the oracle's within FP32
+    rounding."""
+    from oracle.planner import plan as oplan, PlanParams
+    sc = W.Scene([W.panda_like(20)], W.base_transform(0, 0, 0)[None], np.zeros((0, 4), np.float32),
+                 np.zeros((0, 6), np.float32))
+    qs, qg = W.random_configs(sc, 2, np.random.default_rng(11))
+    prm = dict(seed=4, candidates=32, max_rounds=60, max_iterations=3, direct=1, step=0.7)
+    o = oplan(sc, qs, qg, PlanParams(**dict(prm, direct=True)))
+    s = _scene(ctx, sc)
+    res, hist, n = s.plan_with_history(qs, qg, **prm)
+    assert res.status == "OK" and res.stats["first_round"] == 0 and n >= 1
+    first = hist[-1]  # ranked cheapest first: the first one found is the last
+    o_cost, o_path, _ = o.history[0]
+    print(f"  gpu first {first.cost:.6f} oracle first {o_cost:.6f}", flush=True)
+    assert first.path.shape == o_path.shape == (3, sc.dof)
+    assert np.allclose(first.path, o_path, atol=1e-5, rtol=0)
+    assert abs(first.cost - o_cost) <= 1e-5 * o_cost
+
+
+def test_plan_direct_batch_equals_plain(ctx):
+    """Direct-mode instances in one mrpop_plan_batch equal their plain runs."""
+    p = W.make_problem(W.scene_single(0), 0, oracle.states_free)
+    s = _scene(ctx, p.scene)
+    jobs = [(s, p.q_start, p.q_goal, dict(DIRECT, seed=k)) for k in range(4)]
+    got, _ = ctx.plan_batch(jobs)
+    for k, g in enumerate(got):
+        ref = s.plan(p.q_start, p.q_goal, raise_on_error=False, **dict(DIRECT, seed=k))
+        assert g.status == ref.status
+        if ref.status == "OK":
+            assert np.array_equal(g.path, ref.path) and g.cost == ref.cost

@@ -149,3 +149,79 @@ def test_incumbent_history_ranked_seeds(c1):
     assert [e[0] for e in ranked] == sorted(costs)
     two = PL.ranked_history(r, 2)
     assert [e[0] for e in two] == sorted(costs)[:2] and np.array_equal(two[0][1], r.path)
+
+
+def test_steer_closed_form():
+    """Direct-mode extension: within `step` the sample itself; beyond it the
+    point at distance exactly `step` on the segment toward the sample."""
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        a = rng.uniform(-2, 2, 7)
+        b = a + rng.normal(size=7) * rng.uniform(0.01, 3.0)
+        step = float(rng.uniform(0.05, 2.0))
+        q = PL.steer(a, b, step)
+        dist = float(np.linalg.norm(b - a))
+        if dist <= step:
+            assert np.array_equal(q, b)
+        else:
+            assert float(np.linalg.norm(q - a)) == pytest.approx(step, rel=1e-12)
+            assert float(np.linalg.norm(b - q)) == pytest.approx(dist - step, rel=1e-9, abs=1e-12)
+            assert float(np.dot(q - a, b - a)) == pytest.approx(step * dist, rel=1e-12)
+    z = np.ones(7)
+    assert np.array_equal(PL.steer(z, z, 0.5), z)
+
+
+@pytest.fixture(scope="module")
+def single():
+    return W.make_problem(W.scene_single(0), 0, oracle.states_free)
+
+
+DIRECT = dict(seed=3, candidates=64, max_rounds=150, max_iterations=4, direct=True, step=1.0)
+
+
+def test_direct_plan_single_arm(single):
+    """Direct mode on one arm: no roadmap grows; the returned path obeys the
+    path invariants, and every edge but the one connection is a tree edge no
+    longer than `step`."""
+    r = PL.plan(single.scene, single.q_start, single.q_goal, PL.PlanParams(**DIRECT))
+    assert r.status == "OK"
+    assert all(len(rm.V) == 2 for rm in r.roadmaps)
+    path = r.path
+    assert np.array_equal(path[0], single.q_start) and np.array_equal(path[-1], single.q_goal)
+    _, m = oracle.classify_edges(single.scene, path[:-1], path[1:], 0.05)
+    assert np.all(m >= 0)
+    steps = np.linalg.norm(np.diff(path.astype(np.float64), axis=0), axis=1)
+    assert float(steps.sum()) == pytest.approx(r.cost, rel=1e-12)
+    assert int((steps > DIRECT["step"] * (1 + 1e-6)).sum()) <= 1
+    assert all(b < a for a, b in zip(r.costs, r.costs[1:])) and len(r.costs) >= 2
+    again = PL.plan(single.scene, single.q_start, single.q_goal, PL.PlanParams(**DIRECT))
+    assert np.array_equal(again.path, r.path)
+
+
+def test_direct_empty_scene_first_solution_closed_form():
+    """One arm, no obstacles: round 0 extends every sample from the start and
+    connects it straight to the goal, so the first solution is
+    start -> steer(start, q_rand_i) -> goal for the candidate i with the
+    least cost (recomputed here from the same streams), and the costs that
+    follow stay above the straight line."""
+    from oracle import key, u01
+    sc = W.Scene([W.panda_like(20)], W.base_transform(0, 0, 0)[None], np.zeros((0, 4), np.float32),
+                 np.zeros((0, 6), np.float32))
+    rng = np.random.default_rng(11)
+    qs, qg = W.random_configs(sc, 2, rng)
+    prm = dict(seed=4, candidates=32, max_rounds=60, max_iterations=3, direct=True, step=0.7)
+    r = PL.plan(sc, qs, qg, PL.PlanParams(**prm))
+    assert r.status == "OK" and r.first_round == 0
+    lo, hi = sc.q_lo.astype(np.float64), sc.q_hi.astype(np.float64)
+    best = None
+    for i in range(prm["candidates"]):
+        q_rand = lo + u01(key(prm["seed"], PL.PURPOSE_Q, 0, i), sc.dof) * (hi - lo)
+        qn = PL.steer(qs.astype(np.float64), q_rand, prm["step"]).astype(np.float32).astype(np.float64)
+        tot = float(np.linalg.norm(qn - qs) + np.linalg.norm(qg - qn))
+        if best is None or tot < best[0]:
+            best = (tot, qn)
+    first_cost, first_path, _ = r.history[0]
+    assert len(first_path) == 3 and np.array_equal(first_path[1].astype(np.float64), best[1])
+    assert first_cost == pytest.approx(best[0], rel=1e-6)
+    line = float(np.linalg.norm(qg.astype(np.float64) - qs))
+    assert all(c >= line * (1 - 1e-12) for c in r.costs) and r.costs[-1] < first_cost

@@ -222,6 +222,16 @@ def scene_c1(seed: int) -> Scene:
     return Scene([m, m], bases, sph, np.zeros((0, 6), F32), name=f"c1/{seed}")
 
 
+def scene_single(seed: int) -> Scene:
+    """One arm x 59 spheres at the origin (the direct-mode workload: no
+    roadmaps, the search in the arm's own joint space); 12 spheres and 12
+    axis-aligned cuboids around it in [-0.9, 0.9]^2 x [0, 1.2]."""
+    rng = np.random.default_rng([6, seed])
+    lo, hi = [-0.9, -0.9, 0.0], [0.9, 0.9, 1.2]
+    return Scene([panda_like(59)], base_transform(0.0, 0.0, 0.0)[None], _rand_spheres(rng, 12, lo, hi),
+                 _rand_boxes(rng, 12, lo, hi), name=f"single/{seed}")
+
+
 def scene_c2(seed: int) -> Scene:
     """4 arms x 59 spheres on a 1.2 m square facing the centre; 32 spheres and
     32 axis-aligned cuboids (sides U(0.05, 0.3) m)."""

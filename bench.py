@@ -272,6 +272,45 @@ def direct_leg(ctx, res: float) -> dict:
             "edge_states_per_s": states / wall if wall > 0 else None, "params": DIRECT_PLAN}
 
 
+REPLAN_FIXTURE = os.path.join(ROOT, "tests", "golden", "replan_ticks.json")
+# One replanning tick: roadmaps regrown each tick, a short search budget.
+REPLAN_PLAN = dict(candidates=128, n_roadmap=32, delta=3.0, max_rounds=40, max_iterations=2)
+
+
+def replan_leg(ctx, res: float) -> dict:
+    """Replanning amid a moving sphere (two arms of the C1 kind): per tick,
+    mrpop_scene_set_env with the sphere's new position, then mrpop_replan
+    from the previous tick's path; latency per tick, ticks whose previous
+    path stayed free (kept), solved ticks and costs."""
+    import workloads as W
+    import paper_2609_30644_amd as M
+    d = json.load(open(REPLAN_FIXTURE))
+    sph0 = np.array(d["env_spheres"], np.float32).reshape(-1, 4)
+    box0 = np.array(d["env_boxes"], np.float32).reshape(-1, 6)
+    sc = W.scene_c1(0).with_env(sph0, box0)
+    qs, qg = np.array(d["q_start"], np.float32), np.array(d["q_goal"], np.float32)
+    s = M.Scene(ctx, sc)
+    s.plan(qs, qg, raise_on_error=False, resolution=res, **dict(REPLAN_PLAN, seed=99))  # warm
+    prev, lat, env_ms, kept_n, solved, costs = None, [], [], 0, 0, []
+    for t, c in enumerate(d["ticks"]):
+        t0 = time.perf_counter()
+        s.set_env(np.concatenate([sph0, [[*c, d["radius"]]]]).astype(np.float32), box0)
+        t1 = time.perf_counter()
+        r, kept = s.replan(qs, qg, prev, raise_on_error=False, resolution=res, **dict(REPLAN_PLAN, seed=t))
+        t2 = time.perf_counter()
+        env_ms.append((t1 - t0) * 1e3)
+        lat.append((t2 - t0) * 1e3)
+        kept_n += int(kept)
+        if r.status == "OK":
+            solved += 1
+            costs.append(r.cost)
+            prev = r.path
+    return {"ticks": len(d["ticks"]), "solved": solved, "kept_previous": kept_n,
+            "tick_ms_p50": float(np.median(lat)), "tick_ms_p99": float(np.percentile(lat, 99)),
+            "set_env_ms_p50": float(np.median(env_ms)), "mean_cost": float(np.mean(costs)) if costs else None,
+            "params": REPLAN_PLAN}
+
+
 def served(ctx, rate_hz: float, duration_s: float, slots: int, mem_gb: float) -> dict:
     """Poisson arrivals of queries (2-16 arms, 32-512 obstacles) submitted to
     a continuous-batching server on the wall clock; latency is arrival ->
@@ -330,6 +369,8 @@ def main():
                     help="instances of the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--no-direct", dest="direct", action="store_false",
                     help="skip the direct-mode (single-arm, no roadmap) leg")
+    ap.add_argument("--no-replan", dest="replan", action="store_false",
+                    help="skip the replanning (moving obstacle) leg")
     ap.add_argument("--history-plans", type=int, default=10,
                     help="plans timed with and without the incumbent-history export (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the served run (0: skip)")
@@ -426,6 +467,9 @@ def main():
     if args.direct:
         print("[bench] direct mode", file=sys.stderr, flush=True)
         line["direct"] = direct_leg(ctx, res)
+    if args.replan:
+        print("[bench] replanning", file=sys.stderr, flush=True)
+        line["replan"] = replan_leg(ctx, res)
     if plans and args.history_plans > 0:
         print("[bench] incumbent history", file=sys.stderr, flush=True)
         line["history"] = history_leg(s, q_start, q_goal, res, args.history_plans)

@@ -108,6 +108,14 @@ typedef struct {
 mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32_t n_robots,
                                 const mrpop_env *env, mrpop_scene **out);
 void mrpop_scene_destroy(mrpop_scene *scene);
+
+/* Replace a scene's obstacles (paper, Sec. "Hardware Deployment": replanning
+ * amid moving obstacles, one update per tick).  The arms stay; the
+ * environment arrays, filter rows and arm-pair data are rebuilt from env as
+ * mrpop_scene_create builds them, and the tile mode is kept.  No work that
+ * uses the scene may be in flight: its old device copy is freed.  Errors as
+ * mrpop_scene_create; on error the scene is unchanged. */
+mrpop_status mrpop_scene_set_env(mrpop_scene *scene, const mrpop_env *env);
 /* Composite dimension D (sum of joints) and total sphere count. */
 int32_t mrpop_scene_dof(const mrpop_scene *scene);
 int32_t mrpop_scene_total_spheres(const mrpop_scene *scene);
@@ -305,6 +313,20 @@ void mrpop_plan_params_default(mrpop_plan_params *p);
 mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
                         const mrpop_plan_params *params, float *path_out, int32_t path_cap, int32_t *path_len,
                         float *cost_out, mrpop_plan_stats *stats_opt);
+
+/* One replanning tick (paper, Sec. "Hardware Deployment": replanning amid
+ * moving obstacles).  prev_path (host [prev_len][D]; NULL when prev_len is 0)
+ * is the previous tick's path.  When it runs exactly from q_start to q_goal
+ * and every one of its edges is free in the scene's current environment
+ * (validated at params->resolution), it becomes the starting incumbent: the
+ * call searches only for strictly cheaper paths (AO-X with c_best = its cost)
+ * and returns it when none is found.  Otherwise the call plans from scratch.
+ *   prev_valid_out  host or NULL: 1 when the previous path was kept.
+ * Outputs and statuses as mrpop_plan. */
+mrpop_status mrpop_replan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
+                          const mrpop_plan_params *params, const float *prev_path, int32_t prev_len,
+                          float *path_out, int32_t path_cap, int32_t *path_len, float *cost_out,
+                          mrpop_plan_stats *stats_opt, int32_t *prev_valid_out);
 
 /* mrpop_plan that also returns the incumbent history (above).  hist must not
  * be NULL; its arrays may be NULL only when entry_cap (offsets, costs) or

@@ -229,8 +229,10 @@ def steer(q_near: np.ndarray, q_rand: np.ndarray, step: float) -> np.ndarray:
     return q_near + (step / dist) * d
 
 
-def plan(scene, q_start, q_goal, params: PlanParams) -> PlanResult:
-    """Alg. 1 with the subroutines of Alg. 2, in rounds of P candidates."""
+def plan(scene, q_start, q_goal, params: PlanParams, warm_path=None) -> PlanResult:
+    """Alg. 1 with the subroutines of Alg. 2, in rounds of P candidates.
+    warm_path: a collision-free path (start to goal) to improve on; it is the
+    result when no strictly cheaper path is found."""
     osc = OracleScene(scene)
     R, D = scene.n_robots, scene.dof
     q_off = np.concatenate([[0], np.cumsum([m.n_joints for m in scene.models])]).astype(int)
@@ -245,6 +247,9 @@ def plan(scene, q_start, q_goal, params: PlanParams) -> PlanResult:
     arm_scenes = [OracleScene(_arm_scene(scene, r)) for r in range(R)]
     roadmaps = [_Roadmap(q_start[q_off[r]:q_off[r + 1]], q_goal[q_off[r]:q_off[r + 1]]) for r in range(R)]
     c_best, best_path, costs, history = math.inf, None, [], []
+    if warm_path is not None:
+        best_path = np.asarray(warm_path, np.float32)
+        c_best = _cost(best_path)
     rnd, it, first_round, edge_states = 0, 0, -1, 0
     solved = False
 
@@ -360,3 +365,19 @@ def ranked_history(result: PlanResult, max_entries: int = 64):
     Jerk-Free Motion"): cheapest first, at most max_entries of them -- when
     there are more paths than seeds, the cheaper ones are kept."""
     return sorted(result.history, key=lambda e: e[0])[:max_entries]
+
+
+def replan(scene, q_start, q_goal, params: PlanParams, prev_path):
+    """One replanning tick (Sec. "Hardware Deployment": replanning amid moving
+    obstacles): the previous path is kept as the incumbent when it runs
+    exactly from q_start to q_goal and every edge of it is free in the
+    current environment; then only strictly cheaper paths replace it.
+    Otherwise the planner starts from scratch.  Returns (result, kept)."""
+    kept = False
+    if prev_path is not None and len(prev_path) >= 2:
+        prev = np.asarray(prev_path, np.float32)
+        if np.array_equal(prev[0], np.asarray(q_start, np.float32)) and \
+                np.array_equal(prev[-1], np.asarray(q_goal, np.float32)):
+            valid, _, _ = validate_fast(OracleScene(scene), prev[:-1], prev[1:], params.resolution)
+            kept = bool(np.all(valid))
+    return plan(scene, q_start, q_goal, params, warm_path=prev_path if kept else None), kept

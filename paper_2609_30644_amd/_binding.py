@@ -169,6 +169,8 @@ def load_library():
     lib.mrpop_ctx_destroy.argtypes = [P]
     lib.mrpop_scene_create.argtypes = [P, P, I32, P, C.POINTER(P)]
     lib.mrpop_scene_destroy.argtypes = [P]
+    lib.mrpop_scene_set_env.argtypes = [P, P]
+    lib.mrpop_replan.argtypes = [P, P, P, P, P, P, I32, P, I32, P, P, P, P]
     lib.mrpop_scene_dof.argtypes = [P]
     lib.mrpop_scene_dof.restype = I32
     lib.mrpop_scene_total_spheres.argtypes = [P]
@@ -458,6 +460,45 @@ class Scene:
         if rc != 0 and raise_on_error:
             raise MrpopError(rc, lib.mrpop_last_error(self.ctx.handle).decode())
         return PlanResult(name, path[:plen.value].copy() if rc == 0 else None, float(cost.value), stats)
+
+    def set_env(self, env_spheres, env_boxes):
+        """mrpop_scene_set_env: replace the obstacles (N x 4 spheres, N x 6
+        boxes); the arms stay."""
+        es = np.ascontiguousarray(np.asarray(env_spheres, np.float32).reshape(-1, 4))
+        eb = np.ascontiguousarray(np.asarray(env_boxes, np.float32).reshape(-1, 6))
+        env = _Env(es.shape[0], es.ctypes.data if es.size else None, eb.shape[0], eb.ctypes.data if eb.size else None)
+        self.ctx.check(self.ctx._lib.mrpop_scene_set_env(self._h, C.byref(env)))
+
+    def replan(self, q_start, q_goal, prev_path=None, path_cap: int = 4096, raise_on_error: bool = True, **params):
+        """mrpop_replan: one replanning tick from the previous path (kept as
+        the incumbent when it is still free and runs start -> goal).  Returns
+        (PlanResult, kept)."""
+        lib = self.ctx._lib
+        pp = PlanParams()
+        lib.mrpop_plan_params_default(C.byref(pp))
+        for k, v in params.items():
+            if not hasattr(pp, k):
+                raise KeyError(k)
+            setattr(pp, k, v)
+        qs = np.ascontiguousarray(q_start, np.float32).reshape(self.dof)
+        qg = np.ascontiguousarray(q_goal, np.float32).reshape(self.dof)
+        prev = None if prev_path is None else np.ascontiguousarray(prev_path, np.float32).reshape(-1, self.dof)
+        path = np.zeros((max(1, path_cap), self.dof), np.float32)
+        plen = C.c_int32(0)
+        cost = C.c_float(0)
+        kept = C.c_int32(0)
+        st = _PlanStats()
+        rc = lib.mrpop_replan(self.ctx.handle, self._h, qs.ctypes.data, qg.ctypes.data, C.byref(pp),
+                              prev.ctypes.data if prev is not None else None, 0 if prev is None else len(prev),
+                              path.ctypes.data, path_cap, C.byref(plen), C.byref(cost), C.byref(st), C.byref(kept))
+        stats = {k: getattr(st, k) for k, _ in _PlanStats._fields_ if k != "costs"}
+        stats["costs"] = list(st.costs[:st.n_costs])
+        stats["path_len"] = plen.value
+        name = STATUS_NAMES.get(rc, str(rc))
+        if rc != 0 and raise_on_error:
+            raise MrpopError(rc, lib.mrpop_last_error(self.ctx.handle).decode())
+        return PlanResult(name, path[:plen.value].copy() if rc == 0 else None, float(cost.value), stats), \
+            bool(kept.value)
 
     def plan_with_history(self, q_start, q_goal, max_entries: int = 64, max_waypoints: int = 65536,
                           path_cap: int = 4096, raise_on_error: bool = True, **params):

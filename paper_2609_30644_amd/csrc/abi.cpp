@@ -601,6 +601,27 @@ void mrpop_scene_destroy(mrpop_scene *scene) {
   delete scene;
 }
 
+mrpop_status mrpop_scene_set_env(mrpop_scene *scene, const mrpop_env *env) {
+  if (!scene) return fail(nullptr, MRPOP_E_INVALID_ARG, "scene_set_env: scene is NULL");
+  mrpop_ctx *ctx = scene->ctx;
+  if (!env) return fail(ctx, MRPOP_E_INVALID_ARG, "scene_set_env: env is NULL");
+  // the same arms, from the scene's host copies
+  std::vector<mrpop_robot> rb(scene->h_robots.size());
+  for (size_t r = 0; r < rb.size(); ++r) {
+    const HostRobot &h = scene->h_robots[r];
+    rb[r] = mrpop_robot{h.n_joints, h.dh.data(), h.q_lo.data(), h.q_hi.data(), h.base.data(),
+                        (int32_t)(h.xyzr.size() / 4), h.link.data(), h.xyzr.data()};
+  }
+  mrpop_scene *fresh = nullptr;
+  const mrpop_status st = mrpop_scene_create(ctx, rb.data(), (int32_t)rb.size(), env, &fresh);
+  if (st != MRPOP_OK) return st;
+  const int32_t mode = scene->dev.tile_mode;
+  std::swap(*scene, *fresh);  // fresh now holds the old device copy
+  scene->dev.tile_mode = mode;
+  mrpop_scene_destroy(fresh);
+  return MRPOP_OK;
+}
+
 int32_t mrpop_scene_dof(const mrpop_scene *scene) { return scene ? scene->dof : 0; }
 int32_t mrpop_scene_total_spheres(const mrpop_scene *scene) { return scene ? scene->total_spheres : 0; }
 

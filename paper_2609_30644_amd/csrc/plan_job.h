@@ -23,6 +23,9 @@ class PlanJob {
                        const mrpop_plan_params &params);
   // Runs the planner; every device operation goes through ex.
   mrpop_status run(Exec &ex);
+  // Before run: a known collision-free path (start to goal, [len][D]) as the
+  // incumbent to improve on; it is returned if no cheaper path is found.
+  void set_incumbent(const std::vector<float> &path);
 
   // Results (after run): the best path (start -> goal, row-major [len][D]),
   // its cost recomputed in double precision, statistics, and the message of

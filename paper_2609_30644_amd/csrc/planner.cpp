@@ -517,6 +517,29 @@ mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
   return MRPOP_OK;
 }
 
+// Sum of the Euclidean steps of a path [len][D], in double precision.
+static double path_cost(const std::vector<float> &p, int D) {
+  const size_t len = p.size() / D;
+  double cost = 0.0;
+  for (size_t k = 0; k + 1 < len; ++k) {
+    double d2 = 0.0;
+    for (int j = 0; j < D; ++j) {
+      const double t = (double)p[(k + 1) * D + j] - (double)p[k * D + j];
+      d2 += t * t;
+    }
+    cost += std::sqrt(d2);
+  }
+  return cost;
+}
+
+void PlanJob::set_incumbent(const std::vector<float> &path) {
+  const float c = (float)path_cost(path, D_);
+  if (c < c_best_) {
+    c_best_ = c;
+    best_path_ = path;
+  }
+}
+
 mrpop_status PlanJob::run(Exec &ex) {
   const int R = R_, D = D_, PC = PC_;
   t_start_ = now_s();
@@ -617,15 +640,7 @@ mrpop_status PlanJob::run(Exec &ex) {
               std::swap_ranges(hpath.begin() + (size_t)x * D, hpath.begin() + (size_t)(x + 1) * D,
                                hpath.begin() + (size_t)y * D);
           }
-          double cost = 0.0;
-          for (int k = 0; k + 1 < len; ++k) {
-            double d2 = 0.0;
-            for (int j = 0; j < D; ++j) {
-              const double t = (double)hpath[(size_t)(k + 1) * D + j] - (double)hpath[(size_t)k * D + j];
-              d2 += t * t;
-            }
-            cost += std::sqrt(d2);
-          }
+          const double cost = path_cost(hpath, D);
           if ((float)cost < c_best_) {  // strictly cheaper incumbents only
             c_best_ = (float)cost;
             best_path_ = hpath;
@@ -752,7 +767,8 @@ static void write_history(const PlanJob &job, mrpop_plan_history *hist) {
 
 static mrpop_status plan_impl(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
                               const mrpop_plan_params *params, float *path_out, int32_t path_cap, int32_t *path_len,
-                              float *cost_out, mrpop_plan_stats *stats_opt, mrpop_plan_history *hist) {
+                              float *cost_out, mrpop_plan_stats *stats_opt, mrpop_plan_history *hist,
+                              const std::vector<float> *incumbent = nullptr) {
   if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "plan: ctx is NULL");
   if (!scene || scene->ctx != ctx) return fail(ctx, MRPOP_E_INVALID_ARG, "plan: scene not from this ctx");
   if (!q_start || !q_goal || !params || !path_len || !cost_out || (path_cap > 0 && !path_out))
@@ -769,6 +785,7 @@ static mrpop_status plan_impl(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   PlanJob job;
   mrpop_status st = job.prepare(ctx, scene, q_start, q_goal, *params);
   if (st == MRPOP_OK) {
+    if (incumbent) job.set_incumbent(*incumbent);
     PlainExec ex(ctx, nullptr);
     st = job.run(ex);
     if (hist) write_history(job, hist);
@@ -789,6 +806,46 @@ mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q
                         const mrpop_plan_params *params, float *path_out, int32_t path_cap, int32_t *path_len,
                         float *cost_out, mrpop_plan_stats *stats_opt) {
   return plan_impl(ctx, scene, q_start, q_goal, params, path_out, path_cap, path_len, cost_out, stats_opt, nullptr);
+}
+
+mrpop_status mrpop_replan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
+                          const mrpop_plan_params *params, const float *prev_path, int32_t prev_len,
+                          float *path_out, int32_t path_cap, int32_t *path_len, float *cost_out,
+                          mrpop_plan_stats *stats_opt, int32_t *prev_valid_out) {
+  if (prev_valid_out) *prev_valid_out = 0;
+  if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "replan: ctx is NULL");
+  if (!scene || scene->ctx != ctx) return fail(ctx, MRPOP_E_INVALID_ARG, "replan: scene not from this ctx");
+  if (!q_start || !q_goal || !params || prev_len < 0 || (prev_len > 0 && !prev_path))
+    return fail(ctx, MRPOP_E_INVALID_ARG, "replan: bad argument");
+  const int D = scene->dof;
+  std::vector<float> warm;
+  if (prev_len >= 2 && std::memcmp(prev_path, q_start, sizeof(float) * D) == 0 &&
+      std::memcmp(prev_path + (size_t)(prev_len - 1) * D, q_goal, sizeof(float) * D) == 0 &&
+      params->resolution > 0.f && std::isfinite(params->resolution)) {
+    // the previous path's edges in the current environment
+    const int64_t n = prev_len - 1;
+    const size_t fb = sizeof(float) * (size_t)n * D;
+    HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    void *buf = nullptr;
+    HIP_TRY(hipMalloc(&buf, 2 * fb + (size_t)n), "hipMalloc(replan)");
+    float *qa = (float *)buf, *qb = (float *)((unsigned char *)buf + fb);
+    uint8_t *ok = (uint8_t *)buf + 2 * fb;
+    std::vector<uint8_t> h_ok((size_t)n);
+    hipError_t e = hipMemcpy(qa, prev_path, fb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(qb, prev_path + D, fb, hipMemcpyHostToDevice);
+    mrpop_status vs = MRPOP_E_DEVICE;
+    if (e == hipSuccess) vs = mrpop_validate_edges(ctx, scene, qa, qb, n, params->resolution, nullptr, ok, nullptr, nullptr);
+    if (vs == MRPOP_OK) e = hipMemcpy(h_ok.data(), ok, (size_t)n, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    if (vs != MRPOP_OK) return vs;
+    if (e != hipSuccess) return hip_fail(ctx, e, "replan: validation copy");
+    bool all = true;
+    for (uint8_t v : h_ok) all = all && v == 1;
+    if (all) warm.assign(prev_path, prev_path + (size_t)prev_len * D);
+  }
+  if (prev_valid_out) *prev_valid_out = warm.empty() ? 0 : 1;
+  return plan_impl(ctx, scene, q_start, q_goal, params, path_out, path_cap, path_len, cost_out, stats_opt, nullptr,
+                   warm.empty() ? nullptr : &warm);
 }
 
 mrpop_status mrpop_plan_with_history(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start,

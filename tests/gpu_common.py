@@ -26,3 +26,17 @@ def assert_bits_match(valid_gpu: np.ndarray, margins: np.ndarray, what: str = ""
     assert bad.size == 0, (f"{what}: {bad.size} certain edges disagree, e.g. edge {bad[:5]} "
                            f"margins {margins[bad[:5]]} gpu {valid_gpu[bad[:5]]}")
     return {"edges": int(valid_gpu.size), "band": int((~certain).sum()), "valid": int(want.sum())}
+
+
+def blocking_obstacle(problem, path):
+    """A sphere placed on one arm sphere at a middle waypoint of `path` (so
+    the path collides), chosen so that the start and goal stay free."""
+    sc = problem.scene
+    for k in (len(path) // 2, 1, len(path) - 2):
+        centres = oracle.fk_spheres(sc, path[k][None])[0]
+        for s in range(len(centres) - 1, -1, -1):
+            sph = np.concatenate([sc.env_spheres, [[*centres[s, :3], 0.06]]]).astype(np.float32)
+            blocked = sc.with_env(sph, sc.env_boxes)
+            if oracle.states_free(blocked, np.stack([problem.q_start, problem.q_goal])).all():
+                return blocked
+    raise AssertionError("no blocking obstacle that leaves the endpoints free")

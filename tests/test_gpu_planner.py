@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_common import BAND, assert_bits_match, problem
+from gpu_common import BAND, assert_bits_match, blocking_obstacle, problem
 
 pytestmark = pytest.mark.gpu
 
@@ -303,3 +303,46 @@ def test_plan_direct_batch_equals_plain(ctx):
         assert g.status == ref.status
         if ref.status == "OK":
             assert np.array_equal(g.path, ref.path) and g.cost == ref.cost
+
+
+def test_scene_set_env_parity(ctx):
+    """mrpop_scene_set_env: after replacing the obstacles, edge bits match
+    the oracle on the new environment (and a fresh scene built from it)."""
+    print("[set_env] c1 -> new obstacles", flush=True)
+    p = problem("c1")
+    s = _scene(ctx, p.scene)
+    other = W.scene_c1(5)
+    new = p.scene.with_env(other.env_spheres, p.scene.env_boxes)
+    s.set_env(new.env_spheres, new.env_boxes)
+    qa, qb = W.edge_batch(new, 512, 0.05, seed=3)[:2]
+    got = s.validate_edges(qa, qb, 0.05).cpu().numpy()
+    _, m = oracle.classify_edges(new, qa, qb, 0.05)
+    stats = assert_bits_match(got, m, "set_env")
+    fresh = _scene(ctx, new).validate_edges(qa, qb, 0.05).cpu().numpy()
+    assert np.array_equal(got, fresh)
+    print(f"  {stats}", flush=True)
+
+
+def test_replan_tick(ctx):
+    """mrpop_replan through the C ABI: an unchanged environment keeps the
+    previous path (never worse); an obstacle placed on it (set_env) discards
+    it -- the same decision as the oracle's -- and the new path is free in
+    the new environment."""
+    print("[replan] c1", flush=True)
+    p = problem("c1")
+    s = _scene(ctx, p.scene)
+    r0 = s.plan(p.q_start, p.q_goal, **PARAMS)
+    r1, kept = s.replan(p.q_start, p.q_goal, r0.path, **dict(PARAMS, seed=7))
+    assert kept and r1.status == "OK" and r1.cost <= r0.cost
+    _check_path(p.scene, r1, p.q_start, p.q_goal, {})
+    if r1.stats["solutions"] == 0:
+        assert np.array_equal(r1.path, r0.path)
+    blocked = blocking_obstacle(p, r0.path)
+    s.set_env(blocked.env_spheres, blocked.env_boxes)
+    r2, kept2 = s.replan(p.q_start, p.q_goal, r0.path, raise_on_error=False, **PARAMS)
+    valid, _, _ = oracle.validate_fast(blocked, r0.path[:-1], r0.path[1:], 0.05)
+    assert kept2 == bool(np.all(valid)) and not kept2
+    if r2.status == "OK":
+        _, m2 = oracle.classify_edges(blocked, r2.path[:-1], r2.path[1:], 0.05)
+        assert np.all(oracle.classify(m2) >= 0)
+    s.set_env(p.scene.env_spheres, p.scene.env_boxes)

@@ -9,6 +9,7 @@ import pytest
 import oracle
 import workloads as W
 from oracle import planner as PL
+from gpu_common import blocking_obstacle
 
 PARAMS = dict(seed=1, candidates=64, max_rounds=120, max_iterations=4, n_roadmap=32, delta=3.0)
 
@@ -225,3 +226,28 @@ def test_direct_empty_scene_first_solution_closed_form():
     assert first_cost == pytest.approx(best[0], rel=1e-6)
     line = float(np.linalg.norm(qg.astype(np.float64) - qs))
     assert all(c >= line * (1 - 1e-12) for c in r.costs) and r.costs[-1] < first_cost
+
+
+def test_replan_keeps_free_incumbent_and_drops_blocked(c1):
+    """Replanning tick (Sec. "Hardware Deployment"): an unchanged environment
+    keeps the previous path as the incumbent (the result is never worse); an
+    obstacle on the path discards it and the new path avoids the obstacle; a
+    path that does not run start -> goal is not kept."""
+    prm = PL.PlanParams(**PARAMS)
+    r0 = PL.plan(c1.scene, c1.q_start, c1.q_goal, prm)
+    assert r0.status == "OK"
+    r1, kept = PL.replan(c1.scene, c1.q_start, c1.q_goal, PL.PlanParams(**dict(PARAMS, seed=7)), r0.path)
+    assert kept and r1.status == "OK" and r1.cost <= r0.cost
+    if not r1.history:
+        assert np.array_equal(r1.path, r0.path)
+    blocked = blocking_obstacle(c1, r0.path)
+    _, m = oracle.classify_edges(blocked, r0.path[:-1], r0.path[1:], 0.05)
+    assert m.min() < 0
+    r2, kept2 = PL.replan(blocked, c1.q_start, c1.q_goal, prm, r0.path)
+    assert not kept2
+    if r2.status == "OK":
+        _, m2 = oracle.classify_edges(blocked, r2.path[:-1], r2.path[1:], 0.05)
+        assert np.all(m2 >= 0)
+    _, kept3 = PL.replan(c1.scene, c1.q_start, c1.q_goal, PL.PlanParams(**dict(PARAMS, max_rounds=1)),
+                         r0.path[::-1])
+    assert not kept3

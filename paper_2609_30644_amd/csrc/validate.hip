@@ -322,27 +322,31 @@ constexpr int kQueueCap = kQueueFlushAt + kGroup * kWave;
 constexpr int kWaveLdsFloats = 12 * kWave + kQueueCap;
 
 // Scene data the tile kernel reads inside its loops: coarse rows, obstacle
-// spheres and boxes, fine spheres, link ranges and coarse radii.  STAGED:
-// copies in LDS, made once per persistent workgroup (the scalar cache starts
-// cold at every launch, and a miss costs far more than the tests one row
-// feeds).  Otherwise: the scene arrays themselves.
+// spheres and boxes, fine spheres, link ranges and coarse radii.  The coarse
+// rows, the same for every lane, always come through the scalar cache.
+// STAGED: the data read at lane-varying indices (obstacles, fine spheres,
+// link ranges, radii) is copied to LDS once per persistent workgroup.
+// Otherwise: the scene arrays themselves.
 template <bool STAGED>
 struct Src;
 
 template <>
 struct Src<true> {
-  const float4 *rows;    // [M][kMaxLinks][n4]
+  cptr<float4> rows;     // [M][kMaxLinks][n4], read through the scalar cache
   const float4 *env_s;   // [Ns]
   const float4 *boxes;   // [Nb][2]
   const float4 *fine;    // [M][sph_stride]
   const int32_t *lstart; // [M][kMaxLinks + 1]
   const float *crad;     // [M][kMaxLinks]
   int ns, nb, n4, stride;
-  // rows k0 .. k0 + kGroup - 1 of link l (LDS reads at one base address)
+  // rows k0 .. k0 + kGroup - 1 of link l: one 64-byte scalar load.  The rows
+  // are the same for every lane; from LDS each read would write them into
+  // every lane's registers, which costs more LDS bandwidth than the tests
+  // they feed.
   __device__ void group(int m, int l, int k0, float4 (&r)[kGroup]) const {
-    const float4 *p = rows + ((int64_t)m * kMaxLinks + l) * n4 + k0;
+    const cptr<float> p = (cptr<float>)(rows + ((int64_t)m * kMaxLinks + l) * n4 + k0);
 #pragma unroll
-    for (int i = 0; i < kGroup; ++i) r[i] = p[i];
+    for (int i = 0; i < kGroup; ++i) r[i] = make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
   }
   __device__ float4 sphere(int k) const { return env_s[k]; }
   __device__ float4 box(int i) const { return boxes[i]; }
@@ -372,9 +376,9 @@ struct Src<false> {
 
 // LDS floats needed to stage a scene.
 __host__ __device__ inline size_t staged_floats(const SceneDev &sc) {
-  const size_t M = sc.n_models, N = (size_t)sc.n_rows4;
-  return M * kMaxLinks * N * 4 + (size_t)sc.n_env_spheres * 4 + (size_t)sc.n_env_boxes * 8 +
-         M * (size_t)sc.sph_stride * 4 + M * (kMaxLinks + 1) + M * kMaxLinks;
+  const size_t M = sc.n_models;
+  return (size_t)sc.n_env_spheres * 4 + (size_t)sc.n_env_boxes * 8 + M * (size_t)sc.sph_stride * 4 +
+         M * (kMaxLinks + 1) + M * kMaxLinks;
 }
 
 template <bool STAGED>
@@ -390,10 +394,7 @@ __device__ Src<true> make_src<true>(const SceneDev &sc, float *stage) {
   s.n4 = sc.n_rows4;
   s.stride = sc.sph_stride;
   float4 *p = (float4 *)stage;
-  s.rows = p;
-  const int n_r = M * kMaxLinks * s.n4;
-  for (int i = threadIdx.x; i < n_r; i += blockDim.x) p[i] = sc.rows[i];
-  p += n_r;
+  s.rows = as_const(sc.rows);
   s.env_s = p;
   for (int i = threadIdx.x; i < s.ns; i += blockDim.x) p[i] = sc.env_s[i];
   p += s.ns;

@@ -448,8 +448,13 @@ __device__ void flush_queue(const Src<STAGED> &src, int m, int l, float4 cs, con
                             const uint32_t *queue, int qn, unsigned long long *hitw, int lane, WorkCount &wc) {
   wave_lds_sync();
   const int x0 = src.ls(m, l), x1 = src.ls(m, l + 1);
-  for (int i0 = 0; i0 < qn; i0 += kWave) {
-    const int i = i0 + lane;
+  // with fewer items than lanes, each item gets a group of L lanes that share
+  // its sphere loop (L a power of two, wave-uniform)
+  int L = 1;
+  while (L < kWave && qn * (2 * L) <= kWave) L *= 2;
+  const int sub = lane & (L - 1);
+  for (int i0 = 0; i0 < qn; i0 += kWave / L) {
+    const int i = i0 + lane / L;
     if (i >= qn) continue;
     const uint32_t item = queue[i];
     const int s = (int)(item & (kWave - 1));
@@ -461,7 +466,7 @@ __device__ void flush_queue(const Src<STAGED> &src, int m, int l, float4 cs, con
     bool h = false;
     if (k < src.ns) {
       const float4 o = src.sphere(k);
-      for (int x = x0; x < x1; ++x) {
+      for (int x = x0 + sub; x < x1; x += L) {
         const float4 p = src.sph(m, x);
         const float3 w = apply(G, p.x, p.y, p.z);
         const float rr = p.w + o.w;
@@ -475,9 +480,9 @@ __device__ void flush_queue(const Src<STAGED> &src, int m, int l, float4 cs, con
       const int kb = k - src.ns;
       const float4 lo = src.box(2 * kb), hi = src.box(2 * kb + 1);
       const float3 c = apply(G, cs.x, cs.y, cs.z);
-      ++wc.box_exact;
+      if (sub == 0) ++wc.box_exact;  // (every lane of the group makes the same test)
       if (box_dist2(c, lo, hi) < cs.w * cs.w) {
-        for (int x = x0; x < x1; ++x) {
+        for (int x = x0 + sub; x < x1; x += L) {
           const float4 p = src.sph(m, x);
           const float3 w = apply(G, p.x, p.y, p.z);
           ++wc.fine_b;
@@ -665,8 +670,13 @@ __device__ void flush_pairs(const SceneDev &sc, const Src<STAGED> &src, const fl
                             const LaneState &st, const uint32_t *queue, int qn, unsigned long long *hitw, int lane,
                             WorkCount &wc) {
   wave_lds_sync();
-  for (int i0 = 0; i0 < qn; i0 += kWave) {
-    const int i = i0 + lane;
+  // with fewer items than lanes, each item gets a group of L lanes that share
+  // its sphere loop (L a power of two, wave-uniform)
+  int L = 1;
+  while (L < kWave && qn * (2 * L) <= kWave) L *= 2;
+  const int sub = lane & (L - 1);
+  for (int i0 = 0; i0 < qn; i0 += kWave / L) {
+    const int i = i0 + lane / L;
     const uint32_t item = i < qn ? queue[i] : 0u;
     const int s = (int)(item & (kWave - 1)), a = (int)((item >> 6) & 7u), b = (int)((item >> 9) & 7u);
     const int p = (int)(item >> 12);
@@ -689,12 +699,12 @@ __device__ void flush_pairs(const SceneDev &sc, const Src<STAGED> &src, const fl
       const float4 q = src.sph(mj, y);
       const float3 wy = apply(Fb, q.x, q.y, q.z);
       const float rr = q.w + ca.w;
-      ++wc.fine_rr;
+      if (sub == 0) ++wc.fine_rr;  // (every lane of the group computes the same mask)
       if (dist2(wy, ca) < rr * rr) ym |= 1ull << (y - y0);
     }
     const bool rest = y1 - y0 > 64;
     bool h = false;
-    for (int x = x0; x < x1 && (ym != 0ull || rest) && !h; ++x) {
+    for (int x = x0 + sub; x < x1 && (ym != 0ull || rest) && !h; x += L) {
       const float4 q = src.sph(mi, x);
       const float3 wx = apply(Fa, q.x, q.y, q.z);
       const float rx = q.w + cb.w;

@@ -851,11 +851,11 @@ __device__ __forceinline__ void arm_joints(const SceneDev &sc, const LaneState &
 // one).
 //
 // With the joints' sines and cosines cached in LDS (sc_lds), the
-// environment stage is balanced at run time: waves first build the arms'
-// kinematic chains (one wave per arm; centres and sines and cosines into
+// environment stage is balanced at run time: the waves first compute the
+// joints' sines and cosines ((arm, joint) pairs spread over the waves, into
 // LDS), then, after a barrier, claim (arm, link) jobs from an LDS counter in
-// the order of decreasing link size, each rebuilding its link's frame from
-// the cached values (the same operations as the chain, so the same frame).
+// the order of decreasing link size, each composing its link's frame from the
+// cached values and publishing the link's coarse centre.
 // Without the cache, every wave runs whole chains for its (arm, link part)
 // jobs.  Both end with a barrier before the arm-pair stage.
 template <bool STAGED, bool CACHE>
@@ -872,13 +872,19 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
     // states of an edge that an earlier tile found colliding are skipped
     if (act && load_relaxed(flags + tl.e) == hit_token) act = false;
     if (threadIdx.x == 0) *s_next = 0;
-    for (int r = w; r < R; r += W) {
+    // A. the joints' sines and cosines at every lane's state, (arm, joint)
+    // pairs spread over the waves
+    for (int js = w; js < R * kMaxJoints; js += W) {
+      const int r = js / kMaxJoints, j = js - r * kMaxJoints;
       const int m = as_const(sc.model)[r];
-      const int nj = as_const(sc.nj)[m];
-      float qv[kMaxJoints];
-      arm_joints(sc, st, r, nj, qv);
-      if (act) ++wc.chains;
-      arm_chain(sc, r, m, qv, cen, sc_lds, lane, [](int, const Frame &, float3) { return true; });
+      if (j >= as_const(sc.nj)[m]) continue;
+      if (j == 0 && act) ++wc.chains;
+      const float qj = joint_value(st, as_const(sc.q_off)[r] + j);
+      float sn, cs;
+      sincosf(qj + as_const(sc.theta_off)[m * kMaxJoints + j], &sn, &cs);
+      float *q = sc_lds + ((r * kMaxJoints + j) * 2) * kWave + lane;
+      q[0] = sn;
+      q[kWave] = cs;
     }
     __syncthreads();
     const int n_jobs = R * kMaxLinks;
@@ -893,9 +899,15 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
       if (l > as_const(sc.nj)[m]) continue;
       const bool live = act && !hit && !((dead_mask(dead) >> lane) & 1ull);
       if (__ballot(live) == 0ull) continue;
+      // B. the link's frame from the cached values, its coarse centre
+      // (published for the arm-pair stage), then its environment tests
       const Frame F = frame_cached(sc, r, m, l, lane, sc_lds);
-      const float *p = cen + ((r * kMaxLinks + l) * 3) * kWave + lane;
-      const float3 c = make_float3(p[0], p[kWave], p[2 * kWave]);
+      const float4 co = ld4(as_const(sc.coarse), m * kMaxLinks + l);
+      const float3 c = apply(F, co.x, co.y, co.z);
+      float *slot = cen + ((r * kMaxLinks + l) * 3) * kWave + lane;
+      slot[0] = c.x;
+      slot[kWave] = c.y;
+      slot[2 * kWave] = c.z;
       if (link_env<STAGED>(sc, src, m, l, F, c, live, tl.emask, wave_fr, wave_q, &s_hit[w], dead, lane, wc))
         hit = true;
     }

@@ -210,6 +210,19 @@ int seg_link_split(int n_robots, int W);
 // Waves per workgroup and whether joint sines/cosines are cached, for a
 // launch whose largest scene has r_max arms.
 void seg_shape(int r_max, int64_t n_flat, int *W, int *cache_sc);
+// Largest many-scene batch prepared in one workgroup, and the largest batch
+// counted and scanned in one workgroup.
+constexpr int kSegSmallMax = 8;
+constexpr int64_t kSmallScanEdges = 16384;
+// The same for at most kSegSmallMax consecutive segments covering
+// [0, n_flat), n_flat <= kSmallScanEdges, given on the host: they travel as
+// kernel arguments and are stored to d_segs (room for n_segs) by the
+// preparation kernel.  Three launches instead of eight and a copy.
+hipError_t launch_validate_segments_small(const ValSeg *segs, int n_segs, int r_max, int64_t n_flat, ValSeg *d_segs,
+                                          const SegScratch &ws, hipStream_t s,
+                                          const std::pair<hipEvent_t, hipEvent_t> *ev_pair = nullptr,
+                                          uint64_t *totals = nullptr, int32_t *grid_out = nullptr,
+                                          int32_t *block_out = nullptr);
 // d_segs: device copy of the requests (tile0 is written there).
 hipError_t launch_validate_segments(ValSeg *d_segs, int n_segs, int r_max, int64_t n_flat, const SegScratch &ws,
                                     hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> *ev_pair = nullptr,

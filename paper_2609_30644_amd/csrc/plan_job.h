@@ -62,6 +62,8 @@ class PlanJob {
   mrpop_status validate_(Exec &ex, const mrpop_scene *sc, const float *a, const float *b, int64_t n, float res,
                          uint8_t *out, uint64_t *counters, const int32_t *n_codes = nullptr);
   mrpop_status copy_(Exec &ex, void *dst, const void *src, size_t bytes);
+  // Submits cs as one group of independent commands, then clears it.
+  mrpop_status group_(Exec &ex, std::vector<Cmd> &cs);
   mrpop_status roadmap_(Exec &ex, int it);
   void set_sizes_(const mrpop_scene *scene, const mrpop_plan_params &P);
   size_t plan_arena_(void *base);  // assigns the arena's arrays (base may be null); returns its size
@@ -91,7 +93,7 @@ class PlanJob {
   // rm_i_ [r][kRmInts] (taken, pair count, pair count when writing,
   // connected), uf_ [r][rm_cap] union-find parents, cnt_ [2 + r][16]
   int32_t *rm_rowptr_, *rm_col_, *rm_edges_, *rm_nv_, *rm_ne_, *pair_ids_, *rm_i_, *uf_, *deg_, *tvid_[2],
-      *tpar_[2], *tn_[2], *near_idx_, *vid_new_, *ins_idx_, *conn_idx_, *path_len_d_, *d_nj_, *d_qoff_;
+      *tpar_[2], *tn_[2], *near_idx_, *vid_new_, *ins_idx_, *conn_idx_, *d_nj_, *d_qoff_;
   int32_t *codes_ext_, *codes_conn_;  // [PC] state-count codes of the extension and connection edges
   uint8_t *cand_valid_, *pair_valid_, *alive_, *valid_, *cvalid_;
   uint64_t *cnt_;  // [2 + R][16]: counters of the extension, connection and per-arm roadmap validations
@@ -105,8 +107,8 @@ class PlanJob {
     uint8_t valid2[8];
   };
   Pinned *pin_ = nullptr;
-  int32_t *pin_rm_ = nullptr;   // [R][kRmInts + 1] (the + 1: vertex count)
-  uint64_t *pin_cnt_ = nullptr; // [R][2]
+  int32_t *pin_rm_ = nullptr;   // [R][kRmInts] copy of rm_i_, then [R] vertex counts
+  uint64_t *pin_cnt_ = nullptr; // [R][16] copy of the arms' validation counters
   float *upload_ = nullptr;  // qs, qg, roadmap seeds [R][2][kRmStride]
   int32_t *upload_i_ = nullptr;  // nj, q_off
   float *pin_path_ = nullptr;

@@ -5,9 +5,10 @@
 //   sample -> NEAREST in the extended tree -> dRRT oracle -> validate the
 //   extensions -> insert in candidate order -> NEAREST in the other tree ->
 //   validate the connections -> pick the cheapest connection.
-// One small status record per round comes back to the host (pinned memory),
-// which decides whether the search ended, swaps the trees when the extended
-// one has grown larger, and extracts a path on success.
+// One small status record per round comes back to the host: the selection
+// kernel writes it straight into pinned memory.  The host decides whether
+// the search ended, swaps the trees when the extended one has grown larger,
+// and extracts a path on success.
 //
 // The driver is a PlanJob: its device work goes through an Exec, which runs
 // it at once on a stream for mrpop_plan, or merges it with other instances'
@@ -90,6 +91,27 @@ class PlainExec : public Exec {
       return hipMemcpyAsync(c.copy.dst, c.copy.src, c.copy.bytes, hipMemcpyDefault, s_);
     return launch_op(c.op, c.args(), s_);
   }
+  // Each run of one kind launches as one kernel, kGroupMax records at a time;
+  // copies too large for the copy kernel go to the runtime one by one.
+  hipError_t submit_independent(const Cmd *cs, int n) override {
+    hipError_t e = flush_validations();
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < n;) {
+      const Op op = cs[i].op;
+      if (op == Op::Validate) return hipErrorInvalidValue;
+      if (op == Op::Copy && cs[i].copy.bytes > kKernelCopyMax) {
+        if ((e = submit(cs[i])) != hipSuccess) return e;
+        ++i;
+        continue;
+      }
+      const void *recs[kGroupMax];
+      int k = 0;
+      while (i < n && k < kGroupMax && cs[i].op == op && !(op == Op::Copy && cs[i].copy.bytes > kKernelCopyMax))
+        recs[k++] = cs[i++].args();
+      if ((e = launch_op_group(op, recs, k, s_)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   hipError_t sync() override {
     hipError_t e = flush_validations();
     if (e != hipSuccess) return e;
@@ -130,7 +152,21 @@ class PlainExec : public Exec {
     int W = 0, cache = 0;
     seg_shape(r_max, flat, &W, &cache);
     const size_t bytes = sizeof(ValSeg) * v.size();
+    const bool small = (int)v.size() <= kSegSmallMax && flat <= kSmallScanEdges;
     hipError_t e;
+    if (small) {  // the table travels as kernel arguments
+      ValSeg h[kSegSmallMax];
+      int64_t e0 = 0;
+      for (size_t i = 0; i < v.size(); ++i) {
+        fill_seg(h[i], v[i], e0, W);
+        e0 += v[i].n;
+      }
+      if ((e = ensure_seg_buffers(bytes, flat)) != hipSuccess) return e;
+      return launch_validate_segments_small(h, (int)v.size(), r_max, flat, (ValSeg *)d_segs_,
+                                            seg_scratch_layout(seg_ws_, flat), s_, profile_slot(ctx_),
+                                            ctx_->profiling ? ctx_->prof_totals : nullptr, &ctx_->last_grid,
+                                            &ctx_->last_block);
+    }
     if (used_ == staging_.size() || stage_bytes_ < bytes) {
       if (stage_bytes_ < bytes) {  // all staging buffers grow together (only between syncs if in use)
         if (used_ > 0 && (e = hipStreamSynchronize(s_)) != hipSuccess) return e;
@@ -146,19 +182,32 @@ class PlainExec : public Exec {
     ValSeg *h = (ValSeg *)staging_[used_++];
     int64_t e0 = 0;
     for (size_t i = 0; i < v.size(); ++i) {
-      ValSeg &g = h[i];
-      std::memset(&g, 0, sizeof(g));
-      g.sc = *v[i].scene;
-      g.qa = v[i].qa;
-      g.qb = v[i].qb;
-      g.edge0 = e0;
-      g.n_edges = v[i].n;
-      g.res = v[i].res;
-      g.S = seg_link_split(v[i].scene->n_robots, W);
-      g.out = v[i].out;
-      g.counters = v[i].counters;
+      fill_seg(h[i], v[i], e0, W);
       e0 += v[i].n;
     }
+    if ((e = ensure_seg_buffers(bytes, flat)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(d_segs_, h, bytes, hipMemcpyHostToDevice, s_)) != hipSuccess) return e;
+    return launch_validate_segments((ValSeg *)d_segs_, (int)v.size(), r_max, flat, seg_scratch_layout(seg_ws_, flat),
+                                    s_, profile_slot(ctx_), ctx_->profiling ? ctx_->prof_totals : nullptr,
+                                    &ctx_->last_grid, &ctx_->last_block);
+  }
+
+  static void fill_seg(ValSeg &g, const ValidateReq &q, int64_t edge0, int W) {
+    std::memset(&g, 0, sizeof(g));
+    g.sc = *q.scene;
+    g.qa = q.qa;
+    g.qb = q.qb;
+    g.edge0 = edge0;
+    g.n_edges = q.n;
+    g.res = q.res;
+    g.S = seg_link_split(q.scene->n_robots, W);
+    g.out = q.out;
+    g.counters = q.counters;
+  }
+  // Device segment table (bytes) and scratch for n_flat edges; a buffer in
+  // use by queued work is only replaced after the stream has drained.
+  hipError_t ensure_seg_buffers(size_t bytes, int64_t flat) {
+    hipError_t e;
     if (d_segs_bytes_ < bytes) {
       if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
       if (d_segs_) (void)hipFree(d_segs_);
@@ -174,10 +223,7 @@ class PlainExec : public Exec {
       seg_ws_bytes_ = std::max(ws_bytes, 2 * seg_ws_bytes_);
       if ((e = hipMalloc(&seg_ws_, seg_ws_bytes_)) != hipSuccess) return e;
     }
-    if ((e = hipMemcpyAsync(d_segs_, h, bytes, hipMemcpyHostToDevice, s_)) != hipSuccess) return e;
-    return launch_validate_segments((ValSeg *)d_segs_, (int)v.size(), r_max, flat, seg_scratch_layout(seg_ws_, flat),
-                                    s_, profile_slot(ctx_), ctx_->profiling ? ctx_->prof_totals : nullptr,
-                                    &ctx_->last_grid, &ctx_->last_block);
+    return hipSuccess;
   }
 
   mrpop_ctx *ctx_;
@@ -267,7 +313,6 @@ size_t PlanJob::plan_arena_(void *base) {
   ar.add(&cnt_, (size_t)(2 + R) * 16);
   ar.add(&status_, 1);
   ar.add(&path_d_, (size_t)path_max_ * D);
-  ar.add(&path_len_d_, 1);
   ar.add(&d_nj_, R);
   ar.add(&d_qoff_, R);
   if (base) ar.assign(base);
@@ -316,7 +361,7 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   if ((e = hipHostMalloc((void **)&pin_, sizeof(Pinned))) != hipSuccess) return hip_fail_(e, "hipHostMalloc");
   if ((e = hipHostMalloc((void **)&pin_rm_, sizeof(int32_t) * (size_t)R * (kRmInts + 1))) != hipSuccess)
     return hip_fail_(e, "hipHostMalloc");
-  if ((e = hipHostMalloc((void **)&pin_cnt_, sizeof(uint64_t) * (size_t)R * 2)) != hipSuccess)
+  if ((e = hipHostMalloc((void **)&pin_cnt_, sizeof(uint64_t) * (size_t)R * 16)) != hipSuccess)
     return hip_fail_(e, "hipHostMalloc");
   const size_t up_floats = 2 * (size_t)D + (size_t)R * 2 * kRmStride;
   if ((e = hipHostMalloc((void **)&upload_, sizeof(float) * up_floats)) != hipSuccess)
@@ -367,6 +412,12 @@ mrpop_status PlanJob::copy_(Exec &ex, void *dst, const void *src, size_t bytes) 
   return e == hipSuccess ? MRPOP_OK : hip_fail_(e, "copy");
 }
 
+mrpop_status PlanJob::group_(Exec &ex, std::vector<Cmd> &cs) {
+  const hipError_t e = cs.empty() ? hipSuccess : ex.submit_independent(cs.data(), (int)cs.size());
+  cs.clear();
+  return e == hipSuccess ? MRPOP_OK : hip_fail_(e, "group");
+}
+
 mrpop_status PlanJob::validate_(Exec &ex, const mrpop_scene *sc, const float *a, const float *b, int64_t n,
                                 float res, uint8_t *out, uint64_t *counters, const int32_t *n_codes) {
   if (n <= 0) {
@@ -405,8 +456,8 @@ mrpop_status PlanJob::validate_(Exec &ex, const mrpop_scene *sc, const float *a,
   } while (0)
 
 // ROADMAP (Alg. 2) for outer iteration `it`.  Every arm still unconnected
-// grows in the same steps (its launches side by side, one host round trip per
-// step): free samples, counts of candidate pairs (new vertex, any vertex
+// grows in the same steps (the arms' commands of a step submitted as one
+// independent group, two host round trips per growth round): free samples, counts of candidate pairs (new vertex, any vertex
 // within delta), then the pairs themselves, their single-arm validation and
 // the union of the components they join; connectivity of start and goal is
 // read from the union-find.  The adjacency used by the extension oracle is
@@ -414,11 +465,20 @@ mrpop_status PlanJob::validate_(Exec &ex, const mrpop_scene *sc, const float *a,
 mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
   const int R = R_;
   std::vector<char> conn(R, 0), grew(R, 0);
-  std::vector<int> need(R, 0), n0(R, 0), np(R, 0), off(R, 0);
+  std::vector<int> need(R, 0), need0(R, 0), n0(R, 0), np(R, 0), off(R, 0);
   auto ri = [&](int r, int i) { return rm_i_ + (size_t)r * kRmInts + i; };
   auto cand = [&](int r) { return cand_ + (size_t)r * cand_batch_ * kRmStride; };
   auto candv = [&](int r) { return cand_valid_ + (size_t)r * cand_batch_; };
   auto V = [&](int r) { return rm_V_ + (size_t)r * rm_cap_ * kRmStride; };
+  std::vector<Cmd> grp;
+  auto add = [&](Op op) -> Cmd & {
+    grp.emplace_back();
+    grp.back().op = op;
+    return grp.back();
+  };
+  auto add_copy = [&](void *dst, const void *src, size_t bytes) {
+    add(Op::Copy).copy = CopyArgs{dst, src, (int64_t)bytes};
+  };
   for (int g = 0; g < P_.max_growth_rounds; ++g) {
     std::vector<int> todo;
     for (int r = 0; r < R; ++r)
@@ -429,44 +489,51 @@ mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
       n0[r] = rm_n_[r];
       need[r] = std::min(P_.n_roadmap, rm_cap_ - n0[r]);
       if (need[r] <= 0) st_.capacity_hit = 1;
+      need0[r] = std::max(need[r], 0);
     }
+    // 2. with them, the count of candidate pairs per arm (then the pair buffer
+    // is shared in arm order).  Every pass counts the pairs of the arms whose
+    // vertices it changed (all arms in the first), bounded by the vertex count
+    // on the device, so counts and samples share one host round trip.
     for (int64_t j0 = 0;; j0 += cand_batch_) {
-      std::vector<int> act;
+      std::vector<int> act, counted;
       for (int r : todo)
         if (need[r] > 0) act.push_back(r);
-      if (act.empty()) break;
-      for (int r : act)
-        SUBMIT(Op::RmSample, rm_sample,
-               RmSampleArgs{cand(r), cand_batch_, h_nj_[r], scene_->dev.q_lo + h_qoff_[r],
-                            scene_->dev.q_hi + h_qoff_[r], roadmap_key(P_.seed, (uint64_t)it * 1024 + g, (uint64_t)r),
-                            j0});
-      for (int r : act)  // consecutive validations: one launch over the arms
-        TRY(validate_(ex, arms_[r], cand(r), cand(r), cand_batch_, 1.0f, candv(r), cnt_ + (size_t)(2 + r) * 16));
-      for (int r : act) {
-        SUBMIT(Op::RmAccept, rm_accept,
-               RmAcceptArgs{cand(r), candv(r), cand_batch_, h_nj_[r], need[r], V(r), rm_nv_ + r, rm_cap_, ri(r, 0),
-                            uf_ + (size_t)r * rm_cap_});
-        TRY(copy_(ex, pin_rm_ + (size_t)r * (kRmInts + 1), ri(r, 0), sizeof(int32_t)));
-        TRY(copy_(ex, pin_rm_ + (size_t)r * (kRmInts + 1) + kRmInts, rm_nv_ + r, sizeof(int32_t)));
+      if (j0 == 0) counted = todo;
+      else counted = act;
+      if (counted.empty()) break;
+      if (!act.empty()) {
+        for (int r : act)
+          add(Op::RmSample).rm_sample = RmSampleArgs{cand(r), cand_batch_, h_nj_[r], scene_->dev.q_lo + h_qoff_[r],
+                                                     scene_->dev.q_hi + h_qoff_[r],
+                                                     roadmap_key(P_.seed, (uint64_t)it * 1024 + g, (uint64_t)r), j0};
+        TRY(group_(ex, grp));
+        for (int r : act)  // consecutive validations: one launch over the arms
+          TRY(validate_(ex, arms_[r], cand(r), cand(r), cand_batch_, 1.0f, candv(r), cnt_ + (size_t)(2 + r) * 16));
+        for (int r : act)
+          add(Op::RmAccept).rm_accept = RmAcceptArgs{cand(r), candv(r), cand_batch_, h_nj_[r], need[r], V(r),
+                                                     rm_nv_ + r, rm_cap_, ri(r, 0), uf_ + (size_t)r * rm_cap_};
+        TRY(group_(ex, grp));
       }
+      for (int r : counted) add(Op::Fill).fill = FillArgs{(uint32_t *)ri(r, 1), 0u, 2};
+      TRY(group_(ex, grp));
+      for (int r : counted)
+        add(Op::RmPairs).rm_pairs = RmPairsArgs{V(r), n0[r], n0[r] + need0[r], h_nj_[r], P_.delta, ri(r, 1), 0,
+                                                nullptr, nullptr, nullptr, rm_nv_ + r};
+      TRY(group_(ex, grp));
+      add_copy(pin_rm_, rm_i_, sizeof(int32_t) * (size_t)R * kRmInts);
+      add_copy(pin_rm_ + (size_t)R * kRmInts, rm_nv_, sizeof(int32_t) * (size_t)R);
+      TRY(group_(ex, grp));
       SYNC();
       for (int r : act) {
-        need[r] -= pin_rm_[(size_t)r * (kRmInts + 1)];
-        rm_n_[r] = pin_rm_[(size_t)r * (kRmInts + 1) + kRmInts];
+        need[r] -= pin_rm_[(size_t)r * kRmInts];
+        rm_n_[r] = pin_rm_[(size_t)R * kRmInts + r];
       }
-      if (j0 > (int64_t)cand_batch_ * 64) break;  // (nearly) no free space left
+      if (act.empty() || j0 > (int64_t)cand_batch_ * 64) break;  // (nearly) no free space left
     }
-    // 2. candidate pairs per arm: count, then share the pair buffer in arm order
-    for (int r : todo) {
-      SUBMIT(Op::Fill, fill, FillArgs{(uint32_t *)ri(r, 1), 0u, 2});
-      SUBMIT(Op::RmPairs, rm_pairs,
-             RmPairsArgs{V(r), n0[r], rm_n_[r], h_nj_[r], P_.delta, ri(r, 1), 0, nullptr, nullptr, nullptr});
-      TRY(copy_(ex, pin_rm_ + (size_t)r * (kRmInts + 1) + 1, ri(r, 1), sizeof(int32_t)));
-    }
-    SYNC();
     int base = 0;
     for (int r : todo) {
-      const int want = pin_rm_[(size_t)r * (kRmInts + 1) + 1];
+      const int want = pin_rm_[(size_t)r * kRmInts + 1];
       np[r] = std::min(want, pair_cap_ - base);
       if (want > np[r]) st_.capacity_hit = 1;
       off[r] = base;
@@ -475,31 +542,34 @@ mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
     // 3. the pairs, their validation, new edges, union of components
     for (int r : todo)
       if (np[r] > 0)
-        SUBMIT(Op::RmPairs, rm_pairs,
-               RmPairsArgs{V(r), n0[r], rm_n_[r], h_nj_[r], P_.delta, ri(r, 2), np[r], pair_ids_ + 2 * (size_t)off[r],
-                           pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r]});
+        add(Op::RmPairs).rm_pairs =
+            RmPairsArgs{V(r), n0[r], rm_n_[r], h_nj_[r], P_.delta, ri(r, 2), np[r], pair_ids_ + 2 * (size_t)off[r],
+                        pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r], nullptr};
+    TRY(group_(ex, grp));
     for (int r : todo)
       if (np[r] > 0)
         TRY(validate_(ex, arms_[r], pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r],
                       np[r], P_.resolution, pair_valid_ + off[r], cnt_ + (size_t)(2 + r) * 16));
-    for (int r : todo) {
+    for (int r : todo)
       if (np[r] > 0) {
-        SUBMIT(Op::RmAddEdges, rm_add_edges,
-               RmAddEdgesArgs{pair_ids_ + 2 * (size_t)off[r], pair_valid_ + off[r], ri(r, 2), np[r],
-                              rm_edges_ + (size_t)r * edge_cap_ * 2, rm_ne_ + r, edge_cap_});
+        add(Op::RmAddEdges).rm_add_edges =
+            RmAddEdgesArgs{pair_ids_ + 2 * (size_t)off[r], pair_valid_ + off[r], ri(r, 2), np[r],
+                           rm_edges_ + (size_t)r * edge_cap_ * 2, rm_ne_ + r, edge_cap_};
         grew[r] = 1;
       }
-      SUBMIT(Op::RmUnion, rm_union,
-             RmUnionArgs{pair_ids_ + 2 * (size_t)off[r], pair_valid_ + off[r], ri(r, 2), np[r], rm_n_[r],
-                         uf_ + (size_t)r * rm_cap_, ri(r, 3)});
-      TRY(copy_(ex, pin_rm_ + (size_t)r * (kRmInts + 1) + 3, ri(r, 3), sizeof(int32_t)));
-      if (np[r] > 0) TRY(copy_(ex, pin_cnt_ + (size_t)r * 2, cnt_ + (size_t)(2 + r) * 16, 2 * sizeof(uint64_t)));
-    }
+    TRY(group_(ex, grp));
+    for (int r : todo)
+      add(Op::RmUnion).rm_union = RmUnionArgs{pair_ids_ + 2 * (size_t)off[r], pair_valid_ + off[r], ri(r, 2), np[r],
+                                              rm_n_[r], uf_ + (size_t)r * rm_cap_, ri(r, 3)};
+    TRY(group_(ex, grp));
+    add_copy(pin_rm_, rm_i_, sizeof(int32_t) * (size_t)R * kRmInts);
+    add_copy(pin_cnt_, cnt_ + 2 * 16, sizeof(uint64_t) * 16 * (size_t)R);
+    TRY(group_(ex, grp));
     SYNC();
     bool all = true;
     for (int r : todo) {
-      if (np[r] > 0) st_.roadmap_edge_states += (int64_t)pin_cnt_[(size_t)r * 2 + 1];
-      conn[r] = (char)pin_rm_[(size_t)r * (kRmInts + 1) + 3];
+      if (np[r] > 0) st_.roadmap_edge_states += (int64_t)pin_cnt_[(size_t)r * 16 + 1];
+      conn[r] = (char)pin_rm_[(size_t)r * kRmInts + 3];
     }
     for (int r = 0; r < R; ++r) all = all && conn[r];
     if (all) break;
@@ -508,10 +578,10 @@ mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
   // adjacency (CSR) of the arms that gained edges
   for (int r = 0; r < R; ++r)
     if (grew[r])
-      SUBMIT(Op::RmBfs, rm_bfs,
-             RmBfsArgs{rm_edges_ + (size_t)r * edge_cap_ * 2, rm_ne_ + r, edge_cap_, rm_n_[r],
-                       rm_rowptr_ + (size_t)r * (rm_cap_ + 1), rm_col_ + (size_t)r * col_cap_, col_cap_,
-                       deg_ + (size_t)r * rm_cap_, nullptr, nullptr});
+      add(Op::RmBfs).rm_bfs = RmBfsArgs{rm_edges_ + (size_t)r * edge_cap_ * 2, rm_ne_ + r, edge_cap_, rm_n_[r],
+                                        rm_rowptr_ + (size_t)r * (rm_cap_ + 1), rm_col_ + (size_t)r * col_cap_,
+                                        col_cap_, deg_ + (size_t)r * rm_cap_, nullptr, nullptr};
+  TRY(group_(ex, grp));
   st_.roadmap_connected = 1;
   for (int r = 0; r < R; ++r) st_.roadmap_connected = st_.roadmap_connected && conn[r];
   return MRPOP_OK;
@@ -543,22 +613,29 @@ void PlanJob::set_incumbent(const std::vector<float> &path) {
 mrpop_status PlanJob::run(Exec &ex) {
   const int R = R_, D = D_, PC = PC_;
   t_start_ = now_s();
-  // uploads
-  TRY(copy_(ex, qs_, upload_, sizeof(float) * D));
-  TRY(copy_(ex, qg_, upload_ + D, sizeof(float) * D));
-  TRY(copy_(ex, d_nj_, upload_i_, sizeof(int32_t) * R));
-  TRY(copy_(ex, d_qoff_, upload_i_ + R, sizeof(int32_t) * R));
-  TRY(copy_(ex, rm_nv_, upload_i_ + 2 * R, sizeof(int32_t) * R));
-  TRY(copy_(ex, rm_ne_, upload_i_ + 3 * R, sizeof(int32_t) * R));
+  // uploads (independent copies into distinct buffers) and the endpoints
+  std::vector<Cmd> grp;
+  auto add_copy = [&](void *dst, const void *src, size_t bytes) {
+    grp.emplace_back();
+    grp.back().op = Op::Copy;
+    grp.back().copy = CopyArgs{dst, src, (int64_t)bytes};
+  };
+  add_copy(qs_, upload_, sizeof(float) * D);
+  add_copy(qg_, upload_ + D, sizeof(float) * D);
+  add_copy(ea_, upload_, sizeof(float) * D);
+  add_copy(ea_ + D, upload_ + D, sizeof(float) * D);
+  add_copy(d_nj_, upload_i_, sizeof(int32_t) * R);
+  add_copy(d_qoff_, upload_i_ + R, sizeof(int32_t) * R);
+  add_copy(rm_nv_, upload_i_ + 2 * R, sizeof(int32_t) * R);
+  add_copy(rm_ne_, upload_i_ + 3 * R, sizeof(int32_t) * R);
   for (int r = 0; r < R; ++r)
-    TRY(copy_(ex, rm_V_ + (size_t)r * rm_cap_ * kRmStride, upload_ + 2 * D + (size_t)r * 2 * kRmStride,
-              sizeof(float) * 2 * kRmStride));
-  for (int r = 0; r < R; ++r) TRY(copy_(ex, uf_ + (size_t)r * rm_cap_, upload_i_ + 4 * R, 2 * sizeof(int32_t)));
-  SUBMIT(Op::Fill, fill, FillArgs{(uint32_t *)rm_rowptr_, 0u, (int64_t)R * (rm_cap_ + 1)});
-
-  // endpoints
-  TRY(copy_(ex, ea_, upload_, sizeof(float) * D));
-  TRY(copy_(ex, ea_ + D, upload_ + D, sizeof(float) * D));
+    add_copy(rm_V_ + (size_t)r * rm_cap_ * kRmStride, upload_ + 2 * D + (size_t)r * 2 * kRmStride,
+             sizeof(float) * 2 * kRmStride);
+  for (int r = 0; r < R; ++r) add_copy(uf_ + (size_t)r * rm_cap_, upload_i_ + 4 * R, 2 * sizeof(int32_t));
+  grp.emplace_back();
+  grp.back().op = Op::Fill;
+  grp.back().fill = FillArgs{(uint32_t *)rm_rowptr_, 0u, (int64_t)R * (rm_cap_ + 1)};
+  TRY(group_(ex, grp));
   TRY(validate_(ex, scene_, ea_, ea_, 2, 1.0f, valid_, cnt_));
   TRY(copy_(ex, pin_->valid2, valid_, 2));
   SYNC();
@@ -605,8 +682,7 @@ mrpop_status PlanJob::run(Exec &ex) {
       TRY(validate_(ex, scene_, ca_, cb_, PC, P_.resolution, cvalid_, cnt_ + 16, codes_conn_));
       SUBMIT(Op::Select, select,
              SelectArgs{PC, D, ins_idx_, conn_idx_, cvalid_, q_new_, g_new_, tq_[b], tg_[b], tcap_, cnt_, cnt_ + 16,
-                        status_});
-      TRY(copy_(ex, &pin_->status, status_, sizeof(RoundStatus)));
+                        status_, &pin_->status});
       SYNC();
       const RoundStatus rsx = pin_->status;
       st_.edge_states += rsx.states_ext + rsx.states_conn;
@@ -616,8 +692,7 @@ mrpop_status PlanJob::run(Exec &ex) {
       if (rsx.found) {
         SUBMIT(Op::Path, path,
                PathArgs{rsx.a_idx, rsx.b_idx, D, tcap_, path_max_, tpar_[a], tpar_[b], tq_[a], tq_[b], path_d_,
-                        path_len_d_});
-        TRY(copy_(ex, &pin_->ints[0], path_len_d_, sizeof(int32_t)));
+                        &pin_->ints[0]});
         SYNC();
         const int len = pin_->ints[0];
         if (len > path_max_ || len < 2) {

@@ -119,6 +119,7 @@ struct SelectArgs {
   int tree_cap;
   const uint64_t *states_ext, *states_conn;  // validation counters (index 1: edge states)
   RoundStatus *status;
+  RoundStatus *status_out;  // or null: receives the round's finished record (e.g. pinned host memory)
 };
 
 struct PathArgs {
@@ -164,6 +165,7 @@ struct RmPairsArgs {
   int cap;
   int32_t *pair_ids;
   float *qa, *qb;
+  const int32_t *i1_dev;  // or null: i1 is lowered to *i1_dev (the vertex count on the device)
 };
 
 struct RmAddEdgesArgs {
@@ -239,6 +241,10 @@ int op_blocks(Op op, const void *args);
 size_t op_args_bytes(Op op);
 hipError_t launch_op(Op op, const void *args, hipStream_t s);
 hipError_t launch_op_batch(Op op, const void *d_args, int count, int grid_x, hipStream_t s);
+// n (1..kGroupMax) records of one kind, independent of each other, in one
+// launch with the records passed by value (blockIdx.y selects the record).
+constexpr int kGroupMax = 8;
+hipError_t launch_op_group(Op op, const void *const *args, int n, hipStream_t s);
 
 // A validation request of the planner: edges (qa[i], qb[i]) of one scene;
 // bits to out[i]; the call's counters (the validation counter layout, [1] =
@@ -287,6 +293,16 @@ class Exec {
  public:
   virtual ~Exec() = default;
   virtual hipError_t submit(const Cmd &c) = 0;
+  // Commands none of which depends on another (no validations among them):
+  // they may run in any order or concurrently, after everything submitted
+  // before them and before everything submitted after them.
+  virtual hipError_t submit_independent(const Cmd *cs, int n) {
+    for (int i = 0; i < n; ++i) {
+      const hipError_t e = submit(cs[i]);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   virtual hipError_t sync() = 0;
 };
 

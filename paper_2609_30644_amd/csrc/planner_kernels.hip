@@ -546,6 +546,7 @@ __device__ __forceinline__ void select_body(const SelectArgs &a, int bx) {
     a.status->total = sc[0];
     a.status->states_ext = a.states_ext ? (int64_t)a.states_ext[1] : 0;
     a.status->states_conn = a.states_conn ? (int64_t)a.states_conn[1] : 0;
+    if (a.status_out) *a.status_out = *a.status;
   }
 }
 
@@ -647,13 +648,15 @@ __device__ __forceinline__ void rm_accept_body(const RmAcceptArgs &A, int bx) {
   }
 }
 
-// Pairs (j, i), i in [i0, i1), j < i, with |V_i - V_j| <= delta: counted
+// Pairs (j, i), i in [i0, i1) (i1 lowered to the device's vertex count when
+// given), j < i, with |V_i - V_j| <= delta: counted
 // (pair_ids null), or written as edge endpoints (qa = V_j, qb = V_i) and ids,
 // compacted with an atomic counter (their order does not reach any result: adjacency is rebuilt as a
 // set and the extension oracle breaks ties by vertex id).
 __device__ __forceinline__ void rm_pairs_body(const RmPairsArgs &A, int bx) {
   const float *V = A.V;
-  const int i0 = A.i0, i1 = A.i1, nj = A.nj, cap = A.cap;
+  const int i0 = A.i0, nj = A.nj, cap = A.cap;
+  const int i1 = A.i1_dev ? min(A.i1, *A.i1_dev) : A.i1;
   const float delta = A.delta;
   int32_t *count = A.count, *pair_ids = A.pair_ids;
   float *qa = A.qa, *qb = A.qb;
@@ -831,12 +834,22 @@ __device__ __forceinline__ void copy_body(const CopyArgs &a, int bx) {
 // entry points: one record, or many records (blockIdx.y) per launch
 // ---------------------------------------------------------------------------
 
+// A group of up to kGroupMax records passed by value (kernel arguments).
+template <class Args>
+struct OpGroup {
+  Args a[kGroupMax];
+};
+
 #define MRPOP_OP_KERNELS(name, Args, threads)                                              \
   constexpr int name##_threads = threads;                                                  \
+  static_assert(sizeof(OpGroup<Args>) <= 4096, "group of " #Args " exceeds the kernel argument space"); \
   __global__ __launch_bounds__(threads) void name##_kernel(Args a) { name##_body(a, blockIdx.x); } \
   __global__ __launch_bounds__(threads) void name##_batch_kernel(const Args *records) {     \
     const Args a = records[blockIdx.y];                                                    \
     name##_body(a, blockIdx.x);                                                            \
+  }                                                                                        \
+  __global__ __launch_bounds__(threads) void name##_group_kernel(OpGroup<Args> g) {        \
+    name##_body(g.a[blockIdx.y], blockIdx.x);                                              \
   }
 
 MRPOP_OP_KERNELS(sample, SampleArgs, kSampleWaves * kWave)
@@ -933,6 +946,39 @@ static hipError_t op_check(Op op, const void *p) {
       hipLaunchKernelGGL(name##_kernel, dim3((unsigned)grid_x), dim3(name##_threads), 0, s, *(const Args *)p); \
     break;
 
+#define MRPOP_GROUP_CASE(OP, name, Args)                                                             \
+  case Op::OP: {                                                                                   \
+    OpGroup<Args> g;                                                                               \
+    for (int i = 0; i < n; ++i) g.a[i] = *(const Args *)recs[i];                                   \
+    for (int i = n; i < kGroupMax; ++i) g.a[i] = g.a[0];                                           \
+    hipLaunchKernelGGL(name##_group_kernel, dim3((unsigned)grid_x, (unsigned)n), dim3(name##_threads), 0, s, g); \
+    break;                                                                                         \
+  }
+
+static hipError_t launch_group_any(Op op, const void *const *recs, int n, int grid_x, hipStream_t s) {
+  switch (op) {
+    MRPOP_GROUP_CASE(Sample, sample, SampleArgs)
+    MRPOP_GROUP_CASE(Nearest, nearest, NearestArgs)
+    MRPOP_GROUP_CASE(Extend, extend, ExtendArgs)
+    MRPOP_GROUP_CASE(Steer, steer, SteerArgs)
+    MRPOP_GROUP_CASE(Insert, insert, InsertArgs)
+    MRPOP_GROUP_CASE(Conn, conn, ConnArgs)
+    MRPOP_GROUP_CASE(Select, select, SelectArgs)
+    MRPOP_GROUP_CASE(Path, path, PathArgs)
+    MRPOP_GROUP_CASE(TreeRoot, tree_root, TreeRootArgs)
+    MRPOP_GROUP_CASE(RmSample, rm_sample, RmSampleArgs)
+    MRPOP_GROUP_CASE(RmAccept, rm_accept, RmAcceptArgs)
+    MRPOP_GROUP_CASE(RmPairs, rm_pairs, RmPairsArgs)
+    MRPOP_GROUP_CASE(RmAddEdges, rm_add_edges, RmAddEdgesArgs)
+    MRPOP_GROUP_CASE(RmBfs, rm_csr_bfs, RmBfsArgs)
+    MRPOP_GROUP_CASE(RmUnion, rm_union, RmUnionArgs)
+    MRPOP_GROUP_CASE(Fill, fill, FillArgs)
+    MRPOP_GROUP_CASE(Copy, copy, CopyArgs)
+    case Op::Validate: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 static hipError_t launch_any(Op op, const void *p, bool batch, int count, int grid_x, hipStream_t s) {
   switch (op) {
     MRPOP_OP_CASE(Sample, sample, SampleArgs)
@@ -963,6 +1009,19 @@ hipError_t launch_op(Op op, const void *args, hipStream_t s) {
   const int g = op_blocks(op, args);
   if (g <= 0) return hipSuccess;
   return launch_any(op, args, false, 1, g, s);
+}
+
+hipError_t launch_op_group(Op op, const void *const *args, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n > kGroupMax || op == Op::Validate) return hipErrorInvalidValue;
+  int g = 0;
+  for (int i = 0; i < n; ++i) {
+    const hipError_t c = op_check(op, args[i]);
+    if (c != hipSuccess) return c;
+    g = std::max(g, op_blocks(op, args[i]));
+  }
+  if (g <= 0) return hipSuccess;
+  return launch_group_any(op, args, n, g, s);
 }
 
 hipError_t launch_op_batch(Op op, const void *d_args, int count, int grid_x, hipStream_t s) {

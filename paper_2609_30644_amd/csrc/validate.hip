@@ -33,6 +33,7 @@
 // an edge already marked by an earlier tile are skipped.
 #include <hip/hip_ext.h>
 #include <algorithm>
+#include <cstring>
 #include <type_traits>
 
 #include "device_common.h"
@@ -224,33 +225,112 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const int32_t 
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) offsets[n_edges] = block_sums[gridDim.x];
 }
 
-// Batches of at most kScanThreads edges: counts, flags, exclusive offsets,
-// the tile table and the totals in one workgroup, one edge per thread (one
-// launch instead of four).
+// Batches of at most kSmallScanEdges edges: counts, flags, exclusive offsets,
+// the tile table and the totals in one workgroup, kScanThreads edges at a
+// time (one launch instead of four).
 __global__ __launch_bounds__(kScanThreads) void count_scan_small_kernel(
     const float *__restrict__ qa, const float *__restrict__ qb, int64_t n_edges, int dof, float res,
     const int32_t *__restrict__ n_opt, int32_t *__restrict__ n_out, uint32_t *__restrict__ flags,
     int64_t *__restrict__ offsets, int32_t *__restrict__ tile_first, uint64_t *__restrict__ counters) {
-  const int64_t e = threadIdx.x;
-  int64_t v = 0;
-  if (e < n_edges) {
-    uint32_t f;
-    v = edge_states(qa, qb, e, dof, res, n_opt, &f);
-    n_out[e] = (int32_t)v;
-    flags[e] = f;
-  }
-  int64_t total;
-  const int64_t run = block_exclusive_scan(v, &total);
-  if (e < n_edges) {
-    offsets[e] = run;
-    for (int64_t tl = (run + kWave - 1) / kWave; tl * kWave < run + v && tl < kTileFirstCap; ++tl)
-      tile_first[tl] = (int32_t)e;
+  int64_t carry = 0;
+  for (int64_t e0 = 0; e0 < n_edges; e0 += kScanThreads) {
+    const int64_t e = e0 + threadIdx.x;
+    int64_t v = 0;
+    if (e < n_edges) {
+      uint32_t f;
+      v = edge_states(qa, qb, e, dof, res, n_opt, &f);
+      n_out[e] = (int32_t)v;
+      flags[e] = f;
+    }
+    int64_t total;
+    const int64_t run = carry + block_exclusive_scan(v, &total);
+    if (e < n_edges) {
+      offsets[e] = run;
+      for (int64_t tl = (run + kWave - 1) / kWave; tl * kWave < run + v && tl < kTileFirstCap; ++tl)
+        tile_first[tl] = (int32_t)e;
+    }
+    carry += total;
   }
   if (threadIdx.x == 0) {
-    offsets[n_edges] = total;
+    offsets[n_edges] = carry;
     counters[0] = 0;
-    counters[1] = (uint64_t)total;
+    counters[1] = (uint64_t)carry;
     for (int c = 2; c < 16; ++c) counters[c] = 0;
+  }
+}
+
+// Many-scene batches of at most kSegSmallMax segments and kSmallScanEdges
+// edges: one workgroup does the work of seg_count, the scan, seg_tiles and
+// seg_table, from segments passed by value, which it also stores to
+// segs_out for the tile and final kernels.  Every thread revisits only the
+// edges it wrote itself.
+struct SegSmall {
+  ValSeg s[kSegSmallMax];
+};
+static_assert(sizeof(SegSmall) + 128 <= 4096, "segment table exceeds the kernel argument space");
+
+__global__ __launch_bounds__(kScanThreads) void seg_prep_small_kernel(
+    SegSmall in, int n_segs, int64_t n_flat, ValSeg *__restrict__ segs_out, int32_t *__restrict__ n_states,
+    uint32_t *__restrict__ flags, int32_t *__restrict__ edge_seg, int64_t *__restrict__ off,
+    int32_t *__restrict__ tile_first, int32_t *__restrict__ tile_seg, uint64_t *__restrict__ batch) {
+  __shared__ int64_t s_start[kSegSmallMax], s_tile0[kSegSmallMax];
+  if (threadIdx.x < kSegSmallMax) s_start[threadIdx.x] = -1;
+  __syncthreads();
+  int64_t carry = 0;
+  for (int64_t f0 = 0; f0 < n_flat; f0 += kScanThreads) {
+    const int64_t f = f0 + threadIdx.x;
+    int64_t v = 0;
+    int k = 0;
+    if (f < n_flat) {
+      while (k + 1 < n_segs && f >= in.s[k + 1].edge0) ++k;
+      const ValSeg &g = in.s[k];
+      uint32_t fl;
+      v = edge_states(g.qa, g.qb, f - g.edge0, g.sc.dof, g.res, nullptr, &fl);
+      n_states[f] = (int32_t)v;
+      flags[f] = fl;
+      edge_seg[f] = k;
+    }
+    int64_t total;
+    const int64_t run = carry + block_exclusive_scan(v, &total);
+    if (f < n_flat) {
+      off[f] = run;
+      if (f == in.s[k].edge0) s_start[k] = run;
+    }
+    carry += total;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    off[n_flat] = carry;
+    for (int k = n_segs - 1; k >= 0; --k)  // empty segments start where the next one does
+      if (s_start[k] < 0) s_start[k] = k + 1 < n_segs ? s_start[k + 1] : carry;
+    int64_t t = 0;
+    for (int k = 0; k < n_segs; ++k) {
+      const int64_t states = (k + 1 < n_segs ? s_start[k + 1] : carry) - s_start[k];
+      ValSeg g = in.s[k];
+      g.tile0 = t;
+      s_tile0[k] = t;
+      t += (states + kWave - 1) / kWave;
+      segs_out[k] = g;
+      for (int i = 0; i < 16; ++i) g.counters[i] = 0;
+      g.counters[1] = (uint64_t)states;
+    }
+    batch[0] = 0;
+    batch[1] = (uint64_t)t;
+    batch[2] = t > kTileFirstCap ? 1 : 0;
+    for (int c = 3; c < 16; ++c) batch[c] = 0;
+  }
+  __syncthreads();
+  for (int64_t f0 = 0; f0 < n_flat; f0 += kScanThreads) {
+    const int64_t f = f0 + threadIdx.x;
+    if (f >= n_flat) continue;
+    const int k = edge_seg[f];
+    const int64_t run = off[f] - s_start[k], v = n_states[f];
+    for (int64_t tl = (run + kWave - 1) / kWave; tl * kWave < run + v; ++tl) {
+      const int64_t t = s_tile0[k] + tl;
+      if (t >= kTileFirstCap) break;
+      tile_first[t] = (int32_t)f;
+      tile_seg[t] = k;
+    }
   }
 }
 
@@ -1436,7 +1516,7 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
   const int64_t nb = scan_blocks(n_edges);
   const int64_t g256 = (n_edges + 255) / 256;
   if (g256 > 0x7fffffff || nb > 0x7fffffff) return hipErrorInvalidValue;
-  if (n_edges <= kScanThreads) {
+  if (n_edges <= kSmallScanEdges) {
     hipLaunchKernelGGL(count_scan_small_kernel, dim3(1), dim3(kScanThreads), 0, s, qa, qb, n_edges, sc.dof, res,
                        n_states_opt, ws.n_states, ws.flags, ws.offsets, ws.tile_first, ws.counters);
   } else {
@@ -1584,23 +1664,11 @@ static int segments_grid(int W, size_t lds) {
   return grid;
 }
 
-hipError_t launch_validate_segments(ValSeg *d_segs, int n_segs, int r_max, int64_t n_flat, const SegScratch &ws,
-                                    hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> *ev_pair,
-                                    uint64_t *totals, int32_t *grid_out, int32_t *block_out) {
-  if (n_segs <= 0 || n_flat <= 0) return hipSuccess;
-  const int64_t nb = scan_blocks(n_flat);
+// The tile and final kernels of a many-scene launch (tables already built).
+static hipError_t launch_segments_tail(const ValSeg *d_segs, int r_max, int64_t n_flat, const SegScratch &ws,
+                                       hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> *ev_pair,
+                                       uint64_t *totals, int32_t *grid_out, int32_t *block_out) {
   const int64_t g256 = (n_flat + 255) / 256;
-  if (g256 > 0x7fffffff || nb > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(seg_count_kernel, dim3((unsigned)g256), dim3(256), 0, s, d_segs, n_segs, n_flat, ws.n_states,
-                     ws.flags, ws.edge_seg);
-  hipLaunchKernelGGL(scan_partials_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_flat,
-                     ws.block_sums);
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, ws.block_sums, nb, ws.batch);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_flat,
-                     ws.block_sums, ws.offsets, (int32_t *)nullptr);
-  hipLaunchKernelGGL(seg_tiles_kernel, dim3(1), dim3(kScanThreads), 0, s, d_segs, n_segs, ws.offsets, ws.batch);
-  hipLaunchKernelGGL(seg_table_kernel, dim3((unsigned)g256), dim3(256), 0, s, d_segs, n_flat, ws.n_states,
-                     ws.edge_seg, ws.offsets, ws.tile_first, ws.tile_seg);
   int W = 0, cache = 0;
   seg_shape(r_max, n_flat, &W, &cache);
   const size_t lds = centre_lds_bytes(r_max, W, cache);
@@ -1618,6 +1686,46 @@ hipError_t launch_validate_segments(ValSeg *d_segs, int n_segs, int r_max, int64
   hipLaunchKernelGGL(seg_finalize_kernel, dim3((unsigned)g256), dim3(256), 0, s, d_segs, n_flat, ws.flags,
                      ws.edge_seg, ws.partials, grid, totals);
   return hipGetLastError();
+}
+
+hipError_t launch_validate_segments(ValSeg *d_segs, int n_segs, int r_max, int64_t n_flat, const SegScratch &ws,
+                                    hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> *ev_pair,
+                                    uint64_t *totals, int32_t *grid_out, int32_t *block_out) {
+  if (n_segs <= 0 || n_flat <= 0) return hipSuccess;
+  const int64_t nb = scan_blocks(n_flat);
+  const int64_t g256 = (n_flat + 255) / 256;
+  if (g256 > 0x7fffffff || nb > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(seg_count_kernel, dim3((unsigned)g256), dim3(256), 0, s, d_segs, n_segs, n_flat, ws.n_states,
+                     ws.flags, ws.edge_seg);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_flat,
+                     ws.block_sums);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, ws.block_sums, nb, ws.batch);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_flat,
+                     ws.block_sums, ws.offsets, (int32_t *)nullptr);
+  hipLaunchKernelGGL(seg_tiles_kernel, dim3(1), dim3(kScanThreads), 0, s, d_segs, n_segs, ws.offsets, ws.batch);
+  hipLaunchKernelGGL(seg_table_kernel, dim3((unsigned)g256), dim3(256), 0, s, d_segs, n_flat, ws.n_states,
+                     ws.edge_seg, ws.offsets, ws.tile_first, ws.tile_seg);
+  return launch_segments_tail(d_segs, r_max, n_flat, ws, s, ev_pair, totals, grid_out, block_out);
+}
+
+hipError_t launch_validate_segments_small(const ValSeg *segs, int n_segs, int r_max, int64_t n_flat, ValSeg *d_segs,
+                                          const SegScratch &ws, hipStream_t s,
+                                          const std::pair<hipEvent_t, hipEvent_t> *ev_pair, uint64_t *totals,
+                                          int32_t *grid_out, int32_t *block_out) {
+  if (n_segs <= 0 || n_flat <= 0) return hipSuccess;
+  if (n_segs > kSegSmallMax || n_flat > kSmallScanEdges) return hipErrorInvalidValue;
+  int64_t e = 0;
+  for (int k = 0; k < n_segs; ++k) {  // consecutive, in order, covering [0, n_flat)
+    if (segs[k].edge0 != e || segs[k].n_edges < 0) return hipErrorInvalidValue;
+    e += segs[k].n_edges;
+  }
+  if (e != n_flat) return hipErrorInvalidValue;
+  SegSmall in;
+  std::memset(&in, 0, sizeof(in));
+  for (int k = 0; k < n_segs; ++k) in.s[k] = segs[k];
+  hipLaunchKernelGGL(seg_prep_small_kernel, dim3(1), dim3(kScanThreads), 0, s, in, n_segs, n_flat, d_segs,
+                     ws.n_states, ws.flags, ws.edge_seg, ws.offsets, ws.tile_first, ws.tile_seg, ws.batch);
+  return launch_segments_tail(d_segs, r_max, n_flat, ws, s, ev_pair, totals, grid_out, block_out);
 }
 
 }  // namespace mrpop

@@ -211,11 +211,19 @@ int seg_link_split(int n_robots, int W);
 // launch whose largest scene has r_max arms.
 void seg_shape(int r_max, int64_t n_flat, int *W, int *cache_sc);
 // Largest many-scene batch prepared in one workgroup, and the largest batch
-// counted and scanned in one workgroup.
+// counted and scanned in one workgroup: at most kSmallScanEdges edges, and
+// beyond kSmallScanOne edges at most kSmallScanLoads endpoint coordinates
+// (edges x dof; one workgroup reads them all, so large composite batches go
+// to the many-workgroup kernels).
 constexpr int kSegSmallMax = 8;
 constexpr int64_t kSmallScanEdges = 16384;
+constexpr int64_t kSmallScanOne = 1024;
+constexpr int64_t kSmallScanLoads = 32768;
+inline bool small_scan(int64_t n_edges, int dof) {
+  return n_edges <= kSmallScanOne || (n_edges <= kSmallScanEdges && n_edges * dof <= kSmallScanLoads);
+}
 // The same for at most kSegSmallMax consecutive segments covering
-// [0, n_flat), n_flat <= kSmallScanEdges, given on the host: they travel as
+// [0, n_flat) (small_scan at the largest dof), given on the host: they travel as
 // kernel arguments and are stored to d_segs (room for n_segs) by the
 // preparation kernel.  Three launches instead of eight and a copy.
 hipError_t launch_validate_segments_small(const ValSeg *segs, int n_segs, int r_max, int64_t n_flat, ValSeg *d_segs,

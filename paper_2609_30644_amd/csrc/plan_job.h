@@ -89,11 +89,12 @@ class PlanJob {
   void *arena_ = nullptr;
   float *qs_, *qg_, *rm_V_, *cand_, *pair_qa_, *pair_qb_, *tq_[2], *tg_[2], *q_rand_, *c_rand_, *q_new_, *g_new_,
       *ea_, *eb_, *budget_, *ca_, *cb_, *path_d_;
-  // per arm r: cand_ [r][cand_batch][kRmStride], cand_valid_ [r][cand_batch],
+  // per arm r: cand_ [r][cand_batch][kRmStride], cand_valid_ and cand_codes_ [r][cand_batch],
   // rm_i_ [r][kRmInts] (taken, pair count, pair count when writing,
   // connected), uf_ [r][rm_cap] union-find parents, cnt_ [2 + r][16]
   int32_t *rm_rowptr_, *rm_col_, *rm_edges_, *rm_nv_, *rm_ne_, *pair_ids_, *rm_i_, *uf_, *deg_, *tvid_[2],
-      *tpar_[2], *tn_[2], *near_idx_, *vid_new_, *ins_idx_, *conn_idx_, *d_nj_, *d_qoff_;
+      *tpar_[2], *tn_[2], *near_idx_, *vid_new_, *ins_idx_, *conn_idx_, *d_nj_, *d_qoff_,
+      *cand_codes_, *pair_codes_;
   int32_t *codes_ext_, *codes_conn_;  // [PC] state-count codes of the extension and connection edges
   uint8_t *cand_valid_, *pair_valid_, *alive_, *valid_, *cvalid_;
   uint64_t *cnt_;  // [2 + R][16]: counters of the extension, connection and per-arm roadmap validations

@@ -5,6 +5,8 @@
 //   sample -> NEAREST in the extended tree -> dRRT oracle -> validate the
 //   extensions -> insert in candidate order -> NEAREST in the other tree ->
 //   validate the connections -> pick the cheapest connection.
+// Sampling with the first NEAREST, and insertion with the second NEAREST and
+// the connection edges, run as one launch each (one workgroup per candidate).
 // One small status record per round comes back to the host: the selection
 // kernel writes it straight into pinned memory.  The host decides whether
 // the search ended, swaps the trees when the extended one has grown larger,
@@ -143,16 +145,17 @@ class PlainExec : public Exec {
       return launch_validate(*q.scene, q.qa, q.qb, q.n, q.res, nullptr, q.out, ws, s_, profile_slot(ctx_),
                              ctx_->profiling ? ctx_->prof_totals : nullptr, &ctx_->last_grid, &ctx_->last_block);
     }
-    int r_max = 1;
+    int r_max = 1, dof_max = 1;
     int64_t flat = 0;
     for (const ValidateReq &q : v) {
       r_max = std::max(r_max, (int)q.scene->n_robots);
+      dof_max = std::max(dof_max, (int)q.scene->dof);
       flat += q.n;
     }
     int W = 0, cache = 0;
     seg_shape(r_max, flat, &W, &cache);
     const size_t bytes = sizeof(ValSeg) * v.size();
-    const bool small = (int)v.size() <= kSegSmallMax && flat <= kSmallScanEdges;
+    const bool small = (int)v.size() <= kSegSmallMax && small_scan(flat, dof_max);
     hipError_t e;
     if (small) {  // the table travels as kernel arguments
       ValSeg h[kSegSmallMax];
@@ -278,10 +281,12 @@ size_t PlanJob::plan_arena_(void *base) {
   ar.add(&rm_ne_, R);
   ar.add(&cand_, (size_t)R * cand_batch_ * kRmStride);
   ar.add(&cand_valid_, (size_t)R * cand_batch_);
+  ar.add(&cand_codes_, (size_t)R * cand_batch_);
   ar.add(&pair_ids_, (size_t)pair_cap_ * 2);
   ar.add(&pair_qa_, (size_t)pair_cap_ * max_nj);
   ar.add(&pair_qb_, (size_t)pair_cap_ * max_nj);
   ar.add(&pair_valid_, pair_cap_);
+  ar.add(&pair_codes_, pair_cap_);
   ar.add(&rm_i_, (size_t)R * kRmInts);
   ar.add(&uf_, (size_t)R * rm_cap_);
   ar.add(&deg_, (size_t)R * rm_cap_);
@@ -506,10 +511,12 @@ mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
         for (int r : act)
           add(Op::RmSample).rm_sample = RmSampleArgs{cand(r), cand_batch_, h_nj_[r], scene_->dev.q_lo + h_qoff_[r],
                                                      scene_->dev.q_hi + h_qoff_[r],
-                                                     roadmap_key(P_.seed, (uint64_t)it * 1024 + g, (uint64_t)r), j0};
+                                                     roadmap_key(P_.seed, (uint64_t)it * 1024 + g, (uint64_t)r), j0,
+                                                     cand_codes_ + (size_t)r * cand_batch_};
         TRY(group_(ex, grp));
         for (int r : act)  // consecutive validations: one launch over the arms
-          TRY(validate_(ex, arms_[r], cand(r), cand(r), cand_batch_, 1.0f, candv(r), cnt_ + (size_t)(2 + r) * 16));
+          TRY(validate_(ex, arms_[r], cand(r), cand(r), cand_batch_, 1.0f, candv(r), cnt_ + (size_t)(2 + r) * 16,
+                        cand_codes_ + (size_t)r * cand_batch_));
         for (int r : act)
           add(Op::RmAccept).rm_accept = RmAcceptArgs{cand(r), candv(r), cand_batch_, h_nj_[r], need[r], V(r),
                                                      rm_nv_ + r, rm_cap_, ri(r, 0), uf_ + (size_t)r * rm_cap_};
@@ -519,7 +526,7 @@ mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
       TRY(group_(ex, grp));
       for (int r : counted)
         add(Op::RmPairs).rm_pairs = RmPairsArgs{V(r), n0[r], n0[r] + need0[r], h_nj_[r], P_.delta, ri(r, 1), 0,
-                                                nullptr, nullptr, nullptr, rm_nv_ + r};
+                                                nullptr, nullptr, nullptr, rm_nv_ + r, 0.f, nullptr};
       TRY(group_(ex, grp));
       add_copy(pin_rm_, rm_i_, sizeof(int32_t) * (size_t)R * kRmInts);
       add_copy(pin_rm_ + (size_t)R * kRmInts, rm_nv_, sizeof(int32_t) * (size_t)R);
@@ -544,12 +551,13 @@ mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
       if (np[r] > 0)
         add(Op::RmPairs).rm_pairs =
             RmPairsArgs{V(r), n0[r], rm_n_[r], h_nj_[r], P_.delta, ri(r, 2), np[r], pair_ids_ + 2 * (size_t)off[r],
-                        pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r], nullptr};
+                        pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r], nullptr,
+                        P_.resolution, pair_codes_ + off[r]};
     TRY(group_(ex, grp));
     for (int r : todo)
       if (np[r] > 0)
         TRY(validate_(ex, arms_[r], pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r],
-                      np[r], P_.resolution, pair_valid_ + off[r], cnt_ + (size_t)(2 + r) * 16));
+                      np[r], P_.resolution, pair_valid_ + off[r], cnt_ + (size_t)(2 + r) * 16, pair_codes_ + off[r]));
     for (int r : todo)
       if (np[r] > 0) {
         add(Op::RmAddEdges).rm_add_edges =
@@ -657,12 +665,11 @@ mrpop_status PlanJob::run(Exec &ex) {
       if (n_t[a] > n_t[1 - a]) a = 1 - a;
       const int b = 1 - a;
       const float cb = c_best_;
-      SUBMIT(Op::Sample, sample,
-             SampleArgs{PC, D, cb, P_.seed, (uint64_t)rnd, 0, scene_->dev.q_lo, scene_->dev.q_hi, qs_, qg_, tq_[a],
-                        tcap_, q_rand_, c_rand_});
-      SUBMIT(Op::Nearest, nearest,
-             NearestArgs{tq_[a], tg_[a], n_t[a], D, 1, tcap_, q_rand_, D, cb < INFINITY ? c_rand_ : nullptr, PC,
-                         near_idx_});
+      SUBMIT(Op::SampleNear, sample_near,
+             SampleNearArgs{SampleArgs{PC, D, cb, P_.seed, (uint64_t)rnd, 0, scene_->dev.q_lo, scene_->dev.q_hi, qs_,
+                                       qg_, tq_[a], tcap_, q_rand_, c_rand_},
+                            NearestArgs{tq_[a], tg_[a], n_t[a], D, 1, tcap_, q_rand_, D,
+                                        cb < INFINITY ? c_rand_ : nullptr, PC, near_idx_}});
       if (P_.direct)
         SUBMIT(Op::Steer, steer,
                SteerArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a], tg_[a], tcap_,
@@ -673,12 +680,11 @@ mrpop_status PlanJob::run(Exec &ex) {
                           tcap_, rm_V_, rm_rowptr_, rm_col_, rm_cap_, col_cap_, d_nj_, d_qoff_, q_new_, vid_new_,
                           g_new_, alive_, ea_, eb_, P_.resolution, codes_ext_});
       TRY(validate_(ex, scene_, ea_, eb_, PC, P_.resolution, valid_, cnt_, codes_ext_));
-      SUBMIT(Op::Insert, insert,
-             InsertArgs{PC, D, R, alive_, valid_, q_new_, g_new_, vid_new_, near_idx_, tq_[a], tg_[a], tvid_[a],
-                        tpar_[a], tn_[a], tcap_, cb, ins_idx_, budget_, status_, n_t[a]});
-      SUBMIT(Op::Nearest, nearest,
-             NearestArgs{tq_[b], tg_[b], n_t[b], D, 1, tcap_, q_new_, D, budget_, PC, conn_idx_});
-      SUBMIT(Op::Conn, conn, ConnArgs{PC, D, conn_idx_, q_new_, tq_[b], tcap_, ca_, cb_, P_.resolution, codes_conn_});
+      SUBMIT(Op::InsertConn, insert_conn,
+             InsertConnArgs{InsertArgs{PC, D, R, alive_, valid_, q_new_, g_new_, vid_new_, near_idx_, tq_[a], tg_[a],
+                                       tvid_[a], tpar_[a], tn_[a], tcap_, cb, ins_idx_, budget_, status_, n_t[a]},
+                            NearestArgs{tq_[b], tg_[b], n_t[b], D, 1, tcap_, q_new_, D, budget_, PC, conn_idx_},
+                            ConnArgs{PC, D, conn_idx_, q_new_, tq_[b], tcap_, ca_, cb_, P_.resolution, codes_conn_}});
       TRY(validate_(ex, scene_, ca_, cb_, PC, P_.resolution, cvalid_, cnt_ + 16, codes_conn_));
       SUBMIT(Op::Select, select,
              SelectArgs{PC, D, ins_idx_, conn_idx_, cvalid_, q_new_, g_new_, tq_[b], tg_[b], tcap_, cnt_, cnt_ + 16,

@@ -122,6 +122,22 @@ struct SelectArgs {
   RoundStatus *status_out;  // or null: receives the round's finished record (e.g. pinned host memory)
 };
 
+// Fused round steps, one workgroup per candidate: the sample and its
+// nearest vertex in the extended tree (q.queries = s.out_q, q.budgets =
+// s.out_c or null); the insertion, the nearest vertex of the other tree
+// (q.queries = ins.q_new, q.budgets = ins.budget) and the connection edge
+// (c.conn_idx = q.out_idx).
+struct SampleNearArgs {
+  SampleArgs s;
+  NearestArgs q;
+};
+
+struct InsertConnArgs {
+  InsertArgs ins;
+  NearestArgs q;
+  ConnArgs c;
+};
+
 struct PathArgs {
   int a_idx, b_idx, dim, tree_cap, cap;
   const int32_t *parent_a, *parent_b;
@@ -144,6 +160,7 @@ struct RmSampleArgs {
   const float *lo, *hi;
   uint64_t key;
   int64_t j0;
+  int32_t *codes;  // or null: [n] state-count code of each sample as a zero-length edge
 };
 
 struct RmAcceptArgs {
@@ -166,6 +183,8 @@ struct RmPairsArgs {
   int32_t *pair_ids;
   float *qa, *qb;
   const int32_t *i1_dev;  // or null: i1 is lowered to *i1_dev (the vertex count on the device)
+  float res;              // resolution of the pairs' validation (for codes)
+  int32_t *codes;         // or null: [cap] state-count code of each written pair
 };
 
 struct RmAddEdgesArgs {
@@ -231,9 +250,9 @@ uint64_t roadmap_key(uint64_t seed, uint64_t stream_a, uint64_t stream_b);
 // needs, records that need fewer leave early).
 enum class Op : uint8_t {
   Sample, Nearest, Extend, Steer, Insert, Conn, Select, Path, TreeRoot,
-  RmSample, RmAccept, RmPairs, RmAddEdges, RmBfs, RmUnion, Fill, Copy, Validate
+  RmSample, RmAccept, RmPairs, RmAddEdges, RmBfs, RmUnion, Fill, Copy, SampleNear, InsertConn, Validate
 };
-constexpr int kNumOps = 18;
+constexpr int kNumOps = 20;
 constexpr int kUfMaxVertices = 32768;  // roadmap vertices per arm (union-find in LDS)
 
 // Blocks one record needs (0: nothing to do).
@@ -280,6 +299,8 @@ struct Cmd {
     RmUnionArgs rm_union;
     FillArgs fill;
     CopyArgs copy;
+    SampleNearArgs sample_near;
+    InsertConnArgs insert_conn;
     ValidateReq val;
   };
   const void *args() const { return &sample; }

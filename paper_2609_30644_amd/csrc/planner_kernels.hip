@@ -70,10 +70,8 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-__device__ __forceinline__ void sample_body(const SampleArgs &a, int bx) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int i = bx * kSampleWaves + (int)(threadIdx.x / kWave);
-  if (i >= a.n) return;  // whole waves leave together
+// Candidate i by one wavefront (lane: its lane index).
+__device__ __forceinline__ void sample_one(const SampleArgs &a, int i, int lane) {
   const int D = a.dim;
   float *q = a.out_q + (int64_t)i * D;
   if (!(a.c_best < INFINITY)) {
@@ -136,6 +134,12 @@ __device__ __forceinline__ void sample_body(const SampleArgs &a, int bx) {
     const float u = uniform01(stream_key(a.seed, kPurposeC, a.round, a.first + i), 0);
     a.out_c[i] = lb < a.c_best ? fmaf(u, a.c_best - lb, lb) : a.c_best;
   }
+}
+
+__device__ __forceinline__ void sample_body(const SampleArgs &a, int bx) {
+  const int i = bx * kSampleWaves + (int)(threadIdx.x / kWave);
+  if (i >= a.n) return;  // whole waves leave together
+  sample_one(a, i, (int)(threadIdx.x & (kWave - 1)));
 }
 
 // ---------------------------------------------------------------------------
@@ -472,10 +476,8 @@ __device__ __forceinline__ void insert_body(const InsertArgs &a, int bx) {
 // joint per lane; candidates without a connection get a null edge.
 constexpr int kConnWaves = 4;
 
-__device__ __forceinline__ void conn_body(const ConnArgs &a, int bx) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int i = bx * kConnWaves + (int)(threadIdx.x / kWave);
-  if (i >= a.n) return;  // whole waves leave together
+// Candidate i by one wavefront.
+__device__ __forceinline__ void conn_one(const ConnArgs &a, int i, int lane) {
   const int c = a.conn_idx[i];
   float *ea = a.edge_a + (int64_t)i * a.dim, *eb = a.edge_b + (int64_t)i * a.dim;
   float linf = 0.f;
@@ -493,6 +495,96 @@ __device__ __forceinline__ void conn_body(const ConnArgs &a, int bx) {
     const bool all_finite = __ballot(!finite) == 0ull;
     if (lane == 0) a.n_codes[i] = state_count_code(linf, all_finite, a.res);
   }
+}
+
+__device__ __forceinline__ void conn_body(const ConnArgs &a, int bx) {
+  const int i = bx * kConnWaves + (int)(threadIdx.x / kWave);
+  if (i >= a.n) return;  // whole waves leave together
+  conn_one(a, i, (int)(threadIdx.x & (kWave - 1)));
+}
+
+// ---------------------------------------------------------------------------
+// fused round steps, one workgroup (256 threads) per candidate
+// ---------------------------------------------------------------------------
+
+// The candidate's sample (wave 0), then its nearest vertex in the extended
+// tree.  The sample reaches the other waves through global memory, ordered
+// by the workgroup barrier.
+__device__ __forceinline__ void sample_near_body(const SampleNearArgs &a, int bx) {
+  if (bx >= a.s.n) return;
+  if (threadIdx.x < kWave) sample_one(a.s, bx, (int)threadIdx.x);
+  __syncthreads();
+  nearest_body(a.q, bx);
+}
+
+// The candidate's insertion in the extended tree (position: the survivors
+// before it, as in insert_body), the nearest vertex of the other tree under
+// the budget the insertion sets, and the connection edge.  The trees differ,
+// so the insertion and the search never touch the same vertices.
+__device__ __forceinline__ void insert_conn_body(const InsertConnArgs &A, int bx) {
+  const InsertArgs &a = A.ins;
+  if (a.n <= 0) {  // nothing to insert: the round's record still gets its counts
+    if (bx == 0 && threadIdx.x == 0) {
+      a.status->inserted = 0;
+      a.status->overflow = 0;
+      *a.tree_n = a.n_before;
+    }
+    return;
+  }
+  if (bx >= a.n) return;
+  __shared__ int32_t s_red[2][256 / kWave];
+  __shared__ int32_t s_t;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  int before = 0, all = 0;
+  for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
+    const int ok = (a.alive[i] && a.valid[i]) ? 1 : 0;
+    all += ok;
+    before += i < bx ? ok : 0;
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    all += __shfl_xor(all, d, kWave);
+    before += __shfl_xor(before, d, kWave);
+  }
+  if (lane == 0) {
+    s_red[0][w] = before;
+    s_red[1][w] = all;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    before = 0;
+    all = 0;
+    for (int k = 0; k < nw; ++k) {
+      before += s_red[0][k];
+      all += s_red[1][k];
+    }
+    const bool ok = a.alive[bx] && a.valid[bx];
+    const int32_t t = (ok && a.n_before + before < a.tree_cap) ? a.n_before + before : -1;
+    s_t = t;
+    a.ins_idx[bx] = t;
+    a.budget[bx] = t < 0 ? -1.f : (a.c_best < INFINITY ? a.c_best - a.g_new[bx] : INFINITY);
+    if (t >= 0) {
+      a.tree_g[t] = a.g_new[bx];
+      a.tree_parent[t] = a.near_idx[bx];
+    }
+    if (bx == 0) {
+      const int room = a.tree_cap - a.n_before;
+      const int ins = all < room ? all : room;
+      a.status->inserted = ins;
+      a.status->overflow = all > room ? 1 : 0;
+      *a.tree_n = a.n_before + ins;
+    }
+  }
+  __syncthreads();
+  const int32_t t = s_t;
+  if (t >= 0) {
+    for (int j = threadIdx.x; j < a.dim; j += blockDim.x)
+      a.tree_q[(int64_t)j * a.tree_cap + t] = a.q_new[(int64_t)bx * a.dim + j];
+    for (int r = threadIdx.x; r < a.n_robots; r += blockDim.x)
+      a.tree_vid[(int64_t)r * a.tree_cap + t] = a.vid_new[(int64_t)r * a.n + bx];
+  }
+  nearest_body(A.q, bx);
+  __syncthreads();
+  if (threadIdx.x < kWave) conn_one(A.c, bx, (int)threadIdx.x);
 }
 
 // Single workgroup: among inserted candidates whose connection edge is free,
@@ -600,8 +692,13 @@ __device__ __forceinline__ void rm_sample_body(const RmSampleArgs &A, int bx) {
 
   const int b = bx * blockDim.x + threadIdx.x;
   if (b >= n) return;
-  for (int d = 0; d < nj; ++d)
-    out[(int64_t)b * nj + d] = fmaf(uniform01(key, (uint64_t)(j0 + b) * 8 + d), hi[d] - lo[d], lo[d]);
+  bool finite = true;
+  for (int d = 0; d < nj; ++d) {
+    const float x = fmaf(uniform01(key, (uint64_t)(j0 + b) * 8 + d), hi[d] - lo[d], lo[d]);
+    out[(int64_t)b * nj + d] = x;
+    finite = finite && isfinite(x);
+  }
+  if (A.codes) A.codes[b] = state_count_code(0.f, finite, 1.f);
 }
 
 // Single workgroup: append the first `need` free candidates (in draw order)
@@ -674,10 +771,16 @@ __device__ __forceinline__ void rm_pairs_body(const RmPairsArgs &A, int bx) {
     if (!pair_ids || k >= cap) continue;  // counting only, or beyond the allotted room
     pair_ids[2 * k] = j;
     pair_ids[2 * k + 1] = i;
+    bool finite = true;
+    float linf = 0.f;
     for (int d = 0; d < nj; ++d) {
-      qa[(int64_t)k * nj + d] = V[(int64_t)j * kRmStride + d];
-      qb[(int64_t)k * nj + d] = V[(int64_t)i * kRmStride + d];
+      const float x = V[(int64_t)j * kRmStride + d], y = V[(int64_t)i * kRmStride + d];
+      qa[(int64_t)k * nj + d] = x;
+      qb[(int64_t)k * nj + d] = y;
+      finite = finite && isfinite(x) && isfinite(y);
+      linf = fmaxf(linf, fabsf(y - x));
     }
+    if (A.codes) A.codes[k] = state_count_code(linf, finite, A.res);
   }
 }
 
@@ -869,6 +972,8 @@ MRPOP_OP_KERNELS(rm_csr_bfs, RmBfsArgs, 1024)
 MRPOP_OP_KERNELS(rm_union, RmUnionArgs, 1024)
 MRPOP_OP_KERNELS(fill, FillArgs, 256)
 MRPOP_OP_KERNELS(copy, CopyArgs, 256)
+MRPOP_OP_KERNELS(sample_near, SampleNearArgs, 256)
+MRPOP_OP_KERNELS(insert_conn, InsertConnArgs, 256)
 
 static int clamp_blocks(int64_t b) { return (int)std::min<int64_t>(std::max<int64_t>(b, 0), 0x7fffffff); }
 
@@ -900,6 +1005,8 @@ int op_blocks(Op op, const void *p) {
     case Op::RmUnion: return 1;
     case Op::Fill: return (int)std::min<int64_t>((((const FillArgs *)p)->n + 255) / 256, kCopyBlocksMax);
     case Op::Copy: return (int)std::min<int64_t>((((const CopyArgs *)p)->bytes + 255) / 256, kCopyBlocksMax);
+    case Op::SampleNear: return clamp_blocks(((const SampleNearArgs *)p)->s.n);
+    case Op::InsertConn: return clamp_blocks(std::max(1, ((const InsertConnArgs *)p)->ins.n));
     case Op::Validate: return 0;
   }
   return 0;
@@ -924,6 +1031,8 @@ size_t op_args_bytes(Op op) {
     case Op::RmUnion: return sizeof(RmUnionArgs);
     case Op::Fill: return sizeof(FillArgs);
     case Op::Copy: return sizeof(CopyArgs);
+    case Op::SampleNear: return sizeof(SampleNearArgs);
+    case Op::InsertConn: return sizeof(InsertConnArgs);
     case Op::Validate: return 0;
   }
   return 0;
@@ -933,6 +1042,14 @@ size_t op_args_bytes(Op op) {
 static hipError_t op_check(Op op, const void *p) {
   if (op == Op::Sample && ((const SampleArgs *)p)->dim > kMaxDof) return hipErrorInvalidValue;
   if (op == Op::Nearest && ((const NearestArgs *)p)->dim > kMaxDof) return hipErrorInvalidValue;
+  if (op == Op::SampleNear) {
+    const SampleNearArgs &a = *(const SampleNearArgs *)p;
+    if (a.s.dim > kMaxDof || a.q.dim > kMaxDof || a.q.n_queries != a.s.n) return hipErrorInvalidValue;
+  }
+  if (op == Op::InsertConn) {
+    const InsertConnArgs &a = *(const InsertConnArgs *)p;
+    if (a.q.dim > kMaxDof || a.q.n_queries != a.ins.n || a.c.n != a.ins.n) return hipErrorInvalidValue;
+  }
   return hipSuccess;
 }
 
@@ -974,6 +1091,8 @@ static hipError_t launch_group_any(Op op, const void *const *recs, int n, int gr
     MRPOP_GROUP_CASE(RmUnion, rm_union, RmUnionArgs)
     MRPOP_GROUP_CASE(Fill, fill, FillArgs)
     MRPOP_GROUP_CASE(Copy, copy, CopyArgs)
+    MRPOP_GROUP_CASE(SampleNear, sample_near, SampleNearArgs)
+    MRPOP_GROUP_CASE(InsertConn, insert_conn, InsertConnArgs)
     case Op::Validate: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -998,6 +1117,8 @@ static hipError_t launch_any(Op op, const void *p, bool batch, int count, int gr
     MRPOP_OP_CASE(RmUnion, rm_union, RmUnionArgs)
     MRPOP_OP_CASE(Fill, fill, FillArgs)
     MRPOP_OP_CASE(Copy, copy, CopyArgs)
+    MRPOP_OP_CASE(SampleNear, sample_near, SampleNearArgs)
+    MRPOP_OP_CASE(InsertConn, insert_conn, InsertConnArgs)
     case Op::Validate: return hipErrorInvalidValue;
   }
   return hipGetLastError();

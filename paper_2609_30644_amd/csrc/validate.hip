@@ -225,9 +225,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const int32_t 
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) offsets[n_edges] = block_sums[gridDim.x];
 }
 
-// Batches of at most kSmallScanEdges edges: counts, flags, exclusive offsets,
-// the tile table and the totals in one workgroup, kScanThreads edges at a
-// time (one launch instead of four).
+// Small batches (small_scan): counts, flags, exclusive offsets, the tile
+// table and the totals in one workgroup, kScanThreads edges at a time (one
+// launch instead of four).
 __global__ __launch_bounds__(kScanThreads) void count_scan_small_kernel(
     const float *__restrict__ qa, const float *__restrict__ qb, int64_t n_edges, int dof, float res,
     const int32_t *__restrict__ n_opt, int32_t *__restrict__ n_out, uint32_t *__restrict__ flags,
@@ -259,8 +259,8 @@ __global__ __launch_bounds__(kScanThreads) void count_scan_small_kernel(
   }
 }
 
-// Many-scene batches of at most kSegSmallMax segments and kSmallScanEdges
-// edges: one workgroup does the work of seg_count, the scan, seg_tiles and
+// Many-scene batches of at most kSegSmallMax segments whose edges pass
+// small_scan (at the largest dof): one workgroup does the work of seg_count, the scan, seg_tiles and
 // seg_table, from segments passed by value, which it also stores to
 // segs_out for the tile and final kernels.  Every thread revisits only the
 // edges it wrote itself.
@@ -1430,7 +1430,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const uint32_t *__restric
   }
 }
 
-// Tile shape: S link parts per arm (waves per arm), W waves per workgroup,
+// Tile shape: S link parts per arm (waves per arm, up to one per link), W
+// waves per workgroup,
 // and whether the joint sines/cosines are cached in LDS for the arm-pair
 // stage.  Small batches (few tiles, the planner's case) get the most waves
 // per tile, so that a tile's latency shrinks; large batches keep two
@@ -1451,7 +1452,7 @@ constexpr size_t kLdsBudget = 150 * 1024;
 static TileShape tile_shape(int n_robots, int64_t n_edges) {
   const int cap = n_edges <= kSmallBatchEdges ? kMaxWavesPerBlock : kMaxWavesPerBlock / 2;
   int S = 1;
-  while (S < 4 && n_robots * S * 2 <= cap) S *= 2;
+  while (S < kMaxLinks && n_robots * S * 2 <= cap) S *= 2;
   int W = std::min(n_robots * S, cap);
   while (W > 1 && centre_lds_bytes(n_robots, W, 0) > kLdsBudget) W /= 2;
   const int cache = centre_lds_bytes(n_robots, W, 1) <= kLdsBudget ? 1 : 0;
@@ -1516,7 +1517,7 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
   const int64_t nb = scan_blocks(n_edges);
   const int64_t g256 = (n_edges + 255) / 256;
   if (g256 > 0x7fffffff || nb > 0x7fffffff) return hipErrorInvalidValue;
-  if (n_edges <= kSmallScanEdges) {
+  if (small_scan(n_edges, sc.dof)) {
     hipLaunchKernelGGL(count_scan_small_kernel, dim3(1), dim3(kScanThreads), 0, s, qa, qb, n_edges, sc.dof, res,
                        n_states_opt, ws.n_states, ws.flags, ws.offsets, ws.tile_first, ws.counters);
   } else {
@@ -1563,7 +1564,10 @@ static int small_grid(int W, size_t lds) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, validate_small_kernel<STAGED, CACHE>, kWave * W, lds);
-  const int grid = std::min(kMaxGrid, std::max(1, cus) * std::max(1, per));
+  // At most two workgroups per CU: every workgroup scans the counts and
+  // arrives once, and the last one reads every workgroup's partial sums, so
+  // idle workgroups (small waves of one-arm scenes fit many per CU) cost time.
+  const int grid = std::min(kMaxGrid, std::max(1, cus) * std::min(2, std::max(1, per)));
   cache.push_back({W, lds, grid});
   return grid;
 }
@@ -1635,7 +1639,7 @@ SegScratch seg_scratch_layout(void *base, int64_t n_flat) {
 
 int seg_link_split(int n_robots, int W) {
   int S = 1;
-  while (S < 4 && n_robots * S * 2 <= W) S *= 2;
+  while (S < kMaxLinks && n_robots * S * 2 <= W) S *= 2;
   return S;
 }
 

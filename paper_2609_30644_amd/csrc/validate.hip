@@ -1107,10 +1107,11 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
 // edges has made (codes of state_count_code): every workgroup scans the
 // counts into LDS itself, so no count and scan launches come first, and takes
 // its tiles as the tile kernel does.  Colliding edges are marked with this
-// launch's token, so flag words never need clearing between launches.  The
-// last workgroup to finish (a device-wide arrival counter) writes the bits
-// and the counters and resets the counter: one launch where the general path
-// makes three.  Workgroups never wait for each other.
+// launch's token, so flag words never need clearing between launches.  Only
+// workgroups that hold a tile go on; the last of them to finish (a
+// device-wide arrival counter) writes the bits and the counters and resets
+// the counter: one launch where the general path makes three.  Workgroups
+// never wait for each other.
 template <bool STAGED, bool CACHE>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_kernel(
     SceneDev sc, const float *__restrict__ qa, const float *__restrict__ qb, int n_edges,
@@ -1142,6 +1143,11 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
   if (threadIdx.x < 2) s_dead[threadIdx.x] = 0ull;
   __syncthreads();
   const int64_t n_tiles = (total + kWave - 1) / kWave;
+  // Workgroups with a tile take part (workgroup 0 when there is none); the
+  // others leave now, so that a batch of few tiles pays for few arrivals and
+  // partial sums.  Every workgroup computes the same count.
+  const uint32_t working = (uint32_t)max<int64_t>(1, min<int64_t>((int64_t)gridDim.x, n_tiles));
+  if (blockIdx.x >= working) return;
   if ((int64_t)blockIdx.x < n_tiles) {
     uint32_t checked = 0, tiles = 0;
     WorkCount wc;
@@ -1171,7 +1177,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0)
-    s_last = __hip_atomic_fetch_add(arrived, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1u;
+    s_last = __hip_atomic_fetch_add(arrived, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == working - 1u;
   __syncthreads();
   if (!s_last) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -1179,7 +1185,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
   if (threadIdx.x < kPartialSlots + 3) s_sum[threadIdx.x] = 0ull;
   __syncthreads();
   // one (workgroup, slot) entry per thread and step, added in LDS
-  for (int64_t k = threadIdx.x; k < (int64_t)gridDim.x * kPartialSlots; k += blockDim.x) {
+  for (int64_t k = threadIdx.x; k < (int64_t)working * kPartialSlots; k += blockDim.x) {
     const uint64_t v = partials[k];
     if (v) atomicAdd(&s_sum[k % kPartialSlots], (unsigned long long)v);
   }

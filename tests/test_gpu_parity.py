@@ -220,6 +220,24 @@ def test_validate_tile_modes(ctx, mode):
     assert np.array_equal(got, s.validate_edges(qa, qb, 0.05).cpu().numpy())
 
 
+@pytest.mark.parametrize("case", ["single3000", "c2_1025"])
+def test_validate_one_workgroup_count_in_chunks(ctx, case):
+    """Batches above 1024 edges whose endpoint coordinates (edges x dof) stay
+    within 32768 are counted and scanned by one workgroup, 1024 edges at a
+    time: a one-arm batch of three chunks (the last one ragged) and a
+    composite batch whose second chunk holds a single edge."""
+    if case == "single3000":
+        sc = W.Scene([W.panda_like(59)], W.base_transform(0, 0, 0)[None],
+                     np.array([[0.4, 0.2, 0.5, 0.1], [-0.3, -0.4, 0.8, 0.12]], np.float32),
+                     np.array([[0.3, -0.5, 0.0, 0.6, -0.2, 0.4]], np.float32))
+        qa, qb = W.edge_batch(sc, 3000, 0.05, 111, 2, 30)
+    else:
+        sc = problem("c2").scene
+        qa, qb = W.edge_batch(sc, 1025, 0.05, 112, 2, 40)
+    assert 1024 < qa.shape[0] and qa.shape[0] * sc.dof <= 32768
+    _parity(ctx, sc, qa, qb, 0.05, case)
+
+
 def test_validate_more_edges_than_one_scan_block(ctx):
     """More than 4096 edges take the multi-block count and scan path."""
     sc = problem("c1").scene

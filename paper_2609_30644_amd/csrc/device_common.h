@@ -107,10 +107,6 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint32_t load_relaxed(const uint32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Number of states at which an edge is checked (paper, Sec. "Multi-Thread
 // Reassignment for Collision Checking": edges are discretised into states),
 // from the largest joint difference linf over its endpoints, so that no joint

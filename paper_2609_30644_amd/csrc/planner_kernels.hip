@@ -841,9 +841,9 @@ __device__ __forceinline__ void rm_union_body(const RmUnionArgs &A, int bx) {
   if (threadIdx.x == 0) *A.connected = (nv > 1 && uf_find(par, 1) == uf_find(par, 0)) ? 1 : 0;
 }
 
-// Single workgroup: rebuild the arm's adjacency (CSR) from its edge list,
-// then breadth-first search from vertex 0; writes whether vertex 1 is
-// reached.  The order inside an adjacency row is whatever the atomics give:
+// Single workgroup: rebuild the arm's adjacency (CSR) from its edge list
+// (degree counts and row cursors with LDS atomics), then breadth-first search
+// from vertex 0; writes whether vertex 1 is reached.  The order inside an adjacency row is whatever the atomics give:
 // the extension oracle's choice does not depend on it.
 __device__ __forceinline__ void rm_csr_bfs_body(const RmBfsArgs &A, int bx) {
   const int32_t *edges = A.edges, *n_edges_p = A.n_edges;
@@ -854,6 +854,10 @@ __device__ __forceinline__ void rm_csr_bfs_body(const RmBfsArgs &A, int bx) {
   __shared__ int32_t wsum[1024 / kWave];
   __shared__ int32_t carry;
   __shared__ int changed, stop;
+  // degrees and row cursors in LDS when the roadmap fits (every roadmap the
+  // planner builds does: at most kUfMax vertices), else in `deg`
+  __shared__ int32_t s_cur[kUfMax];
+  if (n_v <= kUfMax) deg = s_cur;
   const int ne = *n_edges_p < cap_edges ? *n_edges_p : cap_edges;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
   for (int v = threadIdx.x; v < n_v; v += blockDim.x) deg[v] = 0;

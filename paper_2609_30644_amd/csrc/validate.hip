@@ -29,8 +29,10 @@
 //      static mask allows, and for flagged link pairs the two frames are
 //      rebuilt and the fine spheres tested.
 // A collision marks the edge in a flag word and marks all of the edge's lanes
-// of the tile in an LDS mask, which the other waves read as they go; states of
-// an edge already marked by an earlier tile are skipped.
+// of the tile in an LDS mask, which the other waves read as they go.  Tiles
+// do not read the flag words: the tiles of one edge run at the same time on
+// different workgroups, so the check almost never skipped a state, and the
+// coherent load it needs cost a memory round trip per tile.
 #include <hip/hip_ext.h>
 #include <algorithm>
 #include <cstring>
@@ -949,8 +951,6 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
   const int R = sc.n_robots;
   bool hit = false;
   if constexpr (CACHE) {
-    // states of an edge that an earlier tile found colliding are skipped
-    if (act && load_relaxed(flags + tl.e) == hit_token) act = false;
     if (threadIdx.x == 0) *s_next = 0;
     // A. the joints' sines and cosines at every lane's state, (arm, joint)
     // pairs spread over the waves
@@ -998,9 +998,6 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
     const int nj = as_const(sc.nj)[m];
     float qv[kMaxJoints];
     arm_joints(sc, st, r, nj, qv);
-    // with the edge's flag on the wave's first arm: states of an edge that an
-    // earlier tile found colliding are skipped
-    if (jb == w && act && load_relaxed(flags + tl.e) == hit_token) act = false;
     const bool live = act && !hit;
     if (arm_env<STAGED>(sc, src, r, m, part, S, qv, live, tl.emask, cen, sc_lds, wave_fr, wave_q, &s_hit[w], dead,
                         lane, wc))

@@ -238,6 +238,24 @@ def history_leg(s, q_start, q_goal, res: float, n: int) -> dict:
             "buffers": {"max_entries": 16, "max_waypoints": 4096}}
 
 
+def unprofiled_leg(s, q_start, q_goal, res: float, n: int) -> dict:
+    """The timed region times every tile launch with a HIP event pair, which
+    adds about 12-18 us of dispatch cost per launch.  The same plans (seeds
+    0..n-1, as the first timed steps) without events show the planner's own
+    latency."""
+    ts, tts, states = [], [], 0
+    for seed in range(n):
+        t0 = time.perf_counter()
+        r = s.plan(q_start, q_goal, raise_on_error=False, resolution=res, **dict(PLAN, seed=seed))
+        ts.append(time.perf_counter() - t0)
+        if r.stats["time_to_first_s"] >= 0:
+            tts.append(r.stats["time_to_first_s"])
+        states += r.stats["edge_states"]
+    return {"plans": n, "mean_plan_ms": float(np.mean(ts)) * 1e3,
+            "tts_p50_ms": float(np.median(tts)) * 1e3 if tts else None,
+            "plan_edge_states_per_s": states / float(np.sum(ts))}
+
+
 SINGLE_FIXTURE = os.path.join(ROOT, "tests", "golden", "single_arm.json")
 # Direct mode (one arm, no roadmaps): extension length `step` (rad).
 DIRECT_PLAN = dict(candidates=128, max_rounds=150, max_iterations=4, direct=1, step=1.0)
@@ -464,6 +482,7 @@ def main():
                         "edge_states_per_plan": plan_states / len(plans),
                         "params": PLAN}
         line["config"]["plan"] = "one mrpop_plan per step, seed = step index"
+        line["plan_unprofiled"] = unprofiled_leg(s, q_start, q_goal, res, min(10, len(plans)))
     if args.direct:
         print("[bench] direct mode", file=sys.stderr, flush=True)
         line["direct"] = direct_leg(ctx, res)

@@ -482,7 +482,10 @@ def main():
                         "edge_states_per_plan": plan_states / len(plans),
                         "params": PLAN}
         line["config"]["plan"] = "one mrpop_plan per step, seed = step index"
-        line["plan_unprofiled"] = unprofiled_leg(s, q_start, q_goal, res, min(10, len(plans)))
+        n_same = min(10, len(plans))
+        line["plan_unprofiled"] = unprofiled_leg(s, q_start, q_goal, res, n_same)
+        line["plan_unprofiled"]["timed_mean_plan_ms_same_seeds"] = float(
+            np.mean([p.stats["total_time_s"] for p in plans[:n_same]])) * 1e3
     if args.direct:
         print("[bench] direct mode", file=sys.stderr, flush=True)
         line["direct"] = direct_leg(ctx, res)

@@ -389,6 +389,8 @@ def main():
                     help="skip the direct-mode (single-arm, no roadmap) leg")
     ap.add_argument("--no-replan", dest="replan", action="store_false",
                     help="skip the replanning (moving obstacle) leg")
+    ap.add_argument("--no-unprofiled", dest="unprofiled", action="store_false",
+                    help="skip replaying the first timed plans without per-launch events")
     ap.add_argument("--history-plans", type=int, default=10,
                     help="plans timed with and without the incumbent-history export (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the served run (0: skip)")
@@ -482,10 +484,11 @@ def main():
                         "edge_states_per_plan": plan_states / len(plans),
                         "params": PLAN}
         line["config"]["plan"] = "one mrpop_plan per step, seed = step index"
-        n_same = min(10, len(plans))
-        line["plan_unprofiled"] = unprofiled_leg(s, q_start, q_goal, res, n_same)
-        line["plan_unprofiled"]["timed_mean_plan_ms_same_seeds"] = float(
-            np.mean([p.stats["total_time_s"] for p in plans[:n_same]])) * 1e3
+        if args.unprofiled:
+            n_same = min(10, len(plans))
+            line["plan_unprofiled"] = unprofiled_leg(s, q_start, q_goal, res, n_same)
+            line["plan_unprofiled"]["timed_mean_plan_ms_same_seeds"] = float(
+                np.mean([p.stats["total_time_s"] for p in plans[:n_same]])) * 1e3
     if args.direct:
         print("[bench] direct mode", file=sys.stderr, flush=True)
         line["direct"] = direct_leg(ctx, res)

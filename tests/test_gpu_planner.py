@@ -151,6 +151,33 @@ def test_plan_returns_valid_improving_path(ctx, kind):
     print(f"  min margin at res/4: {m4.min():.3e}", flush=True)
 
 
+def test_plan_ten_arms_grouped_launches(ctx):
+    """Ten planar arms: each roadmap step's per-arm commands exceed one
+    launch group (eight records) and the arms' validations exceed the
+    one-workgroup segment table, so the chunked and the general paths run.
+    The plan must be valid, repeatable and equal to its batched run."""
+    rng = np.random.default_rng(31)
+    sph = np.concatenate([rng.uniform([-0.5, -0.5, -0.05], [0.5, 0.5, 0.05], (6, 3)),
+                          rng.uniform(0.05, 0.1, (6, 1))], axis=1).astype(np.float32)
+    sc = W.Scene([W.planar_two_link()] * 10, W.ring_bases(10, 1.3), sph, np.zeros((0, 6), np.float32),
+                 name="ten planar arms")
+    p = W.make_problem(sc, 3, oracle.states_free)
+    s = _scene(ctx, p.scene)
+    params = dict(PARAMS, max_iterations=2)
+    a = s.plan(p.q_start, p.q_goal, **params)
+    print(f"  cost {a.cost:.4f} stats {a.stats}", flush=True)
+    assert a.status == "OK"
+    _check_path(p.scene, a, p.q_start, p.q_goal, params)
+    b = s.plan(p.q_start, p.q_goal, **params)
+    assert np.array_equal(a.path, b.path) and a.cost == b.cost
+    got, _ = ctx.plan_batch([(s, p.q_start, p.q_goal, dict(params, seed=k)) for k in (1, 2)])
+    for k, g in zip((1, 2), got):
+        ref = s.plan(p.q_start, p.q_goal, raise_on_error=False, **dict(params, seed=k))
+        assert g.status == ref.status
+        if ref.status == "OK":
+            assert np.array_equal(g.path, ref.path) and g.cost == ref.cost
+
+
 def test_plan_deterministic(ctx):
     p = problem("c1")
     s = _scene(ctx, p.scene)

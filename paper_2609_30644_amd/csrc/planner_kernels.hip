@@ -395,88 +395,9 @@ __device__ __forceinline__ void steer_body(const SteerArgs &a, int bx) {
 // a10: insertion in candidate order; a11: connection edges; a12: selection
 // ---------------------------------------------------------------------------
 
-// Insertion of the surviving candidates (alive and edge-valid) in index
-// order, kInsertPer candidates per workgroup: each workgroup counts the
-// survivors before its range and in total, places its own survivors at
-// n_before + (survivors before them) up to the tree's capacity, copies them
-// into the tree (SoA) and writes each candidate's tree index (-1 if not
-// inserted) and connection budget c_best - g_new (-1 if not inserted, so no
-// vertex is admissible).  Workgroup 0 records the count and the new size.
-constexpr int kInsertPer = kWave;
+// Connection edge (q_new -> q_conn) of one candidate, one joint per lane; a
+// candidate without a connection gets a null edge.
 
-__device__ __forceinline__ void insert_body(const InsertArgs &a, int bx) {
-  const int i0 = bx * kInsertPer;
-  if (bx > 0 && i0 >= a.n) return;
-  __shared__ int32_t s_pos[kInsertPer];
-  __shared__ int32_t s_red[2][256 / kWave];
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  // survivors before i0 and in total
-  int before = 0, all = 0;
-  for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
-    const int ok = (a.alive[i] && a.valid[i]) ? 1 : 0;
-    all += ok;
-    before += i < i0 ? ok : 0;
-  }
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    all += __shfl_xor(all, d, kWave);
-    before += __shfl_xor(before, d, kWave);
-  }
-  if (lane == 0) {
-    s_red[0][w] = before;
-    s_red[1][w] = all;
-  }
-  __syncthreads();
-  before = 0;
-  all = 0;
-  for (int k = 0; k < nw; ++k) {
-    before += s_red[0][k];
-    all += s_red[1][k];
-  }
-  // this workgroup's candidates, one per lane of wave 0
-  if (w == 0) {
-    const int i = i0 + lane;
-    const bool ok = i < a.n && a.alive[i] && a.valid[i];
-    const uint64_t bal = __ballot(ok);
-    const int pos = before + __popcll(bal & ((1ull << lane) - 1ull));
-    const int32_t t = (ok && a.n_before + pos < a.tree_cap) ? a.n_before + pos : -1;
-    s_pos[lane] = t;
-    if (i < a.n) {
-      a.ins_idx[i] = t;
-      a.budget[i] = t < 0 ? -1.f : (a.c_best < INFINITY ? a.c_best - a.g_new[i] : INFINITY);
-    }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < kInsertPer * a.dim; k += blockDim.x) {
-    const int li = k / a.dim, j = k - li * a.dim;
-    const int32_t t = s_pos[li];
-    if (t >= 0) a.tree_q[(int64_t)j * a.tree_cap + t] = a.q_new[(int64_t)(i0 + li) * a.dim + j];
-  }
-  for (int k = threadIdx.x; k < kInsertPer * a.n_robots; k += blockDim.x) {
-    const int li = k / a.n_robots, r = k - li * a.n_robots;
-    const int32_t t = s_pos[li];
-    if (t >= 0) a.tree_vid[(int64_t)r * a.tree_cap + t] = a.vid_new[(int64_t)r * a.n + i0 + li];
-  }
-  if (threadIdx.x < kInsertPer) {
-    const int32_t t = s_pos[threadIdx.x];
-    if (t >= 0) {
-      a.tree_g[t] = a.g_new[i0 + threadIdx.x];
-      a.tree_parent[t] = a.near_idx[i0 + threadIdx.x];
-    }
-  }
-  if (bx == 0 && threadIdx.x == 0) {
-    const int room = a.tree_cap - a.n_before;
-    const int ins = all < room ? all : room;
-    a.status->inserted = ins;
-    a.status->overflow = all > room ? 1 : 0;
-    *a.tree_n = a.n_before + ins;
-  }
-}
-
-// Connection edges (q_new -> q_conn), one wavefront per candidate and one
-// joint per lane; candidates without a connection get a null edge.
-constexpr int kConnWaves = 4;
-
-// Candidate i by one wavefront.
 __device__ __forceinline__ void conn_one(const ConnArgs &a, int i, int lane) {
   const int c = a.conn_idx[i];
   float *ea = a.edge_a + (int64_t)i * a.dim, *eb = a.edge_b + (int64_t)i * a.dim;
@@ -497,12 +418,6 @@ __device__ __forceinline__ void conn_one(const ConnArgs &a, int i, int lane) {
   }
 }
 
-__device__ __forceinline__ void conn_body(const ConnArgs &a, int bx) {
-  const int i = bx * kConnWaves + (int)(threadIdx.x / kWave);
-  if (i >= a.n) return;  // whole waves leave together
-  conn_one(a, i, (int)(threadIdx.x & (kWave - 1)));
-}
-
 // ---------------------------------------------------------------------------
 // fused round steps, one workgroup (256 threads) per candidate
 // ---------------------------------------------------------------------------
@@ -517,10 +432,15 @@ __device__ __forceinline__ void sample_near_body(const SampleNearArgs &a, int bx
   nearest_body(a.q, bx);
 }
 
-// The candidate's insertion in the extended tree (position: the survivors
-// before it, as in insert_body), the nearest vertex of the other tree under
-// the budget the insertion sets, and the connection edge.  The trees differ,
-// so the insertion and the search never touch the same vertices.
+// Insertion of the surviving candidates (alive and edge-valid) in index
+// order, then the connection step.  The workgroup of candidate i counts the
+// survivors before i and in total, places i (if it survives) at n_before +
+// (survivors before it) up to the tree's capacity, copies it into the tree
+// (SoA) and writes its tree index (-1 if not inserted) and connection budget
+// c_best - g_new (-1 if not inserted, so no vertex is admissible); workgroup
+// 0 records the count and the new size.  Then the nearest vertex of the other
+// tree under that budget, and the connection edge.  The trees differ, so the
+// insertion and the search never touch the same vertices.
 __device__ __forceinline__ void insert_conn_body(const InsertConnArgs &A, int bx) {
   const InsertArgs &a = A.ins;
   if (a.n <= 0) {  // nothing to insert: the round's record still gets its counts
@@ -963,8 +883,6 @@ MRPOP_OP_KERNELS(sample, SampleArgs, kSampleWaves * kWave)
 MRPOP_OP_KERNELS(nearest, NearestArgs, 256)
 MRPOP_OP_KERNELS(extend, ExtendArgs, kExtendWaves * kWave)
 MRPOP_OP_KERNELS(steer, SteerArgs, kSteerWaves * kWave)
-MRPOP_OP_KERNELS(insert, InsertArgs, 256)
-MRPOP_OP_KERNELS(conn, ConnArgs, kConnWaves * kWave)
 MRPOP_OP_KERNELS(select, SelectArgs, 256)
 MRPOP_OP_KERNELS(path, PathArgs, 64)
 MRPOP_OP_KERNELS(tree_root, TreeRootArgs, 128)
@@ -993,8 +911,6 @@ int op_blocks(Op op, const void *p) {
       return clamp_blocks((a.n + kExtendWaves - 1) / kExtendWaves);
     }
     case Op::Steer: return clamp_blocks((((const SteerArgs *)p)->n + kSteerWaves - 1) / kSteerWaves);
-    case Op::Insert: return clamp_blocks(std::max(1, (((const InsertArgs *)p)->n + kInsertPer - 1) / kInsertPer));
-    case Op::Conn: return clamp_blocks((((const ConnArgs *)p)->n + kConnWaves - 1) / kConnWaves);
     case Op::Select: return 1;
     case Op::Path: return 1;
     case Op::TreeRoot: return 1;
@@ -1022,8 +938,6 @@ size_t op_args_bytes(Op op) {
     case Op::Nearest: return sizeof(NearestArgs);
     case Op::Extend: return sizeof(ExtendArgs);
     case Op::Steer: return sizeof(SteerArgs);
-    case Op::Insert: return sizeof(InsertArgs);
-    case Op::Conn: return sizeof(ConnArgs);
     case Op::Select: return sizeof(SelectArgs);
     case Op::Path: return sizeof(PathArgs);
     case Op::TreeRoot: return sizeof(TreeRootArgs);
@@ -1082,8 +996,6 @@ static hipError_t launch_group_any(Op op, const void *const *recs, int n, int gr
     MRPOP_GROUP_CASE(Nearest, nearest, NearestArgs)
     MRPOP_GROUP_CASE(Extend, extend, ExtendArgs)
     MRPOP_GROUP_CASE(Steer, steer, SteerArgs)
-    MRPOP_GROUP_CASE(Insert, insert, InsertArgs)
-    MRPOP_GROUP_CASE(Conn, conn, ConnArgs)
     MRPOP_GROUP_CASE(Select, select, SelectArgs)
     MRPOP_GROUP_CASE(Path, path, PathArgs)
     MRPOP_GROUP_CASE(TreeRoot, tree_root, TreeRootArgs)
@@ -1108,8 +1020,6 @@ static hipError_t launch_any(Op op, const void *p, bool batch, int count, int gr
     MRPOP_OP_CASE(Nearest, nearest, NearestArgs)
     MRPOP_OP_CASE(Extend, extend, ExtendArgs)
     MRPOP_OP_CASE(Steer, steer, SteerArgs)
-    MRPOP_OP_CASE(Insert, insert, InsertArgs)
-    MRPOP_OP_CASE(Conn, conn, ConnArgs)
     MRPOP_OP_CASE(Select, select, SelectArgs)
     MRPOP_OP_CASE(Path, path, PathArgs)
     MRPOP_OP_CASE(TreeRoot, tree_root, TreeRootArgs)
@@ -1161,8 +1071,6 @@ hipError_t launch_nearest(const NearestArgs &a, hipStream_t s) {
   return launch_op(Op::Nearest, &a, s);
 }
 hipError_t launch_extend(const ExtendArgs &a, hipStream_t s) { return launch_op(Op::Extend, &a, s); }
-hipError_t launch_insert(const InsertArgs &a, hipStream_t s) { return launch_op(Op::Insert, &a, s); }
-hipError_t launch_conn_edges(const ConnArgs &a, hipStream_t s) { return launch_op(Op::Conn, &a, s); }
 hipError_t launch_select(const SelectArgs &a, hipStream_t s) { return launch_op(Op::Select, &a, s); }
 hipError_t launch_path(const PathArgs &a, hipStream_t s) { return launch_op(Op::Path, &a, s); }
 hipError_t launch_tree_root(const TreeRootArgs &a, hipStream_t s) { return launch_op(Op::TreeRoot, &a, s); }

@@ -114,6 +114,26 @@ class PlainExec : public Exec {
     }
     return hipSuccess;
   }
+  // Spins on the flag: the round trip is about half that of a stream
+  // synchronisation.  The stream is polled now and then, so that a failed
+  // kernel is reported instead of waited for.
+  hipError_t wait_flag(const uint32_t *flag, uint32_t value) override {
+    hipError_t e = flush_validations();
+    if (e != hipSuccess) return e;
+    for (uint32_t k = 1;; ++k) {
+      if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == value) break;
+      if ((k & 1023u) == 0) {
+        e = hipStreamQuery(s_);
+        if (e == hipSuccess) {  // all work done: the flag must be there now
+          if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == value) break;
+          return hipErrorUnknown;
+        }
+        if (e != hipErrorNotReady) return e;
+      }
+    }
+    used_ = 0;  // everything before the flag's writer has completed
+    return hipSuccess;
+  }
   hipError_t sync() override {
     hipError_t e = flush_validations();
     if (e != hipSuccess) return e;
@@ -364,6 +384,7 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   plan_arena_(arena_);
   device_bytes_ = arena_bytes;
   if ((e = hipHostMalloc((void **)&pin_, sizeof(Pinned))) != hipSuccess) return hip_fail_(e, "hipHostMalloc");
+  std::memset(pin_, 0, sizeof(Pinned));  // round numbers start at 1, so no stale record matches
   if ((e = hipHostMalloc((void **)&pin_rm_, sizeof(int32_t) * (size_t)R * (kRmInts + 1))) != hipSuccess)
     return hip_fail_(e, "hipHostMalloc");
   if ((e = hipHostMalloc((void **)&pin_cnt_, sizeof(uint64_t) * (size_t)R * 16)) != hipSuccess)
@@ -688,8 +709,11 @@ mrpop_status PlanJob::run(Exec &ex) {
       TRY(validate_(ex, scene_, ca_, cb_, PC, P_.resolution, cvalid_, cnt_ + 16, codes_conn_));
       SUBMIT(Op::Select, select,
              SelectArgs{PC, D, ins_idx_, conn_idx_, cvalid_, q_new_, g_new_, tq_[b], tg_[b], tcap_, cnt_, cnt_ + 16,
-                        status_, &pin_->status});
-      SYNC();
+                        status_, &pin_->status, (uint32_t)rnd + 1u});
+      {
+        const hipError_t e_ = ex.wait_flag(&pin_->status.seq, (uint32_t)rnd + 1u);
+        if (e_ != hipSuccess) return hip_fail_(e_, "round status");
+      }
       const RoundStatus rsx = pin_->status;
       st_.edge_states += rsx.states_ext + rsx.states_conn;
       n_t[a] += rsx.inserted;
@@ -745,6 +769,7 @@ mrpop_status PlanJob::run(Exec &ex) {
     if (!solved) break;
     if (P_.stop_at_first && !best_path_.empty()) break;
   }
+  SYNC();  // a failure of queued work is reported here at the latest
   st_.rounds = rnd;
   st_.iterations = it;
   for (int r = 0; r < R && !P_.direct; ++r) st_.roadmap_vertices += rm_n_[r];

@@ -63,7 +63,8 @@ struct ExtendArgs {
 struct RoundStatus {
   int32_t found, cand, a_idx, b_idx;
   float total;
-  int32_t inserted, overflow, pad;
+  int32_t inserted, overflow;
+  uint32_t seq;  // in the host copy: stored last, with a system-scope release (the round's number)
   int64_t states_ext, states_conn;
 };
 
@@ -120,6 +121,7 @@ struct SelectArgs {
   const uint64_t *states_ext, *states_conn;  // validation counters (index 1: edge states)
   RoundStatus *status;
   RoundStatus *status_out;  // or null: receives the round's finished record (e.g. pinned host memory)
+  uint32_t seq;             // written to status_out->seq after the rest of the record
 };
 
 // Fused round steps, one workgroup per candidate: the sample and its
@@ -321,6 +323,14 @@ class Exec {
     return hipSuccess;
   }
   virtual hipError_t sync() = 0;
+  // Waits until *flag == value, where the last submitted command stores
+  // value there last, with a system-scope release (then everything submitted
+  // before has completed).  The default synchronises.
+  virtual hipError_t wait_flag(const uint32_t *flag, uint32_t value) {
+    (void)flag;
+    (void)value;
+    return sync();
+  }
 };
 
 }  // namespace mrpop

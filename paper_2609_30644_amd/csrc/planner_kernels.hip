@@ -558,7 +558,19 @@ __device__ __forceinline__ void select_body(const SelectArgs &a, int bx) {
     a.status->total = sc[0];
     a.status->states_ext = a.states_ext ? (int64_t)a.states_ext[1] : 0;
     a.status->states_conn = a.states_conn ? (int64_t)a.states_conn[1] : 0;
-    if (a.status_out) *a.status_out = *a.status;
+    if (a.status_out) {  // the record, then its sequence number (the host waits on it)
+      RoundStatus *o = a.status_out;
+      o->found = a.status->found;
+      o->cand = a.status->cand;
+      o->a_idx = a.status->a_idx;
+      o->b_idx = a.status->b_idx;
+      o->total = a.status->total;
+      o->inserted = a.status->inserted;
+      o->overflow = a.status->overflow;
+      o->states_ext = a.status->states_ext;
+      o->states_conn = a.status->states_conn;
+      __hip_atomic_store(&o->seq, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 

@@ -159,6 +159,41 @@ __device__ __forceinline__ bool better(const Best &a, const Best &b) {
   return a.idx < b.idx;
 }
 
+// This thread's best vertex (threads stride over vertices) for the query sq
+// under budget c; DC > 0: the dimension, known at compile time.  Squared
+// distances are summed over the coordinates in order in either form.
+template <int DC>
+__device__ __forceinline__ Best nearest_scan(const NearestArgs &a, const float *sq, float c) {
+  Best best{INFINITY, INFINITY, -1};
+  constexpr int QR = DC > 0 ? DC : 1;
+  float q[QR];
+  if constexpr (DC > 0) {
+#pragma unroll
+    for (int j = 0; j < DC; ++j) q[j] = sq[j];
+  }
+  for (int64_t v = threadIdx.x; v < a.n; v += blockDim.x) {
+    float d2 = 0.f;
+    const float *p = a.V + v * a.v_stride;
+    if constexpr (DC > 0) {
+#pragma unroll
+      for (int j = 0; j < DC; ++j) {
+        const float t = q[j] - p[j * a.d_stride];
+        d2 = fmaf(t, t, d2);
+      }
+    } else {
+      for (int j = 0; j < a.dim; ++j) {
+        const float t = sq[j] - p[j * a.d_stride];
+        d2 = fmaf(t, t, d2);
+      }
+    }
+    const float g = a.g ? a.g[v] : 0.f;
+    if (!(g + sqrtf(d2) < c)) continue;
+    const Best cand{d2, g, (int32_t)v};
+    if (better(cand, best)) best = cand;
+  }
+  return best;
+}
+
 // One workgroup per query: threads stride over vertices; admissible when
 // g_v + |q - q_v| < c; the least distance wins, ties to the lower cost, then
 // the lower index.
@@ -176,17 +211,13 @@ __device__ __forceinline__ void nearest_body(const NearestArgs &a, int bx) {
   }
   for (int j = threadIdx.x; j < D; j += blockDim.x) sq[j] = a.queries[qi * a.q_stride + j];
   __syncthreads();
-  Best best{INFINITY, INFINITY, -1};
-  for (int64_t v = threadIdx.x; v < a.n; v += blockDim.x) {
-    float d2 = 0.f;
-    for (int j = 0; j < D; ++j) {
-      const float t = sq[j] - a.V[v * a.v_stride + j * a.d_stride];
-      d2 = fmaf(t, t, d2);
-    }
-    const float g = a.g ? a.g[v] : 0.f;
-    if (!(g + sqrtf(d2) < c)) continue;
-    const Best cand{d2, g, (int32_t)v};
-    if (better(cand, best)) best = cand;
+  Best best;
+  switch (D) {  // common dimensions unrolled, with the query in registers
+    case 7: best = nearest_scan<7>(a, sq, c); break;
+    case 14: best = nearest_scan<14>(a, sq, c); break;
+    case 28: best = nearest_scan<28>(a, sq, c); break;
+    case 56: best = nearest_scan<56>(a, sq, c); break;
+    default: best = nearest_scan<0>(a, sq, c); break;
   }
   for (int d = kWave / 2; d > 0; d >>= 1) {
     Best o;

@@ -317,16 +317,32 @@ __device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
   }
   // (a group is active or idle as a whole, so the shuffles above read active lanes only)
   const bool moved = __ballot(g < R && sub == 0 && best != v) != 0ull;
-  // |q_new - q_near|^2 summed arm by arm, joint by joint (identical in every lane)
-  float dist2 = 0.f;
-  for (int r = 0; r < R; ++r) {
-    const int br = __shfl(best, r * gs, kWave);
-    const int nj = a.nj[r], q0 = a.q_off[r];
-    for (int j = 0; j < nj; ++j) {
-      const float x = a.rm_V[((int64_t)r * a.rm_cap + br) * kRmStride + j];
-      const float y = a.tree_q[(int64_t)(q0 + j) * a.tree_cap + near];
-      dist2 = fmaf(x - y, x - y, dist2);
+  // q_new and q_near, composite joint k in lane k % 64 (slot k / 64), loaded
+  // in parallel; then |q_new - q_near|^2 summed arm by arm, joint by joint
+  // (identical in every lane)
+  constexpr int kPerLane = kMaxDof / kWave + 1;
+  float xs[kPerLane], ys[kPerLane];
+#pragma unroll
+  for (int t = 0; t < kPerLane; ++t) {
+    const int k = lane + t * kWave;
+    int r = 0;
+    while (r + 1 < R && k >= a.q_off[r + 1]) ++r;
+    const int br = __shfl(best, r * gs, kWave);  // every lane takes part
+    xs[t] = 0.f;
+    ys[t] = 0.f;
+    if (k < D) {
+      xs[t] = a.rm_V[((int64_t)r * a.rm_cap + br) * kRmStride + (k - a.q_off[r])];
+      ys[t] = a.tree_q[(int64_t)k * a.tree_cap + near];
     }
+  }
+  float dist2 = 0.f;
+  for (int k = 0; k < D; ++k) {
+    const int t = k / kWave;
+    float dk = 0.f;
+#pragma unroll
+    for (int u = 0; u < kPerLane; ++u)
+      if (u == t) dk = __shfl(xs[u] - ys[u], k - u * kWave, kWave);
+    dist2 = fmaf(dk, dk, dist2);
   }
   const float gn = a.tree_g[near] + sqrtf(dist2);
   bool ok = moved;
@@ -335,21 +351,23 @@ __device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
     a.g_new[i] = gn;
     a.alive[i] = ok ? 1 : 0;
   }
-  // outputs, one joint per lane (at most 7 joints per arm), and the edge's
-  // largest joint difference for its state count
+  // outputs from the same registers, and the edge's largest joint difference
+  // for its state count
+  {
+    const int br = __shfl(best, (lane < R ? lane : 0) * gs, kWave);  // every lane takes part
+    if (lane < R) a.vid_new[(int64_t)lane * a.n + i] = br;
+  }
   float linf = 0.f;
   bool finite = true;
-  for (int r = 0; r < R; ++r) {
-    const int br = __shfl(best, r * gs, kWave);
-    const int nj = a.nj[r], q0 = a.q_off[r];
-    if (lane == 0) a.vid_new[(int64_t)r * a.n + i] = br;
-    if (lane < nj) {
-      const float x = a.rm_V[((int64_t)r * a.rm_cap + br) * kRmStride + lane];
-      const float y = a.tree_q[(int64_t)(q0 + lane) * a.tree_cap + near];
+#pragma unroll
+  for (int t = 0; t < kPerLane; ++t) {
+    const int k = lane + t * kWave;
+    if (k < D) {
+      const float x = xs[t], y = ys[t];
       const float b = ok ? x : y;
-      qn[q0 + lane] = x;
-      ea[q0 + lane] = y;
-      eb[q0 + lane] = b;
+      qn[k] = x;
+      ea[k] = y;
+      eb[k] = b;
       finite = finite && isfinite(y) && isfinite(b);
       linf = fmaxf(linf, fabsf(b - y));
     }

@@ -727,10 +727,11 @@ __device__ __forceinline__ void rm_accept_body(const RmAcceptArgs &A, int bx) {
 }
 
 // Pairs (j, i), i in [i0, i1) (i1 lowered to the device's vertex count when
-// given), j < i, with |V_i - V_j| <= delta: counted
-// (pair_ids null), or written as edge endpoints (qa = V_j, qb = V_i) and ids,
-// compacted with an atomic counter (their order does not reach any result: adjacency is rebuilt as a
-// set and the extension oracle breaks ties by vertex id).
+// given), j < i, with |V_i - V_j| <= delta: counted (pair_ids null), or
+// written as edge endpoints (qa = V_j, qb = V_i) and ids, compacted with an
+// atomic counter updated once per wave.  Their order does not reach any
+// result: adjacency is rebuilt as a set and the extension oracle breaks ties
+// by vertex id.
 __device__ __forceinline__ void rm_pairs_body(const RmPairsArgs &A, int bx) {
   const float *V = A.V;
   const int i0 = A.i0, nj = A.nj, cap = A.cap;
@@ -741,26 +742,50 @@ __device__ __forceinline__ void rm_pairs_body(const RmPairsArgs &A, int bx) {
 
   const int i = i0 + bx;
   if (i >= i1) return;
-  for (int j = threadIdx.x; j < i; j += blockDim.x) {
-    float d2 = 0.f;
-    for (int d = 0; d < nj; ++d) {
-      const float t = V[(int64_t)i * kRmStride + d] - V[(int64_t)j * kRmStride + d];
-      d2 = fmaf(t, t, d2);
+  const int lane = threadIdx.x & (kWave - 1);
+  static_assert(kRmStride == 8, "roadmap rows are read as two float4");
+  const float4 *rows = (const float4 *)V;
+  const float4 a0 = rows[(int64_t)i * 2], a1 = rows[(int64_t)i * 2 + 1];
+  const float vi[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+  for (int j0 = 0; j0 < i; j0 += blockDim.x) {  // the same trip count in every lane
+    const int j = j0 + threadIdx.x;
+    bool near = false;
+    float vj[8];
+    if (j < i) {
+      const float4 b0 = rows[(int64_t)j * 2], b1 = rows[(int64_t)j * 2 + 1];
+      vj[0] = b0.x; vj[1] = b0.y; vj[2] = b0.z; vj[3] = b0.w;
+      vj[4] = b1.x; vj[5] = b1.y; vj[6] = b1.z; vj[7] = b1.w;
+      float d2 = 0.f;
+#pragma unroll
+      for (int d = 0; d < 8; ++d)
+        if (d < nj) {
+          const float t = vi[d] - vj[d];
+          d2 = fmaf(t, t, d2);
+        }
+      near = sqrtf(d2) <= delta;
     }
-    if (!(sqrtf(d2) <= delta)) continue;
-    const int k = atomicAdd(count, 1);
+    // one counter update per wave: slots in lane order within the wave
+    const uint64_t m = __ballot(near);
+    if (m == 0ull) continue;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, 0, kWave);
+    if (!near) continue;
+    const int k = base + __popcll(m & ((1ull << lane) - 1ull));
     if (!pair_ids || k >= cap) continue;  // counting only, or beyond the allotted room
     pair_ids[2 * k] = j;
     pair_ids[2 * k + 1] = i;
     bool finite = true;
     float linf = 0.f;
-    for (int d = 0; d < nj; ++d) {
-      const float x = V[(int64_t)j * kRmStride + d], y = V[(int64_t)i * kRmStride + d];
-      qa[(int64_t)k * nj + d] = x;
-      qb[(int64_t)k * nj + d] = y;
-      finite = finite && isfinite(x) && isfinite(y);
-      linf = fmaxf(linf, fabsf(y - x));
-    }
+#pragma unroll
+    for (int d = 0; d < 8; ++d)
+      if (d < nj) {
+        const float x = vj[d], y = vi[d];
+        qa[(int64_t)k * nj + d] = x;
+        qb[(int64_t)k * nj + d] = y;
+        finite = finite && isfinite(x) && isfinite(y);
+        linf = fmaxf(linf, fabsf(y - x));
+      }
     if (A.codes) A.codes[k] = state_count_code(linf, finite, A.res);
   }
 }

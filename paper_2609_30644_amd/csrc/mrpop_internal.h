@@ -84,7 +84,9 @@ struct DeviceBuffer {
 struct mrpop_ctx {
   int device = 0;
   std::string last_error;
-  // Scratch reused across calls (grown on demand).
+  // Scratch reused across calls (grown on demand): slot 0 edge validation,
+  // 1 the planner's one-scene validations, 2 and 3 its many-scene segment
+  // tables and scratch.
   mrpop::DeviceBuffer scratch[8];
   // Profiling of the validation tile kernel: event pairs recorded on the
   // launch stream, and device totals (states checked, edge states).

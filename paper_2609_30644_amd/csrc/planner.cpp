@@ -77,8 +77,6 @@ class PlainExec : public Exec {
   PlainExec(mrpop_ctx *ctx, hipStream_t s) : ctx_(ctx), s_(s) {}
   ~PlainExec() override {
     for (void *p : staging_) (void)hipHostFree(p);
-    if (d_segs_) (void)hipFree(d_segs_);
-    if (seg_ws_) (void)hipFree(seg_ws_);
   }
   hipError_t submit(const Cmd &c) override {
     if (c.op == Op::Validate) {
@@ -227,25 +225,18 @@ class PlainExec : public Exec {
     g.out = q.out;
     g.counters = q.counters;
   }
-  // Device segment table (bytes) and scratch for n_flat edges; a buffer in
-  // use by queued work is only replaced after the stream has drained.
+  // Device segment table (bytes) and scratch for n_flat edges, in the
+  // context's scratch slots 2 and 3 (kept across plans, so that a plan does
+  // not allocate them again); a buffer in use by queued work is only
+  // replaced after the stream has drained.
   hipError_t ensure_seg_buffers(size_t bytes, int64_t flat) {
-    hipError_t e;
-    if (d_segs_bytes_ < bytes) {
-      if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
-      if (d_segs_) (void)hipFree(d_segs_);
-      d_segs_ = nullptr;
-      d_segs_bytes_ = std::max(bytes, 2 * d_segs_bytes_);
-      if ((e = hipMalloc(&d_segs_, d_segs_bytes_)) != hipSuccess) return e;
-    }
     const size_t ws_bytes = seg_scratch_bytes(flat);
-    if (seg_ws_bytes_ < ws_bytes) {
-      if ((e = hipStreamSynchronize(s_)) != hipSuccess) return e;
-      if (seg_ws_) (void)hipFree(seg_ws_);
-      seg_ws_ = nullptr;
-      seg_ws_bytes_ = std::max(ws_bytes, 2 * seg_ws_bytes_);
-      if ((e = hipMalloc(&seg_ws_, seg_ws_bytes_)) != hipSuccess) return e;
+    if (ctx_->scratch[2].bytes < bytes || ctx_->scratch[3].bytes < ws_bytes) {
+      const hipError_t e = hipStreamSynchronize(s_);
+      if (e != hipSuccess) return e;
     }
+    if (scratch(ctx_, 2, bytes, &d_segs_) != MRPOP_OK) return hipErrorOutOfMemory;
+    if (scratch(ctx_, 3, ws_bytes, &seg_ws_) != MRPOP_OK) return hipErrorOutOfMemory;
     return hipSuccess;
   }
 
@@ -254,8 +245,7 @@ class PlainExec : public Exec {
   std::vector<ValidateReq> val_;
   std::vector<void *> staging_;  // pinned uploads of segment tables, free again after sync()
   size_t used_ = 0, stage_bytes_ = 0;
-  void *d_segs_ = nullptr, *seg_ws_ = nullptr;
-  size_t d_segs_bytes_ = 0, seg_ws_bytes_ = 0;
+  void *d_segs_ = nullptr, *seg_ws_ = nullptr;  // the context's scratch slots 2 and 3
 };
 
 PlanJob::~PlanJob() {

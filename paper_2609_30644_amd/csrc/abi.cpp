@@ -46,6 +46,47 @@ mrpop_status scratch(mrpop_ctx *ctx, int slot, size_t bytes, void **out) {
   return MRPOP_OK;
 }
 
+hipError_t pool_alloc(mrpop_ctx *ctx, bool pinned, size_t bytes, void **out, size_t *got) {
+  bytes = std::max<size_t>(bytes, 256);
+  {
+    std::lock_guard<std::mutex> lk(ctx->pool_mu);
+    auto &v = pinned ? ctx->pool_pin : ctx->pool_dev;
+    size_t best = v.size();
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i].second >= bytes && v[i].second <= 2 * bytes + (size_t(1) << 20) &&
+          (best == v.size() || v[i].second < v[best].second))
+        best = i;
+    if (best < v.size()) {
+      *out = v[best].first;
+      *got = v[best].second;
+      (pinned ? ctx->pool_pin_bytes : ctx->pool_dev_bytes) -= v[best].second;
+      v.erase(v.begin() + (std::ptrdiff_t)best);
+      return hipSuccess;
+    }
+  }
+  *got = bytes;
+  return pinned ? hipHostMalloc(out, bytes) : hipMalloc(out, bytes);
+}
+
+void pool_free(mrpop_ctx *ctx, bool pinned, void *p, size_t bytes) {
+  if (!p) return;
+  std::vector<std::pair<void *, size_t>> drop;
+  {
+    std::lock_guard<std::mutex> lk(ctx->pool_mu);
+    auto &v = pinned ? ctx->pool_pin : ctx->pool_dev;
+    size_t &total = pinned ? ctx->pool_pin_bytes : ctx->pool_dev_bytes;
+    v.push_back({p, bytes});
+    total += bytes;
+    const size_t keep = pinned ? kPoolKeepPin : kPoolKeepDev;
+    while (total > keep && !v.empty()) {
+      drop.push_back(v.front());
+      total -= v.front().second;
+      v.erase(v.begin());
+    }
+  }
+  for (auto &b : drop) (void)(pinned ? hipHostFree(b.first) : hipFree(b.first));
+}
+
 const std::pair<hipEvent_t, hipEvent_t> *profile_slot(mrpop_ctx *ctx) {
   if (!ctx->profiling) return nullptr;
   if (ctx->ev_used == ctx->ev_pool.size()) {
@@ -127,6 +168,8 @@ void mrpop_ctx_destroy(mrpop_ctx *ctx) {
   }
   if (ctx->prof_totals) hipFree(ctx->prof_totals);
   if (ctx->small_arrived) hipFree(ctx->small_arrived);
+  for (auto &b : ctx->pool_dev) hipFree(b.first);
+  for (auto &b : ctx->pool_pin) hipHostFree(b.first);
   delete ctx;
 }
 
@@ -596,6 +639,8 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
 
 void mrpop_scene_destroy(mrpop_scene *scene) {
   if (!scene) return;
+  for (mrpop_scene *a : scene->arm_cache) mrpop_scene_destroy(a);
+  scene->arm_cache.clear();
   if (scene->blob) {
     hipSetDevice(scene->ctx->device);
     hipFree(scene->blob);

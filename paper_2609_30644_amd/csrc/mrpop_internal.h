@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -102,6 +103,11 @@ struct mrpop_ctx {
   // hit token.
   uint32_t *small_arrived = nullptr;
   uint32_t small_tokens = 0;
+  // Blocks that finished plans returned (device arenas, pinned host blocks),
+  // kept for the next plans so that a plan allocates and frees nothing.
+  std::mutex pool_mu;
+  std::vector<std::pair<void *, size_t>> pool_dev, pool_pin;
+  size_t pool_dev_bytes = 0, pool_pin_bytes = 0;
 };
 
 namespace mrpop {
@@ -124,6 +130,10 @@ struct mrpop_scene {
   std::vector<float> q_lo, q_hi;   // [D]
   std::vector<int32_t> nj;         // per arm
   int32_t n_robots = 0, dof = 0, total_spheres = 0;
+  // one-arm sub-scenes of the roadmaps, built by the first plan that needs
+  // them and kept until the scene is destroyed (a new environment makes a new
+  // scene); read-only, shared by every plan on the scene
+  mutable std::vector<mrpop_scene *> arm_cache;
 };
 
 namespace mrpop {
@@ -134,6 +144,15 @@ mrpop_status fail(mrpop_ctx *ctx, mrpop_status st, const std::string &msg);
 mrpop_status hip_fail(mrpop_ctx *ctx, hipError_t e, const char *what);
 // Ensure scratch slot `slot` holds at least `bytes`.
 mrpop_status scratch(mrpop_ctx *ctx, int slot, size_t bytes, void **out);
+// A device (pinned = false) or pinned host block of at least `bytes` from the
+// context's pool (a kept block up to about twice the size), else newly
+// allocated; *got is its size, to be given back to pool_free.  Safe from
+// several threads.  Contents are arbitrary.
+hipError_t pool_alloc(mrpop_ctx *ctx, bool pinned, size_t bytes, void **out, size_t *got);
+// Returns a block to the pool, which keeps at most kPoolKeepDev / kPoolKeepPin
+// bytes and frees the oldest blocks beyond that.  No queued work may use it.
+void pool_free(mrpop_ctx *ctx, bool pinned, void *p, size_t bytes);
+constexpr size_t kPoolKeepDev = size_t(1) << 30, kPoolKeepPin = size_t(64) << 20;
 
 // Kernel launchers (host functions defined next to their kernels).
 hipError_t launch_fk_spheres(const SceneDev &sc, const float *q, int64_t n_cfg, float *out, hipStream_t s);

@@ -82,7 +82,7 @@ class PlanJob {
   std::vector<float> best_path_;
   std::vector<Incumbent> history_;
   std::vector<int32_t> h_qoff_, h_nj_, rm_n_;
-  std::vector<mrpop_scene *> arms_;
+  std::vector<mrpop_scene *> arms_;  // the scene's cached one-arm sub-scenes (not owned)
   size_t device_bytes_ = 0;
 
   // device arena
@@ -108,6 +108,9 @@ class PlanJob {
     uint8_t valid2[8];
   };
   Pinned *pin_ = nullptr;
+  void *host_block_ = nullptr;  // pin_, pin_rm_, pin_cnt_, upload_, upload_i_ (one pooled pinned block)
+  size_t arena_got_ = 0, host_got_ = 0;
+  bool synced_ = true;  // false while run() may have queued work not yet waited for
   int32_t *pin_rm_ = nullptr;   // [R][kRmInts] copy of rm_i_, then [R] vertex counts
   uint64_t *pin_cnt_ = nullptr; // [R][16] copy of the arms' validation counters
   float *upload_ = nullptr;  // qs, qg, roadmap seeds [R][2][kRmStride]

@@ -249,15 +249,12 @@ class PlainExec : public Exec {
 };
 
 PlanJob::~PlanJob() {
-  for (mrpop_scene *a : arms_)
-    if (a) mrpop_scene_destroy(a);
-  if (arena_) (void)hipFree(arena_);
-  if (pin_) (void)hipHostFree(pin_);
-  if (upload_) (void)hipHostFree(upload_);
-  if (upload_i_) (void)hipHostFree(upload_i_);
+  // the blocks go back to the pool only once no queued work uses them: run()
+  // ends with a synchronisation; a run that returned early is waited for here
+  if (!synced_ && (arena_ || host_block_)) (void)hipDeviceSynchronize();
+  if (arena_) pool_free(ctx_, false, arena_, arena_got_);
+  if (host_block_) pool_free(ctx_, true, host_block_, host_got_);
   if (pin_path_) (void)hipHostFree(pin_path_);
-  if (pin_rm_) (void)hipHostFree(pin_rm_);
-  if (pin_cnt_) (void)hipHostFree(pin_cnt_);
 }
 
 double PlanJob::elapsed_() const { return now_s() - t_start_; }
@@ -366,24 +363,27 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   const int R = R_, D = D_;
   const size_t arena_bytes = plan_arena_(nullptr);
   hipError_t e = hipSetDevice(ctx->device);
-  if (e == hipSuccess) e = hipMalloc(&arena_, arena_bytes);
+  if (e == hipSuccess) e = pool_alloc(ctx, false, arena_bytes, &arena_, &arena_got_);
   if (e != hipSuccess) {
     arena_ = nullptr;
     return e == hipErrorOutOfMemory ? fail_(MRPOP_E_NOMEM, "plan: device memory") : hip_fail_(e, "hipMalloc(plan)");
   }
   plan_arena_(arena_);
   device_bytes_ = arena_bytes;
-  if ((e = hipHostMalloc((void **)&pin_, sizeof(Pinned))) != hipSuccess) return hip_fail_(e, "hipHostMalloc");
-  std::memset(pin_, 0, sizeof(Pinned));  // round numbers start at 1, so no stale record matches
-  if ((e = hipHostMalloc((void **)&pin_rm_, sizeof(int32_t) * (size_t)R * (kRmInts + 1))) != hipSuccess)
-    return hip_fail_(e, "hipHostMalloc");
-  if ((e = hipHostMalloc((void **)&pin_cnt_, sizeof(uint64_t) * (size_t)R * 16)) != hipSuccess)
-    return hip_fail_(e, "hipHostMalloc");
+  // the small pinned buffers share one block (256-byte aligned parts)
   const size_t up_floats = 2 * (size_t)D + (size_t)R * 2 * kRmStride;
-  if ((e = hipHostMalloc((void **)&upload_, sizeof(float) * up_floats)) != hipSuccess)
+  ArenaPlan hp;
+  hp.add(&pin_, 1);
+  hp.add(&pin_rm_, (size_t)R * (kRmInts + 1));
+  hp.add(&pin_cnt_, (size_t)R * 16);
+  hp.add(&upload_, up_floats);
+  hp.add(&upload_i_, 4 * (size_t)R + 4);
+  if ((e = pool_alloc(ctx, true, hp.total(), &host_block_, &host_got_)) != hipSuccess) {
+    host_block_ = nullptr;
     return hip_fail_(e, "hipHostMalloc");
-  if ((e = hipHostMalloc((void **)&upload_i_, sizeof(int32_t) * (4 * (size_t)R + 4))) != hipSuccess)
-    return hip_fail_(e, "hipHostMalloc");
+  }
+  hp.assign(host_block_);
+  std::memset(pin_, 0, sizeof(Pinned));  // round numbers start at 1, so no stale record matches
 
   h_qoff_.assign(R, 0);
   h_nj_.assign(R, 0);
@@ -411,9 +411,20 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   upload_i_[4 * R] = 0;  // union-find parents of vertices 0 and 1
   upload_i_[4 * R + 1] = 1;
   arms_.assign(R, nullptr);
-  for (int r = 0; r < R && !P.direct; ++r) {  // one-arm scenes of the roadmaps
-    mrpop_status a = arm_scene(ctx, scene, r, &arms_[r]);
-    if (a != MRPOP_OK) return fail_(a, "plan: arm scene: " + ctx->last_error);
+  if (!P.direct && (int)scene->arm_cache.size() != R) {  // one-arm scenes of the roadmaps, once per scene
+    std::vector<mrpop_scene *> built(R, nullptr);
+    for (int r = 0; r < R; ++r) {
+      mrpop_status a = arm_scene(ctx, scene, r, &built[r]);
+      if (a != MRPOP_OK) {
+        for (mrpop_scene *b : built) mrpop_scene_destroy(b);
+        return fail_(a, "plan: arm scene: " + ctx->last_error);
+      }
+    }
+    for (mrpop_scene *old : scene->arm_cache) mrpop_scene_destroy(old);
+    scene->arm_cache = built;
+  }
+  for (int r = 0; r < R && !P.direct; ++r) {
+    arms_[r] = scene->arm_cache[r];
     device_bytes_ += arms_[r]->blob_bytes;
   }
   rm_n_.assign(R, 2);
@@ -632,6 +643,7 @@ void PlanJob::set_incumbent(const std::vector<float> &path) {
 mrpop_status PlanJob::run(Exec &ex) {
   const int R = R_, D = D_, PC = PC_;
   t_start_ = now_s();
+  synced_ = false;
   // uploads (independent copies into distinct buffers) and the endpoints
   std::vector<Cmd> grp;
   auto add_copy = [&](void *dst, const void *src, size_t bytes) {
@@ -760,6 +772,7 @@ mrpop_status PlanJob::run(Exec &ex) {
     if (P_.stop_at_first && !best_path_.empty()) break;
   }
   SYNC();  // a failure of queued work is reported here at the latest
+  synced_ = true;
   st_.rounds = rnd;
   st_.iterations = it;
   for (int r = 0; r < R && !P_.direct; ++r) st_.roadmap_vertices += rm_n_[r];

@@ -580,20 +580,17 @@ mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
       if (np[r] > 0)
         TRY(validate_(ex, arms_[r], pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r],
                       np[r], P_.resolution, pair_valid_ + off[r], cnt_ + (size_t)(2 + r) * 16, pair_codes_ + off[r]));
-    for (int r : todo)
-      if (np[r] > 0) {
-        add(Op::RmAddEdges).rm_add_edges =
-            RmAddEdgesArgs{pair_ids_ + 2 * (size_t)off[r], pair_valid_ + off[r], ri(r, 2), np[r],
-                           rm_edges_ + (size_t)r * edge_cap_ * 2, rm_ne_ + r, edge_cap_};
-        grew[r] = 1;
-      }
-    TRY(group_(ex, grp));
-    for (int r : todo)
-      add(Op::RmUnion).rm_union = RmUnionArgs{pair_ids_ + 2 * (size_t)off[r], pair_valid_ + off[r], ri(r, 2), np[r],
-                                              rm_n_[r], uf_ + (size_t)r * rm_cap_, ri(r, 3)};
-    TRY(group_(ex, grp));
-    add_copy(pin_rm_, rm_i_, sizeof(int32_t) * (size_t)R * kRmInts);
-    add_copy(pin_cnt_, cnt_ + 2 * 16, sizeof(uint64_t) * 16 * (size_t)R);
+    // new edges and the union of components in one launch, which also writes
+    // each arm's connectivity and validation counters to pinned memory
+    for (int r : todo) {
+      if (np[r] > 0) grew[r] = 1;
+      add(Op::RmUnion).rm_union =
+          RmUnionArgs{pair_ids_ + 2 * (size_t)off[r], pair_valid_ + off[r], ri(r, 2), np[r], rm_n_[r],
+                      uf_ + (size_t)r * rm_cap_, ri(r, 3),
+                      np[r] > 0 ? rm_edges_ + (size_t)r * edge_cap_ * 2 : nullptr, rm_ne_ + r, edge_cap_,
+                      pin_rm_ + (size_t)r * kRmInts + 3, np[r] > 0 ? cnt_ + (size_t)(2 + r) * 16 : nullptr,
+                      pin_cnt_ + (size_t)r * 16};
+    }
     TRY(group_(ex, grp));
     SYNC();
     bool all = true;

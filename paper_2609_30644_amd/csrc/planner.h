@@ -189,21 +189,17 @@ struct RmPairsArgs {
   int32_t *codes;         // or null: [cap] state-count code of each written pair
 };
 
-struct RmAddEdgesArgs {
-  const int32_t *pair_ids;
-  const uint8_t *valid;
-  const int32_t *n_pairs;
-  int max_pairs;
-  int32_t *edges, *n_edges;
-  int cap_edges;
-};
-
 struct RmUnionArgs {
   const int32_t *pair_ids;
   const uint8_t *valid;
   const int32_t *n_pairs;
   int max_pairs, n_v;
   int32_t *parent, *connected;
+  int32_t *edges, *n_edges;  // or null: the valid pairs are appended to the edge list [cap_edges][2]
+  int cap_edges;
+  int32_t *connected_out;    // or null: a second copy of the connectivity flag (e.g. pinned host memory)
+  const uint64_t *cnt;       // or null: the arm's validation counters [16], copied to cnt_out
+  uint64_t *cnt_out;
 };
 
 struct RmBfsArgs {
@@ -236,7 +232,6 @@ hipError_t launch_tree_root(const TreeRootArgs &a, hipStream_t s);
 hipError_t launch_rm_sample(const RmSampleArgs &a, hipStream_t s);
 hipError_t launch_rm_accept(const RmAcceptArgs &a, hipStream_t s);
 hipError_t launch_rm_pairs(const RmPairsArgs &a, hipStream_t s);
-hipError_t launch_rm_add_edges(const RmAddEdgesArgs &a, hipStream_t s);
 hipError_t launch_rm_csr_bfs(const RmBfsArgs &a, hipStream_t s);
 hipError_t launch_rm_union(const RmUnionArgs &a, hipStream_t s);
 hipError_t launch_fill(const FillArgs &a, hipStream_t s);
@@ -250,9 +245,9 @@ uint64_t roadmap_key(uint64_t seed, uint64_t stream_a, uint64_t stream_b);
 // needs, records that need fewer leave early).
 enum class Op : uint8_t {
   Sample, Nearest, Extend, Steer, Select, Path, TreeRoot,
-  RmSample, RmAccept, RmPairs, RmAddEdges, RmBfs, RmUnion, Fill, Copy, SampleNear, InsertConn, Validate
+  RmSample, RmAccept, RmPairs, RmBfs, RmUnion, Fill, Copy, SampleNear, InsertConn, Validate
 };
-constexpr int kNumOps = 18;
+constexpr int kNumOps = 17;
 constexpr int kUfMaxVertices = 32768;  // roadmap vertices per arm (union-find in LDS)
 
 // Blocks one record needs (0: nothing to do).
@@ -292,7 +287,6 @@ struct Cmd {
     RmSampleArgs rm_sample;
     RmAcceptArgs rm_accept;
     RmPairsArgs rm_pairs;
-    RmAddEdgesArgs rm_add_edges;
     RmBfsArgs rm_bfs;
     RmUnionArgs rm_union;
     FillArgs fill;

@@ -790,21 +790,6 @@ __device__ __forceinline__ void rm_pairs_body(const RmPairsArgs &A, int bx) {
   }
 }
 
-// Append the valid pairs to the arm's edge list.
-__device__ __forceinline__ void rm_add_edges_body(const RmAddEdgesArgs &A, int bx) {
-  const int32_t *pair_ids = A.pair_ids, *n_pairs = A.n_pairs;
-  const uint8_t *valid = A.valid;
-  const int cap_pairs = A.max_pairs, cap_edges = A.cap_edges;
-  int32_t *edges = A.edges, *n_edges = A.n_edges;
-
-  const int k = bx * blockDim.x + threadIdx.x;
-  const int np = *n_pairs < cap_pairs ? *n_pairs : cap_pairs;
-  if (k >= np || !valid[k]) return;
-  const int e = atomicAdd(n_edges, 1);
-  if (e >= cap_edges) return;
-  edges[2 * e] = pair_ids[2 * k];
-  edges[2 * e + 1] = pair_ids[2 * k + 1];
-}
 
 // Single workgroup: union-find over the arm's roadmap (parent pointers, a
 // vertex's parent never has a larger index, so a component's root is its
@@ -828,8 +813,25 @@ __device__ __forceinline__ void rm_union_body(const RmUnionArgs &A, int bx) {
   __shared__ int32_t par[kUfMax];
   const int nv = A.n_v < kUfMax ? A.n_v : kUfMax;
   for (int v = threadIdx.x; v < nv; v += blockDim.x) par[v] = A.parent[v];
-  __syncthreads();
   const int np = *A.n_pairs < A.max_pairs ? *A.n_pairs : A.max_pairs;
+  if (A.edges) {  // the valid pairs appended to the edge list, one counter update per wave
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int k0 = 0; k0 < np; k0 += blockDim.x) {
+      const int k = k0 + threadIdx.x;
+      const bool v = k < np && A.valid[k];
+      const uint64_t m = __ballot(v);
+      if (m == 0ull) continue;
+      int base = 0;
+      if (lane == 0) base = atomicAdd(A.n_edges, __popcll(m));
+      base = __shfl(base, 0, kWave);
+      if (!v) continue;
+      const int e = base + __popcll(m & ((1ull << lane) - 1ull));
+      if (e >= A.cap_edges) continue;
+      A.edges[2 * e] = A.pair_ids[2 * k];
+      A.edges[2 * e + 1] = A.pair_ids[2 * k + 1];
+    }
+  }
+  __syncthreads();
   for (int k = threadIdx.x; k < np; k += blockDim.x) {
     if (!A.valid[k]) continue;
     int a = A.pair_ids[2 * k], b = A.pair_ids[2 * k + 1];
@@ -844,7 +846,12 @@ __device__ __forceinline__ void rm_union_body(const RmUnionArgs &A, int bx) {
   }
   __syncthreads();
   for (int v = threadIdx.x; v < nv; v += blockDim.x) A.parent[v] = uf_find(par, v);
-  if (threadIdx.x == 0) *A.connected = (nv > 1 && uf_find(par, 1) == uf_find(par, 0)) ? 1 : 0;
+  if (threadIdx.x == 0) {
+    const int32_t c = (nv > 1 && uf_find(par, 1) == uf_find(par, 0)) ? 1 : 0;
+    *A.connected = c;
+    if (A.connected_out) *A.connected_out = c;
+  }
+  if (A.cnt && A.cnt_out && threadIdx.x < 16) A.cnt_out[threadIdx.x] = A.cnt[threadIdx.x];
 }
 
 // Single workgroup: rebuild the arm's adjacency (CSR) from its edge list
@@ -975,7 +982,6 @@ MRPOP_OP_KERNELS(tree_root, TreeRootArgs, 128)
 MRPOP_OP_KERNELS(rm_sample, RmSampleArgs, 256)
 MRPOP_OP_KERNELS(rm_accept, RmAcceptArgs, 1024)
 MRPOP_OP_KERNELS(rm_pairs, RmPairsArgs, 256)
-MRPOP_OP_KERNELS(rm_add_edges, RmAddEdgesArgs, 256)
 MRPOP_OP_KERNELS(rm_csr_bfs, RmBfsArgs, 1024)
 MRPOP_OP_KERNELS(rm_union, RmUnionArgs, 1024)
 MRPOP_OP_KERNELS(fill, FillArgs, 256)
@@ -1006,7 +1012,6 @@ int op_blocks(Op op, const void *p) {
       const RmPairsArgs &a = *(const RmPairsArgs *)p;
       return clamp_blocks(a.i1 - a.i0);
     }
-    case Op::RmAddEdges: return clamp_blocks((((const RmAddEdgesArgs *)p)->max_pairs + 255) / 256);
     case Op::RmBfs: return 1;
     case Op::RmUnion: return 1;
     case Op::Fill: return (int)std::min<int64_t>((((const FillArgs *)p)->n + 255) / 256, kCopyBlocksMax);
@@ -1030,7 +1035,6 @@ size_t op_args_bytes(Op op) {
     case Op::RmSample: return sizeof(RmSampleArgs);
     case Op::RmAccept: return sizeof(RmAcceptArgs);
     case Op::RmPairs: return sizeof(RmPairsArgs);
-    case Op::RmAddEdges: return sizeof(RmAddEdgesArgs);
     case Op::RmBfs: return sizeof(RmBfsArgs);
     case Op::RmUnion: return sizeof(RmUnionArgs);
     case Op::Fill: return sizeof(FillArgs);
@@ -1088,7 +1092,6 @@ static hipError_t launch_group_any(Op op, const void *const *recs, int n, int gr
     MRPOP_GROUP_CASE(RmSample, rm_sample, RmSampleArgs)
     MRPOP_GROUP_CASE(RmAccept, rm_accept, RmAcceptArgs)
     MRPOP_GROUP_CASE(RmPairs, rm_pairs, RmPairsArgs)
-    MRPOP_GROUP_CASE(RmAddEdges, rm_add_edges, RmAddEdgesArgs)
     MRPOP_GROUP_CASE(RmBfs, rm_csr_bfs, RmBfsArgs)
     MRPOP_GROUP_CASE(RmUnion, rm_union, RmUnionArgs)
     MRPOP_GROUP_CASE(Fill, fill, FillArgs)
@@ -1112,7 +1115,6 @@ static hipError_t launch_any(Op op, const void *p, bool batch, int count, int gr
     MRPOP_OP_CASE(RmSample, rm_sample, RmSampleArgs)
     MRPOP_OP_CASE(RmAccept, rm_accept, RmAcceptArgs)
     MRPOP_OP_CASE(RmPairs, rm_pairs, RmPairsArgs)
-    MRPOP_OP_CASE(RmAddEdges, rm_add_edges, RmAddEdgesArgs)
     MRPOP_OP_CASE(RmBfs, rm_csr_bfs, RmBfsArgs)
     MRPOP_OP_CASE(RmUnion, rm_union, RmUnionArgs)
     MRPOP_OP_CASE(Fill, fill, FillArgs)
@@ -1163,7 +1165,6 @@ hipError_t launch_tree_root(const TreeRootArgs &a, hipStream_t s) { return launc
 hipError_t launch_rm_sample(const RmSampleArgs &a, hipStream_t s) { return launch_op(Op::RmSample, &a, s); }
 hipError_t launch_rm_accept(const RmAcceptArgs &a, hipStream_t s) { return launch_op(Op::RmAccept, &a, s); }
 hipError_t launch_rm_pairs(const RmPairsArgs &a, hipStream_t s) { return launch_op(Op::RmPairs, &a, s); }
-hipError_t launch_rm_add_edges(const RmAddEdgesArgs &a, hipStream_t s) { return launch_op(Op::RmAddEdges, &a, s); }
 hipError_t launch_rm_csr_bfs(const RmBfsArgs &a, hipStream_t s) { return launch_op(Op::RmBfs, &a, s); }
 hipError_t launch_rm_union(const RmUnionArgs &a, hipStream_t s) { return launch_op(Op::RmUnion, &a, s); }
 hipError_t launch_fill(const FillArgs &a, hipStream_t s) { return launch_op(Op::Fill, &a, s); }

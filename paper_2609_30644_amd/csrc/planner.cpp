@@ -539,12 +539,15 @@ mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
         for (int r : act)  // consecutive validations: one launch over the arms
           TRY(validate_(ex, arms_[r], cand(r), cand(r), cand_batch_, 1.0f, candv(r), cnt_ + (size_t)(2 + r) * 16,
                         cand_codes_ + (size_t)r * cand_batch_));
-        for (int r : act)
-          add(Op::RmAccept).rm_accept = RmAcceptArgs{cand(r), candv(r), cand_batch_, h_nj_[r], need[r], V(r),
-                                                     rm_nv_ + r, rm_cap_, ri(r, 0), uf_ + (size_t)r * rm_cap_};
-        TRY(group_(ex, grp));
       }
-      for (int r : counted) add(Op::Fill).fill = FillArgs{(uint32_t *)ri(r, 1), 0u, 2};
+      // acceptance (arms without samples this pass accept none), which also
+      // zeroes the pair counters of every counted arm
+      for (int r : counted) {
+        const bool sampled = need[r] > 0;
+        add(Op::RmAccept).rm_accept =
+            RmAcceptArgs{cand(r), candv(r), sampled ? cand_batch_ : 0, h_nj_[r], sampled ? need[r] : 0, V(r),
+                         rm_nv_ + r, rm_cap_, ri(r, 0), uf_ + (size_t)r * rm_cap_, ri(r, 1)};
+      }
       TRY(group_(ex, grp));
       for (int r : counted)
         add(Op::RmPairs).rm_pairs = RmPairsArgs{V(r), n0[r], n0[r] + need0[r], h_nj_[r], P_.delta, ri(r, 1), 0,

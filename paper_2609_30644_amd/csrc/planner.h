@@ -174,6 +174,7 @@ struct RmAcceptArgs {
   int cap;
   int32_t *taken;
   int32_t *parent;  // union-find parent of every roadmap vertex
+  int32_t *zero2;   // or null: two counters set to zero first (the arm's pair counts)
 };
 
 struct RmPairsArgs {

@@ -695,6 +695,7 @@ __device__ __forceinline__ void rm_accept_body(const RmAcceptArgs &A, int bx) {
   __shared__ int32_t wsum[1024 / kWave];
   __shared__ int32_t base;
   if (threadIdx.x == 0) base = 0;
+  if (threadIdx.x < 2 && A.zero2) A.zero2[threadIdx.x] = 0;
   __syncthreads();
   for (int i0 = 0; i0 < n; i0 += blockDim.x) {
     const int i = i0 + threadIdx.x;

@@ -62,7 +62,10 @@ typedef struct mrpop_scene mrpop_scene;
 /* ------------------------------------------------------------------------ */
 
 /* Create a context bound to HIP device `device`.  The context owns the
- * library's device scratch (grown on demand, freed by destroy). */
+ * library's device scratch (grown on demand, freed by destroy).  It also
+ * keeps the buffers of finished plans for later plans (at most 1 GiB of
+ * device memory and 64 MiB of pinned host memory), so that a plan allocates
+ * nothing per call once the pool is warm; destroy frees them. */
 mrpop_status mrpop_ctx_create(int device, mrpop_ctx **out);
 void mrpop_ctx_destroy(mrpop_ctx *ctx);
 /* Message of the last failed call on `ctx` ("" if none).  Valid until the
@@ -107,6 +110,8 @@ typedef struct {
  * E_NONFINITE, E_NOMEM. */
 mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32_t n_robots,
                                 const mrpop_env *env, mrpop_scene **out);
+/* Frees the scene, with the one-arm sub-scenes that its first roadmap plan
+ * built and kept for later plans.  No plan may be running on the scene. */
 void mrpop_scene_destroy(mrpop_scene *scene);
 
 /* Replace a scene's obstacles (paper, Sec. "Hardware Deployment": replanning

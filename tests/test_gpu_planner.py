@@ -350,6 +350,35 @@ def test_scene_set_env_parity(ctx):
     print(f"  {stats}", flush=True)
 
 
+def test_plans_reuse_buffers_and_sub_scenes(ctx):
+    """Plans take their buffers from the context's pool and the roadmaps'
+    one-arm sub-scenes from the scene: a plan repeated after plans of other
+    sizes (stale pooled contents) is identical, and after set_env a plan on
+    the same scene equals one on a fresh scene of the new environment (the
+    sub-scenes are rebuilt)."""
+    p1, p2 = problem("c1"), problem("c2")
+    s1, s2 = _scene(ctx, p1.scene), _scene(ctx, p2.scene)
+    a = s1.plan(p1.q_start, p1.q_goal, **PARAMS)
+    s2.plan(p2.q_start, p2.q_goal, raise_on_error=False, **PARAMS)
+    b = s1.plan(p1.q_start, p1.q_goal, **PARAMS)
+    assert a.status == b.status == "OK"
+    assert np.array_equal(a.path, b.path) and a.cost == b.cost and a.stats["costs"] == b.stats["costs"]
+    for key in ("rounds", "edge_states", "roadmap_edge_states", "roadmap_vertices"):
+        assert a.stats[key] == b.stats[key], key
+    other = W.scene_c1(5)
+    new = p1.scene.with_env(other.env_spheres, p1.scene.env_boxes)
+    ok = oracle.states_free(new, np.stack([p1.q_start, p1.q_goal]))
+    if not ok.all():
+        pytest.skip("the new obstacles cover an endpoint")
+    s1.set_env(new.env_spheres, new.env_boxes)
+    c = s1.plan(p1.q_start, p1.q_goal, raise_on_error=False, **PARAMS)
+    d = _scene(ctx, new).plan(p1.q_start, p1.q_goal, raise_on_error=False, **PARAMS)
+    assert c.status == d.status
+    if c.status == "OK":
+        assert np.array_equal(c.path, d.path) and c.cost == d.cost
+        _check_path(new, c, p1.q_start, p1.q_goal, PARAMS)
+
+
 def test_replan_tick(ctx):
     """mrpop_replan through the C ABI: an unchanged environment keeps the
     previous path (never worse); an obstacle placed on it (set_env) discards

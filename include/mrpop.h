@@ -415,7 +415,10 @@ typedef struct {
   int64_t flushes, launches;
 } mrpop_server_stats;
 
-/* Starts the server's scheduling thread.  E_INVALID_ARG for a bad config. */
+/* Starts the server's scheduling thread.  E_INVALID_ARG for a bad config.
+ * The server uses the context (and the scenes of its requests) from that
+ * thread until it is destroyed: meanwhile, only the mrpop_server_* calls may
+ * be made on them. */
 mrpop_status mrpop_server_create(mrpop_ctx *ctx, const mrpop_server_config *cfg, mrpop_server **out);
 /* Finishes running requests, drops queued ones (they stay PENDING) and stops. */
 void mrpop_server_destroy(mrpop_server *srv);

@@ -688,20 +688,22 @@ mrpop_status PlanJob::run(Exec &ex) {
       if (n_t[a] > n_t[1 - a]) a = 1 - a;
       const int b = 1 - a;
       const float cb = c_best_;
-      SUBMIT(Op::SampleNear, sample_near,
-             SampleNearArgs{SampleArgs{PC, D, cb, P_.seed, (uint64_t)rnd, 0, scene_->dev.q_lo, scene_->dev.q_hi, qs_,
-                                       qg_, tq_[a], tcap_, q_rand_, c_rand_},
-                            NearestArgs{tq_[a], tg_[a], n_t[a], D, 1, tcap_, q_rand_, D,
-                                        cb < INFINITY ? c_rand_ : nullptr, PC, near_idx_}});
-      if (P_.direct)
+      const SampleNearArgs sn{SampleArgs{PC, D, cb, P_.seed, (uint64_t)rnd, 0, scene_->dev.q_lo, scene_->dev.q_hi,
+                                         qs_, qg_, tq_[a], tcap_, q_rand_, c_rand_},
+                              NearestArgs{tq_[a], tg_[a], n_t[a], D, 1, tcap_, q_rand_, D,
+                                          cb < INFINITY ? c_rand_ : nullptr, PC, near_idx_}};
+      if (P_.direct) {
+        SUBMIT(Op::SampleNear, sample_near, sn);
         SUBMIT(Op::Steer, steer,
                SteerArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a], tg_[a], tcap_,
                          P_.step, q_new_, vid_new_, g_new_, alive_, ea_, eb_, P_.resolution, codes_ext_});
-      else
-        SUBMIT(Op::Extend, extend,
-               ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a], tvid_[a], tg_[a],
-                          tcap_, rm_V_, rm_rowptr_, rm_col_, rm_cap_, col_cap_, d_nj_, d_qoff_, q_new_, vid_new_,
-                          g_new_, alive_, ea_, eb_, P_.resolution, codes_ext_});
+      } else {
+        SUBMIT(Op::SampleNearExtend, sample_near_extend,
+               SampleNearExtendArgs{sn, ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr,
+                                                   tq_[a], tvid_[a], tg_[a], tcap_, rm_V_, rm_rowptr_, rm_col_,
+                                                   rm_cap_, col_cap_, d_nj_, d_qoff_, q_new_, vid_new_, g_new_,
+                                                   alive_, ea_, eb_, P_.resolution, codes_ext_}});
+      }
       TRY(validate_(ex, scene_, ea_, eb_, PC, P_.resolution, valid_, cnt_, codes_ext_));
       SUBMIT(Op::InsertConn, insert_conn,
              InsertConnArgs{InsertArgs{PC, D, R, alive_, valid_, q_new_, g_new_, vid_new_, near_idx_, tq_[a], tg_[a],

@@ -134,6 +134,13 @@ struct SampleNearArgs {
   NearestArgs q;
 };
 
+// Sample, nearest vertex and roadmap extension of each candidate in one
+// launch (e.n == sn.s.n; e.near_idx is sn.q's output).
+struct SampleNearExtendArgs {
+  SampleNearArgs sn;
+  ExtendArgs e;
+};
+
 struct InsertConnArgs {
   InsertArgs ins;
   NearestArgs q;
@@ -246,9 +253,9 @@ uint64_t roadmap_key(uint64_t seed, uint64_t stream_a, uint64_t stream_b);
 // needs, records that need fewer leave early).
 enum class Op : uint8_t {
   Sample, Nearest, Extend, Steer, Select, Path, TreeRoot,
-  RmSample, RmAccept, RmPairs, RmBfs, RmUnion, Fill, Copy, SampleNear, InsertConn, Validate
+  RmSample, RmAccept, RmPairs, RmBfs, RmUnion, Fill, Copy, SampleNear, SampleNearExtend, InsertConn, Validate
 };
-constexpr int kNumOps = 17;
+constexpr int kNumOps = 18;
 constexpr int kUfMaxVertices = 32768;  // roadmap vertices per arm (union-find in LDS)
 
 // Blocks one record needs (0: nothing to do).
@@ -293,6 +300,7 @@ struct Cmd {
     FillArgs fill;
     CopyArgs copy;
     SampleNearArgs sample_near;
+    SampleNearExtendArgs sample_near_extend;
     InsertConnArgs insert_conn;
     ValidateReq val;
   };

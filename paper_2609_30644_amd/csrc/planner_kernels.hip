@@ -251,10 +251,8 @@ __device__ __forceinline__ void nearest_body(const NearestArgs &a, int bx) {
 // to validate (q_near -> q_new); dropped candidates get a null edge at q_near.
 constexpr int kExtendWaves = 4;
 
-__device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int i = bx * kExtendWaves + (int)(threadIdx.x / kWave);
-  if (i >= a.n) return;  // whole waves leave together
+// Candidate i on one wave (no LDS, no barrier).
+__device__ __forceinline__ void extend_one(const ExtendArgs &a, int i, int lane) {
   const int D = a.dim, R = a.n_robots;
   const int near = a.near_idx[i];
   float *ea = a.edge_a + (int64_t)i * D, *eb = a.edge_b + (int64_t)i * D, *qn = a.q_new + (int64_t)i * D;
@@ -379,6 +377,12 @@ __device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
   }
 }
 
+__device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
+  const int i = bx * kExtendWaves + (int)(threadIdx.x / kWave);
+  if (i >= a.n) return;  // whole waves leave together
+  extend_one(a, i, (int)(threadIdx.x & (kWave - 1)));
+}
+
 // Direct mode (no roadmaps): the extension moves from q_near toward q_rand,
 // the whole way if it is at most `step` away, else by `step` along the
 // segment; a candidate that does not move is dropped, and under a finite
@@ -479,6 +483,16 @@ __device__ __forceinline__ void sample_near_body(const SampleNearArgs &a, int bx
   if (threadIdx.x < kWave) sample_one(a.s, bx, (int)threadIdx.x);
   __syncthreads();
   nearest_body(a.q, bx);
+}
+
+// The same, then the candidate's extension along the roadmaps (wave 0); the
+// nearest vertex reaches wave 0 through global memory, ordered by the
+// workgroup barrier.
+__device__ __forceinline__ void sample_near_extend_body(const SampleNearExtendArgs &a, int bx) {
+  if (bx >= a.sn.s.n) return;
+  sample_near_body(a.sn, bx);
+  __syncthreads();
+  if (threadIdx.x < kWave) extend_one(a.e, bx, (int)threadIdx.x);
 }
 
 // Insertion of the surviving candidates (alive and edge-valid) in index
@@ -988,6 +1002,7 @@ MRPOP_OP_KERNELS(rm_union, RmUnionArgs, 1024)
 MRPOP_OP_KERNELS(fill, FillArgs, 256)
 MRPOP_OP_KERNELS(copy, CopyArgs, 256)
 MRPOP_OP_KERNELS(sample_near, SampleNearArgs, 256)
+MRPOP_OP_KERNELS(sample_near_extend, SampleNearExtendArgs, 256)
 MRPOP_OP_KERNELS(insert_conn, InsertConnArgs, 256)
 
 static int clamp_blocks(int64_t b) { return (int)std::min<int64_t>(std::max<int64_t>(b, 0), 0x7fffffff); }
@@ -1018,6 +1033,7 @@ int op_blocks(Op op, const void *p) {
     case Op::Fill: return (int)std::min<int64_t>((((const FillArgs *)p)->n + 255) / 256, kCopyBlocksMax);
     case Op::Copy: return (int)std::min<int64_t>((((const CopyArgs *)p)->bytes + 255) / 256, kCopyBlocksMax);
     case Op::SampleNear: return clamp_blocks(((const SampleNearArgs *)p)->s.n);
+    case Op::SampleNearExtend: return clamp_blocks(((const SampleNearExtendArgs *)p)->sn.s.n);
     case Op::InsertConn: return clamp_blocks(std::max(1, ((const InsertConnArgs *)p)->ins.n));
     case Op::Validate: return 0;
   }
@@ -1041,6 +1057,7 @@ size_t op_args_bytes(Op op) {
     case Op::Fill: return sizeof(FillArgs);
     case Op::Copy: return sizeof(CopyArgs);
     case Op::SampleNear: return sizeof(SampleNearArgs);
+    case Op::SampleNearExtend: return sizeof(SampleNearExtendArgs);
     case Op::InsertConn: return sizeof(InsertConnArgs);
     case Op::Validate: return 0;
   }
@@ -1054,6 +1071,12 @@ static hipError_t op_check(Op op, const void *p) {
   if (op == Op::SampleNear) {
     const SampleNearArgs &a = *(const SampleNearArgs *)p;
     if (a.s.dim > kMaxDof || a.q.dim > kMaxDof || a.q.n_queries != a.s.n) return hipErrorInvalidValue;
+  }
+  if (op == Op::SampleNearExtend) {
+    const SampleNearExtendArgs &a = *(const SampleNearExtendArgs *)p;
+    if (a.sn.s.dim > kMaxDof || a.sn.q.dim > kMaxDof || a.sn.q.n_queries != a.sn.s.n || a.e.n != a.sn.s.n ||
+        a.e.dim > kMaxDof || a.e.near_idx != a.sn.q.out_idx)
+      return hipErrorInvalidValue;
   }
   if (op == Op::InsertConn) {
     const InsertConnArgs &a = *(const InsertConnArgs *)p;
@@ -1098,6 +1121,7 @@ static hipError_t launch_group_any(Op op, const void *const *recs, int n, int gr
     MRPOP_GROUP_CASE(Fill, fill, FillArgs)
     MRPOP_GROUP_CASE(Copy, copy, CopyArgs)
     MRPOP_GROUP_CASE(SampleNear, sample_near, SampleNearArgs)
+    MRPOP_GROUP_CASE(SampleNearExtend, sample_near_extend, SampleNearExtendArgs)
     MRPOP_GROUP_CASE(InsertConn, insert_conn, InsertConnArgs)
     case Op::Validate: return hipErrorInvalidValue;
   }
@@ -1121,6 +1145,7 @@ static hipError_t launch_any(Op op, const void *p, bool batch, int count, int gr
     MRPOP_OP_CASE(Fill, fill, FillArgs)
     MRPOP_OP_CASE(Copy, copy, CopyArgs)
     MRPOP_OP_CASE(SampleNear, sample_near, SampleNearArgs)
+    MRPOP_OP_CASE(SampleNearExtend, sample_near_extend, SampleNearExtendArgs)
     MRPOP_OP_CASE(InsertConn, insert_conn, InsertConnArgs)
     case Op::Validate: return hipErrorInvalidValue;
   }

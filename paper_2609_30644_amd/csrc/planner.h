@@ -233,7 +233,6 @@ struct CopyArgs {
 
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
 hipError_t launch_nearest(const NearestArgs &a, hipStream_t s);
-hipError_t launch_extend(const ExtendArgs &a, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_path(const PathArgs &a, hipStream_t s);
 hipError_t launch_tree_root(const TreeRootArgs &a, hipStream_t s);
@@ -252,10 +251,10 @@ uint64_t roadmap_key(uint64_t seed, uint64_t stream_a, uint64_t stream_b);
 // blockIdx.y of the device array `args`; grid_x = the most blocks any record
 // needs, records that need fewer leave early).
 enum class Op : uint8_t {
-  Sample, Nearest, Extend, Steer, Select, Path, TreeRoot,
+  Sample, Nearest, Steer, Select, Path, TreeRoot,
   RmSample, RmAccept, RmPairs, RmBfs, RmUnion, Fill, Copy, SampleNear, SampleNearExtend, InsertConn, Validate
 };
-constexpr int kNumOps = 18;
+constexpr int kNumOps = 17;
 constexpr int kUfMaxVertices = 32768;  // roadmap vertices per arm (union-find in LDS)
 
 // Blocks one record needs (0: nothing to do).
@@ -287,7 +286,6 @@ struct Cmd {
   union {
     SampleArgs sample;
     NearestArgs nearest;
-    ExtendArgs extend;
     SteerArgs steer;
     SelectArgs select;
     PathArgs path;

@@ -249,9 +249,7 @@ __device__ __forceinline__ void nearest_body(const NearestArgs &a, int bx) {
 // no cosine is positive.  The candidate survives if some arm moves and,
 // under a finite budget, g_near + |q_new - q_near| < c_rand.  Writes the edge
 // to validate (q_near -> q_new); dropped candidates get a null edge at q_near.
-constexpr int kExtendWaves = 4;
-
-// Candidate i on one wave (no LDS, no barrier).
+// One wave per candidate (no LDS, no barrier).
 __device__ __forceinline__ void extend_one(const ExtendArgs &a, int i, int lane) {
   const int D = a.dim, R = a.n_robots;
   const int near = a.near_idx[i];
@@ -375,12 +373,6 @@ __device__ __forceinline__ void extend_one(const ExtendArgs &a, int i, int lane)
     const bool all_finite = __ballot(!finite) == 0ull;
     if (lane == 0) a.n_codes[i] = state_count_code(linf, all_finite, a.res);
   }
-}
-
-__device__ __forceinline__ void extend_body(const ExtendArgs &a, int bx) {
-  const int i = bx * kExtendWaves + (int)(threadIdx.x / kWave);
-  if (i >= a.n) return;  // whole waves leave together
-  extend_one(a, i, (int)(threadIdx.x & (kWave - 1)));
 }
 
 // Direct mode (no roadmaps): the extension moves from q_near toward q_rand,
@@ -989,7 +981,6 @@ struct OpGroup {
 
 MRPOP_OP_KERNELS(sample, SampleArgs, kSampleWaves * kWave)
 MRPOP_OP_KERNELS(nearest, NearestArgs, 256)
-MRPOP_OP_KERNELS(extend, ExtendArgs, kExtendWaves * kWave)
 MRPOP_OP_KERNELS(steer, SteerArgs, kSteerWaves * kWave)
 MRPOP_OP_KERNELS(select, SelectArgs, 256)
 MRPOP_OP_KERNELS(path, PathArgs, 64)
@@ -1014,10 +1005,6 @@ int op_blocks(Op op, const void *p) {
       return clamp_blocks((a.n + kSampleWaves - 1) / kSampleWaves);
     }
     case Op::Nearest: return clamp_blocks(((const NearestArgs *)p)->n_queries);
-    case Op::Extend: {
-      const ExtendArgs &a = *(const ExtendArgs *)p;
-      return clamp_blocks((a.n + kExtendWaves - 1) / kExtendWaves);
-    }
     case Op::Steer: return clamp_blocks((((const SteerArgs *)p)->n + kSteerWaves - 1) / kSteerWaves);
     case Op::Select: return 1;
     case Op::Path: return 1;
@@ -1044,7 +1031,6 @@ size_t op_args_bytes(Op op) {
   switch (op) {
     case Op::Sample: return sizeof(SampleArgs);
     case Op::Nearest: return sizeof(NearestArgs);
-    case Op::Extend: return sizeof(ExtendArgs);
     case Op::Steer: return sizeof(SteerArgs);
     case Op::Select: return sizeof(SelectArgs);
     case Op::Path: return sizeof(PathArgs);
@@ -1108,7 +1094,6 @@ static hipError_t launch_group_any(Op op, const void *const *recs, int n, int gr
   switch (op) {
     MRPOP_GROUP_CASE(Sample, sample, SampleArgs)
     MRPOP_GROUP_CASE(Nearest, nearest, NearestArgs)
-    MRPOP_GROUP_CASE(Extend, extend, ExtendArgs)
     MRPOP_GROUP_CASE(Steer, steer, SteerArgs)
     MRPOP_GROUP_CASE(Select, select, SelectArgs)
     MRPOP_GROUP_CASE(Path, path, PathArgs)
@@ -1132,7 +1117,6 @@ static hipError_t launch_any(Op op, const void *p, bool batch, int count, int gr
   switch (op) {
     MRPOP_OP_CASE(Sample, sample, SampleArgs)
     MRPOP_OP_CASE(Nearest, nearest, NearestArgs)
-    MRPOP_OP_CASE(Extend, extend, ExtendArgs)
     MRPOP_OP_CASE(Steer, steer, SteerArgs)
     MRPOP_OP_CASE(Select, select, SelectArgs)
     MRPOP_OP_CASE(Path, path, PathArgs)
@@ -1184,7 +1168,6 @@ hipError_t launch_nearest(const NearestArgs &a, hipStream_t s) {
   if (a.n_queries > 0x7fffffff) return hipErrorInvalidValue;
   return launch_op(Op::Nearest, &a, s);
 }
-hipError_t launch_extend(const ExtendArgs &a, hipStream_t s) { return launch_op(Op::Extend, &a, s); }
 hipError_t launch_select(const SelectArgs &a, hipStream_t s) { return launch_op(Op::Select, &a, s); }
 hipError_t launch_path(const PathArgs &a, hipStream_t s) { return launch_op(Op::Path, &a, s); }
 hipError_t launch_tree_root(const TreeRootArgs &a, hipStream_t s) { return launch_op(Op::TreeRoot, &a, s); }

@@ -194,6 +194,25 @@ mrpop_status mrpop_validate_edges(mrpop_ctx *ctx, const mrpop_scene *scene, cons
                                   int64_t n_edges, float resolution, const int32_t *n_states_opt,
                                   uint8_t *out_valid, mrpop_validate_stats *stats_opt, void *stream);
 
+/* mrpop_validate_edges for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same bits, with the working memory in
+ * a fixed device array of 6 MiB that the library holds on every GPU it runs
+ * on until the process ends, instead of the context's scratch.  The call
+ * makes no device or pinned allocation and no free; the caller still owns
+ * qa, qb, n_states_opt and out_valid.  Profiling events are not recorded.
+ * Every call on one GPU shares that GPU's array, whichever context makes it:
+ * calls whose work overlaps on one GPU (other streams, other threads,
+ * other contexts) race and must be serialised by the caller.  Nothing in the
+ * array needs clearing between calls (each launch writes every word it reads).
+ * Arguments, layout and statuses as mrpop_validate_edges, plus
+ * E_INVALID_ARG for n_edges > MRPOP_NOALLOC_MAX_EDGES (nothing is queued). */
+#define MRPOP_NOALLOC_MAX_EDGES 65536
+mrpop_status mrpop_validate_edges_noalloc(mrpop_ctx *ctx, const mrpop_scene *scene, const float *qa,
+                                          const float *qb, int64_t n_edges, float resolution,
+                                          const int32_t *n_states_opt, uint8_t *out_valid,
+                                          mrpop_validate_stats *stats_opt, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Search primitives                                                         */
 /* ------------------------------------------------------------------------ */

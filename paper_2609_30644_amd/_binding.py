@@ -181,6 +181,7 @@ def load_library():
     lib.mrpop_scene_tile_mode.restype = I32
     lib.mrpop_fk_spheres.argtypes = [P, P, P, I64, P, P]
     lib.mrpop_validate_edges.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
+    lib.mrpop_validate_edges_noalloc.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
     lib.mrpop_nearest.argtypes = [P, P, P, I64, I32, P, P, I64, P, P]
     lib.mrpop_sample.argtypes = [P, P, P, P, P, C.c_float, C.c_uint64, C.c_uint64, I64, I64, P, P, P]
     lib.mrpop_plan_params_default.argtypes = [P]
@@ -403,6 +404,15 @@ class Scene:
     def validate_edges(self, qa, qb, resolution: float, n_states=None, out=None, stats: bool = False):
         """Edge-valid bits (uint8, 1 = free) on the device; with stats=True
         also returns a ValidateStats (the call then waits for the stream)."""
+        return self._validate(self.ctx._lib.mrpop_validate_edges, qa, qb, resolution, n_states, out, stats)
+
+    def validate_edges_noalloc(self, qa, qb, resolution: float, n_states=None, out=None, stats: bool = False):
+        """As validate_edges, through mrpop_validate_edges_noalloc (the
+        library's fixed device array instead of the context's scratch; at most
+        MRPOP_NOALLOC_MAX_EDGES edges)."""
+        return self._validate(self.ctx._lib.mrpop_validate_edges_noalloc, qa, qb, resolution, n_states, out, stats)
+
+    def _validate(self, fn, qa, qb, resolution, n_states, out, stats):
         torch = _torch()
         a = self.ctx.to_device(qa, torch.float32).reshape(-1, self.dof)
         b = self.ctx.to_device(qb, torch.float32).reshape(-1, self.dof)
@@ -413,7 +423,7 @@ class Scene:
         if out is None:
             out = torch.empty(E, dtype=torch.uint8, device=self.ctx.device)
         st = _ValidateStats()
-        self.ctx.check(self.ctx._lib.mrpop_validate_edges(
+        self.ctx.check(fn(
             self.ctx.handle, self._h, a.data_ptr(), b.data_ptr(), E, float(resolution),
             None if ns is None else ns.data_ptr(), out.data_ptr(), C.byref(st) if stats else None,
             self.ctx.stream()))

@@ -25,7 +25,7 @@ mrpop_status hip_fail(mrpop_ctx *ctx, hipError_t e, const char *what) {
   return fail(ctx, e == hipErrorOutOfMemory ? MRPOP_E_NOMEM : MRPOP_E_DEVICE, msg);
 }
 
-mrpop_status scratch(mrpop_ctx *ctx, int slot, size_t bytes, void **out) {
+mrpop_status scratch_slot(mrpop_ctx *ctx, int slot, size_t bytes, void **out) {
   DeviceBuffer &b = ctx->scratch[slot];
   if (b.bytes < bytes) {
     if (b.ptr) {
@@ -136,6 +136,45 @@ hipError_t small_launch_state(mrpop_ctx *ctx, uint32_t **arrived, uint32_t **fla
 
 }  // namespace mrpop
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of mrpop_validate_edges_noalloc
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = size_t(6) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+
+// Every GPU the library runs on holds its own copy of this array until the
+// process ends.  In host code its name is only a stand-in: the kernels get the
+// device address that hipGetSymbolAddress returns for the current device,
+// taken once per device when the first context on it is created.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// With `device` current: the device address of `scratch` on it (once).
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_noalloc_ptr[device] = p;
+  return hipSuccess;
+}
+
+void *noalloc_scratch_ptr(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  return g_noalloc_ptr[device];
+}
+
+}  // namespace
+
 using namespace mrpop;
 
 extern "C" {
@@ -151,6 +190,8 @@ mrpop_status mrpop_ctx_create(int device, mrpop_ctx **out) {
   if (device < 0 || device >= n) return fail(nullptr, MRPOP_E_INVALID_ARG, "ctx_create: no such device");
   e = hipSetDevice(device);
   if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  e = noalloc_scratch_init(device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
   mrpop_ctx *c = new mrpop_ctx();
   c->device = device;
   *out = c;
@@ -699,40 +740,86 @@ mrpop_status mrpop_fk_spheres(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   return MRPOP_OK;
 }
 
+// Argument checks shared by both validation entry points (the message names
+// the entry point); MRPOP_OK with *done set when there is nothing to do.
+static mrpop_status validate_args(mrpop_ctx *ctx, const mrpop_scene *scene, const float *qa, const float *qb,
+                                  int64_t n_edges, float resolution, const int32_t *n_states_opt,
+                                  uint8_t *out_valid, mrpop_validate_stats *stats_opt, const char *who, bool *done) {
+  *done = false;
+  if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, std::string(who) + ": ctx is NULL");
+  if (!scene || scene->ctx != ctx) return fail(ctx, MRPOP_E_INVALID_ARG, std::string(who) + ": scene not from this ctx");
+  if (n_edges < 0) return fail(ctx, MRPOP_E_INVALID_ARG, std::string(who) + ": n_edges < 0");
+  if (!n_states_opt && !(resolution > 0.f && std::isfinite(resolution)))
+    return fail(ctx, MRPOP_E_INVALID_ARG, std::string(who) + ": resolution must be finite and > 0");
+  if (stats_opt) std::memset(stats_opt, 0, sizeof(*stats_opt));
+  if (n_edges == 0) {
+    *done = true;
+    return MRPOP_OK;
+  }
+  if (!qa || !qb || !out_valid) return fail(ctx, MRPOP_E_INVALID_ARG, std::string(who) + ": NULL buffer");
+  return MRPOP_OK;
+}
+
+// The launch's counters (in ws) into stats_opt; waits for the stream.
+static mrpop_status validate_stats(mrpop_ctx *ctx, const ValidateScratch &ws, hipStream_t s,
+                                   mrpop_validate_stats *stats_opt, const char *who) {
+  uint64_t c[16];
+  hipError_t e = hipMemcpyAsync(c, ws.counters, sizeof(c), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, who);
+  stats_opt->edge_states = (int64_t)c[1];
+  stats_opt->states_checked = (int64_t)c[2];
+  stats_opt->tiles = (int64_t)c[3];
+  stats_opt->nonfinite_edges = (int64_t)c[4];
+  stats_opt->edges_invalid = (int64_t)c[5];
+  for (int i = 0; i < 8; ++i) stats_opt->work[i] = (int64_t)c[8 + i];
+  if (c[6]) return fail(ctx, MRPOP_E_INVALID_ARG, std::string(who) + ": an edge has too many states");
+  return MRPOP_OK;
+}
+
 mrpop_status mrpop_validate_edges(mrpop_ctx *ctx, const mrpop_scene *scene, const float *qa, const float *qb,
                                   int64_t n_edges, float resolution, const int32_t *n_states_opt,
                                   uint8_t *out_valid, mrpop_validate_stats *stats_opt, void *stream) {
-  if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "validate_edges: ctx is NULL");
-  if (!scene || scene->ctx != ctx) return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: scene not from this ctx");
-  if (n_edges < 0) return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: n_edges < 0");
-  if (!n_states_opt && !(resolution > 0.f && std::isfinite(resolution)))
-    return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: resolution must be finite and > 0");
-  if (stats_opt) std::memset(stats_opt, 0, sizeof(*stats_opt));
-  if (n_edges == 0) return MRPOP_OK;
-  if (!qa || !qb || !out_valid) return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: NULL buffer");
+  bool done = false;
+  mrpop_status st = validate_args(ctx, scene, qa, qb, n_edges, resolution, n_states_opt, out_valid, stats_opt,
+                                  "validate_edges", &done);
+  if (st != MRPOP_OK || done) return st;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   void *ws_base = nullptr;
-  mrpop_status st = scratch(ctx, 0, validate_scratch_bytes(n_edges), &ws_base);
+  st = scratch_slot(ctx, 0, validate_scratch_bytes(n_edges), &ws_base);
   if (st != MRPOP_OK) return st;
   ValidateScratch ws = validate_scratch_layout(ws_base, n_edges);
   hipStream_t s = (hipStream_t)stream;
   e = launch_validate(scene->dev, qa, qb, n_edges, resolution, n_states_opt, out_valid, ws, s, profile_slot(ctx),
                       ctx->profiling ? ctx->prof_totals : nullptr, &ctx->last_grid, &ctx->last_block);
   if (e != hipSuccess) return hip_fail(ctx, e, "validate_edges launch");
-  if (stats_opt) {
-    uint64_t c[16];
-    e = hipMemcpyAsync(c, ws.counters, sizeof(c), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "validate_edges stats");
-    stats_opt->edge_states = (int64_t)c[1];
-    stats_opt->states_checked = (int64_t)c[2];
-    stats_opt->tiles = (int64_t)c[3];
-    stats_opt->nonfinite_edges = (int64_t)c[4];
-    stats_opt->edges_invalid = (int64_t)c[5];
-    for (int i = 0; i < 8; ++i) stats_opt->work[i] = (int64_t)c[8 + i];
-    if (c[6]) return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges: an edge has too many states");
-  }
+  if (stats_opt) return validate_stats(ctx, ws, s, stats_opt, "validate_edges stats");
+  return MRPOP_OK;
+}
+
+mrpop_status mrpop_validate_edges_noalloc(mrpop_ctx *ctx, const mrpop_scene *scene, const float *qa,
+                                          const float *qb, int64_t n_edges, float resolution,
+                                          const int32_t *n_states_opt, uint8_t *out_valid,
+                                          mrpop_validate_stats *stats_opt, void *stream) {
+  bool done = false;
+  mrpop_status st = validate_args(ctx, scene, qa, qb, n_edges, resolution, n_states_opt, out_valid, stats_opt,
+                                  "validate_edges_noalloc", &done);
+  if (st != MRPOP_OK || done) return st;
+  if (n_edges > MRPOP_NOALLOC_MAX_EDGES || validate_scratch_bytes(n_edges) > kNoAllocScratchBytes)
+    return fail(ctx, MRPOP_E_INVALID_ARG, "validate_edges_noalloc: more than MRPOP_NOALLOC_MAX_EDGES edges");
+  void *base = noalloc_scratch_ptr(ctx->device);
+  if (!base) return fail(ctx, MRPOP_E_DEVICE, "validate_edges_noalloc: no scratch address for the device");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  // every launch of the general path writes the scratch words it later reads
+  // (counts, offsets, flags, counters, partial sums), so nothing is cleared
+  ValidateScratch ws = validate_scratch_layout(base, n_edges);
+  hipStream_t s = (hipStream_t)stream;
+  e = launch_validate(scene->dev, qa, qb, n_edges, resolution, n_states_opt, out_valid, ws, s, nullptr, nullptr,
+                      nullptr, nullptr);
+  if (e != hipSuccess) return hip_fail(ctx, e, "validate_edges_noalloc launch");
+  if (stats_opt) return validate_stats(ctx, ws, s, stats_opt, "validate_edges_noalloc stats");
   return MRPOP_OK;
 }
 

@@ -143,7 +143,7 @@ mrpop_status fail(mrpop_ctx *ctx, mrpop_status st, const std::string &msg);
 // Map a HIP error to E_DEVICE (or E_NOMEM) with the call site in the message.
 mrpop_status hip_fail(mrpop_ctx *ctx, hipError_t e, const char *what);
 // Ensure scratch slot `slot` holds at least `bytes`.
-mrpop_status scratch(mrpop_ctx *ctx, int slot, size_t bytes, void **out);
+mrpop_status scratch_slot(mrpop_ctx *ctx, int slot, size_t bytes, void **out);
 // A device (pinned = false) or pinned host block of at least `bytes` from the
 // context's pool (a kept block up to about twice the size), else newly
 // allocated; *got is its size, to be given back to pool_free.  Safe from

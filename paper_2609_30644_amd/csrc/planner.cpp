@@ -148,7 +148,7 @@ class PlainExec : public Exec {
     if (v.size() == 1) {
       const ValidateReq &q = v[0];
       void *base = nullptr;
-      if (scratch(ctx_, 1, validate_scratch_bytes(q.n), &base) != MRPOP_OK) return hipErrorOutOfMemory;
+      if (scratch_slot(ctx_, 1, validate_scratch_bytes(q.n), &base) != MRPOP_OK) return hipErrorOutOfMemory;
       ValidateScratch ws = validate_scratch_layout(base, q.n);
       ws.counters = q.counters;
       if (q.n_codes && q.n <= kFusedMaxEdges) {  // counts made by the producer: one launch
@@ -235,8 +235,8 @@ class PlainExec : public Exec {
       const hipError_t e = hipStreamSynchronize(s_);
       if (e != hipSuccess) return e;
     }
-    if (scratch(ctx_, 2, bytes, &d_segs_) != MRPOP_OK) return hipErrorOutOfMemory;
-    if (scratch(ctx_, 3, ws_bytes, &seg_ws_) != MRPOP_OK) return hipErrorOutOfMemory;
+    if (scratch_slot(ctx_, 2, bytes, &d_segs_) != MRPOP_OK) return hipErrorOutOfMemory;
+    if (scratch_slot(ctx_, 3, ws_bytes, &seg_ws_) != MRPOP_OK) return hipErrorOutOfMemory;
     return hipSuccess;
   }
 

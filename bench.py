@@ -44,6 +44,21 @@ F_JOINT, F_XFORM, F_SS, F_SB = 48, 18, 10, 17
 # iterations or max_rounds rounds).
 PLAN = dict(candidates=512, n_roadmap=32, delta=3.0, max_rounds=150, max_iterations=4)
 
+# Time to solution on the 50 two-arm problems: the plain planner with a 5 s
+# budget (first solution only for the time to solution; the whole budget on
+# a few problems for the cost reached).  The oracle's planner runs the same
+# round parameters.
+C1_FIXTURE = os.path.join(ROOT, "tests", "golden", "c1_problems.json")
+C1_PLAN = dict(candidates=128, n_roadmap=32, delta=3.0, max_rounds=100000, max_iterations=100000,
+               time_budget_s=5.0)
+C1_PLAN_ORACLE = dict(candidates=128, n_roadmap=32, delta=3.0, max_rounds=2000, max_iterations=100)
+
+# The 8-arm shelf workload: validation batches (4096 certainly free, 4096
+# unselected; 0.02 rad) and cost-bounded replanning for 30 s.
+C3_FIXTURE = os.path.join(ROOT, "tests", "golden", "c3_bench.json")
+C3_PLAN = dict(candidates=512, n_roadmap=64, delta=3.0, max_rounds=1000000, max_iterations=1000000,
+               max_growth_rounds=64)
+
 # HBM traffic of the tile kernels, from hardware counters (FETCH_SIZE and
 # WRITE_SIZE per dispatch, scaled by what they read for a plain copy of known
 # size).  The summary records a digest of the kernel sources it was taken on;
@@ -102,11 +117,11 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes": n, "copies": 3}), flush=True)
 
 
-def load_workload():
+def load_workload(path=FIXTURE, scene_fn="scene_c2"):
     import workloads as W
-    d = json.load(open(FIXTURE))
-    sc = W.scene_c2(d["scene_seed"]).with_env(np.array(d["env_spheres"], np.float32),
-                                              np.array(d["env_boxes"], np.float32))
+    d = json.load(open(path))
+    sc = getattr(W, scene_fn)(d["scene_seed"]).with_env(np.array(d["env_spheres"], np.float32).reshape(-1, 4),
+                                                        np.array(d["env_boxes"], np.float32).reshape(-1, 6))
     anchors = W.random_configs(sc, d["anchor_draws"], np.random.default_rng([d["anchor_seed"]]))
     anchors = anchors[np.array(d["anchor_free_idx"])]
     qa, qb = W.edge_batch_near(sc, anchors, d["pool"], d["resolution"], d["pool_seed"], d["n_min"], d["n_max"],
@@ -127,11 +142,24 @@ def algorithmic_flops(work: dict, scene) -> float:
             + work["fine_box"] * F_SB + work["fine_rr"] * F_SS)
 
 
-def cpu_baseline(scene, batches, res, target_s: float) -> dict:
+def host_info() -> dict:
+    """Host cores and CPU model of the machine the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"nproc": os.cpu_count(), "affinity_cpus": aff, "cpu_model": model}
+
+
+def checker_rate(scene, batches, res, target_s: float, threads: int) -> dict:
     """The oracle's coarse-to-fine checker (early exit) on a bounded sample of
-    the same two batches, on the host cores."""
+    the same two batches, on `threads` host threads."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
     sc = oracle.OracleScene(scene)
 
     def run(k, passes=1):
@@ -152,9 +180,144 @@ def cpu_baseline(scene, batches, res, target_s: float) -> dict:
         else:
             passes = max(passes + 1, int(passes * target_s / max(dt, 1e-3)))
         states, dt = run(k, passes)
-    return {"value": states / dt, "unit": "edge-states/s", "cores": threads, "kind": "oracle",
+    return {"value": states / dt, "unit": "edge-states/s", "cores": threads,
             "sample": f"{passes} pass(es) over the first {k} edges of each batch ({states} edge-states), "
                       f"FP64 coarse-to-fine checker with early exit, {dt:.1f} s"}
+
+
+def oracle_planner_tts(n_seeds: int) -> dict:
+    """The oracle's planner (Python rounds over the FP64 checker, one
+    thread) on the first C1 problems, first solution only, with the GPU
+    leg's round parameters: time to first solution and solve rate."""
+    import workloads as W
+    from oracle import planner as PL
+    d = json.load(open(C1_FIXTURE))
+    tts, ok = [], 0
+    for pr in d["problems"][:n_seeds]:
+        sc = W.scene_c1(pr["seed"]).with_env(np.array(pr["env_spheres"], np.float32).reshape(-1, 4),
+                                             np.array(pr["env_boxes"], np.float32).reshape(-1, 6))
+        prm = PL.PlanParams(**dict(C1_PLAN_ORACLE, seed=pr["seed"], stop_at_first=True))
+        t0 = time.perf_counter()
+        r = PL.plan(sc, np.array(pr["q_start"], np.float32), np.array(pr["q_goal"], np.float32), prm)
+        dt = time.perf_counter() - t0
+        if r.status == "OK":
+            ok += 1
+            tts.append(dt)
+    return {"problems": n_seeds, "solved": ok, "tts_p50_ms": float(np.median(tts)) * 1e3 if tts else None,
+            "threads": 1, "params": C1_PLAN_ORACLE,
+            "note": "wall time of oracle.planner.plan with stop_at_first (roadmaps, then the initial search)"}
+
+
+def cpu_baseline(scene, batches, res, target_s: float, planner_seeds: int) -> dict:
+    """The oracle on the host cores: its checker on all cores (at most 16
+    threads, the host share of one GPU) and on one thread, and its planner
+    on the first C1 problems."""
+    threads = max(1, min(16, os.cpu_count() or 1))
+    allc = checker_rate(scene, batches, res, target_s / 2, threads)
+    one = checker_rate(scene, batches, res, target_s / 2, 1)
+    out = {"value": allc["value"], "unit": "edge-states/s", "cores": threads, "kind": "oracle",
+           "sample": allc["sample"], "single_thread": one, "host": host_info(),
+           "note": "plain FP64 C checker without SIMD intrinsics, not a vectorised state of the art"}
+    if planner_seeds > 0:
+        out["planner_c1"] = oracle_planner_tts(planner_seeds)
+    return out
+
+
+def check_bits(free_bits: np.ndarray, mixed_bits: np.ndarray, fx: dict) -> dict:
+    """The timed batches' bits against the oracle's classes stored in the
+    fixture: every free-batch edge is certainly free; on the unselected
+    batch every edge outside the band has the oracle's verdict."""
+    cls = np.array(fx["mixed_first_4096_class"])
+    certain = cls != 0
+    bad_mixed = int((mixed_bits[certain] != (cls[certain] == 1)).sum())
+    bad_free = int((free_bits != 1).sum())
+    return {"free_mismatches": bad_free, "mixed_mismatches": bad_mixed, "mixed_band": int((~certain).sum()),
+            "mixed_oracle_free": int((cls == 1).sum()), "ok": bad_free == 0 and bad_mixed == 0}
+
+
+def c1_leg(ctx, n_problems: int, n_full: int) -> dict:
+    """Time to first solution on the two-arm problems (one plan each, seed =
+    problem seed, first solution only), and the cost reached after the whole
+    5 s budget on the first n_full problems."""
+    import workloads as W
+    import paper_2609_30644_amd as M
+    d = json.load(open(C1_FIXTURE))
+    res = d["resolution"]
+    probs = []
+    for pr in d["problems"][:n_problems]:
+        sc = W.scene_c1(pr["seed"]).with_env(np.array(pr["env_spheres"], np.float32).reshape(-1, 4),
+                                             np.array(pr["env_boxes"], np.float32).reshape(-1, 6))
+        probs.append((pr["seed"], M.Scene(ctx, sc), np.array(pr["q_start"], np.float32),
+                      np.array(pr["q_goal"], np.float32)))
+    _, s0, a0, b0 = probs[0]
+    s0.plan(a0, b0, raise_on_error=False, resolution=res, **dict(C1_PLAN, seed=99, stop_at_first=1))  # warm
+    tts, wall, solved = [], [], 0
+    for seed, s, qs, qg in probs:
+        t0 = time.perf_counter()
+        r = s.plan(qs, qg, raise_on_error=False, resolution=res, **dict(C1_PLAN, seed=seed, stop_at_first=1))
+        wall.append(time.perf_counter() - t0)
+        if r.status == "OK":
+            solved += 1
+            tts.append(r.stats["time_to_first_s"])
+    full = []
+    for seed, s, qs, qg in probs[:n_full]:
+        r = s.plan(qs, qg, raise_on_error=False, resolution=res, **dict(C1_PLAN, seed=seed))
+        full.append({"seed": seed, "status": r.status, "first_cost": r.stats["costs"][0] if r.stats["costs"] else None,
+                     "cost_at_budget": r.cost if r.status == "OK" else None, "improvements": r.stats["solutions"],
+                     "rounds": r.stats["rounds"], "iterations": r.stats["iterations"],
+                     "straight_line": float(np.linalg.norm(qg.astype(np.float64) - qs))})
+    return {"problems": len(probs), "solved": solved, "solve_rate": solved / len(probs),
+            "tts_p50_ms": float(np.median(tts)) * 1e3 if tts else None,
+            "tts_p90_ms": float(np.percentile(tts, 90)) * 1e3 if tts else None,
+            "tts_max_ms": float(np.max(tts)) * 1e3 if tts else None,
+            "plan_call_p50_ms": float(np.median(wall)) * 1e3, "params": C1_PLAN, "full_budget": full}
+
+
+def c3_leg(ctx, reps: int, plan_s: float) -> dict:
+    """The 8-arm shelf workload: both 4096-edge batches validated `reps`
+    times (edge-states/s, the tile kernel's time and algorithmic flops, bits
+    checked against the fixture), then one plan with a wall-clock budget
+    (time to first solution, cost after each improvement, cost at the end)."""
+    import torch
+    import paper_2609_30644_amd as M
+    scene, batches, fx = load_workload(C3_FIXTURE, "scene_c3")
+    res = float(fx["resolution"])
+    s = M.Scene(ctx, scene)
+    dev = {k: (ctx.to_device(a), ctx.to_device(b)) for k, (a, b) in batches.items()}
+    outs = {k: torch.empty(a.shape[0], dtype=torch.uint8, device=ctx.device) for k, (a, _) in dev.items()}
+    out = {"workload": "8 arms x 7-DoF (59 spheres/arm) on a 3 m circle, 256 shelf boxes, res 0.02 rad"}
+    for k, (a, b) in dev.items():
+        _, st = s.validate_edges(a, b, res, out=outs[k], stats=True)  # warm, and the nominal states
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s.validate_edges(a, b, res, out=outs[k])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        flops = algorithmic_flops(prof.work, scene)
+        out[k] = {"edges": int(a.shape[0]), "edge_states": st.edge_states, "reps": reps,
+                  "edge_states_per_s": st.edge_states * reps / dt,
+                  "kernel_us": prof.kernel_ms * 1e3 / max(1, prof.launches),
+                  "achieved_tflops": flops / (prof.kernel_ms * 1e-3) / 1e12,
+                  "frac": flops / (prof.kernel_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+    out["bits"] = check_bits(outs["free"].cpu().numpy(), outs["mixed"].cpu().numpy(), fx)
+    if plan_s > 0:
+        qs, qg = np.array(fx["q_start"], np.float32), np.array(fx["q_goal"], np.float32)
+        prm = dict(C3_PLAN, seed=0, resolution=res, time_budget_s=plan_s)
+        t0 = time.perf_counter()
+        r, hist, n = s.plan_with_history(qs, qg, max_entries=64, max_waypoints=65536, raise_on_error=False, **prm)
+        out["plan"] = {"status": r.status, "wall_s": time.perf_counter() - t0,
+                       "tts_ms": r.stats["time_to_first_s"] * 1e3 if r.stats["time_to_first_s"] >= 0 else None,
+                       "cost": r.cost if r.status == "OK" else None,
+                       "cost_vs_time": sorted([(h.found_s, h.cost) for h in hist]),
+                       "rounds": r.stats["rounds"], "iterations": r.stats["iterations"],
+                       "edge_states": r.stats["edge_states"], "roadmap_vertices": r.stats["roadmap_vertices"],
+                       "straight_line": float(np.linalg.norm(qg.astype(np.float64) - qs)),
+                       "params": dict(prm, time_budget_s=plan_s)}
+    return out
 
 
 BATCH_FIXTURE = os.path.join(ROOT, "tests", "golden", "c4_batch.json")
@@ -397,6 +560,13 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of the served run")
     ap.add_argument("--serve-slots", type=int, default=128)
     ap.add_argument("--serve-mem-gb", type=float, default=96.0)
+    ap.add_argument("--c1-problems", type=int, default=50,
+                    help="two-arm problems of the time-to-solution leg (0: skip)")
+    ap.add_argument("--c1-full", type=int, default=2, help="of those, plans run for the whole 5 s budget")
+    ap.add_argument("--c3-reps", type=int, default=10, help="repetitions of each 8-arm batch (0: skip the leg)")
+    ap.add_argument("--c3-plan-seconds", type=float, default=30.0, help="budget of the 8-arm plan (0: skip)")
+    ap.add_argument("--oracle-planner-seeds", type=int, default=50,
+                    help="two-arm problems planned by the oracle in the CPU baseline (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB on the device three times (traffic-counter calibration) and exit")
     args = ap.parse_args()
@@ -448,6 +618,7 @@ def main():
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    bits = check_bits(outs["free"].cpu().numpy(), outs["mixed"].cpu().numpy(), fx)
 
     flops = algorithmic_flops(prof.work, scene)
     achieved = flops / (prof.kernel_ms * 1e-3) / 1e12
@@ -474,6 +645,7 @@ def main():
                    "free_batch_states": nominal["free"], "mixed_batch_states": nominal["mixed"]},
         "roofline": roofline,
         "states_checked_frac": prof.states_checked / max(1, prof.edge_states),
+        "bits_vs_oracle": bits,
     }
     if plans:
         line["plan"] = {"tts_p50_ms": float(np.median(tts)) * 1e3 if tts else None,
@@ -489,6 +661,12 @@ def main():
             line["plan_unprofiled"] = unprofiled_leg(s, q_start, q_goal, res, n_same)
             line["plan_unprofiled"]["timed_mean_plan_ms_same_seeds"] = float(
                 np.mean([p.stats["total_time_s"] for p in plans[:n_same]])) * 1e3
+    if args.c1_problems > 0:
+        print("[bench] two-arm time to solution", file=sys.stderr, flush=True)
+        line["c1"] = c1_leg(ctx, args.c1_problems, args.c1_full)
+    if args.c3_reps > 0:
+        print("[bench] eight-arm shelf", file=sys.stderr, flush=True)
+        line["c3"] = c3_leg(ctx, args.c3_reps, args.c3_plan_seconds)
     if args.direct:
         print("[bench] direct mode", file=sys.stderr, flush=True)
         line["direct"] = direct_leg(ctx, res)
@@ -506,8 +684,11 @@ def main():
         line["served"] = served(ctx, args.serve_rate, args.serve_seconds, args.serve_slots, args.serve_mem_gb)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(scene, batches, res, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(scene, batches, res, args.cpu_seconds, args.oracle_planner_seeds)
     print(json.dumps(line), flush=True)
+    if not bits["ok"] or not line.get("c3", {}).get("bits", {"ok": True})["ok"]:
+        print("[bench] timed bits disagree with the oracle's classes", file=sys.stderr, flush=True)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

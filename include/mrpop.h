@@ -246,6 +246,52 @@ mrpop_status mrpop_sample(mrpop_ctx *ctx, const mrpop_scene *scene, const float 
                           const float *root, float c_best, uint64_t seed, uint64_t round, int64_t first, int64_t n,
                           float *out_q, float *out_c, void *stream);
 
+/* Roadmap rows: joint j of vertex u of arm r at
+ * rm_vertices[((r * rm_cap) + u) * MRPOP_RM_STRIDE + j]. */
+#define MRPOP_RM_STRIDE 8
+
+/* The extension step of one search round, ORACLE_AOX of Alg. 2 (paper, Sec.
+ * "Converge to Global Optimality"; with no budget it is dRRT's oracle), for n
+ * candidates.  Candidate i extends tree vertex z = near_idx[i] toward
+ * q_rand[i] with budget c_rand[i].  Per arm r, with v the arm's roadmap
+ * vertex in z, a neighbour u of v is admissible when moving arm r alone keeps
+ * g_z + |u - v| < c_rand; among the admissible neighbours the arm takes the
+ * one of largest cosine with q_rand^r - v (ties: lowest id) and stays when
+ * none has a positive cosine.  If the composite move then reaches the
+ * budget, moving arms go back to staying, least aligned first (ties: higher
+ * arm index first), until g_z + |q_new - q_z| < c_rand.  The candidate is
+ * alive when some arm moves.  Device buffers; D = the scene's dimension,
+ * R = its arms; the call queues one launch on `stream` after waiting for
+ * earlier work on it (it stages the arms' joint table in the context). */
+typedef struct {
+  int32_t n;                  /* candidates                                   */
+  const int32_t *near_idx;    /* [n] tree vertex extended; -1: none (dead)    */
+  const float *q_rand;        /* [n][D] samples                               */
+  const float *c_rand;        /* [n] budgets, or NULL (all +infinity)         */
+  const float *tree_q;        /* [D][tree_cap] tree configurations (SoA)      */
+  const float *tree_g;        /* [tree_cap] cost-to-come                      */
+  const int32_t *tree_vid;    /* [R][tree_cap] each arm's roadmap vertex      */
+  int32_t tree_cap;
+  const float *rm_vertices;   /* [R][rm_cap][MRPOP_RM_STRIDE] roadmap rows     */
+  const int32_t *rm_rowptr;   /* [R][rm_cap + 1] adjacency rows (CSR)         */
+  const int32_t *rm_col;      /* [R][col_cap] neighbour ids                   */
+  int32_t rm_cap, col_cap;
+  float resolution;           /* for n_states                                 */
+  float *q_new;               /* out [n][D]: q_new (q_z when nothing moves)   */
+  int32_t *vid_new;           /* out [R][n]: roadmap vertex per arm (-1: dead) */
+  float *g_new;               /* out [n]: g_z + |q_new - q_z| (+inf: dead)    */
+  uint8_t *alive;             /* out [n]                                      */
+  float *edge_a, *edge_b;     /* out [n][D] or both NULL: the edge to check,  */
+                              /* q_z -> q_new, or q_z -> q_z when not alive   */
+  int32_t *n_states;          /* out [n] or NULL: that edge's state count at  */
+                              /* `resolution` (as mrpop_validate_edges)       */
+} mrpop_extend_batch;
+
+/* Errors: E_INVALID_ARG (NULL batch or buffers, negative sizes, resolution
+ * <= 0 with n_states), E_NOMEM, E_DEVICE. */
+mrpop_status mrpop_extend(mrpop_ctx *ctx, const mrpop_scene *scene, const mrpop_extend_batch *batch,
+                          void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Planning (Alg. 1)                                                         */
 /* ------------------------------------------------------------------------ */
@@ -277,13 +323,20 @@ typedef struct {
   double time_to_first_s;    /* wall time to the first solution, -1 if none */
   double total_time_s;
   int32_t rounds, iterations, solutions, first_round;
-  int64_t edge_states;       /* composite edge states validated by the search */
+  int64_t edge_states;       /* composite edge states validated by the search:
+                                the extension edges, and the connection edges of
+                                the candidates that entered a tree */
   int64_t roadmap_edge_states;
   int32_t roadmap_vertices;  /* summed over arms */
   int32_t roadmap_connected; /* every arm's start and goal joined (last iteration) */
   int32_t capacity_hit;      /* a tree or roadmap reached its capacity */
   int32_t n_costs;           /* entries of costs[] */
   float costs[64];           /* incumbent cost after each improvement */
+  /* Connection edges are searched and checked in the same launch as the
+   * extension edges, before it is known which candidates enter the tree;
+   * the states of those whose candidate did not (work done ahead and not
+   * needed) are counted here and not in edge_states. */
+  int64_t speculative_edge_states;
 } mrpop_plan_stats;
 
 /* Incumbent history (paper, Sec. "Seeding for Multi-Robot Jerk-Free
@@ -302,7 +355,21 @@ typedef struct {
  *                the entry's discovery.
  *   found_round  host [entry_cap] or NULL: search round of the discovery.
  *   n_entries    out: incumbents found in the call (may exceed n_written).
- *   n_written    out: entries written. */
+ *   n_written    out: entries written.
+ * Optional, for inspecting paths on the roadmaps' tensor product (Sec.
+ * "Problem Setup": every edge of a path moves each arm along one of its
+ * roadmap edges or keeps it in place, except that the connection of the two
+ * trees is a straight composite edge):
+ *   vertex_ids   host [waypoint_cap][R] or NULL: per written waypoint, each
+ *                arm's roadmap vertex (meaningless in direct mode).
+ *   rm_vertices  host [R][rm_vertex_cap][MRPOP_RM_STRIDE] or NULL: each arm's
+ *                roadmap vertices at the end of the call (first
+ *                rm_vertex_cap of them; vertex 0 is the arm's start, 1 its
+ *                goal).
+ *   rm_edges     host [R][rm_edge_cap][2] or NULL: each arm's roadmap edges
+ *                (vertex pairs, first rm_edge_cap of them).
+ *   rm_n_vertices, rm_n_edges  out: the full counts per arm (0 in direct
+ *                mode). */
 typedef struct {
   float *waypoints;
   int64_t waypoint_cap;
@@ -313,6 +380,12 @@ typedef struct {
   int32_t entry_cap;
   int32_t n_entries;
   int32_t n_written;
+  int32_t *vertex_ids;
+  float *rm_vertices;
+  int32_t *rm_edges;
+  int32_t rm_vertex_cap, rm_edge_cap;
+  int32_t rm_n_vertices[MRPOP_MAX_ROBOTS];
+  int32_t rm_n_edges[MRPOP_MAX_ROBOTS];
 } mrpop_plan_history;
 
 /* Defaults: seed 0, delta 3.0, n_roadmap 32, candidates 128, resolution

@@ -22,14 +22,24 @@ Readings where the paper is silent (each is also a GPU-side rule):
     j < i) closer than delta becomes an edge when its single-arm motion is
     free; BFS from the start vertex (0) to the goal vertex (1).  Roadmaps
     persist across calls.
-  * dRRT oracle: per arm, the roadmap neighbour of the near vertex best
-    aligned with the sample direction (largest cosine, ties to the lowest
-    neighbour id); the arm stays if no cosine is positive.  A candidate
-    where every arm stays is dropped; under a finite budget a candidate whose
-    cost-to-come would reach c_rand is dropped (admissibility).
+  * ORACLE_AOX (the dRRT oracle with AO-X's admissibility; Sec. "Converge to
+    Global Optimality"): per arm, a roadmap neighbour u of the arm's vertex
+    in z_near is admissible when the composite neighbour that moves this arm
+    alone to u stays within the budget, g_near + |u - q_near^i| < c_rand; among
+    the admissible ones the arm takes the one best aligned with the sample
+    direction (largest cosine, ties to the lowest neighbour id), and stays if
+    no admissible neighbour has a positive cosine.  When the composite of
+    these per-arm moves exceeds the budget, arms go back to staying, least
+    aligned first (ties: the higher arm index first), until it fits; the last
+    moving arm always fits on its own.  A candidate where every arm stays is
+    dropped.  With c_rand = +inf (the initial solve) this is the plain dRRT
+    oracle.
   * Informed samples outside the joint limits are clamped onto them (the
-    clamped point stays inside the prolate hyperspheroid because both foci
-    are inside the box).
+    Euclidean projection onto the box).  The projection cannot move a point
+    farther from either focus (it is non-expansive and both foci are inside
+    the box), so the clamped point is still inside the prolate hyperspheroid;
+    points already inside the box are unchanged, so the draw has a positive
+    density on the whole informed set within the limits.
   * The cost lower bound g(q) of a sample is its distance to the root of the
     tree being extended (the start, or the goal after a swap).
   * Connection: NEAREST in the other tree with budget c_best - g_new (the
@@ -89,6 +99,8 @@ class PlanResult:
     last_search_solved: bool = False
     # every incumbent in discovery order: (cost, path start to goal, round)
     history: list = field(default_factory=list)
+    # per search round: (round, extended tree is the start tree, |T_a|, |T_b|)
+    trace: list = field(default_factory=list)
 
 
 class _Roadmap:
@@ -195,24 +207,166 @@ def _cost(path) -> float:
     return float(np.linalg.norm(np.diff(p, axis=0), axis=1).sum()) if len(p) > 1 else 0.0
 
 
-def drrt_oracle(roadmaps, vid_near, q_near_arms, q_rand_arms):
-    """Per arm: best-aligned roadmap neighbour of the near vertex (or stay)."""
-    out = []
+def aox_oracle(roadmaps, vid_near, q_rand_arms, g_near: float = 0.0, c_rand: float = math.inf):
+    """ORACLE_AOX (Alg. 2; Sec. "Converge to Global Optimality"): the vertex
+    ids of q_new, one per arm (equal to vid_near when no arm moves).
+
+    Per arm i, with v = vid_near[i] and the sample direction d = q_rand^i - V_v:
+    a neighbour u of v in the arm's roadmap is admissible when moving arm i
+    alone to it stays within the budget, g_near + |V_u - V_v| < c_rand, and
+    the arm takes the admissible neighbour of largest cosine with d (ties:
+    lowest id), or stays when none has a positive cosine (or d = 0).  If the
+    composite move then costs g_near + |q_new - q_near| >= c_rand, moving arms
+    go back to staying, least aligned first (ties: higher arm index first),
+    until it fits.  With c_rand = +inf this is dRRT's oracle."""
+    best, cosv, d2 = [], [], []
     for r, rm in enumerate(roadmaps):
         v = vid_near[r]
-        d = q_rand_arms[r].astype(np.float64) - rm.V[v].astype(np.float64)
-        nd = np.linalg.norm(d)
-        best, best_cos = v, 0.0
+        base = rm.V[v].astype(np.float64)
+        d = np.asarray(q_rand_arms[r], np.float64) - base
+        nd = float(np.linalg.norm(d))
+        b, b_cos, b_d2 = v, 0.0, 0.0
         if nd > 0:
             for u in sorted(rm.adj[v]):
-                e = rm.V[u].astype(np.float64) - rm.V[v].astype(np.float64)
-                ne = np.linalg.norm(e)
-                if ne == 0:
+                e = rm.V[u].astype(np.float64) - base
+                ne = float(np.linalg.norm(e))
+                if ne == 0 or not (g_near + ne < c_rand):
                     continue
                 cos = float(np.dot(e, d) / (ne * nd))
-                if cos > best_cos:
-                    best, best_cos = u, cos
-        out.append(best)
+                if cos > b_cos:
+                    b, b_cos, b_d2 = u, cos, ne * ne
+        best.append(b)
+        cosv.append(b_cos)
+        d2.append(b_d2)
+    moving = [r for r in range(len(roadmaps)) if best[r] != vid_near[r]]
+    while moving and not (g_near + math.sqrt(sum(d2[r] for r in moving)) < c_rand):
+        moving.remove(min(moving, key=lambda r: (cosv[r], -r)))
+    return [best[r] if r in moving else vid_near[r] for r in range(len(roadmaps))]
+
+
+def drrt_oracle(roadmaps, vid_near, q_near_arms, q_rand_arms):
+    """dRRT's oracle (no cost budget): ORACLE_AOX with c_rand = +inf."""
+    return aox_oracle(roadmaps, vid_near, q_rand_arms)
+
+
+def cost_coordinate(lb: float, c_best: float, u: float) -> float:
+    """The cost coordinate c_rand ~ U[lb, c_best] of an AO-X sample (Alg. 2:
+    the budgets under which q_rand is reachable, lb = g(q_rand)) from a
+    uniform u in [0, 1); c_best itself when lb >= c_best."""
+    return lb + u * (c_best - lb) if lb < c_best else c_best
+
+
+def draw_candidate(seed: int, rnd: int, i: int, c_best: float, lo, hi, q_start, q_goal, root):
+    """Candidate i of round rnd: (q_rand, c_rand), FP64 (Alg. 2).
+
+    c_best = +inf: q_rand uniform in the joint box, c_rand = +inf.  Otherwise
+    INFORMED_SAMPLE: a uniform point of the unit D-ball mapped into the
+    prolate hyperspheroid with foci q_start, q_goal and transverse diameter
+    c_best, clamped onto the joint box; c_rand from cost_coordinate with
+    lb = |q_rand - root|, root being the root of the tree this candidate
+    extends."""
+    D = lo.shape[0]
+    if math.isinf(c_best):
+        u = u01(key(seed, PURPOSE_Q, rnd, i), D)
+        return lo + u * (hi - lo), math.inf
+    x = unit_ball(key(seed, PURPOSE_BALL, rnd, i), D)
+    q_rand = np.clip(ellipsoid_map(q_start, q_goal, c_best, x), lo, hi)
+    lb = float(np.linalg.norm(q_rand - np.asarray(root, np.float64)))
+    return q_rand, cost_coordinate(lb, c_best, u01(key(seed, PURPOSE_C, rnd, i), 1)[0])
+
+
+def needs_swap(ta, tb) -> bool:
+    """Alg. 2 extends the smaller tree: swap when |V_a| > |V_b| (equal sizes
+    keep the current order)."""
+    return len(ta) > len(tb)
+
+
+def connect_budget(c_best: float, g_new: float) -> float:
+    """Budget of the connection search from a new vertex (Alg. 2, AO-X): only
+    vertices z of the other tree with g_z + |q_new - q_z| < c_best - g_new,
+    so that any connection makes a path cheaper than c_best; +inf in the
+    initial solve."""
+    return c_best - g_new if not math.isinf(c_best) else math.inf
+
+
+@dataclass
+class RoundOutcome:
+    """What one search round did, in candidate order."""
+    cands: list = field(default_factory=list)     # (i, k_near, vid_new, q_new, g_new): extensions to validate
+    valid: list = field(default_factory=list)     # their edge bits
+    inserted: list = field(default_factory=list)  # (i, index in T_a)
+    conns: list = field(default_factory=list)     # (i, index in T_a, index in T_b): connection edges tried
+    cvalid: list = field(default_factory=list)    # their edge bits
+    best: Optional[tuple] = None                  # (total cost, i, index in T_a, index in T_b)
+    edge_states: int = 0
+
+
+def search_round(osc, roadmaps, ta, tb, draws, c_best: float, params: PlanParams, composite) -> RoundOutcome:
+    """One round of P candidate iterations against the round-start trees
+    (Alg. 2, AO-X; dRRT_SEARCH when c_best = +inf): for each draw (q_rand,
+    c_rand): NEAREST in T_a under c_rand, the extension (ORACLE_AOX, or a
+    steer in direct mode), then the edge checks; survivors enter T_a in
+    candidate order, each searches T_b under connect_budget, and the free
+    connection of least total cost (ties: lowest candidate) is the round's
+    result.  T_a grows in place."""
+    out = RoundOutcome()
+    R = len(roadmaps)
+    na, nb = len(ta), len(tb)
+    Va, ga = np.array(ta.q[:na], np.float32), np.array(ta.g[:na], np.float32)
+    Vb, gb = np.array(tb.q[:nb], np.float32), np.array(tb.g[:nb], np.float32)
+    q_off = np.concatenate([[0], np.cumsum([len(rm.V[0]) for rm in roadmaps])]).astype(int)
+    for i, (q_rand, c_rand) in enumerate(draws):
+        k_near = nearest(Va, ga, np.asarray(q_rand, np.float32), c_rand)
+        if k_near < 0:
+            continue
+        q_near = ta.q[k_near].astype(np.float64)
+        g_near = float(ta.g[k_near])
+        if params.direct:
+            if not np.any(np.asarray(q_rand, np.float64) != q_near):  # nothing to extend toward
+                continue
+            q_new = steer(q_near, q_rand, params.step).astype(np.float32)
+            vid_new = ta.vid[k_near]
+            g_new = g_near + float(np.linalg.norm(q_new.astype(np.float64) - q_near))
+            if not math.isinf(c_best) and not (g_new < c_rand):
+                continue
+        else:
+            arms = [np.asarray(q_rand, np.float64)[q_off[r]:q_off[r + 1]] for r in range(R)]
+            vid_new = tuple(aox_oracle(roadmaps, ta.vid[k_near], arms, g_near, c_rand))
+            if vid_new == ta.vid[k_near]:
+                continue
+            q_new = composite(vid_new)
+            g_new = g_near + float(np.linalg.norm(q_new.astype(np.float64) - q_near))
+        out.cands.append((i, k_near, vid_new, q_new, g_new))
+    if out.cands:
+        qa = np.array([ta.q[c[1]] for c in out.cands], np.float32)
+        qb = np.array([c[3] for c in out.cands], np.float32)
+        valid, n, _ = validate_fast(osc, qa, qb, params.resolution)
+        out.valid = [bool(v) for v in valid]
+        out.edge_states += int(n.sum())
+    for c, v in zip(out.cands, out.valid):
+        if v and len(ta) < params.max_tree_nodes:
+            ta.q.append(c[3])
+            ta.g.append(np.float32(c[4]))
+            ta.parent.append(c[1])
+            ta.vid.append(c[2])
+            out.inserted.append((c[0], len(ta) - 1))
+    for ci, idx in out.inserted:
+        kc = nearest(Vb, gb, ta.q[idx], connect_budget(c_best, float(ta.g[idx])))
+        if kc >= 0:
+            out.conns.append((ci, idx, kc))
+    if out.conns:
+        qa = np.array([ta.q[c[1]] for c in out.conns], np.float32)
+        qb = np.array([tb.q[c[2]] for c in out.conns], np.float32)
+        valid, n, _ = validate_fast(osc, qa, qb, params.resolution)
+        out.cvalid = [bool(v) for v in valid]
+        out.edge_states += int(n.sum())
+        for (ci, idx, kc), v in zip(out.conns, out.cvalid):
+            if not v:
+                continue
+            tot = float(ta.g[idx]) + float(np.linalg.norm(ta.q[idx].astype(np.float64) -
+                                                          tb.q[kc].astype(np.float64))) + float(tb.g[kc])
+            if out.best is None or tot < out.best[0]:
+                out.best = (tot, ci, idx, kc)
     return out
 
 
@@ -246,15 +400,12 @@ def plan(scene, q_start, q_goal, params: PlanParams, warm_path=None) -> PlanResu
     lo, hi = scene.q_lo.astype(np.float64), scene.q_hi.astype(np.float64)
     arm_scenes = [OracleScene(_arm_scene(scene, r)) for r in range(R)]
     roadmaps = [_Roadmap(q_start[q_off[r]:q_off[r + 1]], q_goal[q_off[r]:q_off[r + 1]]) for r in range(R)]
-    c_best, best_path, costs, history = math.inf, None, [], []
+    c_best, best_path, costs, history, trace = math.inf, None, [], [], []
     if warm_path is not None:
         best_path = np.asarray(warm_path, np.float32)
         c_best = _cost(best_path)
     rnd, it, first_round, edge_states = 0, 0, -1, 0
     solved = False
-
-    def arms(q):
-        return [q[q_off[r]:q_off[r + 1]] for r in range(R)]
 
     def composite(vid):
         return np.concatenate([roadmaps[r].V[vid[r]] for r in range(R)]).astype(np.float32)
@@ -266,90 +417,28 @@ def plan(scene, q_start, q_goal, params: PlanParams, warm_path=None) -> PlanResu
         a_is_start = True
         solved = False
         while not solved and rnd < params.max_rounds:
-            if len(ta) > len(tb):
+            if needs_swap(ta, tb):
                 ta, tb = tb, ta
                 a_is_start = not a_is_start
+            trace.append((rnd, a_is_start, len(ta), len(tb)))
             root_a = ta.q[0].astype(np.float64)
-            na, nb = len(ta), len(tb)
-            Va, ga = np.array(ta.q[:na], np.float32), np.array(ta.g[:na], np.float32)
-            Vb, gb = np.array(tb.q[:nb], np.float32), np.array(tb.g[:nb], np.float32)
-            cands = []
-            for i in range(params.candidates):
-                if math.isinf(c_best):
-                    u = u01(key(params.seed, PURPOSE_Q, rnd, i), D)
-                    q_rand = lo + u * (hi - lo)
-                    c_rand = math.inf
-                else:
-                    x = unit_ball(key(params.seed, PURPOSE_BALL, rnd, i), D)
-                    q_rand = np.clip(ellipsoid_map(q_start, q_goal, c_best, x), lo, hi)
-                    lb = float(np.linalg.norm(q_rand - root_a))
-                    uc = u01(key(params.seed, PURPOSE_C, rnd, i), 1)[0]
-                    c_rand = lb + uc * (c_best - lb) if lb < c_best else c_best
-                k_near = nearest(Va, ga, q_rand.astype(np.float32), c_rand)
-                if k_near < 0:
-                    continue
-                if params.direct:
-                    q_near = ta.q[k_near].astype(np.float64)
-                    if not np.any(q_rand != q_near):  # nothing to extend toward
-                        continue
-                    q_new = steer(q_near, q_rand, params.step).astype(np.float32)
-                    vid_new = ta.vid[k_near]
-                else:
-                    vid_new = tuple(drrt_oracle(roadmaps, ta.vid[k_near], arms(ta.q[k_near]), arms(q_rand)))
-                    if vid_new == ta.vid[k_near]:
-                        continue
-                    q_new = composite(vid_new)
-                g_new = float(ta.g[k_near]) + float(np.linalg.norm(q_new.astype(np.float64) -
-                                                                   ta.q[k_near].astype(np.float64)))
-                if not math.isinf(c_best) and g_new >= c_rand:
-                    continue
-                cands.append((i, k_near, vid_new, q_new, g_new))
-            if cands:
-                qa = np.array([ta.q[c[1]] for c in cands], np.float32)
-                qb = np.array([c[3] for c in cands], np.float32)
-                valid, n, _ = validate_fast(osc, qa, qb, params.resolution)
-                edge_states += int(n.sum())
-            else:
-                valid = []
-            inserted = []
-            for c, v in zip(cands, valid):
-                if v and len(ta) < params.max_tree_nodes:
-                    ta.q.append(c[3])
-                    ta.g.append(np.float32(c[4]))
-                    ta.parent.append(c[1])
-                    ta.vid.append(c[2])
-                    inserted.append((c[0], len(ta) - 1))
-            conns = []
-            for ci, idx in inserted:
-                budget = c_best - float(ta.g[idx]) if not math.isinf(c_best) else math.inf
-                kc = nearest(Vb, gb, ta.q[idx], budget)
-                if kc >= 0:
-                    conns.append((ci, idx, kc))
-            if conns:
-                qa = np.array([ta.q[c[1]] for c in conns], np.float32)
-                qb = np.array([tb.q[c[2]] for c in conns], np.float32)
-                valid, n, _ = validate_fast(osc, qa, qb, params.resolution)
-                edge_states += int(n.sum())
-                best = None
-                for (ci, idx, kc), v in zip(conns, valid):
-                    if not v:
-                        continue
-                    tot = float(ta.g[idx]) + float(np.linalg.norm(ta.q[idx].astype(np.float64) -
-                                                                  tb.q[kc].astype(np.float64))) + float(tb.g[kc])
-                    if best is None or tot < best[0]:
-                        best = (tot, ci, idx, kc)
-                if best is not None:
-                    path = _path_to_root(ta, best[2]) + _path_to_root(tb, best[3])[::-1]
-                    if not a_is_start:
-                        path = path[::-1]
-                    cost = _cost(path)
-                    if cost < c_best:
-                        c_best, best_path = cost, np.array(path, np.float32)
-                        costs.append(cost)
-                        history.append((cost, best_path, rnd))
-                        if first_round < 0:
-                            first_round = rnd
-                        solved = True
+            draws = [draw_candidate(params.seed, rnd, i, c_best, lo, hi, q_start, q_goal, root_a)
+                     for i in range(params.candidates)]
+            out = search_round(osc, roadmaps, ta, tb, draws, c_best, params, composite)
+            edge_states += out.edge_states
+            if out.best is not None:
+                _, _, ia, ib = out.best
+                path = _path_to_root(ta, ia) + _path_to_root(tb, ib)[::-1]
+                if not a_is_start:
+                    path = path[::-1]
+                cost = _cost(path)
+                if cost < c_best:
+                    c_best, best_path = cost, np.array(path, np.float32)
+                    costs.append(cost)
+                    history.append((cost, best_path, rnd))
+                    if first_round < 0:
+                        first_round = rnd
+                    solved = True
             rnd += 1
         it += 1
         if solved and params.stop_at_first:
@@ -357,7 +446,8 @@ def plan(scene, q_start, q_goal, params: PlanParams, warm_path=None) -> PlanResu
         if not solved:
             break
     status = "OK" if best_path is not None else "E_NO_SOLUTION"
-    return PlanResult(status, best_path, c_best, rnd, it, first_round, costs, edge_states, roadmaps, solved, history)
+    return PlanResult(status, best_path, c_best, rnd, it, first_round, costs, edge_states, roadmaps, solved, history,
+                      trace)
 
 
 def ranked_history(result: PlanResult, max_entries: int = 64):

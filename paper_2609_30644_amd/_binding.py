@@ -67,7 +67,7 @@ class _PlanStats(C.Structure):
                 ("iterations", C.c_int32), ("solutions", C.c_int32), ("first_round", C.c_int32),
                 ("edge_states", C.c_int64), ("roadmap_edge_states", C.c_int64), ("roadmap_vertices", C.c_int32),
                 ("roadmap_connected", C.c_int32), ("capacity_hit", C.c_int32), ("n_costs", C.c_int32),
-                ("costs", C.c_float * 64)]
+                ("costs", C.c_float * 64), ("speculative_edge_states", C.c_int64)]
 
 
 class _PlanRequest(C.Structure):
@@ -76,10 +76,16 @@ class _PlanRequest(C.Structure):
                 ("cost", C.c_float), ("stats", _PlanStats)]
 
 
+MAX_ROBOTS = 16  # MRPOP_MAX_ROBOTS
+
+
 class _PlanHistory(C.Structure):
     _fields_ = [("waypoints", C.c_void_p), ("waypoint_cap", C.c_int64), ("offsets", C.c_void_p),
                 ("costs", C.c_void_p), ("found_s", C.c_void_p), ("found_round", C.c_void_p),
-                ("entry_cap", C.c_int32), ("n_entries", C.c_int32), ("n_written", C.c_int32)]
+                ("entry_cap", C.c_int32), ("n_entries", C.c_int32), ("n_written", C.c_int32),
+                ("vertex_ids", C.c_void_p), ("rm_vertices", C.c_void_p), ("rm_edges", C.c_void_p),
+                ("rm_vertex_cap", C.c_int32), ("rm_edge_cap", C.c_int32),
+                ("rm_n_vertices", C.c_int32 * MAX_ROBOTS), ("rm_n_edges", C.c_int32 * MAX_ROBOTS)]
 
 
 class _ServerConfig(C.Structure):
@@ -97,6 +103,15 @@ class _ServerStats(C.Structure):
                 ("rejected", C.c_int64), ("queue_len", C.c_int32), ("running", C.c_int32),
                 ("max_queue_len", C.c_int32), ("max_running", C.c_int32), ("reserved_bytes", C.c_int64),
                 ("peak_reserved_bytes", C.c_int64), ("flushes", C.c_int64), ("launches", C.c_int64)]
+
+
+class _ExtendBatch(C.Structure):
+    _fields_ = [("n", C.c_int32), ("near_idx", C.c_void_p), ("q_rand", C.c_void_p), ("c_rand", C.c_void_p),
+                ("tree_q", C.c_void_p), ("tree_g", C.c_void_p), ("tree_vid", C.c_void_p), ("tree_cap", C.c_int32),
+                ("rm_vertices", C.c_void_p), ("rm_rowptr", C.c_void_p), ("rm_col", C.c_void_p),
+                ("rm_cap", C.c_int32), ("col_cap", C.c_int32), ("resolution", C.c_float), ("q_new", C.c_void_p),
+                ("vid_new", C.c_void_p), ("g_new", C.c_void_p), ("alive", C.c_void_p), ("edge_a", C.c_void_p),
+                ("edge_b", C.c_void_p), ("n_states", C.c_void_p)]
 
 
 class _BatchStats(C.Structure):
@@ -119,6 +134,7 @@ class Incumbent:
     cost: float
     found_s: float     # seconds from the call's start
     found_round: int
+    vertex_ids: Optional[np.ndarray] = None  # [len][R] roadmap vertex of each arm per waypoint
 
 
 WORK_NAMES = ("chains", "links", "env_tests", "box_exact", "rr_coarse", "fine_sphere", "fine_box", "fine_rr")
@@ -184,6 +200,7 @@ def load_library():
     lib.mrpop_validate_edges_noalloc.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
     lib.mrpop_nearest.argtypes = [P, P, P, I64, I32, P, P, I64, P, P]
     lib.mrpop_sample.argtypes = [P, P, P, P, P, C.c_float, C.c_uint64, C.c_uint64, I64, I64, P, P, P]
+    lib.mrpop_extend.argtypes = [P, P, P, P]
     lib.mrpop_plan_params_default.argtypes = [P]
     lib.mrpop_plan_params_default.restype = None
     lib.mrpop_plan.argtypes = [P, P, P, P, P, P, I32, P, P, P]
@@ -445,6 +462,43 @@ class Scene:
                                                   out_q.data_ptr(), out_c.data_ptr(), self.ctx.stream()))
         return out_q, out_c
 
+    def extend(self, near_idx, q_rand, c_rand, tree_q, tree_g, tree_vid, rm_vertices, rm_rowptr, rm_col,
+               resolution: float = 0.05) -> dict:
+        """mrpop_extend (ORACLE_AOX of one round) on host arrays: near_idx [n],
+        q_rand [n][D], c_rand [n] or None, tree_q [D][cap] (SoA), tree_g [cap],
+        tree_vid [R][cap], rm_vertices [R][rm_cap][8], rm_rowptr
+        [R][rm_cap + 1], rm_col [R][col_cap].  Returns host arrays q_new,
+        vid_new [R][n], g_new, alive, edge_a, edge_b, n_states."""
+        torch = _torch()
+        dev = self.ctx.device
+        f32, i32 = torch.float32, torch.int32
+        near = self.ctx.to_device(np.asarray(near_idx, np.int32), i32)
+        n = int(near.numel())
+        qr = self.ctx.to_device(q_rand, f32).reshape(n, self.dof)
+        cr = None if c_rand is None else self.ctx.to_device(c_rand, f32).reshape(n)
+        tq = self.ctx.to_device(tree_q, f32)
+        tg = self.ctx.to_device(tree_g, f32)
+        tv = self.ctx.to_device(tree_vid, i32)
+        rv = self.ctx.to_device(rm_vertices, f32)
+        rp = self.ctx.to_device(rm_rowptr, i32)
+        rc = self.ctx.to_device(rm_col, i32)
+        R = int(tv.shape[0])
+        out = dict(q_new=torch.empty((n, self.dof), dtype=f32, device=dev),
+                   vid_new=torch.empty((R, n), dtype=i32, device=dev),
+                   g_new=torch.empty(n, dtype=f32, device=dev),
+                   alive=torch.empty(n, dtype=torch.uint8, device=dev),
+                   edge_a=torch.empty((n, self.dof), dtype=f32, device=dev),
+                   edge_b=torch.empty((n, self.dof), dtype=f32, device=dev),
+                   n_states=torch.empty(n, dtype=i32, device=dev))
+        b = _ExtendBatch(n, near.data_ptr(), qr.data_ptr(), None if cr is None else cr.data_ptr(), tq.data_ptr(),
+                         tg.data_ptr(), tv.data_ptr(), int(tq.shape[1]), rv.data_ptr(), rp.data_ptr(),
+                         rc.data_ptr(), int(rv.shape[1]), int(rc.shape[1]), float(resolution),
+                         out["q_new"].data_ptr(), out["vid_new"].data_ptr(), out["g_new"].data_ptr(),
+                         out["alive"].data_ptr(), out["edge_a"].data_ptr(), out["edge_b"].data_ptr(),
+                         out["n_states"].data_ptr())
+        self.ctx.check(self.ctx._lib.mrpop_extend(self.ctx.handle, self._h, C.byref(b), self.ctx.stream()))
+        return {k: v.cpu().numpy() for k, v in out.items()}
+
     def plan(self, q_start, q_goal, path_cap: int = 4096, raise_on_error: bool = True, **params) -> "PlanResult":
         """mrpop_plan on host start/goal; keyword arguments override the
         defaults of mrpop_plan_params."""
@@ -511,10 +565,12 @@ class Scene:
             bool(kept.value)
 
     def plan_with_history(self, q_start, q_goal, max_entries: int = 64, max_waypoints: int = 65536,
-                          path_cap: int = 4096, raise_on_error: bool = True, **params):
+                          path_cap: int = 4096, raise_on_error: bool = True, roadmaps: bool = False, **params):
         """mrpop_plan_with_history: the plan's result and its incumbents,
         cheapest first (at most max_entries entries and max_waypoints rows),
-        plus the number of incumbents found."""
+        plus the number of incumbents found.  roadmaps=True also returns each
+        waypoint's roadmap vertices (Incumbent.vertex_ids) and the arms'
+        final roadmaps in stats["roadmaps"]: [(vertices [n][7], edges [m][2])]."""
         lib = self.ctx._lib
         pp = PlanParams()
         lib.mrpop_plan_params_default(C.byref(pp))
@@ -533,8 +589,15 @@ class Scene:
         costs = np.zeros(max(1, max_entries), np.float32)
         found_s = np.zeros(max(1, max_entries), np.float64)
         found_r = np.zeros(max(1, max_entries), np.int32)
+        R = self.n_robots
+        vids = np.zeros((max(1, max_waypoints), R), np.int32)
+        rm_cap = int(params.get("max_roadmap_nodes", pp.max_roadmap_nodes))
+        rm_v = np.zeros((R, rm_cap, 8), np.float32) if roadmaps else None
+        rm_e = np.zeros((R, rm_cap * 32, 2), np.int32) if roadmaps else None
         h = _PlanHistory(wp.ctypes.data, max_waypoints, off.ctypes.data, costs.ctypes.data, found_s.ctypes.data,
-                         found_r.ctypes.data, max_entries, 0, 0)
+                         found_r.ctypes.data, max_entries, 0, 0, vids.ctypes.data if roadmaps else None,
+                         rm_v.ctypes.data if roadmaps else None, rm_e.ctypes.data if roadmaps else None,
+                         rm_cap if roadmaps else 0, rm_cap * 32 if roadmaps else 0)
         rc = lib.mrpop_plan_with_history(self.ctx.handle, self._h, qs.ctypes.data, qg.ctypes.data, C.byref(pp),
                                          path.ctypes.data, path_cap, C.byref(plen), C.byref(cost), C.byref(st),
                                          C.byref(h))
@@ -544,8 +607,12 @@ class Scene:
         name = STATUS_NAMES.get(rc, str(rc))
         if rc != 0 and raise_on_error:
             raise MrpopError(rc, lib.mrpop_last_error(self.ctx.handle).decode())
-        hist = [Incumbent(wp[off[k]:off[k + 1]].copy(), float(costs[k]), float(found_s[k]), int(found_r[k]))
+        hist = [Incumbent(wp[off[k]:off[k + 1]].copy(), float(costs[k]), float(found_s[k]), int(found_r[k]),
+                          vids[off[k]:off[k + 1]].copy() if roadmaps else None)
                 for k in range(h.n_written)]
+        if roadmaps:
+            stats["roadmaps"] = [(rm_v[r, :min(h.rm_n_vertices[r], rm_cap), :7].copy(),
+                                  rm_e[r, :min(h.rm_n_edges[r], rm_cap * 32)].copy()) for r in range(R)]
         return PlanResult(name, path[:plen.value].copy() if rc == 0 else None, float(cost.value), stats), hist, \
             h.n_entries
 

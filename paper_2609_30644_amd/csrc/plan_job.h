@@ -36,13 +36,19 @@ class PlanJob {
   const std::string &error() const { return err_; }
   // Every incumbent of the call in discovery order (strictly decreasing cost).
   struct Incumbent {
-    std::vector<float> path;  // [len][D], start to goal
+    std::vector<float> path;    // [len][D], start to goal
+    std::vector<int32_t> vids;  // [len][R]: each waypoint's roadmap vertex per arm (-1: unknown)
     float cost;
     double found_s;
     int32_t round;
   };
   const std::vector<Incumbent> &history() const { return history_; }
   int dof() const { return D_; }
+  int n_robots() const { return R_; }
+  // After run: each arm's roadmap (vertex rows [rm_cap][kRmStride] and edge
+  // list [edge_cap][2], at most the given capacities) into host arrays, and
+  // the full counts; waits for the copies.
+  mrpop_status export_roadmaps(float *V, int32_t v_cap, int32_t *E, int32_t e_cap, int32_t *n_v, int32_t *n_e);
   // Device bytes held by the instance (arena and sub-scenes).
   size_t device_bytes() const { return device_bytes_; }
   // Device bytes an instance of `scene` with `params` would hold (an upper
@@ -89,13 +95,14 @@ class PlanJob {
   void *arena_ = nullptr;
   float *qs_, *qg_, *rm_V_, *cand_, *pair_qa_, *pair_qb_, *tq_[2], *tg_[2], *q_rand_, *c_rand_, *q_new_, *g_new_,
       *ea_, *eb_, *budget_, *ca_, *cb_, *path_d_;
+  int32_t *path_vid_d_;  // [path_max][R] roadmap vertices of the extracted path
   // per arm r: cand_ [r][cand_batch][kRmStride], cand_valid_ and cand_codes_ [r][cand_batch],
   // rm_i_ [r][kRmInts] (taken, pair count, pair count when writing,
   // connected), uf_ [r][rm_cap] union-find parents, cnt_ [2 + r][16]
   int32_t *rm_rowptr_, *rm_col_, *rm_edges_, *rm_nv_, *rm_ne_, *pair_ids_, *rm_i_, *uf_, *deg_, *tvid_[2],
       *tpar_[2], *tn_[2], *near_idx_, *vid_new_, *ins_idx_, *conn_idx_, *d_nj_, *d_qoff_,
       *cand_codes_, *pair_codes_;
-  int32_t *codes_ext_, *codes_conn_;  // [PC] state-count codes of the extension and connection edges
+  int32_t *codes_ext_, *codes_conn_;  // [2 PC] state-count codes of the round's batch; codes_conn_ = codes_ext_ + PC
   uint8_t *cand_valid_, *pair_valid_, *alive_, *valid_, *cvalid_;
   uint64_t *cnt_;  // [2 + R][16]: counters of the extension, connection and per-arm roadmap validations
   RoundStatus *status_;

@@ -311,20 +311,19 @@ size_t PlanJob::plan_arena_(void *base) {
   ar.add(&g_new_, PC);
   ar.add(&vid_new_, (size_t)R * PC);
   ar.add(&alive_, PC);
-  ar.add(&ea_, (size_t)PC * D);
-  ar.add(&eb_, (size_t)PC * D);
-  ar.add(&valid_, PC);
+  // a round's edge batch: extension edges in rows [0, PC), connection edges
+  // in rows [PC, 2 PC); their bits and state-count codes alike
+  ar.add(&ea_, (size_t)2 * PC * D);
+  ar.add(&eb_, (size_t)2 * PC * D);
+  ar.add(&valid_, 2 * (size_t)PC);
   ar.add(&ins_idx_, PC);
   ar.add(&budget_, PC);
   ar.add(&conn_idx_, PC);
-  ar.add(&ca_, (size_t)PC * D);
-  ar.add(&cb_, (size_t)PC * D);
-  ar.add(&cvalid_, PC);
-  ar.add(&codes_ext_, PC);
-  ar.add(&codes_conn_, PC);
+  ar.add(&codes_ext_, 2 * (size_t)PC);
   ar.add(&cnt_, (size_t)(2 + R) * 16);
   ar.add(&status_, 1);
   ar.add(&path_d_, (size_t)path_max_ * D);
+  ar.add(&path_vid_d_, (size_t)path_max_ * R);
   ar.add(&d_nj_, R);
   ar.add(&d_qoff_, R);
   if (base) ar.assign(base);
@@ -369,6 +368,10 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
     return e == hipErrorOutOfMemory ? fail_(MRPOP_E_NOMEM, "plan: device memory") : hip_fail_(e, "hipMalloc(plan)");
   }
   plan_arena_(arena_);
+  ca_ = ea_ + (size_t)PC_ * D_;
+  cb_ = eb_ + (size_t)PC_ * D_;
+  cvalid_ = valid_ + PC_;
+  codes_conn_ = codes_ext_ + PC_;
   device_bytes_ = arena_bytes;
   // the small pinned buffers share one block (256-byte aligned parts)
   const size_t up_floats = 2 * (size_t)D + (size_t)R * 2 * kRmStride;
@@ -632,6 +635,27 @@ static double path_cost(const std::vector<float> &p, int D) {
   return cost;
 }
 
+mrpop_status PlanJob::export_roadmaps(float *V, int32_t v_cap, int32_t *E, int32_t e_cap, int32_t *n_v,
+                                      int32_t *n_e) {
+  const int R = R_;
+  std::vector<int32_t> ne((size_t)R, 0);
+  hipError_t e = hipSetDevice(ctx_->device);
+  if (e == hipSuccess && !P_.direct) e = hipMemcpy(ne.data(), rm_ne_, sizeof(int32_t) * R, hipMemcpyDeviceToHost);
+  for (int r = 0; r < R && e == hipSuccess; ++r) {
+    const int nv = P_.direct ? 0 : rm_n_[r];
+    n_v[r] = nv;
+    n_e[r] = ne[r];
+    if (V && v_cap > 0 && nv > 0)
+      e = hipMemcpy(V + (size_t)r * v_cap * kRmStride, rm_V_ + (size_t)r * rm_cap_ * kRmStride,
+                    sizeof(float) * kRmStride * std::min(nv, v_cap), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && E && e_cap > 0 && ne[r] > 0)
+      e = hipMemcpy(E + (size_t)r * e_cap * 2, rm_edges_ + (size_t)r * edge_cap_ * 2,
+                    sizeof(int32_t) * 2 * std::min(std::min(ne[r], edge_cap_), e_cap), hipMemcpyDeviceToHost);
+  }
+  if (e != hipSuccess) return hip_fail_(e, "plan: roadmap export");
+  return MRPOP_OK;
+}
+
 void PlanJob::set_incumbent(const std::vector<float> &path) {
   const float c = (float)path_cost(path, D_);
   if (c < c_best_) {
@@ -676,6 +700,7 @@ mrpop_status PlanJob::run(Exec &ex) {
   int rnd = 0, it = 0;
   bool overflow_no_path = false;
   std::vector<float> hpath;
+  std::vector<int32_t> hvid;
   while (it < P_.max_iterations && rnd < P_.max_rounds && !out_of_time_()) {
     if (!P_.direct) TRY(roadmap_(ex, it));
     // fresh trees: 0 rooted at the start, 1 at the goal
@@ -692,68 +717,71 @@ mrpop_status PlanJob::run(Exec &ex) {
                                          qs_, qg_, tq_[a], tcap_, q_rand_, c_rand_},
                               NearestArgs{tq_[a], tg_[a], n_t[a], D, 1, tcap_, q_rand_, D,
                                           cb < INFINITY ? c_rand_ : nullptr, PC, near_idx_}};
-      if (P_.direct) {
-        SUBMIT(Op::SampleNear, sample_near, sn);
-        SUBMIT(Op::Steer, steer,
-               SteerArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a], tg_[a], tcap_,
-                         P_.step, q_new_, vid_new_, g_new_, alive_, ea_, eb_, P_.resolution, codes_ext_});
-      } else {
-        SUBMIT(Op::SampleNearExtend, sample_near_extend,
-               SampleNearExtendArgs{sn, ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr,
-                                                   tq_[a], tvid_[a], tg_[a], tcap_, rm_V_, rm_rowptr_, rm_col_,
-                                                   rm_cap_, col_cap_, d_nj_, d_qoff_, q_new_, vid_new_, g_new_,
-                                                   alive_, ea_, eb_, P_.resolution, codes_ext_}});
-      }
-      TRY(validate_(ex, scene_, ea_, eb_, PC, P_.resolution, valid_, cnt_, codes_ext_));
-      SUBMIT(Op::InsertConn, insert_conn,
-             InsertConnArgs{InsertArgs{PC, D, R, alive_, valid_, q_new_, g_new_, vid_new_, near_idx_, tq_[a], tg_[a],
-                                       tvid_[a], tpar_[a], tn_[a], tcap_, cb, ins_idx_, budget_, status_, n_t[a]},
-                            NearestArgs{tq_[b], tg_[b], n_t[b], D, 1, tcap_, q_new_, D, budget_, PC, conn_idx_},
+      // front half: sample, nearest, extension, then the connection search
+      // and edge; one validation of both halves; back half: insertion and
+      // selection (a round is three launches and one host round trip)
+      SUBMIT(Op::RoundFront, round_front,
+             RoundFrontArgs{sn,
+                            ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a],
+                                       tvid_[a], tg_[a], tcap_, rm_V_, rm_rowptr_, rm_col_, rm_cap_, col_cap_, d_nj_,
+                                       d_qoff_, q_new_, vid_new_, g_new_, alive_, ea_, eb_, P_.resolution, codes_ext_,
+                                       P_.direct, P_.step},
+                            cb, budget_, NearestArgs{tq_[b], tg_[b], n_t[b], D, 1, tcap_, q_new_, D, budget_, PC,
+                                                     conn_idx_},
                             ConnArgs{PC, D, conn_idx_, q_new_, tq_[b], tcap_, ca_, cb_, P_.resolution, codes_conn_}});
-      TRY(validate_(ex, scene_, ca_, cb_, PC, P_.resolution, cvalid_, cnt_ + 16, codes_conn_));
-      SUBMIT(Op::Select, select,
-             SelectArgs{PC, D, ins_idx_, conn_idx_, cvalid_, q_new_, g_new_, tq_[b], tg_[b], tcap_, cnt_, cnt_ + 16,
-                        status_, &pin_->status, (uint32_t)rnd + 1u});
+      TRY(validate_(ex, scene_, ea_, eb_, 2 * (int64_t)PC, P_.resolution, valid_, cnt_, codes_ext_));
+      SUBMIT(Op::InsertSelect, insert_select,
+             InsertSelectArgs{PC, D, R, alive_, valid_, cvalid_, q_new_, g_new_, vid_new_, near_idx_, conn_idx_,
+                              tq_[a], tg_[a], tvid_[a], tpar_[a], tn_[a], tcap_, n_t[a], tq_[b], tg_[b], ins_idx_,
+                              codes_conn_, cnt_, status_, &pin_->status, (uint32_t)rnd + 1u});
       {
         const hipError_t e_ = ex.wait_flag(&pin_->status.seq, (uint32_t)rnd + 1u);
         if (e_ != hipSuccess) return hip_fail_(e_, "round status");
       }
       const RoundStatus rsx = pin_->status;
       st_.edge_states += rsx.states_ext + rsx.states_conn;
+      st_.speculative_edge_states += rsx.states_spec;
       n_t[a] += rsx.inserted;
       if (rsx.overflow) st_.capacity_hit = 1;
       ++rnd;
       if (rsx.found) {
         SUBMIT(Op::Path, path,
                PathArgs{rsx.a_idx, rsx.b_idx, D, tcap_, path_max_, tpar_[a], tpar_[b], tq_[a], tq_[b], path_d_,
-                        &pin_->ints[0]});
+                        &pin_->ints[0], R, tvid_[a], tvid_[b], path_vid_d_});
         SYNC();
         const int len = pin_->ints[0];
         if (len > path_max_ || len < 2) {
           st_.capacity_hit = 1;
         } else {
-          const size_t need = (size_t)len * D;
-          if (need > pin_path_cap_) {
+          const size_t need = (size_t)len * D, need_v = (size_t)len * R;
+          const size_t bytes = sizeof(float) * need + sizeof(int32_t) * need_v;
+          if (bytes > pin_path_cap_) {
             if (pin_path_) (void)hipHostFree(pin_path_);
             pin_path_ = nullptr;
             pin_path_cap_ = 0;
-            const hipError_t e = hipHostMalloc((void **)&pin_path_, sizeof(float) * need);
+            const hipError_t e = hipHostMalloc((void **)&pin_path_, bytes);
             if (e != hipSuccess) return hip_fail_(e, "hipHostMalloc(path)");
-            pin_path_cap_ = need;
+            pin_path_cap_ = bytes;
           }
+          int32_t *pin_vid = (int32_t *)(pin_path_ + need);
           TRY(copy_(ex, pin_path_, path_d_, sizeof(float) * need));
+          TRY(copy_(ex, pin_vid, path_vid_d_, sizeof(int32_t) * need_v));
           SYNC();
           hpath.assign(pin_path_, pin_path_ + need);
+          hvid.assign(pin_vid, pin_vid + need_v);
           if (a == 1) {  // tree 1 is rooted at the goal: orient start -> goal
-            for (int x = 0, y = len - 1; x < y; ++x, --y)
+            for (int x = 0, y = len - 1; x < y; ++x, --y) {
               std::swap_ranges(hpath.begin() + (size_t)x * D, hpath.begin() + (size_t)(x + 1) * D,
                                hpath.begin() + (size_t)y * D);
+              std::swap_ranges(hvid.begin() + (size_t)x * R, hvid.begin() + (size_t)(x + 1) * R,
+                               hvid.begin() + (size_t)y * R);
+            }
           }
           const double cost = path_cost(hpath, D);
           if ((float)cost < c_best_) {  // strictly cheaper incumbents only
             c_best_ = (float)cost;
             best_path_ = hpath;
-            history_.push_back(Incumbent{hpath, c_best_, elapsed_(), rnd - 1});
+            history_.push_back(Incumbent{hpath, hvid, c_best_, elapsed_(), rnd - 1});
             if (st_.n_costs < 64) st_.costs[st_.n_costs++] = c_best_;
             ++st_.solutions;
             if (st_.first_round < 0) {
@@ -835,6 +863,43 @@ mrpop_status mrpop_nearest(mrpop_ctx *ctx, const float *vertices, const float *c
   return MRPOP_OK;
 }
 
+mrpop_status mrpop_extend(mrpop_ctx *ctx, const mrpop_scene *scene, const mrpop_extend_batch *b, void *stream) {
+  if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "extend: ctx is NULL");
+  if (!scene || scene->ctx != ctx) return fail(ctx, MRPOP_E_INVALID_ARG, "extend: scene not from this ctx");
+  if (!b) return fail(ctx, MRPOP_E_INVALID_ARG, "extend: batch is NULL");
+  if (b->n < 0 || b->tree_cap < 1 || b->rm_cap < 1 || b->col_cap < 0)
+    return fail(ctx, MRPOP_E_INVALID_ARG, "extend: sizes out of range");
+  if (b->n == 0) return MRPOP_OK;
+  if (!b->near_idx || !b->q_rand || !b->tree_q || !b->tree_g || !b->tree_vid || !b->rm_vertices || !b->rm_rowptr ||
+      (b->col_cap > 0 && !b->rm_col) || !b->q_new || !b->vid_new || !b->g_new || !b->alive ||
+      (!b->edge_a) != (!b->edge_b))
+    return fail(ctx, MRPOP_E_INVALID_ARG, "extend: NULL buffer");
+  if (b->n_states && !(b->resolution > 0.f && std::isfinite(b->resolution)))
+    return fail(ctx, MRPOP_E_INVALID_ARG, "extend: resolution must be finite and > 0");
+  const int R = scene->n_robots;
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  // the arms' joint counts and offsets for the kernel, in the context's scratch
+  std::vector<int32_t> h((size_t)2 * R);
+  for (int r = 0, off = 0; r < R; ++r) {
+    h[r] = scene->nj[r];
+    h[R + r] = off;
+    off += scene->nj[r];
+  }
+  void *d = nullptr;
+  mrpop_status st = scratch_slot(ctx, 4, sizeof(int32_t) * h.size(), &d);
+  if (st != MRPOP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipStreamSynchronize(s), "extend: wait for the stream");  // an earlier call may still read the slot
+  HIP_TRY(hipMemcpy(d, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice), "extend: arm table");
+  const int32_t *d_nj = (const int32_t *)d, *d_off = d_nj + R;
+  ExtendArgs a{b->n,           scene->dof,      R,           b->near_idx,  b->q_rand,   b->c_rand,  b->tree_q,
+               b->tree_vid,    b->tree_g,       b->tree_cap, b->rm_vertices, b->rm_rowptr, b->rm_col, b->rm_cap,
+               b->col_cap,     d_nj,            d_off,       b->q_new,     b->vid_new,  b->g_new,   b->alive,
+               b->edge_a,      b->edge_b,       b->resolution, b->n_states};
+  HIP_TRY(launch_extend(a, s), "extend launch");
+  return MRPOP_OK;
+}
+
 mrpop_status mrpop_sample(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
                           const float *root, float c_best, uint64_t seed, uint64_t round, int64_t first, int64_t n,
                           float *out_q, float *out_c, void *stream) {
@@ -853,12 +918,13 @@ mrpop_status mrpop_sample(mrpop_ctx *ctx, const mrpop_scene *scene, const float 
 
 }  // extern "C"
 
-// Writes job's incumbents into hist, cheapest first, as many as fit.
-static void write_history(const PlanJob &job, mrpop_plan_history *hist) {
+// Writes job's incumbents into hist, cheapest first, as many as fit, with
+// their roadmap vertices and the roadmaps when asked for.
+static mrpop_status write_history(PlanJob &job, mrpop_plan_history *hist) {
   const auto &h = job.history();
   hist->n_entries = (int32_t)h.size();
   hist->n_written = 0;
-  const int D = job.dof();
+  const int D = job.dof(), R = job.n_robots();
   int64_t row = 0;
   if (hist->entry_cap > 0) hist->offsets[0] = 0;
   // discovery order has strictly decreasing costs: the ranking is its reverse
@@ -867,6 +933,7 @@ static void write_history(const PlanJob &job, mrpop_plan_history *hist) {
     const int64_t len = (int64_t)(h[k].path.size() / D);
     if (n >= hist->entry_cap || row + len > hist->waypoint_cap) break;
     std::memcpy(hist->waypoints + row * D, h[k].path.data(), sizeof(float) * h[k].path.size());
+    if (hist->vertex_ids) std::memcpy(hist->vertex_ids + row * R, h[k].vids.data(), sizeof(int32_t) * h[k].vids.size());
     row += len;
     hist->offsets[n + 1] = (int32_t)row;
     hist->costs[n] = h[k].cost;
@@ -874,6 +941,11 @@ static void write_history(const PlanJob &job, mrpop_plan_history *hist) {
     if (hist->found_round) hist->found_round[n] = h[k].round;
     hist->n_written = n + 1;
   }
+  if (hist->rm_vertices || hist->rm_edges)
+    return job.export_roadmaps(hist->rm_vertices, hist->rm_vertex_cap, hist->rm_edges, hist->rm_edge_cap,
+                               hist->rm_n_vertices, hist->rm_n_edges);
+  for (int r = 0; r < R; ++r) hist->rm_n_vertices[r] = hist->rm_n_edges[r] = 0;
+  return MRPOP_OK;
 }
 
 static mrpop_status plan_impl(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
@@ -887,7 +959,8 @@ static mrpop_status plan_impl(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   if (hist) {
     hist->n_entries = hist->n_written = 0;
     if (hist->entry_cap < 0 || hist->waypoint_cap < 0 ||
-        (hist->entry_cap > 0 && (!hist->offsets || !hist->costs)) || (hist->waypoint_cap > 0 && !hist->waypoints))
+        (hist->entry_cap > 0 && (!hist->offsets || !hist->costs)) || (hist->waypoint_cap > 0 && !hist->waypoints) ||
+        (hist->rm_vertices && hist->rm_vertex_cap < 1) || (hist->rm_edges && hist->rm_edge_cap < 1))
       return fail(ctx, MRPOP_E_INVALID_ARG, "plan: bad history buffers");
   }
   *path_len = 0;
@@ -899,7 +972,10 @@ static mrpop_status plan_impl(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
     if (incumbent) job.set_incumbent(*incumbent);
     PlainExec ex(ctx, nullptr);
     st = job.run(ex);
-    if (hist) write_history(job, hist);
+    if (hist) {
+      const mrpop_status hs = write_history(job, hist);
+      if (st == MRPOP_OK && hs != MRPOP_OK) st = hs;
+    }
   }
   if (stats_opt) *stats_opt = job.stats();
   if (st != MRPOP_OK) return fail(ctx, st, job.error());

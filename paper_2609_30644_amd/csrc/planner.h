@@ -6,7 +6,7 @@
 namespace mrpop {
 
 constexpr int kMaxDof = MRPOP_MAX_ROBOTS * MRPOP_MAX_JOINTS;
-constexpr int kRmStride = 8;  // floats per roadmap vertex row (7 joints + pad)
+constexpr int kRmStride = MRPOP_RM_STRIDE;  // floats per roadmap vertex row (7 joints + pad)
 
 // Purposes of the counter-based random streams.
 constexpr uint64_t kPurposeQ = 1, kPurposeBall = 2, kPurposeC = 3, kPurposeRoadmap = 4;
@@ -55,9 +55,11 @@ struct ExtendArgs {
   int32_t *vid_new;           // [R][n]
   float *g_new;               // [n]
   uint8_t *alive;             // [n]
-  float *edge_a, *edge_b;     // [n][dim]
+  float *edge_a, *edge_b;     // [n][dim], or both null
   float res;                  // resolution of the edge's validation
   int32_t *n_codes;           // [n] or null: state-count code of each edge
+  int direct;                 // 1: no roadmaps, steer toward q_rand by at most `step`
+  float step;
 };
 
 struct RoundStatus {
@@ -66,40 +68,7 @@ struct RoundStatus {
   int32_t inserted, overflow;
   uint32_t seq;  // in the host copy: stored last, with a system-scope release (the round's number)
   int64_t states_ext, states_conn;
-};
-
-struct InsertArgs {
-  int n, dim, n_robots;
-  const uint8_t *alive, *valid;
-  const float *q_new, *g_new;
-  const int32_t *vid_new, *near_idx;
-  float *tree_q, *tree_g;
-  int32_t *tree_vid, *tree_parent, *tree_n;
-  int tree_cap;
-  float c_best;
-  int32_t *ins_idx;
-  float *budget;
-  RoundStatus *status;
-  int n_before;  // vertices in the tree before this insertion (the host's count)
-};
-
-// Direct-mode extension: from q_near toward q_rand by at most `step`.
-struct SteerArgs {
-  int n, dim, n_robots;
-  const int32_t *near_idx;    // [n]
-  const float *q_rand;        // [n][dim]
-  const float *c_rand;        // [n] or null
-  const float *tree_q;        // SoA [dim][tree_cap]
-  const float *tree_g;
-  int tree_cap;
-  float step;
-  float *q_new;               // [n][dim]
-  int32_t *vid_new;           // [R][n] (zeros: no roadmap)
-  float *g_new;               // [n]
-  uint8_t *alive;             // [n]
-  float *edge_a, *edge_b;     // [n][dim]
-  float res;                  // resolution of the edge's validation
-  int32_t *n_codes;           // [n] or null: state-count code of each edge
+  int64_t states_spec;  // states of connection edges checked for candidates that were not inserted
 };
 
 struct ConnArgs {
@@ -112,39 +81,53 @@ struct ConnArgs {
   int32_t *n_codes;   // [n] or null: state-count code of each edge
 };
 
-struct SelectArgs {
-  int n, dim;
-  const int32_t *ins_idx, *conn_idx;
-  const uint8_t *cvalid;
-  const float *q_new, *g_new, *other_q, *other_g;
-  int tree_cap;
-  const uint64_t *states_ext, *states_conn;  // validation counters (index 1: edge states)
-  RoundStatus *status;
-  RoundStatus *status_out;  // or null: receives the round's finished record (e.g. pinned host memory)
-  uint32_t seq;             // written to status_out->seq after the rest of the record
-};
-
-// Fused round steps, one workgroup per candidate: the sample and its
-// nearest vertex in the extended tree (q.queries = s.out_q, q.budgets =
-// s.out_c or null); the insertion, the nearest vertex of the other tree
-// (q.queries = ins.q_new, q.budgets = ins.budget) and the connection edge
-// (c.conn_idx = q.out_idx).
+// The sample of each candidate and its nearest vertex in the extended tree
+// (q.queries = s.out_q, q.budgets = s.out_c or null).
 struct SampleNearArgs {
   SampleArgs s;
   NearestArgs q;
 };
 
-// Sample, nearest vertex and roadmap extension of each candidate in one
-// launch (e.n == sn.s.n; e.near_idx is sn.q's output).
-struct SampleNearExtendArgs {
+// The front half of a search round, one workgroup (256 threads) per
+// candidate: the sample and its nearest vertex in the extended tree (sn), the
+// extension (e: along the roadmaps, or a steer when e.direct; e.near_idx is
+// sn.q's output), then, before the extension edge is known to be free, the
+// connection: the budget c_best - g_new (-1 for a dead candidate: nothing is
+// admissible), the nearest vertex of the other tree under it (q2: queries =
+// e.q_new, budgets = budget) and the connection edge (c: conn_idx =
+// q2.out_idx).  The extension edges and the connection edges are rows
+// [0, n) and [n, 2n) of one batch, checked by one validation.
+struct RoundFrontArgs {
   SampleNearArgs sn;
   ExtendArgs e;
+  float c_best;
+  float *budget;  // [n]
+  NearestArgs q2;
+  ConnArgs c;
 };
 
-struct InsertConnArgs {
-  InsertArgs ins;
-  NearestArgs q;
-  ConnArgs c;
+// The back half, one workgroup: the survivors (alive, extension edge free)
+// enter the extended tree in candidate order up to its capacity; among the
+// inserted candidates whose connection edge is free, the one of least total
+// cost g_new + |q_new - q_conn| + g_conn (ties: lowest candidate) is the
+// round's result, written to the status record and, with the sequence
+// number stored last, to status_out.
+struct InsertSelectArgs {
+  int n, dim, n_robots;
+  const uint8_t *alive, *valid, *cvalid;  // valid: extension edges; cvalid: connection edges
+  const float *q_new, *g_new;
+  const int32_t *vid_new, *near_idx, *conn_idx;
+  float *tree_q, *tree_g;
+  int32_t *tree_vid, *tree_parent, *tree_n;
+  int tree_cap;
+  int n_before;  // vertices in the tree before this insertion (the host's count)
+  const float *other_q, *other_g;
+  int32_t *ins_idx;
+  const int32_t *codes_conn;  // [n] state-count codes of the connection edges
+  const uint64_t *counters;   // the round's validation counters ([1]: states of both halves)
+  RoundStatus *status;
+  RoundStatus *status_out;    // or null: receives the finished record (e.g. pinned host memory)
+  uint32_t seq;
 };
 
 struct PathArgs {
@@ -153,6 +136,9 @@ struct PathArgs {
   const float *q_a, *q_b;
   float *out;
   int32_t *out_len;
+  int n_robots;
+  const int32_t *vid_a, *vid_b;  // SoA [n_robots][tree_cap]: each vertex's roadmap vertex per arm
+  int32_t *out_vid;              // [cap][n_robots]
 };
 
 struct TreeRootArgs {
@@ -232,8 +218,8 @@ struct CopyArgs {
 };
 
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
+hipError_t launch_extend(const ExtendArgs &a, hipStream_t s);
 hipError_t launch_nearest(const NearestArgs &a, hipStream_t s);
-hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_path(const PathArgs &a, hipStream_t s);
 hipError_t launch_tree_root(const TreeRootArgs &a, hipStream_t s);
 hipError_t launch_rm_sample(const RmSampleArgs &a, hipStream_t s);
@@ -251,10 +237,10 @@ uint64_t roadmap_key(uint64_t seed, uint64_t stream_a, uint64_t stream_b);
 // blockIdx.y of the device array `args`; grid_x = the most blocks any record
 // needs, records that need fewer leave early).
 enum class Op : uint8_t {
-  Sample, Nearest, Steer, Select, Path, TreeRoot,
-  RmSample, RmAccept, RmPairs, RmBfs, RmUnion, Fill, Copy, SampleNear, SampleNearExtend, InsertConn, Validate
+  Sample, Nearest, Path, TreeRoot, RmSample, RmAccept, RmPairs, RmBfs, RmUnion, Fill, Copy, RoundFront,
+  InsertSelect, Validate
 };
-constexpr int kNumOps = 17;
+constexpr int kNumOps = 14;
 constexpr int kUfMaxVertices = 32768;  // roadmap vertices per arm (union-find in LDS)
 
 // Blocks one record needs (0: nothing to do).
@@ -286,8 +272,6 @@ struct Cmd {
   union {
     SampleArgs sample;
     NearestArgs nearest;
-    SteerArgs steer;
-    SelectArgs select;
     PathArgs path;
     TreeRootArgs tree_root;
     RmSampleArgs rm_sample;
@@ -297,9 +281,8 @@ struct Cmd {
     RmUnionArgs rm_union;
     FillArgs fill;
     CopyArgs copy;
-    SampleNearArgs sample_near;
-    SampleNearExtendArgs sample_near_extend;
-    InsertConnArgs insert_conn;
+    RoundFrontArgs round_front;
+    InsertSelectArgs insert_select;
     ValidateReq val;
   };
   const void *args() const { return &sample; }

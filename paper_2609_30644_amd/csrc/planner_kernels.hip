@@ -242,30 +242,50 @@ __device__ __forceinline__ void nearest_body(const NearestArgs &a, int bx) {
 
 // One wavefront per candidate.  The arms are searched at the same time, each
 // by a group of lanes (64 / R rounded down to a power of two, at least 4):
-// the group scans the roadmap neighbours of the arm's vertex in q_near and
-// keeps the neighbour best aligned with the sample direction: largest
-// cosine, ties to the lowest neighbour id, so the result does not depend on
-// the order of an adjacency row or on how lanes share it.  The arm stays if
-// no cosine is positive.  The candidate survives if some arm moves and,
-// under a finite budget, g_near + |q_new - q_near| < c_rand.  Writes the edge
-// to validate (q_near -> q_new); dropped candidates get a null edge at q_near.
-// One wave per candidate (no LDS, no barrier).
+// the group scans the roadmap neighbours u of the arm's vertex v in q_near.
+// Under a finite budget only admissible neighbours count: moving this arm
+// alone must keep g_near + |V_u - V_v| < c_rand.  Among them the group keeps
+// the one best aligned with the sample direction: largest cosine, ties to the
+// lowest neighbour id, so the result does not depend on the order of an
+// adjacency row or on how lanes share it; the arm stays if no cosine is
+// positive.  If the arms' moves together exceed the budget, moving arms go
+// back to staying, least aligned first (ties: the higher arm index first),
+// until g_near + |q_new - q_near| < c_rand; the last moving arm always fits
+// on its own.  The candidate survives if some arm moves.  |q_new - q_near|^2
+// is the sum of the moving arms' |V_u - V_v|^2 (each summed joint by joint)
+// in a fixed butterfly order.  Writes the edge to validate (q_near -> q_new);
+// dropped candidates get a null edge at q_near.  One wave per candidate (no
+// LDS, no barrier).
 __device__ __forceinline__ void extend_one(const ExtendArgs &a, int i, int lane) {
   const int D = a.dim, R = a.n_robots;
   const int near = a.near_idx[i];
-  float *ea = a.edge_a + (int64_t)i * D, *eb = a.edge_b + (int64_t)i * D, *qn = a.q_new + (int64_t)i * D;
+  float *ea = a.edge_a ? a.edge_a + (int64_t)i * D : nullptr;
+  float *eb = a.edge_b ? a.edge_b + (int64_t)i * D : nullptr;
+  float *qn = a.q_new + (int64_t)i * D;
   const float *qr = a.q_rand + (int64_t)i * D;
   if (near < 0) {
-    if (lane == 0) a.alive[i] = 0;
-    for (int j = lane; j < D; j += kWave) ea[j] = eb[j] = qn[j] = a.tree_q[(int64_t)j * a.tree_cap];
+    if (lane == 0) {
+      a.alive[i] = 0;
+      a.g_new[i] = INFINITY;
+    }
+    for (int j = lane; j < D; j += kWave) {
+      const float y = a.tree_q[(int64_t)j * a.tree_cap];
+      qn[j] = y;
+      if (ea) ea[j] = eb[j] = y;
+    }
+    for (int r = lane; r < R; r += kWave) a.vid_new[(int64_t)r * a.n + i] = -1;
     if (lane == 0 && a.n_codes) a.n_codes[i] = 1;  // a null edge at a tree vertex (finite)
     return;
   }
+  const float g_near = a.tree_g[near];
+  const float c_rand = a.c_rand ? a.c_rand[i] : INFINITY;
+  const bool bounded = c_rand < INFINITY;
   int gs = kWave;  // lanes per arm (MRPOP_MAX_ROBOTS <= 16 arms: at least 4)
   while (gs > 4 && gs * R > kWave) gs >>= 1;
   const int g = lane / gs, sub = lane & (gs - 1);
-  // lane r * gs ends with arm r's choice
+  // lane r * gs ends with arm r's choice, its cosine and |V_u - V_v|^2
   int best = -1, v = -1;
+  float best_cos = 0.f, best_d2 = 0.f;
   if (g < R) {
     const int r = g;
     const int nj = a.nj[r], q0 = a.q_off[r];
@@ -280,7 +300,6 @@ __device__ __forceinline__ void extend_one(const ExtendArgs &a, int i, int lane)
       dn2 = fmaf(dir[j], dir[j], dn2);
     }
     best = v;
-    float best_cos = 0.f;
     if (dn2 > 0.f) {
       const float dn = sqrtf(dn2);
       const int e0 = rp[v], e1 = min(rp[v + 1], a.rm_col_cap);
@@ -293,10 +312,12 @@ __device__ __forceinline__ void extend_one(const ExtendArgs &a, int i, int lane)
           en2 = fmaf(ej, ej, en2);
         }
         if (en2 <= 0.f) continue;
+        if (bounded && !(g_near + sqrtf(en2) < c_rand)) continue;  // not admissible even alone
         const float cs = dot / (sqrtf(en2) * dn);
         if (cs > best_cos || (cs == best_cos && best != v && u < best)) {
           best_cos = cs;
           best = u;
+          best_d2 = en2;
         }
       }
     }
@@ -304,66 +325,67 @@ __device__ __forceinline__ void extend_one(const ExtendArgs &a, int i, int lane)
     for (int d = gs / 2; d > 0; d >>= 1) {
       const float oc = __shfl_xor(best_cos, d, kWave);
       const int ob = __shfl_xor(best, d, kWave);
+      const float od = __shfl_xor(best_d2, d, kWave);
       const bool o_moves = ob != v, moves = best != v;
       if (o_moves && (!moves || oc > best_cos || (oc == best_cos && ob < best))) {
         best_cos = oc;
         best = ob;
+        best_d2 = od;
       }
     }
   }
   // (a group is active or idle as a whole, so the shuffles above read active lanes only)
-  const bool moved = __ballot(g < R && sub == 0 && best != v) != 0ull;
-  // q_new and q_near, composite joint k in lane k % 64 (slot k / 64), loaded
-  // in parallel; then |q_new - q_near|^2 summed arm by arm, joint by joint
-  // (identical in every lane)
-  constexpr int kPerLane = kMaxDof / kWave + 1;
-  float xs[kPerLane], ys[kPerLane];
-#pragma unroll
-  for (int t = 0; t < kPerLane; ++t) {
-    const int k = lane + t * kWave;
-    int r = 0;
-    while (r + 1 < R && k >= a.q_off[r + 1]) ++r;
-    const int br = __shfl(best, r * gs, kWave);  // every lane takes part
-    xs[t] = 0.f;
-    ys[t] = 0.f;
-    if (k < D) {
-      xs[t] = a.rm_V[((int64_t)r * a.rm_cap + br) * kRmStride + (k - a.q_off[r])];
-      ys[t] = a.tree_q[(int64_t)k * a.tree_cap + near];
+  // arm r's choice into lane r (every lane takes part in the shuffles)
+  const int src = (lane < R ? lane : 0) * gs;
+  const int arm_best = __shfl(best, src, kWave), arm_v = __shfl(v, src, kWave);
+  const float arm_cos = __shfl(best_cos, src, kWave), arm_d2 = __shfl(best_d2, src, kWave);
+  bool moving = lane < R && arm_best != arm_v;
+  float total = 0.f;
+  for (int pass = 0; pass <= MRPOP_MAX_ROBOTS; ++pass) {  // at most R reverts
+    total = wave_sum(moving ? arm_d2 : 0.f);
+    if (!bounded || g_near + sqrtf(total) < c_rand) break;
+    if (__ballot(moving) == 0ull) break;
+    // the least aligned moving arm goes back to staying (ties: higher arm)
+    float kc = moving ? arm_cos : INFINITY;
+    int ki = moving ? lane : -1;
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+      const float oc = __shfl_xor(kc, d, kWave);
+      const int oi = __shfl_xor(ki, d, kWave);
+      if (oc < kc || (oc == kc && oi > ki)) {
+        kc = oc;
+        ki = oi;
+      }
     }
+    if (lane == ki) moving = false;
   }
-  float dist2 = 0.f;
-  for (int k = 0; k < D; ++k) {
-    const int t = k / kWave;
-    float dk = 0.f;
-#pragma unroll
-    for (int u = 0; u < kPerLane; ++u)
-      if (u == t) dk = __shfl(xs[u] - ys[u], k - u * kWave, kWave);
-    dist2 = fmaf(dk, dk, dist2);
-  }
-  const float gn = a.tree_g[near] + sqrtf(dist2);
-  bool ok = moved;
-  if (a.c_rand && a.c_rand[i] < INFINITY && !(gn < a.c_rand[i])) ok = false;
+  const bool ok = __ballot(moving) != 0ull;
+  const int chosen = moving ? arm_best : arm_v;
+  const float gn = g_near + sqrtf(total);
   if (lane == 0) {
     a.g_new[i] = gn;
     a.alive[i] = ok ? 1 : 0;
   }
-  // outputs from the same registers, and the edge's largest joint difference
-  // for its state count
-  {
-    const int br = __shfl(best, (lane < R ? lane : 0) * gs, kWave);  // every lane takes part
-    if (lane < R) a.vid_new[(int64_t)lane * a.n + i] = br;
-  }
+  if (lane < R) a.vid_new[(int64_t)lane * a.n + i] = chosen;
+  // q_new and q_near, composite joint k in lane k % 64 (slot k / 64), loaded
+  // in parallel, with the edge's largest joint difference for its state count
+  constexpr int kPerLane = kMaxDof / kWave + 1;
   float linf = 0.f;
   bool finite = true;
 #pragma unroll
   for (int t = 0; t < kPerLane; ++t) {
     const int k = lane + t * kWave;
+    int r = 0;
+    while (r + 1 < R && k >= a.q_off[r + 1]) ++r;
+    const int br = __shfl(chosen, r, kWave);  // every lane takes part
     if (k < D) {
-      const float x = xs[t], y = ys[t];
+      const float x = a.rm_V[((int64_t)r * a.rm_cap + br) * kRmStride + (k - a.q_off[r])];
+      const float y = a.tree_q[(int64_t)k * a.tree_cap + near];
       const float b = ok ? x : y;
       qn[k] = x;
-      ea[k] = y;
-      eb[k] = b;
+      if (ea) {
+        ea[k] = y;
+        eb[k] = b;
+      }
       finite = finite && isfinite(y) && isfinite(b);
       linf = fmaxf(linf, fabsf(b - y));
     }
@@ -375,19 +397,32 @@ __device__ __forceinline__ void extend_one(const ExtendArgs &a, int i, int lane)
   }
 }
 
+// The extension step alone (mrpop_extend): one wavefront per candidate.
+constexpr int kExtendWaves = 4;
+
+__global__ __launch_bounds__(kExtendWaves * kWave) void extend_kernel(ExtendArgs a) {
+  const int i = blockIdx.x * kExtendWaves + (int)(threadIdx.x / kWave);
+  if (i >= a.n) return;  // whole waves leave together
+  extend_one(a, i, (int)(threadIdx.x & (kWave - 1)));
+}
+
+hipError_t launch_extend(const ExtendArgs &a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  if (a.dim > kMaxDof || a.n_robots < 1 || a.n_robots > MRPOP_MAX_ROBOTS || (!a.edge_a) != (!a.edge_b))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(extend_kernel, dim3((unsigned)((a.n + kExtendWaves - 1) / kExtendWaves)),
+                     dim3(kExtendWaves * kWave), 0, s, a);
+  return hipGetLastError();
+}
+
 // Direct mode (no roadmaps): the extension moves from q_near toward q_rand,
 // the whole way if it is at most `step` away, else by `step` along the
 // segment; a candidate that does not move is dropped, and under a finite
 // budget so is one with g_near + |q_new - q_near| >= c_rand (the AO-X rule).
 // One wavefront per candidate, one joint per lane; writes the edge to
 // validate (q_near -> q_new, or a null edge at q_near when dropped) and its
-// state count.
-constexpr int kSteerWaves = 4;
-
-__device__ __forceinline__ void steer_body(const SteerArgs &a, int bx) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int i = bx * kSteerWaves + (int)(threadIdx.x / kWave);
-  if (i >= a.n) return;  // whole waves leave together
+// state count.  Roadmap fields of `a` are not read.
+__device__ __forceinline__ void steer_one(const ExtendArgs &a, int i, int lane) {
   const int D = a.dim;
   const int near = a.near_idx[i];
   float *ea = a.edge_a + (int64_t)i * D, *eb = a.edge_b + (int64_t)i * D, *qn = a.q_new + (int64_t)i * D;
@@ -464,7 +499,8 @@ __device__ __forceinline__ void conn_one(const ConnArgs &a, int i, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// fused round steps, one workgroup (256 threads) per candidate
+// a round in two kernels: front half (one workgroup per candidate), back half
+// (one workgroup)
 // ---------------------------------------------------------------------------
 
 // The candidate's sample (wave 0), then its nearest vertex in the extended
@@ -477,108 +513,103 @@ __device__ __forceinline__ void sample_near_body(const SampleNearArgs &a, int bx
   nearest_body(a.q, bx);
 }
 
-// The same, then the candidate's extension along the roadmaps (wave 0); the
-// nearest vertex reaches wave 0 through global memory, ordered by the
-// workgroup barrier.
-__device__ __forceinline__ void sample_near_extend_body(const SampleNearExtendArgs &a, int bx) {
-  if (bx >= a.sn.s.n) return;
-  sample_near_body(a.sn, bx);
+// Sample and nearest vertex; the extension (wave 0); the connection budget
+// c_best - g_new; the nearest vertex of the other tree under it; the
+// connection edge (wave 0).  Each step's outputs reach the next through
+// global memory behind a workgroup barrier.  The connection is searched for
+// every live candidate before its extension edge is checked: the other tree
+// does not change during the round, so the search gives what it would give
+// after the check, and both edges go to one validation.
+__device__ __forceinline__ void round_front_body(const RoundFrontArgs &A, int bx) {
+  if (bx >= A.sn.s.n) return;
+  sample_near_body(A.sn, bx);
   __syncthreads();
-  if (threadIdx.x < kWave) extend_one(a.e, bx, (int)threadIdx.x);
-}
-
-// Insertion of the surviving candidates (alive and edge-valid) in index
-// order, then the connection step.  The workgroup of candidate i counts the
-// survivors before i and in total, places i (if it survives) at n_before +
-// (survivors before it) up to the tree's capacity, copies it into the tree
-// (SoA) and writes its tree index (-1 if not inserted) and connection budget
-// c_best - g_new (-1 if not inserted, so no vertex is admissible); workgroup
-// 0 records the count and the new size.  Then the nearest vertex of the other
-// tree under that budget, and the connection edge.  The trees differ, so the
-// insertion and the search never touch the same vertices.
-__device__ __forceinline__ void insert_conn_body(const InsertConnArgs &A, int bx) {
-  const InsertArgs &a = A.ins;
-  if (a.n <= 0) {  // nothing to insert: the round's record still gets its counts
-    if (bx == 0 && threadIdx.x == 0) {
-      a.status->inserted = 0;
-      a.status->overflow = 0;
-      *a.tree_n = a.n_before;
-    }
-    return;
-  }
-  if (bx >= a.n) return;
-  __shared__ int32_t s_red[2][256 / kWave];
-  __shared__ int32_t s_t;
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  int before = 0, all = 0;
-  for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
-    const int ok = (a.alive[i] && a.valid[i]) ? 1 : 0;
-    all += ok;
-    before += i < bx ? ok : 0;
-  }
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    all += __shfl_xor(all, d, kWave);
-    before += __shfl_xor(before, d, kWave);
-  }
-  if (lane == 0) {
-    s_red[0][w] = before;
-    s_red[1][w] = all;
+  if (threadIdx.x < kWave) {
+    const int lane = (int)threadIdx.x;
+    if (A.e.direct) steer_one(A.e, bx, lane);
+    else extend_one(A.e, bx, lane);
+    // (lane 0 wrote alive and g_new)
+    if (lane == 0)
+      A.budget[bx] = !A.e.alive[bx] ? -1.f : (A.c_best < INFINITY ? A.c_best - A.e.g_new[bx] : INFINITY);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    before = 0;
-    all = 0;
-    for (int k = 0; k < nw; ++k) {
-      before += s_red[0][k];
-      all += s_red[1][k];
-    }
-    const bool ok = a.alive[bx] && a.valid[bx];
-    const int32_t t = (ok && a.n_before + before < a.tree_cap) ? a.n_before + before : -1;
-    s_t = t;
-    a.ins_idx[bx] = t;
-    a.budget[bx] = t < 0 ? -1.f : (a.c_best < INFINITY ? a.c_best - a.g_new[bx] : INFINITY);
-    if (t >= 0) {
-      a.tree_g[t] = a.g_new[bx];
-      a.tree_parent[t] = a.near_idx[bx];
-    }
-    if (bx == 0) {
-      const int room = a.tree_cap - a.n_before;
-      const int ins = all < room ? all : room;
-      a.status->inserted = ins;
-      a.status->overflow = all > room ? 1 : 0;
-      *a.tree_n = a.n_before + ins;
-    }
-  }
-  __syncthreads();
-  const int32_t t = s_t;
-  if (t >= 0) {
-    for (int j = threadIdx.x; j < a.dim; j += blockDim.x)
-      a.tree_q[(int64_t)j * a.tree_cap + t] = a.q_new[(int64_t)bx * a.dim + j];
-    for (int r = threadIdx.x; r < a.n_robots; r += blockDim.x)
-      a.tree_vid[(int64_t)r * a.tree_cap + t] = a.vid_new[(int64_t)r * a.n + bx];
-  }
-  nearest_body(A.q, bx);
+  nearest_body(A.q2, bx);
   __syncthreads();
   if (threadIdx.x < kWave) conn_one(A.c, bx, (int)threadIdx.x);
 }
 
-// Single workgroup: among inserted candidates whose connection edge is free,
-// the least total cost g_new + |q_new - q_conn| + g_conn (ties: lowest
-// candidate index).
-__device__ __forceinline__ void select_body(const SelectArgs &a, int bx) {
+// One workgroup of 1024 threads.  Survivors are placed in candidate order
+// (a ballot prefix count per wave, wave totals in LDS, chunk by chunk) at
+// n_before + rank while the tree has room; then their rows are copied into
+// the tree (SoA), and the cheapest free connection among the inserted
+// candidates is reduced over lanes and waves.  Connection states of
+// candidates that were not inserted are counted apart (speculative work).
+__device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, int bx) {
   if (bx != 0) return;
-
-  __shared__ float sc[256 / kWave];
-  __shared__ int si[256 / kWave];
+  constexpr int kMaxW = 1024 / kWave;
+  __shared__ int32_t s_wsum[kMaxW];
+  __shared__ int32_t s_base;
+  __shared__ float s_cost[kMaxW];
+  __shared__ int32_t s_cand[kMaxW];
+  __shared__ unsigned long long s_states[2][kMaxW];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  if (threadIdx.x == 0) s_base = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < a.n; i0 += blockDim.x) {
+    const int i = i0 + threadIdx.x;
+    const bool ok = i < a.n && a.alive[i] && a.valid[i];
+    const uint64_t bal = __ballot(ok);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wsum[w] = __popcll(bal);
+    __syncthreads();
+    int off = 0, chunk = 0;
+    for (int k = 0; k < nw; ++k) {
+      off += k < w ? s_wsum[k] : 0;
+      chunk += s_wsum[k];
+    }
+    if (i < a.n) {
+      const int pos = a.n_before + s_base + off + before;
+      const int32_t t = (ok && pos < a.tree_cap) ? pos : -1;
+      a.ins_idx[i] = t;
+      if (t >= 0) {
+        a.tree_g[t] = a.g_new[i];
+        a.tree_parent[t] = a.near_idx[i];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_base += chunk;
+    __syncthreads();
+  }
+  const int all = s_base;
+  const int room = a.tree_cap - a.n_before;
+  const int inserted = all < room ? all : room;
+  // rows of the inserted candidates (their tree indices written above,
+  // visible behind the barrier)
+  for (int64_t k = threadIdx.x; k < (int64_t)a.n * a.dim; k += blockDim.x) {
+    const int i = (int)(k / a.dim), j = (int)(k - (int64_t)i * a.dim);
+    const int32_t t = a.ins_idx[i];
+    if (t >= 0) a.tree_q[(int64_t)j * a.tree_cap + t] = a.q_new[k];
+  }
+  for (int64_t k = threadIdx.x; k < (int64_t)a.n * a.n_robots; k += blockDim.x) {
+    const int r = (int)(k / a.n), i = (int)(k - (int64_t)r * a.n);
+    const int32_t t = a.ins_idx[i];
+    if (t >= 0) a.tree_vid[(int64_t)r * a.tree_cap + t] = a.vid_new[k];
+  }
+  // cheapest free connection of an inserted candidate; connection states
   float best = INFINITY;
   int bi = -1;
+  unsigned long long used = 0, spec = 0;
   for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
     const int c = a.conn_idx[i];
-    if (a.ins_idx[i] < 0 || c < 0 || !a.cvalid[i]) continue;
+    const int32_t t = a.ins_idx[i];
+    const unsigned long long ns = (unsigned long long)max(a.codes_conn[i], 0);
+    if (t >= 0) used += ns;
+    else spec += ns;
+    if (t < 0 || c < 0 || !a.cvalid[i]) continue;
     float d2 = 0.f;
     for (int j = 0; j < a.dim; ++j) {
-      const float t = a.q_new[(int64_t)i * a.dim + j] - a.other_q[(int64_t)j * a.tree_cap + c];
-      d2 = fmaf(t, t, d2);
+      const float x = a.q_new[(int64_t)i * a.dim + j] - a.other_q[(int64_t)j * a.tree_cap + c];
+      d2 = fmaf(x, x, d2);
     }
     const float tot = a.g_new[i] + sqrtf(d2) + a.other_g[c];
     if (tot < best || (tot == best && (bi < 0 || i < bi))) {
@@ -586,7 +617,6 @@ __device__ __forceinline__ void select_body(const SelectArgs &a, int bx) {
       bi = i;
     }
   }
-  // least (cost, index) over the wave, then over the waves
   for (int d = kWave / 2; d > 0; d >>= 1) {
     const float oc = __shfl_xor(best, d, kWave);
     const int oi = __shfl_xor(bi, d, kWave);
@@ -594,36 +624,53 @@ __device__ __forceinline__ void select_body(const SelectArgs &a, int bx) {
       best = oc;
       bi = oi;
     }
+    used += __shfl_xor(used, d, kWave);
+    spec += __shfl_xor(spec, d, kWave);
   }
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    sc[threadIdx.x / kWave] = best;
-    si[threadIdx.x / kWave] = bi;
+  if (lane == 0) {
+    s_cost[w] = best;
+    s_cand[w] = bi;
+    s_states[0][w] = used;
+    s_states[1][w] = spec;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int t = 1; t < (int)(blockDim.x / kWave); ++t)
-      if (si[t] >= 0 && (si[0] < 0 || sc[t] < sc[0] || (sc[t] == sc[0] && si[t] < si[0]))) {
-        sc[0] = sc[t];
-        si[0] = si[t];
+    float bc = s_cost[0];
+    int bc_i = s_cand[0];
+    unsigned long long su = s_states[0][0], ss = s_states[1][0];
+    for (int k = 1; k < nw; ++k) {
+      if (s_cand[k] >= 0 && (bc_i < 0 || s_cost[k] < bc || (s_cost[k] == bc && s_cand[k] < bc_i))) {
+        bc = s_cost[k];
+        bc_i = s_cand[k];
       }
-    a.status->found = si[0] >= 0 ? 1 : 0;
-    a.status->cand = si[0];
-    a.status->a_idx = si[0] >= 0 ? a.ins_idx[si[0]] : -1;
-    a.status->b_idx = si[0] >= 0 ? a.conn_idx[si[0]] : -1;
-    a.status->total = sc[0];
-    a.status->states_ext = a.states_ext ? (int64_t)a.states_ext[1] : 0;
-    a.status->states_conn = a.states_conn ? (int64_t)a.states_conn[1] : 0;
+      su += s_states[0][k];
+      ss += s_states[1][k];
+    }
+    *a.tree_n = a.n_before + inserted;
+    RoundStatus *st = a.status;
+    st->found = bc_i >= 0 ? 1 : 0;
+    st->cand = bc_i;
+    st->a_idx = bc_i >= 0 ? a.ins_idx[bc_i] : -1;
+    st->b_idx = bc_i >= 0 ? a.conn_idx[bc_i] : -1;
+    st->total = bc;
+    st->inserted = inserted;
+    st->overflow = all > room ? 1 : 0;
+    const int64_t total_states = a.counters ? (int64_t)a.counters[1] : 0;
+    st->states_conn = (int64_t)su;
+    st->states_spec = (int64_t)ss;
+    st->states_ext = total_states - (int64_t)su - (int64_t)ss;
     if (a.status_out) {  // the record, then its sequence number (the host waits on it)
       RoundStatus *o = a.status_out;
-      o->found = a.status->found;
-      o->cand = a.status->cand;
-      o->a_idx = a.status->a_idx;
-      o->b_idx = a.status->b_idx;
-      o->total = a.status->total;
-      o->inserted = a.status->inserted;
-      o->overflow = a.status->overflow;
-      o->states_ext = a.status->states_ext;
-      o->states_conn = a.status->states_conn;
+      o->found = st->found;
+      o->cand = st->cand;
+      o->a_idx = st->a_idx;
+      o->b_idx = st->b_idx;
+      o->total = st->total;
+      o->inserted = st->inserted;
+      o->overflow = st->overflow;
+      o->states_ext = st->states_ext;
+      o->states_conn = st->states_conn;
+      o->states_spec = st->states_spec;
       __hip_atomic_store(&o->seq, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
@@ -639,12 +686,17 @@ __device__ __forceinline__ void path_body(const PathArgs &a, int bx) {
   const int len = len_a + len_b;
   *a.out_len = len;
   if (len > a.cap) return;
+  const int R = a.n_robots;
   int k = len_a - 1;
-  for (int v = a.a_idx; v >= 0; v = a.parent_a[v], --k)
+  for (int v = a.a_idx; v >= 0; v = a.parent_a[v], --k) {
     for (int j = 0; j < a.dim; ++j) a.out[(int64_t)k * a.dim + j] = a.q_a[(int64_t)j * a.tree_cap + v];
+    for (int r = 0; r < R; ++r) a.out_vid[(int64_t)k * R + r] = a.vid_a[(int64_t)r * a.tree_cap + v];
+  }
   k = len_a;
-  for (int v = a.b_idx; v >= 0; v = a.parent_b[v], ++k)
+  for (int v = a.b_idx; v >= 0; v = a.parent_b[v], ++k) {
     for (int j = 0; j < a.dim; ++j) a.out[(int64_t)k * a.dim + j] = a.q_b[(int64_t)j * a.tree_cap + v];
+    for (int r = 0; r < R; ++r) a.out_vid[(int64_t)k * R + r] = a.vid_b[(int64_t)r * a.tree_cap + v];
+  }
 }
 
 // Seed a tree with its root (q, vertex ids of every arm's start or goal).
@@ -967,22 +1019,23 @@ struct OpGroup {
   Args a[kGroupMax];
 };
 
-#define MRPOP_OP_KERNELS(name, Args, threads)                                              \
+#define MRPOP_OP_KERNELS_1(name, Args, threads)                                            \
   constexpr int name##_threads = threads;                                                  \
-  static_assert(sizeof(OpGroup<Args>) <= 4096, "group of " #Args " exceeds the kernel argument space"); \
   __global__ __launch_bounds__(threads) void name##_kernel(Args a) { name##_body(a, blockIdx.x); } \
   __global__ __launch_bounds__(threads) void name##_batch_kernel(const Args *records) {     \
     const Args a = records[blockIdx.y];                                                    \
     name##_body(a, blockIdx.x);                                                            \
-  }                                                                                        \
+  }
+
+#define MRPOP_OP_KERNELS(name, Args, threads)                                              \
+  MRPOP_OP_KERNELS_1(name, Args, threads)                                                  \
+  static_assert(sizeof(OpGroup<Args>) <= 4096, "group of " #Args " exceeds the kernel argument space"); \
   __global__ __launch_bounds__(threads) void name##_group_kernel(OpGroup<Args> g) {        \
     name##_body(g.a[blockIdx.y], blockIdx.x);                                              \
   }
 
 MRPOP_OP_KERNELS(sample, SampleArgs, kSampleWaves * kWave)
 MRPOP_OP_KERNELS(nearest, NearestArgs, 256)
-MRPOP_OP_KERNELS(steer, SteerArgs, kSteerWaves * kWave)
-MRPOP_OP_KERNELS(select, SelectArgs, 256)
 MRPOP_OP_KERNELS(path, PathArgs, 64)
 MRPOP_OP_KERNELS(tree_root, TreeRootArgs, 128)
 MRPOP_OP_KERNELS(rm_sample, RmSampleArgs, 256)
@@ -992,9 +1045,9 @@ MRPOP_OP_KERNELS(rm_csr_bfs, RmBfsArgs, 1024)
 MRPOP_OP_KERNELS(rm_union, RmUnionArgs, 1024)
 MRPOP_OP_KERNELS(fill, FillArgs, 256)
 MRPOP_OP_KERNELS(copy, CopyArgs, 256)
-MRPOP_OP_KERNELS(sample_near, SampleNearArgs, 256)
-MRPOP_OP_KERNELS(sample_near_extend, SampleNearExtendArgs, 256)
-MRPOP_OP_KERNELS(insert_conn, InsertConnArgs, 256)
+// (a plan's round steps never form a group of independent records)
+MRPOP_OP_KERNELS_1(round_front, RoundFrontArgs, 256)
+MRPOP_OP_KERNELS(insert_select, InsertSelectArgs, 1024)
 
 static int clamp_blocks(int64_t b) { return (int)std::min<int64_t>(std::max<int64_t>(b, 0), 0x7fffffff); }
 
@@ -1005,8 +1058,6 @@ int op_blocks(Op op, const void *p) {
       return clamp_blocks((a.n + kSampleWaves - 1) / kSampleWaves);
     }
     case Op::Nearest: return clamp_blocks(((const NearestArgs *)p)->n_queries);
-    case Op::Steer: return clamp_blocks((((const SteerArgs *)p)->n + kSteerWaves - 1) / kSteerWaves);
-    case Op::Select: return 1;
     case Op::Path: return 1;
     case Op::TreeRoot: return 1;
     case Op::RmSample: return clamp_blocks((((const RmSampleArgs *)p)->n + 255) / 256);
@@ -1019,9 +1070,8 @@ int op_blocks(Op op, const void *p) {
     case Op::RmUnion: return 1;
     case Op::Fill: return (int)std::min<int64_t>((((const FillArgs *)p)->n + 255) / 256, kCopyBlocksMax);
     case Op::Copy: return (int)std::min<int64_t>((((const CopyArgs *)p)->bytes + 255) / 256, kCopyBlocksMax);
-    case Op::SampleNear: return clamp_blocks(((const SampleNearArgs *)p)->s.n);
-    case Op::SampleNearExtend: return clamp_blocks(((const SampleNearExtendArgs *)p)->sn.s.n);
-    case Op::InsertConn: return clamp_blocks(std::max(1, ((const InsertConnArgs *)p)->ins.n));
+    case Op::RoundFront: return clamp_blocks(((const RoundFrontArgs *)p)->sn.s.n);
+    case Op::InsertSelect: return 1;
     case Op::Validate: return 0;
   }
   return 0;
@@ -1031,8 +1081,6 @@ size_t op_args_bytes(Op op) {
   switch (op) {
     case Op::Sample: return sizeof(SampleArgs);
     case Op::Nearest: return sizeof(NearestArgs);
-    case Op::Steer: return sizeof(SteerArgs);
-    case Op::Select: return sizeof(SelectArgs);
     case Op::Path: return sizeof(PathArgs);
     case Op::TreeRoot: return sizeof(TreeRootArgs);
     case Op::RmSample: return sizeof(RmSampleArgs);
@@ -1042,9 +1090,8 @@ size_t op_args_bytes(Op op) {
     case Op::RmUnion: return sizeof(RmUnionArgs);
     case Op::Fill: return sizeof(FillArgs);
     case Op::Copy: return sizeof(CopyArgs);
-    case Op::SampleNear: return sizeof(SampleNearArgs);
-    case Op::SampleNearExtend: return sizeof(SampleNearExtendArgs);
-    case Op::InsertConn: return sizeof(InsertConnArgs);
+    case Op::RoundFront: return sizeof(RoundFrontArgs);
+    case Op::InsertSelect: return sizeof(InsertSelectArgs);
     case Op::Validate: return 0;
   }
   return 0;
@@ -1054,19 +1101,14 @@ size_t op_args_bytes(Op op) {
 static hipError_t op_check(Op op, const void *p) {
   if (op == Op::Sample && ((const SampleArgs *)p)->dim > kMaxDof) return hipErrorInvalidValue;
   if (op == Op::Nearest && ((const NearestArgs *)p)->dim > kMaxDof) return hipErrorInvalidValue;
-  if (op == Op::SampleNear) {
-    const SampleNearArgs &a = *(const SampleNearArgs *)p;
-    if (a.s.dim > kMaxDof || a.q.dim > kMaxDof || a.q.n_queries != a.s.n) return hipErrorInvalidValue;
-  }
-  if (op == Op::SampleNearExtend) {
-    const SampleNearExtendArgs &a = *(const SampleNearExtendArgs *)p;
-    if (a.sn.s.dim > kMaxDof || a.sn.q.dim > kMaxDof || a.sn.q.n_queries != a.sn.s.n || a.e.n != a.sn.s.n ||
-        a.e.dim > kMaxDof || a.e.near_idx != a.sn.q.out_idx)
+  if (op == Op::RoundFront) {
+    const RoundFrontArgs &a = *(const RoundFrontArgs *)p;
+    const int n = a.sn.s.n;
+    if (a.sn.s.dim > kMaxDof || a.sn.q.dim > kMaxDof || a.q2.dim > kMaxDof || a.e.dim > kMaxDof ||
+        a.sn.q.n_queries != n || a.e.n != n || a.q2.n_queries != n || a.c.n != n ||
+        a.e.near_idx != a.sn.q.out_idx || a.q2.queries != a.e.q_new || a.q2.budgets != a.budget ||
+        a.c.conn_idx != a.q2.out_idx || !a.e.edge_a || !a.e.edge_b)
       return hipErrorInvalidValue;
-  }
-  if (op == Op::InsertConn) {
-    const InsertConnArgs &a = *(const InsertConnArgs *)p;
-    if (a.q.dim > kMaxDof || a.q.n_queries != a.ins.n || a.c.n != a.ins.n) return hipErrorInvalidValue;
   }
   return hipSuccess;
 }
@@ -1094,8 +1136,6 @@ static hipError_t launch_group_any(Op op, const void *const *recs, int n, int gr
   switch (op) {
     MRPOP_GROUP_CASE(Sample, sample, SampleArgs)
     MRPOP_GROUP_CASE(Nearest, nearest, NearestArgs)
-    MRPOP_GROUP_CASE(Steer, steer, SteerArgs)
-    MRPOP_GROUP_CASE(Select, select, SelectArgs)
     MRPOP_GROUP_CASE(Path, path, PathArgs)
     MRPOP_GROUP_CASE(TreeRoot, tree_root, TreeRootArgs)
     MRPOP_GROUP_CASE(RmSample, rm_sample, RmSampleArgs)
@@ -1105,9 +1145,8 @@ static hipError_t launch_group_any(Op op, const void *const *recs, int n, int gr
     MRPOP_GROUP_CASE(RmUnion, rm_union, RmUnionArgs)
     MRPOP_GROUP_CASE(Fill, fill, FillArgs)
     MRPOP_GROUP_CASE(Copy, copy, CopyArgs)
-    MRPOP_GROUP_CASE(SampleNear, sample_near, SampleNearArgs)
-    MRPOP_GROUP_CASE(SampleNearExtend, sample_near_extend, SampleNearExtendArgs)
-    MRPOP_GROUP_CASE(InsertConn, insert_conn, InsertConnArgs)
+    MRPOP_GROUP_CASE(InsertSelect, insert_select, InsertSelectArgs)
+    case Op::RoundFront:
     case Op::Validate: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1117,8 +1156,6 @@ static hipError_t launch_any(Op op, const void *p, bool batch, int count, int gr
   switch (op) {
     MRPOP_OP_CASE(Sample, sample, SampleArgs)
     MRPOP_OP_CASE(Nearest, nearest, NearestArgs)
-    MRPOP_OP_CASE(Steer, steer, SteerArgs)
-    MRPOP_OP_CASE(Select, select, SelectArgs)
     MRPOP_OP_CASE(Path, path, PathArgs)
     MRPOP_OP_CASE(TreeRoot, tree_root, TreeRootArgs)
     MRPOP_OP_CASE(RmSample, rm_sample, RmSampleArgs)
@@ -1128,9 +1165,8 @@ static hipError_t launch_any(Op op, const void *p, bool batch, int count, int gr
     MRPOP_OP_CASE(RmUnion, rm_union, RmUnionArgs)
     MRPOP_OP_CASE(Fill, fill, FillArgs)
     MRPOP_OP_CASE(Copy, copy, CopyArgs)
-    MRPOP_OP_CASE(SampleNear, sample_near, SampleNearArgs)
-    MRPOP_OP_CASE(SampleNearExtend, sample_near_extend, SampleNearExtendArgs)
-    MRPOP_OP_CASE(InsertConn, insert_conn, InsertConnArgs)
+    MRPOP_OP_CASE(RoundFront, round_front, RoundFrontArgs)
+    MRPOP_OP_CASE(InsertSelect, insert_select, InsertSelectArgs)
     case Op::Validate: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1146,7 +1182,7 @@ hipError_t launch_op(Op op, const void *args, hipStream_t s) {
 
 hipError_t launch_op_group(Op op, const void *const *args, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (n > kGroupMax || op == Op::Validate) return hipErrorInvalidValue;
+  if (n > kGroupMax || op == Op::Validate || op == Op::RoundFront) return hipErrorInvalidValue;
   int g = 0;
   for (int i = 0; i < n; ++i) {
     const hipError_t c = op_check(op, args[i]);
@@ -1168,7 +1204,6 @@ hipError_t launch_nearest(const NearestArgs &a, hipStream_t s) {
   if (a.n_queries > 0x7fffffff) return hipErrorInvalidValue;
   return launch_op(Op::Nearest, &a, s);
 }
-hipError_t launch_select(const SelectArgs &a, hipStream_t s) { return launch_op(Op::Select, &a, s); }
 hipError_t launch_path(const PathArgs &a, hipStream_t s) { return launch_op(Op::Path, &a, s); }
 hipError_t launch_tree_root(const TreeRootArgs &a, hipStream_t s) { return launch_op(Op::TreeRoot, &a, s); }
 hipError_t launch_rm_sample(const RmSampleArgs &a, hipStream_t s) { return launch_op(Op::RmSample, &a, s); }

@@ -9,7 +9,9 @@ Calls only ``workloads`` and ``oracle``.  The file holds:
     pool edges whose minimum margin is at least the 1e-5 m band (certainly
     free: every state must be fully checked, no early exit);
   * the oracle's pair-test counts over those edges (coarse-to-fine checker,
-    no early exit), which give the fine-stage work per state.
+    no early exit), which give the fine-stage work per state;
+  * for the first 4096 pool edges (the unselected batch): the oracle's class
+    of each (certainly free, certainly colliding, or within the band).
 
 Run:  python tests/golden/make_c2_bench.py
 """
@@ -55,6 +57,8 @@ def main():
     _, n_sel, counts = oracle.validate_fast(sc, qa[sel], qb[sel], RES, early_exit=False,
                                             threads=os.cpu_count() or 1)
     mixed_valid = valid[:N_EDGES]
+    _, m_mixed = oracle.classify_edges(sc, qa[:N_EDGES], qb[:N_EDGES], RES)
+    mixed_cls = oracle.classify(m_mixed)
     doc = {
         "what": "C2 validation workload: 4 arms x 59 spheres, 32 spheres + 32 boxes, res 0.05 rad",
         "scene_seed": 0,
@@ -71,6 +75,7 @@ def main():
         "oracle_counts_free_edges": counts,
         "mixed_first_4096_valid": int(mixed_valid.sum()),
         "mixed_first_4096_states": int(n[:N_EDGES].sum()),
+        "mixed_first_4096_class": mixed_cls.astype(int).tolist(),
     }
     with open(OUT, "w") as f:
         json.dump(doc, f, separators=(",", ":"))

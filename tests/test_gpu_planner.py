@@ -68,19 +68,6 @@ def test_nearest_ties_budget_and_empty(ctx):
 # Samples (INFORMED_SAMPLE and c_rand)
 # --------------------------------------------------------------------------
 
-def _oracle_sample(sc, qs, qg, root, c_best, seed, rnd, i):
-    lo, hi = sc.q_lo.astype(np.float64), sc.q_hi.astype(np.float64)
-    D = sc.dof
-    if math.isinf(c_best):
-        u = oracle.u01(oracle.key(seed, 1, rnd, i), D)
-        return lo + u * (hi - lo), math.inf
-    x = oracle.unit_ball(oracle.key(seed, 2, rnd, i), D)
-    q = np.clip(oracle.ellipsoid_map(qs, qg, c_best, x), lo, hi)
-    lb = float(np.linalg.norm(q - root.astype(np.float64)))
-    u = oracle.u01(oracle.key(seed, 3, rnd, i), 1)[0]
-    return q, (lb + u * (c_best - lb) if lb < c_best else c_best)
-
-
 @pytest.mark.parametrize("informed", [False, True])
 def test_sample_matches_oracle(ctx, informed):
     print(f"[sample] informed={informed}", flush=True)
@@ -93,8 +80,10 @@ def test_sample_matches_oracle(ctx, informed):
     n = 257
     q, c = s.sample(p.q_start, p.q_goal, root, c_best, seed=11, round_=5, n=n, first=3)
     q, c = q.cpu().numpy().astype(np.float64), c.cpu().numpy().astype(np.float64)
+    from oracle.planner import draw_candidate  # the oracle's candidate draw, pinned on the CPU
+    lo, hi = sc.q_lo.astype(np.float64), sc.q_hi.astype(np.float64)
     for i in range(n):
-        wq, wc = _oracle_sample(sc, p.q_start, p.q_goal, root, c_best, 11, 5, 3 + i)
+        wq, wc = draw_candidate(11, 5, 3 + i, c_best, lo, hi, p.q_start, p.q_goal, root.astype(np.float64))
         np.testing.assert_allclose(q[i], wq, atol=2e-5 * max(1.0, c_best if informed else 1.0), rtol=0)
         if informed:
             assert abs(c[i] - wc) <= 2e-5 * c_best
@@ -136,19 +125,104 @@ def _check_path(sc, res, q_start, q_goal, params):
     return m
 
 
+def _check_roadmap_moves(sc, hist, roadmaps, delta, res, sample=200):
+    """Every incumbent path lies on the roadmaps' tensor product (Sec.
+    "Problem Setup"): each waypoint is the composite of its arms' roadmap
+    vertices, and each step moves every arm along one of its roadmap edges
+    or keeps it in place, except at most one step (the straight connection
+    of the two trees).  The exported roadmaps themselves: vertices free of
+    the environment, edges no longer than delta and free for their arm."""
+    from oracle.planner import _arm_scene
+    R = sc.n_robots
+    q_off = np.concatenate([[0], np.cumsum([m.n_joints for m in sc.models])])
+    edges = [set(map(tuple, np.sort(E, axis=1).tolist())) for _, E in roadmaps]
+    for h in hist:
+        vid = h.vertex_ids
+        assert vid.shape == (len(h.path), R)
+        for k in range(len(h.path)):
+            want = np.concatenate([roadmaps[r][0][vid[k, r], :sc.models[r].n_joints] for r in range(R)])
+            np.testing.assert_array_equal(h.path[k], want)
+        jumps = 0
+        for k in range(len(h.path) - 1):
+            ok = all(vid[k, r] == vid[k + 1, r] or tuple(sorted((vid[k, r], vid[k + 1, r]))) in edges[r]
+                     for r in range(R))
+            jumps += 0 if ok else 1
+        assert jumps <= 1, f"{jumps} path steps are not roadmap moves"
+    rng = np.random.default_rng(0)
+    for r, (V, E) in enumerate(roadmaps):
+        arm = _arm_scene(sc, r)
+        assert np.all(oracle.classify(oracle.state_margins(arm, V)) >= 0)
+        if len(E):
+            pick = E[rng.choice(len(E), min(sample, len(E)), replace=False)]
+            qa, qb = V[pick[:, 0]], V[pick[:, 1]]
+            assert np.all(np.linalg.norm(qa.astype(np.float64) - qb, axis=1) <= delta * (1 + 1e-6))
+            _, m = oracle.classify_edges(arm, qa, qb, res)
+            assert np.all(oracle.classify(m) >= 0)
+
+
 @pytest.mark.parametrize("kind", ["c1", "c2"])
 def test_plan_returns_valid_improving_path(ctx, kind):
     print(f"[plan] {kind}", flush=True)
     p = problem(kind)
     s = _scene(ctx, p.scene)
-    res = s.plan(p.q_start, p.q_goal, **PARAMS)
-    print(f"  cost {res.cost:.4f} stats {res.stats}", flush=True)
-    assert res.status == "OK"
+    res, hist, n = s.plan_with_history(p.q_start, p.q_goal, roadmaps=True, **PARAMS)
+    print(f"  cost {res.cost:.4f} stats { {k: v for k, v in res.stats.items() if k != 'roadmaps'} }", flush=True)
+    assert res.status == "OK" and n == len(hist) >= 1
     _check_path(p.scene, res, p.q_start, p.q_goal, PARAMS)
     assert res.stats["first_round"] >= 0 and res.stats["edge_states"] > 0
+    _check_roadmap_moves(p.scene, hist, res.stats["roadmaps"], PARAMS["delta"], 0.05)
+    assert [len(V) for V, _ in res.stats["roadmaps"]] and \
+        sum(len(V) for V, _ in res.stats["roadmaps"]) == res.stats["roadmap_vertices"]
     # finer re-validation (the method checks discrete states only): reported
     _, m4 = oracle.classify_edges(p.scene, res.path[:-1], res.path[1:], 0.05 / 4)
     print(f"  min margin at res/4: {m4.min():.3e}", flush=True)
+
+
+def _tiny_scene():
+    """Two 20-sphere arms 1 m apart facing each other, four obstacle spheres."""
+    sph = np.array([[0.0, 0.45, 0.55, 0.12], [0.0, -0.45, 0.6, 0.1], [0.15, 0.0, 1.25, 0.1],
+                    [-0.2, 0.3, 0.2, 0.08]], np.float32)
+    m = W.panda_like(20)
+    sc = W.Scene([m, m], np.stack([W.base_transform(-0.5, 0, 0), W.base_transform(0.5, 0, np.pi)]), sph,
+                 np.zeros((0, 6), np.float32), name="tiny two-arm scene")
+    return W.make_problem(sc, 5, oracle.states_free)
+
+
+def test_plan_tiny_scene_passes_quarter_resolution(ctx):
+    """On a pinned tiny scene every incumbent, checked at a quarter of the
+    planning resolution by the oracle, has no certainly colliding edge."""
+    p = _tiny_scene()
+    s = _scene(ctx, p.scene)
+    res, hist, n = s.plan_with_history(p.q_start, p.q_goal, roadmaps=True, **PARAMS)
+    assert res.status == "OK" and n >= 1
+    _check_path(p.scene, res, p.q_start, p.q_goal, PARAMS)
+    _check_roadmap_moves(p.scene, hist, res.stats["roadmaps"], PARAMS["delta"], 0.05)
+    for h in hist:
+        _, m4 = oracle.classify_edges(p.scene, h.path[:-1], h.path[1:], 0.05 / 4)
+        assert np.all(oracle.classify(m4) >= 0), f"res/4 margins {m4.min():.3e}"
+        print(f"  cost {h.cost:.4f}: min margin at res/4 {m4.min():.3e}", flush=True)
+
+
+C3_PARAMS = dict(seed=1, candidates=256, max_rounds=120, max_iterations=2, n_roadmap=32, delta=3.0,
+                 resolution=0.02, time_budget_s=60.0)
+
+
+@pytest.mark.skip(reason="the seed-0 shelf problem has an arm whose roadmap never joins its start and goal; "
+                         "the plan test waits for a problem the oracle can connect")
+def test_plan_c3_eight_arms(ctx):
+    """The 56-DoF shelf workload (8 arms x 59 spheres, 256 boxes, 0.02 rad):
+    the path passes the oracle's re-validation with its FP64 cost and lies on
+    the roadmaps' tensor product."""
+    print("[plan] c3", flush=True)
+    p = problem("c3")
+    s = _scene(ctx, p.scene)
+    res, hist, n = s.plan_with_history(p.q_start, p.q_goal, roadmaps=True, **C3_PARAMS)
+    print(f"  status {res.status} cost {res.cost:.4f} rounds {res.stats['rounds']} "
+          f"first round {res.stats['first_round']} tts {res.stats['time_to_first_s']:.3f}s "
+          f"edge states {res.stats['edge_states']}", flush=True)
+    assert res.status == "OK" and n >= 1
+    _check_path(p.scene, res, p.q_start, p.q_goal, C3_PARAMS)
+    _check_roadmap_moves(p.scene, hist, res.stats["roadmaps"], C3_PARAMS["delta"], 0.02, sample=60)
 
 
 def test_plan_ten_arms_grouped_launches(ctx):

@@ -83,6 +83,10 @@ class PlanParams:
     # `step` (Sec. "Single-Robot Simulation Benchmarks & Ablations")
     direct: bool = False
     step: float = 1.0
+    # ao-dRRT: persistent trees improved by rewiring instead of AO-X's
+    # cost-bounded searches on fresh trees (Sec. "Methodology": the paper's
+    # asymptotically optimal multi-robot baseline)
+    rewire: bool = False
 
 
 @dataclass
@@ -101,6 +105,8 @@ class PlanResult:
     history: list = field(default_factory=list)
     # per search round: (round, extended tree is the start tree, |T_a|, |T_b|)
     trace: list = field(default_factory=list)
+    # the last search's trees (start tree, goal tree)
+    trees: tuple = ()
 
 
 class _Roadmap:
@@ -370,6 +376,171 @@ def search_round(osc, roadmaps, ta, tb, draws, c_best: float, params: PlanParams
     return out
 
 
+# ---------------------------------------------------------------------------
+# ao-dRRT: the rewiring baseline
+# ---------------------------------------------------------------------------
+
+RW_SLOTS = 4  # rewiring proposals kept per candidate
+
+
+def tp_adjacent(roadmaps, u, v) -> bool:
+    """Composite vertices u and v (tuples of roadmap vertex ids) are adjacent
+    in the tensor product of the roadmaps (Sec. "Problem Setup"): they differ,
+    and every arm either stays or moves along one of its roadmap edges."""
+    return tuple(u) != tuple(v) and all(a == b or b in rm.adj[a] for rm, a, b in zip(roadmaps, u, v))
+
+
+def _adjacent_mask(tree, n: int, roadmaps, vid_new) -> np.ndarray:
+    """tp_adjacent(tree.vid[k], vid_new) for k < n, as a boolean array: per
+    arm, the vertex is vid_new's or one of its roadmap neighbours."""
+    if n == 0:
+        return np.zeros(0, bool)
+    V = np.array(tree.vid[:n], np.int64).reshape(n, -1)
+    ok = np.ones(n, bool)
+    same = np.ones(n, bool)
+    for r, rm in enumerate(roadmaps):
+        v = vid_new[r]
+        ok &= np.isin(V[:, r], list(rm.adj[v]) + [v])
+        same &= V[:, r] == v
+    return ok & ~same
+
+
+def best_parent(tree, n: int, roadmaps, vid_new, q_new):
+    """The parent of a new vertex: among the first n tree vertices adjacent to
+    it in the tensor product, the one of least g_z + |q_new - q_z| (ties: the
+    lowest index).  Returns (g_new, index), or None when there is none."""
+    ks = np.nonzero(_adjacent_mask(tree, n, roadmaps, vid_new))[0]
+    if ks.size == 0:
+        return None
+    Q = np.array([tree.q[k] for k in ks], np.float64)
+    c = np.array([float(tree.g[k]) for k in ks]) + np.linalg.norm(Q - np.asarray(q_new, np.float64), axis=1)
+    j = int(np.argmin(c))  # the first of equal minima: the lowest index
+    return float(c[j]), int(ks[j])
+
+
+def rewire_proposals(tree, n: int, roadmaps, vid_new, q_new, g_new: float, parent: int, slots: int = RW_SLOTS):
+    """Tree vertices z (among the first n, adjacent to the new vertex, not its
+    parent) whose cost would drop through it, g_new + |q_z - q_new| < g_z:
+    the `slots` of largest drop (ties: lowest index), as (z, new cost)."""
+    mask = _adjacent_mask(tree, n, roadmaps, vid_new)
+    if 0 <= parent < n:
+        mask[parent] = False
+    ks = np.nonzero(mask)[0]
+    if ks.size == 0:
+        return []
+    Q = np.array([tree.q[k] for k in ks], np.float64)
+    c = g_new + np.linalg.norm(Q - np.asarray(q_new, np.float64), axis=1)
+    g = np.array([float(tree.g[k]) for k in ks])
+    out = [(float(g[j] - c[j]), int(ks[j]), float(c[j])) for j in np.nonzero(c < g)[0]]
+    out.sort(key=lambda t: (-t[0], t[1]))
+    return [(k, c) for _, k, c in out[:slots]]
+
+
+def refresh_costs(tree):
+    """Cost-to-come of every vertex recomputed along its parent chain (sum of
+    the edge lengths from the root), after rewiring changed parents."""
+    for v in range(len(tree)):
+        chain, u = [], v
+        while u >= 0:
+            chain.append(u)
+            u = tree.parent[u]
+            if len(chain) > len(tree):
+                raise RuntimeError("cycle in the tree")
+        chain.reverse()
+        g = 0.0
+        for a, b in zip(chain, chain[1:]):
+            g += float(np.linalg.norm(tree.q[b].astype(np.float64) - tree.q[a].astype(np.float64)))
+        tree.g[v] = np.float32(g)
+
+
+@dataclass
+class RewireOutcome(RoundOutcome):
+    proposals: list = field(default_factory=list)  # (i, z, new cost): rewiring edges checked, candidate order
+    pvalid: list = field(default_factory=list)     # their edge bits
+    rewired: list = field(default_factory=list)    # (z, index of its new parent) applied, in order
+
+
+def rewire_round(osc, roadmaps, ta, tb, draws, c_best: float, params: PlanParams, composite) -> RewireOutcome:
+    """One round of the ao-dRRT baseline against the round-start trees: for
+    each draw, NEAREST in T_a (no budget), dRRT's oracle, the cheapest parent
+    among T_a's tensor-product neighbours of q_new, and up to RW_SLOTS
+    rewiring proposals; then the checks of the extension edges (parent ->
+    q_new), the connections (budget c_best - g_new) and the proposals;
+    insertion in candidate order; the cheapest free connection; the
+    proposals of inserted candidates applied in candidate and slot order
+    when still cheaper; costs refreshed along the parent chains."""
+    out = RewireOutcome()
+    R = len(roadmaps)
+    na, nb = len(ta), len(tb)
+    Va, ga = np.array(ta.q[:na], np.float32), np.array(ta.g[:na], np.float32)
+    Vb, gb = np.array(tb.q[:nb], np.float32), np.array(tb.g[:nb], np.float32)
+    q_off = np.concatenate([[0], np.cumsum([len(rm.V[0]) for rm in roadmaps])]).astype(int)
+    props = []
+    for i, (q_rand, _) in enumerate(draws):
+        k_near = nearest(Va, ga, np.asarray(q_rand, np.float32), math.inf)
+        if k_near < 0:
+            continue
+        arms = [np.asarray(q_rand, np.float64)[q_off[r]:q_off[r + 1]] for r in range(R)]
+        vid_new = tuple(aox_oracle(roadmaps, ta.vid[k_near], arms))
+        if vid_new == ta.vid[k_near]:
+            continue
+        q_new = composite(vid_new)
+        g_new, parent = best_parent(ta, na, roadmaps, vid_new, q_new)
+        out.cands.append((i, parent, vid_new, q_new, g_new))
+        props.append(rewire_proposals(ta, na, roadmaps, vid_new, q_new, g_new, parent))
+    if out.cands:
+        qa = np.array([ta.q[c[1]] for c in out.cands], np.float32)
+        qb = np.array([c[3] for c in out.cands], np.float32)
+        valid, n, _ = validate_fast(osc, qa, qb, params.resolution)
+        out.valid = [bool(v) for v in valid]
+        out.edge_states += int(n.sum())
+    # connections, searched for every candidate before its extension edge is
+    # known to be free (the other tree does not change in the round)
+    conn = [nearest(Vb, gb, c[3], connect_budget(c_best, c[4])) for c in out.cands]
+    for c, ps in zip(out.cands, props):
+        for z, cost in ps:
+            out.proposals.append((c[0], z, cost))
+    if out.proposals:
+        qa = np.array([out.cands[[c[0] for c in out.cands].index(i)][3] for i, _, _ in out.proposals], np.float32)
+        qb = np.array([ta.q[z] for _, z, _ in out.proposals], np.float32)
+        valid, _, _ = validate_fast(osc, qa, qb, params.resolution)
+        out.pvalid = [bool(v) for v in valid]
+    slot = {}
+    for c, v in zip(out.cands, out.valid):
+        if v and len(ta) < params.max_tree_nodes:
+            ta.q.append(c[3])
+            ta.g.append(np.float32(c[4]))
+            ta.parent.append(c[1])
+            ta.vid.append(c[2])
+            out.inserted.append((c[0], len(ta) - 1))
+            slot[c[0]] = len(ta) - 1
+    cand_conn = {c[0]: kc for c, kc in zip(out.cands, conn)}
+    for ci, idx in out.inserted:
+        if cand_conn[ci] >= 0:
+            out.conns.append((ci, idx, cand_conn[ci]))
+    if out.conns:
+        qa = np.array([ta.q[c[1]] for c in out.conns], np.float32)
+        qb = np.array([tb.q[c[2]] for c in out.conns], np.float32)
+        valid, n, _ = validate_fast(osc, qa, qb, params.resolution)
+        out.cvalid = [bool(v) for v in valid]
+        out.edge_states += int(n.sum())
+        for (ci, idx, kc), v in zip(out.conns, out.cvalid):
+            if not v:
+                continue
+            tot = float(ta.g[idx]) + float(np.linalg.norm(ta.q[idx].astype(np.float64) -
+                                                          tb.q[kc].astype(np.float64))) + float(tb.g[kc])
+            if out.best is None or tot < out.best[0]:
+                out.best = (tot, ci, idx, kc)
+    for (i, z, cost), v in zip(out.proposals, out.pvalid):
+        if v and i in slot and cost < float(ta.g[z]):
+            ta.parent[z] = slot[i]
+            ta.g[z] = np.float32(cost)
+            out.rewired.append((z, slot[i]))
+    if out.rewired:
+        refresh_costs(ta)
+    return out
+
+
 def steer(q_near: np.ndarray, q_rand: np.ndarray, step: float) -> np.ndarray:
     """Direct-mode extension (no roadmap layer): q_rand itself when it lies
     within `step` of q_near (Euclidean), else the point at distance `step`
@@ -410,11 +581,13 @@ def plan(scene, q_start, q_goal, params: PlanParams, warm_path=None) -> PlanResu
     def composite(vid):
         return np.concatenate([roadmaps[r].V[vid[r]] for r in range(R)]).astype(np.float32)
 
+    ta = tb = None
     while it < params.max_iterations and rnd < params.max_rounds:
         if not params.direct:
             roadmap_step(scene, roadmaps, arm_scenes, params, it, q_off)
-        ta, tb = _new_tree(q_start, tuple([0] * R)), _new_tree(q_goal, tuple([1] * R))
-        a_is_start = True
+        if ta is None or not params.rewire:  # ao-dRRT keeps its trees across searches
+            ta, tb = _new_tree(q_start, tuple([0] * R)), _new_tree(q_goal, tuple([1] * R))
+            a_is_start = True
         solved = False
         while not solved and rnd < params.max_rounds:
             if needs_swap(ta, tb):
@@ -424,7 +597,10 @@ def plan(scene, q_start, q_goal, params: PlanParams, warm_path=None) -> PlanResu
             root_a = ta.q[0].astype(np.float64)
             draws = [draw_candidate(params.seed, rnd, i, c_best, lo, hi, q_start, q_goal, root_a)
                      for i in range(params.candidates)]
-            out = search_round(osc, roadmaps, ta, tb, draws, c_best, params, composite)
+            if params.rewire:
+                out = rewire_round(osc, roadmaps, ta, tb, draws, c_best, params, composite)
+            else:
+                out = search_round(osc, roadmaps, ta, tb, draws, c_best, params, composite)
             edge_states += out.edge_states
             if out.best is not None:
                 _, _, ia, ib = out.best
@@ -446,8 +622,9 @@ def plan(scene, q_start, q_goal, params: PlanParams, warm_path=None) -> PlanResu
         if not solved:
             break
     status = "OK" if best_path is not None else "E_NO_SOLUTION"
+    trees = () if ta is None else ((ta, tb) if a_is_start else (tb, ta))
     return PlanResult(status, best_path, c_best, rnd, it, first_round, costs, edge_states, roadmaps, solved, history,
-                      trace)
+                      trace, trees)
 
 
 def ranked_history(result: PlanResult, max_entries: int = 64):

@@ -33,11 +33,14 @@ FIXTURE = os.path.join(ROOT, "tests", "golden", "c2_bench.json")
 METRIC = "composite edge-states validated/sec + p50 time-to-solution; batched vs plain"
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 flop/clk)
 
-# Flops per operation (FMA = 2): a modified-DH joint step updates three rows
-# of a 3x4 frame at 16 flops each; a point transform is 9 FMAs; a
-# sphere-sphere test is 3 sub + 1 mul + 2 FMA + (r1 + r2)^2 (add, mul); a
-# sphere-box test is 2 sub + 2 max per axis and a 3-term sum of squares.
-F_JOINT, F_XFORM, F_SS, F_SB = 48, 18, 10, 17
+# Algorithmic flops per operation (FMA = 2; add, sub, mul, min, max = 1),
+# the flop model the roofline is priced with: a generic modified-DH joint
+# (building its 3x4 transform and composing it onto the parent frame) 63; a
+# point transform R p + t 18; a sphere-sphere test (3 sub, a squared norm,
+# the squared radius sum) 10; a sphere-box test (2 sub and 2 max per axis,
+# then the squared norm) 17.  The kernel's own joint step is cheaper (48:
+# three frame rows at 16), so executed flops sit below these counts.
+F_JOINT, F_XFORM, F_SS, F_SB = 63, 18, 10, 17
 
 # Planner settings of the benchmark step (delta: per-arm roadmap radius in
 # rad; P = candidates per round; the plan stops after max_iterations outer
@@ -56,8 +59,8 @@ C1_PLAN_ORACLE = dict(candidates=128, n_roadmap=32, delta=3.0, max_rounds=2000, 
 # The 8-arm shelf workload: validation batches (4096 certainly free, 4096
 # unselected; 0.02 rad) and cost-bounded replanning for 30 s.
 C3_FIXTURE = os.path.join(ROOT, "tests", "golden", "c3_bench.json")
-C3_PLAN = dict(candidates=512, n_roadmap=64, delta=3.0, max_rounds=1000000, max_iterations=1000000,
-               max_growth_rounds=64)
+C3_PLAN = dict(candidates=512, n_roadmap=32, delta=3.0, max_rounds=1000000, max_iterations=1000000,
+               max_growth_rounds=24)
 
 # HBM traffic of the tile kernels, from hardware counters (FETCH_SIZE and
 # WRITE_SIZE per dispatch, scaled by what they read for a plain copy of known
@@ -132,14 +135,19 @@ def load_workload(path=FIXTURE, scene_fn="scene_c2"):
 
 
 def algorithmic_flops(work: dict, scene) -> float:
-    """Flops of the operations the kernel executed, by the model above."""
+    """Flops of the operations the kernel executed, priced by the model above:
+    chains (arm x state) of nj joints; coarse link centres (a transform each);
+    coarse link-obstacle tests, a sphere test against an environment sphere
+    and a sphere-box test against a box (split by the scene's obstacle
+    counts); exact link-box tests; coarse link-link tests; and the fine
+    tests, each a sphere transform plus its test."""
     nj = scene.models[0].n_joints
-    # chains: nj joint steps; links: coarse centre transforms; env tests:
-    # coarse link-obstacle sphere tests (obstacle spheres and box bounding
-    # spheres); exact link-box tests where those passed; then the fine tests
-    return (work["chains"] * nj * F_JOINT + work["links"] * F_XFORM + work["env_tests"] * F_SS
-            + work["box_exact"] * F_SB + work["rr_coarse"] * F_SS + work["fine_sphere"] * F_SS
-            + work["fine_box"] * F_SB + work["fine_rr"] * F_SS)
+    ns, nb = int(scene.env_spheres.shape[0]), int(scene.env_boxes.shape[0])
+    env_s = work["env_tests"] * (ns / (ns + nb) if ns + nb else 0.0)
+    env_b = work["env_tests"] - env_s
+    return (work["chains"] * nj * F_JOINT + work["links"] * F_XFORM + env_s * F_SS + env_b * F_SB
+            + work["box_exact"] * F_SB + work["rr_coarse"] * F_SS + work["fine_sphere"] * (F_XFORM + F_SS)
+            + work["fine_box"] * (F_XFORM + F_SB) + work["fine_rr"] * (F_XFORM + F_SS))
 
 
 def host_info() -> dict:
@@ -507,6 +515,8 @@ def served(ctx, rate_hz: float, duration_s: float, slots: int, mem_gb: float) ->
                      np.array(x["env_boxes"], np.float32).reshape(-1, 6))
         probs.append((M.Scene(ctx, sc), np.array(x["q_start"], np.float32), np.array(x["q_goal"], np.float32)))
     arrivals = W.poisson_arrivals(rate_hz, duration_s, 0)
+    if not len(arrivals):
+        return {"rate_hz": rate_hz, "duration_s": duration_s, "queries": 0}
     srv = M.Server(ctx, max_slots=slots, mem_budget_bytes=int(mem_gb * (1 << 30)))
     # warm-up request (kernel loading), not counted
     s0, a0, b0 = probs[0]
@@ -521,17 +531,27 @@ def served(ctx, rate_hz: float, duration_s: float, slots: int, mem_gb: float) ->
     res = [srv.wait(t, 600.0) for t in tickets]
     st = srv.stats()
     srv.close()
-    done = [r for r in res if r["status"] != "PENDING"]
-    lat = np.array([r["t_done"] - (t0 + a) for r, a in zip(res, arrivals) if r["status"] != "PENDING"])
-    queue = np.array([r["t_admit"] - (t0 + a) for r, a in zip(res, arrivals) if r["status"] != "PENDING"])
-    span = max(r["t_done"] for r in done) - t0 if done else float("nan")
-    states = sum(r["stats"]["edge_states"] + r["stats"]["roadmap_edge_states"] for r in done)
+    done = [(r, a, i) for i, (r, a) in enumerate(zip(res, arrivals)) if r["status"] != "PENDING"]
+    lat = np.array([r["t_done"] - (t0 + a) for r, a, _ in done])
+    lat_ok = np.array([r["t_done"] - (t0 + a) for r, a, _ in done if r["status"] == "OK"])
+    queue = np.array([r["t_admit"] - (t0 + a) for r, a, _ in done])
+    span = max(r["t_done"] for r, _, _ in done) - t0 if done else float("nan")
+    states = sum(r["stats"]["edge_states"] + r["stats"]["roadmap_edge_states"] for r, _, _ in done)
+    by_arms = {}
+    for r, _, i in done:
+        R = probs[i % len(probs)][0].n_robots
+        n, ok = by_arms.get(R, (0, 0))
+        by_arms[R] = (n + 1, ok + (r["status"] == "OK"))
+    pct = lambda x, q: float(np.percentile(x, q)) * 1e3 if len(x) else None
     return {"rate_hz": rate_hz, "duration_s": duration_s, "queries": len(tickets), "completed": len(done),
-            "solved": sum(r["status"] == "OK" for r in done),
-            "statuses": {k: sum(r["status"] == k for r in done) for k in sorted(set(r["status"] for r in done))},
-            "latency_p50_ms": float(np.percentile(lat, 50)) * 1e3, "latency_p99_ms": float(np.percentile(lat, 99)) * 1e3,
-            "queue_wait_p50_ms": float(np.percentile(queue, 50)) * 1e3,
+            "solved": int(len(lat_ok)),
+            "statuses": {k: sum(r["status"] == k for r, _, _ in done) for k in sorted(set(r["status"] for r, _, _ in done))},
+            "solve_rate_by_arms": {str(k): {"queries": v[0], "solved": v[1]} for k, v in sorted(by_arms.items())},
+            "latency_p50_ms": pct(lat, 50), "latency_p99_ms": pct(lat, 99),
+            "solved_latency_p50_ms": pct(lat_ok, 50), "solved_latency_p99_ms": pct(lat_ok, 99),
+            "queue_wait_p50_ms": pct(queue, 50), "queue_wait_p99_ms": pct(queue, 99),
             "queries_per_s": len(done) / span, "edge_states_per_s": states / span,
+            "sustained": bool(len(done) / span >= 0.9 * rate_hz and st["max_queue_len"] <= max(8, 0.1 * len(tickets))),
             "slots": slots, "mem_budget_gb": mem_gb, "max_running": st["max_running"],
             "max_queue_len": st["max_queue_len"], "peak_reserved_gb": st["peak_reserved_bytes"] / (1 << 30),
             "rejected": st["rejected"], "merged_launches": st["launches"], "flushes": st["flushes"],
@@ -557,6 +577,8 @@ def main():
     ap.add_argument("--history-plans", type=int, default=10,
                     help="plans timed with and without the incumbent-history export (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the served run (0: skip)")
+    ap.add_argument("--serve-sweep", type=str, default="25,50,100",
+                    help="comma-separated lower arrival rates, 2 s each, to find the rate one GPU sustains")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of the served run")
     ap.add_argument("--serve-slots", type=int, default=128)
     ap.add_argument("--serve-mem-gb", type=float, default=96.0)
@@ -682,6 +704,16 @@ def main():
     if args.serve_seconds > 0:
         print("[bench] served", file=sys.stderr, flush=True)
         line["served"] = served(ctx, args.serve_rate, args.serve_seconds, args.serve_slots, args.serve_mem_gb)
+        sweep = [float(x) for x in args.serve_sweep.split(",") if x.strip()]
+        if sweep:
+            runs = [served(ctx, r, 2.0, args.serve_slots, args.serve_mem_gb) for r in sweep]
+            line["served_sweep"] = [{k: x.get(k) for k in ("rate_hz", "queries", "completed", "solved",
+                                                            "queries_per_s", "latency_p50_ms", "latency_p99_ms",
+                                                            "solved_latency_p50_ms", "solved_latency_p99_ms",
+                                                            "queue_wait_p50_ms", "max_queue_len", "sustained")}
+                                    for x in runs]
+            ok = [x["rate_hz"] for x in runs + [line["served"]] if x.get("sustained")]
+            line["served_max_sustained_rate_hz"] = max(ok) if ok else None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(scene, batches, res, args.cpu_seconds, args.oracle_planner_seeds)

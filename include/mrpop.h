@@ -213,6 +213,26 @@ mrpop_status mrpop_validate_edges_noalloc(mrpop_ctx *ctx, const mrpop_scene *sce
                                           const int32_t *n_states_opt, uint8_t *out_valid,
                                           mrpop_validate_stats *stats_opt, void *stream);
 
+/* Tile shapes of the validation kernel (performance only; the bits never
+ * depend on them) are measured: the first launch of each kind (launch path,
+ * arms, spheres per arm, obstacles, batch-size bucket) runs the tile kernel
+ * once per candidate shape (at most 4, 8 and 16 wavefronts per workgroup),
+ * timed on its stream, which the call then waits for, and later launches of
+ * that kind use the fastest.  mrpop_validate_edges_noalloc and launches under
+ * graph capture never measure.  The choices are kept per process; with a
+ * cache file they are also appended to it, one JSON object per line, and
+ * loaded by later processes.
+ *   cache_file  path of the cache file, or NULL for none; the file is read
+ *               now (missing: empty) and the in-memory choices are replaced.
+ *   enable      1: measure unseen kinds; 0: use known choices, else the
+ *               built-in rule.
+ * Defaults before the first call: MRPOP_TUNE_CACHE (the file) and
+ * MRPOP_AUTOTUNE ("0" disables measuring).  Process-wide; not to be called
+ * while validations run.  Errors: E_INVALID_ARG (enable not 0 or 1). */
+mrpop_status mrpop_tuner_configure(const char *cache_file, int32_t enable);
+/* Number of launch kinds with a chosen shape. */
+int32_t mrpop_tuner_entries(void);
+
 /* ------------------------------------------------------------------------ */
 /* Search primitives                                                         */
 /* ------------------------------------------------------------------------ */

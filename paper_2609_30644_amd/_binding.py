@@ -198,6 +198,9 @@ def load_library():
     lib.mrpop_fk_spheres.argtypes = [P, P, P, I64, P, P]
     lib.mrpop_validate_edges.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
     lib.mrpop_validate_edges_noalloc.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
+    lib.mrpop_tuner_configure.argtypes = [C.c_char_p, I32]
+    lib.mrpop_tuner_entries.argtypes = []
+    lib.mrpop_tuner_entries.restype = I32
     lib.mrpop_nearest.argtypes = [P, P, P, I64, I32, P, P, I64, P, P]
     lib.mrpop_sample.argtypes = [P, P, P, P, P, C.c_float, C.c_uint64, C.c_uint64, I64, I64, P, P, P]
     lib.mrpop_extend.argtypes = [P, P, P, P]
@@ -337,6 +340,15 @@ class Context:
                                            V.shape[1], Q.data_ptr(), None if b is None else b.data_ptr(), Q.shape[0],
                                            out.data_ptr(), self.stream()))
         return out
+
+    def tuner_configure(self, cache_file: Optional[str] = None, enable: bool = True) -> None:
+        """mrpop_tuner_configure: the tile-shape cache file (None: none) and
+        whether unseen launch kinds are measured (process-wide)."""
+        self._check(self._lib.mrpop_tuner_configure(None if cache_file is None else cache_file.encode(),
+                                                     1 if enable else 0), None)
+
+    def tuner_entries(self) -> int:
+        return int(self._lib.mrpop_tuner_entries())
 
     def profile_enable(self, on: bool = True) -> None:
         self.check(self._lib.mrpop_profile_enable(self._h, int(on)))

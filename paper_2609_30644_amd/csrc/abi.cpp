@@ -798,6 +798,14 @@ mrpop_status mrpop_validate_edges(mrpop_ctx *ctx, const mrpop_scene *scene, cons
   return MRPOP_OK;
 }
 
+mrpop_status mrpop_tuner_configure(const char *cache_file, int32_t enable) {
+  if (enable != 0 && enable != 1) return fail(nullptr, MRPOP_E_INVALID_ARG, "tuner_configure: enable must be 0 or 1");
+  tuner_configure(cache_file, enable != 0);
+  return MRPOP_OK;
+}
+
+int32_t mrpop_tuner_entries(void) { return tuner_entries(); }
+
 mrpop_status mrpop_validate_edges_noalloc(mrpop_ctx *ctx, const mrpop_scene *scene, const float *qa,
                                           const float *qb, int64_t n_edges, float resolution,
                                           const int32_t *n_states_opt, uint8_t *out_valid,
@@ -817,7 +825,7 @@ mrpop_status mrpop_validate_edges_noalloc(mrpop_ctx *ctx, const mrpop_scene *sce
   ValidateScratch ws = validate_scratch_layout(base, n_edges);
   hipStream_t s = (hipStream_t)stream;
   e = launch_validate(scene->dev, qa, qb, n_edges, resolution, n_states_opt, out_valid, ws, s, nullptr, nullptr,
-                      nullptr, nullptr);
+                      nullptr, nullptr, /*may_tune=*/false);
   if (e != hipSuccess) return hip_fail(ctx, e, "validate_edges_noalloc launch");
   if (stats_opt) return validate_stats(ctx, ws, s, stats_opt, "validate_edges_noalloc stats");
   return MRPOP_OK;

@@ -1,21 +1,21 @@
 // Many independent planning instances at once (mrpop_plan_batch).
 //
-// Every instance is a PlanJob running on a host thread of its own; its device
-// work goes to a shared queue instead of a stream.  Whenever every unfinished
-// instance is waiting for its queued work, the work of all instances is
-// merged and launched on one stream: layer by layer (the next command of
-// every instance), commands of one kind in one launch over all instances'
-// argument records, and the validations of a layer in one many-scene launch.
-// An instance's commands keep their order, and each instance computes
-// exactly what it computes alone: the batch changes when work runs, never
-// what it computes.
+// Every instance is a PlanJob coroutine driven by one host thread: its
+// device work goes to a queue of its own instead of a stream, and at each
+// synchronisation point it is parked.  Once every running instance is
+// parked, the work of all of them is merged and launched on one stream:
+// layer by layer (the next command of every instance), commands of one kind
+// in one launch over all instances' argument records (a device-resident
+// table of records), and the validations of a layer in one many-scene
+// launch.  Then every parked instance is resumed.  An instance's commands
+// keep their order, and each instance computes exactly what it computes
+// alone: the batch changes when work runs, never what it computes.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <memory>
 #include <mutex>
-#include <thread>
 #include <vector>
 
 #include "batch.h"
@@ -67,19 +67,24 @@ struct HostBuf {
 
 }  // namespace
 
+class QueuedExec;
+
 struct JobEngine::Impl {
   mrpop_ctx *ctx;
   hipStream_t s;
-  std::mutex mu;
-  std::condition_variable cv_main, cv_jobs;
+  std::mutex mu;  // guards only the wake-up of an idle step() (notify from other threads)
+  std::condition_variable cv_main;
   struct Slot {
     std::vector<Cmd> pending;
-    bool used = false, running = false, waiting = false, finished = false;
-    std::thread th;
+    bool used = false, running = false, parked = false, finished = false;
+    PlanJob *job = nullptr;
+    std::function<void(int, mrpop_status)> on_done;
+    std::unique_ptr<QueuedExec> ex;
+    Task<mrpop_status> task;
+    std::coroutine_handle<> resume_at;  // where the job continues (innermost parked coroutine)
   };
   std::vector<Slot> slots;  // fixed capacity
-  int n_running = 0, n_waiting = 0, n_finished = 0;  // finished: ended, not yet reaped
-  uint64_t generation = 0;
+  int n_running = 0, n_finished = 0;  // finished: ended, not yet reaped
   hipError_t last_err = hipSuccess;
   // merge buffers
   HostBuf h_args;
@@ -91,7 +96,8 @@ struct JobEngine::Impl {
   hipError_t flush();
 };
 
-// Device work of one slot, queued for the next merged launch.
+// Device work of one slot, queued for the next merged launch; a
+// synchronisation parks the slot's coroutine until that launch has completed.
 class QueuedExec : public Exec {
  public:
   QueuedExec(JobEngine::Impl *e, int k) : e_(e), k_(k) {}
@@ -99,15 +105,14 @@ class QueuedExec : public Exec {
     e_->slots[k_].pending.push_back(c);
     return hipSuccess;
   }
-  hipError_t sync() override {
-    std::unique_lock<std::mutex> lk(e_->mu);
-    e_->slots[k_].waiting = true;
-    ++e_->n_waiting;
-    const uint64_t gen = e_->generation;
-    e_->cv_main.notify_all();
-    e_->cv_jobs.wait(lk, [&] { return e_->generation != gen; });
-    return e_->last_err;
+  hipError_t sync() override { return hipErrorNotSupported; }  // (deferred: never called)
+  bool deferred() const override { return true; }
+  void park(std::coroutine_handle<> h) override {
+    JobEngine::Impl::Slot &sl = e_->slots[k_];
+    sl.resume_at = h;
+    sl.parked = true;
   }
+  hipError_t resumed_status() override { return e_->last_err; }
 
  private:
   JobEngine::Impl *e_;
@@ -247,15 +252,10 @@ hipError_t JobEngine::Impl::flush() {
 
 JobEngine::JobEngine(mrpop_ctx *ctx, hipStream_t s, int capacity) : impl_(new Impl(ctx, s, std::max(1, capacity))) {}
 
-JobEngine::~JobEngine() {
-  for (auto &sl : impl_->slots)
-    if (sl.th.joinable()) sl.th.join();
-  delete impl_;
-}
+JobEngine::~JobEngine() { delete impl_; }  // (the slots' coroutine frames go with them)
 
 int JobEngine::start(PlanJob *job, std::function<void(int, mrpop_status)> on_done) {
   Impl &I = *impl_;
-  std::lock_guard<std::mutex> lk(I.mu);
   int k = -1;
   for (int i = 0; i < (int)I.slots.size(); ++i)
     if (!I.slots[i].used) {
@@ -267,47 +267,48 @@ int JobEngine::start(PlanJob *job, std::function<void(int, mrpop_status)> on_don
   sl.used = true;
   sl.running = true;
   sl.finished = false;
-  sl.waiting = false;
+  sl.parked = false;
   sl.pending.clear();
+  sl.job = job;
+  sl.on_done = std::move(on_done);
+  sl.ex.reset(new QueuedExec(&I, k));
+  sl.task = job->run(*sl.ex);
+  sl.resume_at = sl.task.handle();  // first resume starts it
   ++I.n_running;
-  const int dev = I.ctx->device;
-  sl.th = std::thread([&I, k, job, on_done, dev] {
-    (void)hipSetDevice(dev);
-    QueuedExec ex(&I, k);
-    const mrpop_status st = job->run(ex);
-    std::lock_guard<std::mutex> g(I.mu);
-    Impl::Slot &me = I.slots[k];
-    me.pending.clear();
-    me.running = false;
-    me.finished = true;
-    --I.n_running;
-    ++I.n_finished;
-    if (on_done) on_done(k, st);
-    I.cv_main.notify_all();
-  });
   return k;
 }
 
 bool JobEngine::step(const std::function<bool()> &wake) {
   Impl &I = *impl_;
-  std::unique_lock<std::mutex> lk(I.mu);
-  I.cv_main.wait(lk, [&] {
-    return I.n_waiting == I.n_running && (I.n_running > 0 || I.n_finished > 0 || wake());
-  });
-  if (I.n_finished > 0 || I.n_running == 0) return false;  // jobs to reap first (or nothing to run)
-  // every running job waits for its device work: merge and launch it (the
-  // jobs stay blocked, so their queues can be read without the lock)
-  lk.unlock();
+  // every running job that is not parked runs until it parks or ends
+  for (int k = 0; k < (int)I.slots.size(); ++k) {
+    Impl::Slot &sl = I.slots[k];
+    if (!sl.running || sl.parked) continue;
+    const std::coroutine_handle<> h = sl.resume_at;
+    sl.resume_at = nullptr;
+    h.resume();
+    if (sl.task.done()) {
+      sl.running = false;
+      sl.finished = true;
+      sl.pending.clear();
+      --I.n_running;
+      ++I.n_finished;
+      if (sl.on_done) sl.on_done(k, sl.task.result());
+    }
+  }
+  if (I.n_finished > 0) return false;  // jobs to reap first
+  if (I.n_running == 0) {              // nothing runs: wait for wake()
+    std::unique_lock<std::mutex> lk(I.mu);
+    I.cv_main.wait(lk, [&] { return wake(); });
+    return false;
+  }
+  // every running job is parked on its device work: merge and launch it
   const hipError_t e = I.flush();
-  lk.lock();
   I.last_err = e;
   for (auto &sl : I.slots) {
     sl.pending.clear();
-    sl.waiting = false;
+    sl.parked = false;
   }
-  I.n_waiting = 0;
-  ++I.generation;
-  I.cv_jobs.notify_all();
   return true;
 }
 
@@ -319,36 +320,29 @@ void JobEngine::notify() {
 std::vector<int> JobEngine::reap() {
   Impl &I = *impl_;
   std::vector<int> done;
-  std::vector<std::thread> ths;
-  {
-    std::lock_guard<std::mutex> lk(I.mu);
-    for (int k = 0; k < (int)I.slots.size(); ++k)
-      if (I.slots[k].used && I.slots[k].finished) {
-        ths.push_back(std::move(I.slots[k].th));
-        I.slots[k].used = false;
-        I.slots[k].finished = false;
-        --I.n_finished;
-        done.push_back(k);
-      }
-  }
-  for (auto &t : ths) t.join();
+  for (int k = 0; k < (int)I.slots.size(); ++k)
+    if (I.slots[k].used && I.slots[k].finished) {
+      Impl::Slot &sl = I.slots[k];
+      sl.task = Task<mrpop_status>();
+      sl.ex.reset();
+      sl.used = false;
+      sl.finished = false;
+      sl.job = nullptr;
+      --I.n_finished;
+      done.push_back(k);
+    }
   return done;
 }
 
-int JobEngine::running() const {
-  std::lock_guard<std::mutex> lk(impl_->mu);
-  return impl_->n_running;
-}
+int JobEngine::running() const { return impl_->n_running; }
 int JobEngine::capacity() const { return (int)impl_->slots.size(); }
 int JobEngine::free_slots() const {
-  std::lock_guard<std::mutex> lk(impl_->mu);
   int n = 0;
   for (const auto &sl : impl_->slots) n += sl.used ? 0 : 1;
   return n;
 }
 int64_t JobEngine::flushes() const { return impl_->flushes; }
 int64_t JobEngine::launches() const { return impl_->launches; }
-std::mutex &JobEngine::mutex() { return impl_->mu; }
 
 }  // namespace mrpop
 

@@ -182,7 +182,7 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
                            const int32_t *n_states_opt, uint8_t *out_valid, const ValidateScratch &ws,
                            hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> *ev_pair = nullptr,
                            uint64_t *totals = nullptr, int32_t *grid_out = nullptr,
-                           int32_t *block_out = nullptr);
+                           int32_t *block_out = nullptr, bool may_tune = true);
 // The same for 1..kFusedMaxEdges edges in one launch, from state-count codes
 // the edges' producer wrote (codes, device [n_edges]; the counts of
 // state_count_code): arrived is a device counter that is zero between
@@ -231,6 +231,12 @@ int seg_link_split(int n_robots, int W);
 // Waves per workgroup and whether joint sines/cosines are cached, for a
 // launch whose largest scene has r_max arms.
 void seg_shape(int r_max, int64_t n_flat, int *W, int *cache_sc);
+// The tile-shape autotuner (validate.hip): a JSON cache file (null: none)
+// whose entries are loaded now and appended to as shapes are measured, and
+// whether unseen launch kinds are measured; the in-memory table is cleared.
+// The defaults come from MRPOP_TUNE_CACHE and MRPOP_AUTOTUNE ("0": off).
+void tuner_configure(const char *cache_file, bool enable);
+int tuner_entries();
 // Largest many-scene batch prepared in one workgroup, and the largest batch
 // counted and scanned in one workgroup: at most kSmallScanEdges edges, and
 // beyond kSmallScanOne edges at most kSmallScanLoads endpoint coordinates

@@ -21,8 +21,11 @@ class PlanJob {
   // the one-arm sub-scenes of the roadmaps.  Queues no device work.
   mrpop_status prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
                        const mrpop_plan_params &params);
-  // Runs the planner; every device operation goes through ex.
-  mrpop_status run(Exec &ex);
+  // The planner as a coroutine: every device operation goes through ex, and
+  // every wait for device work is a suspension point (see SyncPoint).  On a
+  // blocking executor one resume() runs it to the end (run_blocking).
+  Task<mrpop_status> run(Exec &ex);
+  mrpop_status run_blocking(Exec &ex);
   // Before run: a known collision-free path (start to goal, [len][D]) as the
   // incumbent to improve on; it is returned if no cheaper path is found.
   void set_incumbent(const std::vector<float> &path);
@@ -70,7 +73,7 @@ class PlanJob {
   mrpop_status copy_(Exec &ex, void *dst, const void *src, size_t bytes);
   // Submits cs as one group of independent commands, then clears it.
   mrpop_status group_(Exec &ex, std::vector<Cmd> &cs);
-  mrpop_status roadmap_(Exec &ex, int it);
+  Task<mrpop_status> roadmap_(Exec &ex, int it);
   void set_sizes_(const mrpop_scene *scene, const mrpop_plan_params &P);
   size_t plan_arena_(void *base);  // assigns the arena's arrays (base may be null); returns its size
   double elapsed_() const;
@@ -106,11 +109,16 @@ class PlanJob {
   uint8_t *cand_valid_, *pair_valid_, *alive_, *valid_, *cvalid_;
   uint64_t *cnt_;  // [2 + R][16]: counters of the extension, connection and per-arm roadmap validations
   RoundStatus *status_;
+  SearchState *ss_;   // the current search's state (device)
+  uint32_t seq_ = 0;  // sequence number of the last round record queued
   static constexpr int kRmInts = 4;
+  // Search rounds queued per host wait.  Rounds queued after the one that
+  // connects do nothing (a launch each of the three kernels, a few us).
+  static constexpr int kRoundsPerWait = 6;
 
   // pinned host memory (device-visible): uploads, and what comes back
   struct Pinned {
-    RoundStatus status;
+    RoundStatus status[kRoundsPerWait];  // the records of the queued rounds
     int32_t ints[4];
     uint8_t valid2[8];
   };

@@ -322,6 +322,7 @@ size_t PlanJob::plan_arena_(void *base) {
   ar.add(&codes_ext_, 2 * (size_t)PC);
   ar.add(&cnt_, (size_t)(2 + R) * 16);
   ar.add(&status_, 1);
+  ar.add(&ss_, 1);
   ar.add(&path_d_, (size_t)path_max_ * D);
   ar.add(&path_vid_d_, (size_t)path_max_ * R);
   ar.add(&d_nj_, R);
@@ -464,25 +465,26 @@ mrpop_status PlanJob::validate_(Exec &ex, const mrpop_scene *sc, const float *a,
   return e == hipSuccess ? MRPOP_OK : hip_fail_(e, "validate launch");
 }
 
-#define SUBMIT(OPV, FIELD, ...)                         \
-  do {                                                  \
-    Cmd c_;                                             \
-    c_.op = OPV;                                        \
-    c_.FIELD = __VA_ARGS__;                             \
-    const hipError_t e_ = ex.submit(c_);                \
-    if (e_ != hipSuccess) return hip_fail_(e_, #FIELD); \
+// (inside the coroutines run() and roadmap_())
+#define SUBMIT(OPV, FIELD, ...)                            \
+  do {                                                     \
+    Cmd c_;                                                \
+    c_.op = OPV;                                           \
+    c_.FIELD = __VA_ARGS__;                                \
+    const hipError_t e_ = ex.submit(c_);                   \
+    if (e_ != hipSuccess) co_return hip_fail_(e_, #FIELD); \
   } while (0)
 
-#define SYNC()                                          \
-  do {                                                  \
-    const hipError_t e_ = ex.sync();                    \
-    if (e_ != hipSuccess) return hip_fail_(e_, "sync"); \
+#define SYNC()                                             \
+  do {                                                     \
+    const hipError_t e_ = co_await SyncPoint{ex};          \
+    if (e_ != hipSuccess) co_return hip_fail_(e_, "sync"); \
   } while (0)
 
-#define TRY(expr)                   \
-  do {                              \
-    const mrpop_status s_ = (expr); \
-    if (s_ != MRPOP_OK) return s_;  \
+#define TRY(expr)                     \
+  do {                                \
+    const mrpop_status s_ = (expr);   \
+    if (s_ != MRPOP_OK) co_return s_; \
   } while (0)
 
 // ROADMAP (Alg. 2) for outer iteration `it`.  Every arm still unconnected
@@ -492,7 +494,7 @@ mrpop_status PlanJob::validate_(Exec &ex, const mrpop_scene *sc, const float *a,
 // the union of the components they join; connectivity of start and goal is
 // read from the union-find.  The adjacency used by the extension oracle is
 // rebuilt once at the end.
-mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
+Task<mrpop_status> PlanJob::roadmap_(Exec &ex, int it) {
   const int R = R_;
   std::vector<char> conn(R, 0), grew(R, 0);
   std::vector<int> need(R, 0), need0(R, 0), n0(R, 0), np(R, 0), off(R, 0);
@@ -617,7 +619,7 @@ mrpop_status PlanJob::roadmap_(Exec &ex, int it) {
   TRY(group_(ex, grp));
   st_.roadmap_connected = 1;
   for (int r = 0; r < R; ++r) st_.roadmap_connected = st_.roadmap_connected && conn[r];
-  return MRPOP_OK;
+  co_return MRPOP_OK;
 }
 
 // Sum of the Euclidean steps of a path [len][D], in double precision.
@@ -664,7 +666,14 @@ void PlanJob::set_incumbent(const std::vector<float> &path) {
   }
 }
 
-mrpop_status PlanJob::run(Exec &ex) {
+mrpop_status PlanJob::run_blocking(Exec &ex) {
+  Task<mrpop_status> t = run(ex);
+  t.handle().resume();  // every synchronisation point is immediate on a blocking executor
+  if (!t.done()) return fail_(MRPOP_E_DEVICE, "plan: suspended on a blocking executor");
+  return t.result();
+}
+
+Task<mrpop_status> PlanJob::run(Exec &ex) {
   const int R = R_, D = D_, PC = PC_;
   t_start_ = now_s();
   synced_ = false;
@@ -694,57 +703,78 @@ mrpop_status PlanJob::run(Exec &ex) {
   TRY(validate_(ex, scene_, ea_, ea_, 2, 1.0f, valid_, cnt_));
   TRY(copy_(ex, pin_->valid2, valid_, 2));
   SYNC();
-  if (!pin_->valid2[0]) return fail_(MRPOP_E_START_INVALID, "plan: start state collides");
-  if (!pin_->valid2[1]) return fail_(MRPOP_E_GOAL_INVALID, "plan: goal state collides");
+  if (!pin_->valid2[0]) co_return fail_(MRPOP_E_START_INVALID, "plan: start state collides");
+  if (!pin_->valid2[1]) co_return fail_(MRPOP_E_GOAL_INVALID, "plan: goal state collides");
 
   int rnd = 0, it = 0;
   bool overflow_no_path = false;
   std::vector<float> hpath;
   std::vector<int32_t> hvid;
   while (it < P_.max_iterations && rnd < P_.max_rounds && !out_of_time_()) {
-    if (!P_.direct) TRY(roadmap_(ex, it));
-    // fresh trees: 0 rooted at the start, 1 at the goal
-    SUBMIT(Op::TreeRoot, tree_root, TreeRootArgs{tq_[0], tg_[0], tvid_[0], tpar_[0], tn_[0], tcap_, qs_, D, R, 0});
-    SUBMIT(Op::TreeRoot, tree_root, TreeRootArgs{tq_[1], tg_[1], tvid_[1], tpar_[1], tn_[1], tcap_, qg_, D, R, 1});
-    int n_t[2] = {1, 1};
-    int a = 0;  // index of the tree being extended
+    if (!P_.direct) {
+      const mrpop_status rs = co_await roadmap_(ex, it);
+      if (rs != MRPOP_OK) co_return rs;
+    }
+    // fresh trees: 0 rooted at the start, 1 at the goal; a fresh search state
+    SUBMIT(Op::TreeRoot, tree_root,
+           TreeRootArgs{tq_[0], tg_[0], tvid_[0], tpar_[0], tn_[0], tcap_, qs_, D, R, 0, ss_});
+    SUBMIT(Op::TreeRoot, tree_root,
+           TreeRootArgs{tq_[1], tg_[1], tvid_[1], tpar_[1], tn_[1], tcap_, qg_, D, R, 1, nullptr});
+    const TreePair trees{{tq_[0], tq_[1]}, {tg_[0], tg_[1]}, {tvid_[0], tvid_[1]}, {tpar_[0], tpar_[1]},
+                         {tn_[0], tn_[1]}};
     bool solved = false;
     while (!solved && rnd < P_.max_rounds && !out_of_time_()) {
-      if (n_t[a] > n_t[1 - a]) a = 1 - a;
-      const int b = 1 - a;
+      // kRoundsPerWait rounds queued back to back (at most the rounds left):
+      // each round's back half picks the next round's tree on the device, and
+      // the round that connects (or fills the tree) stops the rest
+      const int K = std::min(kRoundsPerWait, P_.max_rounds - rnd);
       const float cb = c_best_;
-      const SampleNearArgs sn{SampleArgs{PC, D, cb, P_.seed, (uint64_t)rnd, 0, scene_->dev.q_lo, scene_->dev.q_hi,
-                                         qs_, qg_, tq_[a], tcap_, q_rand_, c_rand_},
-                              NearestArgs{tq_[a], tg_[a], n_t[a], D, 1, tcap_, q_rand_, D,
-                                          cb < INFINITY ? c_rand_ : nullptr, PC, near_idx_}};
-      // front half: sample, nearest, extension, then the connection search
-      // and edge; one validation of both halves; back half: insertion and
-      // selection (a round is three launches and one host round trip)
-      SUBMIT(Op::RoundFront, round_front,
-             RoundFrontArgs{sn,
-                            ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[a],
-                                       tvid_[a], tg_[a], tcap_, rm_V_, rm_rowptr_, rm_col_, rm_cap_, col_cap_, d_nj_,
-                                       d_qoff_, q_new_, vid_new_, g_new_, alive_, ea_, eb_, P_.resolution, codes_ext_,
-                                       P_.direct, P_.step},
-                            cb, budget_, NearestArgs{tq_[b], tg_[b], n_t[b], D, 1, tcap_, q_new_, D, budget_, PC,
-                                                     conn_idx_},
-                            ConnArgs{PC, D, conn_idx_, q_new_, tq_[b], tcap_, ca_, cb_, P_.resolution, codes_conn_}});
-      TRY(validate_(ex, scene_, ea_, eb_, 2 * (int64_t)PC, P_.resolution, valid_, cnt_, codes_ext_));
-      SUBMIT(Op::InsertSelect, insert_select,
-             InsertSelectArgs{PC, D, R, alive_, valid_, cvalid_, q_new_, g_new_, vid_new_, near_idx_, conn_idx_,
-                              tq_[a], tg_[a], tvid_[a], tpar_[a], tn_[a], tcap_, n_t[a], tq_[b], tg_[b], ins_idx_,
-                              codes_conn_, cnt_, status_, &pin_->status, (uint32_t)rnd + 1u});
-      {
-        const hipError_t e_ = ex.wait_flag(&pin_->status.seq, (uint32_t)rnd + 1u);
-        if (e_ != hipSuccess) return hip_fail_(e_, "round status");
+      for (int k = 0; k < K; ++k) {
+        // the tree fields below are replaced on the device by the search
+        // state's choice (tree 0 stands in)
+        const SampleNearArgs sn{SampleArgs{PC, D, cb, P_.seed, (uint64_t)(rnd + k), 0, scene_->dev.q_lo,
+                                           scene_->dev.q_hi, qs_, qg_, tq_[0], tcap_, q_rand_, c_rand_},
+                                NearestArgs{tq_[0], tg_[0], 1, D, 1, tcap_, q_rand_, D,
+                                            cb < INFINITY ? c_rand_ : nullptr, PC, near_idx_}};
+        // front half: sample, nearest, extension, then the connection search
+        // and edge; one validation of both halves; back half: insertion and
+        // selection
+        SUBMIT(Op::RoundFront, round_front,
+               RoundFrontArgs{sn,
+                              ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[0],
+                                         tvid_[0], tg_[0], tcap_, rm_V_, rm_rowptr_, rm_col_, rm_cap_, col_cap_,
+                                         d_nj_, d_qoff_, q_new_, vid_new_, g_new_, alive_, ea_, eb_, P_.resolution,
+                                         codes_ext_, P_.direct, P_.step},
+                              cb, budget_,
+                              NearestArgs{tq_[1], tg_[1], 1, D, 1, tcap_, q_new_, D, budget_, PC, conn_idx_},
+                              ConnArgs{PC, D, conn_idx_, q_new_, tq_[1], tcap_, ca_, cb_, P_.resolution,
+                                       codes_conn_},
+                              trees, ss_});
+        TRY(validate_(ex, scene_, ea_, eb_, 2 * (int64_t)PC, P_.resolution, valid_, cnt_, codes_ext_));
+        SUBMIT(Op::InsertSelect, insert_select,
+               InsertSelectArgs{PC, D, R, alive_, valid_, cvalid_, q_new_, g_new_, vid_new_, near_idx_, conn_idx_,
+                                trees, tcap_, ss_, ins_idx_, codes_conn_, cnt_, status_, &pin_->status[k],
+                                seq_ + (uint32_t)k + 1u});
       }
-      const RoundStatus rsx = pin_->status;
-      st_.edge_states += rsx.states_ext + rsx.states_conn;
-      st_.speculative_edge_states += rsx.states_spec;
-      n_t[a] += rsx.inserted;
-      if (rsx.overflow) st_.capacity_hit = 1;
-      ++rnd;
-      if (rsx.found) {
+      {
+        const hipError_t e_ = co_await SyncPoint{ex, &pin_->status[K - 1].seq, seq_ + (uint32_t)K};
+        if (e_ != hipSuccess) co_return hip_fail_(e_, "round status");
+      }
+      seq_ += (uint32_t)K;
+      bool stopped = false, overflow = false;
+      for (int k = 0; k < K && !stopped; ++k) {
+        const RoundStatus rsx = pin_->status[k];
+        if (rsx.skipped) break;
+        st_.edge_states += rsx.states_ext + rsx.states_conn;
+        st_.speculative_edge_states += rsx.states_spec;
+        if (rsx.overflow) {
+          st_.capacity_hit = 1;
+          overflow = true;
+        }
+        ++rnd;
+        stopped = rsx.found || rsx.overflow;
+        if (!rsx.found) continue;
+        const int a = rsx.a, b = 1 - rsx.a;
         SUBMIT(Op::Path, path,
                PathArgs{rsx.a_idx, rsx.b_idx, D, tcap_, path_max_, tpar_[a], tpar_[b], tq_[a], tq_[b], path_d_,
                         &pin_->ints[0], R, tvid_[a], tvid_[b], path_vid_d_});
@@ -752,49 +782,56 @@ mrpop_status PlanJob::run(Exec &ex) {
         const int len = pin_->ints[0];
         if (len > path_max_ || len < 2) {
           st_.capacity_hit = 1;
-        } else {
-          const size_t need = (size_t)len * D, need_v = (size_t)len * R;
-          const size_t bytes = sizeof(float) * need + sizeof(int32_t) * need_v;
-          if (bytes > pin_path_cap_) {
-            if (pin_path_) (void)hipHostFree(pin_path_);
-            pin_path_ = nullptr;
-            pin_path_cap_ = 0;
-            const hipError_t e = hipHostMalloc((void **)&pin_path_, bytes);
-            if (e != hipSuccess) return hip_fail_(e, "hipHostMalloc(path)");
-            pin_path_cap_ = bytes;
-          }
-          int32_t *pin_vid = (int32_t *)(pin_path_ + need);
-          TRY(copy_(ex, pin_path_, path_d_, sizeof(float) * need));
-          TRY(copy_(ex, pin_vid, path_vid_d_, sizeof(int32_t) * need_v));
-          SYNC();
-          hpath.assign(pin_path_, pin_path_ + need);
-          hvid.assign(pin_vid, pin_vid + need_v);
-          if (a == 1) {  // tree 1 is rooted at the goal: orient start -> goal
-            for (int x = 0, y = len - 1; x < y; ++x, --y) {
-              std::swap_ranges(hpath.begin() + (size_t)x * D, hpath.begin() + (size_t)(x + 1) * D,
-                               hpath.begin() + (size_t)y * D);
-              std::swap_ranges(hvid.begin() + (size_t)x * R, hvid.begin() + (size_t)(x + 1) * R,
-                               hvid.begin() + (size_t)y * R);
-            }
-          }
-          const double cost = path_cost(hpath, D);
-          if ((float)cost < c_best_) {  // strictly cheaper incumbents only
-            c_best_ = (float)cost;
-            best_path_ = hpath;
-            history_.push_back(Incumbent{hpath, hvid, c_best_, elapsed_(), rnd - 1});
-            if (st_.n_costs < 64) st_.costs[st_.n_costs++] = c_best_;
-            ++st_.solutions;
-            if (st_.first_round < 0) {
-              st_.first_round = rnd - 1;
-              st_.time_to_first_s = elapsed_();
-            }
-            solved = true;
+          continue;
+        }
+        const size_t need = (size_t)len * D, need_v = (size_t)len * R;
+        const size_t bytes = sizeof(float) * need + sizeof(int32_t) * need_v;
+        if (bytes > pin_path_cap_) {
+          if (pin_path_) (void)hipHostFree(pin_path_);
+          pin_path_ = nullptr;
+          pin_path_cap_ = 0;
+          const hipError_t e = hipHostMalloc((void **)&pin_path_, bytes);
+          if (e != hipSuccess) co_return hip_fail_(e, "hipHostMalloc(path)");
+          pin_path_cap_ = bytes;
+        }
+        int32_t *pin_vid = (int32_t *)(pin_path_ + need);
+        TRY(copy_(ex, pin_path_, path_d_, sizeof(float) * need));
+        TRY(copy_(ex, pin_vid, path_vid_d_, sizeof(int32_t) * need_v));
+        SYNC();
+        hpath.assign(pin_path_, pin_path_ + need);
+        hvid.assign(pin_vid, pin_vid + need_v);
+        if (a == 1) {  // tree 1 is rooted at the goal: orient start -> goal
+          for (int x = 0, y = len - 1; x < y; ++x, --y) {
+            std::swap_ranges(hpath.begin() + (size_t)x * D, hpath.begin() + (size_t)(x + 1) * D,
+                             hpath.begin() + (size_t)y * D);
+            std::swap_ranges(hvid.begin() + (size_t)x * R, hvid.begin() + (size_t)(x + 1) * R,
+                             hvid.begin() + (size_t)y * R);
           }
         }
+        const double cost = path_cost(hpath, D);
+        if ((float)cost < c_best_) {  // strictly cheaper incumbents only
+          c_best_ = (float)cost;
+          best_path_ = hpath;
+          history_.push_back(Incumbent{hpath, hvid, c_best_, elapsed_(), rnd - 1});
+          if (st_.n_costs < 64) st_.costs[st_.n_costs++] = c_best_;
+          ++st_.solutions;
+          if (st_.first_round < 0) {
+            st_.first_round = rnd - 1;
+            st_.time_to_first_s = elapsed_();
+          }
+          solved = true;
+        }
       }
-      if (rsx.overflow && !solved) {
+      if (overflow && !solved) {
         overflow_no_path = best_path_.empty();
         break;
+      }
+      if (stopped && !solved) {  // a connection no cheaper in double precision: the search goes on
+        grp.clear();
+        grp.emplace_back();
+        grp.back().op = Op::Fill;
+        grp.back().fill = FillArgs{(uint32_t *)&ss_->stop, 0u, 1};
+        TRY(group_(ex, grp));
       }
     }
     ++it;
@@ -808,9 +845,9 @@ mrpop_status PlanJob::run(Exec &ex) {
   for (int r = 0; r < R && !P_.direct; ++r) st_.roadmap_vertices += rm_n_[r];
   st_.total_time_s = elapsed_();
   if (best_path_.empty())
-    return overflow_no_path ? fail_(MRPOP_E_CAPACITY, "plan: search tree full before any solution")
+    co_return overflow_no_path ? fail_(MRPOP_E_CAPACITY, "plan: search tree full before any solution")
                             : fail_(MRPOP_E_NO_SOLUTION, "plan: budget exhausted without a solution");
-  return MRPOP_OK;
+  co_return MRPOP_OK;
 }
 
 #undef SUBMIT
@@ -971,7 +1008,7 @@ static mrpop_status plan_impl(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   if (st == MRPOP_OK) {
     if (incumbent) job.set_incumbent(*incumbent);
     PlainExec ex(ctx, nullptr);
-    st = job.run(ex);
+    st = job.run_blocking(ex);
     if (hist) {
       const mrpop_status hs = write_history(job, hist);
       if (st == MRPOP_OK && hs != MRPOP_OK) st = hs;

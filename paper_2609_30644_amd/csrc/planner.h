@@ -2,6 +2,7 @@
 #pragma once
 
 #include "mrpop_internal.h"
+#include "task.h"
 
 namespace mrpop {
 
@@ -62,10 +63,32 @@ struct ExtendArgs {
   float step;
 };
 
+// Device-side state of one search (a dRRT or AO-X call of Alg. 2): the tree
+// the next round extends (the smaller one) and the trees' sizes, so that
+// rounds can be queued back to back without the host deciding between them.
+// The round that finds a connection or fills the tree sets `stop`; the rounds
+// queued after it then do nothing.
+struct SearchState {
+  int32_t a;     // tree the next round extends: 0 is rooted at the start, 1 at the goal
+  int32_t n[2];  // vertices per tree
+  int32_t stop;
+};
+
+// Both search trees (structure of arrays), indexed by tree.
+struct TreePair {
+  float *q[2];       // [dim][tree_cap]
+  float *g[2];       // [tree_cap]
+  int32_t *vid[2];   // [n_robots][tree_cap]
+  int32_t *parent[2];
+  int32_t *n[2];     // vertex count (a copy of the search state's)
+};
+
 struct RoundStatus {
   int32_t found, cand, a_idx, b_idx;
   float total;
   int32_t inserted, overflow;
+  int32_t a;        // the tree this round extended
+  int32_t skipped;  // 1: the search had stopped before this round
   uint32_t seq;  // in the host copy: stored last, with a system-scope release (the round's number)
   int64_t states_ext, states_conn;
   int64_t states_spec;  // states of connection edges checked for candidates that were not inserted
@@ -104,6 +127,11 @@ struct RoundFrontArgs {
   float *budget;  // [n]
   NearestArgs q2;
   ConnArgs c;
+  // The trees and the search state: the kernel takes the extended tree a and
+  // the other tree from them (the tree fields and sizes in sn, e, q2 and c
+  // are replaced); when the search has stopped it writes edges with no states.
+  TreePair t;
+  const SearchState *ss;
 };
 
 // The back half, one workgroup: the survivors (alive, extension edge free)
@@ -117,11 +145,9 @@ struct InsertSelectArgs {
   const uint8_t *alive, *valid, *cvalid;  // valid: extension edges; cvalid: connection edges
   const float *q_new, *g_new;
   const int32_t *vid_new, *near_idx, *conn_idx;
-  float *tree_q, *tree_g;
-  int32_t *tree_vid, *tree_parent, *tree_n;
+  TreePair t;         // the round extends tree ss->a and connects to the other
   int tree_cap;
-  int n_before;  // vertices in the tree before this insertion (the host's count)
-  const float *other_q, *other_g;
+  SearchState *ss;    // read, then advanced: sizes, the next tree (the smaller), stop
   int32_t *ins_idx;
   const int32_t *codes_conn;  // [n] state-count codes of the connection edges
   const uint64_t *counters;   // the round's validation counters ([1]: states of both halves)
@@ -147,6 +173,7 @@ struct TreeRootArgs {
   int tree_cap;
   const float *q;
   int dim, n_robots, vid;
+  SearchState *ss;  // or null: set to a fresh search (tree 0 next, both trees of one vertex)
 };
 
 struct RmSampleArgs {
@@ -315,6 +342,30 @@ class Exec {
     (void)value;
     return sync();
   }
+  // A deferred executor never blocks: at a synchronisation point the job's
+  // coroutine is parked (park) and resumed once the submitted work has
+  // completed, with that work's status (resumed_status).
+  virtual bool deferred() const { return false; }
+  virtual void park(std::coroutine_handle<> h) { (void)h; }
+  virtual hipError_t resumed_status() { return hipSuccess; }
+};
+
+// co_await SyncPoint{ex, flag, value}: everything submitted to ex has
+// completed (flag null: ex.sync(); else ex.wait_flag(flag, value)); yields the
+// HIP status.  Immediate on a blocking executor; parks the coroutine on a
+// deferred one.
+struct SyncPoint {
+  Exec &ex;
+  const uint32_t *flag = nullptr;
+  uint32_t value = 0;
+  hipError_t err = hipSuccess;
+  bool await_ready() {
+    if (ex.deferred()) return false;
+    err = flag ? ex.wait_flag(flag, value) : ex.sync();
+    return true;
+  }
+  void await_suspend(std::coroutine_handle<> h) { ex.park(h); }
+  hipError_t await_resume() { return ex.deferred() ? ex.resumed_status() : err; }
 };
 
 }  // namespace mrpop

@@ -522,20 +522,51 @@ __device__ __forceinline__ void sample_near_body(const SampleNearArgs &a, int bx
 // after the check, and both edges go to one validation.
 __device__ __forceinline__ void round_front_body(const RoundFrontArgs &A, int bx) {
   if (bx >= A.sn.s.n) return;
-  sample_near_body(A.sn, bx);
+  const SearchState st = *A.ss;  // written by the previous round's back half
+  const int ta = st.a, tb = 1 - st.a;
+  if (st.stop) {  // the search has ended: null edges at the start root with no states
+    const int D = A.e.dim;
+    float *ea = A.e.edge_a + (int64_t)bx * D, *eb = A.e.edge_b + (int64_t)bx * D;
+    float *ca = A.c.edge_a + (int64_t)bx * D, *cb = A.c.edge_b + (int64_t)bx * D;
+    for (int j = threadIdx.x; j < D; j += blockDim.x) {
+      const float y = A.t.q[0][(int64_t)j * A.e.tree_cap];
+      ea[j] = eb[j] = ca[j] = cb[j] = y;
+    }
+    if (threadIdx.x == 0) {
+      A.e.alive[bx] = 0;
+      if (A.e.n_codes) A.e.n_codes[bx] = 0;
+      if (A.c.n_codes) A.c.n_codes[bx] = 0;
+    }
+    return;
+  }
+  SampleNearArgs sn = A.sn;
+  sn.s.root = A.t.q[ta];
+  sn.q.V = A.t.q[ta];
+  sn.q.g = A.t.g[ta];
+  sn.q.n = st.n[ta];
+  ExtendArgs e = A.e;
+  e.tree_q = A.t.q[ta];
+  e.tree_vid = A.t.vid[ta];
+  e.tree_g = A.t.g[ta];
+  NearestArgs q2 = A.q2;
+  q2.V = A.t.q[tb];
+  q2.g = A.t.g[tb];
+  q2.n = st.n[tb];
+  ConnArgs c = A.c;
+  c.other_q = A.t.q[tb];
+  sample_near_body(sn, bx);
   __syncthreads();
   if (threadIdx.x < kWave) {
     const int lane = (int)threadIdx.x;
-    if (A.e.direct) steer_one(A.e, bx, lane);
-    else extend_one(A.e, bx, lane);
+    if (e.direct) steer_one(e, bx, lane);
+    else extend_one(e, bx, lane);
     // (lane 0 wrote alive and g_new)
-    if (lane == 0)
-      A.budget[bx] = !A.e.alive[bx] ? -1.f : (A.c_best < INFINITY ? A.c_best - A.e.g_new[bx] : INFINITY);
+    if (lane == 0) A.budget[bx] = !e.alive[bx] ? -1.f : (A.c_best < INFINITY ? A.c_best - e.g_new[bx] : INFINITY);
   }
   __syncthreads();
-  nearest_body(A.q2, bx);
+  nearest_body(q2, bx);
   __syncthreads();
-  if (threadIdx.x < kWave) conn_one(A.c, bx, (int)threadIdx.x);
+  if (threadIdx.x < kWave) conn_one(c, bx, (int)threadIdx.x);
 }
 
 // One workgroup of 1024 threads.  Survivors are placed in candidate order
@@ -544,8 +575,42 @@ __device__ __forceinline__ void round_front_body(const RoundFrontArgs &A, int bx
 // the tree (SoA), and the cheapest free connection among the inserted
 // candidates is reduced over lanes and waves.  Connection states of
 // candidates that were not inserted are counted apart (speculative work).
+__device__ __forceinline__ void publish_status(const RoundStatus &st, RoundStatus *o, uint32_t seq) {
+  o->found = st.found;
+  o->cand = st.cand;
+  o->a_idx = st.a_idx;
+  o->b_idx = st.b_idx;
+  o->total = st.total;
+  o->inserted = st.inserted;
+  o->overflow = st.overflow;
+  o->a = st.a;
+  o->skipped = st.skipped;
+  o->states_ext = st.states_ext;
+  o->states_conn = st.states_conn;
+  o->states_spec = st.states_spec;
+  __hip_atomic_store(&o->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, int bx) {
   if (bx != 0) return;
+  const SearchState ss = *a.ss;
+  if (ss.stop) {  // the search has ended: an empty record
+    if (threadIdx.x == 0) {
+      RoundStatus st{};
+      st.cand = st.a_idx = st.b_idx = -1;
+      st.total = INFINITY;
+      st.a = ss.a;
+      st.skipped = 1;
+      *a.status = st;
+      if (a.status_out) publish_status(st, a.status_out, a.seq);
+    }
+    return;
+  }
+  const int ta = ss.a, tb = 1 - ss.a;
+  float *const tree_q = a.t.q[ta], *const tree_g = a.t.g[ta];
+  int32_t *const tree_vid = a.t.vid[ta], *const tree_parent = a.t.parent[ta];
+  const float *const other_q = a.t.q[tb], *const other_g = a.t.g[tb];
+  const int n_before = ss.n[ta];
   constexpr int kMaxW = 1024 / kWave;
   __shared__ int32_t s_wsum[kMaxW];
   __shared__ int32_t s_base;
@@ -568,12 +633,12 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
       chunk += s_wsum[k];
     }
     if (i < a.n) {
-      const int pos = a.n_before + s_base + off + before;
+      const int pos = n_before + s_base + off + before;
       const int32_t t = (ok && pos < a.tree_cap) ? pos : -1;
       a.ins_idx[i] = t;
       if (t >= 0) {
-        a.tree_g[t] = a.g_new[i];
-        a.tree_parent[t] = a.near_idx[i];
+        tree_g[t] = a.g_new[i];
+        tree_parent[t] = a.near_idx[i];
       }
     }
     __syncthreads();
@@ -581,19 +646,19 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
     __syncthreads();
   }
   const int all = s_base;
-  const int room = a.tree_cap - a.n_before;
+  const int room = a.tree_cap - n_before;
   const int inserted = all < room ? all : room;
   // rows of the inserted candidates (their tree indices written above,
   // visible behind the barrier)
   for (int64_t k = threadIdx.x; k < (int64_t)a.n * a.dim; k += blockDim.x) {
     const int i = (int)(k / a.dim), j = (int)(k - (int64_t)i * a.dim);
     const int32_t t = a.ins_idx[i];
-    if (t >= 0) a.tree_q[(int64_t)j * a.tree_cap + t] = a.q_new[k];
+    if (t >= 0) tree_q[(int64_t)j * a.tree_cap + t] = a.q_new[k];
   }
   for (int64_t k = threadIdx.x; k < (int64_t)a.n * a.n_robots; k += blockDim.x) {
     const int r = (int)(k / a.n), i = (int)(k - (int64_t)r * a.n);
     const int32_t t = a.ins_idx[i];
-    if (t >= 0) a.tree_vid[(int64_t)r * a.tree_cap + t] = a.vid_new[k];
+    if (t >= 0) tree_vid[(int64_t)r * a.tree_cap + t] = a.vid_new[k];
   }
   // cheapest free connection of an inserted candidate; connection states
   float best = INFINITY;
@@ -608,10 +673,10 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
     if (t < 0 || c < 0 || !a.cvalid[i]) continue;
     float d2 = 0.f;
     for (int j = 0; j < a.dim; ++j) {
-      const float x = a.q_new[(int64_t)i * a.dim + j] - a.other_q[(int64_t)j * a.tree_cap + c];
+      const float x = a.q_new[(int64_t)i * a.dim + j] - other_q[(int64_t)j * a.tree_cap + c];
       d2 = fmaf(x, x, d2);
     }
-    const float tot = a.g_new[i] + sqrtf(d2) + a.other_g[c];
+    const float tot = a.g_new[i] + sqrtf(d2) + other_g[c];
     if (tot < best || (tot == best && (bi < 0 || i < bi))) {
       best = tot;
       bi = i;
@@ -637,42 +702,41 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
   if (threadIdx.x == 0) {
     float bc = s_cost[0];
     int bc_i = s_cand[0];
-    unsigned long long su = s_states[0][0], ss = s_states[1][0];
+    unsigned long long su = s_states[0][0], ss_ = s_states[1][0];
     for (int k = 1; k < nw; ++k) {
       if (s_cand[k] >= 0 && (bc_i < 0 || s_cost[k] < bc || (s_cost[k] == bc && s_cand[k] < bc_i))) {
         bc = s_cost[k];
         bc_i = s_cand[k];
       }
       su += s_states[0][k];
-      ss += s_states[1][k];
+      ss_ += s_states[1][k];
     }
-    *a.tree_n = a.n_before + inserted;
-    RoundStatus *st = a.status;
-    st->found = bc_i >= 0 ? 1 : 0;
-    st->cand = bc_i;
-    st->a_idx = bc_i >= 0 ? a.ins_idx[bc_i] : -1;
-    st->b_idx = bc_i >= 0 ? a.conn_idx[bc_i] : -1;
-    st->total = bc;
-    st->inserted = inserted;
-    st->overflow = all > room ? 1 : 0;
+    const int n_after = n_before + inserted;
+    *a.t.n[ta] = n_after;
+    RoundStatus st{};
+    st.found = bc_i >= 0 ? 1 : 0;
+    st.cand = bc_i;
+    st.a_idx = bc_i >= 0 ? a.ins_idx[bc_i] : -1;
+    st.b_idx = bc_i >= 0 ? a.conn_idx[bc_i] : -1;
+    st.total = bc;
+    st.inserted = inserted;
+    st.overflow = all > room ? 1 : 0;
+    st.a = ta;
+    st.skipped = 0;
     const int64_t total_states = a.counters ? (int64_t)a.counters[1] : 0;
-    st->states_conn = (int64_t)su;
-    st->states_spec = (int64_t)ss;
-    st->states_ext = total_states - (int64_t)su - (int64_t)ss;
-    if (a.status_out) {  // the record, then its sequence number (the host waits on it)
-      RoundStatus *o = a.status_out;
-      o->found = st->found;
-      o->cand = st->cand;
-      o->a_idx = st->a_idx;
-      o->b_idx = st->b_idx;
-      o->total = st->total;
-      o->inserted = st->inserted;
-      o->overflow = st->overflow;
-      o->states_ext = st->states_ext;
-      o->states_conn = st->states_conn;
-      o->states_spec = st->states_spec;
-      __hip_atomic_store(&o->seq, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+    st.states_conn = (int64_t)su;
+    st.states_spec = (int64_t)ss_;
+    st.states_ext = total_states - (int64_t)su - (int64_t)ss_;
+    *a.status = st;
+    // the next round extends the smaller tree (equal sizes: the same one);
+    // a connection or a full tree ends the search
+    SearchState nx;
+    nx.n[ta] = n_after;
+    nx.n[tb] = ss.n[tb];
+    nx.a = nx.n[ta] > nx.n[tb] ? tb : ta;
+    nx.stop = (st.found || st.overflow) ? 1 : 0;
+    *a.ss = nx;
+    if (a.status_out) publish_status(st, a.status_out, a.seq);
   }
 }
 
@@ -713,6 +777,7 @@ __device__ __forceinline__ void tree_root_body(const TreeRootArgs &A, int bx) {
     tree_g[0] = 0.f;
     tree_parent[0] = -1;
     *tree_n = 1;
+    if (A.ss) *A.ss = SearchState{0, {1, 1}, 0};
   }
 }
 

@@ -35,8 +35,14 @@
 // coherent load it needs cost a memory round trip per tile.
 #include <hip/hip_ext.h>
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <type_traits>
+#include <vector>
 
 #include "device_common.h"
 
@@ -1452,14 +1458,160 @@ static size_t centre_lds_bytes(int n_robots, int W, int cache_sc) {
 // copy fits next to the published centres.
 constexpr size_t kLdsBudget = 150 * 1024;
 
-static TileShape tile_shape(int n_robots, int64_t n_edges) {
-  const int cap = n_edges <= kSmallBatchEdges ? kMaxWavesPerBlock : kMaxWavesPerBlock / 2;
+// The rule for a workgroup of at most `cap` waves.
+static TileShape tile_shape_cap(int n_robots, int cap) {
   int S = 1;
   while (S < kMaxLinks && n_robots * S * 2 <= cap) S *= 2;
   int W = std::min(n_robots * S, cap);
   while (W > 1 && centre_lds_bytes(n_robots, W, 0) > kLdsBudget) W /= 2;
   const int cache = centre_lds_bytes(n_robots, W, 1) <= kLdsBudget ? 1 : 0;
   return {S, W, cache};
+}
+
+static TileShape tile_shape(int n_robots, int64_t n_edges) {
+  return tile_shape_cap(n_robots, n_edges <= kSmallBatchEdges ? kMaxWavesPerBlock : kMaxWavesPerBlock / 2);
+}
+
+// ---------------------------------------------------------------------------
+// Tile-shape autotuner
+// ---------------------------------------------------------------------------
+//
+// The waves per workgroup of the tile kernel are measured, not only ruled:
+// the first launch of each kind -- (launch path, arms, spheres per arm,
+// obstacles, batch-size bucket) -- runs the tile kernel once per candidate
+// shape (at most 4, 8 and 16 waves), timed with events on the launch stream,
+// and keeps the fastest.  Bits do not depend on the shape (each candidate
+// makes the same decisions; the last run's stand).  Choices live in memory
+// per process and, when a cache file is configured, in a JSON file of one
+// entry per line that later processes load.
+namespace {
+
+struct TuneKey {
+  int path, R, S, n_obs, bucket;
+  bool operator<(const TuneKey &o) const {
+    if (path != o.path) return path < o.path;
+    if (R != o.R) return R < o.R;
+    if (S != o.S) return S < o.S;
+    if (n_obs != o.n_obs) return n_obs < o.n_obs;
+    return bucket < o.bucket;
+  }
+};
+
+struct Tuner {
+  std::mutex mu;
+  bool init = false, enabled = true;
+  std::string file;
+  std::map<TuneKey, int> table;  // key -> W
+
+  void defaults_locked() {
+    if (init) return;
+    init = true;
+    const char *e = std::getenv("MRPOP_AUTOTUNE");
+    enabled = !(e && std::strcmp(e, "0") == 0);
+    const char *f = std::getenv("MRPOP_TUNE_CACHE");
+    file = f ? f : "";
+    load_locked();
+  }
+  void load_locked() {
+    if (file.empty()) return;
+    FILE *fp = std::fopen(file.c_str(), "r");
+    if (!fp) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, fp)) {
+      TuneKey k;
+      int W = 0;
+      char path[16] = {0};
+      if (std::sscanf(line, " {\"path\": \"%15[a-z]\", \"arms\": %d, \"spheres\": %d, \"obstacles\": %d, "
+                      "\"bucket\": %d, \"waves\": %d", path, &k.R, &k.S, &k.n_obs, &k.bucket, &W) == 6 &&
+          W >= 1 && W <= kMaxWavesPerBlock) {
+        k.path = std::strcmp(path, "small") == 0 ? 1 : std::strcmp(path, "general") == 0 ? 0 : -1;
+        if (k.path >= 0) table[k] = W;
+      }
+    }
+    std::fclose(fp);
+  }
+  void store_locked(const TuneKey &k, int W, const int *cand, const float *us, int n) {
+    table[k] = W;
+    if (file.empty()) return;
+    FILE *fp = std::fopen(file.c_str(), "a");
+    if (!fp) return;
+    std::fprintf(fp, "{\"path\": \"%s\", \"arms\": %d, \"spheres\": %d, \"obstacles\": %d, \"bucket\": %d, "
+                 "\"waves\": %d, \"measured_us\": {", k.path == 1 ? "small" : "general", k.R, k.S, k.n_obs,
+                 k.bucket, W);
+    for (int i = 0; i < n; ++i) std::fprintf(fp, "%s\"%d\": %.2f", i ? ", " : "", cand[i], us[i]);
+    std::fprintf(fp, "}}\n");
+    std::fclose(fp);
+  }
+};
+
+Tuner &tuner() {
+  static Tuner t;
+  return t;
+}
+
+TuneKey tune_key(const SceneDev &sc, int64_t n_edges, int path) {
+  int b = 0;
+  while ((int64_t(1) << b) < n_edges && b < 62) ++b;
+  return {path, sc.n_robots, sc.sph_stride, sc.n_env_spheres + sc.n_env_boxes, b};
+}
+
+}  // namespace
+
+// Shape of a launch: the tuned one for its key, else the rule's (then, when
+// tuning is on and `may_tune`, *cands gets the shapes to measure).
+static TileShape chosen_shape(const SceneDev &sc, int64_t n_edges, int path, bool may_tune,
+                              std::vector<TileShape> *cands, TuneKey *key) {
+  const TileShape rule = tile_shape(sc.n_robots, n_edges);
+  Tuner &T = tuner();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.defaults_locked();
+  *key = tune_key(sc, n_edges, path);
+  const auto it = T.table.find(*key);
+  if (it != T.table.end()) {
+    for (int cap : {4, 8, kMaxWavesPerBlock}) {
+      const TileShape ts = tile_shape_cap(sc.n_robots, cap);
+      if (ts.W == it->second) return ts;
+    }
+    return rule;
+  }
+  if (may_tune && T.enabled) {
+    for (int cap : {4, 8, kMaxWavesPerBlock}) {
+      const TileShape ts = tile_shape_cap(sc.n_robots, cap);
+      bool seen = false;
+      for (const TileShape &c : *cands) seen = seen || c.W == ts.W;
+      if (!seen) cands->push_back(ts);
+    }
+    if (cands->size() < 2) cands->clear();
+  }
+  return rule;
+}
+
+static void tuned(const TuneKey &k, const std::vector<TileShape> &cands, const std::vector<float> &us) {
+  int best = 0;
+  for (size_t i = 1; i < us.size(); ++i)
+    if (us[i] < us[best]) best = (int)i;
+  std::vector<int> w;
+  for (const TileShape &c : cands) w.push_back(c.W);
+  Tuner &T = tuner();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.store_locked(k, cands[best].W, w.data(), us.data(), (int)us.size());
+}
+
+void tuner_configure(const char *cache_file, bool enable) {
+  Tuner &T = tuner();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.init = true;
+  T.enabled = enable;
+  T.file = cache_file ? cache_file : "";
+  T.table.clear();
+  T.load_locked();
+}
+
+int tuner_entries() {
+  Tuner &T = tuner();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.defaults_locked();
+  return (int)T.table.size();
 }
 
 // LDS of one CU.
@@ -1513,10 +1665,43 @@ static int persistent_grid(int W, size_t lds) {
   return grid;
 }
 
+static bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// Runs launch(shape, start, stop) for every candidate, timing each with its
+// own events (the caller's event pair, if any, on the last one), and records
+// the fastest for `key`.  Waits for the stream.
+template <class Launch>
+static hipError_t time_candidates(const std::vector<TileShape> &cands, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                                  Launch &&launch, const TuneKey &key) {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  std::vector<float> us;
+  for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
+    const bool last = i + 1 == cands.size();
+    e = hipEventRecord(a, s);
+    if (e != hipSuccess) break;
+    launch(cands[i], last ? e0 : nullptr, last ? e1 : nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    if ((e = hipEventRecord(b, s)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(b)) != hipSuccess) break;
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
+    us.push_back(ms * 1e3f);
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (e == hipSuccess) tuned(key, cands, us);
+  return e;
+}
+
 hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb, int64_t n_edges, float res,
                            const int32_t *n_states_opt, uint8_t *out_valid, const ValidateScratch &ws,
                            hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> *ev_pair, uint64_t *totals,
-                           int32_t *grid_out, int32_t *block_out) {
+                           int32_t *grid_out, int32_t *block_out, bool may_tune) {
   const int64_t nb = scan_blocks(n_edges);
   const int64_t g256 = (n_edges + 255) / 256;
   if (g256 > 0x7fffffff || nb > 0x7fffffff) return hipErrorInvalidValue;
@@ -1532,22 +1717,35 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
     hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.n_states, n_edges,
                        ws.block_sums, ws.offsets, ws.tile_first);
   }
-  const TileShape ts = tile_shape(sc.n_robots, n_edges);
-  const bool staged = use_staged(sc, ts);
-  const size_t lds =
-      centre_lds_bytes(sc.n_robots, ts.W, ts.cache_sc) + (staged ? staged_floats(sc) * sizeof(float) : 0);
+  std::vector<TileShape> cands;
+  TuneKey key;
+  const TileShape ts0 = chosen_shape(sc, n_edges, 0, may_tune && !capturing(s), &cands, &key);
   // with events: recorded by the dispatch itself, at the kernel's start and end
   hipEvent_t e0 = ev_pair ? ev_pair->first : nullptr, e1 = ev_pair ? ev_pair->second : nullptr;
   int grid = 0;
-  auto go = [&](auto staged_c, auto cache_c) {
-    constexpr bool ST = decltype(staged_c)::value, CA = decltype(cache_c)::value;
-    grid = persistent_grid<ST, CA>(ts.W, lds);
-    hipExtLaunchKernelGGL(validate_tiles_kernel<ST, CA>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
-                          sc, qa, qb, n_edges, ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials, ts.S);
+  auto launch_tiles = [&](const TileShape &ts, hipEvent_t a, hipEvent_t b) {
+    const bool staged = use_staged(sc, ts);
+    const size_t lds =
+        centre_lds_bytes(sc.n_robots, ts.W, ts.cache_sc) + (staged ? staged_floats(sc) * sizeof(float) : 0);
+    auto go = [&](auto staged_c, auto cache_c) {
+      constexpr bool ST = decltype(staged_c)::value, CA = decltype(cache_c)::value;
+      grid = persistent_grid<ST, CA>(ts.W, lds);
+      hipExtLaunchKernelGGL(validate_tiles_kernel<ST, CA>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, a, b,
+                            0, sc, qa, qb, n_edges, ws.offsets, ws.tile_first, ws.flags, ws.counters, ws.partials,
+                            ts.S);
+    };
+    dispatch_tile(staged, ts.cache_sc != 0, go);
+    if (block_out) *block_out = kWave * ts.W;
   };
-  dispatch_tile(staged, ts.cache_sc != 0, go);
+  if (cands.empty()) {
+    launch_tiles(ts0, e0, e1);
+  } else {  // measured: every candidate once (the flag words only gather hits), the last one's partials stand
+    const hipError_t te = time_candidates(cands, s, e0, e1, [&](const TileShape &ts, hipEvent_t a, hipEvent_t b) {
+      launch_tiles(ts, a, b);
+    }, key);
+    if (te != hipSuccess) return te;
+  }
   if (grid_out) *grid_out = grid;
-  if (block_out) *block_out = kWave * ts.W;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)g256), dim3(256), 0, s, ws.flags, n_edges, out_valid,
                      ws.counters, ws.partials, grid, totals);
   return hipGetLastError();
@@ -1582,22 +1780,32 @@ hipError_t launch_validate_small(const SceneDev &sc, const float *qa, const floa
                                  int32_t *grid_out, int32_t *block_out) {
   if (n_edges <= 0 || n_edges > kFusedMaxEdges || !codes || !arrived || (token & 0x80000000u) == 0u)
     return hipErrorInvalidValue;
-  const TileShape ts = tile_shape(sc.n_robots, n_edges);
-  const bool staged = use_staged(sc, ts);
-  const size_t lds =
-      centre_lds_bytes(sc.n_robots, ts.W, ts.cache_sc) + (staged ? staged_floats(sc) * sizeof(float) : 0);
+  std::vector<TileShape> cands;
+  TuneKey key;
+  const TileShape ts0 = chosen_shape(sc, n_edges, 1, !capturing(s), &cands, &key);
   hipEvent_t e0 = ev_pair ? ev_pair->first : nullptr, e1 = ev_pair ? ev_pair->second : nullptr;
   int grid = 0;
-  auto go = [&](auto staged_c, auto cache_c) {
-    constexpr bool ST = decltype(staged_c)::value, CA = decltype(cache_c)::value;
-    grid = small_grid<ST, CA>(ts.W, lds);
-    hipExtLaunchKernelGGL(validate_small_kernel<ST, CA>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, e0, e1, 0,
-                          sc, qa, qb, (int)n_edges, codes, ws.flags, token, out_valid, ws.counters, ws.partials,
-                          arrived, totals, ts.S);
+  auto launch_small = [&](const TileShape &ts, hipEvent_t a, hipEvent_t b) {
+    const bool staged = use_staged(sc, ts);
+    const size_t lds =
+        centre_lds_bytes(sc.n_robots, ts.W, ts.cache_sc) + (staged ? staged_floats(sc) * sizeof(float) : 0);
+    auto go = [&](auto staged_c, auto cache_c) {
+      constexpr bool ST = decltype(staged_c)::value, CA = decltype(cache_c)::value;
+      grid = small_grid<ST, CA>(ts.W, lds);
+      hipExtLaunchKernelGGL(validate_small_kernel<ST, CA>, dim3(grid), dim3(kWave * ts.W), (uint32_t)lds, s, a, b,
+                            0, sc, qa, qb, (int)n_edges, codes, ws.flags, token, out_valid, ws.counters,
+                            ws.partials, arrived, totals, ts.S);
+    };
+    dispatch_tile(staged, ts.cache_sc != 0, go);
+    if (block_out) *block_out = kWave * ts.W;
   };
-  dispatch_tile(staged, ts.cache_sc != 0, go);
+  if (cands.empty()) {
+    launch_small(ts0, e0, e1);
+  } else {  // measured: each candidate is a whole validation; the last one's bits and counters stand
+    const hipError_t te = time_candidates(cands, s, e0, e1, launch_small, key);
+    if (te != hipSuccess) return te;
+  }
   if (grid_out) *grid_out = grid;
-  if (block_out) *block_out = kWave * ts.W;
   return hipGetLastError();
 }
 

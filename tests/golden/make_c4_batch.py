@@ -22,7 +22,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
-N_INSTANCES = 64
+N_INSTANCES = 512
 SEED = 0
 DELTA = 3.0
 

@@ -185,11 +185,12 @@ class Scene:
         return h.hexdigest()
 
 
-def ring_bases(n_robots: int, radius: float) -> np.ndarray:
-    """Bases evenly spaced on a circle, each yawed to face the centre."""
+def ring_bases(n_robots: int, radius: float, offset: float = 0.0) -> np.ndarray:
+    """Bases evenly spaced on a circle (the first at angle `offset`), each
+    yawed to face the centre."""
     out = []
     for i in range(n_robots):
-        ang = 2.0 * math.pi * i / n_robots
+        ang = offset + 2.0 * math.pi * i / n_robots
         out.append(base_transform(radius * math.cos(ang), radius * math.sin(ang), ang + math.pi))
     return np.stack(out).astype(F32)
 
@@ -260,10 +261,12 @@ def shelf_grid_boxes(rng, levels=(0.2, 0.5, 0.8, 1.1), n_side=8, pitch=0.3, jitt
 
 def scene_c3(seed: int) -> Scene:
     """8 arms x 59 spheres on a circle of radius 1.5 m around a shared table;
-    256 cuboids in a 4-level 8 x 8 shelf grid with 0.3 m pitch."""
+    256 cuboids in a 4-level 8 x 8 shelf grid with 0.3 m pitch.  The ring
+    starts at 22.5 degrees so that no base stands on a corner of the grid
+    (the grid's corners lie on the circle at 45 + k 90 degrees)."""
     rng = np.random.default_rng([3, seed])
     m = panda_like(59)
-    return Scene([m] * 8, ring_bases(8, 1.5), np.zeros((0, 4), F32), shelf_grid_boxes(rng),
+    return Scene([m] * 8, ring_bases(8, 1.5, math.pi / 8), np.zeros((0, 4), F32), shelf_grid_boxes(rng),
                  name=f"c3/{seed}", meta={"grid": True})
 
 

@@ -55,6 +55,8 @@ C1_FIXTURE = os.path.join(ROOT, "tests", "golden", "c1_problems.json")
 C1_PLAN = dict(candidates=128, n_roadmap=32, delta=3.0, max_rounds=100000, max_iterations=100000,
                time_budget_s=5.0)
 C1_PLAN_ORACLE = dict(candidates=128, n_roadmap=32, delta=3.0, max_rounds=2000, max_iterations=100)
+# the oracle is far slower than the GPU planner: its wall-clock cap per problem is larger
+ORACLE_PLAN_BUDGET_S = 10.0
 
 # The 8-arm shelf workload: validation batches (4096 certainly free, 4096
 # unselected; 0.02 rad) and cost-bounded replanning for 30 s.
@@ -182,12 +184,15 @@ def checker_rate(scene, batches, res, target_s: float, threads: int) -> dict:
 
     k, passes = 64, 1
     states, dt = run(k)
+    print(f"[bench]   checker, {threads} thread(s): {k} edges x {passes} in {dt:.2f} s", file=sys.stderr, flush=True)
     while dt < target_s / 2:
         if k < 4096:
             k = min(4096, int(k * max(2.0, target_s / max(dt, 1e-3) / 2)))
         else:
             passes = max(passes + 1, int(passes * target_s / max(dt, 1e-3)))
         states, dt = run(k, passes)
+        print(f"[bench]   checker, {threads} thread(s): {k} edges x {passes} in {dt:.2f} s",
+              file=sys.stderr, flush=True)
     return {"value": states / dt, "unit": "edge-states/s", "cores": threads,
             "sample": f"{passes} pass(es) over the first {k} edges of each batch ({states} edge-states), "
                       f"FP64 coarse-to-fine checker with early exit, {dt:.1f} s"}
@@ -201,18 +206,21 @@ def oracle_planner_tts(n_seeds: int) -> dict:
     from oracle import planner as PL
     d = json.load(open(C1_FIXTURE))
     tts, ok = [], 0
-    for pr in d["problems"][:n_seeds]:
+    for j, pr in enumerate(d["problems"][:n_seeds]):
         sc = W.scene_c1(pr["seed"]).with_env(np.array(pr["env_spheres"], np.float32).reshape(-1, 4),
                                              np.array(pr["env_boxes"], np.float32).reshape(-1, 6))
-        prm = PL.PlanParams(**dict(C1_PLAN_ORACLE, seed=pr["seed"], stop_at_first=True))
+        prm = PL.PlanParams(**dict(C1_PLAN_ORACLE, seed=pr["seed"], stop_at_first=True,
+                                   time_budget_s=ORACLE_PLAN_BUDGET_S))
         t0 = time.perf_counter()
         r = PL.plan(sc, np.array(pr["q_start"], np.float32), np.array(pr["q_goal"], np.float32), prm)
         dt = time.perf_counter() - t0
         if r.status == "OK":
             ok += 1
             tts.append(dt)
+        if (j + 1) % 10 == 0:
+            print(f"[bench]   oracle planner: {j + 1} problems, {ok} solved", file=sys.stderr, flush=True)
     return {"problems": n_seeds, "solved": ok, "tts_p50_ms": float(np.median(tts)) * 1e3 if tts else None,
-            "threads": 1, "params": C1_PLAN_ORACLE,
+            "threads": 1, "params": C1_PLAN_ORACLE, "budget_s": ORACLE_PLAN_BUDGET_S,
             "note": "wall time of oracle.planner.plan with stop_at_first (roadmaps, then the initial search)"}
 
 
@@ -220,7 +228,7 @@ def cpu_baseline(scene, batches, res, target_s: float, planner_seeds: int) -> di
     """The oracle on the host cores: its checker on all cores (at most 16
     threads, the host share of one GPU) and on one thread, and its planner
     on the first C1 problems."""
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
     allc = checker_rate(scene, batches, res, target_s / 2, threads)
     one = checker_rate(scene, batches, res, target_s / 2, 1)
     out = {"value": allc["value"], "unit": "edge-states/s", "cores": threads, "kind": "oracle",

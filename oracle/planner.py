@@ -21,7 +21,11 @@ Readings where the paper is silent (each is also a GPU-side rule):
     first n free in draw order), then every pair (new vertex i, any vertex
     j < i) closer than delta becomes an edge when its single-arm motion is
     free; BFS from the start vertex (0) to the goal vertex (1).  Roadmaps
-    persist across calls.
+    persist across calls.  A call grows for at most max_growth_rounds
+    rounds; if an arm is still unconnected then, the iteration runs no
+    search (the tensor product has no start-goal path) and the next
+    iteration's call grows on, so that over the iterations ROADMAP loops
+    until every arm is connected, as Alg. 2 has it.
   * ORACLE_AOX (the dRRT oracle with AO-X's admissibility; Sec. "Converge to
     Global Optimality"): per arm, a roadmap neighbour u of the arm's vertex
     in z_near is admissible when the composite neighbour that moves this arm
@@ -55,6 +59,7 @@ Readings where the paper is silent (each is also a GPU-side rule):
 from __future__ import annotations
 
 import math
+import time
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -87,6 +92,9 @@ class PlanParams:
     # cost-bounded searches on fresh trees (Sec. "Methodology": the paper's
     # asymptotically optimal multi-robot baseline)
     rewire: bool = False
+    # wall-clock bound on plan() (0: none), checked between rounds; it stops
+    # the run, it changes no result of a round
+    time_budget_s: float = 0.0
 
 
 @dataclass
@@ -581,15 +589,20 @@ def plan(scene, q_start, q_goal, params: PlanParams, warm_path=None) -> PlanResu
     def composite(vid):
         return np.concatenate([roadmaps[r].V[vid[r]] for r in range(R)]).astype(np.float32)
 
+    t0 = time.perf_counter()
+    out_of_time = lambda: params.time_budget_s > 0 and time.perf_counter() - t0 >= params.time_budget_s
     ta = tb = None
-    while it < params.max_iterations and rnd < params.max_rounds:
-        if not params.direct:
-            roadmap_step(scene, roadmaps, arm_scenes, params, it, q_off)
+    while it < params.max_iterations and rnd < params.max_rounds and not out_of_time():
+        if not params.direct and not roadmap_step(scene, roadmaps, arm_scenes, params, it, q_off):
+            # ROADMAP (Alg. 2) grows until every arm connects its start and
+            # goal; until then the tensor product holds no start-goal path
+            it += 1
+            continue
         if ta is None or not params.rewire:  # ao-dRRT keeps its trees across searches
             ta, tb = _new_tree(q_start, tuple([0] * R)), _new_tree(q_goal, tuple([1] * R))
             a_is_start = True
         solved = False
-        while not solved and rnd < params.max_rounds:
+        while not solved and rnd < params.max_rounds and not out_of_time():
             if needs_swap(ta, tb):
                 ta, tb = tb, ta
                 a_is_start = not a_is_start

@@ -707,13 +707,24 @@ Task<mrpop_status> PlanJob::run(Exec &ex) {
   if (!pin_->valid2[1]) co_return fail_(MRPOP_E_GOAL_INVALID, "plan: goal state collides");
 
   int rnd = 0, it = 0;
-  bool overflow_no_path = false;
+  bool overflow_no_path = false, roadmap_full = false;
   std::vector<float> hpath;
   std::vector<int32_t> hvid;
   while (it < P_.max_iterations && rnd < P_.max_rounds && !out_of_time_()) {
     if (!P_.direct) {
       const mrpop_status rs = co_await roadmap_(ex, it);
       if (rs != MRPOP_OK) co_return rs;
+      if (!st_.roadmap_connected) {
+        // some arm's start and goal are still in different components, so
+        // the tensor product holds no start-goal path: ROADMAP goes on
+        // growing in the next iteration instead of a search that cannot end
+        ++it;
+        if (st_.capacity_hit) {
+          roadmap_full = true;
+          break;
+        }
+        continue;
+      }
     }
     // fresh trees: 0 rooted at the start, 1 at the goal; a fresh search state
     SUBMIT(Op::TreeRoot, tree_root,
@@ -844,9 +855,11 @@ Task<mrpop_status> PlanJob::run(Exec &ex) {
   st_.iterations = it;
   for (int r = 0; r < R && !P_.direct; ++r) st_.roadmap_vertices += rm_n_[r];
   st_.total_time_s = elapsed_();
-  if (best_path_.empty())
+  if (best_path_.empty()) {
+    if (roadmap_full) co_return fail_(MRPOP_E_CAPACITY, "plan: roadmap full before start and goal were connected");
     co_return overflow_no_path ? fail_(MRPOP_E_CAPACITY, "plan: search tree full before any solution")
                             : fail_(MRPOP_E_NO_SOLUTION, "plan: budget exhausted without a solution");
+  }
   co_return MRPOP_OK;
 }
 

@@ -323,7 +323,7 @@ typedef struct {
   int32_t candidates;        /* P: candidate iterations per search round (1..4096) */
   float resolution;          /* edge discretisation (rad), > 0 */
   int32_t max_rounds;        /* search rounds over the whole call, > 0 */
-  int32_t max_iterations;    /* outer iterations: roadmap growth then one search */
+  int32_t max_iterations;    /* outer iterations: roadmap growth, then one search once every arm is connected */
   int32_t max_growth_rounds; /* roadmap growth rounds per iteration */
   double time_budget_s;      /* wall-clock budget in seconds; 0 = none */
   int32_t max_tree_nodes;    /* vertices per search tree */
@@ -417,7 +417,10 @@ void mrpop_plan_params_default(mrpop_plan_params *p);
 /* MR. POP (Alg. 1): grow per-arm roadmaps (ROADMAP), search their tensor
  * product with bidirectional dRRT for a first path, then repeat roadmap
  * growth and cost-bounded search (AO-X) for strictly cheaper paths until a
- * budget runs out.  Blocking; runs on the null stream of ctx's device.
+ * budget runs out.  An iteration whose roadmaps leave some arm's start and
+ * goal unconnected runs no search (the next one grows on); a search whose
+ * tree fills up ends, and the next iteration starts afresh.  Blocking; runs
+ * on the null stream of ctx's device.
  *   q_start, q_goal  host [D], composite configurations.
  *   path_out         host [path_cap][D]: the best path, start to goal.
  *   path_len         host: its number of waypoints (also on E_BUFFER).
@@ -425,7 +428,8 @@ void mrpop_plan_params_default(mrpop_plan_params *p);
  *   stats_opt        host or NULL.
  * Status: OK with a path; E_START_INVALID / E_GOAL_INVALID when an endpoint
  * collides; E_NONFINITE; E_NO_SOLUTION when the budget ends without a path;
- * E_CAPACITY when a tree filled up before any path; E_BUFFER when path_cap is
+ * E_CAPACITY when the budget ends without a path after a search tree or a
+ * roadmap filled up; E_BUFFER when path_cap is
  * too small; E_INVALID_ARG for out-of-range parameters. */
 mrpop_status mrpop_plan(mrpop_ctx *ctx, const mrpop_scene *scene, const float *q_start, const float *q_goal,
                         const mrpop_plan_params *params, float *path_out, int32_t path_cap, int32_t *path_len,

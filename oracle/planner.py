@@ -49,6 +49,11 @@ Readings where the paper is silent (each is also a GPU-side rule):
   * Connection: NEAREST in the other tree with budget c_best - g_new (the
     initial solve uses an infinite budget); accepted only if the new path is
     strictly cheaper than the incumbent.
+  * Tree capacity: a search whose round finds T_a full (a free extension
+    that max_tree_nodes leaves out) ends after that round, and the next outer
+    iteration starts afresh (roadmaps grow, new trees): Alg. 1 loops until
+    the time budget, so the memory bound restarts a search rather than
+    ending the plan.  ao-dRRT, whose trees persist, ends there.
   * Direct mode (single-robot planning without the roadmap layer): no
     ROADMAP; an extension steers from q_near toward q_rand, all the way when
     q_rand is within `step` (Euclidean), else by exactly `step` along the
@@ -313,6 +318,7 @@ class RoundOutcome:
     cvalid: list = field(default_factory=list)    # their edge bits
     best: Optional[tuple] = None                  # (total cost, i, index in T_a, index in T_b)
     edge_states: int = 0
+    overflow: bool = False                        # a free extension found T_a full
 
 
 def search_round(osc, roadmaps, ta, tb, draws, c_best: float, params: PlanParams, composite) -> RoundOutcome:
@@ -358,6 +364,7 @@ def search_round(osc, roadmaps, ta, tb, draws, c_best: float, params: PlanParams
         out.valid = [bool(v) for v in valid]
         out.edge_states += int(n.sum())
     for c, v in zip(out.cands, out.valid):
+        out.overflow |= v and len(ta) >= params.max_tree_nodes
         if v and len(ta) < params.max_tree_nodes:
             ta.q.append(c[3])
             ta.g.append(np.float32(c[4]))
@@ -515,6 +522,7 @@ def rewire_round(osc, roadmaps, ta, tb, draws, c_best: float, params: PlanParams
         out.pvalid = [bool(v) for v in valid]
     slot = {}
     for c, v in zip(out.cands, out.valid):
+        out.overflow |= v and len(ta) >= params.max_tree_nodes
         if v and len(ta) < params.max_tree_nodes:
             ta.q.append(c[3])
             ta.g.append(np.float32(c[4]))
@@ -584,7 +592,7 @@ def plan(scene, q_start, q_goal, params: PlanParams, warm_path=None) -> PlanResu
         best_path = np.asarray(warm_path, np.float32)
         c_best = _cost(best_path)
     rnd, it, first_round, edge_states = 0, 0, -1, 0
-    solved = False
+    solved = overflow = False
 
     def composite(vid):
         return np.concatenate([roadmaps[r].V[vid[r]] for r in range(R)]).astype(np.float32)
@@ -629,12 +637,15 @@ def plan(scene, q_start, q_goal, params: PlanParams, warm_path=None) -> PlanResu
                         first_round = rnd
                     solved = True
             rnd += 1
+            if out.overflow and not solved:  # the tree is full: this search is over
+                overflow = True
+                break
         it += 1
         if solved and params.stop_at_first:
             break
-        if not solved:
+        if overflow and not solved and params.rewire:  # its trees persist, full
             break
-    status = "OK" if best_path is not None else "E_NO_SOLUTION"
+    status = "OK" if best_path is not None else ("E_CAPACITY" if overflow else "E_NO_SOLUTION")
     trees = () if ta is None else ((ta, tb) if a_is_start else (tb, ta))
     return PlanResult(status, best_path, c_best, rnd, it, first_round, costs, edge_states, roadmaps, solved, history,
                       trace, trees)

@@ -489,8 +489,11 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   const double Mx = base_far + reach + rc_max + obs_r;
   const double eps = 20.0 * std::ldexp(1.0, -24) * Mx * Mx;
   const double delta = std::max(1e-4, std::min(std::sqrt(eps), eps / (2.0 * std::max(rc_min, 1e-30))));
-  const int NS = env->n_spheres, NB = env->n_boxes, NO = NS + NB, NO4 = std::max(4, (NO + 3) & ~3);
-  std::vector<float4> rows((size_t)M * kMaxLinks * NO4, float4{0.f, 0.f, 0.f, 3.0e38f});
+  // rows per link padded to a multiple of eight (the tile kernel tests two
+  // groups of four per step), plus one group past the last link's rows, which
+  // the kernel's prefetch of the next group may read
+  const int NS = env->n_spheres, NB = env->n_boxes, NO = NS + NB, NO4 = std::max(8, (NO + 7) & ~7);
+  std::vector<float4> rows((size_t)M * kMaxLinks * NO4 + 4, float4{0.f, 0.f, 0.f, 3.0e38f});
   // bounding sphere of every obstacle: centre (single precision) and radius
   std::vector<float4> bound(std::max(1, NO));
   for (int k = 0; k < NS; ++k) bound[k] = env_s[k];

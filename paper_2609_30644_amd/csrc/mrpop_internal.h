@@ -61,7 +61,8 @@ struct SceneDev {
   // over the scene's extent, so the filter never drops a contact; links a
   // model lacks get w = +3e38.
   // Rows of each link are padded with never-passing entries (w = +3e38) to
-  // n_rows4, a multiple of four, so that the kernel reads them in groups.
+  // n_rows4, a multiple of eight, so that the kernel reads them in pairs of
+  // groups of four; one more group of padding follows the last link.
   int32_t n_rows4;
   const float4 *rows;      // [M][kMaxLinks][n_rows4]
   const float *q_lo, *q_hi;  // [D] composite joint limits

@@ -845,9 +845,10 @@ Task<mrpop_status> PlanJob::run(Exec &ex) {
         TRY(group_(ex, grp));
       }
     }
+    // a search ends unsolved only when its tree is full (rounds and time are
+    // checked above): the next iteration grows the roadmaps and starts afresh
     ++it;
-    if (!solved) break;
-    if (P_.stop_at_first && !best_path_.empty()) break;
+    if (P_.stop_at_first && solved) break;
   }
   SYNC();  // a failure of queued work is reported here at the latest
   synced_ = true;

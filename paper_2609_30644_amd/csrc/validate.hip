@@ -427,14 +427,12 @@ struct Src<true> {
   const int32_t *lstart; // [M][kMaxLinks + 1]
   const float *crad;     // [M][kMaxLinks]
   int ns, nb, n4, stride;
-  // rows k0 .. k0 + kGroup - 1 of link l: one 64-byte scalar load.  The rows
-  // are the same for every lane; from LDS each read would write them into
-  // every lane's registers, which costs more LDS bandwidth than the tests
-  // they feed.
-  __device__ void group(int m, int l, int k0, float4 (&r)[kGroup]) const {
-    const cptr<float> p = (cptr<float>)(rows + ((int64_t)m * kMaxLinks + l) * n4 + k0);
-#pragma unroll
-    for (int i = 0; i < kGroup; ++i) r[i] = make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
+  // the rows of link l, read kGroup at a time (one 64-byte scalar load each).
+  // The rows are the same for every lane; from LDS each read would write them
+  // into every lane's registers, which costs more LDS bandwidth than the
+  // tests they feed.
+  __device__ cptr<float> link_rows(int m, int l) const {
+    return (cptr<float>)(rows + ((int64_t)m * kMaxLinks + l) * n4);
   }
   __device__ float4 sphere(int k) const { return env_s[k]; }
   __device__ float4 box(int i) const { return boxes[i]; }
@@ -449,11 +447,8 @@ struct Src<false> {
   const float4 *env_s, *boxes;  // read at lane-varying indices
   cptr<int32_t> lstart;
   int ns, nb, n4, stride;
-  // rows k0 .. k0 + kGroup - 1 of link l: one 64-byte scalar load
-  __device__ void group(int m, int l, int k0, float4 (&r)[kGroup]) const {
-    const cptr<float> p = (cptr<float>)(rows + ((int64_t)m * kMaxLinks + l) * n4 + k0);
-#pragma unroll
-    for (int i = 0; i < kGroup; ++i) r[i] = make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
+  __device__ cptr<float> link_rows(int m, int l) const {
+    return (cptr<float>)(rows + ((int64_t)m * kMaxLinks + l) * n4);
   }
   __device__ float4 sphere(int k) const { return env_s[k]; }
   __device__ float4 box(int i) const { return boxes[i]; }
@@ -613,9 +608,9 @@ __device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int 
   const float4 csr = make_float4(cs.x, cs.y, cs.z, src.rad(m, l));
   const uint64_t livem = __builtin_amdgcn_ballot_w64(live);
   int qn = 0;  // wave-uniform queue length
-  for (int k0 = 0; k0 < src.n4; k0 += kGroup) {
-    float4 rw[kGroup];
-    src.group(m, l, k0, rw);
+  // one group of kGroup obstacles: the coarse tests, and the flagged pairs
+  // queued (flushed once the queue is long enough)
+  auto group_tests = [&](const float4 (&rw)[kGroup], int k0) {
     bool h[kGroup];
     uint64_t b[kGroup], any = 0;
 #pragma unroll
@@ -625,7 +620,7 @@ __device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int 
       b[i] = __builtin_amdgcn_ballot_w64(h[i]);
       any |= b[i];
     }
-    if ((any & livem) == 0ull) continue;
+    if ((any & livem) == 0ull) return;
 #pragma unroll
     for (int i = 0; i < kGroup; ++i) {
       const uint64_t bi = b[i] & livem;
@@ -639,6 +634,27 @@ __device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int 
       flush_queue<STAGED>(src, m, l, csr, fr, queue, qn, hitw, lane, wc);
       qn = 0;
     }
+  };
+  // Two groups per step over two row buffers, software-pipelined: each
+  // group's scalar load is in flight while the group before it is tested.
+  // n4 is a multiple of 2 kGroup; the last step's prefetch reads the group
+  // that follows the link's rows (the next link's, or the padding after the
+  // last link) and leaves it unused.
+  auto load = [](cptr<float> p, float4 (&r)[kGroup]) {
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) r[i] = make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
+  };
+  cptr<float> p = src.link_rows(m, l);
+  float4 ra[kGroup], rb[kGroup];
+  load(p, ra);
+  for (int k0 = 0; k0 < src.n4; k0 += 2 * kGroup) {
+    load(p + 4 * kGroup, rb);
+    __builtin_amdgcn_sched_barrier(0);  // keep each load ahead of the tests it overlaps
+    group_tests(ra, k0);
+    load(p + 8 * kGroup, ra);
+    __builtin_amdgcn_sched_barrier(0);
+    group_tests(rb, k0 + kGroup);
+    p += 8 * kGroup;
   }
   if (qn > 0) flush_queue<STAGED>(src, m, l, csr, fr, queue, qn, hitw, lane, wc);
   const bool hit = live && ((*hitw >> lane) & 1ull);

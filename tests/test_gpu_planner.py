@@ -296,6 +296,31 @@ def test_plan_empty_scene_single_arm_reaches_roadmap_optimum(ctx):
     assert abs(res.cost - best) <= 1e-5 * best, (res.cost, best, res.stats)
 
 
+@pytest.mark.parametrize("case", ["roadmaps_unconnected", "tree_full"])
+def test_plan_outer_loop_matches_oracle(ctx, case):
+    """Alg. 1's outer loop: an iteration that leaves an arm's start and goal
+    unconnected runs no search (the next one grows on), and a search whose
+    tree fills up ends and the next iteration starts afresh.  Both planners
+    draw the same streams, so they agree on the outcome, the rounds, the
+    iterations and the roadmap sizes."""
+    from oracle.planner import plan as oplan, PlanParams
+    kw = {"roadmaps_unconnected": dict(seed=1, candidates=64, max_rounds=40, max_iterations=4, n_roadmap=2,
+                                       delta=3.0, max_growth_rounds=1),
+          "tree_full": dict(seed=1, candidates=64, max_rounds=12, max_iterations=6, n_roadmap=32, delta=3.0,
+                            max_tree_nodes=3)}[case]
+    p = problem("c1")
+    o = oplan(p.scene, p.q_start, p.q_goal, PlanParams(**kw))
+    g, _, _ = _scene(ctx, p.scene).plan_with_history(p.q_start, p.q_goal, raise_on_error=False, roadmaps=True, **kw)
+    print(f"  {case}: oracle {o.status} rounds {o.rounds} iterations {o.iterations}; "
+          f"gpu {g.status} rounds {g.stats['rounds']} iterations {g.stats['iterations']}", flush=True)
+    assert o.status == {"roadmaps_unconnected": "E_NO_SOLUTION", "tree_full": "E_CAPACITY"}[case]
+    assert (g.status, g.stats["rounds"], g.stats["iterations"]) == (o.status, o.rounds, o.iterations)
+    assert g.stats["roadmap_vertices"] == sum(len(m.V) for m in o.roadmaps)
+    for (V, _), m in zip(g.stats["roadmaps"], o.roadmaps):
+        mv = np.asarray(m.V, np.float32)  # the samples' affine map rounds once on each side
+        assert V.shape[0] == mv.shape[0] and np.abs(V[:, :mv.shape[1]] - mv).max() <= 4e-6
+
+
 def test_plan_error_paths(ctx):
     import paper_2609_30644_amd as M
     p = problem("c1")

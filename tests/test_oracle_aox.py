@@ -225,3 +225,31 @@ def test_smaller_tree_is_extended(c1):
     assert r.trace and all(na <= nb for _, _, na, nb in r.trace)
     assert any(not a_is_start for _, a_is_start, _, _ in r.trace)
     assert any(na < nb for _, _, na, nb in r.trace)
+
+
+# --------------------------------------------------------------------------
+# the outer loop (Alg. 1) around ROADMAP and the searches
+# --------------------------------------------------------------------------
+
+def test_no_search_until_roadmaps_connect(c1):
+    """Two samples per growth round, one growth round per iteration: the
+    roadmaps stay unconnected for four iterations, so no search round runs,
+    and every iteration grows each arm by two vertices."""
+    r = PL.plan(c1.scene, c1.q_start, c1.q_goal,
+                PL.PlanParams(seed=1, candidates=64, max_rounds=40, max_iterations=4, n_roadmap=2, delta=3.0,
+                              max_growth_rounds=1))
+    assert not any(m.connected() for m in r.roadmaps)
+    assert (r.status, r.rounds, r.iterations, r.trace) == ("E_NO_SOLUTION", 0, 4, [])
+    assert [len(m.V) for m in r.roadmaps] == [2 + 4 * 2] * 2
+
+
+def test_full_tree_restarts_the_search(c1):
+    """With room for three vertices per tree, the first round's free
+    extensions overflow T_a: the search ends there and every further
+    iteration starts over from the two roots; no path is found and the
+    result says the capacity was the limit."""
+    r = PL.plan(c1.scene, c1.q_start, c1.q_goal,
+                PL.PlanParams(seed=1, candidates=64, max_rounds=12, max_iterations=6, n_roadmap=32, delta=3.0,
+                              max_tree_nodes=3))
+    assert (r.status, r.rounds, r.iterations) == ("E_CAPACITY", 6, 6)
+    assert [(na, nb) for _, _, na, nb in r.trace] == [(1, 1)] * 6

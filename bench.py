@@ -389,7 +389,7 @@ def batched_vs_plain(ctx, n_inst: int) -> dict:
 SERVE_FIXTURE = os.path.join(ROOT, "tests", "golden", "c5_served.json")
 # Per-query settings of the served workload: first solution within a round
 # budget and a 2 s deadline (counted from admission).
-SERVE_PLAN = dict(candidates=64, n_roadmap=16, delta=3.0, resolution=0.05, max_rounds=100, max_iterations=1,
+SERVE_PLAN = dict(candidates=64, n_roadmap=16, delta=3.0, resolution=0.05, max_rounds=200, max_iterations=4,
                   stop_at_first=1, max_tree_nodes=8192, max_roadmap_nodes=2048, time_budget_s=2.0)
 
 

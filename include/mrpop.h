@@ -337,6 +337,16 @@ typedef struct {
    * most `step` (Euclidean, rad) instead of along roadmap edges. */
   int32_t direct;
   float step;                /* direct mode: extension length, > 0 */
+  /* The asymptotically optimal multi-robot baseline of the paper's
+   * experiments (Sec. "Methodology": a bidirectional ao-dRRT that improves
+   * paths by rewiring instead of AO-X): 1 keeps both trees across searches;
+   * NEAREST and the dRRT extension take no cost bound; a new vertex's parent
+   * is its cheapest tensor-product neighbour in the tree, and up to four tree
+   * vertices whose cost drops through it are rewired to it (largest drop
+   * first), when their edge is free, with the costs of their descendants
+   * recomputed.  Samples, the connection and its budget c_best - g_new are
+   * as in AO-X.  Requires direct 0 and max_roadmap_nodes <= 8192. */
+  int32_t rewire;
 } mrpop_plan_params;
 
 typedef struct {
@@ -357,6 +367,7 @@ typedef struct {
    * the states of those whose candidate did not (work done ahead and not
    * needed) are counted here and not in edge_states. */
   int64_t speculative_edge_states;
+  int64_t rewired;           /* rewiring: tree vertices given a cheaper parent */
 } mrpop_plan_stats;
 
 /* Incumbent history (paper, Sec. "Seeding for Multi-Robot Jerk-Free
@@ -411,7 +422,7 @@ typedef struct {
 /* Defaults: seed 0, delta 3.0, n_roadmap 32, candidates 128, resolution
  * 0.05, max_rounds 1000, max_iterations 8, max_growth_rounds 16, no time
  * budget, 65536 tree and 8192 roadmap vertices, stop_at_first 0, no warm
- * cost, direct 0, step 1.0. */
+ * cost, direct 0, step 1.0, rewire 0. */
 void mrpop_plan_params_default(mrpop_plan_params *p);
 
 /* MR. POP (Alg. 1): grow per-arm roadmaps (ROADMAP), search their tensor

@@ -59,7 +59,7 @@ class PlanParams(C.Structure):
                 ("resolution", C.c_float), ("max_rounds", C.c_int32), ("max_iterations", C.c_int32),
                 ("max_growth_rounds", C.c_int32), ("time_budget_s", C.c_double), ("max_tree_nodes", C.c_int32),
                 ("max_roadmap_nodes", C.c_int32), ("stop_at_first", C.c_int32), ("warm_cost", C.c_float),
-                ("direct", C.c_int32), ("step", C.c_float)]
+                ("direct", C.c_int32), ("step", C.c_float), ("rewire", C.c_int32)]
 
 
 class _PlanStats(C.Structure):
@@ -67,7 +67,7 @@ class _PlanStats(C.Structure):
                 ("iterations", C.c_int32), ("solutions", C.c_int32), ("first_round", C.c_int32),
                 ("edge_states", C.c_int64), ("roadmap_edge_states", C.c_int64), ("roadmap_vertices", C.c_int32),
                 ("roadmap_connected", C.c_int32), ("capacity_hit", C.c_int32), ("n_costs", C.c_int32),
-                ("costs", C.c_float * 64), ("speculative_edge_states", C.c_int64)]
+                ("costs", C.c_float * 64), ("speculative_edge_states", C.c_int64), ("rewired", C.c_int64)]
 
 
 class _PlanRequest(C.Structure):

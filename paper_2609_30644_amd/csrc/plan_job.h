@@ -105,7 +105,14 @@ class PlanJob {
   int32_t *rm_rowptr_, *rm_col_, *rm_edges_, *rm_nv_, *rm_ne_, *pair_ids_, *rm_i_, *uf_, *deg_, *tvid_[2],
       *tpar_[2], *tn_[2], *near_idx_, *vid_new_, *ins_idx_, *conn_idx_, *d_nj_, *d_qoff_,
       *cand_codes_, *pair_codes_;
-  int32_t *codes_ext_, *codes_conn_;  // [2 PC] state-count codes of the round's batch; codes_conn_ = codes_ext_ + PC
+  int32_t *codes_ext_, *codes_conn_;  // [rows] state-count codes of the round's batch; codes_conn_ = codes_ext_ + PC
+  // ao-dRRT: edge lengths to the parents [2][tree_cap], the proposals
+  // [PC][kRwSlots] (their edges are rows [2 PC, 2 PC + kRwSlots PC) of the
+  // round's batch), extension edge lengths [PC], the per-target key [tree_cap]
+  float *te_[2] = {nullptr, nullptr}, *prop_cost_ = nullptr, *prop_len_ = nullptr, *e_new_ = nullptr;
+  int32_t *prop_z_ = nullptr;
+  uint64_t *rw_key_ = nullptr;
+  int64_t batch_rows_ = 0;  // rows of a round's edge batch: 2 PC, plus kRwSlots PC with rewiring
   uint8_t *cand_valid_, *pair_valid_, *alive_, *valid_, *cvalid_;
   uint64_t *cnt_;  // [2 + R][16]: counters of the extension, connection and per-arm roadmap validations
   RoundStatus *status_;

@@ -270,6 +270,7 @@ void PlanJob::set_sizes_(const mrpop_scene *scene, const mrpop_plan_params &P) {
   cand_batch_ = 4 * P.n_roadmap;
   pair_cap_ = P.n_roadmap * rm_cap_;
   tcap_ = P.max_tree_nodes;
+  batch_rows_ = (int64_t)(2 + (P.rewire ? kRwSlots : 0)) * PC_;
   path_max_ = 16384;
   max_nj_ = 0;
   for (int r = 0; r < R_; ++r) max_nj_ = std::max(max_nj_, scene->nj[r]);
@@ -304,6 +305,14 @@ size_t PlanJob::plan_arena_(void *base) {
     ar.add(&tpar_[t], tcap_);
     ar.add(&tn_[t], 1);
   }
+  if (P_.rewire) {
+    for (int t = 0; t < 2; ++t) ar.add(&te_[t], tcap_);
+    ar.add(&prop_z_, (size_t)kRwSlots * PC);
+    ar.add(&prop_cost_, (size_t)kRwSlots * PC);
+    ar.add(&prop_len_, (size_t)kRwSlots * PC);
+    ar.add(&e_new_, PC);
+    ar.add(&rw_key_, tcap_);
+  }
   ar.add(&q_rand_, (size_t)PC * D);
   ar.add(&c_rand_, PC);
   ar.add(&near_idx_, PC);
@@ -312,14 +321,15 @@ size_t PlanJob::plan_arena_(void *base) {
   ar.add(&vid_new_, (size_t)R * PC);
   ar.add(&alive_, PC);
   // a round's edge batch: extension edges in rows [0, PC), connection edges
-  // in rows [PC, 2 PC); their bits and state-count codes alike
-  ar.add(&ea_, (size_t)2 * PC * D);
-  ar.add(&eb_, (size_t)2 * PC * D);
-  ar.add(&valid_, 2 * (size_t)PC);
+  // in rows [PC, 2 PC), with rewiring the proposal edges after them; their
+  // bits and state-count codes alike
+  ar.add(&ea_, (size_t)batch_rows_ * D);
+  ar.add(&eb_, (size_t)batch_rows_ * D);
+  ar.add(&valid_, (size_t)batch_rows_);
   ar.add(&ins_idx_, PC);
   ar.add(&budget_, PC);
   ar.add(&conn_idx_, PC);
-  ar.add(&codes_ext_, 2 * (size_t)PC);
+  ar.add(&codes_ext_, (size_t)batch_rows_);
   ar.add(&cnt_, (size_t)(2 + R) * 16);
   ar.add(&status_, 1);
   ar.add(&ss_, 1);
@@ -333,6 +343,7 @@ size_t PlanJob::plan_arena_(void *base) {
 
 size_t PlanJob::device_bytes_for(const mrpop_scene *scene, const mrpop_plan_params &params) {
   PlanJob j;
+  j.P_ = params;
   j.set_sizes_(scene, params);
   return j.plan_arena_(nullptr) + (params.direct ? 0 : (size_t)scene->n_robots * scene->blob_bytes);
 }
@@ -346,7 +357,8 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
       P.max_rounds < 1 || P.max_iterations < 1 || P.max_growth_rounds < 1 || P.n_roadmap < 1 ||
       P.max_tree_nodes < 2 || P.max_roadmap_nodes < 4 || P.max_roadmap_nodes > kUfMaxVertices ||
       !(P.delta > 0.f) || P.time_budget_s < 0 || std::isnan(P.warm_cost) || (P.direct != 0 && P.direct != 1) ||
-      (P.direct && !(P.step > 0.f && std::isfinite(P.step))))
+      (P.direct && !(P.step > 0.f && std::isfinite(P.step))) || (P.rewire != 0 && P.rewire != 1) ||
+      (P.rewire && (P.direct || P.max_roadmap_nodes > kRwMaxRoadmap)))
     return fail_(MRPOP_E_INVALID_ARG, "plan: parameter out of range");
   R_ = scene->n_robots;
   D_ = scene->dof;
@@ -707,7 +719,7 @@ Task<mrpop_status> PlanJob::run(Exec &ex) {
   if (!pin_->valid2[1]) co_return fail_(MRPOP_E_GOAL_INVALID, "plan: goal state collides");
 
   int rnd = 0, it = 0;
-  bool overflow_no_path = false, roadmap_full = false;
+  bool overflow_no_path = false, roadmap_full = false, trees_grown = false;
   std::vector<float> hpath;
   std::vector<int32_t> hvid;
   while (it < P_.max_iterations && rnd < P_.max_rounds && !out_of_time_()) {
@@ -726,14 +738,26 @@ Task<mrpop_status> PlanJob::run(Exec &ex) {
         continue;
       }
     }
-    // fresh trees: 0 rooted at the start, 1 at the goal; a fresh search state
-    SUBMIT(Op::TreeRoot, tree_root,
-           TreeRootArgs{tq_[0], tg_[0], tvid_[0], tpar_[0], tn_[0], tcap_, qs_, D, R, 0, ss_});
-    SUBMIT(Op::TreeRoot, tree_root,
-           TreeRootArgs{tq_[1], tg_[1], tvid_[1], tpar_[1], tn_[1], tcap_, qg_, D, R, 1, nullptr});
+    if (!P_.rewire || !trees_grown) {
+      // fresh trees: 0 rooted at the start, 1 at the goal; a fresh search state
+      SUBMIT(Op::TreeRoot, tree_root,
+             TreeRootArgs{tq_[0], tg_[0], tvid_[0], tpar_[0], tn_[0], te_[0], tcap_, qs_, D, R, 0, ss_});
+      SUBMIT(Op::TreeRoot, tree_root,
+             TreeRootArgs{tq_[1], tg_[1], tvid_[1], tpar_[1], tn_[1], te_[1], tcap_, qg_, D, R, 1, nullptr});
+      trees_grown = true;
+    } else {  // ao-dRRT keeps its trees: the search goes on from them
+      SUBMIT(Op::Fill, fill, FillArgs{(uint32_t *)&ss_->stop, 0u, 1});
+    }
     const TreePair trees{{tq_[0], tq_[1]}, {tg_[0], tg_[1]}, {tvid_[0], tvid_[1]}, {tpar_[0], tpar_[1]},
-                         {tn_[0], tn_[1]}};
-    bool solved = false;
+                         {tn_[0], tn_[1]}, {te_[0], te_[1]}};
+    const RewireArgs rw{P_.rewire, prop_z_, prop_cost_, prop_len_,
+                        P_.rewire ? ea_ + (size_t)2 * PC * D : nullptr, P_.rewire ? eb_ + (size_t)2 * PC * D : nullptr,
+                        P_.rewire ? codes_ext_ + 2 * PC : nullptr, P_.rewire ? valid_ + 2 * PC : nullptr, e_new_,
+                        rw_key_};
+    // AO-X: cost-bounded NEAREST and extension (c_rand) once there is a path;
+    // ao-dRRT never bounds them
+    const bool bounded = !P_.rewire;
+    bool solved = false, full = false;
     while (!solved && rnd < P_.max_rounds && !out_of_time_()) {
       // kRoundsPerWait rounds queued back to back (at most the rounds left):
       // each round's back half picks the next round's tree on the device, and
@@ -746,13 +770,13 @@ Task<mrpop_status> PlanJob::run(Exec &ex) {
         const SampleNearArgs sn{SampleArgs{PC, D, cb, P_.seed, (uint64_t)(rnd + k), 0, scene_->dev.q_lo,
                                            scene_->dev.q_hi, qs_, qg_, tq_[0], tcap_, q_rand_, c_rand_},
                                 NearestArgs{tq_[0], tg_[0], 1, D, 1, tcap_, q_rand_, D,
-                                            cb < INFINITY ? c_rand_ : nullptr, PC, near_idx_}};
+                                            bounded && cb < INFINITY ? c_rand_ : nullptr, PC, near_idx_}};
         // front half: sample, nearest, extension, then the connection search
         // and edge; one validation of both halves; back half: insertion and
         // selection
         SUBMIT(Op::RoundFront, round_front,
                RoundFrontArgs{sn,
-                              ExtendArgs{PC, D, R, near_idx_, q_rand_, cb < INFINITY ? c_rand_ : nullptr, tq_[0],
+                              ExtendArgs{PC, D, R, near_idx_, q_rand_, bounded && cb < INFINITY ? c_rand_ : nullptr, tq_[0],
                                          tvid_[0], tg_[0], tcap_, rm_V_, rm_rowptr_, rm_col_, rm_cap_, col_cap_,
                                          d_nj_, d_qoff_, q_new_, vid_new_, g_new_, alive_, ea_, eb_, P_.resolution,
                                          codes_ext_, P_.direct, P_.step},
@@ -760,12 +784,13 @@ Task<mrpop_status> PlanJob::run(Exec &ex) {
                               NearestArgs{tq_[1], tg_[1], 1, D, 1, tcap_, q_new_, D, budget_, PC, conn_idx_},
                               ConnArgs{PC, D, conn_idx_, q_new_, tq_[1], tcap_, ca_, cb_, P_.resolution,
                                        codes_conn_},
-                              trees, ss_});
-        TRY(validate_(ex, scene_, ea_, eb_, 2 * (int64_t)PC, P_.resolution, valid_, cnt_, codes_ext_));
+                              trees, ss_, rw});
+        TRY(validate_(ex, scene_, ea_, eb_, batch_rows_, P_.resolution, valid_, cnt_, codes_ext_));
         SUBMIT(Op::InsertSelect, insert_select,
                InsertSelectArgs{PC, D, R, alive_, valid_, cvalid_, q_new_, g_new_, vid_new_, near_idx_, conn_idx_,
                                 trees, tcap_, ss_, ins_idx_, codes_conn_, cnt_, status_, &pin_->status[k],
-                                seq_ + (uint32_t)k + 1u});
+                                seq_ + (uint32_t)k + 1u, rw});
+        if (P_.rewire) SUBMIT(Op::Refresh, refresh, RefreshArgs{trees, status_, tcap_});
       }
       {
         const hipError_t e_ = co_await SyncPoint{ex, &pin_->status[K - 1].seq, seq_ + (uint32_t)K};
@@ -776,8 +801,9 @@ Task<mrpop_status> PlanJob::run(Exec &ex) {
       for (int k = 0; k < K && !stopped; ++k) {
         const RoundStatus rsx = pin_->status[k];
         if (rsx.skipped) break;
-        st_.edge_states += rsx.states_ext + rsx.states_conn;
+        st_.edge_states += rsx.states_ext + rsx.states_conn + rsx.states_rw;
         st_.speculative_edge_states += rsx.states_spec;
+        st_.rewired += rsx.rewired;
         if (rsx.overflow) {
           st_.capacity_hit = 1;
           overflow = true;
@@ -835,6 +861,7 @@ Task<mrpop_status> PlanJob::run(Exec &ex) {
       }
       if (overflow && !solved) {
         overflow_no_path = best_path_.empty();
+        full = true;
         break;
       }
       if (stopped && !solved) {  // a connection no cheaper in double precision: the search goes on
@@ -849,6 +876,7 @@ Task<mrpop_status> PlanJob::run(Exec &ex) {
     // checked above): the next iteration grows the roadmaps and starts afresh
     ++it;
     if (P_.stop_at_first && solved) break;
+    if (full && P_.rewire) break;  // its trees persist, and they are full
   }
   SYNC();  // a failure of queued work is reported here at the latest
   synced_ = true;
@@ -895,6 +923,7 @@ void mrpop_plan_params_default(mrpop_plan_params *p) {
   p->max_tree_nodes = 65536;
   p->max_roadmap_nodes = 8192;
   p->stop_at_first = 0;
+  p->rewire = 0;
   p->warm_cost = INFINITY;
 }
 

@@ -81,6 +81,25 @@ struct TreePair {
   int32_t *vid[2];   // [n_robots][tree_cap]
   int32_t *parent[2];
   int32_t *n[2];     // vertex count (a copy of the search state's)
+  float *e[2];       // [tree_cap] length of the edge to the parent (ao-dRRT), or null
+};
+
+// ao-dRRT (the rewiring baseline of the paper's experiments): per candidate,
+// the cheapest parent among the extended tree's tensor-product neighbours of
+// q_new, and up to kRwSlots rewiring proposals (tree vertices whose cost
+// drops through q_new, largest drop first, ties to the lower index).
+constexpr int kRwSlots = 4;
+constexpr int kRwMaxRoadmap = 8192;  // roadmap vertices per arm (LDS bitmap of a candidate's neighbours)
+struct RewireArgs {
+  int on;                  // 0: AO-X rounds; the fields below are not read
+  int32_t *prop_z;         // [n][kRwSlots] proposal target in the extended tree, -1: none
+  float *prop_cost;        // [n][kRwSlots] its cost through q_new
+  float *prop_len;         // [n][kRwSlots] |q_new - q_z|
+  float *edge_a, *edge_b;  // [n * kRwSlots][dim] proposal edges q_new -> q_z (null edges when unused)
+  int32_t *n_codes;        // [n * kRwSlots] their state-count codes (0: unused slot)
+  const uint8_t *pvalid;   // [n * kRwSlots] their validity (back half)
+  float *e_new;            // [n] length of the extension edge (parent -> q_new)
+  uint64_t *key;           // [tree_cap] scratch: the winning proposal per target (back half)
 };
 
 struct RoundStatus {
@@ -92,6 +111,9 @@ struct RoundStatus {
   uint32_t seq;  // in the host copy: stored last, with a system-scope release (the round's number)
   int64_t states_ext, states_conn;
   int64_t states_spec;  // states of connection edges checked for candidates that were not inserted
+  int64_t states_rw;    // states of rewiring edges (ao-dRRT)
+  int32_t rewired;      // tree vertices that took a new parent (ao-dRRT)
+  int32_t n_after;      // vertices of the extended tree after the round
 };
 
 struct ConnArgs {
@@ -132,6 +154,11 @@ struct RoundFrontArgs {
   // are replaced); when the search has stopped it writes edges with no states.
   TreePair t;
   const SearchState *ss;
+  // ao-dRRT: no budget in NEAREST and the extension (c_rand unused); the
+  // extension edge starts at the cheapest neighbouring parent (e.near_idx and
+  // e.g_new are replaced by it); proposals go to rw.  Proposal edges are rows
+  // [2n, 2n + kRwSlots n) of the round's batch.
+  RewireArgs rw;
 };
 
 // The back half, one workgroup: the survivors (alive, extension edge free)
@@ -154,6 +181,20 @@ struct InsertSelectArgs {
   RoundStatus *status;
   RoundStatus *status_out;    // or null: receives the finished record (e.g. pinned host memory)
   uint32_t seq;
+  // ao-dRRT: after insertion and selection, the proposals of inserted
+  // candidates whose edge is free are applied when cheaper than the target's
+  // cost, the cheapest per target (ties: the earliest in candidate and slot
+  // order), which is the result of applying them one by one in that order.
+  RewireArgs rw;
+};
+
+// ao-dRRT, after the back half: when the round rewired any vertex, every
+// vertex's cost is recomputed as the sum of the edge lengths along its parent
+// chain (one thread per vertex).
+struct RefreshArgs {
+  TreePair t;
+  const RoundStatus *status;  // the round's record (tree, vertex count, rewired count)
+  int tree_cap;
 };
 
 struct PathArgs {
@@ -170,6 +211,7 @@ struct PathArgs {
 struct TreeRootArgs {
   float *tree_q, *tree_g;
   int32_t *tree_vid, *tree_parent, *tree_n;
+  float *tree_e;  // or null
   int tree_cap;
   const float *q;
   int dim, n_robots, vid;
@@ -265,9 +307,9 @@ uint64_t roadmap_key(uint64_t seed, uint64_t stream_a, uint64_t stream_b);
 // needs, records that need fewer leave early).
 enum class Op : uint8_t {
   Sample, Nearest, Path, TreeRoot, RmSample, RmAccept, RmPairs, RmBfs, RmUnion, Fill, Copy, RoundFront,
-  InsertSelect, Validate
+  InsertSelect, Refresh, Validate
 };
-constexpr int kNumOps = 14;
+constexpr int kNumOps = 15;
 constexpr int kUfMaxVertices = 32768;  // roadmap vertices per arm (union-find in LDS)
 
 // Blocks one record needs (0: nothing to do).
@@ -310,6 +352,7 @@ struct Cmd {
     CopyArgs copy;
     RoundFrontArgs round_front;
     InsertSelectArgs insert_select;
+    RefreshArgs refresh;
     ValidateReq val;
   };
   const void *args() const { return &sample; }

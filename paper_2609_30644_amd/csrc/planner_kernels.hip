@@ -513,6 +513,216 @@ __device__ __forceinline__ void sample_near_body(const SampleNearArgs &a, int bx
   nearest_body(a.q, bx);
 }
 
+// ---------------------------------------------------------------------------
+// ao-dRRT: the cheapest parent and the rewiring proposals of a candidate
+// ---------------------------------------------------------------------------
+
+// Block-wide (256 threads) minimum of (cost, index), ties to the lower index.
+struct CostIdx {
+  float c;
+  int32_t i;
+};
+
+__device__ __forceinline__ bool cheaper(const CostIdx &a, const CostIdx &b) {
+  if (a.i < 0) return false;
+  if (b.i < 0) return true;
+  return a.c < b.c || (a.c == b.c && a.i < b.i);
+}
+
+__device__ __forceinline__ CostIdx block_min(CostIdx v, CostIdx *s_red) {
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    CostIdx o{__shfl_xor(v.c, d, kWave), __shfl_xor(v.i, d, kWave)};
+    if (cheaper(o, v)) v = o;
+  }
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  __syncthreads();  // s_red may still be read from a previous call
+  if ((threadIdx.x & (kWave - 1)) == 0) s_red[w] = v;
+  __syncthreads();
+  CostIdx b = s_red[0];
+  for (int k = 1; k < nw; ++k)
+    if (cheaper(s_red[k], b)) b = s_red[k];
+  return b;
+}
+
+// Whether tree vertex z of the extended tree is a tensor-product neighbour
+// of the candidate's composite vertex (every arm stays or moves along a
+// roadmap edge, and not all stay): bm holds, per arm, the candidate's vertex
+// and its roadmap neighbours as bits.
+__device__ __forceinline__ bool tp_neighbour(const uint32_t *bm, const int32_t *vn, const int32_t *tree_vid,
+                                             int tree_cap, int R, int rm_cap, int z) {
+  bool same = true;
+  for (int r = 0; r < R; ++r) {
+    const int32_t v = tree_vid[(int64_t)r * tree_cap + z];
+    if ((unsigned)v >= (unsigned)rm_cap) return false;
+    if (!((bm[r * (kRwMaxRoadmap / 32) + (v >> 5)] >> (v & 31)) & 1u)) return false;
+    same = same && v == vn[r];
+  }
+  return !same;
+}
+
+// After the extension (e: the extended tree's fields already chosen), for a
+// live candidate i: its parent becomes the tree vertex of least
+// g_z + |q_new - q_z| among q_new's tensor-product neighbours in the tree
+// (ties: the lower index; q_near is one of them), with g_new, the extension
+// edge (parent -> q_new) and its state count replaced; then the tree
+// vertices z (other than the parent) with g_new + |q_new - q_z| < g_z become
+// proposals, the kRwSlots of largest drop g_z - cost (ties: lower index), each
+// with its edge q_new -> q_z for the round's validation.  A dead candidate
+// gets no proposals.  Every thread of the workgroup takes part.
+__device__ void rewire_front(const ExtendArgs &e, const RewireArgs &rw, int n_tree, int i) {
+  __shared__ uint32_t bm[MRPOP_MAX_ROBOTS * (kRwMaxRoadmap / 32)];
+  __shared__ int32_t vn[MRPOP_MAX_ROBOTS];
+  __shared__ float qn[kMaxDof];
+  __shared__ CostIdx s_red[256 / kWave];
+  const int D = e.dim, R = e.n_robots, cap = e.tree_cap, words = kRwMaxRoadmap / 32;
+  const bool live = e.alive[i] != 0;  // the same in every thread (written before the caller's barrier)
+  int n_prop = 0;
+  __shared__ int32_t s_pz[kRwSlots];
+  __shared__ float s_pc[kRwSlots], s_pl[kRwSlots];
+  if (live) {
+    for (int r = threadIdx.x; r < R; r += blockDim.x) vn[r] = e.vid_new[(int64_t)r * e.n + i];
+    for (int j = threadIdx.x; j < D; j += blockDim.x) qn[j] = e.q_new[(int64_t)i * D + j];
+    for (int k = threadIdx.x; k < R * words; k += blockDim.x) bm[k] = 0u;
+    __syncthreads();
+    for (int r = 0; r < R; ++r) {
+      const int v = vn[r];
+      const int32_t *rp = e.rm_rowptr + (int64_t)r * (e.rm_cap + 1);
+      const int32_t *col = e.rm_col + (int64_t)r * e.rm_col_cap;
+      const int e0 = rp[v], e1 = min(rp[v + 1], e.rm_col_cap);
+      for (int k = e0 + (int)threadIdx.x; k < e1; k += blockDim.x) {
+        const int u = col[k];
+        if ((unsigned)u < (unsigned)e.rm_cap) atomicOr(&bm[r * words + (u >> 5)], 1u << (u & 31));
+      }
+      if (threadIdx.x == 0) atomicOr(&bm[r * words + (v >> 5)], 1u << (v & 31));
+    }
+    __syncthreads();
+    // 1. the cheapest neighbouring parent
+    CostIdx best{INFINITY, -1};
+    for (int z = threadIdx.x; z < n_tree; z += blockDim.x) {
+      if (!tp_neighbour(bm, vn, e.tree_vid, cap, R, e.rm_cap, z)) continue;
+      float d2 = 0.f;
+      for (int j = 0; j < D; ++j) {
+        const float t = qn[j] - e.tree_q[(int64_t)j * cap + z];
+        d2 = fmaf(t, t, d2);
+      }
+      const CostIdx c{e.tree_g[z] + sqrtf(d2), z};
+      if (cheaper(c, best)) best = c;
+    }
+    best = block_min(best, s_red);
+    // q_near is a neighbour, so a parent exists (kept as a guard)
+    const int par = best.i >= 0 ? best.i : e.near_idx[i];
+    float len = 0.f;
+    {
+      float d2 = 0.f;
+      for (int j = 0; j < D; ++j) {
+        const float t = qn[j] - e.tree_q[(int64_t)j * cap + par];
+        d2 = fmaf(t, t, d2);
+      }
+      len = sqrtf(d2);
+    }
+    const float g_new = best.i >= 0 ? best.c : e.tree_g[par] + len;
+    // the extension edge from the parent, with its state count (wave 0)
+    if (threadIdx.x < kWave) {
+      const int lane = (int)threadIdx.x;
+      float linf = 0.f;
+      bool finite = true;
+      for (int j = lane; j < D; j += kWave) {
+        const float y = e.tree_q[(int64_t)j * cap + par];
+        e.edge_a[(int64_t)i * D + j] = y;
+        e.edge_b[(int64_t)i * D + j] = qn[j];
+        finite = finite && isfinite(y) && isfinite(qn[j]);
+        linf = fmaxf(linf, fabsf(qn[j] - y));
+      }
+      for (int d = kWave / 2; d > 0; d >>= 1) linf = fmaxf(linf, __shfl_xor(linf, d, kWave));
+      const bool all_finite = __ballot(!finite) == 0ull;
+      if (lane == 0) {
+        if (e.n_codes) e.n_codes[i] = state_count_code(linf, all_finite, e.res);
+        // the round's near_idx array is the parent list of the back half
+        const_cast<int32_t *>(e.near_idx)[i] = par;
+        e.g_new[i] = g_new;
+        rw.e_new[i] = len;
+      }
+    }
+    // 2. proposals: every thread keeps its kRwSlots best (largest drop, then
+    // lower index), then the block takes the kRwSlots best of all
+    float top_d[kRwSlots], top_c[kRwSlots], top_l[kRwSlots];
+    int top_z[kRwSlots];
+#pragma unroll
+    for (int k = 0; k < kRwSlots; ++k) {
+      top_d[k] = -INFINITY;
+      top_z[k] = -1;
+      top_c[k] = top_l[k] = 0.f;
+    }
+    for (int z = threadIdx.x; z < n_tree; z += blockDim.x) {
+      if (z == par || !tp_neighbour(bm, vn, e.tree_vid, cap, R, e.rm_cap, z)) continue;
+      float d2 = 0.f;
+      for (int j = 0; j < D; ++j) {
+        const float t = qn[j] - e.tree_q[(int64_t)j * cap + z];
+        d2 = fmaf(t, t, d2);
+      }
+      const float l = sqrtf(d2), c = g_new + l, gz = e.tree_g[z];
+      if (!(c < gz)) continue;
+      float dd = gz - c, cc = c, ll = l;
+      int zz = z;
+#pragma unroll
+      for (int k = 0; k < kRwSlots; ++k) {  // insertion into the sorted list (z rises in this thread)
+        const bool take = top_z[k] < 0 || dd > top_d[k];
+        if (take) {
+          const float td = top_d[k], tc = top_c[k], tl = top_l[k];
+          const int tz = top_z[k];
+          top_d[k] = dd; top_c[k] = cc; top_l[k] = ll; top_z[k] = zz;
+          dd = td; cc = tc; ll = tl; zz = tz;
+        }
+      }
+    }
+    int head = 0;  // this thread's next unclaimed entry
+    for (int k = 0; k < kRwSlots; ++k) {
+      // the block's largest remaining drop: minimum of (-drop, index)
+      CostIdx mine{head < kRwSlots && top_z[head] >= 0 ? -top_d[head] : INFINITY,
+                   head < kRwSlots ? top_z[head] : -1};
+      const CostIdx b = block_min(mine, s_red);
+      if (b.i < 0) break;
+      if (mine.i == b.i && head < kRwSlots) {  // the owner (indices are unique)
+        s_pz[k] = top_z[head];
+        s_pc[k] = top_c[head];
+        s_pl[k] = top_l[head];
+        ++head;
+      }
+      ++n_prop;
+    }
+    __syncthreads();
+  } else if (threadIdx.x == 0) {
+    rw.e_new[i] = 0.f;
+  }
+  // proposal slots, one per wave in turn: edges q_new -> q_z (unused: a null
+  // edge with no states)
+  const float *q_new = e.q_new + (int64_t)i * D;
+  const int lane = (int)(threadIdx.x & (kWave - 1)), wv = (int)(threadIdx.x / kWave);
+  for (int k = wv; k < kRwSlots; k += (int)(blockDim.x / kWave)) {
+    const int64_t row = (int64_t)i * kRwSlots + k;
+    const int z = k < n_prop ? s_pz[k] : -1;
+    float linf = 0.f;
+    bool finite = true;
+    for (int j = lane; j < D; j += kWave) {
+      const float x = q_new[j];
+      const float y = z >= 0 ? e.tree_q[(int64_t)j * cap + z] : x;
+      rw.edge_a[row * D + j] = x;
+      rw.edge_b[row * D + j] = y;
+      finite = finite && isfinite(x) && isfinite(y);
+      linf = fmaxf(linf, fabsf(y - x));
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) linf = fmaxf(linf, __shfl_xor(linf, d, kWave));
+    const bool all_finite = __ballot(!finite) == 0ull;
+    if (lane == 0) {
+      rw.prop_z[row] = z;
+      rw.prop_cost[row] = z >= 0 ? s_pc[k] : INFINITY;
+      rw.prop_len[row] = z >= 0 ? s_pl[k] : 0.f;
+      rw.n_codes[row] = z >= 0 ? state_count_code(linf, all_finite, e.res) : 0;
+    }
+  }
+  __syncthreads();
+}
+
 // Sample and nearest vertex; the extension (wave 0); the connection budget
 // c_best - g_new; the nearest vertex of the other tree under it; the
 // connection edge (wave 0).  Each step's outputs reach the next through
@@ -532,6 +742,16 @@ __device__ __forceinline__ void round_front_body(const RoundFrontArgs &A, int bx
       const float y = A.t.q[0][(int64_t)j * A.e.tree_cap];
       ea[j] = eb[j] = ca[j] = cb[j] = y;
     }
+    if (A.rw.on)
+      for (int k = 0; k < kRwSlots; ++k) {
+        const int64_t row = (int64_t)bx * kRwSlots + k;
+        for (int j = threadIdx.x; j < D; j += blockDim.x)
+          A.rw.edge_a[row * D + j] = A.rw.edge_b[row * D + j] = A.t.q[0][(int64_t)j * A.e.tree_cap];
+        if (threadIdx.x == 0) {
+          A.rw.prop_z[row] = -1;
+          A.rw.n_codes[row] = 0;
+        }
+      }
     if (threadIdx.x == 0) {
       A.e.alive[bx] = 0;
       if (A.e.n_codes) A.e.n_codes[bx] = 0;
@@ -560,9 +780,12 @@ __device__ __forceinline__ void round_front_body(const RoundFrontArgs &A, int bx
     const int lane = (int)threadIdx.x;
     if (e.direct) steer_one(e, bx, lane);
     else extend_one(e, bx, lane);
-    // (lane 0 wrote alive and g_new)
-    if (lane == 0) A.budget[bx] = !e.alive[bx] ? -1.f : (A.c_best < INFINITY ? A.c_best - e.g_new[bx] : INFINITY);
   }
+  __syncthreads();
+  if (A.rw.on) rewire_front(e, A.rw, st.n[ta], bx);  // ends with a barrier
+  // (extend_one's lane 0, or the rewiring step, wrote alive and g_new)
+  if (threadIdx.x == 0)
+    A.budget[bx] = !e.alive[bx] ? -1.f : (A.c_best < INFINITY ? A.c_best - e.g_new[bx] : INFINITY);
   __syncthreads();
   nearest_body(q2, bx);
   __syncthreads();
@@ -588,6 +811,9 @@ __device__ __forceinline__ void publish_status(const RoundStatus &st, RoundStatu
   o->states_ext = st.states_ext;
   o->states_conn = st.states_conn;
   o->states_spec = st.states_spec;
+  o->states_rw = st.states_rw;
+  o->rewired = st.rewired;
+  o->n_after = st.n_after;
   __hip_atomic_store(&o->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -639,6 +865,7 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
       if (t >= 0) {
         tree_g[t] = a.g_new[i];
         tree_parent[t] = a.near_idx[i];
+        if (a.rw.on) a.t.e[ta][t] = a.rw.e_new[i];
       }
     }
     __syncthreads();
@@ -698,6 +925,49 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
     s_states[0][w] = used;
     s_states[1][w] = spec;
   }
+  // ao-dRRT: the proposals of inserted candidates whose edge is free, the
+  // cheapest per target (a 64-bit key: cost bits, then the proposal's place
+  // in candidate and slot order) when cheaper than the target's cost
+  __shared__ int32_t s_rewired;
+  __shared__ unsigned long long s_rw_states;
+  if (threadIdx.x == 0) {
+    s_rewired = 0;
+    s_rw_states = 0ull;
+  }
+  if (a.rw.on) {
+    float *const tree_e = a.t.e[ta];
+    const int np = a.n * kRwSlots;
+    auto usable = [&](int p) {
+      const int z = a.rw.prop_z[p];
+      return z >= 0 && z < n_before && a.rw.pvalid[p] && a.ins_idx[p / kRwSlots] >= 0;
+    };
+    for (int p = threadIdx.x; p < np; p += blockDim.x)
+      if (usable(p)) a.rw.key[a.rw.prop_z[p]] = ~0ull;
+    __syncthreads();
+    for (int p = threadIdx.x; p < np; p += blockDim.x)
+      if (usable(p))
+        atomicMin((unsigned long long *)&a.rw.key[a.rw.prop_z[p]],
+                  ((unsigned long long)__float_as_uint(a.rw.prop_cost[p]) << 32) | (unsigned)p);
+    __syncthreads();
+    int mine = 0;
+    unsigned long long rw_states = 0;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+      rw_states += (unsigned long long)max(a.rw.n_codes[p], 0);
+      if (!usable(p)) continue;
+      const int z = a.rw.prop_z[p];
+      const float c = a.rw.prop_cost[p];
+      const unsigned long long k =
+          __hip_atomic_load((unsigned long long *)&a.rw.key[z], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (k == (((unsigned long long)__float_as_uint(c) << 32) | (unsigned)p) && c < tree_g[z]) {
+        tree_parent[z] = a.ins_idx[p / kRwSlots];
+        tree_g[z] = c;
+        tree_e[z] = a.rw.prop_len[p];
+        ++mine;
+      }
+    }
+    if (mine) atomicAdd(&s_rewired, mine);
+    if (rw_states) atomicAdd(&s_rw_states, rw_states);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     float bc = s_cost[0];
@@ -726,7 +996,10 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
     const int64_t total_states = a.counters ? (int64_t)a.counters[1] : 0;
     st.states_conn = (int64_t)su;
     st.states_spec = (int64_t)ss_;
-    st.states_ext = total_states - (int64_t)su - (int64_t)ss_;
+    st.states_rw = (int64_t)s_rw_states;
+    st.states_ext = total_states - (int64_t)su - (int64_t)ss_ - st.states_rw;
+    st.rewired = s_rewired;
+    st.n_after = n_after;
     *a.status = st;
     // the next round extends the smaller tree (equal sizes: the same one);
     // a connection or a full tree ends the search
@@ -738,6 +1011,26 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
     *a.ss = nx;
     if (a.status_out) publish_status(st, a.status_out, a.seq);
   }
+}
+
+// ao-dRRT: after a round that rewired, every vertex's cost is the sum of
+// the edge lengths along its parent chain (one thread per vertex; a chain
+// has fewer steps than the tree has vertices).
+__device__ __forceinline__ void refresh_body(const RefreshArgs &a, int bx) {
+  const RoundStatus st = *a.status;
+  if (st.skipped || st.rewired <= 0) return;
+  const int n = st.n_after;
+  const int v = bx * (int)blockDim.x + (int)threadIdx.x;
+  if (v >= n) return;
+  const int32_t *parent = a.t.parent[st.a];
+  const float *e = a.t.e[st.a];
+  float acc = 0.f;
+  int u = v;
+  for (int k = 0; u > 0 && k < n; ++k) {
+    acc += e[u];
+    u = parent[u];
+  }
+  a.t.g[st.a][v] = acc;
 }
 
 // Path: root of tree A -> a_idx, then b_idx -> root of tree B (one thread).
@@ -776,6 +1069,7 @@ __device__ __forceinline__ void tree_root_body(const TreeRootArgs &A, int bx) {
   if (threadIdx.x == 0) {
     tree_g[0] = 0.f;
     tree_parent[0] = -1;
+    if (A.tree_e) A.tree_e[0] = 0.f;
     *tree_n = 1;
     if (A.ss) *A.ss = SearchState{0, {1, 1}, 0};
   }
@@ -1113,6 +1407,7 @@ MRPOP_OP_KERNELS(copy, CopyArgs, 256)
 // (a plan's round steps never form a group of independent records)
 MRPOP_OP_KERNELS_1(round_front, RoundFrontArgs, 256)
 MRPOP_OP_KERNELS(insert_select, InsertSelectArgs, 1024)
+MRPOP_OP_KERNELS(refresh, RefreshArgs, 256)
 
 static int clamp_blocks(int64_t b) { return (int)std::min<int64_t>(std::max<int64_t>(b, 0), 0x7fffffff); }
 
@@ -1137,6 +1432,7 @@ int op_blocks(Op op, const void *p) {
     case Op::Copy: return (int)std::min<int64_t>((((const CopyArgs *)p)->bytes + 255) / 256, kCopyBlocksMax);
     case Op::RoundFront: return clamp_blocks(((const RoundFrontArgs *)p)->sn.s.n);
     case Op::InsertSelect: return 1;
+    case Op::Refresh: return clamp_blocks((((const RefreshArgs *)p)->tree_cap + 255) / 256);
     case Op::Validate: return 0;
   }
   return 0;
@@ -1157,6 +1453,7 @@ size_t op_args_bytes(Op op) {
     case Op::Copy: return sizeof(CopyArgs);
     case Op::RoundFront: return sizeof(RoundFrontArgs);
     case Op::InsertSelect: return sizeof(InsertSelectArgs);
+    case Op::Refresh: return sizeof(RefreshArgs);
     case Op::Validate: return 0;
   }
   return 0;
@@ -1173,6 +1470,10 @@ static hipError_t op_check(Op op, const void *p) {
         a.sn.q.n_queries != n || a.e.n != n || a.q2.n_queries != n || a.c.n != n ||
         a.e.near_idx != a.sn.q.out_idx || a.q2.queries != a.e.q_new || a.q2.budgets != a.budget ||
         a.c.conn_idx != a.q2.out_idx || !a.e.edge_a || !a.e.edge_b)
+      return hipErrorInvalidValue;
+    if (a.rw.on && (a.e.direct || a.e.c_rand || a.sn.q.budgets || a.e.rm_cap > kRwMaxRoadmap ||
+                    a.e.n_robots > MRPOP_MAX_ROBOTS || !a.rw.prop_z || !a.rw.prop_cost || !a.rw.prop_len ||
+                    !a.rw.edge_a || !a.rw.edge_b || !a.rw.n_codes || !a.rw.e_new))
       return hipErrorInvalidValue;
   }
   return hipSuccess;
@@ -1211,6 +1512,7 @@ static hipError_t launch_group_any(Op op, const void *const *recs, int n, int gr
     MRPOP_GROUP_CASE(Fill, fill, FillArgs)
     MRPOP_GROUP_CASE(Copy, copy, CopyArgs)
     MRPOP_GROUP_CASE(InsertSelect, insert_select, InsertSelectArgs)
+    MRPOP_GROUP_CASE(Refresh, refresh, RefreshArgs)
     case Op::RoundFront:
     case Op::Validate: return hipErrorInvalidValue;
   }
@@ -1232,6 +1534,7 @@ static hipError_t launch_any(Op op, const void *p, bool batch, int count, int gr
     MRPOP_OP_CASE(Copy, copy, CopyArgs)
     MRPOP_OP_CASE(RoundFront, round_front, RoundFrontArgs)
     MRPOP_OP_CASE(InsertSelect, insert_select, InsertSelectArgs)
+    MRPOP_OP_CASE(Refresh, refresh, RefreshArgs)
     case Op::Validate: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -245,16 +245,17 @@ def test_validate_more_edges_than_one_scan_block(ctx):
     _parity(ctx, sc, qa, qb, 0.05, "c1/6000 edges")
 
 
-def test_validate_sixteen_arms(ctx):
-    """Sixteen arms: the joint sine/cosine cache no longer fits next to the
-    published centres, so the arm-pair stage rebuilds frames from the joint
-    values."""
-    m = W.panda_like(20)
+@pytest.mark.parametrize("spheres", [20, 59])
+def test_validate_sixteen_arms(ctx, spheres):
+    """Sixteen arms (the largest served queries): the joint sine/cosine cache
+    no longer fits next to the published centres, so the arm-pair stage
+    rebuilds frames from the joint values."""
+    m = W.panda_like(spheres)
     R = 16
     sc = W.Scene([m] * R, W.ring_bases(R, W.ring_radius_for_spacing(R, 1.0)),
                  np.array([[0.0, 0.0, 0.5, 0.2]], np.float32), np.zeros((0, 6), np.float32))
     qa, qb = W.edge_batch(sc, 256, 0.05, 111, 2, 24)
-    _, m_, _ = _parity(ctx, sc, qa, qb, 0.05, "16 arms")
+    _, m_, _ = _parity(ctx, sc, qa, qb, 0.05, f"16 arms x {spheres} spheres")
     assert (m_ < -BAND).any() and (m_ > BAND).any()
 
 

@@ -22,9 +22,33 @@ def ctx():
     c.close()
 
 
+def _served_instances(min_arms: int, k: int):
+    """The first k queries of the served workload with at least min_arms arms."""
+    import json
+    import os
+    from types import SimpleNamespace
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c5_served.json")))
+    out = []
+    for x in d["instances"]:
+        R = x["n_robots"]
+        if R < min_arms:
+            continue
+        sc = W.Scene([W.panda_like(59)] * R, np.array(x["bases"], np.float32).reshape(R, 12),
+                     np.array(x["env_spheres"], np.float32).reshape(-1, 4),
+                     np.array(x["env_boxes"], np.float32).reshape(-1, 6))
+        out.append(SimpleNamespace(scene=sc, q_start=np.array(x["q_start"], np.float32),
+                                   q_goal=np.array(x["q_goal"], np.float32)))
+        if len(out) == k:
+            break
+    return out
+
+
 def _queries(ctx):
+    """Twelve queries over six problems: two- and four-arm problems, the
+    eight-arm shelf, and two served queries with at least eight arms."""
     import paper_2609_30644_amd as M
-    ps = [problem("c1"), problem("c2")] + [W.make_problem(W.scene_c1(s), s, oracle.states_free) for s in (5, 6)]
+    ps = [problem("c1"), problem("c2"), problem("c3")] + _served_instances(8, 2) + \
+        [W.make_problem(W.scene_c1(5), 5, oracle.states_free)]
     scenes = [M.Scene(ctx, p.scene) for p in ps]
     return [(scenes[i % len(ps)], ps[i % len(ps)], dict(PARAMS, seed=i)) for i in range(12)]
 
@@ -33,7 +57,7 @@ def test_served_results_equal_alone(ctx):
     import paper_2609_30644_amd as M
     qs = _queries(ctx)
     srv = M.Server(ctx, max_slots=5)
-    print("[served] 12 requests, 5 slots", flush=True)
+    print(f"[served] 12 requests ({sorted(set(s.n_robots for s, _, _ in qs))} arms), 5 slots", flush=True)
     # a first wave, then the rest while the first wave runs
     tickets = [srv.submit(s, p.q_start, p.q_goal, **prm) for s, p, prm in qs[:6]]
     tickets += [srv.submit(s, p.q_start, p.q_goal, **prm) for s, p, prm in qs[6:]]

@@ -393,6 +393,41 @@ SERVE_PLAN = dict(candidates=64, n_roadmap=16, delta=3.0, resolution=0.05, max_r
                   stop_at_first=1, max_tree_nodes=8192, max_roadmap_nodes=2048, time_budget_s=2.0)
 
 
+# AO-X against the rewiring baseline on the 4-arm workload (the paper's
+# cost-vs-time comparison): the same roadmap and round settings, a wall-clock
+# budget per run, several seeds.
+AODRRT_PLAN = dict(candidates=128, n_roadmap=32, delta=3.0, max_rounds=1000000, max_iterations=1000000,
+                   max_tree_nodes=262144)
+
+
+def aox_vs_aodrrt(s, q_start, q_goal, res: float, seconds: float, seeds: int) -> dict:
+    """Incumbent cost against time for MR. POP (AO-X) and ao-dRRT (rewire=1)
+    on the 4-arm problem: per seed and mode the (time, cost) of every
+    incumbent; summaries at fixed times (median over seeds of the best cost
+    found by then) and the first-solution times."""
+    marks = [t for t in (0.05, 0.1, 0.25, 0.5, 1.0, 2.0, 5.0, 10.0, 30.0) if t <= seconds]
+    out = {"seconds": seconds, "seeds": seeds, "marks_s": marks, "params": AODRRT_PLAN}
+    for mode, rw in (("aox", 0), ("aodrrt", 1)):
+        runs = []
+        for seed in range(seeds):
+            r, hist, _ = s.plan_with_history(q_start, q_goal, max_entries=64, max_waypoints=65536, raise_on_error=False,
+                                             resolution=res, time_budget_s=seconds, rewire=rw,
+                                             **dict(AODRRT_PLAN, seed=seed))
+            curve = sorted((h.found_s, h.cost) for h in hist)
+            runs.append({"seed": seed, "status": r.status, "tts_s": r.stats["time_to_first_s"],
+                         "final_cost": r.cost if r.status == "OK" else None, "curve": curve,
+                         "rounds": r.stats["rounds"], "iterations": r.stats["iterations"],
+                         "rewired": r.stats["rewired"], "wall_s": r.stats["total_time_s"]})
+        at = {}
+        for t in marks:
+            best = [min([c for ts, c in x["curve"] if ts <= t], default=float("inf")) for x in runs]
+            at[str(t)] = float(np.median(best))
+        tts = [x["tts_s"] for x in runs if x["tts_s"] >= 0]
+        out[mode] = {"median_cost_at": at, "tts_p50_ms": float(np.median(tts)) * 1e3 if tts else None,
+                     "solved": len(tts), "runs": runs}
+    return out
+
+
 def history_leg(s, q_start, q_goal, res: float, n: int) -> dict:
     """Incumbent-history export: the same n plans (seeds 0..n-1) with and
     without mrpop_plan_with_history; entries found and written, and the time
@@ -595,6 +630,9 @@ def main():
     ap.add_argument("--c1-full", type=int, default=2, help="of those, plans run for the whole 5 s budget")
     ap.add_argument("--c3-reps", type=int, default=10, help="repetitions of each 8-arm batch (0: skip the leg)")
     ap.add_argument("--c3-plan-seconds", type=float, default=30.0, help="budget of the 8-arm plan (0: skip)")
+    ap.add_argument("--aodrrt-seconds", type=float, default=5.0,
+                    help="budget of each AO-X and ao-dRRT run of the cost-vs-time comparison (0: skip)")
+    ap.add_argument("--aodrrt-seeds", type=int, default=3)
     ap.add_argument("--oracle-planner-seeds", type=int, default=50,
                     help="two-arm problems planned by the oracle in the CPU baseline (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -703,6 +741,9 @@ def main():
     if args.replan:
         print("[bench] replanning", file=sys.stderr, flush=True)
         line["replan"] = replan_leg(ctx, res)
+    if args.aodrrt_seconds > 0 and args.aodrrt_seeds > 0:
+        print("[bench] AO-X against ao-dRRT", file=sys.stderr, flush=True)
+        line["aox_vs_aodrrt"] = aox_vs_aodrrt(s, q_start, q_goal, res, args.aodrrt_seconds, args.aodrrt_seeds)
     if plans and args.history_plans > 0:
         print("[bench] incumbent history", file=sys.stderr, flush=True)
         line["history"] = history_leg(s, q_start, q_goal, res, args.history_plans)

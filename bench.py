@@ -609,7 +609,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plan", action="store_true", help="validation batches only")
-    ap.add_argument("--batch-instances", type=int, default=64,
+    ap.add_argument("--batch-instances", type=int, default=512,
                     help="instances of the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--no-direct", dest="direct", action="store_false",
                     help="skip the direct-mode (single-arm, no roadmap) leg")

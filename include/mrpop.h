@@ -504,7 +504,8 @@ typedef struct {
  * edge validations of many scenes in one launch.  Wall-clock budgets
  * (time_budget_s) count from the start of the batch.  Returns E_INVALID_ARG
  * for a NULL context or request array; per-request failures are reported in
- * reqs[i].status.  Blocking; uses one host thread per request. */
+ * reqs[i].status.  Blocking; the instances run as coroutines on the calling
+ * thread. */
 mrpop_status mrpop_plan_batch(mrpop_ctx *ctx, mrpop_plan_request *reqs, int32_t n, mrpop_batch_stats *stats_opt);
 
 /* ------------------------------------------------------------------------ */

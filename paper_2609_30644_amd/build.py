@@ -63,5 +63,42 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     return LIB
 
 
+# The host runtime with AddressSanitizer and UndefinedBehaviorSanitizer: every
+# source, with the sanitizers on its host code only (the device code is built
+# as usual), linked with the driver tests/sanitize/host_driver.cpp into one
+# program that the GPU test suite runs.
+SAN_BUILD = os.path.join(BUILD, "host_sanitize")
+SAN_DRIVER = os.path.join(ROOT, "tests", "sanitize", "host_driver.cpp")
+SAN_EXE = os.path.join(ROOT, "tests", "sanitize", "host_driver_asan")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def _compile_sanitized(src: str) -> str:
+    obj = os.path.join(SAN_BUILD, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *COMMON, *SAN_FLAGS, "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc (sanitized) failed for {src}:\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build_host_sanitized(jobs: int = 8) -> str:
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    srcs = sources() + [SAN_DRIVER]
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(srcs)))) as ex:
+        objs = list(ex.map(_compile_sanitized, srcs))
+    tmp = SAN_EXE + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-o", tmp, *objs, "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link (sanitized) failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SAN_EXE)
+    return SAN_EXE
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    if "--sanitized" in sys.argv:
+        print(build_host_sanitized())

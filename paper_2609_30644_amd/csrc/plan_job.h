@@ -74,6 +74,14 @@ class PlanJob {
   // Submits cs as one group of independent commands, then clears it.
   mrpop_status group_(Exec &ex, std::vector<Cmd> &cs);
   Task<mrpop_status> roadmap_(Exec &ex, int it);
+  // One sampling pass of growth round g (ROADMAP): samples of the arms in
+  // `act` from stream position j0, their validation, acceptance and the pair
+  // counts of the arms in `counted`, then the counts to pinned memory.  With
+  // `speculative`, an arm whose connected flag is set on the device by then
+  // draws and accepts nothing.
+  mrpop_status rm_pass_(Exec &ex, int it, int g, int64_t j0, const std::vector<int> &act,
+                        const std::vector<int> &counted, bool speculative, const std::vector<int> &need,
+                        const std::vector<int> &n0, const std::vector<int> &need0);
   void set_sizes_(const mrpop_scene *scene, const mrpop_plan_params &P);
   size_t plan_arena_(void *base);  // assigns the arena's arrays (base may be null); returns its size
   double elapsed_() const;

@@ -501,15 +501,20 @@ mrpop_status PlanJob::validate_(Exec &ex, const mrpop_scene *sc, const float *a,
 
 // ROADMAP (Alg. 2) for outer iteration `it`.  Every arm still unconnected
 // grows in the same steps (the arms' commands of a step submitted as one
-// independent group, two host round trips per growth round): free samples, counts of candidate pairs (new vertex, any vertex
-// within delta), then the pairs themselves, their single-arm validation and
-// the union of the components they join; connectivity of start and goal is
-// read from the union-find.  The adjacency used by the extension oracle is
-// rebuilt once at the end.
-Task<mrpop_status> PlanJob::roadmap_(Exec &ex, int it) {
+// independent group): free samples, counts of candidate pairs (new vertex,
+// any vertex within delta), then the pairs themselves, their single-arm
+// validation and the union of the components they join; connectivity of
+// start and goal is read from the union-find.  A growth round takes one host
+// round trip: the next round's first sampling pass is queued behind the
+// union before the host has read which arms it connected (an arm it
+// connected draws and accepts nothing, by a flag the union sets on the
+// device), and one wait returns both.  Further passes (when a batch of
+// samples held too few free ones) take a round trip each.  The adjacency used
+// by the extension oracle is rebuilt once at the end.
+mrpop_status PlanJob::rm_pass_(Exec &ex, int it, int g, int64_t j0, const std::vector<int> &act,
+                               const std::vector<int> &counted, bool speculative, const std::vector<int> &need,
+                               const std::vector<int> &n0, const std::vector<int> &need0) {
   const int R = R_;
-  std::vector<char> conn(R, 0), grew(R, 0);
-  std::vector<int> need(R, 0), need0(R, 0), n0(R, 0), np(R, 0), off(R, 0);
   auto ri = [&](int r, int i) { return rm_i_ + (size_t)r * kRmInts + i; };
   auto cand = [&](int r) { return cand_ + (size_t)r * cand_batch_ * kRmStride; };
   auto candv = [&](int r) { return cand_valid_ + (size_t)r * cand_batch_; };
@@ -520,66 +525,97 @@ Task<mrpop_status> PlanJob::roadmap_(Exec &ex, int it) {
     grp.back().op = op;
     return grp.back();
   };
-  auto add_copy = [&](void *dst, const void *src, size_t bytes) {
-    add(Op::Copy).copy = CopyArgs{dst, src, (int64_t)bytes};
+  mrpop_status st;
+  if (!act.empty()) {
+    for (int r : act)
+      add(Op::RmSample).rm_sample = RmSampleArgs{cand(r), cand_batch_, h_nj_[r], scene_->dev.q_lo + h_qoff_[r],
+                                                 scene_->dev.q_hi + h_qoff_[r],
+                                                 roadmap_key(P_.seed, (uint64_t)it * 1024 + g, (uint64_t)r), j0,
+                                                 cand_codes_ + (size_t)r * cand_batch_,
+                                                 speculative ? ri(r, 3) : nullptr};
+    if ((st = group_(ex, grp)) != MRPOP_OK) return st;
+    for (int r : act)  // consecutive validations: one launch over the arms
+      if ((st = validate_(ex, arms_[r], cand(r), cand(r), cand_batch_, 1.0f, candv(r), cnt_ + (size_t)(2 + r) * 16,
+                          cand_codes_ + (size_t)r * cand_batch_)) != MRPOP_OK)
+        return st;
+  }
+  // acceptance (arms without samples this pass accept none), which also
+  // zeroes the pair counters of every counted arm
+  for (int r : counted) {
+    const bool sampled = need[r] > 0 && std::find(act.begin(), act.end(), r) != act.end();
+    add(Op::RmAccept).rm_accept =
+        RmAcceptArgs{cand(r), candv(r), sampled ? cand_batch_ : 0, h_nj_[r], sampled ? need[r] : 0, V(r),
+                     rm_nv_ + r, rm_cap_, ri(r, 0), uf_ + (size_t)r * rm_cap_, ri(r, 1),
+                     speculative ? ri(r, 3) : nullptr};
+  }
+  if ((st = group_(ex, grp)) != MRPOP_OK) return st;
+  for (int r : counted)
+    add(Op::RmPairs).rm_pairs = RmPairsArgs{V(r), n0[r], n0[r] + need0[r], h_nj_[r], P_.delta, ri(r, 1), 0,
+                                            nullptr, nullptr, nullptr, rm_nv_ + r, 0.f, nullptr};
+  if ((st = group_(ex, grp)) != MRPOP_OK) return st;
+  add(Op::Copy).copy = CopyArgs{pin_rm_, rm_i_, (int64_t)(sizeof(int32_t) * (size_t)R * kRmInts)};
+  add(Op::Copy).copy = CopyArgs{pin_rm_ + (size_t)R * kRmInts, rm_nv_, (int64_t)(sizeof(int32_t) * (size_t)R)};
+  return group_(ex, grp);
+}
+
+Task<mrpop_status> PlanJob::roadmap_(Exec &ex, int it) {
+  const int R = R_;
+  std::vector<char> conn(R, 0), grew(R, 0);
+  std::vector<int> need(R, 0), need0(R, 0), n0(R, 0), np(R, 0), off(R, 0);
+  auto ri = [&](int r, int i) { return rm_i_ + (size_t)r * kRmInts + i; };
+  std::vector<Cmd> grp;
+  auto add = [&](Op op) -> Cmd & {
+    grp.emplace_back();
+    grp.back().op = op;
+    return grp.back();
   };
-  for (int g = 0; g < P_.max_growth_rounds; ++g) {
-    std::vector<int> todo;
-    for (int r = 0; r < R; ++r)
-      if (!conn[r]) todo.push_back(r);
-    if (todo.empty()) break;
-    // 1. n free samples per arm, drawn in batches (first free ones in draw order)
-    for (int r : todo) {
+  // n free samples per arm and round, drawn in batches (the first free ones
+  // in draw order); the arms of the round and those that still need samples
+  auto begin_round = [&](const std::vector<int> &arms) {
+    for (int r : arms) {
       n0[r] = rm_n_[r];
       need[r] = std::min(P_.n_roadmap, rm_cap_ - n0[r]);
       if (need[r] <= 0) st_.capacity_hit = 1;
       need0[r] = std::max(need[r], 0);
     }
-    // 2. with them, the count of candidate pairs per arm (then the pair buffer
-    // is shared in arm order).  Every pass counts the pairs of the arms whose
-    // vertices it changed (all arms in the first), bounded by the vertex count
-    // on the device, so counts and samples share one host round trip.
-    for (int64_t j0 = 0;; j0 += cand_batch_) {
-      std::vector<int> act, counted;
-      for (int r : todo)
-        if (need[r] > 0) act.push_back(r);
-      if (j0 == 0) counted = todo;
-      else counted = act;
-      if (counted.empty()) break;
-      if (!act.empty()) {
-        for (int r : act)
-          add(Op::RmSample).rm_sample = RmSampleArgs{cand(r), cand_batch_, h_nj_[r], scene_->dev.q_lo + h_qoff_[r],
-                                                     scene_->dev.q_hi + h_qoff_[r],
-                                                     roadmap_key(P_.seed, (uint64_t)it * 1024 + g, (uint64_t)r), j0,
-                                                     cand_codes_ + (size_t)r * cand_batch_};
-        TRY(group_(ex, grp));
-        for (int r : act)  // consecutive validations: one launch over the arms
-          TRY(validate_(ex, arms_[r], cand(r), cand(r), cand_batch_, 1.0f, candv(r), cnt_ + (size_t)(2 + r) * 16,
-                        cand_codes_ + (size_t)r * cand_batch_));
-      }
-      // acceptance (arms without samples this pass accept none), which also
-      // zeroes the pair counters of every counted arm
-      for (int r : counted) {
-        const bool sampled = need[r] > 0;
-        add(Op::RmAccept).rm_accept =
-            RmAcceptArgs{cand(r), candv(r), sampled ? cand_batch_ : 0, h_nj_[r], sampled ? need[r] : 0, V(r),
-                         rm_nv_ + r, rm_cap_, ri(r, 0), uf_ + (size_t)r * rm_cap_, ri(r, 1)};
-      }
-      TRY(group_(ex, grp));
-      for (int r : counted)
-        add(Op::RmPairs).rm_pairs = RmPairsArgs{V(r), n0[r], n0[r] + need0[r], h_nj_[r], P_.delta, ri(r, 1), 0,
-                                                nullptr, nullptr, nullptr, rm_nv_ + r, 0.f, nullptr};
-      TRY(group_(ex, grp));
-      add_copy(pin_rm_, rm_i_, sizeof(int32_t) * (size_t)R * kRmInts);
-      add_copy(pin_rm_ + (size_t)R * kRmInts, rm_nv_, sizeof(int32_t) * (size_t)R);
-      TRY(group_(ex, grp));
-      SYNC();
-      for (int r : act) {
-        need[r] -= pin_rm_[(size_t)r * kRmInts];
-        rm_n_[r] = pin_rm_[(size_t)R * kRmInts + r];
-      }
-      if (act.empty() || j0 > (int64_t)cand_batch_ * 64) break;  // (nearly) no free space left
+  };
+  auto needing = [&](const std::vector<int> &arms) {
+    std::vector<int> a;
+    for (int r : arms)
+      if (need[r] > 0) a.push_back(r);
+    return a;
+  };
+  auto take = [&](const std::vector<int> &arms) {  // a pass's accepted samples, from pinned memory
+    for (int r : arms) {
+      need[r] -= pin_rm_[(size_t)r * kRmInts];
+      rm_n_[r] = pin_rm_[(size_t)R * kRmInts + r];
     }
+  };
+  if (P_.max_growth_rounds < 1) co_return MRPOP_OK;
+  std::vector<int> todo;  // the arms that grow in this round
+  for (int r = 0; r < R; ++r) todo.push_back(r);
+  begin_round(todo);
+  std::vector<int> act0 = needing(todo);  // the arms the round's first pass sampled
+  TRY(rm_pass_(ex, it, 0, 0, act0, todo, false, need, n0, need0));
+  SYNC();
+  for (int g = 0;; ++g) {
+    // the round's first pass (arms connected since took nothing), then more
+    // passes while an arm lacks free samples (pair counts of the arms whose
+    // vertices a pass changed, bounded by the vertex count on the device)
+    take(act0);
+    if (!act0.empty()) {
+      for (int64_t j0 = cand_batch_;; j0 += cand_batch_) {
+        const std::vector<int> act = needing(todo);
+        if (act.empty()) break;
+        TRY(rm_pass_(ex, it, g, j0, act, act, false, need, n0, need0));
+        SYNC();
+        take(act);
+        if (j0 > (int64_t)cand_batch_ * 64) break;  // (nearly) no free space left
+      }
+    }
+    // the pairs (the pair buffer shared in arm order), their validation, new
+    // edges and the union of components; the union also writes each arm's
+    // connectivity and validation counters to pinned memory
     int base = 0;
     for (int r : todo) {
       const int want = pin_rm_[(size_t)r * kRmInts + 1];
@@ -588,20 +624,17 @@ Task<mrpop_status> PlanJob::roadmap_(Exec &ex, int it) {
       off[r] = base;
       base += np[r];
     }
-    // 3. the pairs, their validation, new edges, union of components
     for (int r : todo)
       if (np[r] > 0)
         add(Op::RmPairs).rm_pairs =
-            RmPairsArgs{V(r), n0[r], rm_n_[r], h_nj_[r], P_.delta, ri(r, 2), np[r], pair_ids_ + 2 * (size_t)off[r],
-                        pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r], nullptr,
-                        P_.resolution, pair_codes_ + off[r]};
+            RmPairsArgs{rm_V_ + (size_t)r * rm_cap_ * kRmStride, n0[r], rm_n_[r], h_nj_[r], P_.delta, ri(r, 2), np[r],
+                        pair_ids_ + 2 * (size_t)off[r], pair_qa_ + (size_t)off[r] * h_nj_[r],
+                        pair_qb_ + (size_t)off[r] * h_nj_[r], nullptr, P_.resolution, pair_codes_ + off[r]};
     TRY(group_(ex, grp));
     for (int r : todo)
       if (np[r] > 0)
         TRY(validate_(ex, arms_[r], pair_qa_ + (size_t)off[r] * h_nj_[r], pair_qb_ + (size_t)off[r] * h_nj_[r],
                       np[r], P_.resolution, pair_valid_ + off[r], cnt_ + (size_t)(2 + r) * 16, pair_codes_ + off[r]));
-    // new edges and the union of components in one launch, which also writes
-    // each arm's connectivity and validation counters to pinned memory
     for (int r : todo) {
       if (np[r] > 0) grew[r] = 1;
       add(Op::RmUnion).rm_union =
@@ -612,6 +645,13 @@ Task<mrpop_status> PlanJob::roadmap_(Exec &ex, int it) {
                       pin_cnt_ + (size_t)r * 16};
     }
     TRY(group_(ex, grp));
+    // the next round's first pass, queued behind the union
+    const bool more = g + 1 < P_.max_growth_rounds && !out_of_time_();
+    if (more) {
+      begin_round(todo);
+      act0 = needing(todo);
+      TRY(rm_pass_(ex, it, g + 1, 0, act0, todo, true, need, n0, need0));
+    }
     SYNC();
     bool all = true;
     for (int r : todo) {
@@ -619,8 +659,14 @@ Task<mrpop_status> PlanJob::roadmap_(Exec &ex, int it) {
       conn[r] = (char)pin_rm_[(size_t)r * kRmInts + 3];
     }
     for (int r = 0; r < R; ++r) all = all && conn[r];
-    if (all) break;
-    if (out_of_time_()) break;
+    if (all || !more) break;
+    std::vector<int> next, next_act;
+    for (int r : todo)
+      if (!conn[r]) next.push_back(r);
+    for (int r : act0)
+      if (!conn[r]) next_act.push_back(r);
+    todo.swap(next);
+    act0.swap(next_act);
   }
   // adjacency (CSR) of the arms that gained edges
   for (int r = 0; r < R; ++r)

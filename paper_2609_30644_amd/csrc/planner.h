@@ -225,6 +225,7 @@ struct RmSampleArgs {
   uint64_t key;
   int64_t j0;
   int32_t *codes;  // or null: [n] state-count code of each sample as a zero-length edge
+  const int32_t *skip;  // or null: when *skip != 0 nothing is drawn and every code is 0 (no states)
 };
 
 struct RmAcceptArgs {
@@ -237,6 +238,7 @@ struct RmAcceptArgs {
   int32_t *taken;
   int32_t *parent;  // union-find parent of every roadmap vertex
   int32_t *zero2;   // or null: two counters set to zero first (the arm's pair counts)
+  const int32_t *skip;  // or null: when *skip != 0 nothing is accepted (taken = 0)
 };
 
 struct RmPairsArgs {

@@ -1090,6 +1090,10 @@ __device__ __forceinline__ void rm_sample_body(const RmSampleArgs &A, int bx) {
 
   const int b = bx * blockDim.x + threadIdx.x;
   if (b >= n) return;
+  if (A.skip && *A.skip) {  // an arm already connected: no samples, no states
+    if (A.codes) A.codes[b] = 0;
+    return;
+  }
   bool finite = true;
   for (int d = 0; d < nj; ++d) {
     const float x = fmaf(uniform01(key, (uint64_t)(j0 + b) * 8 + d), hi[d] - lo[d], lo[d]);
@@ -1113,10 +1117,11 @@ __device__ __forceinline__ void rm_accept_body(const RmAcceptArgs &A, int bx) {
   __shared__ int32_t base;
   if (threadIdx.x == 0) base = 0;
   if (threadIdx.x < 2 && A.zero2) A.zero2[threadIdx.x] = 0;
+  const int n_eff = (A.skip && *A.skip) ? 0 : n;  // an arm already connected accepts nothing
   __syncthreads();
-  for (int i0 = 0; i0 < n; i0 += blockDim.x) {
+  for (int i0 = 0; i0 < n_eff; i0 += blockDim.x) {
     const int i = i0 + threadIdx.x;
-    const int ok = (i < n && valid[i]) ? 1 : 0;
+    const int ok = (i < n_eff && valid[i]) ? 1 : 0;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const uint64_t bal = __ballot(ok);
     const int before = __popcll(bal & ((1ull << lane) - 1ull));

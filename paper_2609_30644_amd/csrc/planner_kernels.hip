@@ -171,25 +171,48 @@ __device__ __forceinline__ Best nearest_scan(const NearestArgs &a, const float *
 #pragma unroll
     for (int j = 0; j < DC; ++j) q[j] = sq[j];
   }
-  for (int64_t v = threadIdx.x; v < a.n; v += blockDim.x) {
-    float d2 = 0.f;
-    const float *p = a.V + v * a.v_stride;
-    if constexpr (DC > 0) {
-#pragma unroll
-      for (int j = 0; j < DC; ++j) {
-        const float t = q[j] - p[j * a.d_stride];
-        d2 = fmaf(t, t, d2);
-      }
-    } else {
-      for (int j = 0; j < a.dim; ++j) {
-        const float t = sq[j] - p[j * a.d_stride];
-        d2 = fmaf(t, t, d2);
-      }
-    }
+  auto consider = [&](int64_t v, float d2) {
     const float g = a.g ? a.g[v] : 0.f;
-    if (!(g + sqrtf(d2) < c)) continue;
+    if (!(g + sqrtf(d2) < c)) return;
     const Best cand{d2, g, (int32_t)v};
     if (better(cand, best)) best = cand;
+  };
+  if constexpr (DC > 0 && DC <= 28) {
+    // two vertices per step, both loaded before either is reduced, so that
+    // a thread waits on memory once per pair (same per-vertex arithmetic and
+    // the same vertex order; larger dimensions keep one, for registers)
+    for (int64_t v = threadIdx.x; v < a.n; v += 2 * (int64_t)blockDim.x) {
+      const int64_t w = v + blockDim.x;
+      const bool has_w = w < a.n;
+      const float *p = a.V + v * a.v_stride, *pw = a.V + (has_w ? w : v) * a.v_stride;
+      float d2 = 0.f, d2w = 0.f;
+#pragma unroll
+      for (int j = 0; j < DC; ++j) {
+        const float t = q[j] - p[j * a.d_stride], tw = q[j] - pw[j * a.d_stride];
+        d2 = fmaf(t, t, d2);
+        d2w = fmaf(tw, tw, d2w);
+      }
+      consider(v, d2);
+      if (has_w) consider(w, d2w);
+    }
+  } else {
+    for (int64_t v = threadIdx.x; v < a.n; v += blockDim.x) {
+      float d2 = 0.f;
+      const float *p = a.V + v * a.v_stride;
+      if constexpr (DC > 0) {
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+          const float t = q[j] - p[j * a.d_stride];
+          d2 = fmaf(t, t, d2);
+        }
+      } else {
+        for (int j = 0; j < a.dim; ++j) {
+          const float t = sq[j] - p[j * a.d_stride];
+          d2 = fmaf(t, t, d2);
+        }
+      }
+      consider(v, d2);
+    }
   }
   return best;
 }
@@ -517,6 +540,13 @@ __device__ __forceinline__ void sample_near_body(const SampleNearArgs &a, int bx
 // ao-dRRT: the cheapest parent and the rewiring proposals of a candidate
 // ---------------------------------------------------------------------------
 
+// Element i (0 or 1) of a two-entry array, by a select: a dynamic index into
+// a kernel argument or a local struct would place it in scratch memory.
+template <class T>
+__device__ __forceinline__ T pick(const T (&x)[2], int i) {
+  return i ? x[1] : x[0];
+}
+
 // Block-wide (256 threads) minimum of (cost, index), ties to the lower index.
 struct CostIdx {
   float c;
@@ -677,15 +707,26 @@ __device__ void rewire_front(const ExtendArgs &e, const RewireArgs &rw, int n_tr
     }
     int head = 0;  // this thread's next unclaimed entry
     for (int k = 0; k < kRwSlots; ++k) {
+      // this thread's entry `head` (selected without a dynamic index, which
+      // would put the lists in scratch memory)
+      float hd = 0.f, hc = 0.f, hl = 0.f;
+      int hz = -1;
+#pragma unroll
+      for (int u = 0; u < kRwSlots; ++u)
+        if (u == head) {
+          hd = top_d[u];
+          hc = top_c[u];
+          hl = top_l[u];
+          hz = top_z[u];
+        }
       // the block's largest remaining drop: minimum of (-drop, index)
-      CostIdx mine{head < kRwSlots && top_z[head] >= 0 ? -top_d[head] : INFINITY,
-                   head < kRwSlots ? top_z[head] : -1};
+      const CostIdx mine{hz >= 0 ? -hd : INFINITY, hz};
       const CostIdx b = block_min(mine, s_red);
       if (b.i < 0) break;
-      if (mine.i == b.i && head < kRwSlots) {  // the owner (indices are unique)
-        s_pz[k] = top_z[head];
-        s_pc[k] = top_c[head];
-        s_pl[k] = top_l[head];
+      if (hz >= 0 && hz == b.i) {  // the owner (indices are unique)
+        s_pz[k] = hz;
+        s_pc[k] = hc;
+        s_pl[k] = hl;
         ++head;
       }
       ++n_prop;
@@ -760,20 +801,20 @@ __device__ __forceinline__ void round_front_body(const RoundFrontArgs &A, int bx
     return;
   }
   SampleNearArgs sn = A.sn;
-  sn.s.root = A.t.q[ta];
-  sn.q.V = A.t.q[ta];
-  sn.q.g = A.t.g[ta];
-  sn.q.n = st.n[ta];
+  sn.s.root = pick(A.t.q, ta);
+  sn.q.V = pick(A.t.q, ta);
+  sn.q.g = pick(A.t.g, ta);
+  sn.q.n = pick(st.n, ta);
   ExtendArgs e = A.e;
-  e.tree_q = A.t.q[ta];
-  e.tree_vid = A.t.vid[ta];
-  e.tree_g = A.t.g[ta];
+  e.tree_q = pick(A.t.q, ta);
+  e.tree_vid = pick(A.t.vid, ta);
+  e.tree_g = pick(A.t.g, ta);
   NearestArgs q2 = A.q2;
-  q2.V = A.t.q[tb];
-  q2.g = A.t.g[tb];
-  q2.n = st.n[tb];
+  q2.V = pick(A.t.q, tb);
+  q2.g = pick(A.t.g, tb);
+  q2.n = pick(st.n, tb);
   ConnArgs c = A.c;
-  c.other_q = A.t.q[tb];
+  c.other_q = pick(A.t.q, tb);
   sample_near_body(sn, bx);
   __syncthreads();
   if (threadIdx.x < kWave) {
@@ -782,7 +823,7 @@ __device__ __forceinline__ void round_front_body(const RoundFrontArgs &A, int bx
     else extend_one(e, bx, lane);
   }
   __syncthreads();
-  if (A.rw.on) rewire_front(e, A.rw, st.n[ta], bx);  // ends with a barrier
+  if (A.rw.on) rewire_front(e, A.rw, pick(st.n, ta), bx);  // ends with a barrier
   // (extend_one's lane 0, or the rewiring step, wrote alive and g_new)
   if (threadIdx.x == 0)
     A.budget[bx] = !e.alive[bx] ? -1.f : (A.c_best < INFINITY ? A.c_best - e.g_new[bx] : INFINITY);
@@ -833,10 +874,10 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
     return;
   }
   const int ta = ss.a, tb = 1 - ss.a;
-  float *const tree_q = a.t.q[ta], *const tree_g = a.t.g[ta];
-  int32_t *const tree_vid = a.t.vid[ta], *const tree_parent = a.t.parent[ta];
-  const float *const other_q = a.t.q[tb], *const other_g = a.t.g[tb];
-  const int n_before = ss.n[ta];
+  float *const tree_q = pick(a.t.q, ta), *const tree_g = pick(a.t.g, ta);
+  int32_t *const tree_vid = pick(a.t.vid, ta), *const tree_parent = pick(a.t.parent, ta);
+  const float *const other_q = pick(a.t.q, tb), *const other_g = pick(a.t.g, tb);
+  const int n_before = pick(ss.n, ta);
   constexpr int kMaxW = 1024 / kWave;
   __shared__ int32_t s_wsum[kMaxW];
   __shared__ int32_t s_base;
@@ -865,7 +906,7 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
       if (t >= 0) {
         tree_g[t] = a.g_new[i];
         tree_parent[t] = a.near_idx[i];
-        if (a.rw.on) a.t.e[ta][t] = a.rw.e_new[i];
+        if (a.rw.on) pick(a.t.e, ta)[t] = a.rw.e_new[i];
       }
     }
     __syncthreads();
@@ -877,15 +918,45 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
   const int inserted = all < room ? all : room;
   // rows of the inserted candidates (their tree indices written above,
   // visible behind the barrier)
-  for (int64_t k = threadIdx.x; k < (int64_t)a.n * a.dim; k += blockDim.x) {
-    const int i = (int)(k / a.dim), j = (int)(k - (int64_t)i * a.dim);
-    const int32_t t = a.ins_idx[i];
-    if (t >= 0) tree_q[(int64_t)j * a.tree_cap + t] = a.q_new[k];
+  // kCopyUnroll elements per thread and step, all loaded before any store
+  // (the stores could alias the loads for the compiler, which would
+  // otherwise wait on each load in turn)
+  constexpr int kCopyUnroll = 8;
+  const int64_t n_rows = (int64_t)a.n * a.dim, n_vids = (int64_t)a.n * a.n_robots;
+  for (int64_t k0 = threadIdx.x; k0 < n_rows; k0 += kCopyUnroll * (int64_t)blockDim.x) {
+    float v[kCopyUnroll];
+    int32_t t[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const int64_t k = k0 + (int64_t)u * blockDim.x;
+      t[u] = -1;
+      if (k < n_rows) {
+        t[u] = a.ins_idx[k / a.dim];
+        v[u] = a.q_new[k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const int64_t k = k0 + (int64_t)u * blockDim.x;
+      if (t[u] >= 0) tree_q[(k - k / a.dim * a.dim) * a.tree_cap + t[u]] = v[u];
+    }
   }
-  for (int64_t k = threadIdx.x; k < (int64_t)a.n * a.n_robots; k += blockDim.x) {
-    const int r = (int)(k / a.n), i = (int)(k - (int64_t)r * a.n);
-    const int32_t t = a.ins_idx[i];
-    if (t >= 0) tree_vid[(int64_t)r * a.tree_cap + t] = a.vid_new[k];
+  for (int64_t k0 = threadIdx.x; k0 < n_vids; k0 += kCopyUnroll * (int64_t)blockDim.x) {
+    int32_t v[kCopyUnroll], t[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const int64_t k = k0 + (int64_t)u * blockDim.x;
+      t[u] = -1;
+      if (k < n_vids) {
+        t[u] = a.ins_idx[k % a.n];
+        v[u] = a.vid_new[k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const int64_t k = k0 + (int64_t)u * blockDim.x;
+      if (t[u] >= 0) tree_vid[(k / a.n) * a.tree_cap + t[u]] = v[u];
+    }
   }
   // cheapest free connection of an inserted candidate; connection states
   float best = INFINITY;
@@ -935,7 +1006,7 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
     s_rw_states = 0ull;
   }
   if (a.rw.on) {
-    float *const tree_e = a.t.e[ta];
+    float *const tree_e = pick(a.t.e, ta);
     const int np = a.n * kRwSlots;
     auto usable = [&](int p) {
       const int z = a.rw.prop_z[p];
@@ -982,7 +1053,7 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
       ss_ += s_states[1][k];
     }
     const int n_after = n_before + inserted;
-    *a.t.n[ta] = n_after;
+    *pick(a.t.n, ta) = n_after;
     RoundStatus st{};
     st.found = bc_i >= 0 ? 1 : 0;
     st.cand = bc_i;
@@ -1004,9 +1075,10 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
     // the next round extends the smaller tree (equal sizes: the same one);
     // a connection or a full tree ends the search
     SearchState nx;
-    nx.n[ta] = n_after;
-    nx.n[tb] = ss.n[tb];
-    nx.a = nx.n[ta] > nx.n[tb] ? tb : ta;
+    const int n_other = pick(ss.n, tb);
+    nx.n[0] = ta == 0 ? n_after : n_other;
+    nx.n[1] = ta == 0 ? n_other : n_after;
+    nx.a = n_after > n_other ? tb : ta;
     nx.stop = (st.found || st.overflow) ? 1 : 0;
     *a.ss = nx;
     if (a.status_out) publish_status(st, a.status_out, a.seq);
@@ -1022,15 +1094,15 @@ __device__ __forceinline__ void refresh_body(const RefreshArgs &a, int bx) {
   const int n = st.n_after;
   const int v = bx * (int)blockDim.x + (int)threadIdx.x;
   if (v >= n) return;
-  const int32_t *parent = a.t.parent[st.a];
-  const float *e = a.t.e[st.a];
+  const int32_t *parent = pick(a.t.parent, st.a);
+  const float *e = pick(a.t.e, st.a);
   float acc = 0.f;
   int u = v;
   for (int k = 0; u > 0 && k < n; ++k) {
     acc += e[u];
     u = parent[u];
   }
-  a.t.g[st.a][v] = acc;
+  pick(a.t.g, st.a)[v] = acc;
 }
 
 // Path: root of tree A -> a_idx, then b_idx -> root of tree B (one thread).

@@ -344,18 +344,24 @@ def test_plan_error_paths(ctx):
     assert e.value.name == "E_INVALID_ARG"
 
 
-def test_plan_trajectory_vs_oracle_reported(ctx):
-    """The oracle planner follows the same rounds and random streams; its
-    trajectory is expected to match except after near-ties (reported)."""
+def test_plan_trajectory_matches_oracle_c1(ctx):
+    """The oracle planner follows the same rounds and random streams, so on
+    a problem without near-ties (the C1 problem of seed 0: checked once, the
+    trajectories then agreed to the last incumbent) the two planners find
+    the same incumbents in the same rounds and end on the same path; a
+    near-tie elsewhere could make them part (FP32 against FP64)."""
     from oracle.planner import plan as oplan, PlanParams
     p = problem("c1")
     s = _scene(ctx, p.scene)
     g = s.plan(p.q_start, p.q_goal, **PARAMS)
     o = oplan(p.scene, p.q_start, p.q_goal, PlanParams(**PARAMS))
-    same = o.path is not None and g.path is not None and o.path.shape == g.path.shape and \
-        np.abs(o.path - g.path).max() < 1e-4
     print(f"  gpu costs {[round(c, 4) for c in g.stats['costs']]} first round {g.stats['first_round']}")
-    print(f"  cpu costs {[round(c, 4) for c in o.costs]} first round {o.first_round}; same final path: {same}")
+    print(f"  cpu costs {[round(c, 4) for c in o.costs]} first round {o.first_round}", flush=True)
+    assert g.status == o.status == "OK" and g.stats["first_round"] == o.first_round
+    assert len(g.stats["costs"]) == len(o.costs)
+    for a, b in zip(g.stats["costs"], o.costs):
+        assert abs(a - b) <= 1e-5 * b, (g.stats["costs"], o.costs)
+    assert g.path.shape == o.path.shape and np.abs(g.path - o.path).max() < 1e-4
 
 
 def test_plan_history_ranked_and_valid(ctx):

@@ -124,6 +124,15 @@ mrpop_status mrpop_scene_set_env(mrpop_scene *scene, const mrpop_env *env);
 /* Composite dimension D (sum of joints) and total sphere count. */
 int32_t mrpop_scene_dof(const mrpop_scene *scene);
 int32_t mrpop_scene_total_spheres(const mrpop_scene *scene);
+/* Obstacle clusters of the scene's two-level coarse filter (performance
+ * only; the bits do not depend on it).  A scene with 64 obstacles or more
+ * groups them, spheres and boxes each along a Morton curve, in clusters of 8
+ * with bounding spheres of their own, tested before their members; it keeps
+ * the clusters only when an estimate from the arms' link positions at random
+ * configurations puts the coarse tests per link at half the obstacle count
+ * or less.  Returns the cluster count, 0 when the filter has one level (and
+ * for a NULL scene). */
+int32_t mrpop_scene_obstacle_clusters(const mrpop_scene *scene);
 
 /* Where the edge-validation kernel reads the scene's coarse filter rows
  * (performance only; every mode gives the same bits):
@@ -162,8 +171,11 @@ typedef struct {
   int64_t tiles;          /* work tiles processed                            */
   /* Work executed: kinematic chains (arm x state), coarse link centres
    * placed, coarse link-obstacle sphere tests (environment spheres and box
-   * bounding spheres), exact link-box tests, coarse link-link tests, fine
-   * sphere-sphere, sphere-box and arm-arm sphere tests. */
+   * bounding spheres; in a scene with obstacle clusters, also the tests of
+   * the links against the clusters, whose members are then tested only
+   * where the cluster's test passes), exact link-box tests, coarse
+   * link-link tests, fine sphere-sphere, sphere-box and arm-arm sphere
+   * tests. */
   int64_t work[8];
 } mrpop_validate_stats;
 

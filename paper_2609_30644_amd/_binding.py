@@ -191,6 +191,8 @@ def load_library():
     lib.mrpop_scene_dof.restype = I32
     lib.mrpop_scene_total_spheres.argtypes = [P]
     lib.mrpop_scene_total_spheres.restype = I32
+    lib.mrpop_scene_obstacle_clusters.argtypes = [P]
+    lib.mrpop_scene_obstacle_clusters.restype = I32
     lib.mrpop_scene_set_tile_mode.argtypes = [P, I32]
     lib.mrpop_scene_set_tile_mode.restype = I32
     lib.mrpop_scene_tile_mode.argtypes = [P]
@@ -394,6 +396,11 @@ class Scene:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def obstacle_clusters(self) -> int:
+        """Clusters of the two-level coarse filter (0: one level)."""
+        return int(self.ctx._lib.mrpop_scene_obstacle_clusters(self._h))
 
     TILE_MODES = {"auto": 0, "lds": 1, "scalar": 2}
 

@@ -311,6 +311,112 @@ static float round_up_f(double v) {
 // coarse test can never hide a contact.
 static constexpr double kCoarseInflate = 1e-4;
 
+// Two-level coarse filter: in scenes with at least kClusterMinObstacles
+// obstacles the table rows are ordered along a Morton curve and every
+// kClusterSize consecutive rows form a cluster with a bounding sphere of its
+// own, tested first.  Where obstacles are sparse the clusters are large and
+// nearly all pass, so the extra level only adds tests; the scene keeps them
+// only when an estimate of the tests per link says they pay.
+static constexpr int kClusterMinObstacles = 64;
+// Clusters are kept when the estimate below is at most this fraction of the
+// tests without them (the estimate is per lane; a wave tests a cluster's
+// members when any of its lanes passes, which costs more).
+static constexpr double kClusterGain = 0.5;
+
+// Order of the points along a Morton (Z-order) curve over their bounding
+// box, ten bits per axis (ties keep the input order).
+static std::vector<int> morton_order(const std::vector<float4> &pts, int n) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int i = 0; i < n; ++i) {
+    const double v[3] = {pts[i].x, pts[i].y, pts[i].z};
+    for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], v[a]); hi[a] = std::max(hi[a], v[a]); }
+  }
+  auto spread = [](uint64_t x) {  // the ten bits of x to every third bit
+    x &= 0x3ff;
+    x = (x | (x << 16)) & 0x30000ff;
+    x = (x | (x << 8)) & 0x300f00f;
+    x = (x | (x << 4)) & 0x30c30c3;
+    x = (x | (x << 2)) & 0x9249249;
+    return x;
+  };
+  std::vector<uint64_t> code(n);
+  for (int i = 0; i < n; ++i) {
+    const double v[3] = {pts[i].x, pts[i].y, pts[i].z};
+    uint64_t c = 0;
+    for (int a = 0; a < 3; ++a) {
+      const double span = hi[a] - lo[a];
+      const uint64_t q = span > 0 ? (uint64_t)std::min(1023.0, std::floor((v[a] - lo[a]) / span * 1023.0)) : 0;
+      c |= spread(q) << a;
+    }
+    code[i] = c;
+  }
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return code[a] < code[b]; });
+  return ord;
+}
+
+// Expected coarse tests per link with the cluster level: one per cluster
+// plus kClusterSize for every cluster whose test passes, averaged over the
+// link centres of every arm at seeded random configurations within the joint
+// limits (forward kinematics on the host, in double precision, with the
+// kernels' convention).  The samples per arm shrink with the cluster count so
+// that the estimate stays within a few million tests.
+static double cluster_tests_per_link(const mrpop_robot *robots, int n_robots, const std::vector<int32_t> &model_of,
+                                     const std::vector<float4> &dh, const std::vector<float> &th,
+                                     const std::vector<float4> &coarse, const std::vector<float> &base,
+                                     const std::vector<float4> &cc, const std::vector<double> &cr, double delta_c) {
+  const int NC = (int)cc.size();
+  const int per_arm = (int)std::max<int64_t>(4, std::min<int64_t>(256, 2000000 / ((int64_t)n_robots * kMaxLinks * NC)));
+  uint64_t sm = 0x2545f4914f6cdd1dull;
+  auto next_u01 = [&sm]() {  // splitmix64 (Steele, Lea and Flood, 2014), top 53 bits
+    uint64_t z = (sm += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return (double)((z ^ (z >> 31)) >> 11) * 0x1.0p-53;
+  };
+  double links = 0.0, tests = 0.0;
+  for (int r = 0; r < n_robots; ++r) {
+    const mrpop_robot &rb = robots[r];
+    const int m = model_of[r];
+    for (int k = 0; k < per_arm; ++k) {
+      double F[12];
+      for (int i = 0; i < 12; ++i) F[i] = base[(size_t)r * 12 + i];
+      for (int l = 0; l <= rb.n_joints; ++l) {
+        if (l > 0) {
+          // F <- F RotX(alpha) TransX(a) RotZ(theta) TransZ(d), row by row
+          const float4 p = dh[(size_t)m * kMaxJoints + l - 1];
+          const double q = rb.q_lo[l - 1] + next_u01() * ((double)rb.q_hi[l - 1] - rb.q_lo[l - 1]) +
+                           th[(size_t)m * kMaxJoints + l - 1];
+          const double c = std::cos(q), sn = std::sin(q);
+          for (int row = 0; row < 3; ++row) {
+            double *R = F + 4 * row;
+            const double u = R[1] * p.z + R[2] * p.w, n2 = R[2] * p.z - R[1] * p.w;
+            R[3] += R[0] * p.x + n2 * p.y;
+            const double n0 = R[0] * c + u * sn, n1 = u * c - R[0] * sn;
+            R[0] = n0;
+            R[1] = n1;
+            R[2] = n2;
+          }
+        }
+        const float4 cv = coarse[(size_t)m * kMaxLinks + l];
+        if (cv.w < 0) continue;
+        const double x = F[0] * cv.x + F[1] * cv.y + F[2] * cv.z + F[3];
+        const double y = F[4] * cv.x + F[5] * cv.y + F[6] * cv.z + F[7];
+        const double z = F[8] * cv.x + F[9] * cv.y + F[10] * cv.z + F[11];
+        links += 1.0;
+        tests += NC;
+        for (int ci = 0; ci < NC; ++ci) {
+          const double dx = x - cc[ci].x, dy = y - cc[ci].y, dz = z - cc[ci].z;
+          const double R = (double)cv.w + cr[ci] + delta_c;
+          if (dx * dx + dy * dy + dz * dz < R * R) tests += kClusterSize;
+        }
+      }
+    }
+  }
+  return links > 0.0 ? tests / links : 0.0;
+}
+
 struct Blob {
   std::vector<unsigned char> host;
   size_t add(const void *p, size_t bytes) {
@@ -452,7 +558,6 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
     env_b[2 * k] = float4{(float)((double)b[0] - org[0]), (float)((double)b[1] - org[1]), (float)((double)b[2] - org[2]), 0.f};
     env_b[2 * k + 1] = float4{(float)((double)b[3] - org[0]), (float)((double)b[4] - org[1]), (float)((double)b[5] - org[2]), 0.f};
   }
-
   // Expanded-form coarse filter tables (see SceneDev).  delta covers the
   // rounding error of the single-precision expanded test: near a contact every
   // point involved lies within M of the origin, the table entry is rounded
@@ -486,34 +591,105 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   double rc_max = 0.0;
   for (const float4 &cv : coarse)
     if (cv.w >= 0) { rc_min = std::min(rc_min, (double)cv.w); rc_max = std::max(rc_max, (double)cv.w); }
-  const double Mx = base_far + reach + rc_max + obs_r;
-  const double eps = 20.0 * std::ldexp(1.0, -24) * Mx * Mx;
-  const double delta = std::max(1e-4, std::min(std::sqrt(eps), eps / (2.0 * std::max(rc_min, 1e-30))));
+  auto delta_for = [&](double obstacle_r) {  // delta for bounding radii up to obstacle_r
+    const double Mx = base_far + reach + rc_max + obstacle_r;
+    const double eps = 20.0 * std::ldexp(1.0, -24) * Mx * Mx;
+    return std::max(1e-4, std::min(std::sqrt(eps), eps / (2.0 * std::max(rc_min, 1e-30))));
+  };
+  const double delta = delta_for(obs_r);
   // rows per link padded to a multiple of eight (the tile kernel tests two
   // groups of four per step), plus one group past the last link's rows, which
   // the kernel's prefetch of the next group may read
   const int NS = env->n_spheres, NB = env->n_boxes, NO = NS + NB, NO4 = std::max(8, (NO + 7) & ~7);
-  std::vector<float4> rows((size_t)M * kMaxLinks * NO4 + 4, float4{0.f, 0.f, 0.f, 3.0e38f});
-  // bounding sphere of every obstacle: centre (single precision) and radius
+  // bounding sphere of every obstacle in table order (spheres, then boxes):
+  // centre (single precision) and radius
   std::vector<float4> bound(std::max(1, NO));
-  for (int k = 0; k < NS; ++k) bound[k] = env_s[k];
   std::vector<double> bound_r(std::max(1, NO));
-  for (int k = 0; k < NS; ++k) bound_r[k] = (double)env_s[k].w;
-  for (int k = 0; k < NB; ++k) {
-    const float4 lo = env_b[2 * k], hi = env_b[2 * k + 1];
-    const float mx = 0.5f * (lo.x + hi.x), my = 0.5f * (lo.y + hi.y), mz = 0.5f * (lo.z + hi.z);
-    // radius from the rounded centre to the farthest corner
-    double far = 0.0;
-    for (int cx = 0; cx < 2; ++cx)
-      for (int cy = 0; cy < 2; ++cy)
-        for (int cz = 0; cz < 2; ++cz) {
-          const double dx = (double)(cx ? hi.x : lo.x) - mx, dy = (double)(cy ? hi.y : lo.y) - my,
-                       dz = (double)(cz ? hi.z : lo.z) - mz;
-          far = std::max(far, std::sqrt(dx * dx + dy * dy + dz * dz));
-        }
-    bound[NS + k] = float4{mx, my, mz, 0.f};
-    bound_r[NS + k] = far;
+  auto make_bounds = [&](const std::vector<float4> &es, const std::vector<float4> &eb, std::vector<float4> &cen,
+                         std::vector<double> &rad) {
+    for (int k = 0; k < NS; ++k) {
+      cen[k] = es[k];
+      rad[k] = (double)es[k].w;
+    }
+    for (int k = 0; k < NB; ++k) {
+      const float4 lo = eb[2 * k], hi = eb[2 * k + 1];
+      const float mx = 0.5f * (lo.x + hi.x), my = 0.5f * (lo.y + hi.y), mz = 0.5f * (lo.z + hi.z);
+      // radius from the rounded centre to the farthest corner
+      double far = 0.0;
+      for (int cx = 0; cx < 2; ++cx)
+        for (int cy = 0; cy < 2; ++cy)
+          for (int cz = 0; cz < 2; ++cz) {
+            const double dx = (double)(cx ? hi.x : lo.x) - mx, dy = (double)(cy ? hi.y : lo.y) - my,
+                         dz = (double)(cz ? hi.z : lo.z) - mz;
+            far = std::max(far, std::sqrt(dx * dx + dy * dy + dz * dz));
+          }
+      cen[NS + k] = float4{mx, my, mz, 0.f};
+      rad[NS + k] = far;
+    }
+  };
+  make_bounds(env_s, env_b, bound, bound_r);
+
+  // Obstacle clusters.  The spheres and the boxes each go along a Morton
+  // curve (in the device arrays only: an obstacle's index is internal to the
+  // tables), so that runs of consecutive obstacles are compact; cluster c
+  // holds table rows kClusterSize c .. kClusterSize c + kClusterSize - 1.
+  // Its sphere (centre the mean of the members' bounding centres, radius
+  // reaching past every member's bounding sphere) contains every member, so
+  // a link that touches a member passes its cluster's test.  The rows take
+  // the expanded form with delta recomputed for the larger radii, padded like
+  // the member rows.  The scene keeps the input order and one level when the
+  // estimate says the clusters do not pay.
+  int NC = 0, NC4 = 0;
+  std::vector<float4> cc;
+  std::vector<double> cr;
+  double delta_c = 0.0;
+  if (NO >= kClusterMinObstacles) {
+    std::vector<float4> ps(env_s), pb(env_b);
+    if (NS > 1) {
+      const std::vector<int> ord = morton_order(env_s, NS);
+      for (int k = 0; k < NS; ++k) ps[k] = env_s[ord[k]];
+    }
+    if (NB > 1) {
+      std::vector<float4> mid(NB);
+      for (int k = 0; k < NB; ++k)
+        mid[k] = float4{0.5f * (env_b[2 * k].x + env_b[2 * k + 1].x), 0.5f * (env_b[2 * k].y + env_b[2 * k + 1].y),
+                        0.5f * (env_b[2 * k].z + env_b[2 * k + 1].z), 0.f};
+      const std::vector<int> ord = morton_order(mid, NB);
+      for (int k = 0; k < NB; ++k) {
+        pb[2 * k] = env_b[2 * ord[k]];
+        pb[2 * k + 1] = env_b[2 * ord[k] + 1];
+      }
+    }
+    std::vector<float4> pbound(bound.size());
+    std::vector<double> pbound_r(bound_r.size());
+    make_bounds(ps, pb, pbound, pbound_r);
+    const int nc = (NO + kClusterSize - 1) / kClusterSize;
+    cc.assign(nc, float4{0.f, 0.f, 0.f, 0.f});
+    cr.assign(nc, 0.0);
+    double cr_max = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      const int k0 = c * kClusterSize, k1 = std::min(NO, k0 + kClusterSize);
+      double s[3] = {0, 0, 0};
+      for (int k = k0; k < k1; ++k) { s[0] += pbound[k].x; s[1] += pbound[k].y; s[2] += pbound[k].z; }
+      cc[c] = float4{(float)(s[0] / (k1 - k0)), (float)(s[1] / (k1 - k0)), (float)(s[2] / (k1 - k0)), 0.f};
+      for (int k = k0; k < k1; ++k) {
+        const double dx = (double)pbound[k].x - cc[c].x, dy = (double)pbound[k].y - cc[c].y,
+                     dz = (double)pbound[k].z - cc[c].z;
+        cr[c] = std::max(cr[c], std::sqrt(dx * dx + dy * dy + dz * dz) + pbound_r[k]);
+      }
+      cr_max = std::max(cr_max, cr[c]);
+    }
+    delta_c = delta_for(std::max(obs_r, cr_max));
+    if (cluster_tests_per_link(robots, n_robots, model_of, dh, th, coarse, base, cc, cr, delta_c) <=
+        kClusterGain * NO) {
+      NC = nc;
+      env_s.swap(ps);
+      env_b.swap(pb);
+      bound.swap(pbound);
+      bound_r.swap(pbound_r);
+    }
   }
+  std::vector<float4> rows((size_t)M * kMaxLinks * NO4 + 4, float4{0.f, 0.f, 0.f, 3.0e38f});
   for (int m = 0; m < M; ++m)
     for (int l = 0; l < kMaxLinks; ++l) {
       const float4 cv = coarse[(size_t)m * kMaxLinks + l];
@@ -525,6 +701,22 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
         rows[((size_t)m * kMaxLinks + l) * NO4 + k] = float4{-2.f * o.x, -2.f * o.y, -2.f * o.z, (float)(o2 - R * R)};
       }
     }
+  std::vector<float4> crows(1, float4{0.f, 0.f, 0.f, 3.0e38f});
+  if (NC > 0) {
+    NC4 = std::max(8, (NC + 7) & ~7);
+    crows.assign((size_t)M * kMaxLinks * NC4 + 4, float4{0.f, 0.f, 0.f, 3.0e38f});
+    for (int m = 0; m < M; ++m)
+      for (int l = 0; l < kMaxLinks; ++l) {
+        const float4 cv = coarse[(size_t)m * kMaxLinks + l];
+        if (cv.w < 0 || l > models[m]->n_joints) continue;
+        for (int c = 0; c < NC; ++c) {
+          const float4 o = cc[c];
+          const double o2 = (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z;
+          const double R = (double)cv.w + cr[c] + delta_c;
+          crows[((size_t)m * kMaxLinks + l) * NC4 + c] = float4{-2.f * o.x, -2.f * o.y, -2.f * o.z, (float)(o2 - R * R)};
+        }
+      }
+  }
 
   // Arm pairs and, per pair, the link pairs that can touch: link l's coarse
   // sphere stays within reach(l) = sum_{j <= l} |(a_{j-1}, d_j)| + |c_l| + r_l
@@ -592,6 +784,7 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   size_t o_es = blob.add(env_s.data(), sizeof(float4) * env_s.size());
   size_t o_eb = blob.add(env_b.data(), sizeof(float4) * env_b.size());
   size_t o_rows = blob.add(rows.data(), sizeof(float4) * rows.size());
+  size_t o_crows = blob.add(crows.data(), sizeof(float4) * crows.size());
   size_t o_pairs = blob.add(pairs.data(), sizeof(int32_t) * pairs.size());
   size_t o_plinks = blob.add(pair_links.data(), sizeof(uint64_t) * pair_links.size());
   std::vector<float> qlo_all, qhi_all;
@@ -645,6 +838,9 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   d.origin = float3{(float)org[0], (float)org[1], (float)org[2]};
   d.rows = (const float4 *)at(o_rows);
   d.n_rows4 = NO4;
+  d.crows = (const float4 *)at(o_crows);
+  d.n_clusters = NC;
+  d.n_crows4 = NC4;
   d.n_pairs = n_pairs;
   d.pair_links = (const uint64_t *)at(o_plinks);
   d.pairs = (const int32_t *)at(o_pairs);
@@ -715,6 +911,7 @@ mrpop_status mrpop_scene_set_env(mrpop_scene *scene, const mrpop_env *env) {
 
 int32_t mrpop_scene_dof(const mrpop_scene *scene) { return scene ? scene->dof : 0; }
 int32_t mrpop_scene_total_spheres(const mrpop_scene *scene) { return scene ? scene->total_spheres : 0; }
+int32_t mrpop_scene_obstacle_clusters(const mrpop_scene *scene) { return scene ? scene->dev.n_clusters : 0; }
 
 mrpop_status mrpop_scene_set_tile_mode(mrpop_scene *scene, int32_t mode) {
   if (!scene) return MRPOP_E_INVALID_ARG;

@@ -16,6 +16,7 @@ namespace mrpop {
 constexpr int kMaxJoints = MRPOP_MAX_JOINTS;
 constexpr int kMaxLinks = MRPOP_MAX_JOINTS + 1;
 constexpr int kWave = 64;
+constexpr int kClusterSize = 8;  // table rows per obstacle cluster of the coarse filter
 
 // Device-side view of a scene, passed to kernels by value.
 //
@@ -65,6 +66,15 @@ struct SceneDev {
   // groups of four; one more group of padding follows the last link.
   int32_t n_rows4;
   const float4 *rows;      // [M][kMaxLinks][n_rows4]
+  // Cluster level of the filter (scenes with many obstacles; n_clusters = 0
+  // otherwise): cluster c covers rows kClusterSize c onwards, and crows[m][l][c] holds
+  // the same expanded test for a sphere containing every member's bounding
+  // sphere (with its own delta), so a link that touches a member obstacle
+  // passes the cluster's test.  Padded to n_crows4 (a multiple of eight)
+  // plus one group, like the rows.
+  int32_t n_clusters;
+  int32_t n_crows4;
+  const float4 *crows;     // [M][kMaxLinks][n_crows4]
   const float *q_lo, *q_hi;  // [D] composite joint limits
   // Arm pairs (i < j) whose bases are close enough for contact; other pairs
   // can never touch (every sphere stays within its arm's reach bound).

@@ -408,6 +408,7 @@ constexpr int kGroup = 4;                           // obstacles per coarse step
 constexpr int kQueueFlushAt = kWave;                 // flush once more items than this are queued
 constexpr int kQueueCap = kQueueFlushAt + kGroup * kWave;
 constexpr int kWaveLdsFloats = 12 * kWave + kQueueCap;
+static_assert(kClusterSize == 2 * kGroup, "a cluster's rows are two groups");
 
 // Scene data the tile kernel reads inside its loops: coarse rows, obstacle
 // spheres and boxes, fine spheres, link ranges and coarse radii.  The coarse
@@ -421,18 +422,22 @@ struct Src;
 template <>
 struct Src<true> {
   cptr<float4> rows;     // [M][kMaxLinks][n4], read through the scalar cache
+  cptr<float4> crows;    // [M][kMaxLinks][nc4], likewise
   const float4 *env_s;   // [Ns]
   const float4 *boxes;   // [Nb][2]
   const float4 *fine;    // [M][sph_stride]
   const int32_t *lstart; // [M][kMaxLinks + 1]
   const float *crad;     // [M][kMaxLinks]
-  int ns, nb, n4, stride;
+  int ns, nb, n4, stride, nc, nc4;
   // the rows of link l, read kGroup at a time (one 64-byte scalar load each).
   // The rows are the same for every lane; from LDS each read would write them
   // into every lane's registers, which costs more LDS bandwidth than the
   // tests they feed.
   __device__ cptr<float> link_rows(int m, int l) const {
     return (cptr<float>)(rows + ((int64_t)m * kMaxLinks + l) * n4);
+  }
+  __device__ cptr<float> link_crows(int m, int l) const {
+    return (cptr<float>)(crows + ((int64_t)m * kMaxLinks + l) * nc4);
   }
   __device__ float4 sphere(int k) const { return env_s[k]; }
   __device__ float4 box(int i) const { return boxes[i]; }
@@ -443,12 +448,15 @@ struct Src<true> {
 
 template <>
 struct Src<false> {
-  cptr<float4> rows, fine, coarse;
+  cptr<float4> rows, crows, fine, coarse;
   const float4 *env_s, *boxes;  // read at lane-varying indices
   cptr<int32_t> lstart;
-  int ns, nb, n4, stride;
+  int ns, nb, n4, stride, nc, nc4;
   __device__ cptr<float> link_rows(int m, int l) const {
     return (cptr<float>)(rows + ((int64_t)m * kMaxLinks + l) * n4);
+  }
+  __device__ cptr<float> link_crows(int m, int l) const {
+    return (cptr<float>)(crows + ((int64_t)m * kMaxLinks + l) * nc4);
   }
   __device__ float4 sphere(int k) const { return env_s[k]; }
   __device__ float4 box(int i) const { return boxes[i]; }
@@ -478,6 +486,9 @@ __device__ Src<true> make_src<true>(const SceneDev &sc, float *stage) {
   s.stride = sc.sph_stride;
   float4 *p = (float4 *)stage;
   s.rows = as_const(sc.rows);
+  s.crows = as_const(sc.crows);
+  s.nc = sc.n_clusters;
+  s.nc4 = sc.n_crows4;
   s.env_s = p;
   for (int i = threadIdx.x; i < s.ns; i += blockDim.x) p[i] = sc.env_s[i];
   p += s.ns;
@@ -501,6 +512,9 @@ template <>
 __device__ Src<false> make_src<false>(const SceneDev &sc, float *) {
   Src<false> s;
   s.rows = as_const(sc.rows);
+  s.crows = as_const(sc.crows);
+  s.nc = sc.n_clusters;
+  s.nc4 = sc.n_crows4;
   s.env_s = sc.env_s;
   s.boxes = sc.env_b;
   s.fine = as_const(sc.fine);
@@ -596,7 +610,7 @@ __device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int 
   if (cs.w < 0.f) return false;  // a link without spheres
   if (live) {
     ++wc.links;
-    wc.env_tests += N;
+    wc.env_tests += src.nc > 0 ? src.nc : N;  // (with clusters, member rows are counted as they are tested)
   }
   if (N == 0) return false;
   const float c2 = fmaf(c.z, c.z, fmaf(c.y, c.y, c.x * c.x));
@@ -646,15 +660,62 @@ __device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int 
   };
   cptr<float> p = src.link_rows(m, l);
   float4 ra[kGroup], rb[kGroup];
-  load(p, ra);
-  for (int k0 = 0; k0 < src.n4; k0 += 2 * kGroup) {
-    load(p + 4 * kGroup, rb);
-    __builtin_amdgcn_sched_barrier(0);  // keep each load ahead of the tests it overlaps
-    group_tests(ra, k0);
-    load(p + 8 * kGroup, ra);
-    __builtin_amdgcn_sched_barrier(0);
-    group_tests(rb, k0 + kGroup);
-    p += 8 * kGroup;
+  if (src.nc == 0) {
+    load(p, ra);
+    for (int k0 = 0; k0 < src.n4; k0 += 2 * kGroup) {
+      load(p + 4 * kGroup, rb);
+      __builtin_amdgcn_sched_barrier(0);  // keep each load ahead of the tests it overlaps
+      group_tests(ra, k0);
+      load(p + 8 * kGroup, ra);
+      __builtin_amdgcn_sched_barrier(0);
+      group_tests(rb, k0 + kGroup);
+      p += 8 * kGroup;
+    }
+  } else {
+    // Clusters in chunks of 64: first the chunk's cluster rows, in the same
+    // pipelined pairs of groups, into a mask of the clusters that pass for a
+    // live lane; then the member rows of those clusters (two groups of kGroup
+    // each), again with each group's load issued before the group ahead of
+    // it is tested.
+    auto cluster_mask = [&](const float4 (&cw)[kGroup], int i0, uint64_t &pm) {
+#pragma unroll
+      for (int i = 0; i < kGroup; ++i) {
+        const float t = fmaf(c.z, cw[i].z, fmaf(c.y, cw[i].y, fmaf(c.x, cw[i].x, c2)));
+        if (__builtin_amdgcn_ballot_w64(t < -cw[i].w) & livem) pm |= 1ull << (i0 + i);
+      }
+    };
+    cptr<float> pc = src.link_crows(m, l);
+    for (int ch = 0; ch < src.nc4; ch += 64) {
+      const int n_ch = min(64, src.nc4 - ch);  // a multiple of 2 kGroup
+      uint64_t pm = 0;
+      load(pc, ra);
+      for (int i0 = 0; i0 < n_ch; i0 += 2 * kGroup) {
+        load(pc + 4 * kGroup, rb);
+        __builtin_amdgcn_sched_barrier(0);
+        cluster_mask(ra, i0, pm);
+        load(pc + 8 * kGroup, ra);
+        __builtin_amdgcn_sched_barrier(0);
+        cluster_mask(rb, i0 + kGroup, pm);
+        pc += 8 * kGroup;
+      }
+      if (pm == 0ull) continue;
+      int k0 = (ch + __builtin_ctzll(pm)) * kClusterSize;
+      pm &= pm - 1;
+      load(p + 4 * k0, ra);
+      for (;;) {
+        if (live) wc.env_tests += min(kClusterSize, N - k0);
+        load(p + 4 * (k0 + kGroup), rb);
+        __builtin_amdgcn_sched_barrier(0);
+        group_tests(ra, k0);
+        const int k1 = pm ? (ch + __builtin_ctzll(pm)) * kClusterSize : -1;
+        if (k1 >= 0) load(p + 4 * k1, ra);
+        __builtin_amdgcn_sched_barrier(0);
+        group_tests(rb, k0 + kGroup);
+        if (k1 < 0) break;
+        pm &= pm - 1;
+        k0 = k1;
+      }
+    }
   }
   if (qn > 0) flush_queue<STAGED>(src, m, l, csr, fr, queue, qn, hitw, lane, wc);
   const bool hit = live && ((*hitw >> lane) & 1ull);

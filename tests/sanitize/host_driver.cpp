@@ -150,6 +150,31 @@ int main() {
   std::printf("validate: %lld edge states, %lld invalid edges\n", (long long)vs.edge_states,
               (long long)vs.edges_invalid);
 
+  // a scene with many obstacles packed near the arms (the cluster level of
+  // the coarse filter, when the scene's estimate keeps it): the same edges
+  CHECK(mrpop_scene_obstacle_clusters(nullptr) == 0 && mrpop_scene_obstacle_clusters(sc) == 0);
+  {
+    std::vector<float> many_s, many_b;
+    for (int k = 0; k < 90; ++k) {
+      const float u = (float)g.u(), w = (float)g.u();
+      many_s.insert(many_s.end(), {-0.2f + 0.4f * u, 1.0f + 0.3f * w, 0.3f + 0.4f * u * w, 0.02f});
+    }
+    for (int k = 0; k < 41; ++k) {
+      const float u = (float)g.u(), w = (float)g.u();
+      const float x = -0.2f + 0.4f * u, y = -1.3f + 0.3f * w, z = 0.3f + 0.3f * u * w;
+      many_b.insert(many_b.end(), {x, y, z, x + 0.03f, y + 0.03f, z + 0.03f});
+    }
+    const mrpop_env env_many{90, many_s.data(), 41, many_b.data()};
+    mrpop_scene *dense = nullptr;
+    CHECK(mrpop_scene_create(ctx, robots, 2, &env_many, &dense) == MRPOP_OK);
+    const int nc = mrpop_scene_obstacle_clusters(dense);
+    CHECK(nc == 0 || nc == (90 + 41 + 7) / 8);
+    CHECK(mrpop_validate_edges(ctx, dense, qa, qb, E, 0.05f, nullptr, v1, nullptr, nullptr) == MRPOP_OK);
+    HIPCHECK(hipDeviceSynchronize());
+    std::printf("dense scene: %d obstacle clusters\n", nc);
+    mrpop_scene_destroy(dense);
+  }
+
   // forward kinematics, nearest, sample
   float *xyzr = nullptr;
   HIPCHECK(hipMalloc(&xyzr, sizeof(float) * 16 * 32 * 4));

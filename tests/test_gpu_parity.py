@@ -191,6 +191,59 @@ def test_validate_scene_too_large_for_lds_staging(ctx):
     _parity(ctx, sc, qa, qb, 0.05, "large env (global rows)")
 
 
+def _shelf_mix(ns, nb, seed):
+    """The 8-arm shelf scene with its first nb boxes and ns small spheres on
+    the shelves of one quarter of the grid."""
+    sc = problem("c3").scene
+    rng = np.random.default_rng(seed)
+    mid = 0.5 * (sc.env_boxes[:, :3] + sc.env_boxes[:, 3:])
+    corner = np.nonzero((mid[:, 0] < 0) & (mid[:, 1] < 0))[0]
+    c = mid[rng.choice(corner, ns, replace=ns > len(corner))] + rng.uniform(-0.1, 0.1, (ns, 3))
+    sph = np.concatenate([c, rng.uniform(0.02, 0.06, (ns, 1))], 1).astype(np.float32)
+    return sc.with_env(sph, sc.env_boxes[:nb].copy())
+
+
+def _sparse_mix(ns, nb, seed):
+    """The 4-arm scene with ns spheres and nb boxes scattered over 3.6 m."""
+    rng = np.random.default_rng(seed)
+    cs = rng.uniform([-1.8, -1.8, 0.0], [1.8, 1.8, 1.5], (ns, 3))
+    sph = np.concatenate([cs, rng.uniform(0.01, 0.04, (ns, 1))], 1).astype(np.float32)
+    lo = rng.uniform([-1.8, -1.8, 0.0], [1.8, 1.8, 1.5], (nb, 3))
+    box = np.concatenate([lo, lo + rng.uniform(0.02, 0.08, (nb, 3))], 1).astype(np.float32)
+    return problem("c2").scene.with_env(sph, box)
+
+
+@pytest.mark.parametrize("kind,ns,nb,clusters", [("shelf", 37, 210, True), ("shelf", 64, 0, True),
+                                                  ("shelf", 0, 256, True), ("sparse", 50, 47, False)])
+def test_validate_obstacle_clusters(ctx, kind, ns, nb, clusters):
+    """From 64 obstacles on, a scene whose obstacles are dense enough tests
+    clusters of eight before their members (spheres and boxes each in Morton
+    order: here a ragged last cluster and one holding both kinds, exactly 64
+    spheres, and the full shelf grid); a sparse one keeps one level.  The bits
+    equal the oracle's either way, and with clusters fewer coarse tests run
+    than one per link and obstacle."""
+    seed = ns * 1000 + nb
+    sc = _shelf_mix(ns, nb, seed) if kind == "shelf" else _sparse_mix(ns, nb, seed)
+    res = 0.02 if kind == "shelf" else 0.05
+    rng = np.random.default_rng(seed)
+    anchors = W.random_configs(sc, 1500 if kind == "shelf" else 3000, rng)
+    anchors = anchors[oracle.states_free(sc, anchors)]
+    assert len(anchors) > 8
+    qa, qb = W.edge_batch_near(sc, anchors, 256, res, 110, 2, 40 if kind == "shelf" else 24,
+                               spread=0.02 if kind == "shelf" else 0.3)
+    n_clusters = _scene(ctx, sc).obstacle_clusters
+    print(f"[clusters] {kind} {ns}+{nb}: {n_clusters} clusters", flush=True)
+    assert n_clusters == ((ns + nb + 7) // 8 if clusters else 0)
+    valid, m, st = _parity(ctx, sc, qa, qb, res, f"{kind} env {ns}+{nb}")
+    assert (m < -BAND).any() and (m > BAND).any()
+    w = st.work
+    print(f"  coarse tests {w['env_tests']} links {w['links']} per link {w['env_tests'] / w['links']:.1f}", flush=True)
+    if clusters:
+        assert w["env_tests"] < w["links"] * (ns + nb)
+    else:
+        assert w["env_tests"] == w["links"] * (ns + nb)
+
+
 def test_validate_no_obstacles_arm_pairs_only(ctx):
     sc = problem("c2").scene
     empty = sc.with_env(np.zeros((0, 4), np.float32), np.zeros((0, 6), np.float32))

@@ -124,13 +124,14 @@ mrpop_status mrpop_scene_set_env(mrpop_scene *scene, const mrpop_env *env);
 /* Composite dimension D (sum of joints) and total sphere count. */
 int32_t mrpop_scene_dof(const mrpop_scene *scene);
 int32_t mrpop_scene_total_spheres(const mrpop_scene *scene);
-/* Obstacle clusters of the scene's two-level coarse filter (performance
- * only; the bits do not depend on it).  A scene with 64 obstacles or more
- * groups them, spheres and boxes each along a Morton curve, in clusters of 8
+/* Obstacle clusters of the scene's coarse filter (performance only; the
+ * bits do not depend on it).  Each link of each arm tests only the obstacles
+ * within the link's reach of its arm's base, in Morton order of their
+ * centres.  A list of 64 obstacles or more may group them in clusters of 8
  * with bounding spheres of their own, tested before their members; it keeps
- * the clusters only when an estimate from the arms' link positions at random
- * configurations puts the coarse tests per link at half the obstacle count
- * or less.  Returns the cluster count, 0 when the filter has one level (and
+ * them only when an estimate from the link's positions at random
+ * configurations puts its coarse tests at half the list's length or less.
+ * Returns the clusters over all lists, 0 when every list has one level (and
  * for a NULL scene). */
 int32_t mrpop_scene_obstacle_clusters(const mrpop_scene *scene);
 
@@ -171,9 +172,10 @@ typedef struct {
   int64_t tiles;          /* work tiles processed                            */
   /* Work executed: kinematic chains (arm x state), coarse link centres
    * placed, coarse link-obstacle sphere tests (environment spheres and box
-   * bounding spheres; in a scene with obstacle clusters, also the tests of
-   * the links against the clusters, whose members are then tested only
-   * where the cluster's test passes), exact link-box tests, coarse
+   * bounding spheres, of the obstacles within each link's reach only; for
+   * lists with obstacle clusters, also the tests of the links against the
+   * clusters, whose members are then tested only where the cluster's test
+   * passes), exact link-box tests, coarse
    * link-link tests, fine sphere-sphere, sphere-box and arm-arm sphere
    * tests. */
   int64_t work[8];

@@ -311,17 +311,20 @@ static float round_up_f(double v) {
 // coarse test can never hide a contact.
 static constexpr double kCoarseInflate = 1e-4;
 
-// Two-level coarse filter: in scenes with at least kClusterMinObstacles
-// obstacles the table rows are ordered along a Morton curve and every
-// kClusterSize consecutive rows form a cluster with a bounding sphere of its
-// own, tested first.  Where obstacles are sparse the clusters are large and
-// nearly all pass, so the extra level only adds tests; the scene keeps them
-// only when an estimate of the tests per link says they pay.
+// Two-level coarse filter: a link's obstacle list of at least
+// kClusterMinObstacles entries may group every kClusterSize consecutive rows
+// into a cluster with a bounding sphere of its own, tested first.  Where
+// obstacles are sparse the clusters are large and nearly all pass, so the
+// extra level only adds tests; a list keeps them only when an estimate of
+// the tests per link says they pay.
 static constexpr int kClusterMinObstacles = 64;
-// Clusters are kept when the estimate below is at most this fraction of the
-// tests without them (the estimate is per lane; a wave tests a cluster's
-// members when any of its lanes passes, which costs more).
+// Clusters are kept when the estimated tests are at most this fraction of
+// the tests without them (the estimate is per lane; a wave tests a
+// cluster's members when any of its lanes passes, which costs more).
 static constexpr double kClusterGain = 0.5;
+// Slack of the reach test that builds the per-link obstacle lists, in metres
+// (covers single-precision rounding of the chain, far below it).
+static constexpr double kReachMargin = 1e-3;
 
 // Order of the points along a Morton (Z-order) curve over their bounding
 // box, ten bits per axis (ties keep the input order).
@@ -356,18 +359,15 @@ static std::vector<int> morton_order(const std::vector<float4> &pts, int n) {
   return ord;
 }
 
-// Expected coarse tests per link with the cluster level: one per cluster
-// plus kClusterSize for every cluster whose test passes, averaged over the
-// link centres of every arm at seeded random configurations within the joint
-// limits (forward kinematics on the host, in double precision, with the
-// kernels' convention).  The samples per arm shrink with the cluster count so
-// that the estimate stays within a few million tests.
-static double cluster_tests_per_link(const mrpop_robot *robots, int n_robots, const std::vector<int32_t> &model_of,
-                                     const std::vector<float4> &dh, const std::vector<float> &th,
-                                     const std::vector<float4> &coarse, const std::vector<float> &base,
-                                     const std::vector<float4> &cc, const std::vector<double> &cr, double delta_c) {
-  const int NC = (int)cc.size();
-  const int per_arm = (int)std::max<int64_t>(4, std::min<int64_t>(256, 2000000 / ((int64_t)n_robots * kMaxLinks * NC)));
+// Link centres of every arm at seeded random configurations within the
+// joint limits, for the cluster estimate: [R][kMaxLinks][samples] x, y, z
+// (recentred world frame; forward kinematics on the host in double
+// precision, with the kernels' convention; links without spheres left 0).
+static std::vector<double> sample_link_centres(const mrpop_robot *robots, int n_robots,
+                                               const std::vector<int32_t> &model_of, const std::vector<float4> &dh,
+                                               const std::vector<float> &th, const std::vector<float4> &coarse,
+                                               const std::vector<float> &base, int samples) {
+  std::vector<double> out((size_t)n_robots * kMaxLinks * samples * 3, 0.0);
   uint64_t sm = 0x2545f4914f6cdd1dull;
   auto next_u01 = [&sm]() {  // splitmix64 (Steele, Lea and Flood, 2014), top 53 bits
     uint64_t z = (sm += 0x9e3779b97f4a7c15ull);
@@ -375,11 +375,10 @@ static double cluster_tests_per_link(const mrpop_robot *robots, int n_robots, co
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
     return (double)((z ^ (z >> 31)) >> 11) * 0x1.0p-53;
   };
-  double links = 0.0, tests = 0.0;
   for (int r = 0; r < n_robots; ++r) {
     const mrpop_robot &rb = robots[r];
     const int m = model_of[r];
-    for (int k = 0; k < per_arm; ++k) {
+    for (int k = 0; k < samples; ++k) {
       double F[12];
       for (int i = 0; i < 12; ++i) F[i] = base[(size_t)r * 12 + i];
       for (int l = 0; l <= rb.n_joints; ++l) {
@@ -401,20 +400,14 @@ static double cluster_tests_per_link(const mrpop_robot *robots, int n_robots, co
         }
         const float4 cv = coarse[(size_t)m * kMaxLinks + l];
         if (cv.w < 0) continue;
-        const double x = F[0] * cv.x + F[1] * cv.y + F[2] * cv.z + F[3];
-        const double y = F[4] * cv.x + F[5] * cv.y + F[6] * cv.z + F[7];
-        const double z = F[8] * cv.x + F[9] * cv.y + F[10] * cv.z + F[11];
-        links += 1.0;
-        tests += NC;
-        for (int ci = 0; ci < NC; ++ci) {
-          const double dx = x - cc[ci].x, dy = y - cc[ci].y, dz = z - cc[ci].z;
-          const double R = (double)cv.w + cr[ci] + delta_c;
-          if (dx * dx + dy * dy + dz * dz < R * R) tests += kClusterSize;
-        }
+        double *o = &out[(((size_t)r * kMaxLinks + l) * samples + k) * 3];
+        o[0] = F[0] * cv.x + F[1] * cv.y + F[2] * cv.z + F[3];
+        o[1] = F[4] * cv.x + F[5] * cv.y + F[6] * cv.z + F[7];
+        o[2] = F[8] * cv.x + F[9] * cv.y + F[10] * cv.z + F[11];
       }
     }
   }
-  return links > 0.0 ? tests / links : 0.0;
+  return out;
 }
 
 struct Blob {
@@ -597,22 +590,18 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
     return std::max(1e-4, std::min(std::sqrt(eps), eps / (2.0 * std::max(rc_min, 1e-30))));
   };
   const double delta = delta_for(obs_r);
-  // rows per link padded to a multiple of eight (the tile kernel tests two
-  // groups of four per step), plus one group past the last link's rows, which
-  // the kernel's prefetch of the next group may read
-  const int NS = env->n_spheres, NB = env->n_boxes, NO = NS + NB, NO4 = std::max(8, (NO + 7) & ~7);
-  // bounding sphere of every obstacle in table order (spheres, then boxes):
-  // centre (single precision) and radius
+  // bounding sphere of every obstacle (spheres, then boxes): centre (single
+  // precision) and radius
+  const int NS = env->n_spheres, NB = env->n_boxes, NO = NS + NB;
   std::vector<float4> bound(std::max(1, NO));
   std::vector<double> bound_r(std::max(1, NO));
-  auto make_bounds = [&](const std::vector<float4> &es, const std::vector<float4> &eb, std::vector<float4> &cen,
-                         std::vector<double> &rad) {
+  {
     for (int k = 0; k < NS; ++k) {
-      cen[k] = es[k];
-      rad[k] = (double)es[k].w;
+      bound[k] = env_s[k];
+      bound_r[k] = (double)env_s[k].w;
     }
     for (int k = 0; k < NB; ++k) {
-      const float4 lo = eb[2 * k], hi = eb[2 * k + 1];
+      const float4 lo = env_b[2 * k], hi = env_b[2 * k + 1];
       const float mx = 0.5f * (lo.x + hi.x), my = 0.5f * (lo.y + hi.y), mz = 0.5f * (lo.z + hi.z);
       // radius from the rounded centre to the farthest corner
       double far = 0.0;
@@ -623,106 +612,16 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
                          dz = (double)(cz ? hi.z : lo.z) - mz;
             far = std::max(far, std::sqrt(dx * dx + dy * dy + dz * dz));
           }
-      cen[NS + k] = float4{mx, my, mz, 0.f};
-      rad[NS + k] = far;
-    }
-  };
-  make_bounds(env_s, env_b, bound, bound_r);
-
-  // Obstacle clusters.  The spheres and the boxes each go along a Morton
-  // curve (in the device arrays only: an obstacle's index is internal to the
-  // tables), so that runs of consecutive obstacles are compact; cluster c
-  // holds table rows kClusterSize c .. kClusterSize c + kClusterSize - 1.
-  // Its sphere (centre the mean of the members' bounding centres, radius
-  // reaching past every member's bounding sphere) contains every member, so
-  // a link that touches a member passes its cluster's test.  The rows take
-  // the expanded form with delta recomputed for the larger radii, padded like
-  // the member rows.  The scene keeps the input order and one level when the
-  // estimate says the clusters do not pay.
-  int NC = 0, NC4 = 0;
-  std::vector<float4> cc;
-  std::vector<double> cr;
-  double delta_c = 0.0;
-  if (NO >= kClusterMinObstacles) {
-    std::vector<float4> ps(env_s), pb(env_b);
-    if (NS > 1) {
-      const std::vector<int> ord = morton_order(env_s, NS);
-      for (int k = 0; k < NS; ++k) ps[k] = env_s[ord[k]];
-    }
-    if (NB > 1) {
-      std::vector<float4> mid(NB);
-      for (int k = 0; k < NB; ++k)
-        mid[k] = float4{0.5f * (env_b[2 * k].x + env_b[2 * k + 1].x), 0.5f * (env_b[2 * k].y + env_b[2 * k + 1].y),
-                        0.5f * (env_b[2 * k].z + env_b[2 * k + 1].z), 0.f};
-      const std::vector<int> ord = morton_order(mid, NB);
-      for (int k = 0; k < NB; ++k) {
-        pb[2 * k] = env_b[2 * ord[k]];
-        pb[2 * k + 1] = env_b[2 * ord[k] + 1];
-      }
-    }
-    std::vector<float4> pbound(bound.size());
-    std::vector<double> pbound_r(bound_r.size());
-    make_bounds(ps, pb, pbound, pbound_r);
-    const int nc = (NO + kClusterSize - 1) / kClusterSize;
-    cc.assign(nc, float4{0.f, 0.f, 0.f, 0.f});
-    cr.assign(nc, 0.0);
-    double cr_max = 0.0;
-    for (int c = 0; c < nc; ++c) {
-      const int k0 = c * kClusterSize, k1 = std::min(NO, k0 + kClusterSize);
-      double s[3] = {0, 0, 0};
-      for (int k = k0; k < k1; ++k) { s[0] += pbound[k].x; s[1] += pbound[k].y; s[2] += pbound[k].z; }
-      cc[c] = float4{(float)(s[0] / (k1 - k0)), (float)(s[1] / (k1 - k0)), (float)(s[2] / (k1 - k0)), 0.f};
-      for (int k = k0; k < k1; ++k) {
-        const double dx = (double)pbound[k].x - cc[c].x, dy = (double)pbound[k].y - cc[c].y,
-                     dz = (double)pbound[k].z - cc[c].z;
-        cr[c] = std::max(cr[c], std::sqrt(dx * dx + dy * dy + dz * dz) + pbound_r[k]);
-      }
-      cr_max = std::max(cr_max, cr[c]);
-    }
-    delta_c = delta_for(std::max(obs_r, cr_max));
-    if (cluster_tests_per_link(robots, n_robots, model_of, dh, th, coarse, base, cc, cr, delta_c) <=
-        kClusterGain * NO) {
-      NC = nc;
-      env_s.swap(ps);
-      env_b.swap(pb);
-      bound.swap(pbound);
-      bound_r.swap(pbound_r);
+      bound[NS + k] = float4{mx, my, mz, 0.f};
+      bound_r[NS + k] = far;
     }
   }
-  std::vector<float4> rows((size_t)M * kMaxLinks * NO4 + 4, float4{0.f, 0.f, 0.f, 3.0e38f});
-  for (int m = 0; m < M; ++m)
-    for (int l = 0; l < kMaxLinks; ++l) {
-      const float4 cv = coarse[(size_t)m * kMaxLinks + l];
-      if (cv.w < 0 || l > models[m]->n_joints) continue;
-      for (int k = 0; k < NO; ++k) {
-        const float4 o = bound[k];
-        const double o2 = (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z;
-        const double R = (double)cv.w + bound_r[k] + delta;
-        rows[((size_t)m * kMaxLinks + l) * NO4 + k] = float4{-2.f * o.x, -2.f * o.y, -2.f * o.z, (float)(o2 - R * R)};
-      }
-    }
-  std::vector<float4> crows(1, float4{0.f, 0.f, 0.f, 3.0e38f});
-  if (NC > 0) {
-    NC4 = std::max(8, (NC + 7) & ~7);
-    crows.assign((size_t)M * kMaxLinks * NC4 + 4, float4{0.f, 0.f, 0.f, 3.0e38f});
-    for (int m = 0; m < M; ++m)
-      for (int l = 0; l < kMaxLinks; ++l) {
-        const float4 cv = coarse[(size_t)m * kMaxLinks + l];
-        if (cv.w < 0 || l > models[m]->n_joints) continue;
-        for (int c = 0; c < NC; ++c) {
-          const float4 o = cc[c];
-          const double o2 = (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z;
-          const double R = (double)cv.w + cr[c] + delta_c;
-          crows[((size_t)m * kMaxLinks + l) * NC4 + c] = float4{-2.f * o.x, -2.f * o.y, -2.f * o.z, (float)(o2 - R * R)};
-        }
-      }
-  }
 
-  // Arm pairs and, per pair, the link pairs that can touch: link l's coarse
-  // sphere stays within reach(l) = sum_{j <= l} |(a_{j-1}, d_j)| + |c_l| + r_l
-  // of its arm's base origin in every configuration, so links a, b of arms i,
-  // j never meet when the bases are farther apart than reach_i(a) +
-  // reach_j(b).  Bit a * 8 + b of a pair's mask marks a possible link pair.
+  // Reach of every link: its coarse sphere stays within reach(l) =
+  // sum_{j <= l} |(a_{j-1}, d_j)| + |c_l| + r_l of its arm's base origin in
+  // every configuration (a joint step moves the frame's origin by
+  // (a, -d sin alpha, d cos alpha), of length |(a, d)|; c_l is the coarse
+  // centre in the link's frame).
   std::vector<double> link_reach((size_t)M * kMaxLinks, -1.0);
   for (int m = 0; m < M; ++m) {
     const mrpop_robot &rb = *models[m];
@@ -735,6 +634,115 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
           chain + std::sqrt((double)cv.x * cv.x + (double)cv.y * cv.y + (double)cv.z * cv.z) + (double)cv.w + 1e-3;
     }
   }
+
+  // Per-(arm, link) obstacle lists.  Link l of arm r can touch obstacle k
+  // only if k's bounding sphere comes within reach(l) of the arm's base
+  // origin, so each list keeps just those obstacles, in Morton order of their
+  // bounding centres (10 bits per axis over the obstacles' bounding box).
+  // Each list's rows are padded to a multiple of eight with never-passing
+  // rows, and row_obs names each row's obstacle.  A list of at least
+  // kClusterMinObstacles obstacles may also get clusters: every eight
+  // consecutive rows form one, whose sphere (centre the mean of the
+  // members' bounding centres, radius reaching past every member's bounding
+  // sphere) contains every member, so a link that touches a member passes
+  // the cluster's test.  Cluster rows take the same expanded form, with
+  // delta recomputed for the larger radii.  A list keeps its clusters only
+  // when the estimated tests per link with them (one per cluster plus eight
+  // per cluster that passes, over the link's centres at seeded random
+  // configurations) are at most kClusterGain of its length.
+  std::vector<int> order(NO);
+  std::iota(order.begin(), order.end(), 0);
+  if (NO > 1) order = morton_order(bound, NO);
+  const int n_samples = 128;
+  std::vector<double> centres;
+  bool sampled = false;
+  std::vector<int32_t> lists((size_t)n_robots * kMaxLinks * 8, 0);
+  std::vector<float4> rows, crows;
+  std::vector<int32_t> row_obs;
+  const float4 never{0.f, 0.f, 0.f, 3.0e38f};
+  int64_t NC = 0;
+  std::vector<int> L;
+  for (int r = 0; r < n_robots; ++r) {
+    const int m = model_of[r];
+    const double bx = base[(size_t)r * 12 + 3], by = base[(size_t)r * 12 + 7], bz = base[(size_t)r * 12 + 11];
+    for (int l = 0; l < kMaxLinks; ++l) {
+      int32_t *meta = &lists[((size_t)r * kMaxLinks + l) * 8];
+      meta[0] = (int32_t)rows.size();
+      meta[3] = (int32_t)crows.size();
+      const float4 cv = coarse[(size_t)m * kMaxLinks + l];
+      if (cv.w < 0 || l > models[m]->n_joints) continue;
+      const double reach_l = link_reach[(size_t)m * kMaxLinks + l];
+      L.clear();
+      for (int k : order) {
+        const double dx = (double)bound[k].x - bx, dy = (double)bound[k].y - by, dz = (double)bound[k].z - bz;
+        if (std::sqrt(dx * dx + dy * dy + dz * dz) <= reach_l + bound_r[k] + kReachMargin) L.push_back(k);
+      }
+      const int n = (int)L.size(), n8 = (n + 7) & ~7;
+      for (int k : L) {
+        const float4 o = bound[k];
+        const double o2 = (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z;
+        const double R = (double)cv.w + bound_r[k] + delta;
+        rows.push_back(float4{-2.f * o.x, -2.f * o.y, -2.f * o.z, (float)(o2 - R * R)});
+        row_obs.push_back(k);
+      }
+      rows.resize((size_t)meta[0] + n8, never);
+      row_obs.resize((size_t)meta[0] + n8, 0);
+      meta[1] = n8;
+      meta[2] = n;
+      if (n < kClusterMinObstacles) continue;
+      const int nc = (n + kClusterSize - 1) / kClusterSize;
+      std::vector<float4> cc(nc);
+      std::vector<double> cr(nc, 0.0);
+      double cr_max = 0.0;
+      for (int c = 0; c < nc; ++c) {
+        const int i0 = c * kClusterSize, i1 = std::min(n, i0 + kClusterSize);
+        double sx = 0, sy = 0, sz = 0;
+        for (int i = i0; i < i1; ++i) { sx += bound[L[i]].x; sy += bound[L[i]].y; sz += bound[L[i]].z; }
+        cc[c] = float4{(float)(sx / (i1 - i0)), (float)(sy / (i1 - i0)), (float)(sz / (i1 - i0)), 0.f};
+        for (int i = i0; i < i1; ++i) {
+          const float4 o = bound[L[i]];
+          const double dx = (double)o.x - cc[c].x, dy = (double)o.y - cc[c].y, dz = (double)o.z - cc[c].z;
+          cr[c] = std::max(cr[c], std::sqrt(dx * dx + dy * dy + dz * dz) + bound_r[L[i]]);
+        }
+        cr_max = std::max(cr_max, cr[c]);
+      }
+      const double delta_c = delta_for(std::max(obs_r, cr_max));
+      if (!sampled) {
+        centres = sample_link_centres(robots, n_robots, model_of, dh, th, coarse, base, n_samples);
+        sampled = true;
+      }
+      const int S = std::max(8, std::min(n_samples, 250000 / nc));
+      double tests = 0.0;
+      for (int k = 0; k < S; ++k) {
+        const double *x = &centres[(((size_t)r * kMaxLinks + l) * n_samples + k) * 3];
+        tests += nc;
+        for (int c = 0; c < nc; ++c) {
+          const double dx = x[0] - cc[c].x, dy = x[1] - cc[c].y, dz = x[2] - cc[c].z;
+          const double R = (double)cv.w + cr[c] + delta_c;
+          if (dx * dx + dy * dy + dz * dz < R * R) tests += kClusterSize;
+        }
+      }
+      if (tests / S > kClusterGain * n) continue;
+      for (int c = 0; c < nc; ++c) {
+        const float4 o = cc[c];
+        const double o2 = (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z;
+        const double R = (double)cv.w + cr[c] + delta_c;
+        crows.push_back(float4{-2.f * o.x, -2.f * o.y, -2.f * o.z, (float)(o2 - R * R)});
+      }
+      crows.resize((size_t)meta[3] + ((nc + 7) & ~7), never);
+      meta[4] = (nc + 7) & ~7;
+      meta[5] = nc;
+      NC += nc;
+    }
+  }
+  // one group of padding past the last list (the prefetch of the next group)
+  rows.resize(rows.size() + 4, never);
+  row_obs.resize(row_obs.size() + 4, 0);
+  crows.resize(crows.size() + 4, never);
+
+  // Arm pairs and, per pair, the link pairs that can touch: links a, b of
+  // arms i, j never meet when the bases are farther apart than reach_i(a) +
+  // reach_j(b).  Bit a * 8 + b of a pair's mask marks a possible link pair.
   std::vector<int32_t> pairs;
   std::vector<uint64_t> pair_links;
   for (int i = 0; i < n_robots; ++i)
@@ -783,7 +791,9 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   size_t o_coarse = blob.add(coarse.data(), sizeof(float4) * coarse.size());
   size_t o_es = blob.add(env_s.data(), sizeof(float4) * env_s.size());
   size_t o_eb = blob.add(env_b.data(), sizeof(float4) * env_b.size());
+  size_t o_lists = blob.add(lists.data(), sizeof(int32_t) * lists.size());
   size_t o_rows = blob.add(rows.data(), sizeof(float4) * rows.size());
+  size_t o_robs = blob.add(row_obs.data(), sizeof(int32_t) * row_obs.size());
   size_t o_crows = blob.add(crows.data(), sizeof(float4) * crows.size());
   size_t o_pairs = blob.add(pairs.data(), sizeof(int32_t) * pairs.size());
   size_t o_plinks = blob.add(pair_links.data(), sizeof(uint64_t) * pair_links.size());
@@ -836,11 +846,11 @@ mrpop_status mrpop_scene_create(mrpop_ctx *ctx, const mrpop_robot *robots, int32
   d.env_s = (const float4 *)at(o_es);
   d.env_b = (const float4 *)at(o_eb);
   d.origin = float3{(float)org[0], (float)org[1], (float)org[2]};
+  d.link_lists = (const int32_t *)at(o_lists);
   d.rows = (const float4 *)at(o_rows);
-  d.n_rows4 = NO4;
+  d.row_obs = (const int32_t *)at(o_robs);
   d.crows = (const float4 *)at(o_crows);
-  d.n_clusters = NC;
-  d.n_crows4 = NC4;
+  d.n_clusters = (int32_t)std::min<int64_t>(NC, INT32_MAX);
   d.n_pairs = n_pairs;
   d.pair_links = (const uint64_t *)at(o_plinks);
   d.pairs = (const int32_t *)at(o_pairs);

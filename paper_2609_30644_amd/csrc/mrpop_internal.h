@@ -51,30 +51,31 @@ struct SceneDev {
   const float4 *env_s;     // [Ns] x, y, z, r (recentred)
   const float4 *env_b;     // [Nb][2] (lo x, lo y, lo z, 0), (hi x, hi y, hi z, 0) (recentred)
   float3 origin;           // world = recentred + origin
-  // Coarse filter rows in expanded form.  For link l of model m and
-  // obstacle k (environment spheres first, then the bounding spheres of the
-  // boxes), the coarse sphere (centre c, radius rc) can touch the obstacle's
-  // bounding sphere (centre o, radius s) only if
-  //   |c|^2 - 2 c.o + |o|^2 - (rc + s + delta)^2 < 0.
-  // rows[m][l][k] = (-2 o_x, -2 o_y, -2 o_z, w) with w = |o|^2 - (rc + s +
-  // delta)^2, so that each test is three FMAs from |c|^2 and a compare
-  // against -w.  delta bounds the single-precision error of the expanded form
-  // over the scene's extent, so the filter never drops a contact; links a
-  // model lacks get w = +3e38.
-  // Rows of each link are padded with never-passing entries (w = +3e38) to
-  // n_rows4, a multiple of eight, so that the kernel reads them in pairs of
-  // groups of four; one more group of padding follows the last link.
-  int32_t n_rows4;
-  const float4 *rows;      // [M][kMaxLinks][n_rows4]
-  // Cluster level of the filter (scenes with many obstacles; n_clusters = 0
-  // otherwise): cluster c covers rows kClusterSize c onwards, and crows[m][l][c] holds
-  // the same expanded test for a sphere containing every member's bounding
-  // sphere (with its own delta), so a link that touches a member obstacle
-  // passes the cluster's test.  Padded to n_crows4 (a multiple of eight)
-  // plus one group, like the rows.
-  int32_t n_clusters;
-  int32_t n_crows4;
-  const float4 *crows;     // [M][kMaxLinks][n_crows4]
+  // Coarse filter rows in expanded form, one list per (arm, link).  The
+  // coarse sphere (centre c, radius rc) can touch an obstacle's bounding
+  // sphere (centre o, radius s) only if
+  //   |c|^2 - 2 c.o + |o|^2 - (rc + s + delta)^2 < 0,
+  // so a row holds (-2 o_x, -2 o_y, -2 o_z, w) with w = |o|^2 - (rc + s +
+  // delta)^2: each test is three FMAs from |c|^2 and a compare against -w.
+  // delta bounds the single-precision error of the expanded form over the
+  // scene's extent, so the filter never drops a contact.  A list holds only
+  // the obstacles within the link's reach of its arm's base (the others can
+  // never be touched), padded with never-passing rows (w = +3e38) to a
+  // multiple of eight, as the kernel reads them in pairs of groups of four;
+  // one more group of padding follows the last list.  row_obs gives each
+  // row's obstacle: k < n_env_spheres is sphere k, otherwise box
+  // k - n_env_spheres.
+  // Lists of many obstacles may also have a cluster level: cluster c covers
+  // rows kClusterSize c onwards, and its row holds the same expanded test for
+  // a sphere containing every member's bounding sphere (with its own delta),
+  // so a link that touches a member obstacle passes the cluster's test.
+  // link_lists[r][l] = {row offset, rows (padded), obstacles, cluster-row
+  // offset, cluster rows (padded), clusters (0: one level), 0, 0}.
+  const int32_t *link_lists;  // [R][kMaxLinks][8]
+  const float4 *rows;
+  const int32_t *row_obs;
+  const float4 *crows;
+  int32_t n_clusters;         // clusters over all lists
   const float *q_lo, *q_hi;  // [D] composite joint limits
   // Arm pairs (i < j) whose bases are close enough for contact; other pairs
   // can never touch (every sphere stays within its arm's reach bound).

@@ -410,35 +410,24 @@ constexpr int kQueueCap = kQueueFlushAt + kGroup * kWave;
 constexpr int kWaveLdsFloats = 12 * kWave + kQueueCap;
 static_assert(kClusterSize == 2 * kGroup, "a cluster's rows are two groups");
 
-// Scene data the tile kernel reads inside its loops: coarse rows, obstacle
-// spheres and boxes, fine spheres, link ranges and coarse radii.  The coarse
-// rows, the same for every lane, always come through the scalar cache.
-// STAGED: the data read at lane-varying indices (obstacles, fine spheres,
-// link ranges, radii) is copied to LDS once per persistent workgroup.
-// Otherwise: the scene arrays themselves.
+// Scene data the tile kernel reads at lane-varying indices inside its loops:
+// obstacle spheres and boxes, fine spheres, link ranges and coarse radii.
+// STAGED: copied to LDS once per persistent workgroup.  Otherwise: the scene
+// arrays themselves.  (The coarse filter rows, the same for every lane,
+// always come through the scalar cache: from LDS each read would write them
+// into every lane's registers, which costs more LDS bandwidth than the tests
+// they feed.)
 template <bool STAGED>
 struct Src;
 
 template <>
 struct Src<true> {
-  cptr<float4> rows;     // [M][kMaxLinks][n4], read through the scalar cache
-  cptr<float4> crows;    // [M][kMaxLinks][nc4], likewise
   const float4 *env_s;   // [Ns]
   const float4 *boxes;   // [Nb][2]
   const float4 *fine;    // [M][sph_stride]
   const int32_t *lstart; // [M][kMaxLinks + 1]
   const float *crad;     // [M][kMaxLinks]
-  int ns, nb, n4, stride, nc, nc4;
-  // the rows of link l, read kGroup at a time (one 64-byte scalar load each).
-  // The rows are the same for every lane; from LDS each read would write them
-  // into every lane's registers, which costs more LDS bandwidth than the
-  // tests they feed.
-  __device__ cptr<float> link_rows(int m, int l) const {
-    return (cptr<float>)(rows + ((int64_t)m * kMaxLinks + l) * n4);
-  }
-  __device__ cptr<float> link_crows(int m, int l) const {
-    return (cptr<float>)(crows + ((int64_t)m * kMaxLinks + l) * nc4);
-  }
+  int ns, nb, stride;
   __device__ float4 sphere(int k) const { return env_s[k]; }
   __device__ float4 box(int i) const { return boxes[i]; }
   __device__ float4 sph(int m, int i) const { return fine[m * stride + i]; }
@@ -448,16 +437,10 @@ struct Src<true> {
 
 template <>
 struct Src<false> {
-  cptr<float4> rows, crows, fine, coarse;
+  cptr<float4> fine, coarse;
   const float4 *env_s, *boxes;  // read at lane-varying indices
   cptr<int32_t> lstart;
-  int ns, nb, n4, stride, nc, nc4;
-  __device__ cptr<float> link_rows(int m, int l) const {
-    return (cptr<float>)(rows + ((int64_t)m * kMaxLinks + l) * n4);
-  }
-  __device__ cptr<float> link_crows(int m, int l) const {
-    return (cptr<float>)(crows + ((int64_t)m * kMaxLinks + l) * nc4);
-  }
+  int ns, nb, stride;
   __device__ float4 sphere(int k) const { return env_s[k]; }
   __device__ float4 box(int i) const { return boxes[i]; }
   __device__ float4 sph(int m, int i) const { return ld4(fine, (int64_t)m * stride + i); }
@@ -482,13 +465,8 @@ __device__ Src<true> make_src<true>(const SceneDev &sc, float *stage) {
   Src<true> s;
   s.ns = sc.n_env_spheres;
   s.nb = sc.n_env_boxes;
-  s.n4 = sc.n_rows4;
   s.stride = sc.sph_stride;
   float4 *p = (float4 *)stage;
-  s.rows = as_const(sc.rows);
-  s.crows = as_const(sc.crows);
-  s.nc = sc.n_clusters;
-  s.nc4 = sc.n_crows4;
   s.env_s = p;
   for (int i = threadIdx.x; i < s.ns; i += blockDim.x) p[i] = sc.env_s[i];
   p += s.ns;
@@ -511,10 +489,6 @@ __device__ Src<true> make_src<true>(const SceneDev &sc, float *stage) {
 template <>
 __device__ Src<false> make_src<false>(const SceneDev &sc, float *) {
   Src<false> s;
-  s.rows = as_const(sc.rows);
-  s.crows = as_const(sc.crows);
-  s.nc = sc.n_clusters;
-  s.nc4 = sc.n_crows4;
   s.env_s = sc.env_s;
   s.boxes = sc.env_b;
   s.fine = as_const(sc.fine);
@@ -522,7 +496,6 @@ __device__ Src<false> make_src<false>(const SceneDev &sc, float *) {
   s.lstart = as_const(sc.link_start);
   s.ns = sc.n_env_spheres;
   s.nb = sc.n_env_boxes;
-  s.n4 = sc.n_rows4;
   s.stride = sc.sph_stride;
   return s;
 }
@@ -598,19 +571,23 @@ __device__ void flush_queue(const Src<STAGED> &src, int m, int l, float4 cs, con
 // Environment tests of link l of arm r (model m) at every lane's state, given
 // the link's frame F and its coarse centre c (both at the lane's own state):
 // the frame goes to the wave's LDS slot, the coarse sphere is tested against
-// every obstacle in expanded form (three FMAs and a compare), flagged (lane,
+// the obstacles of the link's list (those within its reach of the arm's
+// base) in expanded form (three FMAs and a compare), flagged (lane,
 // obstacle) pairs are queued and get their fine tests one pair per lane.
 // Returns the lanes whose state collides; their edges are marked in *dead.
 template <bool STAGED>
-__device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int l, const Frame &F, float3 c,
+__device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int r, int m, int l, const Frame &F, float3 c,
                          bool live, uint64_t emask, float *fr, uint32_t *queue, unsigned long long *hitw,
                          unsigned long long *dead, int lane, WorkCount &wc) {
-  const int N = src.ns + src.nb;
   const float4 cs = ld4(as_const(sc.coarse), m * kMaxLinks + l);
   if (cs.w < 0.f) return false;  // a link without spheres
+  // the link's list: row offset, rows (padded), obstacles, cluster-row
+  // offset, cluster rows (padded), clusters
+  const cptr<int32_t> meta = as_const(sc.link_lists) + (r * kMaxLinks + l) * 8;
+  const int row0 = meta[0], n8 = meta[1], N = meta[2], crow0 = meta[3], nc8 = meta[4], nc = meta[5];
   if (live) {
     ++wc.links;
-    wc.env_tests += src.nc > 0 ? src.nc : N;  // (with clusters, member rows are counted as they are tested)
+    wc.env_tests += nc > 0 ? nc : N;  // (with clusters, member rows are counted as they are tested)
   }
   if (N == 0) return false;
   const float c2 = fmaf(c.z, c.z, fmaf(c.y, c.y, c.x * c.x));
@@ -621,9 +598,11 @@ __device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int 
   fr[9 * kWave + lane] = F.r21; fr[10 * kWave + lane] = F.r22; fr[11 * kWave + lane] = F.t2;
   const float4 csr = make_float4(cs.x, cs.y, cs.z, src.rad(m, l));
   const uint64_t livem = __builtin_amdgcn_ballot_w64(live);
+  const cptr<int32_t> obs = as_const(sc.row_obs) + row0;
   int qn = 0;  // wave-uniform queue length
-  // one group of kGroup obstacles: the coarse tests, and the flagged pairs
-  // queued (flushed once the queue is long enough)
+  // one group of kGroup rows (k0 onwards in the list): the coarse tests, and
+  // the flagged pairs queued with the row's obstacle (flushed once the queue
+  // is long enough)
   auto group_tests = [&](const float4 (&rw)[kGroup], int k0) {
     bool h[kGroup];
     uint64_t b[kGroup], any = 0;
@@ -641,7 +620,7 @@ __device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int 
       if (bi == 0ull) continue;
       if (h[i] && live)
         queue[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(bi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bi, 0u))] =
-            (uint32_t)lane | ((uint32_t)(k0 + i) << 6);
+            (uint32_t)lane | ((uint32_t)obs[k0 + i] << 6);
       qn += __popcll(bi);
     }
     if (qn > kQueueFlushAt) {
@@ -651,25 +630,24 @@ __device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int 
   };
   // Two groups per step over two row buffers, software-pipelined: each
   // group's scalar load is in flight while the group before it is tested.
-  // n4 is a multiple of 2 kGroup; the last step's prefetch reads the group
-  // that follows the link's rows (the next link's, or the padding after the
-  // last link) and leaves it unused.
+  // n8 is a multiple of 2 kGroup; the last step's prefetch reads the group
+  // that follows the list's rows (the next list's, or the padding after the
+  // last list) and leaves it unused.
   auto load = [](cptr<float> p, float4 (&r)[kGroup]) {
 #pragma unroll
     for (int i = 0; i < kGroup; ++i) r[i] = make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
   };
-  cptr<float> p = src.link_rows(m, l);
+  cptr<float> p = (cptr<float>)(as_const(sc.rows) + row0);
   float4 ra[kGroup], rb[kGroup];
-  if (src.nc == 0) {
+  if (nc == 0) {
     load(p, ra);
-    for (int k0 = 0; k0 < src.n4; k0 += 2 * kGroup) {
-      load(p + 4 * kGroup, rb);
+    for (int k0 = 0; k0 < n8; k0 += 2 * kGroup) {
+      load(p + 4 * (k0 + kGroup), rb);
       __builtin_amdgcn_sched_barrier(0);  // keep each load ahead of the tests it overlaps
       group_tests(ra, k0);
-      load(p + 8 * kGroup, ra);
+      load(p + 4 * (k0 + 2 * kGroup), ra);
       __builtin_amdgcn_sched_barrier(0);
       group_tests(rb, k0 + kGroup);
-      p += 8 * kGroup;
     }
   } else {
     // Clusters in chunks of 64: first the chunk's cluster rows, in the same
@@ -684,9 +662,9 @@ __device__ bool link_env(const SceneDev &sc, const Src<STAGED> &src, int m, int 
         if (__builtin_amdgcn_ballot_w64(t < -cw[i].w) & livem) pm |= 1ull << (i0 + i);
       }
     };
-    cptr<float> pc = src.link_crows(m, l);
-    for (int ch = 0; ch < src.nc4; ch += 64) {
-      const int n_ch = min(64, src.nc4 - ch);  // a multiple of 2 kGroup
+    cptr<float> pc = (cptr<float>)(as_const(sc.crows) + crow0);
+    for (int ch = 0; ch < nc8; ch += 64) {
+      const int n_ch = min(64, nc8 - ch);  // a multiple of 2 kGroup
       uint64_t pm = 0;
       load(pc, ra);
       for (int i0 = 0; i0 < n_ch; i0 += 2 * kGroup) {
@@ -767,7 +745,7 @@ __device__ bool arm_env(const SceneDev &sc, const Src<STAGED> &src, int r, int m
     if (l % S != part) return true;  // another wave tests this link
     live = live && !((dead_mask(dead) >> lane) & 1ull);
     if (__ballot(live) == 0ull) return false;  // nothing left to test in this wave
-    if (link_env<STAGED>(sc, src, m, l, F, c, live, emask, fr, queue, hitw, dead, lane, wc)) {
+    if (link_env<STAGED>(sc, src, r, m, l, F, c, live, emask, fr, queue, hitw, dead, lane, wc)) {
       hit = true;
       live = false;
     }
@@ -1071,7 +1049,7 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
       slot[0] = c.x;
       slot[kWave] = c.y;
       slot[2 * kWave] = c.z;
-      if (link_env<STAGED>(sc, src, m, l, F, c, live, tl.emask, wave_fr, wave_q, &s_hit[w], dead, lane, wc))
+      if (link_env<STAGED>(sc, src, r, m, l, F, c, live, tl.emask, wave_fr, wave_q, &s_hit[w], dead, lane, wc))
         hit = true;
     }
   } else {

@@ -213,15 +213,15 @@ def _sparse_mix(ns, nb, seed):
     return problem("c2").scene.with_env(sph, box)
 
 
-@pytest.mark.parametrize("kind,ns,nb,clusters", [("shelf", 37, 210, True), ("shelf", 64, 0, True),
+@pytest.mark.parametrize("kind,ns,nb,clusters", [("shelf", 37, 210, True), ("shelf", 200, 0, True),
                                                   ("shelf", 0, 256, True), ("sparse", 50, 47, False)])
-def test_validate_obstacle_clusters(ctx, kind, ns, nb, clusters):
-    """From 64 obstacles on, a scene whose obstacles are dense enough tests
-    clusters of eight before their members (spheres and boxes each in Morton
-    order: here a ragged last cluster and one holding both kinds, exactly 64
-    spheres, and the full shelf grid); a sparse one keeps one level.  The bits
-    equal the oracle's either way, and with clusters fewer coarse tests run
-    than one per link and obstacle."""
+def test_validate_obstacle_lists(ctx, kind, ns, nb, clusters):
+    """Each link tests only the obstacles within its reach of its arm's base,
+    and a long list of dense obstacles first tests clusters of eight (in
+    Morton order: here spheres and boxes mixed in one list, ragged last
+    clusters, and the full shelf grid), while a sparse scene keeps one level.
+    The bits equal the oracle's either way, and fewer coarse tests run than
+    one per link and obstacle."""
     seed = ns * 1000 + nb
     sc = _shelf_mix(ns, nb, seed) if kind == "shelf" else _sparse_mix(ns, nb, seed)
     res = 0.02 if kind == "shelf" else 0.05
@@ -233,15 +233,12 @@ def test_validate_obstacle_clusters(ctx, kind, ns, nb, clusters):
                                spread=0.02 if kind == "shelf" else 0.3)
     n_clusters = _scene(ctx, sc).obstacle_clusters
     print(f"[clusters] {kind} {ns}+{nb}: {n_clusters} clusters", flush=True)
-    assert n_clusters == ((ns + nb + 7) // 8 if clusters else 0)
+    assert (n_clusters > 0) == clusters
     valid, m, st = _parity(ctx, sc, qa, qb, res, f"{kind} env {ns}+{nb}")
     assert (m < -BAND).any() and (m > BAND).any()
     w = st.work
     print(f"  coarse tests {w['env_tests']} links {w['links']} per link {w['env_tests'] / w['links']:.1f}", flush=True)
-    if clusters:
-        assert w["env_tests"] < w["links"] * (ns + nb)
-    else:
-        assert w["env_tests"] == w["links"] * (ns + nb)
+    assert w["env_tests"] < w["links"] * (ns + nb)
 
 
 def test_validate_no_obstacles_arm_pairs_only(ctx):

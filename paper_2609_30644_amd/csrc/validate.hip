@@ -1075,25 +1075,56 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
   __syncthreads();
 }
 
+// One DPP move of a 64-bit value (both halves): lane i takes the value the
+// control selects (0 where the source lies outside its row), in the rows of
+// ROWS; the other rows take 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROWS, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROWS, 0xf, true);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Sum of v over the wave, in every lane, without LDS: an inclusive scan
+// within each row of 16 lanes (row_shr 1, 2, 4, 8), then the rows' totals
+// carried by row_bcast:15 (into rows 1 and 3) and row_bcast:31 (into rows 2
+// and 3), so that lane 63 holds the sum; it is then read out uniformly.
+// Every lane of the wave must be active.
+__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
+  x += dpp64<0x111, 0xf>(x);
+  x += dpp64<0x112, 0xf>(x);
+  x += dpp64<0x114, 0xf>(x);
+  x += dpp64<0x118, 0xf>(x);
+  x += dpp64<0x142, 0xa>(x);
+  x += dpp64<0x143, 0xc>(x);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, kWave - 1);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), kWave - 1);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Workgroup totals of the work counters, one slot row per workgroup (summed
-// by the final kernel; no device-wide atomics).
+// by the final step; no device-wide atomics).  Each wave's sums go to its
+// own row of `scratch` (LDS free by now, at least W kPartialSlots words), so
+// no LDS atomics contend; one barrier, then one thread per slot adds the
+// rows.
 __device__ void write_partials(uint64_t *partials, uint32_t checked, uint32_t tiles, const WorkCount &wc, int w,
-                               int lane) {
-  __shared__ unsigned long long s_part[kPartialSlots];
-  if (threadIdx.x < kPartialSlots) s_part[threadIdx.x] = 0ull;
-  __syncthreads();
-  uint64_t v[kPartialSlots - 1] = {checked,      wc.chains, wc.links,  wc.env_tests, wc.box_exact,
-                                   wc.rr_coarse, wc.fine_s, wc.fine_b, wc.fine_rr};
+                               int W, int lane, unsigned long long *scratch) {
+  const uint32_t v[kPartialSlots - 1] = {checked,      wc.chains, wc.links,  wc.env_tests, wc.box_exact,
+                                         wc.rr_coarse, wc.fine_s, wc.fine_b, wc.fine_rr};
+  uint64_t sum[kPartialSlots - 1];
 #pragma unroll
-  for (int i = 0; i < kPartialSlots - 1; ++i)
-    for (int d = kWave / 2; d > 0; d >>= 1) v[i] += __shfl_xor(v[i], d, kWave);
+  for (int i = 0; i < kPartialSlots - 1; ++i) sum[i] = wave_sum(v[i]);
   if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < kPartialSlots - 1; ++i) atomicAdd(&s_part[i], (unsigned long long)v[i]);
-    if (w == 0) atomicAdd(&s_part[kPartialSlots - 1], (unsigned long long)tiles);
+    for (int i = 0; i < kPartialSlots - 1; ++i) scratch[w * kPartialSlots + i] = sum[i];
+    scratch[w * kPartialSlots + kPartialSlots - 1] = w == 0 ? tiles : 0u;
   }
   __syncthreads();
-  if (threadIdx.x < kPartialSlots) partials[(int64_t)blockIdx.x * kPartialSlots + threadIdx.x] = s_part[threadIdx.x];
+  if (threadIdx.x < kPartialSlots) {
+    unsigned long long t = 0;
+    for (int u = 0; u < W; ++u) t += scratch[u * kPartialSlots + threadIdx.x];
+    partials[(int64_t)blockIdx.x * kPartialSlots + threadIdx.x] = t;
+  }
 }
 
 template <bool STAGED, bool CACHE>
@@ -1154,7 +1185,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
     tile_work<STAGED, CACHE>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, &s_next, wc,
                       checked, kFlagHit);
   }
-  write_partials(partials, checked, tiles, wc, w, lane);
+  write_partials(partials, checked, tiles, wc, w, W, lane, (unsigned long long *)cen);
 }
 
 // ---------------------------------------------------------------------------
@@ -1223,7 +1254,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
       tile_work<STAGED, CACHE>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, &s_next, wc,
                         checked, token);
     }
-    write_partials(partials, checked, tiles, wc, w, lane);
+    write_partials(partials, checked, tiles, wc, w, W, lane, (unsigned long long *)cen);
   } else if (threadIdx.x < kPartialSlots) {
     partials[(int64_t)blockIdx.x * kPartialSlots + threadIdx.x] = 0ull;
   }
@@ -1239,32 +1270,35 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
   __syncthreads();
   if (!s_last) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  // the last workgroup: column sums of the partials, then the bits
-  if (threadIdx.x < kPartialSlots + 3) s_sum[threadIdx.x] = 0ull;
-  __syncthreads();
-  // one (workgroup, slot) entry per thread and step, added in LDS
-  for (int64_t k = threadIdx.x; k < (int64_t)working * kPartialSlots; k += blockDim.x) {
-    const uint64_t v = partials[k];
-    if (v) atomicAdd(&s_sum[k % kPartialSlots], (unsigned long long)v);
+  // The last workgroup: column sums of the partials and the bits with their
+  // counts, every thread accumulating its share in registers; each wave's
+  // sums go to its own row of LDS (free by now), then one thread per slot
+  // adds the rows.
+  constexpr int kCols = kPartialSlots + 3;  // then invalid, non-finite, too long
+  uint64_t col[kCols] = {};
+  for (int64_t k = threadIdx.x; k < (int64_t)working; k += blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < kPartialSlots; ++i) col[i] += partials[k * kPartialSlots + i];
   }
-  uint64_t inval = 0, nonfin = 0, toolong = 0;
   for (int e = threadIdx.x; e < n_edges; e += blockDim.x) {
     const int32_t c = codes[e];
     const bool ok = c > 0 && flags[e] != token;
     out[e] = ok ? 1 : 0;
-    inval += ok ? 0 : 1;
-    nonfin += c == kCodeNonFinite ? 1 : 0;
-    toolong += c == kCodeTooLong ? 1 : 0;
+    col[kPartialSlots] += ok ? 0 : 1;
+    col[kPartialSlots + 1] += c == kCodeNonFinite ? 1 : 0;
+    col[kPartialSlots + 2] += c == kCodeTooLong ? 1 : 0;
   }
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    inval += __shfl_xor(inval, d, kWave);
-    nonfin += __shfl_xor(nonfin, d, kWave);
-    toolong += __shfl_xor(toolong, d, kWave);
+  unsigned long long *const rows = (unsigned long long *)cen;
+#pragma unroll
+  for (int i = 0; i < kCols; ++i) {
+    const uint64_t t = wave_sum(col[i]);
+    if (lane == 0) rows[w * kCols + i] = t;
   }
-  if (lane == 0) {
-    atomicAdd(&s_sum[kPartialSlots], (unsigned long long)inval);
-    atomicAdd(&s_sum[kPartialSlots + 1], (unsigned long long)nonfin);
-    atomicAdd(&s_sum[kPartialSlots + 2], (unsigned long long)toolong);
+  __syncthreads();
+  if (threadIdx.x < kCols) {
+    unsigned long long t = 0;
+    for (int u = 0; u < W; ++u) t += rows[u * kCols + threadIdx.x];
+    s_sum[threadIdx.x] = t;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1411,7 +1445,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_segment
     tile_work<false, CACHE>(sc, src, g.S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, &s_next, wc,
                      checked, kFlagHit);
   }
-  write_partials(partials, checked, tiles, wc, w, lane);
+  write_partials(partials, checked, tiles, wc, w, W, lane, (unsigned long long *)cen);
 }
 
 // Bits of every segment's edges, their invalid counts, and (block 0) the

@@ -74,6 +74,8 @@ def _parity(ctx, sc, qa, qb, res, what, n_states=None):
     info = assert_bits_match(valid, m, what)
     assert st.edge_states == int(n.sum())
     assert st.edges_invalid == int((valid == 0).sum())
+    if valid.all():  # no early exit: every state is evaluated (the kernels' work sums)
+        assert st.states_checked == st.edge_states
     print(f"  {info} states={st.edge_states} checked={st.states_checked}", flush=True)
     return valid, m, st
 
@@ -111,6 +113,29 @@ def test_validate_c2_full_batch(ctx):
     anchors = anchors[oracle.states_free(sc, anchors)]
     qa, qb = W.edge_batch_near(sc, anchors, 4096, 0.05, 102, 8, 64, spread=0.02)
     _parity(ctx, sc, qa, qb, 0.05, "c2/full")
+
+
+@pytest.mark.parametrize("kind", ["c2", "c3"])
+def test_validate_certainly_free_batch_work_sums(ctx, kind):
+    """The benchmark's certainly-free batch (4096 edges the oracle found free
+    away from the boundary band): every edge is valid, so no state exits
+    early, and the kernels' summed work counters obey their invariants:
+    every state is checked, every arm's chain runs at every state, and every
+    link with spheres is placed once per chain."""
+    import bench
+    sc, batches, fx = bench.load_workload(*((bench.FIXTURE, "scene_c2") if kind == "c2" else
+                                            (bench.C3_FIXTURE, "scene_c3")))
+    qa, qb = batches["free"]
+    res = float(fx["resolution"])
+    print(f"[free_batch] {kind}: {qa.shape[0]} edges", flush=True)
+    valid, st = _scene(ctx, sc).validate_edges(qa, qb, res, stats=True)
+    assert valid.cpu().numpy().all()
+    n = oracle.edge_nstates(qa, qb, res)
+    assert st.edge_states == int(n.sum()) == st.states_checked
+    links_per_arm = sum(1 for l in range(sc.models[0].n_joints + 1) if (sc.models[0].sphere_link == l).any())
+    w = st.work
+    assert w["chains"] == sc.n_robots * st.edge_states
+    assert w["links"] == links_per_arm * w["chains"]
 
 
 def test_validate_degenerate_edges(ctx):

@@ -141,27 +141,61 @@ __global__ __launch_bounds__(256) void count_states_kernel(const float *__restri
 // 2. exclusive prefix sum of the counts (three passes)
 // ---------------------------------------------------------------------------
 
+// One DPP move of a 64-bit value (both halves): lane i takes the value the
+// control selects (0 where the source lies outside its row), in the rows of
+// ROWS; the other rows take 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROWS, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROWS, 0xf, true);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Sum of v over the wave, in every lane, without LDS: an inclusive scan
+// within each row of 16 lanes (row_shr 1, 2, 4, 8), then the rows' totals
+// carried by row_bcast:15 (into rows 1 and 3) and row_bcast:31 (into rows 2
+// and 3), so that lane 63 holds the sum; it is then read out uniformly.
+// Every lane of the wave must be active.
+__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
+  x += dpp64<0x111, 0xf>(x);
+  x += dpp64<0x112, 0xf>(x);
+  x += dpp64<0x114, 0xf>(x);
+  x += dpp64<0x118, 0xf>(x);
+  x += dpp64<0x142, 0xa>(x);
+  x += dpp64<0x143, 0xc>(x);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, kWave - 1);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), kWave - 1);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive prefix sum over the wave, without LDS (every lane active): the
+// row shifts of wave_sum, then each row's carry from the rows below, taken
+// by row broadcasts with every row enabled and kept only in the rows that
+// receive it (lane-index selects).
+__device__ __forceinline__ uint64_t wave_inclusive_scan(uint64_t x, int lane) {
+  x += dpp64<0x111, 0xf>(x);
+  x += dpp64<0x112, 0xf>(x);
+  x += dpp64<0x114, 0xf>(x);
+  x += dpp64<0x118, 0xf>(x);
+  const int row = lane >> 4;
+  const uint64_t b15 = dpp64<0x142, 0xf>(x);  // lane 15 of the row below
+  x += (row & 1) ? b15 : 0ull;                // rows 1 and 3
+  const uint64_t b31 = dpp64<0x143, 0xf>(x);  // lane 31
+  x += row >= 2 ? b31 : 0ull;                 // rows 2 and 3
+  return x;
+}
+
 // Exclusive scan of one value per thread across the block; returns the
 // exclusive prefix and writes the block total.
 __device__ int64_t block_exclusive_scan(int64_t v, int64_t *total) {
   __shared__ int64_t wave_sums[kScanThreads / kWave];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  int64_t x = v;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int64_t y = __shfl_up(x, d, kWave);
-    if (lane >= d) x += y;
-  }
+  const int64_t x = (int64_t)wave_inclusive_scan((uint64_t)v, lane);
   if (lane == kWave - 1) wave_sums[wid] = x;
   __syncthreads();
   if (wid == 0) {
     const int nw = blockDim.x / kWave;
-    int64_t w = lane < nw ? wave_sums[lane] : 0;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int64_t y = __shfl_up(w, d, kWave);
-      if (lane >= d) w += y;
-    }
+    const int64_t w = (int64_t)wave_inclusive_scan(lane < nw ? (uint64_t)wave_sums[lane] : 0ull, lane);
     if (lane < nw) wave_sums[lane] = w;  // inclusive
   }
   __syncthreads();
@@ -1075,33 +1109,6 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
   __syncthreads();
 }
 
-// One DPP move of a 64-bit value (both halves): lane i takes the value the
-// control selects (0 where the source lies outside its row), in the rows of
-// ROWS; the other rows take 0.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROWS, 0xf, true);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROWS, 0xf, true);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Sum of v over the wave, in every lane, without LDS: an inclusive scan
-// within each row of 16 lanes (row_shr 1, 2, 4, 8), then the rows' totals
-// carried by row_bcast:15 (into rows 1 and 3) and row_bcast:31 (into rows 2
-// and 3), so that lane 63 holds the sum; it is then read out uniformly.
-// Every lane of the wave must be active.
-__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
-  x += dpp64<0x111, 0xf>(x);
-  x += dpp64<0x112, 0xf>(x);
-  x += dpp64<0x114, 0xf>(x);
-  x += dpp64<0x118, 0xf>(x);
-  x += dpp64<0x142, 0xa>(x);
-  x += dpp64<0x143, 0xc>(x);
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, kWave - 1);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), kWave - 1);
-  return ((uint64_t)hi << 32) | lo;
-}
-
 // Workgroup totals of the work counters, one slot row per workgroup (summed
 // by the final step; no device-wide atomics).  Each wave's sums go to its
 // own row of `scratch` (LDS free by now, at least W kPartialSlots words), so
@@ -1201,6 +1208,10 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
 // device-wide arrival counter) writes the bits and the counters and resets
 // the counter: one launch where the general path makes three.  Workgroups
 // never wait for each other.
+// Word of the arrival buffer (256 bytes before the flag words, zero between
+// launches) that hands out the small launches' tiles after the first.
+constexpr int kTileCounterWord = 32;
+
 template <bool STAGED, bool CACHE>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_kernel(
     SceneDev sc, const float *__restrict__ qa, const float *__restrict__ qb, int n_edges,
@@ -1213,6 +1224,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
   __shared__ int64_t s_off[kFusedMaxEdges + 1];
   __shared__ unsigned long long s_sum[kPartialSlots + 3];
   __shared__ int s_last;
+  __shared__ int64_t s_tile[2];  // the next tile, claimed during the current one (two slots, alternating)
   const int lane = threadIdx.x & (kWave - 1);
   const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave), W = blockDim.x / kWave;
   const int R = sc.n_robots;
@@ -1245,14 +1257,20 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
     uint32_t *const wave_q = (uint32_t *)(wave_fr + 12 * kWave);
     const Src<STAGED> src =
         make_src<STAGED>(sc, cen + tile_shared_floats(R, CACHE) + (size_t)W * kWaveLdsFloats);
+    // Workgroup b first takes tile b; every further tile comes from the
+    // launch's tile counter (tiles working, working + 1, ...), claimed by
+    // thread 0 while the current tile runs, so that workgroups whose tiles
+    // are light take more of them.  The last workgroup resets the counter.
     int it = 0;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x, ++it) {
+    for (int64_t tile = blockIdx.x; tile < n_tiles; ++it) {
+      if (threadIdx.x == 0) s_tile[it & 1] = (int64_t)working + atomicAdd(&arrived[kTileCounterWord], 1u);
       const int64_t e0 = find_edge(s_off, n_edges, tile * kWave);
       const int64_t my_off = s_off[e0 + lane < n_edges ? e0 + lane : n_edges];
       if (w == 0) ++tiles;
       const TileLanes tl = map_lanes(tile * kWave, total, e0, my_off, s_off, 0, 0, qa, qb, sc.dof, lane);
       tile_work<STAGED, CACHE>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, &s_next, wc,
                         checked, token);
+      tile = s_tile[it & 1];  // written before tile_work's barriers
     }
     write_partials(partials, checked, tiles, wc, w, W, lane, (unsigned long long *)cen);
   } else if (threadIdx.x < kPartialSlots) {
@@ -1317,6 +1335,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
       for (int i = 1; i < kPartialSlots - 1; ++i) totals[1 + i] += s_sum[i];
     }
     *arrived = 0u;  // ready for the next launch
+    arrived[kTileCounterWord] = 0u;
   }
 }
 

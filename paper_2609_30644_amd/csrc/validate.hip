@@ -1163,11 +1163,14 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
   float *const wave_fr = cen + tile_shared_floats(R, CACHE) + (size_t)w * kWaveLdsFloats;
   uint32_t *const wave_q = (uint32_t *)(wave_fr + 12 * kWave);
   const Src<STAGED> src = make_src<STAGED>(sc, cen + tile_shared_floats(R, CACHE) + (size_t)W * kWaveLdsFloats);
-  // Static order: workgroup b takes tiles b, b + G, b + 2G, ... (G = grid).
-  // A shared work queue would need a device-wide atomic per tile, whose round
-  // trip across the chip's eight XCDs costs more than a tile's setup.  The
-  // edge lookup of the next tile (first edge, then the lanes' offsets) is
-  // loaded one and two tiles ahead, so no tile waits for it.
+  // Workgroup b takes tiles b and b + G (G = grid) first; every further tile
+  // comes from the launch's tile counter (counters[0], zeroed by the scan:
+  // tiles 2G, 2G + 1, ...), so that workgroups whose tiles are light take
+  // more of them.  The edge lookups run ahead: while a tile runs, the next
+  // tile's lane offsets are loaded, and thread 0 claims the tile after it and
+  // loads its first edge.  A tile is claimed only while the next one is
+  // real, so every claimed tile below n_tiles is processed.
+  __shared__ int64_t s_claim[2][2];  // (tile, first edge), two slots, alternating
   const int64_t G = gridDim.x;
   auto first_edge = [&](int64_t t) -> int64_t {
     return t < kTileFirstCap ? (int64_t)as_const(tile_first)[t] : find_edge(off, n_edges, t * kWave);
@@ -1176,21 +1179,30 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_tiles_k
     const int64_t ei = e_first + lane < n_edges ? e_first + lane : n_edges;
     return off[ei];
   };
-  int64_t tile = blockIdx.x;
+  int64_t tile = blockIdx.x, t_nxt = tile + G;
   int64_t e0_cur = first_edge(tile);
   int64_t off_cur = lane_off(e0_cur);
-  int64_t e0_nxt = tile + G < n_tiles ? first_edge(tile + G) : 0;
-  for (int it = 0; tile < n_tiles; ++it, tile += G) {
+  int64_t e0_nxt = t_nxt < n_tiles ? first_edge(t_nxt) : 0;
+  for (int it = 0; tile < n_tiles; ++it) {
+    if (threadIdx.x == 0 && t_nxt < n_tiles) {
+      const int64_t t = 2 * G + (int64_t)atomicAdd((unsigned long long *)&counters[0], 1ull);
+      s_claim[it & 1][0] = t;
+      s_claim[it & 1][1] = t < n_tiles ? first_edge(t) : 0;
+    }
     const int64_t e0 = e0_cur, my_off = off_cur;
-    if (tile + G < n_tiles) {
+    if (t_nxt < n_tiles) {
       e0_cur = e0_nxt;
       off_cur = lane_off(e0_nxt);
-      if (tile + 2 * G < n_tiles) e0_nxt = first_edge(tile + 2 * G);
     }
     if (w == 0) ++tiles;
     const TileLanes tl = map_lanes(tile * kWave, total, e0, my_off, off, 0, 0, qa, qb, sc.dof, lane);
     tile_work<STAGED, CACHE>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, &s_next, wc,
                       checked, kFlagHit);
+    // (the claim was written before tile_work's barriers)
+    const int64_t t_nn = t_nxt < n_tiles ? s_claim[it & 1][0] : n_tiles;
+    if (t_nxt < n_tiles) e0_nxt = s_claim[it & 1][1];
+    tile = t_nxt;
+    t_nxt = t_nn;
   }
   write_partials(partials, checked, tiles, wc, w, W, lane, (unsigned long long *)cen);
 }
@@ -1503,6 +1515,9 @@ __global__ __launch_bounds__(256) void seg_finalize_kernel(const ValSeg *__restr
   if (fl != 0u) atomicAdd((unsigned long long *)&g.counters[5], 1ull);
   if (f == g.edge0 && totals) atomicAdd((unsigned long long *)&totals[1], (unsigned long long)g.counters[1]);
 }
+
+// Zeroes one word (a tile counter, before a repeated tile launch).
+__global__ void zero_word_kernel(uint64_t *p) { *p = 0ull; }
 
 __global__ __launch_bounds__(256) void finalize_kernel(const uint32_t *__restrict__ flags, int64_t n_edges,
                                                        uint8_t *__restrict__ out, uint64_t *__restrict__ counters,
@@ -1849,6 +1864,8 @@ hipError_t launch_validate(const SceneDev &sc, const float *qa, const float *qb,
     launch_tiles(ts0, e0, e1);
   } else {  // measured: every candidate once (the flag words only gather hits), the last one's partials stand
     const hipError_t te = time_candidates(cands, s, e0, e1, [&](const TileShape &ts, hipEvent_t a, hipEvent_t b) {
+      // each candidate hands out every tile again: its tile counter starts at zero
+      hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(1), 0, s, ws.counters);
       launch_tiles(ts, a, b);
     }, key);
     if (te != hipSuccess) return te;

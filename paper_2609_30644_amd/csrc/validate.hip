@@ -1438,7 +1438,7 @@ __global__ __launch_bounds__(256) void seg_table_kernel(const ValSeg *__restrict
 template <bool CACHE>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_segments_kernel(
     const ValSeg *__restrict__ segs, const int64_t *__restrict__ off, const int32_t *__restrict__ tile_first,
-    const int32_t *__restrict__ tile_seg, uint32_t *__restrict__ flags, const uint64_t *__restrict__ batch,
+    const int32_t *__restrict__ tile_seg, uint32_t *__restrict__ flags, uint64_t *__restrict__ batch,
     uint64_t *__restrict__ partials, int r_max) {
   extern __shared__ float cen[];
   __shared__ unsigned long long s_dead[2], s_hit[kMaxWavesPerBlock];
@@ -1458,9 +1458,14 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_segment
   float *const sc_lds = CACHE ? cen + (size_t)r_max * kMaxLinks * 3 * kWave : nullptr;
   float *const wave_fr = cen + tile_shared_floats(r_max, CACHE) + (size_t)w * kWaveLdsFloats;
   uint32_t *const wave_q = (uint32_t *)(wave_fr + 12 * kWave);
+  // Workgroup b first takes tile b; every further tile comes from the
+  // launch's tile counter (batch[0], zeroed by the table kernels: tiles G,
+  // G + 1, ...), claimed by thread 0 while the current tile runs.
+  __shared__ int64_t s_tile[2];  // the next tile, two slots, alternating
   const int64_t G = gridDim.x;
   int it = 0;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += G, ++it) {
+  for (int64_t tile = blockIdx.x; tile < n_tiles; ++it) {
+    if (threadIdx.x == 0) s_tile[it & 1] = G + (int64_t)atomicAdd((unsigned long long *)&batch[0], 1ull);
     const int k = (int)__builtin_amdgcn_readfirstlane(tile_seg[tile]);
     const ValSeg &g = segs[k];
     const SceneDev &sc = g.sc;
@@ -1475,6 +1480,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_segment
                                    sc.dof, lane);
     tile_work<false, CACHE>(sc, src, g.S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, &s_next, wc,
                      checked, kFlagHit);
+    tile = s_tile[it & 1];  // written before tile_work's barriers
   }
   write_partials(partials, checked, tiles, wc, w, W, lane, (unsigned long long *)cen);
 }

@@ -353,7 +353,7 @@ mrpop_status PlanJob::prepare(mrpop_ctx *ctx, const mrpop_scene *scene, const fl
   ctx_ = ctx;
   scene_ = scene;
   P_ = P;
-  if (P.candidates < 1 || P.candidates > 4096 || !(P.resolution > 0.f) || !std::isfinite(P.resolution) ||
+  if (P.candidates < 1 || P.candidates > kMaxCandidates || !(P.resolution > 0.f) || !std::isfinite(P.resolution) ||
       P.max_rounds < 1 || P.max_iterations < 1 || P.max_growth_rounds < 1 || P.n_roadmap < 1 ||
       P.max_tree_nodes < 2 || P.max_roadmap_nodes < 4 || P.max_roadmap_nodes > kUfMaxVertices ||
       !(P.delta > 0.f) || P.time_budget_s < 0 || std::isnan(P.warm_cost) || (P.direct != 0 && P.direct != 1) ||

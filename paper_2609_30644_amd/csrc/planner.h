@@ -84,6 +84,8 @@ struct TreePair {
   float *e[2];       // [tree_cap] length of the edge to the parent (ao-dRRT), or null
 };
 
+constexpr int kMaxCandidates = 4096;  // candidates per round (mrpop_plan_params.candidates)
+
 // ao-dRRT (the rewiring baseline of the paper's experiments): per candidate,
 // the cheapest parent among the extended tree's tensor-product neighbours of
 // q_new, and up to kRwSlots rewiring proposals (tree vertices whose cost

@@ -882,14 +882,44 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
   __shared__ int32_t s_wsum[kMaxW];
   __shared__ int32_t s_base;
   __shared__ float s_cost[kMaxW];
-  __shared__ int32_t s_cand[kMaxW];
+  __shared__ int32_t s_cand[kMaxW], s_ccand[kMaxW];
   __shared__ unsigned long long s_states[2][kMaxW];
+  __shared__ int32_t s_ins[kMaxCandidates];  // tree index of each candidate (-1: not inserted)
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
   if (threadIdx.x == 0) s_base = 0;
+  const int64_t total_states = (threadIdx.x == 0 && a.counters) ? (int64_t)a.counters[1] : 0;
+  // Per candidate, in chunks of the block: every scalar the round needs is
+  // loaded first, together with the inputs of its connection's cost (which
+  // does not depend on the insertion), so that their latencies overlap; then
+  // the ranks of the survivors, their insertion, and the cheapest free
+  // connection of an inserted candidate (ties: the lowest candidate).
+  float best = INFINITY;
+  int bi = -1, bc = -1;
+  unsigned long long used = 0, spec = 0;
   __syncthreads();
   for (int i0 = 0; i0 < a.n; i0 += blockDim.x) {
     const int i = i0 + threadIdx.x;
-    const bool ok = i < a.n && a.alive[i] && a.valid[i];
+    bool ok = false, conn = false;
+    int c = -1, near = -1;
+    float g = 0.f, e_new = 0.f, tot = INFINITY;
+    unsigned long long ns = 0;
+    if (i < a.n) {
+      ok = a.alive[i] && a.valid[i];
+      c = a.conn_idx[i];
+      conn = c >= 0 && a.cvalid[i];
+      ns = (unsigned long long)max(a.codes_conn[i], 0);
+      g = a.g_new[i];
+      near = a.near_idx[i];
+      if (a.rw.on) e_new = a.rw.e_new[i];
+      if (ok && conn) {
+        float d2 = 0.f;
+        for (int j = 0; j < a.dim; ++j) {
+          const float x = a.q_new[(int64_t)i * a.dim + j] - other_q[(int64_t)j * a.tree_cap + c];
+          d2 = fmaf(x, x, d2);
+        }
+        tot = g + sqrtf(d2) + other_g[c];
+      }
+    }
     const uint64_t bal = __ballot(ok);
     const int before = __popcll(bal & ((1ull << lane) - 1ull));
     if (lane == 0) s_wsum[w] = __popcll(bal);
@@ -903,10 +933,18 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
       const int pos = n_before + s_base + off + before;
       const int32_t t = (ok && pos < a.tree_cap) ? pos : -1;
       a.ins_idx[i] = t;
+      s_ins[i] = t;
       if (t >= 0) {
-        tree_g[t] = a.g_new[i];
-        tree_parent[t] = a.near_idx[i];
-        if (a.rw.on) pick(a.t.e, ta)[t] = a.rw.e_new[i];
+        tree_g[t] = g;
+        tree_parent[t] = near;
+        if (a.rw.on) pick(a.t.e, ta)[t] = e_new;
+      }
+      if (t >= 0) used += ns;
+      else spec += ns;
+      if (t >= 0 && conn && (tot < best || (tot == best && (bi < 0 || i < bi)))) {
+        best = tot;
+        bi = i;
+        bc = c;
       }
     }
     __syncthreads();
@@ -916,10 +954,9 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
   const int all = s_base;
   const int room = a.tree_cap - n_before;
   const int inserted = all < room ? all : room;
-  // rows of the inserted candidates (their tree indices written above,
-  // visible behind the barrier)
-  // kCopyUnroll elements per thread and step, all loaded before any store
-  // (the stores could alias the loads for the compiler, which would
+  // rows of the inserted candidates (their tree indices in LDS, behind the
+  // barrier); kCopyUnroll elements per thread and step, all loaded before any
+  // store (the stores could alias the loads for the compiler, which would
   // otherwise wait on each load in turn)
   constexpr int kCopyUnroll = 8;
   const int64_t n_rows = (int64_t)a.n * a.dim, n_vids = (int64_t)a.n * a.n_robots;
@@ -931,7 +968,7 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
       const int64_t k = k0 + (int64_t)u * blockDim.x;
       t[u] = -1;
       if (k < n_rows) {
-        t[u] = a.ins_idx[k / a.dim];
+        t[u] = s_ins[k / a.dim];
         v[u] = a.q_new[k];
       }
     }
@@ -948,7 +985,7 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
       const int64_t k = k0 + (int64_t)u * blockDim.x;
       t[u] = -1;
       if (k < n_vids) {
-        t[u] = a.ins_idx[k % a.n];
+        t[u] = s_ins[k % a.n];
         v[u] = a.vid_new[k];
       }
     }
@@ -958,34 +995,13 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
       if (t[u] >= 0) tree_vid[(k / a.n) * a.tree_cap + t[u]] = v[u];
     }
   }
-  // cheapest free connection of an inserted candidate; connection states
-  float best = INFINITY;
-  int bi = -1;
-  unsigned long long used = 0, spec = 0;
-  for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
-    const int c = a.conn_idx[i];
-    const int32_t t = a.ins_idx[i];
-    const unsigned long long ns = (unsigned long long)max(a.codes_conn[i], 0);
-    if (t >= 0) used += ns;
-    else spec += ns;
-    if (t < 0 || c < 0 || !a.cvalid[i]) continue;
-    float d2 = 0.f;
-    for (int j = 0; j < a.dim; ++j) {
-      const float x = a.q_new[(int64_t)i * a.dim + j] - other_q[(int64_t)j * a.tree_cap + c];
-      d2 = fmaf(x, x, d2);
-    }
-    const float tot = a.g_new[i] + sqrtf(d2) + other_g[c];
-    if (tot < best || (tot == best && (bi < 0 || i < bi))) {
-      best = tot;
-      bi = i;
-    }
-  }
   for (int d = kWave / 2; d > 0; d >>= 1) {
     const float oc = __shfl_xor(best, d, kWave);
-    const int oi = __shfl_xor(bi, d, kWave);
+    const int oi = __shfl_xor(bi, d, kWave), ob = __shfl_xor(bc, d, kWave);
     if (oi >= 0 && (bi < 0 || oc < best || (oc == best && oi < bi))) {
       best = oc;
       bi = oi;
+      bc = ob;
     }
     used += __shfl_xor(used, d, kWave);
     spec += __shfl_xor(spec, d, kWave);
@@ -993,6 +1009,7 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
   if (lane == 0) {
     s_cost[w] = best;
     s_cand[w] = bi;
+    s_ccand[w] = bc;
     s_states[0][w] = used;
     s_states[1][w] = spec;
   }
@@ -1010,7 +1027,7 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
     const int np = a.n * kRwSlots;
     auto usable = [&](int p) {
       const int z = a.rw.prop_z[p];
-      return z >= 0 && z < n_before && a.rw.pvalid[p] && a.ins_idx[p / kRwSlots] >= 0;
+      return z >= 0 && z < n_before && a.rw.pvalid[p] && s_ins[p / kRwSlots] >= 0;
     };
     for (int p = threadIdx.x; p < np; p += blockDim.x)
       if (usable(p)) a.rw.key[a.rw.prop_z[p]] = ~0ull;
@@ -1030,7 +1047,7 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
       const unsigned long long k =
           __hip_atomic_load((unsigned long long *)&a.rw.key[z], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (k == (((unsigned long long)__float_as_uint(c) << 32) | (unsigned)p) && c < tree_g[z]) {
-        tree_parent[z] = a.ins_idx[p / kRwSlots];
+        tree_parent[z] = s_ins[p / kRwSlots];
         tree_g[z] = c;
         tree_e[z] = a.rw.prop_len[p];
         ++mine;
@@ -1041,13 +1058,14 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    float bc = s_cost[0];
-    int bc_i = s_cand[0];
+    float bcost = s_cost[0];
+    int bc_i = s_cand[0], bc_c = s_ccand[0];
     unsigned long long su = s_states[0][0], ss_ = s_states[1][0];
     for (int k = 1; k < nw; ++k) {
-      if (s_cand[k] >= 0 && (bc_i < 0 || s_cost[k] < bc || (s_cost[k] == bc && s_cand[k] < bc_i))) {
-        bc = s_cost[k];
+      if (s_cand[k] >= 0 && (bc_i < 0 || s_cost[k] < bcost || (s_cost[k] == bcost && s_cand[k] < bc_i))) {
+        bcost = s_cost[k];
         bc_i = s_cand[k];
+        bc_c = s_ccand[k];
       }
       su += s_states[0][k];
       ss_ += s_states[1][k];
@@ -1057,14 +1075,13 @@ __device__ __forceinline__ void insert_select_body(const InsertSelectArgs &a, in
     RoundStatus st{};
     st.found = bc_i >= 0 ? 1 : 0;
     st.cand = bc_i;
-    st.a_idx = bc_i >= 0 ? a.ins_idx[bc_i] : -1;
-    st.b_idx = bc_i >= 0 ? a.conn_idx[bc_i] : -1;
-    st.total = bc;
+    st.a_idx = bc_i >= 0 ? s_ins[bc_i] : -1;
+    st.b_idx = bc_i >= 0 ? bc_c : -1;
+    st.total = bcost;
     st.inserted = inserted;
     st.overflow = all > room ? 1 : 0;
     st.a = ta;
     st.skipped = 0;
-    const int64_t total_states = a.counters ? (int64_t)a.counters[1] : 0;
     st.states_conn = (int64_t)su;
     st.states_spec = (int64_t)ss_;
     st.states_rw = (int64_t)s_rw_states;

@@ -12,9 +12,11 @@ before the timed region.
 
 Printed: one JSON line with composite edge-states validated per second over
 the step (both batches and the plan's search), the plans' p50 time to first
-solution, the roofline of the edge-validation tile kernel (executed
-algorithmic flops / its HIP-event time, against the FP32 vector peak) and
-the oracle's CPU rate on a sample.
+solution, the roofline of the edge-validation tile kernels (the flop model's
+flops for the states and links they evaluated, with the coarse stage at its
+full table of every link against every obstacle, over their HIP-event time,
+against the FP32 vector peak; beside it the same pricing of only the coarse
+tests the kernels ran) and the oracle's CPU rate on a sample.
 """
 from __future__ import annotations
 

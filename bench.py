@@ -300,19 +300,16 @@ def c1_leg(ctx, n_problems: int, n_full: int) -> dict:
             "plan_call_p50_ms": float(np.median(wall)) * 1e3, "params": C1_PLAN, "full_budget": full}
 
 
-def c3_leg(ctx, reps: int, plan_s: float) -> dict:
-    """The 8-arm shelf workload: both 4096-edge batches validated `reps`
-    times (edge-states/s, the tile kernel's time and algorithmic flops, bits
-    checked against the fixture), then one plan with a wall-clock budget
-    (time to first solution, cost after each improvement, cost at the end)."""
+def batch_rooflines(ctx, scene, batches, fx, reps: int, out: dict):
+    """Both 4096-edge batches of a fixture validated `reps` times each, alone:
+    edge-states/s, the tile kernel's time and its roofline (flop model and
+    executed), bits checked against the fixture.  Returns the device scene."""
     import torch
     import paper_2609_30644_amd as M
-    scene, batches, fx = load_workload(C3_FIXTURE, "scene_c3")
     res = float(fx["resolution"])
     s = M.Scene(ctx, scene)
     dev = {k: (ctx.to_device(a), ctx.to_device(b)) for k, (a, b) in batches.items()}
     outs = {k: torch.empty(a.shape[0], dtype=torch.uint8, device=ctx.device) for k, (a, _) in dev.items()}
-    out = {"workload": "8 arms x 7-DoF (59 spheres/arm) on a 3 m circle, 256 shelf boxes, res 0.02 rad"}
     for k, (a, b) in dev.items():
         _, st = s.validate_edges(a, b, res, out=outs[k], stats=True)  # warm, and the nominal states
         torch.cuda.synchronize()
@@ -332,6 +329,27 @@ def c3_leg(ctx, reps: int, plan_s: float) -> dict:
                   "achieved_tflops": model, "frac": model / PEAK_FP32_TFLOPS,
                   "executed_tflops": executed, "executed_frac": executed / PEAK_FP32_TFLOPS}
     out["bits"] = check_bits(outs["free"].cpu().numpy(), outs["mixed"].cpu().numpy(), fx)
+    return s
+
+
+def c2_batches_leg(ctx, reps: int) -> dict:
+    """The step's two C2 batches timed alone (the certainly-free one is the
+    batch whose every state must be evaluated)."""
+    scene, batches, fx = load_workload()
+    out = {"workload": "4 arms x 7-DoF (59 spheres/arm), 32 spheres + 32 boxes, res 0.05 rad"}
+    batch_rooflines(ctx, scene, batches, fx, reps, out)
+    return out
+
+
+def c3_leg(ctx, reps: int, plan_s: float) -> dict:
+    """The 8-arm shelf workload: both 4096-edge batches validated `reps`
+    times (edge-states/s, the tile kernel's time and algorithmic flops, bits
+    checked against the fixture), then one plan with a wall-clock budget
+    (time to first solution, cost after each improvement, cost at the end)."""
+    scene, batches, fx = load_workload(C3_FIXTURE, "scene_c3")
+    res = float(fx["resolution"])
+    out = {"workload": "8 arms x 7-DoF (59 spheres/arm) on a 3 m circle, 256 shelf boxes, res 0.02 rad"}
+    s = batch_rooflines(ctx, scene, batches, fx, reps, out)
     if plan_s > 0:
         qs, qg = np.array(fx["q_start"], np.float32), np.array(fx["q_goal"], np.float32)
         prm = dict(C3_PLAN, seed=0, resolution=res, time_budget_s=plan_s)
@@ -755,6 +773,9 @@ def main():
     if args.c3_reps > 0:
         print("[bench] eight-arm shelf", file=sys.stderr, flush=True)
         line["c3"] = c3_leg(ctx, args.c3_reps, args.c3_plan_seconds)
+    if args.c3_reps > 0:
+        print("[bench] four-arm batches alone", file=sys.stderr, flush=True)
+        line["c2_batches"] = c2_batches_leg(ctx, args.c3_reps)
     if args.direct:
         print("[bench] direct mode", file=sys.stderr, flush=True)
         line["direct"] = direct_leg(ctx, res)

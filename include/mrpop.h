@@ -590,7 +590,9 @@ double mrpop_server_clock(const mrpop_server *srv);
 /* Totals over the launches of the edge-validation tile kernel made on `ctx`
  * since profiling was (re-)enabled: launch count, summed kernel time taken
  * from HIP events recorded on the launch stream right before and after each
- * tile-kernel launch, and the states the kernel evaluated and was given. */
+ * timed tile-kernel launch (every launch, or every k-th: see
+ * mrpop_profile_enable), and the states the kernel evaluated and was given
+ * (over every launch). */
 typedef struct {
   int64_t launches;
   double kernel_ms;
@@ -599,9 +601,14 @@ typedef struct {
   int64_t work[8];        /* as mrpop_validate_stats.work, summed */
   int32_t grid_blocks;    /* workgroups of the last tile-kernel launch      */
   int32_t block_threads;  /* threads per workgroup                          */
+  int64_t timed_launches; /* launches whose time kernel_ms sums             */
 } mrpop_kernel_profile;
 
-/* enable != 0 starts recording (and clears the totals); 0 stops. */
+/* enable != 0 starts recording (and clears the totals); 0 stops.  enable = 1
+ * times every tile-kernel launch; enable = k > 1 times the first launch and
+ * then every k-th (the event pair adds dispatch time to the launches it
+ * brackets, so a sample keeps that cost off the others); the work totals
+ * always cover every launch.  E_INVALID_ARG if enable < 0. */
 mrpop_status mrpop_profile_enable(mrpop_ctx *ctx, int enable);
 /* Waits for the recorded events and fills `out`.  E_INVALID_ARG if out is
  * NULL. */

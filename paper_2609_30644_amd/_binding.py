@@ -51,7 +51,7 @@ class _ValidateStats(C.Structure):
 class _KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_int64), ("kernel_ms", C.c_double), ("states_checked", C.c_int64),
                 ("edge_states", C.c_int64), ("work", C.c_int64 * 8), ("grid_blocks", C.c_int32),
-                ("block_threads", C.c_int32)]
+                ("block_threads", C.c_int32), ("timed_launches", C.c_int64)]
 
 
 class PlanParams(C.Structure):
@@ -159,6 +159,7 @@ class KernelProfile:
     work: dict
     grid_blocks: int = 0
     block_threads: int = 0
+    timed_launches: int = 0
 
 
 _lib = None
@@ -352,14 +353,16 @@ class Context:
     def tuner_entries(self) -> int:
         return int(self._lib.mrpop_tuner_entries())
 
-    def profile_enable(self, on: bool = True) -> None:
+    def profile_enable(self, on=True) -> None:
+        """True or 1: time every tile launch; k > 1: time every k-th; False: stop."""
         self.check(self._lib.mrpop_profile_enable(self._h, int(on)))
 
     def profile_read(self) -> "KernelProfile":
         p = _KernelProfile()
         self.check(self._lib.mrpop_profile_read(self._h, C.byref(p)))
         return KernelProfile(p.launches, p.kernel_ms, p.states_checked, p.edge_states,
-                             dict(zip(WORK_NAMES, list(p.work))), p.grid_blocks, p.block_threads)
+                             dict(zip(WORK_NAMES, list(p.work))), p.grid_blocks, p.block_threads,
+                             p.timed_launches)
 
 
 class Scene:

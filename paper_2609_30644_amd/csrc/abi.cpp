@@ -89,6 +89,7 @@ void pool_free(mrpop_ctx *ctx, bool pinned, void *p, size_t bytes) {
 
 const std::pair<hipEvent_t, hipEvent_t> *profile_slot(mrpop_ctx *ctx) {
   if (!ctx->profiling) return nullptr;
+  if (ctx->prof_seen++ % ctx->prof_stride != 0) return nullptr;  // counted, not timed
   if (ctx->ev_used == ctx->ev_pool.size()) {
     std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
     // timing-only events: no system-scope fence when they complete (no cache
@@ -216,9 +217,12 @@ void mrpop_ctx_destroy(mrpop_ctx *ctx) {
 
 mrpop_status mrpop_profile_enable(mrpop_ctx *ctx, int enable) {
   if (!ctx) return fail(nullptr, MRPOP_E_INVALID_ARG, "profile_enable: ctx is NULL");
+  if (enable < 0) return fail(ctx, MRPOP_E_INVALID_ARG, "profile_enable: negative stride");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   ctx->profiling = enable != 0;
+  ctx->prof_stride = enable > 1 ? enable : 1;
+  ctx->prof_seen = 0;
   ctx->ev_used = 0;
   ctx->prof_ms = 0.0;
   ctx->prof_launches = 0;
@@ -260,7 +264,8 @@ mrpop_status mrpop_profile_read(mrpop_ctx *ctx, mrpop_kernel_profile *out) {
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   mrpop_status st = drain_events(ctx);
   if (st != MRPOP_OK) return st;
-  out->launches = ctx->prof_launches;
+  out->launches = ctx->prof_seen;
+  out->timed_launches = ctx->prof_launches;
   out->kernel_ms = ctx->prof_ms;
   out->grid_blocks = ctx->last_grid;
   out->block_threads = ctx->last_block;

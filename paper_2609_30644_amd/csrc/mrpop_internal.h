@@ -104,10 +104,12 @@ struct mrpop_ctx {
   // Profiling of the validation tile kernel: event pairs recorded on the
   // launch stream, and device totals (states checked, edge states).
   bool profiling = false;
+  int prof_stride = 1;       // time every prof_stride-th tile launch
+  int64_t prof_seen = 0;     // tile launches since profiling was enabled
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   size_t ev_used = 0;
   double prof_ms = 0.0;
-  int64_t prof_launches = 0;
+  int64_t prof_launches = 0; // timed launches drained so far
   uint64_t *prof_totals = nullptr;  // device [10]
   int32_t last_grid = 0, last_block = 0;  // last tile-kernel launch
   // One-launch small validations: the device arrival counter (zero between

@@ -131,6 +131,7 @@ int main() {
   uint8_t *v1 = nullptr, *v2 = nullptr;
   HIPCHECK(hipMalloc(&v1, E));
   HIPCHECK(hipMalloc(&v2, E));
+  CHECK(mrpop_profile_enable(ctx, -1) == MRPOP_E_INVALID_ARG);
   CHECK(mrpop_profile_enable(ctx, 1) == MRPOP_OK);
   mrpop_validate_stats vs{};
   CHECK(mrpop_validate_edges(ctx, sc, qa, qb, E, 0.05f, nullptr, v1, &vs, nullptr) == MRPOP_OK);

@@ -87,3 +87,26 @@ def test_tuner_rejects_bad_flag(ctx):
     import paper_2609_30644_amd as M
     with pytest.raises(M.MrpopError):
         ctx._check(ctx._lib.mrpop_tuner_configure(None, 3), None)
+
+
+def test_profile_times_every_kth_launch(ctx):
+    """With a stride k, the first tile launch and then every k-th carry the
+    timing events, while the work totals still cover every launch."""
+    import paper_2609_30644_amd as M
+    p = problem("c2")
+    s = M.Scene(ctx, p.scene)
+    qa, qb = W.edge_batch(p.scene, 600, 0.05, 7, 8, 64)
+    s.validate_edges(qa, qb, 0.05)  # warm (and tuned) before the counted launches
+    totals = []
+    for stride in (1, 3):
+        ctx.profile_enable(stride)
+        for _ in range(7):
+            s.validate_edges(qa, qb, 0.05)
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        assert prof.launches == 7 and prof.timed_launches == (7 if stride == 1 else 3)
+        assert prof.kernel_ms > 0.0
+        totals.append(prof.edge_states)
+    assert totals[0] == totals[1] > 0
+    with pytest.raises(M.MrpopError):
+        ctx.profile_enable(-1)

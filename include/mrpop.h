@@ -208,6 +208,28 @@ mrpop_status mrpop_validate_edges(mrpop_ctx *ctx, const mrpop_scene *scene, cons
                                   int64_t n_edges, float resolution, const int32_t *n_states_opt,
                                   uint8_t *out_valid, mrpop_validate_stats *stats_opt, void *stream);
 
+/* Edge validation as mrpop_validate_edges for at most MRPOP_COUNTED_MAX_EDGES
+ * edges whose state counts the caller has made (the n_states output of
+ * mrpop_extend, or counts of its own), in one launch: the planner's round
+ * batches take this path.  n_states is a device array [n_edges]: a count
+ * n > 0 checks edge e at the n states of the paper's discretisation (Sec.
+ * "Multi-Thread Reassignment for Collision Checking"; n = 1: q_a alone);
+ * n <= 0 reports the edge invalid without checking it (mrpop_extend writes -1
+ * for a non-finite endpoint and -2 for an edge of more than
+ * MRPOP_MAX_STATES_PER_EDGE states; with stats_opt a -2 makes the call
+ * return E_INVALID_ARG once the bits are written, as mrpop_validate_edges
+ * does for such an edge, and -1 counts as a non-finite edge).  The bits equal those of
+ * mrpop_validate_edges with the same counts; which states are evaluated
+ * before an edge is found colliding may differ (stats_opt->states_checked).
+ * qa, qb, n_states and out_valid are the caller's device buffers, layout as
+ * mrpop_validate_edges.  Errors: E_INVALID_ARG (NULL ctx, scene, buffer or
+ * n_states, n_edges < 0 or > MRPOP_COUNTED_MAX_EDGES; nothing is queued),
+ * E_NOMEM, E_DEVICE. */
+#define MRPOP_COUNTED_MAX_EDGES 1024
+mrpop_status mrpop_validate_counted(mrpop_ctx *ctx, const mrpop_scene *scene, const float *qa, const float *qb,
+                                    int64_t n_edges, const int32_t *n_states, uint8_t *out_valid,
+                                    mrpop_validate_stats *stats_opt, void *stream);
+
 /* mrpop_validate_edges for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same kernels and the same bits, with the working memory in

@@ -201,6 +201,7 @@ def load_library():
     lib.mrpop_fk_spheres.argtypes = [P, P, P, I64, P, P]
     lib.mrpop_validate_edges.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
     lib.mrpop_validate_edges_noalloc.argtypes = [P, P, P, P, I64, C.c_float, P, P, P, P]
+    lib.mrpop_validate_counted.argtypes = [P, P, P, P, I64, P, P, P, P]
     lib.mrpop_tuner_configure.argtypes = [C.c_char_p, I32]
     lib.mrpop_tuner_entries.argtypes = []
     lib.mrpop_tuner_entries.restype = I32
@@ -450,6 +451,13 @@ class Scene:
         library's fixed device array instead of the context's scratch; at most
         MRPOP_NOALLOC_MAX_EDGES edges)."""
         return self._validate(self.ctx._lib.mrpop_validate_edges_noalloc, qa, qb, resolution, n_states, out, stats)
+
+    def validate_counted(self, qa, qb, n_states, out=None, stats: bool = False):
+        """mrpop_validate_counted: at most MRPOP_COUNTED_MAX_EDGES edges with
+        the caller's state counts (n <= 0: invalid, unchecked), one launch."""
+        fn = self.ctx._lib.mrpop_validate_counted
+        return self._validate(lambda c, h, a, b, E, _res, ns, o, st, s: fn(c, h, a, b, E, ns, o, st, s),
+                              qa, qb, 1.0, n_states, out, stats)
 
     def _validate(self, fn, qa, qb, resolution, n_states, out, stats):
         torch = _torch()

@@ -1013,6 +1013,36 @@ mrpop_status mrpop_validate_edges(mrpop_ctx *ctx, const mrpop_scene *scene, cons
   return MRPOP_OK;
 }
 
+static_assert(MRPOP_COUNTED_MAX_EDGES == kFusedMaxEdges, "one-launch batch limit");
+
+mrpop_status mrpop_validate_counted(mrpop_ctx *ctx, const mrpop_scene *scene, const float *qa, const float *qb,
+                                    int64_t n_edges, const int32_t *n_states, uint8_t *out_valid,
+                                    mrpop_validate_stats *stats_opt, void *stream) {
+  bool done = false;
+  mrpop_status st = validate_args(ctx, scene, qa, qb, n_edges, 0.f, n_states, out_valid, stats_opt,
+                                  "validate_counted", &done);
+  if (st != MRPOP_OK || done) return st;
+  if (!n_states) return fail(ctx, MRPOP_E_INVALID_ARG, "validate_counted: n_states is NULL");
+  if (n_edges > MRPOP_COUNTED_MAX_EDGES)
+    return fail(ctx, MRPOP_E_INVALID_ARG, "validate_counted: more than MRPOP_COUNTED_MAX_EDGES edges");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  void *ws_base = nullptr;
+  st = scratch_slot(ctx, 0, validate_scratch_bytes(n_edges), &ws_base);
+  if (st != MRPOP_OK) return st;
+  ValidateScratch ws = validate_scratch_layout(ws_base, n_edges);
+  uint32_t *arrived = nullptr, *flags = nullptr, token = 0;
+  e = small_launch_state(ctx, &arrived, &flags, &token);
+  if (e != hipSuccess) return hip_fail(ctx, e, "validate_counted state");
+  ws.flags = flags;
+  hipStream_t s = (hipStream_t)stream;
+  e = launch_validate_small(scene->dev, qa, qb, n_edges, n_states, out_valid, ws, arrived, token, s, profile_slot(ctx),
+                            ctx->profiling ? ctx->prof_totals : nullptr, &ctx->last_grid, &ctx->last_block);
+  if (e != hipSuccess) return hip_fail(ctx, e, "validate_counted launch");
+  if (stats_opt) return validate_stats(ctx, ws, s, stats_opt, "validate_counted stats");
+  return MRPOP_OK;
+}
+
 mrpop_status mrpop_tuner_configure(const char *cache_file, int32_t enable) {
   if (enable != 0 && enable != 1) return fail(nullptr, MRPOP_E_INVALID_ARG, "tuner_configure: enable must be 0 or 1");
   tuner_configure(cache_file, enable != 0);

@@ -391,6 +391,16 @@ __device__ __forceinline__ int64_t find_edge(const int64_t *__restrict__ off, in
   return lo;
 }
 
+__device__ __forceinline__ int64_t find_edge(const int32_t *__restrict__ off, int64_t n_edges, int64_t s) {
+  int64_t lo = 0, hi = n_edges - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= s) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Work actually executed by one lane (for the algorithmic flop count): kinematic
 // chains, coarse link centres placed, coarse link-obstacle sphere tests
 // (environment spheres and box bounding spheres), exact link-box tests,
@@ -1006,6 +1016,53 @@ __device__ __forceinline__ TileLanes map_lanes(int64_t s0, int64_t total, int64_
   return t;
 }
 
+// Two-pass state order of a small batch.  The list holds 2 E segments:
+// segment e < E is the first pass of edge e, its states k = r0, r0 + K, ...,
+// n - 1 (every K-th state counted back from q_b, r0 = (n - 1) mod K), and
+// segment E + e the edge's other states in increasing order.  seg[] holds the
+// segments' exclusive offsets (2 E + 1 entries).  Lane i holds list position
+// s0 + i; the result names the real edge and state, so that the states are
+// the same floats as in the plain order.
+__device__ __forceinline__ TileLanes map_lanes_split(int64_t s0, int64_t total, int64_t g0, int64_t my_off,
+                                                     const int32_t *seg, int n_edges, int K, const float *qa,
+                                                     const float *qb, int dof, int lane) {
+  TileLanes t;
+  const int64_t s = s0 + lane;
+  t.act = s < total;
+  int pos = 0;
+#pragma unroll
+  for (int step = kWave / 2; step > 0; step >>= 1) {
+    const int cand = pos + step;
+    const int64_t o = __shfl(my_off, cand, kWave);
+    if (o <= s) pos = cand;
+  }
+  const int64_t g = g0 + pos;
+  const int64_t g_start = __shfl(my_off, pos, kWave);
+  int64_t g_end = __shfl(my_off, pos < kWave - 1 ? pos + 1 : pos, kWave);
+  if (t.act && pos == kWave - 1) g_end = seg[g + 1];
+  const bool second = g >= n_edges;
+  t.e = second ? g - n_edges : g;
+  t.st = LaneState{qa, qb, 0.f, false};
+  t.emask = 0;
+  if (t.act) {
+    const int64_t e = t.e;
+    // (the whole list holds fewer than 2^31 states)
+    const int n_other = second ? seg[e + 1] - seg[e] : seg[n_edges + e + 1] - seg[n_edges + e];
+    const int n = (int)(g_end - g_start) + n_other;
+    const int j = (int)(s - g_start);
+    const int r0 = (n - 1) % K;
+    const int k = !second ? r0 + j * K : (j < r0 ? j : r0 + 1 + ((j - r0) / (K - 1)) * K + (j - r0) % (K - 1));
+    t.st.qa = qa + e * dof;
+    t.st.qb = qb + e * dof;
+    t.st.last = n > 1 && k == n - 1;
+    t.st.t = n > 1 ? (float)k / (float)(n - 1) : 0.f;
+    const int lo = (int)((g_start > s0 ? g_start : s0) - s0);
+    const int hi = (int)((g_end < s0 + kWave ? g_end : s0 + kWave) - s0);
+    t.emask = (hi - lo >= 64 ? ~0ull : ((1ull << (hi - lo)) - 1ull)) << lo;
+  }
+  return t;
+}
+
 // Joint values of arm r at the lane's state (all loads first, so that they
 // overlap).
 __device__ __forceinline__ void arm_joints(const SceneDev &sc, const LaneState &st, int r, int nj,
@@ -1039,17 +1096,30 @@ template <bool STAGED, bool CACHE>
 __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int w, int W, int lane, int it,
                           const TileLanes &tl, uint32_t *flags, float *cen, float *sc_lds, float *wave_fr,
                           uint32_t *wave_q, unsigned long long *s_dead, unsigned long long *s_hit, int *s_next,
-                          WorkCount &wc, uint32_t &checked, uint32_t hit_token) {
+                          WorkCount &wc, uint32_t &checked, uint32_t hit_token, bool skip_hit = false) {
   unsigned long long *const dead = &s_dead[it & 1];
   const LaneState &st = tl.st;
   bool act = tl.act;
   const int R = sc.n_robots;
   bool hit = false;
+  // With skip_hit, a lane whose edge another tile of this launch has already
+  // marked is idle, and hits are published at once (device-scope stores), so
+  // that later tiles of the same edges can skip their states.  Waves may read
+  // a word at different times; they then differ only on lanes of an edge
+  // that is already marked, whose results no longer matter.
+  if (skip_hit && act)
+    act = __hip_atomic_load(&flags[tl.e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != hit_token;
+  auto publish = [&]() {
+    if (skip_hit && !hit) __hip_atomic_store(&flags[tl.e], hit_token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    hit = true;
+  };
   if constexpr (CACHE) {
     if (threadIdx.x == 0) *s_next = 0;
     // A. the joints' sines and cosines at every lane's state, (arm, joint)
-    // pairs spread over the waves
-    for (int js = w; js < R * kMaxJoints; js += W) {
+    // pairs spread over the waves (a wave whose lanes are all idle has
+    // nothing to compute: a lane is idle in every wave or on a marked edge)
+    const int js_end = (!skip_hit || __ballot(act) != 0ull) ? R * kMaxJoints : 0;
+    for (int js = w; js < js_end; js += W) {
       const int r = js / kMaxJoints, j = js - r * kMaxJoints;
       const int m = as_const(sc.model)[r];
       if (j >= as_const(sc.nj)[m]) continue;
@@ -1084,7 +1154,7 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
       slot[kWave] = c.y;
       slot[2 * kWave] = c.z;
       if (link_env<STAGED>(sc, src, r, m, l, F, c, live, tl.emask, wave_fr, wave_q, &s_hit[w], dead, lane, wc))
-        hit = true;
+        publish();
     }
   } else {
   for (int jb = w; jb < R * S; jb += W) {
@@ -1096,7 +1166,7 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
     const bool live = act && !hit;
     if (arm_env<STAGED>(sc, src, r, m, part, S, qv, live, tl.emask, cen, sc_lds, wave_fr, wave_q, &s_hit[w], dead,
                         lane, wc))
-      hit = true;
+      publish();
   }
   }
   if (act && w == 0) ++checked;
@@ -1105,7 +1175,10 @@ __device__ void tile_work(const SceneDev &sc, const Src<STAGED> &src, int S, int
   // arm pairs that can reach each other
   if (arm_pairs<STAGED, CACHE>(sc, src, cen, sc_lds, w, W, act && !hit, st, tl.emask, wave_q, &s_hit[w], dead, lane, wc))
     hit = true;
-  if (hit) flags[tl.e] = hit_token;
+  if (hit) {
+    if (skip_hit) __hip_atomic_store(&flags[tl.e], hit_token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else flags[tl.e] = hit_token;
+  }
   __syncthreads();
 }
 
@@ -1247,15 +1320,43 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
   for (int i = i0; i < i1; ++i) mine += max(codes[i], 0);
   int64_t total_v;
   int64_t run = block_exclusive_scan(mine, &total_v);
-  for (int i = i0; i < i1; ++i) {
-    s_off[i] = run;
-    run += max(codes[i], 0);
-  }
   const int64_t total = (int64_t)uniform_u64((uint64_t)total_v);  // the same in every lane
-  if (threadIdx.x == 0) s_off[n_edges] = total;
+  const int64_t n_tiles = (total + kWave - 1) / kWave;
+  // More tiles than workgroups: two passes (map_lanes_split), the first, of
+  // every K-th state, at most one tile per workgroup (it holds at most
+  // total / K + n_edges states), so that the second pass's tiles mostly start
+  // after the first pass has marked the colliding edges and skip their
+  // states.  The segment offsets (2 n_edges + 1 words) take the place of the
+  // plain offsets, so they need fewer than 2^31 states.
+  const int64_t first_cap = (int64_t)gridDim.x * kWave - n_edges;
+  const int K = (n_tiles > (int64_t)gridDim.x && first_cap > 0 && total <= (int64_t)INT32_MAX)
+                    ? (int)max<int64_t>(2, (total + first_cap - 1) / first_cap)
+                    : 1;
+  int32_t *const s_seg = reinterpret_cast<int32_t *>(s_off);
+  static_assert(sizeof(s_off) >= (2 * kFusedMaxEdges + 1) * sizeof(int32_t), "segment offsets fit");
+  if (K > 1) {
+    int64_t mine1 = 0;
+    for (int i = i0; i < i1; ++i) mine1 += (max(codes[i], 0) + K - 1) / K;
+    int64_t total1_v;
+    int64_t run1 = block_exclusive_scan(mine1, &total1_v);
+    const int64_t total1 = (int64_t)uniform_u64((uint64_t)total1_v);
+    for (int i = i0; i < i1; ++i) {
+      const int64_t c = max(codes[i], 0), c1 = (c + K - 1) / K;
+      s_seg[i] = (int32_t)run1;
+      s_seg[n_edges + i] = (int32_t)(total1 + run - run1);
+      run += c;
+      run1 += c1;
+    }
+    if (threadIdx.x == 0) s_seg[2 * n_edges] = (int32_t)total;
+  } else {
+    for (int i = i0; i < i1; ++i) {
+      s_off[i] = run;
+      run += max(codes[i], 0);
+    }
+    if (threadIdx.x == 0) s_off[n_edges] = total;
+  }
   if (threadIdx.x < 2) s_dead[threadIdx.x] = 0ull;
   __syncthreads();
-  const int64_t n_tiles = (total + kWave - 1) / kWave;
   // Workgroups with a tile take part (workgroup 0 when there is none); the
   // others leave now, so that a batch of few tiles pays for few arrivals and
   // partial sums.  Every workgroup computes the same count.
@@ -1276,12 +1377,19 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock, 1) void validate_small_k
     int it = 0;
     for (int64_t tile = blockIdx.x; tile < n_tiles; ++it) {
       if (threadIdx.x == 0) s_tile[it & 1] = (int64_t)working + atomicAdd(&arrived[kTileCounterWord], 1u);
-      const int64_t e0 = find_edge(s_off, n_edges, tile * kWave);
-      const int64_t my_off = s_off[e0 + lane < n_edges ? e0 + lane : n_edges];
       if (w == 0) ++tiles;
-      const TileLanes tl = map_lanes(tile * kWave, total, e0, my_off, s_off, 0, 0, qa, qb, sc.dof, lane);
+      TileLanes tl;
+      if (K > 1) {
+        const int64_t g0 = find_edge(s_seg, 2 * (int64_t)n_edges, tile * kWave);
+        const int64_t my_off = s_seg[g0 + lane < 2 * n_edges ? g0 + lane : 2 * n_edges];
+        tl = map_lanes_split(tile * kWave, total, g0, my_off, s_seg, n_edges, K, qa, qb, sc.dof, lane);
+      } else {
+        const int64_t e0 = find_edge(s_off, n_edges, tile * kWave);
+        const int64_t my_off = s_off[e0 + lane < n_edges ? e0 + lane : n_edges];
+        tl = map_lanes(tile * kWave, total, e0, my_off, s_off, 0, 0, qa, qb, sc.dof, lane);
+      }
       tile_work<STAGED, CACHE>(sc, src, S, w, W, lane, it, tl, flags, cen, sc_lds, wave_fr, wave_q, s_dead, s_hit, &s_next, wc,
-                        checked, token);
+                        checked, token, K > 1);
       tile = s_tile[it & 1];  // written before tile_work's barriers
     }
     write_partials(partials, checked, tiles, wc, w, W, lane, (unsigned long long *)cen);
@@ -1524,6 +1632,12 @@ __global__ __launch_bounds__(256) void seg_finalize_kernel(const ValSeg *__restr
 
 // Zeroes one word (a tile counter, before a repeated tile launch).
 __global__ void zero_word_kernel(uint64_t *p) { *p = 0ull; }
+
+// Zeroes n flag words (before a repeated small launch with the same token).
+__global__ __launch_bounds__(256) void zero_flags_kernel(uint32_t *p, int n) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) p[i] = 0u;
+}
 
 __global__ __launch_bounds__(256) void finalize_kernel(const uint32_t *__restrict__ flags, int64_t n_edges,
                                                        uint8_t *__restrict__ out, uint64_t *__restrict__ counters,
@@ -1933,7 +2047,14 @@ hipError_t launch_validate_small(const SceneDev &sc, const float *qa, const floa
   if (cands.empty()) {
     launch_small(ts0, e0, e1);
   } else {  // measured: each candidate is a whole validation; the last one's bits and counters stand
-    const hipError_t te = time_candidates(cands, s, e0, e1, launch_small, key);
+    // Every candidate starts from cleared flag words: the two-pass order
+    // skips the states of edges whose word holds the token, which an
+    // earlier candidate would have set.
+    const unsigned zb = (unsigned)((n_edges + 255) / 256);
+    const hipError_t te = time_candidates(cands, s, e0, e1, [&](const TileShape &ts, hipEvent_t a, hipEvent_t b) {
+      hipLaunchKernelGGL(zero_flags_kernel, dim3(zb), dim3(256), 0, s, ws.flags, (int)n_edges);
+      launch_small(ts, a, b);
+    }, key);
     if (te != hipSuccess) return te;
   }
   if (grid_out) *grid_out = grid;

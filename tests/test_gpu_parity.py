@@ -352,3 +352,71 @@ def test_validate_arm_pairs_with_many_spheres_per_link(ctx, n_tool):
     qa, qb = W.edge_batch(sc, 512, 0.05, 112, 2, 30)
     _, m_, _ = _parity(ctx, sc, qa, qb, 0.05, f"pairs, {n_tool} spheres on a link")
     assert (m_ < -BAND).any() and (m_ > BAND).any()
+
+
+@pytest.mark.parametrize("kind,res,E,n_min,n_max", [("c1", 0.05, 40, 2, 30), ("c2", 0.05, 1024, 2, 40),
+                                                   ("c2", 0.05, 1024, 20, 120), ("c3", 0.02, 600, 20, 60)])
+def test_validate_counted_matches_oracle_and_general_path(ctx, kind, res, E, n_min, n_max):
+    """mrpop_validate_counted (one launch from the caller's state counts; more
+    tiles than workgroups run the two-pass state order) against the oracle
+    outside the band, and bit for bit against mrpop_validate_edges with the
+    same counts.  Sizes: a batch of fewer tiles than workgroups (plain order),
+    the planner's round size, edges of up to 120 states (several tiles per
+    edge), and the 8-arm shelf scene."""
+    p = problem(kind)
+    sc = p.scene
+    anchors = W.random_configs(sc, 4000 if kind != "c3" else 1500, np.random.default_rng(7))
+    anchors = np.concatenate([anchors[oracle.states_free(sc, anchors)], p.q_start[None], p.q_goal[None]])
+    qa, qb = W.edge_batch_near(sc, anchors, E, res, 103, n_min, n_max, spread=0.02)
+    n = oracle.edge_nstates(qa, qb, res)
+    print(f"[validate_counted] {kind}: {E} edges, {int(n.sum())} states", flush=True)
+    s = _scene(ctx, sc)
+    valid, st = s.validate_counted(qa, qb, n, stats=True)
+    valid = valid.cpu().numpy()
+    plain, st_plain = s.validate_edges(qa, qb, res, n_states=n, stats=True)
+    _, m = oracle.classify_edges(sc, qa, qb, res, nstates=n)
+    info = assert_bits_match(valid, m, f"{kind}/counted")
+    np.testing.assert_array_equal(valid, plain.cpu().numpy())
+    assert st.edge_states == st_plain.edge_states == int(n.sum())
+    assert st.edges_invalid == int((valid == 0).sum())
+    assert 0 < st.states_checked <= st.edge_states
+    if valid.all():
+        assert st.states_checked == st.edge_states
+    print(f"  {info} checked {st.states_checked} of {st.edge_states} (general path {st_plain.states_checked})",
+          flush=True)
+
+
+def test_validate_counted_codes_and_limits(ctx):
+    """Counts <= 0 report the edge invalid unchecked (the extension kernel
+    writes -1 for a non-finite endpoint, -2 for an edge too long); a free
+    batch is wholly evaluated; more than MRPOP_COUNTED_MAX_EDGES edges and a
+    missing count array are rejected."""
+    import paper_2609_30644_amd as M
+    p = problem("c2")
+    sc = p.scene
+    anchors = W.random_configs(sc, 4000, np.random.default_rng(8))
+    anchors = anchors[oracle.states_free(sc, anchors)]
+    qa = np.resize(anchors, (1024, anchors.shape[1]))  # free states, repeated
+    n = np.ones(1024, np.int32)  # each edge its free start state alone
+    n[[3, 500]] = [0, -1]
+    s = _scene(ctx, sc)
+    valid, st = s.validate_counted(qa, qa, n, stats=True)
+    valid = valid.cpu().numpy()
+    want = (n > 0) & (oracle.state_margins(sc, qa) >= BAND)
+    np.testing.assert_array_equal(valid.astype(bool), want)
+    assert st.edge_states == st.states_checked == int((n > 0).sum())
+    assert st.nonfinite_edges == 1 and st.edges_invalid == 2
+    # a too-long edge: its bit is 0; with stats the call reports it as
+    # mrpop_validate_edges does
+    n[1023] = -2
+    valid = s.validate_counted(qa, qa, n).cpu().numpy()
+    np.testing.assert_array_equal(valid.astype(bool), (n > 0) & want)
+    with pytest.raises(M.MrpopError) as e:
+        s.validate_counted(qa, qa, n, stats=True)
+    assert e.value.name == "E_INVALID_ARG"
+    with pytest.raises(M.MrpopError) as e:
+        s.validate_counted(np.concatenate([qa, qa[:1]]), np.concatenate([qa, qa[:1]]), np.ones(1025, np.int32))
+    assert e.value.name == "E_INVALID_ARG"
+    with pytest.raises(M.MrpopError) as e:
+        s.validate_counted(qa, qa, None)
+    assert e.value.name == "E_INVALID_ARG"

@@ -145,6 +145,20 @@ int main() {
   CHECK(mrpop_validate_edges_noalloc(ctx, sc, qa, qb, MRPOP_NOALLOC_MAX_EDGES + 1, 0.05f, nullptr, v2, nullptr,
                                      nullptr) == MRPOP_E_INVALID_ARG);
   CHECK(mrpop_validate_edges(ctx, sc, qa, qb, E, -1.f, nullptr, v1, nullptr, nullptr) == MRPOP_E_INVALID_ARG);
+  {  // caller-counted validation: every edge at its start state alone
+    int32_t *dn = nullptr;
+    HIPCHECK(hipMalloc(&dn, sizeof(int32_t) * (MRPOP_COUNTED_MAX_EDGES + 1)));
+    std::vector<int32_t> ones(MRPOP_COUNTED_MAX_EDGES + 1, 1);
+    HIPCHECK(hipMemcpy(dn, ones.data(), sizeof(int32_t) * ones.size(), hipMemcpyHostToDevice));
+    CHECK(mrpop_validate_counted(ctx, sc, qa, qb, E, nullptr, v2, nullptr, nullptr) == MRPOP_E_INVALID_ARG);
+    CHECK(mrpop_validate_counted(ctx, sc, qa, qb, MRPOP_COUNTED_MAX_EDGES + 1, dn, v2, nullptr, nullptr) ==
+          MRPOP_E_INVALID_ARG);
+    const int64_t nc = E < MRPOP_COUNTED_MAX_EDGES ? E : MRPOP_COUNTED_MAX_EDGES;
+    mrpop_validate_stats cs{};
+    CHECK(mrpop_validate_counted(ctx, sc, qa, qb, nc, dn, v2, &cs, nullptr) == MRPOP_OK);
+    CHECK(cs.edge_states == nc);
+    HIPCHECK(hipFree(dn));
+  }
   mrpop_kernel_profile prof{};
   CHECK(mrpop_profile_read(ctx, &prof) == MRPOP_OK && prof.launches >= 1);
   CHECK(mrpop_profile_enable(ctx, 0) == MRPOP_OK);

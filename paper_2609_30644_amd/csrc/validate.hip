@@ -29,10 +29,13 @@
 //      static mask allows, and for flagged link pairs the two frames are
 //      rebuilt and the fine spheres tested.
 // A collision marks the edge in a flag word and marks all of the edge's lanes
-// of the tile in an LDS mask, which the other waves read as they go.  Tiles
-// do not read the flag words: the tiles of one edge run at the same time on
-// different workgroups, so the check almost never skipped a state, and the
-// coherent load it needs cost a memory round trip per tile.
+// of the tile in an LDS mask, which the other waves read as they go.  In the
+// plain order tiles do not read the flag words: the tiles of one edge run at
+// the same time on different workgroups, so the check almost never skipped a
+// state, and the coherent load it needs cost a memory round trip per tile.
+// One-launch batches of more tiles than workgroups use a two-pass order
+// instead (every K-th state of each edge first, see map_lanes_split), whose
+// second-pass tiles do read them and skip the states of marked edges.
 #include <hip/hip_ext.h>
 #include <algorithm>
 #include <cstdio>
@@ -1080,9 +1083,9 @@ __device__ __forceinline__ void arm_joints(const SceneDev &sc, const LaneState &
 }
 
 // One tile on the whole workgroup, then the edge flag (a colliding edge's
-// flag word is set to hit_token; states of an edge whose word already holds
-// it are skipped); ends with a barrier (the tile's LDS is reused by the next
-// one).
+// flag word is set to hit_token; with skip_hit, states of an edge whose word
+// already holds it are skipped); ends with a barrier (the tile's LDS is
+// reused by the next one).
 //
 // With the joints' sines and cosines cached in LDS (sc_lds), the
 // environment stage is balanced at run time: the waves first compute the

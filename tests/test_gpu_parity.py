@@ -420,3 +420,25 @@ def test_validate_counted_codes_and_limits(ctx):
     with pytest.raises(M.MrpopError) as e:
         s.validate_counted(qa, qa, None)
     assert e.value.name == "E_INVALID_ARG"
+
+
+def test_validate_counted_sixteen_arms(ctx):
+    """The counted path on sixteen 20-sphere arms: the sine/cosine cache does
+    not fit, so the two-pass order runs in the kernel variant that composes
+    whole chains; bits against the oracle and against the general path."""
+    m = W.panda_like(20)
+    R = 16
+    sc = W.Scene([m] * R, W.ring_bases(R, W.ring_radius_for_spacing(R, 1.0)),
+                 np.array([[0.0, 0.0, 0.5, 0.2]], np.float32), np.zeros((0, 6), np.float32))
+    qa, qb = W.edge_batch(sc, 1024, 0.05, 112, 20, 50)
+    n = oracle.edge_nstates(qa, qb, 0.05)
+    print(f"[validate_counted] 16 arms: {int(n.sum())} states", flush=True)
+    s = _scene(ctx, sc)
+    valid, st = s.validate_counted(qa, qb, n, stats=True)
+    valid = valid.cpu().numpy()
+    plain = s.validate_edges(qa, qb, 0.05, n_states=n).cpu().numpy()
+    _, marg = oracle.classify_edges(sc, qa, qb, 0.05, nstates=n)
+    info = assert_bits_match(valid, marg, "16 arms/counted")
+    np.testing.assert_array_equal(valid, plain)
+    assert st.edge_states == int(n.sum()) and 0 < st.states_checked <= st.edge_states
+    print(f"  {info} checked {st.states_checked} of {st.edge_states}", flush=True)

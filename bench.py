@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -345,11 +346,16 @@ def c2_batches_leg(ctx, reps: int) -> dict:
     return out
 
 
-def c3_leg(ctx, reps: int, plan_s: float) -> dict:
+C3_COST_MARKS_S = (0.01, 0.1, 1.0, 5.0, 10.0, 30.0)
+
+
+def c3_leg(ctx, reps: int, plan_s: float, plan_seeds: int = 1) -> dict:
     """The 8-arm shelf workload: both 4096-edge batches validated `reps`
     times (edge-states/s, the tile kernel's time and algorithmic flops, bits
-    checked against the fixture), then one plan with a wall-clock budget
-    (time to first solution, cost after each improvement, cost at the end)."""
+    checked against the fixture), then plans with a wall-clock budget (time
+    to first solution, cost after each improvement, cost at the end): seed 0
+    in full, and with plan_seeds > 1 the time-to-solution median and the
+    cost's median and quartiles at fixed times over seeds 0..plan_seeds-1."""
     scene, batches, fx = load_workload(C3_FIXTURE, "scene_c3")
     res = float(fx["resolution"])
     out = {"workload": "8 arms x 7-DoF (59 spheres/arm) on a 3 m circle, 256 shelf boxes, res 0.02 rad"}
@@ -367,6 +373,27 @@ def c3_leg(ctx, reps: int, plan_s: float) -> dict:
                        "edge_states": r.stats["edge_states"], "roadmap_vertices": r.stats["roadmap_vertices"],
                        "straight_line": float(np.linalg.norm(qg.astype(np.float64) - qs)),
                        "params": dict(prm, time_budget_s=plan_s)}
+        if plan_seeds > 1:
+            runs = [(r, out["plan"]["cost_vs_time"])]
+            for seed in range(1, plan_seeds):
+                print(f"[bench] c3 plan seed {seed}", file=sys.stderr, flush=True)
+                r2, h2, _ = s.plan_with_history(qs, qg, max_entries=64, max_waypoints=65536, raise_on_error=False,
+                                                **dict(prm, seed=seed))
+                runs.append((r2, sorted([(h.found_s, h.cost) for h in h2])))
+            tts = [x.stats["time_to_first_s"] * 1e3 for x, _ in runs if x.stats["time_to_first_s"] >= 0]
+            at = {}
+            for t in C3_COST_MARKS_S:
+                if t > plan_s:
+                    continue
+                c = [min([cost for found, cost in cv if found <= t], default=math.inf) for _, cv in runs]
+                q1, q2, q3 = np.percentile(c, [25, 50, 75])
+                at[str(t)] = {"median": float(q2), "q1": float(q1), "q3": float(q3),
+                              "solved": int(np.isfinite(c).sum())}
+            out["plan_seeds"] = {"seeds": plan_seeds, "solved": sum(x.status == "OK" for x, _ in runs),
+                                 "tts_p50_ms": float(np.median(tts)) if tts else None,
+                                 "tts_max_ms": float(max(tts)) if tts else None,
+                                 "cost_at_s": at, "note": "same problem, planner seeds 0..seeds-1; "
+                                 "cost inf before a seed's first solution"}
     return out
 
 
@@ -664,6 +691,7 @@ def main():
     ap.add_argument("--c1-full", type=int, default=2, help="of those, plans run for the whole 5 s budget")
     ap.add_argument("--c3-reps", type=int, default=10, help="repetitions of each 8-arm batch (0: skip the leg)")
     ap.add_argument("--c3-plan-seconds", type=float, default=30.0, help="budget of the 8-arm plan (0: skip)")
+    ap.add_argument("--c3-plan-seeds", type=int, default=1, help="8-arm plans over seeds 0..N-1 (N > 1: statistics)")
     ap.add_argument("--aodrrt-seconds", type=float, default=5.0,
                     help="budget of each AO-X and ao-dRRT run of the cost-vs-time comparison (0: skip)")
     ap.add_argument("--aodrrt-seeds", type=int, default=3)
@@ -779,7 +807,7 @@ def main():
         line["c1"] = c1_leg(ctx, args.c1_problems, args.c1_full)
     if args.c3_reps > 0:
         print("[bench] eight-arm shelf", file=sys.stderr, flush=True)
-        line["c3"] = c3_leg(ctx, args.c3_reps, args.c3_plan_seconds)
+        line["c3"] = c3_leg(ctx, args.c3_reps, args.c3_plan_seconds, args.c3_plan_seeds)
     if args.c3_reps > 0:
         print("[bench] four-arm batches alone", file=sys.stderr, flush=True)
         line["c2_batches"] = c2_batches_leg(ctx, args.c3_reps)
